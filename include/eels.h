@@ -1,0 +1,172 @@
+/*
+ * eels.h -- C ABI of the MI355X PRISM STEM-EELS library (libeels.so).
+ *
+ * The library computes an atomic-resolution STEM-EELS map with the linear-scaling
+ * scattering-matrix method of Brown, Ciston and Ophus (arXiv:1908.07628):
+ *
+ *   S_1(j)  plane waves of the probe-forming aperture multisliced to the entrance of
+ *           slice j (Sec. 3, PRISM STEM-EELS algorithm; Eq. MSop for one slice);
+ *   S_2(j)  the transposed scattering matrix that takes a wave present at the entrance
+ *           of slice j to the detector beams at the exit (Eq. MSTop, exact transpose);
+ *   A_n(q,R) = sum_r S_2(j)[q](r) H_n(r) sum_k c_k(R) S_1(j)[k](r)   (Eqs. Hn0Psi, SHn0)
+ *   I(R)    = f^2 sum_{sites, n, q} |A_n(q,R)|^2                     (map accumulation)
+ *
+ * with c_k(R) = s A(k) exp(-i chi(k)) exp(-2 pi i k.R) the probe coefficients (Eq. illum),
+ * T_j = exp(i sigma V_j) and P_j = B(k) exp(-i pi lambda dz_j k^2) (Eq. MSop), B the
+ * circular band limit.  The transition of a slice acts at its entrance, before T_j.
+ *
+ * Conventions
+ *   - Arrays are row-major [y][x] (x fastest).  Complex values are interleaved
+ *     (re, im) single-precision pairs ("complex64").
+ *   - Forward transforms carry exp(-2 pi i r.g) (footnote to Eq. 4).
+ *   - Every function returns an eels_status; no C++ exception crosses the ABI.
+ *   - The library never frees caller memory.  Device buffers passed to eels_execute
+ *     are owned by the caller and must stay valid until the stream has finished.
+ *   - A plan is immutable after creation and may be used for several concurrent
+ *     executions on different streams with different workspaces.
+ */
+#ifndef EELS_H
+#define EELS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EELS_VERSION_MAJOR 0
+#define EELS_VERSION_MINOR 3
+
+typedef int eels_status;
+enum {
+    EELS_OK = 0,
+    EELS_ERR_INVALID_ARG = 1,      /* a size, pointer or parameter is out of range       */
+    EELS_ERR_BANDLIMIT = 2,        /* an aperture or detector beam lies outside the band  */
+    EELS_ERR_UNSUPPORTED_SIZE = 3, /* grid side not a power of two in [16, 2048]         */
+    EELS_ERR_WORKSPACE = 4,        /* workspace pointer null or smaller than required     */
+    EELS_ERR_OOM = 5,              /* the problem does not fit the memory budget          */
+    EELS_ERR_DEVICE = 6,           /* a HIP call failed (message via eels_last_error)     */
+    EELS_ERR_CANCELLED = 7,        /* a queued request was cancelled                      */
+    EELS_ERR_INTERNAL = 8
+};
+
+enum { EELS_FP32 = 0, EELS_BF16_SPLIT = 1, EELS_FP16_SPLIT = 2 };
+enum { EELS_ORDER_AUTO = 0, EELS_ORDER_S_FIRST = 1, EELS_ORDER_PROBE_FIRST = 2 };
+
+/* One ionised atom: its transitions act at the entrance of `slice` (0-based).
+ * H rows h_offset .. h_offset + n_trans - 1 hold its transition potentials. */
+typedef struct {
+    int slice;
+    int n_trans;
+    double x_A, y_A;
+    int64_t h_offset;
+} eels_site;
+
+/* The problem statement (all host values; the library copies what it keeps).
+ *
+ * Grid and cell: nx x ny pixels over lx x ly Angstrom (periodic).  Slices: n_slices
+ * thicknesses dz_A[].  Beam: energy_eV; lambda_A and sigma (rad/(V*A)) override the
+ * relativistic values when > 0.  Probe: aperture semi-angle, optional defocus and Cs
+ * (Angstrom) in chi(k) = pi lambda k^2 (Cs lambda^2 k^2 / 2 - defocus).  Detector:
+ * inner/outer semi-angles (inclusive).  interp_f: PRISM interpolation factor (beams on
+ * the lattice f Z^2 / L).  bandlimit: fraction of Nyquist of the circular band limit
+ * (0 -> 2/3).  window_A: side of the crop window of the contraction (Sec. 4.B);
+ * 0 -> full cell.  Probes: n_probes (x, y) positions in Angstrom.  Sites: n_sites
+ * entries; n_trans_total rows of H.  max_workspace_bytes: memory budget for the plan's
+ * workspace (0 -> unlimited); slices are processed in groups to stay within it. */
+typedef struct {
+    int nx, ny;
+    double lx_A, ly_A;
+    int n_slices;
+    const double* dz_A;
+    double energy_eV;
+    double lambda_A;
+    double sigma;
+    double aperture_mrad;
+    double det_inner_mrad, det_outer_mrad;
+    double defocus_A, cs_A;
+    int interp_f;
+    double bandlimit;
+    double window_A;
+    int n_probes;
+    const double* probe_xy;
+    int n_sites;
+    const eels_site* sites;
+    int64_t n_trans_total;
+    int precision;
+    int order;
+    size_t max_workspace_bytes;
+} eels_problem;
+
+/* Derived sizes of a plan (filled by eels_plan_info). */
+typedef struct {
+    int n_beams_in;          /* N_1: aperture beams on the f-lattice                      */
+    int n_beams_out;         /* N_2: detector beams on the f-lattice                      */
+    int n_beams_in_fine;     /* aperture beams at f = 1 (probe normalisation)             */
+    int n_live_x;            /* kx columns inside the band limit                          */
+    int window_nx, window_ny;/* crop window side in pixels (nx, ny if full cell)          */
+    int k_pixels;            /* pixels per window                                         */
+    int k_stride;            /* padded window stride (complex elements)                  */
+    int n_ion_slices;        /* slices that hold at least one site                        */
+    int n_groups;            /* slice groups (forward sweep repeated once per group)      */
+    int n_batches;           /* contraction batches                                       */
+    int order;               /* EELS_ORDER_S_FIRST or EELS_ORDER_PROBE_FIRST              */
+    double lambda_A, sigma;
+    double gemm_flops;       /* useful complex-GEMM flops (8 M N K summed)                */
+    double sweep_bytes;      /* algorithmic HBM bytes of the two sweeps                   */
+    double sweep_beam_slices;/* beam-slice passes of the two sweeps                       */
+    size_t workspace_bytes;
+} eels_plan_info;
+
+typedef struct eels_plan eels_plan;
+
+eels_status eels_get_version(int* major, int* minor);
+const char* eels_status_string(eels_status s);
+/* Text of the last error on the calling thread (empty if none). */
+const char* eels_last_error(void);
+
+/* Host only: validates the problem, builds beam lists (ordered by lattice row, then
+ * column), crop windows, probe eligibility, the contraction order and the workspace
+ * layout.  Touches no device.  Errors: INVALID_ARG, BANDLIMIT, UNSUPPORTED_SIZE, OOM. */
+eels_status eels_plan_create(eels_plan** out, const eels_problem* prob);
+eels_status eels_plan_workspace_bytes(const eels_plan* p, size_t* bytes);
+eels_status eels_plan_info_get(const eels_plan* p, eels_plan_info* info);
+/* Lattice coordinates (a, b) of the aperture (which = 0) or detector (which = 1)
+ * beams, k = (f a / lx, f b / ly); ab must hold 2 * count ints. */
+eels_status eels_plan_beams(const eels_plan* p, int which, int* ab, int count);
+eels_status eels_plan_destroy(eels_plan* p);
+
+/* Device: computes the map.  d_V: float32 [n_slices][ny][nx] projected potential
+ * (V*A).  d_H: complex64 [n_trans_total][wy][wx] transition potentials on each site's
+ * window (window pixel (u, v) is grid pixel (ix0 - h + u, iy0 - h + v) mod n, ix0 the
+ * site's nearest pixel), or [n_trans_total][ny][nx] on the full grid.  d_map: float64
+ * [n_probes], overwritten.  d_workspace: at least eels_plan_workspace_bytes bytes,
+ * 256-byte aligned.  All work is enqueued on `stream` (a hipStream_t, 0 = default);
+ * no device memory is allocated and the host does not wait for the device. */
+eels_status eels_execute(const eels_plan* p, const float* d_V, const void* d_H, double* d_map,
+                         void* d_workspace, size_t workspace_bytes, void* stream);
+
+/* Diagnostics (same workspace contract).  Write the real-space rows of S_1(j)
+ * (scaled by nx*ny, i.e. unit-modulus plane waves at j = 0) as complex64
+ * [N_1][ny][nx], or of S_2(j) as complex64 [N_2][ny][nx]. */
+eels_status eels_debug_s1(const eels_plan* p, const float* d_V, int slice, void* d_out,
+                          void* d_workspace, size_t workspace_bytes, void* stream);
+eels_status eels_debug_s2(const eels_plan* p, const float* d_V, int slice, void* d_out,
+                          void* d_workspace, size_t workspace_bytes, void* stream);
+
+/* Diagnostic complex GEMM through the same kernels as the contraction:
+ * C[m][n] = sum_k A[m][k] * B[n][k] (no conjugation), complex64, row-major with
+ * leading dimensions lda, ldb, ldc (complex elements, multiples of 2).  If d_norm2 is
+ * not null, d_norm2[n] = sum_m |C[m][n]|^2 (float64) is written instead of C.
+ * precision: EELS_FP32 / EELS_BF16_SPLIT / EELS_FP16_SPLIT.  d_work: at least
+ * eels_gemm_work_bytes(m, n) bytes. */
+size_t eels_gemm_work_bytes(int m, int n);
+eels_status eels_debug_cgemm(int precision, int m, int n, int k, const void* d_A, int lda,
+                             const void* d_B, int ldb, void* d_C, int ldc, double* d_norm2,
+                             void* d_work, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EELS_H */

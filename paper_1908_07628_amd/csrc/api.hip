@@ -1,0 +1,358 @@
+// C ABI: plan lifecycle, the device orchestration of one EELS map, and diagnostics.
+//
+// Order of work for one map (all on the caller's stream):
+//   set-up      twiddles, T_j = exp(i sigma V_j), P_j, probe coefficients c_k(R)
+//   per group   forward sweep of S_1 from slice 0 to the group's highest ionised slice,
+//               capturing the S_1 windows of the group's ionised slices; then the
+//               transposed sweep of S_2 continues downward through the group, and at each
+//               ionised slice the captured windows are contracted (two grouped GEMMs and a
+//               deterministic FP64 reduction into the map).
+// Because the S_1 windows of a group are kept, S_2 needs one pass over the slices in
+// total instead of being rebuilt for every slice (Sec. 3 rebuilds it per slice).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "eels.h"
+#include "internal.h"
+#include "kernels.h"
+
+struct eels_plan {
+    eels::Plan p;
+};
+
+namespace eels {
+
+static thread_local std::string g_err;
+void set_error(const std::string& m) { g_err = m; }
+
+#define HIPCHK(x)                                                                       \
+    do {                                                                                \
+        hipError_t e_ = (x);                                                            \
+        if (e_ != hipSuccess) {                                                         \
+            set_error(std::string(#x) + ": " + hipGetErrorString(e_));                  \
+            return EELS_ERR_DEVICE;                                                     \
+        }                                                                               \
+    } while (0)
+
+namespace {
+
+struct Dev {
+    char* ws;
+    const int* blob;
+    const int4* b1;
+    const int4* b2;
+    const double* dz;
+    const double* probes;
+    const GemmDesc* descs;
+    float2 *twx, *twy, *T, *P, *C, *s1, *s2, *w1, *w2, *mid;
+    float* part;
+};
+
+Dev make_dev(const Plan& p, void* ws_) {
+    Dev d{};
+    d.ws = (char*)ws_;
+    d.blob = (const int*)(d.ws + p.off_blob);
+    d.b1 = (const int4*)(d.blob + p.b1_off);
+    d.b2 = (const int4*)(d.blob + p.b2_off);
+    d.dz = (const double*)(d.blob + p.dz_off);
+    d.probes = (const double*)(d.blob + p.probes_off);
+    d.descs = (const GemmDesc*)(d.blob + p.descs_off);
+    d.twx = (float2*)(d.ws + p.off_twx);
+    d.twy = (float2*)(d.ws + p.off_twy);
+    d.T = (float2*)(d.ws + p.off_T);
+    d.P = (float2*)(d.ws + p.off_P);
+    d.C = (float2*)(d.ws + p.off_C);
+    d.s1 = (float2*)(d.ws + p.off_s1);
+    d.s2 = (float2*)(d.ws + p.off_s2);
+    d.w1 = (float2*)(d.ws + p.off_w1);
+    d.w2 = (float2*)(d.ws + p.off_w2);
+    d.mid = (float2*)(d.ws + p.off_mid);
+    d.part = (float*)(d.ws + p.off_part);
+    return d;
+}
+
+eels_status check_ws(const Plan& p, void* ws, size_t bytes) {
+    if (!ws || bytes < p.ws_bytes) {
+        set_error("workspace smaller than eels_plan_workspace_bytes");
+        return EELS_ERR_WORKSPACE;
+    }
+    if (((uintptr_t)ws) & 255) {
+        set_error("workspace must be 256-byte aligned");
+        return EELS_ERR_WORKSPACE;
+    }
+    return EELS_OK;
+}
+
+eels_status setup(const Plan& p, const Dev& d, const float* dV, hipStream_t st) {
+    HIPCHK(hipMemcpyAsync(d.ws + p.off_blob, p.blob.data(), p.blob.size() * 4, hipMemcpyHostToDevice, st));
+    launch_twiddles(d.twx, p.nx, st);
+    launch_twiddles(d.twy, p.ny, st);
+    launch_transmission(d.T, dV, (int64_t)p.nz * p.ny * p.nx, p.sigma, st);
+    launch_propagator(d.P, d.dz, p, st);
+    return EELS_OK;
+}
+
+const float2* Tj(const Plan& p, const Dev& d, int j) { return d.T + (int64_t)j * p.ny * p.nx; }
+const float2* Pj(const Plan& p, const Dev& d, int j) { return d.P + (int64_t)j * p.ny * p.nlx; }
+
+// Forward sweep of S_1 through slices 0..j_end (row pass of j_end included, its column
+// pass not).  Captures the windows of the ionised slices of `group` (if >= 0), or the
+// full real-space S_1(dbg_slice) into dbg_out.
+void forward_sweep(const Plan& p, const Dev& d, int j_end, int group, int dbg_slice, float2* dbg_out,
+                   hipStream_t st) {
+    launch_init_forward(d.s1, d.b1, p, st);
+    for (int j = 0; j <= j_end; ++j) {
+        RowPassArgs a{d.s1, p.N1, p.ny, p.nlx, p.hlx, Tj(p, d, j), d.twx, nullptr, nullptr, d.w1, p.N1, p.Kpad};
+        if (dbg_out && j == dbg_slice) {
+            a.cap_ptr = d.blob + p.dbg_ptr;
+            a.cap_rec = d.blob + p.dbg_rec;
+            a.win = dbg_out;
+            a.Kpad = p.nx * p.ny;
+        } else if (group >= 0 && p.slices[j].ion && p.slices[j].group == group) {
+            a.cap_ptr = d.blob + p.slices[j].cap1_ptr;
+            a.cap_rec = d.blob + p.slices[j].cap1_rec;
+        }
+        launch_row_pass(p.nx, 0, a, st);
+        if (j < j_end) launch_col_pass(p.ny, 0, d.s1, p.N1, p.nlx, Pj(p, d, j), d.twy, st);
+    }
+}
+
+// One step of the transposed sweep: bring S_2 to slice j (from j+1, or start at n_z-1)
+// and capture its windows (or the full plane into dbg_out).
+void reverse_step(const Plan& p, const Dev& d, int j, bool capture, float2* dbg_out, hipStream_t st) {
+    if (j == p.nz - 1) launch_init_reverse(d.s2, d.b2, p, st);
+    else launch_col_pass(p.ny, 1, d.s2, p.N2, p.nlx, Pj(p, d, j), d.twy, st);
+    RowPassArgs a{d.s2, p.N2, p.ny, p.nlx, p.hlx, Tj(p, d, j), d.twx, nullptr, nullptr, d.w2, p.N2, p.Kpad};
+    if (dbg_out) {
+        a.cap_ptr = d.blob + p.dbg_ptr;
+        a.cap_rec = d.blob + p.dbg_rec;
+        a.win = dbg_out;
+        a.Kpad = p.nx * p.ny;
+    } else if (capture) {
+        a.cap_ptr = d.blob + p.slices[j].cap2_ptr;
+        a.cap_rec = d.blob + p.slices[j].cap2_rec;
+    }
+    launch_row_pass(p.nx, 1, a, st);
+}
+
+void contract(const Plan& p, const Dev& d, const float2* dH, double* map, int bi, hipStream_t st) {
+    const Batch& b = p.batches[bi];
+    const GemmDesc* dd = d.descs;
+    if (b.order == EELS_ORDER_S_FIRST) {
+        launch_cgemm(p.precision, 0, 0, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.w2, d.w1, dH, d.mid, nullptr,
+                     d.blob, st);
+        launch_cgemm(p.precision, 0, 1, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.mid, d.C, nullptr, nullptr, d.part,
+                     d.blob, st);
+    } else {
+        launch_cgemm(EELS_FP32, 1, 0, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.C, d.w1, nullptr, d.mid, nullptr,
+                     d.blob, st);
+        launch_cgemm(p.precision, 0, 1, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.w2, d.mid, dH, nullptr, d.part,
+                     d.blob, st);
+    }
+    double nn = (double)p.nx * (double)p.ny;
+    double scale = (double)p.f * p.f / (nn * nn) / ((double)p.c_scale * p.c_scale);
+    if (b.red_ptr < 0) launch_reduce_dense(map, p.P, dd, b.d2_begin, b.d2_count, d.part, scale, st);
+    else launch_reduce(map, p.P, d.blob + b.red_ptr, d.blob + b.red_ent, dd, d.part, scale, st);
+}
+
+}  // namespace
+}  // namespace eels
+
+using namespace eels;
+
+extern "C" {
+
+eels_status eels_get_version(int* major, int* minor) {
+    if (major) *major = EELS_VERSION_MAJOR;
+    if (minor) *minor = EELS_VERSION_MINOR;
+    return EELS_OK;
+}
+
+const char* eels_status_string(eels_status s) {
+    switch (s) {
+        case EELS_OK: return "ok";
+        case EELS_ERR_INVALID_ARG: return "invalid argument";
+        case EELS_ERR_BANDLIMIT: return "beam outside the band limit";
+        case EELS_ERR_UNSUPPORTED_SIZE: return "unsupported grid size";
+        case EELS_ERR_WORKSPACE: return "workspace too small";
+        case EELS_ERR_OOM: return "does not fit the memory budget";
+        case EELS_ERR_DEVICE: return "device error";
+        case EELS_ERR_CANCELLED: return "cancelled";
+        default: return "internal error";
+    }
+}
+
+const char* eels_last_error(void) { return g_err.c_str(); }
+
+eels_status eels_plan_create(eels_plan** out, const eels_problem* prob) {
+    if (!out || !prob) {
+        set_error("null argument");
+        return EELS_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    try {
+        eels_plan* pl = new eels_plan;
+        eels_status s = build_plan(pl->p, *prob);
+        if (s != EELS_OK) {
+            delete pl;
+            return s;
+        }
+        *out = pl;
+        return EELS_OK;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed while planning");
+        return EELS_ERR_OOM;
+    } catch (...) {
+        set_error("unexpected exception while planning");
+        return EELS_ERR_INTERNAL;
+    }
+}
+
+eels_status eels_plan_workspace_bytes(const eels_plan* p, size_t* bytes) {
+    if (!p || !bytes) return EELS_ERR_INVALID_ARG;
+    *bytes = p->p.ws_bytes;
+    return EELS_OK;
+}
+
+eels_status eels_plan_info_get(const eels_plan* pl, eels_plan_info* info) {
+    if (!pl || !info) return EELS_ERR_INVALID_ARG;
+    const Plan& p = pl->p;
+    std::memset(info, 0, sizeof(*info));
+    info->n_beams_in = p.N1;
+    info->n_beams_out = p.N2;
+    info->n_beams_in_fine = p.N1fine;
+    info->n_live_x = p.nlx;
+    info->window_nx = p.nwx;
+    info->window_ny = p.nwy;
+    info->k_pixels = p.K;
+    info->k_stride = p.Kpad;
+    int nion = 0;
+    for (auto& s : p.slices) nion += s.ion ? 1 : 0;
+    info->n_ion_slices = nion;
+    info->n_groups = (int)p.groups.size();
+    info->n_batches = (int)p.batches.size();
+    info->order = p.order;
+    info->lambda_A = p.lam;
+    info->sigma = p.sigma;
+    info->gemm_flops = p.gemm_flops;
+    info->sweep_bytes = p.sweep_bytes;
+    info->sweep_beam_slices = p.sweep_beam_slices;
+    info->workspace_bytes = p.ws_bytes;
+    return EELS_OK;
+}
+
+eels_status eels_plan_beams(const eels_plan* pl, int which, int* ab, int count) {
+    if (!pl || !ab || (which != 0 && which != 1)) return EELS_ERR_INVALID_ARG;
+    const auto& v = which == 0 ? pl->p.ab1 : pl->p.ab2;
+    if (count < (int)v.size() / 2) return EELS_ERR_INVALID_ARG;
+    std::memcpy(ab, v.data(), v.size() * sizeof(int));
+    return EELS_OK;
+}
+
+eels_status eels_plan_destroy(eels_plan* p) {
+    delete p;
+    return EELS_OK;
+}
+
+eels_status eels_execute(const eels_plan* pl, const float* d_V, const void* d_H, double* d_map, void* d_workspace,
+                         size_t workspace_bytes, void* stream) {
+    if (!pl || !d_V || !d_map) {
+        set_error("null argument");
+        return EELS_ERR_INVALID_ARG;
+    }
+    const Plan& p = pl->p;
+    if (p.n_trans_total > 0 && !d_H) {
+        set_error("transition potentials missing");
+        return EELS_ERR_INVALID_ARG;
+    }
+    eels_status s = check_ws(p, d_workspace, workspace_bytes);
+    if (s) return s;
+    hipStream_t st = (hipStream_t)stream;
+    Dev d = make_dev(p, d_workspace);
+    if ((s = setup(p, d, d_V, st))) return s;
+    launch_probe_coefficients(d.C, d.b1, d.probes, p, st);
+    launch_fill_zero_d(d_map, p.P, st);
+    int rev_next = p.nz - 1;
+    for (int gi = 0; gi < (int)p.groups.size(); ++gi) {
+        const Group& g = p.groups[gi];
+        forward_sweep(p, d, g.j_hi, gi, -1, nullptr, st);
+        for (int j = rev_next; j >= g.j_lo; --j) {
+            reverse_step(p, d, j, p.slices[j].ion, nullptr, st);
+            if (p.slices[j].ion)
+                for (int bi : p.slices[j].batches) contract(p, d, (const float2*)d_H, d_map, bi, st);
+        }
+        rev_next = g.j_lo - 1;
+    }
+    HIPCHK(hipGetLastError());
+    return EELS_OK;
+}
+
+eels_status eels_debug_s1(const eels_plan* pl, const float* d_V, int slice, void* d_out, void* d_workspace,
+                          size_t workspace_bytes, void* stream) {
+    if (!pl || !d_V || !d_out || slice < 0 || slice >= pl->p.nz) return EELS_ERR_INVALID_ARG;
+    const Plan& p = pl->p;
+    eels_status s = check_ws(p, d_workspace, workspace_bytes);
+    if (s) return s;
+    hipStream_t st = (hipStream_t)stream;
+    Dev d = make_dev(p, d_workspace);
+    if ((s = setup(p, d, d_V, st))) return s;
+    forward_sweep(p, d, slice, -1, slice, (float2*)d_out, st);
+    HIPCHK(hipGetLastError());
+    return EELS_OK;
+}
+
+eels_status eels_debug_s2(const eels_plan* pl, const float* d_V, int slice, void* d_out, void* d_workspace,
+                          size_t workspace_bytes, void* stream) {
+    if (!pl || !d_V || !d_out || slice < 0 || slice >= pl->p.nz) return EELS_ERR_INVALID_ARG;
+    const Plan& p = pl->p;
+    eels_status s = check_ws(p, d_workspace, workspace_bytes);
+    if (s) return s;
+    hipStream_t st = (hipStream_t)stream;
+    Dev d = make_dev(p, d_workspace);
+    if ((s = setup(p, d, d_V, st))) return s;
+    for (int j = p.nz - 1; j >= slice; --j) reverse_step(p, d, j, false, j == slice ? (float2*)d_out : nullptr, st);
+    HIPCHK(hipGetLastError());
+    return EELS_OK;
+}
+
+size_t eels_gemm_work_bytes(int m, int n) {
+    if (m <= 0 || n <= 0) return 0;
+    return 256 + (size_t)ceil_div(m, GEMM_BM) * (size_t)n * 4 + 256;
+}
+
+eels_status eels_debug_cgemm(int precision, int m, int n, int k, const void* d_A, int lda, const void* d_B, int ldb,
+                             void* d_C, int ldc, double* d_norm2, void* d_work, void* stream) {
+    if (m <= 0 || n <= 0 || k <= 0 || !d_A || !d_B || !d_work || (!d_C && !d_norm2)) return EELS_ERR_INVALID_ARG;
+    if (lda < k || ldb < k || (lda & 1) || (ldb & 1) || (d_C && ldc < n)) return EELS_ERR_INVALID_ARG;
+    if (precision < EELS_FP32 || precision > EELS_FP16_SPLIT) return EELS_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    GemmDesc g{};
+    g.a_off = 0; g.lda = lda; g.b_off = 0; g.ldb = ldb;
+    g.h_off = -1; g.c_off = 0; g.ldc_m = ldc; g.ldc_t = 0; g.p_off = 0; g.ld_part = n; g.a_tstride = 0;
+    g.M = m; g.N_inner = n; g.n_t = 1; g.K = k; g.idx_off = -1;
+    g.tiles_m = (int)ceil_div(m, GEMM_BM);
+    g.tiles_n = (int)ceil_div(n, GEMM_BN);
+    g.tile_start = 0;
+    GemmDesc* dd = (GemmDesc*)d_work;
+    float* part = (float*)((char*)d_work + 256);
+    HIPCHK(hipMemcpyAsync(dd, &g, sizeof(g), hipMemcpyHostToDevice, st));
+    int tiles = g.tiles_m * g.tiles_n;
+    if (d_norm2) {
+        launch_cgemm(precision, 0, 1, dd, 1, tiles, (const float2*)d_A, (const float2*)d_B, nullptr, nullptr, part,
+                     nullptr, st);
+        launch_fill_zero_d(d_norm2, n, st);
+        launch_reduce_dense(d_norm2, n, dd, 0, 1, part, 1.0, st);
+    } else {
+        launch_cgemm(precision, 0, 0, dd, 1, tiles, (const float2*)d_A, (const float2*)d_B, nullptr, (float2*)d_C,
+                     nullptr, nullptr, st);
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipGetLastError());
+    return EELS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,120 @@
+// Internal declarations shared by the host planner and the device orchestration.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "eels.h"
+
+namespace eels {
+
+// Thread-local error text behind eels_last_error().
+void set_error(const std::string& msg);
+
+// One capture record: copy pixels x0 .. x0+nwx-1 (mod nx) of a real-space row into
+// row `dy` of window `win` (window-local pixel index dy*nwx + u).
+struct CaptureRec {
+    int win, dy, x0, nwx;
+};
+
+// One complex-GEMM problem of a grouped launch.  All offsets count elements of the
+// base buffers given at launch time (complex elements for A/B/H/C, floats for the
+// partial sums, ints for the index lists).  The output has n_t column blocks of
+// N_inner columns; for block t:
+//   C_t[m][i] = sum_k A_t[m][k] * B_t[i][k],   A_t = A + t*a_tstride,
+//   B_t[i][k] = Bsrc[idx ? idx[i] : i][k] * (H ? H[t*ldh + k] : 1).
+// Store epilogue: C[c_off + t*ldc_t + m*ldc_m + i].  Norm epilogue:
+// part[p_off + mt*ld_part + t*N_inner + i] = sum over the rows m of tile mt of |C_t[m][i]|^2.
+// Tiles: tiles_m x tiles_n x n_t (m fastest), tiles_n = ceil(N_inner / 128).
+struct GemmDesc {
+    int64_t a_off, b_off, h_off, c_off, p_off;
+    int64_t lda, ldb, ldh, ldc_m, ldc_t, ld_part, a_tstride;
+    int M, N_inner, n_t, K;
+    int idx_off;       // offset into the int table, -1 = no gather
+    int tiles_m, tiles_n, tile_start;
+};
+static_assert(sizeof(GemmDesc) == 128, "GemmDesc layout");
+
+struct Batch {
+    int slice;
+    int order;
+    int d1_begin, d1_count, d1_tiles;   // first GEMM (store epilogue)
+    int d2_begin, d2_count, d2_tiles;   // second GEMM (norm epilogue)
+    int64_t red_ptr;                    // int offset of the per-probe CSR row pointers [P+1], -1: dense
+    int64_t red_ent;                    // int offset of the CSR entries (pairs: desc, column)
+    int64_t n_entries;
+};
+
+struct SliceInfo {
+    bool ion = false;
+    int group = -1;
+    int64_t cap1_ptr = -1, cap1_rec = -1;  // int offsets of the S_1 capture CSR (rows, records)
+    int64_t cap2_ptr = -1, cap2_rec = -1;  // same for S_2
+    std::vector<int> batches;
+};
+
+struct Group {
+    int j_lo, j_hi;                       // ionised slices j_lo..j_hi (inclusive) are captured
+    int n_windows;
+};
+
+struct Plan {
+    // problem (owned copies)
+    int nx, ny;
+    double lx, ly;
+    int nz;
+    std::vector<double> dz;
+    double energy, lam, sigma;
+    double alpha, beta_in, beta_out, defocus, cs;
+    int f;
+    double bandlimit, window_A;
+    int P;
+    std::vector<double> probes;   // [P][2]
+    std::vector<eels_site> sites;
+    int64_t n_trans_total;
+    int precision;
+    int order;
+
+    // derived
+    double kmax;
+    int hlx, nlx;                 // live kx columns: |kx index| <= hlx, count 2*hlx+1
+    std::vector<int> ab1, ab2;    // lattice coordinates (a, b) of beams
+    int N1, N2, N1fine, N1pad;
+    bool full_window;
+    int hwx, hwy, nwx, nwy, K, Kpad;
+    std::vector<int> site_w1, site_w2;          // window index of each site (S_1 group-local, S_2 slice-local)
+    std::vector<int> site_ix0, site_iy0;
+    std::vector<std::vector<int>> site_probes;  // eligible probes (empty vector + flag = all)
+    std::vector<SliceInfo> slices;
+    std::vector<Group> groups;                  // processing order: descending slices
+    std::vector<Batch> batches;
+    std::vector<GemmDesc> descs;
+    int max_w1, max_w2;
+    int64_t mid_elems, part_elems;              // per batch maxima
+    double gemm_flops = 0, sweep_bytes = 0, sweep_beam_slices = 0;
+    float c_scale = 1.0f;                       // probe coefficient pre-scale (FP16 range)
+
+    // device table blob (uploaded at the start of every execute)
+    std::vector<int32_t> blob;
+    int64_t b1_off, b2_off;       // int4 per beam: (live column, iy, a, b)
+    int64_t ident_off;            // 0..P-1
+    int64_t dz_off, probes_off;   // doubles (int offsets, 16-byte aligned)
+    int64_t dbg_ptr, dbg_rec;     // full-plane capture CSR (diagnostics)
+    int64_t descs_off;            // GemmDesc array (int offset, 16-byte aligned)
+
+    // workspace layout (byte offsets)
+    size_t off_blob, off_twx, off_twy, off_T, off_P, off_C, off_s1, off_s2, off_w1, off_w2,
+        off_mid, off_part, ws_bytes;
+};
+
+eels_status build_plan(Plan& p, const eels_problem& prob);
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+constexpr int GEMM_BM = 128;
+constexpr int GEMM_BN = 128;
+constexpr int KPAD_MULT = 16;
+
+}  // namespace eels

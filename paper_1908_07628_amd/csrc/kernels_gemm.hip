@@ -1,0 +1,359 @@
+// Grouped complex GEMM on the CDNA4 matrix cores for the contractions of Eq. SHn0:
+//     C[m][n] = sum_k A[m][k] * B[n][k]              (no conjugation)
+// with an optional transition-potential prologue on B (B[n][k] *= H_t[k], Eq. Hn0Psi)
+// and either a plain store or a |C|^2 column-sum epilogue (the detector sum).
+//
+// Complex products without complex MFMA: with A' = (Ar, Ai) interleaved along k, the
+// real and imaginary parts are the real products
+//     Re C = A' . (Br, -Bi),   Im C = A' . (Bi, Br)
+// so complex data stays interleaved in memory and each lane builds its B operand with
+// a sign flip and a swap.  FP32 uses v_mfma_f32_32x32x2_f32 (one complex k per
+// instruction).  The split precisions store x = hi + lo (hi = rn(x), lo = rn(x - hi))
+// in bf16 or fp16 and use v_mfma_f32_32x32x16 (eight complex k per instruction) for
+// hi*hi + hi*lo + lo*hi with fp32 accumulation.
+//
+// Block: 256 threads = 4 waves in a 2 x 2 grid over a 128 x 128 complex output tile;
+// each wave owns 64 x 64 = 2 x 2 MFMA blocks of 32 x 32.  K advances 16 complex per
+// step through LDS with the next step's global loads issued before the MFMAs.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace eels {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = GEMM_BM, BN = GEMM_BN, BK = 16;
+constexpr int LDF = BK + 1;   // float2 row stride of single-precision tiles
+constexpr int LDS_ = BK + 4;  // u32 row stride of split tiles (one u32 = one complex half pair)
+
+__device__ __forceinline__ float2 cmul2(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// round-to-nearest-even float -> bf16 bits (finite inputs)
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+template <int PREC>
+__device__ __forceinline__ void split2(float a, float b, uint32_t& hi, uint32_t& lo) {
+    if constexpr (PREC == EELS_BF16_SPLIT) {
+        uint32_t ha = bf16_bits(a), hb = bf16_bits(b);
+        float ra = a - __uint_as_float(ha << 16), rb = b - __uint_as_float(hb << 16);
+        hi = ha | (hb << 16);
+        lo = bf16_bits(ra) | (bf16_bits(rb) << 16);
+    } else {
+        _Float16 ha = (_Float16)a, hb = (_Float16)b;
+        _Float16 la = (_Float16)(a - (float)ha), lb = (_Float16)(b - (float)hb);
+        hi = (uint32_t)__builtin_bit_cast(uint16_t, ha) | ((uint32_t)__builtin_bit_cast(uint16_t, hb) << 16);
+        lo = (uint32_t)__builtin_bit_cast(uint16_t, la) | ((uint32_t)__builtin_bit_cast(uint16_t, lb) << 16);
+    }
+}
+
+template <int PREC>
+__device__ __forceinline__ floatx16 mfma16(u32x4 a, u32x4 b, floatx16 c) {
+    if constexpr (PREC == EELS_BF16_SPLIT)
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                       0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(halfx8, a), __builtin_bit_cast(halfx8, b), c,
+                                                      0, 0, 0);
+}
+
+__device__ __forceinline__ u32x4 neg_imag(u32x4 v) {  // (re, im) -> (re, -im) per half pair
+    return v ^ (u32x4){0x80000000u, 0x80000000u, 0x80000000u, 0x80000000u};
+}
+__device__ __forceinline__ u32x4 swap_halves(u32x4 v) {  // (re, im) -> (im, re)
+    return (v >> 16) | (v << 16);
+}
+
+template <int PREC, int KIND, int EPI>
+__global__ __launch_bounds__(256) void k_cgemm(const GemmDesc* __restrict__ descs, int n_desc,
+                                               const float2* __restrict__ Ab, const float2* __restrict__ Bb,
+                                               const float2* __restrict__ Hb, float2* __restrict__ Cb,
+                                               float* __restrict__ Pb, const int* __restrict__ ib) {
+    constexpr bool SPLIT = PREC != EELS_FP32;
+    static_assert(!(SPLIT && KIND == 1), "the [k][n] B layout is single precision only");
+    constexpr int LDS_BYTES = SPLIT ? 4 * BM * LDS_ * 4 : 2 * BM * LDF * 8;
+    __shared__ __attribute__((aligned(16))) char smem[LDS_BYTES > 2048 ? LDS_BYTES : 2048];
+
+    // ---- locate this block's problem and tile
+    const int bid = blockIdx.x;
+    int lo = 0, hi = n_desc - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (descs[mid].tile_start <= bid) lo = mid;
+        else hi = mid - 1;
+    }
+    const GemmDesc& d = descs[lo];
+    const int local = bid - d.tile_start;
+    const int tm = local % d.tiles_m;
+    const int rest = local / d.tiles_m;
+    const int tn = rest % d.tiles_n, t = rest / d.tiles_n;
+    const int M = d.M, K = d.K, N = d.N_inner;
+    const int m0 = tm * BM, n0 = tn * BN;
+    const float2* A = Ab + d.a_off + (int64_t)t * d.a_tstride;
+    const float2* B = Bb + d.b_off;
+    const float2* Hrow = d.h_off >= 0 && Hb ? Hb + d.h_off + (int64_t)t * d.ldh : nullptr;
+    const int* idx = d.idx_off >= 0 ? ib + d.idx_off : nullptr;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int li = lane & 31, hl = lane >> 5;
+
+    // ---- per-thread global load assignment (4 float4 = 8 complex for each operand)
+    int64_t a_row[4];
+    int b_kc[4];
+    int64_t b_row[4];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        int f = tid + l * 256;
+        int row = f >> 3;
+        int m = m0 + row;
+        a_row[l] = -1;
+        if (m < M) a_row[l] = (int64_t)((KIND == 1 && idx) ? idx[m] : m) * d.lda;
+        if constexpr (KIND == 0) {
+            int n = n0 + row;
+            b_row[l] = -1;
+            if (n < N) b_row[l] = (int64_t)(idx ? idx[n] : n) * d.ldb;
+            b_kc[l] = (f & 7) * 2;
+        } else {
+            b_kc[l] = f >> 6;           // k row of the [k][n] tile
+            b_row[l] = (f & 63) * 2;    // column pair within the tile
+        }
+    }
+
+    float4 ra[4], rb[4];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            int kc = ((tid + l * 256) & 7) * 2;
+            int k = k0 + kc;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (a_row[l] >= 0 && k < K) {
+                v = *(const float4*)(A + a_row[l] + k);
+                if (k + 1 >= K) v.z = v.w = 0.f;
+            }
+            ra[l] = v;
+        }
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if constexpr (KIND == 0) {
+                int k = k0 + b_kc[l];
+                if (b_row[l] >= 0 && k < K) {
+                    v = *(const float4*)(B + b_row[l] + k);
+                    if (k + 1 >= K) v.z = v.w = 0.f;
+                    if (Hrow) {
+                        float2 h0 = Hrow[k];
+                        float2 h1 = k + 1 < K ? Hrow[k + 1] : make_float2(0.f, 0.f);
+                        float2 x0 = cmul2(make_float2(v.x, v.y), h0), x1 = cmul2(make_float2(v.z, v.w), h1);
+                        v = make_float4(x0.x, x0.y, x1.x, x1.y);
+                    }
+                }
+            } else {
+                int k = k0 + b_kc[l];
+                int n = n0 + (int)b_row[l];
+                if (k < K && n < N) {
+                    v = *(const float4*)(B + (int64_t)k * d.ldb + n);
+                    if (n + 1 >= N) v.z = v.w = 0.f;
+                }
+            }
+            rb[l] = v;
+        }
+    };
+
+    auto sstore = [&]() {
+        if constexpr (!SPLIT) {
+            float2* As = (float2*)smem;
+            float2* Bs = As + BM * LDF;
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+                int f = tid + l * 256;
+                int row = f >> 3, kc = (f & 7) * 2;
+                As[row * LDF + kc] = make_float2(ra[l].x, ra[l].y);
+                As[row * LDF + kc + 1] = make_float2(ra[l].z, ra[l].w);
+                if constexpr (KIND == 0) {
+                    Bs[row * LDF + kc] = make_float2(rb[l].x, rb[l].y);
+                    Bs[row * LDF + kc + 1] = make_float2(rb[l].z, rb[l].w);
+                } else {
+                    int kr = b_kc[l], nc = (int)b_row[l];
+                    Bs[nc * LDF + kr] = make_float2(rb[l].x, rb[l].y);
+                    Bs[(nc + 1) * LDF + kr] = make_float2(rb[l].z, rb[l].w);
+                }
+            }
+        } else {
+            uint32_t* Ah = (uint32_t*)smem;
+            uint32_t* Al = Ah + BM * LDS_;
+            uint32_t* Bh = Al + BM * LDS_;
+            uint32_t* Bl = Bh + BN * LDS_;
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+                int f = tid + l * 256;
+                int row = f >> 3, kc = (f & 7) * 2;
+                uint32_t h0, l0, h1, l1;
+                split2<PREC>(ra[l].x, ra[l].y, h0, l0);
+                split2<PREC>(ra[l].z, ra[l].w, h1, l1);
+                *(uint2*)&Ah[row * LDS_ + kc] = make_uint2(h0, h1);
+                *(uint2*)&Al[row * LDS_ + kc] = make_uint2(l0, l1);
+                split2<PREC>(rb[l].x, rb[l].y, h0, l0);
+                split2<PREC>(rb[l].z, rb[l].w, h1, l1);
+                *(uint2*)&Bh[row * LDS_ + kc] = make_uint2(h0, h1);
+                *(uint2*)&Bl[row * LDS_ + kc] = make_uint2(l0, l1);
+            }
+        }
+    };
+
+    floatx16 accR[2][2], accI[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) { accR[a][b][v] = 0.f; accI[a][b][v] = 0.f; }
+
+    const int nk = (K + BK - 1) / BK;
+    gload(0);
+    for (int kt = 0; kt < nk; ++kt) {
+        __syncthreads();
+        sstore();
+        __syncthreads();
+        if (kt + 1 < nk) gload((kt + 1) * BK);
+        if constexpr (!SPLIT) {
+            const float* Asf = (const float*)smem;
+            const float2* Bs = (const float2*)smem + BM * LDF;
+#pragma unroll 4
+            for (int kk = 0; kk < BK; ++kk) {
+                float a[2], br[2], bi[2];
+#pragma unroll
+                for (int bm = 0; bm < 2; ++bm) a[bm] = Asf[((wm * 64 + bm * 32 + li) * LDF + kk) * 2 + hl];
+#pragma unroll
+                for (int bn = 0; bn < 2; ++bn) {
+                    float2 b = Bs[(wn * 64 + bn * 32 + li) * LDF + kk];
+                    br[bn] = hl ? -b.y : b.x;
+                    bi[bn] = hl ? b.x : b.y;
+                }
+#pragma unroll
+                for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+                    for (int bn = 0; bn < 2; ++bn) {
+                        accR[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[bm], br[bn], accR[bm][bn], 0, 0, 0);
+                        accI[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[bm], bi[bn], accI[bm][bn], 0, 0, 0);
+                    }
+            }
+        } else {
+            const uint32_t* Ah = (const uint32_t*)smem;
+            const uint32_t* Al = Ah + BM * LDS_;
+            const uint32_t* Bh = Al + BM * LDS_;
+            const uint32_t* Bl = Bh + BN * LDS_;
+#pragma unroll
+            for (int ks = 0; ks < BK / 8; ++ks) {
+                u32x4 ah[2], al[2], brh[2], brl[2], bih[2], bil[2];
+#pragma unroll
+                for (int bm = 0; bm < 2; ++bm) {
+                    int o = (wm * 64 + bm * 32 + li) * LDS_ + ks * 8 + hl * 4;
+                    ah[bm] = *(const u32x4*)&Ah[o];
+                    al[bm] = *(const u32x4*)&Al[o];
+                }
+#pragma unroll
+                for (int bn = 0; bn < 2; ++bn) {
+                    int o = (wn * 64 + bn * 32 + li) * LDS_ + ks * 8 + hl * 4;
+                    u32x4 bh = *(const u32x4*)&Bh[o];
+                    u32x4 bl = *(const u32x4*)&Bl[o];
+                    brh[bn] = neg_imag(bh);
+                    brl[bn] = neg_imag(bl);
+                    bih[bn] = swap_halves(bh);
+                    bil[bn] = swap_halves(bl);
+                }
+#pragma unroll
+                for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+                    for (int bn = 0; bn < 2; ++bn) {
+                        accR[bm][bn] = mfma16<PREC>(ah[bm], brh[bn], accR[bm][bn]);
+                        accR[bm][bn] = mfma16<PREC>(ah[bm], brl[bn], accR[bm][bn]);
+                        accR[bm][bn] = mfma16<PREC>(al[bm], brh[bn], accR[bm][bn]);
+                        accI[bm][bn] = mfma16<PREC>(ah[bm], bih[bn], accI[bm][bn]);
+                        accI[bm][bn] = mfma16<PREC>(ah[bm], bil[bn], accI[bm][bn]);
+                        accI[bm][bn] = mfma16<PREC>(al[bm], bih[bn], accI[bm][bn]);
+                    }
+            }
+        }
+    }
+
+    // ---- epilogues.  32x32 accumulator layout: element v of lane l is row
+    // 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32.
+    if constexpr (EPI == 0) {
+        float2* C = Cb + d.c_off + (int64_t)t * d.ldc_t;
+#pragma unroll
+        for (int bn = 0; bn < 2; ++bn) {
+            int i = n0 + wn * 64 + bn * 32 + li;
+            if (i >= N) continue;
+#pragma unroll
+            for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    int m = m0 + wm * 64 + bm * 32 + 8 * (v >> 2) + 4 * hl + (v & 3);
+                    if (m < M) C[(int64_t)m * d.ldc_m + i] = make_float2(accR[bm][bn][v], accI[bm][bn][v]);
+                }
+        }
+    } else {
+        __syncthreads();
+        float* red = (float*)smem;  // [2][BN]
+#pragma unroll
+        for (int bn = 0; bn < 2; ++bn) {
+            float s = 0.f;
+#pragma unroll
+            for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) s += accR[bm][bn][v] * accR[bm][bn][v] + accI[bm][bn][v] * accI[bm][bn][v];
+            s += __shfl_xor(s, 32);
+            if (hl == 0) red[wm * BN + wn * 64 + bn * 32 + li] = s;
+        }
+        __syncthreads();
+        if (tid < BN) {
+            int i = n0 + tid;
+            if (i < N) Pb[d.p_off + (int64_t)tm * d.ld_part + (int64_t)t * N + i] = red[tid] + red[BN + tid];
+        }
+    }
+}
+
+template <int PREC, int KIND, int EPI>
+static void go(const GemmDesc* dd, int nd, int tiles, const float2* A, const float2* B, const float2* H, float2* C,
+               float* P, const int* idx, hipStream_t st) {
+    hipLaunchKernelGGL((k_cgemm<PREC, KIND, EPI>), dim3(tiles), dim3(256), 0, st, dd, nd, A, B, H, C, P, idx);
+}
+
+void launch_cgemm(int precision, int kind, int epi, const GemmDesc* dd, int nd, int tiles, const float2* A,
+                  const float2* B, const float2* H, float2* C, float* part, const int* idx, hipStream_t st) {
+    if (tiles <= 0 || nd <= 0) return;
+    if (kind == 1) {
+        if (epi == 0) go<EELS_FP32, 1, 0>(dd, nd, tiles, A, B, H, C, part, idx, st);
+        else go<EELS_FP32, 1, 1>(dd, nd, tiles, A, B, H, C, part, idx, st);
+        return;
+    }
+    switch (precision) {
+        case EELS_FP32:
+            if (epi == 0) go<EELS_FP32, 0, 0>(dd, nd, tiles, A, B, H, C, part, idx, st);
+            else go<EELS_FP32, 0, 1>(dd, nd, tiles, A, B, H, C, part, idx, st);
+            break;
+        case EELS_BF16_SPLIT:
+            if (epi == 0) go<EELS_BF16_SPLIT, 0, 0>(dd, nd, tiles, A, B, H, C, part, idx, st);
+            else go<EELS_BF16_SPLIT, 0, 1>(dd, nd, tiles, A, B, H, C, part, idx, st);
+            break;
+        default:
+            if (epi == 0) go<EELS_FP16_SPLIT, 0, 0>(dd, nd, tiles, A, B, H, C, part, idx, st);
+            else go<EELS_FP16_SPLIT, 0, 1>(dd, nd, tiles, A, B, H, C, part, idx, st);
+            break;
+    }
+}
+
+}  // namespace eels

@@ -1,0 +1,412 @@
+// Multislice sweeps of the scattering matrices and the small set-up kernels.
+//
+// A beam's wave is kept between slices in the hybrid (kx, y) representation, stored
+// as [beam][y][c] over the nlx kx columns inside the band limit (column c <-> kx index
+// c for c <= hlx, c - nlx + nx otherwise).  One slice of the forward operator
+// M_j = P_j F T_j F^-1 (Eq. MSop) is two passes over HBM:
+//   row pass     iFFT_x -> (capture S_1 windows) -> * T_j -> FFT_x
+//   column pass  FFT_y  -> * P_j / (nx ny)       -> iFFT_y
+// and one slice of the exact transpose M_j^T = F^-1 T_j F P_j used for S_2 is
+//   column pass  iFFT_y -> * P_j / (nx ny)       -> FFT_y
+//   row pass     FFT_x  -> * T_j -> (capture S_2 windows) -> iFFT_x
+// Transforms are unnormalised; the 1/(nx ny) folded into P keeps S_2 exactly at the
+// scale of its definition and S_1 at nx*ny times it (unit-modulus plane waves at j = 0).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fft_lds.h"
+#include "internal.h"
+#include "kernels.h"
+
+namespace eels {
+
+// --------------------------------------------------------------------- set-up kernels
+
+__global__ void k_twiddles(float2* tw, int n) {
+    int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    double s, c;
+    sincospi(-2.0 * (double)m / (double)n, &s, &c);
+    tw[m] = make_float2((float)c, (float)s);
+}
+
+// T_j(r) = exp(i sigma V_j(r))
+__global__ void k_transmission(float2* T, const float* V, int64_t n, double sigma) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s, c;
+    sincos(sigma * (double)V[i], &s, &c);
+    T[i] = make_float2((float)c, (float)s);
+}
+
+__device__ __forceinline__ int signed_index(int i, int n) { return i < (n + 1) / 2 ? i : i - n; }
+
+__device__ __forceinline__ int live_to_kx_signed(int c, int nlx, int hlx, int nx) {
+    if (nlx == nx) return signed_index(c, nx);
+    return c <= hlx ? c : c - nlx;
+}
+
+// P~_j(kx, ky) = [|k| <= kmax] exp(-i pi lambda dz_j |k|^2) / (nx ny) on the live columns
+__global__ void k_propagator(float2* P, const double* dz, int nz, int nx, int ny, int nlx, int hlx,
+                             double lx, double ly, double lam, double kmax) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t total = (int64_t)nz * ny * nlx;
+    if (i >= total) return;
+    int c = (int)(i % nlx);
+    int y = (int)((i / nlx) % ny);
+    int j = (int)(i / ((int64_t)nlx * ny));
+    double kx = live_to_kx_signed(c, nlx, hlx, nx) / lx;
+    double ky = signed_index(y, ny) / ly;
+    double k2 = kx * kx + ky * ky;
+    float2 out = make_float2(0.f, 0.f);
+    if (sqrt(k2) <= kmax) {
+        double s, co;
+        sincospi(-lam * dz[j] * k2, &s, &co);
+        double sc = 1.0 / ((double)nx * (double)ny);
+        out = make_float2((float)(co * sc), (float)(s * sc));
+    }
+    P[i] = out;
+}
+
+// c_k(R) = s exp(-i chi(k)) exp(-2 pi i k.R), stored [P][N1pad] (zero padding columns).
+// The scan phase is reduced to a fraction of a cycle in double before the sincos.
+__global__ void k_probe_coefficients(float2* C, const int4* beams, int N1, int N1pad, const double* probes, int P,
+                                     int f, double lx, double ly, double lam, double defocus, double cs,
+                                     double scale) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)P * N1pad) return;
+    int k = (int)(i % N1pad);
+    int r = (int)(i / N1pad);
+    float2 out = make_float2(0.f, 0.f);
+    if (k < N1) {
+        int4 b = beams[k];
+        double kx = (double)(f * b.z) / lx, ky = (double)(f * b.w) / ly;
+        double u = kx * probes[2 * r] + ky * probes[2 * r + 1];
+        u -= floor(u);
+        double k2 = kx * kx + ky * ky;
+        double chi = M_PI * lam * k2 * (0.5 * cs * lam * lam * k2 - defocus);
+        double s, c;
+        sincos(-2.0 * M_PI * u - chi, &s, &c);
+        out = make_float2((float)(c * scale), (float)(s * scale));
+    }
+    C[i] = out;
+}
+
+// Forward sweep start: beam b = plane wave e_k, in (kx, y): column col_b holds exp(2 pi i ky y / ny).
+__global__ void k_init_forward(float2* S, const int4* beams, int nb, int ny, int nlx) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t total = (int64_t)nb * ny * nlx;
+    if (i >= total) return;
+    int c = (int)(i % nlx);
+    int y = (int)((i / nlx) % ny);
+    int b = (int)(i / ((int64_t)nlx * ny));
+    int4 bm = beams[b];
+    float2 out = make_float2(0.f, 0.f);
+    if (c == bm.x) {
+        int m = (int)(((int64_t)bm.y * y) % ny);
+        double s, co;
+        sincospi(2.0 * (double)m / (double)ny, &s, &co);
+        out = make_float2((float)co, (float)s);
+    }
+    S[i] = out;
+}
+
+// Reverse sweep start: w = fft_y(P_{nz-1} e_q): column col_q holds P(q) exp(-2 pi i qy y / ny).
+__global__ void k_init_reverse(float2* S, const int4* beams, int nb, int ny, int nlx, int f, double lx, double ly,
+                               double lam, double dz_last) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t total = (int64_t)nb * ny * nlx;
+    if (i >= total) return;
+    int c = (int)(i % nlx);
+    int y = (int)((i / nlx) % ny);
+    int b = (int)(i / ((int64_t)nlx * ny));
+    int4 bm = beams[b];
+    float2 out = make_float2(0.f, 0.f);
+    if (c == bm.x) {
+        double kx = (double)(f * bm.z) / lx, ky = (double)(f * bm.w) / ly;
+        int m = (int)(((int64_t)bm.y * y) % ny);
+        double ph = -lam * dz_last * (kx * kx + ky * ky) - 2.0 * (double)m / (double)ny;  // in units of pi
+        double s, co;
+        sincospi(ph, &s, &co);
+        out = make_float2((float)co, (float)s);
+    }
+    S[i] = out;
+}
+
+__global__ void k_fill_zero(float4* p, int64_t n4) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n4; i += stride) p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+__global__ void k_fill_zero_d(double* p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+// Copy real-space rows of a window buffer holding full planes (diagnostics).
+__global__ void k_copy(float2* dst, const float2* src, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+// --------------------------------------------------------------------- row pass
+//
+// One thread group of T = N/8 threads per row; a block holds S = 256/T rows of the flat
+// row index g = beam * ny + y.  mode 0: forward sweep, mode 1: transposed sweep.
+template <int N, int MODE>
+__global__ __launch_bounds__(256) void k_row_pass(float2* __restrict__ state, int nbeam, int ny, int nlx, int hlx,
+                                                  const float2* __restrict__ Tj, const float2* __restrict__ tw,
+                                                  const int* __restrict__ cap_ptr, const int4* __restrict__ cap_rec,
+                                                  float2* __restrict__ win, int64_t win_beams, int Kpad) {
+    constexpr int E = 8;
+    constexpr int T = N / E;
+    constexpr int S = 256 / T;
+    __shared__ float2 lds[S * N];
+    const int tid = threadIdx.x;
+    const int64_t total = (int64_t)nbeam * ny;
+    const int64_t g0 = (int64_t)blockIdx.x * S;
+    const bool all_live = (nlx == N);
+
+    // load live columns, zero the rest
+    for (int idx = tid; idx < S * N; idx += 256) {
+        int s = idx / N, x = idx % N;
+        int64_t g = g0 + s;
+        int c = all_live ? x : (x <= hlx ? x : (x >= N - hlx ? x - N + nlx : -1));
+        float2 v = make_float2(0.f, 0.f);
+        if (g < total && c >= 0) v = state[g * nlx + c];
+        lds[idx] = v;
+    }
+    __syncthreads();
+
+    const int s = tid / T, t = tid % T;
+    const int64_t g = g0 + s;
+    const bool valid = g < total;
+    const int y = valid ? (int)(g % ny) : 0;
+    const int64_t beam = valid ? g / ny : 0;
+    const int base = s * N;
+
+    if constexpr (MODE == 0) fft_lds<N, E, +1>(lds, base, 1, t, tw);
+    else fft_lds<N, E, -1>(lds, base, 1, t, tw);
+
+    // capture (forward: before T; transposed: after T)
+    auto capture = [&]() {
+        if (cap_ptr && valid) {
+            int r0 = cap_ptr[y], r1 = cap_ptr[y + 1];
+            for (int r = r0; r < r1; ++r) {
+                int4 rec = cap_rec[r];
+                float2* dst = win + ((int64_t)rec.x * win_beams + beam) * Kpad + (int64_t)rec.y * rec.w;
+                for (int u = t; u < rec.w; u += T) {
+                    int x = rec.z + u;
+                    if (x >= N) x -= N;
+                    dst[u] = lds[base + x];
+                }
+            }
+        }
+    };
+    // capture and the T multiply touch pixels owned by other threads of the row: keep
+    // them apart with barriers
+    if constexpr (MODE == 0) {
+        capture();
+        __syncthreads();
+    }
+    const float2* Trow = Tj + (int64_t)y * N;
+    for (int x = t; x < N; x += T) lds[base + x] = cmul(lds[base + x], Trow[x]);
+    __syncthreads();
+    if constexpr (MODE == 1) capture();
+
+    if constexpr (MODE == 0) fft_lds<N, E, -1>(lds, base, 1, t, tw);
+    else fft_lds<N, E, +1>(lds, base, 1, t, tw);
+
+    for (int idx = tid; idx < S * nlx; idx += 256) {
+        int ss = idx / nlx, c = idx % nlx;
+        int64_t gg = g0 + ss;
+        if (gg >= total) continue;
+        int x = all_live ? c : (c <= hlx ? c : c - nlx + N);
+        state[gg * nlx + c] = lds[ss * N + x];
+    }
+}
+
+// --------------------------------------------------------------------- column pass
+//
+// A block transforms CW live columns of one beam along y.  Thread (col, t) with
+// col = tid % CW works on column col; T threads per column, E = N / T elements each.
+template <int N>
+struct ColCfg {
+    static constexpr int NT = N >= 1024 ? 512 : 256;
+    static constexpr int T = N >= 1024 ? 64 : (N >= 512 ? 32 : (N / 8 < 16 ? N / 8 : 16));
+    static constexpr int CW = NT / T;
+    static constexpr int E = N / T;
+};
+
+template <int N, int MODE>
+__global__ __launch_bounds__(ColCfg<N>::NT) void k_col_pass(float2* __restrict__ state, int nbeam, int nlx,
+                                                            const float2* __restrict__ Pj,
+                                                            const float2* __restrict__ tw) {
+    using C = ColCfg<N>;
+    constexpr int CW = C::CW, T = C::T, E = C::E, NT = C::NT;
+    __shared__ float2 lds[N * CW];
+    const int tid = threadIdx.x;
+    const int strips = (nlx + CW - 1) / CW;
+    const int64_t beam = blockIdx.x / strips;
+    const int c0 = (int)(blockIdx.x % strips) * CW;
+    float2* plane = state + beam * (int64_t)N * nlx;
+
+    for (int idx = tid; idx < N * CW; idx += NT) {
+        int row = idx / CW, cc = idx % CW;
+        int c = c0 + cc;
+        lds[idx] = c < nlx ? plane[(int64_t)row * nlx + c] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    const int col = tid % CW, t = tid / CW;
+    if constexpr (MODE == 0) fft_lds<N, E, -1>(lds, col, CW, t, tw);
+    else fft_lds<N, E, +1>(lds, col, CW, t, tw);
+    const int c = c0 + col;
+    for (int i = t; i < N; i += T) {
+        float2 pv = c < nlx ? Pj[(int64_t)i * nlx + c] : make_float2(0.f, 0.f);
+        lds[i * CW + col] = cmul(lds[i * CW + col], pv);
+    }
+    __syncthreads();
+    if constexpr (MODE == 0) fft_lds<N, E, +1>(lds, col, CW, t, tw);
+    else fft_lds<N, E, -1>(lds, col, CW, t, tw);
+
+    for (int idx = tid; idx < N * CW; idx += NT) {
+        int row = idx / CW, cc = idx % CW;
+        int cg = c0 + cc;
+        if (cg < nlx) plane[(int64_t)row * nlx + cg] = lds[idx];
+    }
+}
+
+// --------------------------------------------------------------------- deterministic reduction
+//
+// map[R] += scale * sum over the CSR entries (desc, column i) of R of
+//           sum_{tiles mt} sum_{t} part[p_off + mt ld_part + t N_inner + i]   (fixed order)
+__global__ void k_reduce(double* map, int P, const int* __restrict__ rptr, const int2* __restrict__ ent,
+                         const GemmDesc* __restrict__ descs, const float* __restrict__ part, double scale) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= P) return;
+    double acc = 0.0;
+    for (int e = rptr[r]; e < rptr[r + 1]; ++e) {
+        int2 en = ent[e];
+        const GemmDesc& d = descs[en.x];
+        const float* pp = part + d.p_off + en.y;
+        for (int mt = 0; mt < d.tiles_m; ++mt)
+            for (int t = 0; t < d.n_t; ++t) acc += (double)pp[(int64_t)mt * d.ld_part + (int64_t)t * d.N_inner];
+    }
+    map[r] += scale * acc;
+}
+
+// Dense form: every descriptor of the range covers every probe, column i = probe index.
+__global__ void k_reduce_dense(double* map, int P, const GemmDesc* __restrict__ descs, int d_begin, int d_count,
+                               const float* __restrict__ part, double scale) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= P) return;
+    double acc = 0.0;
+    for (int e = 0; e < d_count; ++e) {
+        const GemmDesc& d = descs[d_begin + e];
+        const float* pp = part + d.p_off + r;
+        for (int mt = 0; mt < d.tiles_m; ++mt)
+            for (int t = 0; t < d.n_t; ++t) acc += (double)pp[(int64_t)mt * d.ld_part + (int64_t)t * d.N_inner];
+    }
+    map[r] += scale * acc;
+}
+
+// --------------------------------------------------------------------- launchers
+
+static inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+void launch_twiddles(float2* tw, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_twiddles, dim3(blocks_for(n, 256)), dim3(256), 0, st, tw, n);
+}
+void launch_transmission(float2* T, const float* V, int64_t n, double sigma, hipStream_t st) {
+    hipLaunchKernelGGL(k_transmission, dim3(blocks_for(n, 256)), dim3(256), 0, st, T, V, n, sigma);
+}
+void launch_propagator(float2* P, const double* dz, const Plan& p, hipStream_t st) {
+    int64_t n = (int64_t)p.nz * p.ny * p.nlx;
+    hipLaunchKernelGGL(k_propagator, dim3(blocks_for(n, 256)), dim3(256), 0, st, P, dz, p.nz, p.nx, p.ny, p.nlx, p.hlx,
+                       p.lx, p.ly, p.lam, p.kmax);
+}
+void launch_probe_coefficients(float2* C, const int4* beams, const double* probes, const Plan& p, hipStream_t st) {
+    int64_t n = (int64_t)p.P * p.N1pad;
+    double scale = (double)p.f * p.f / std::sqrt((double)p.N1fine) * p.c_scale;
+    hipLaunchKernelGGL(k_probe_coefficients, dim3(blocks_for(n, 256)), dim3(256), 0, st, C, beams, p.N1, p.N1pad,
+                       probes, p.P, p.f, p.lx, p.ly, p.lam, p.defocus, p.cs, scale);
+}
+void launch_init_forward(float2* S, const int4* beams, const Plan& p, hipStream_t st) {
+    int64_t n = (int64_t)p.N1 * p.ny * p.nlx;
+    hipLaunchKernelGGL(k_init_forward, dim3(blocks_for(n, 256)), dim3(256), 0, st, S, beams, p.N1, p.ny, p.nlx);
+}
+void launch_init_reverse(float2* S, const int4* beams, const Plan& p, hipStream_t st) {
+    int64_t n = (int64_t)p.N2 * p.ny * p.nlx;
+    hipLaunchKernelGGL(k_init_reverse, dim3(blocks_for(n, 256)), dim3(256), 0, st, S, beams, p.N2, p.ny, p.nlx, p.f,
+                       p.lx, p.ly, p.lam, p.dz[p.nz - 1]);
+}
+void launch_fill_zero(void* ptr, size_t bytes, hipStream_t st) {
+    int64_t n4 = (int64_t)(bytes / 16);
+    if (n4 <= 0) return;
+    int64_t blocks = std::min<int64_t>(blocks_for(n4, 256), 65536);
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, st, (float4*)ptr, n4);
+}
+void launch_fill_zero_d(double* p, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_zero_d, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n);
+}
+void launch_copy(float2* dst, const float2* src, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_copy, dim3(blocks_for(n, 256)), dim3(256), 0, st, dst, src, n);
+}
+
+template <int N, int MODE>
+static void row_pass_n(const RowPassArgs& a, hipStream_t st) {
+    constexpr int S = 256 / (N / 8);
+    int64_t rows = (int64_t)a.nbeam * a.ny;
+    hipLaunchKernelGGL((k_row_pass<N, MODE>), dim3(blocks_for(rows, S)), dim3(256), 0, st, a.state, a.nbeam, a.ny,
+                       a.nlx, a.hlx, a.Tj, a.tw, a.cap_ptr, (const int4*)a.cap_rec, a.win, a.win_beams, a.Kpad);
+}
+
+void launch_row_pass(int nx, int mode, const RowPassArgs& a, hipStream_t st) {
+#define ROWCASE(NN)                                   \
+    case NN:                                          \
+        if (mode == 0) row_pass_n<NN, 0>(a, st);      \
+        else row_pass_n<NN, 1>(a, st);                \
+        break;
+    switch (nx) {
+        ROWCASE(16) ROWCASE(32) ROWCASE(64) ROWCASE(128) ROWCASE(256) ROWCASE(512) ROWCASE(1024)
+        default: break;
+    }
+#undef ROWCASE
+}
+
+template <int N, int MODE>
+static void col_pass_n(float2* state, int nbeam, int nlx, const float2* Pj, const float2* tw, hipStream_t st) {
+    using C = ColCfg<N>;
+    int strips = (nlx + C::CW - 1) / C::CW;
+    hipLaunchKernelGGL((k_col_pass<N, MODE>), dim3((unsigned)((int64_t)nbeam * strips)), dim3(C::NT), 0, st, state,
+                       nbeam, nlx, Pj, tw);
+}
+
+void launch_col_pass(int ny, int mode, float2* state, int nbeam, int nlx, const float2* Pj, const float2* tw,
+                     hipStream_t st) {
+#define COLCASE(NN)                                                   \
+    case NN:                                                          \
+        if (mode == 0) col_pass_n<NN, 0>(state, nbeam, nlx, Pj, tw, st); \
+        else col_pass_n<NN, 1>(state, nbeam, nlx, Pj, tw, st);        \
+        break;
+    switch (ny) {
+        COLCASE(16) COLCASE(32) COLCASE(64) COLCASE(128) COLCASE(256) COLCASE(512) COLCASE(1024)
+        default: break;
+    }
+#undef COLCASE
+}
+
+void launch_reduce(double* map, int P, const int* rptr, const int* ent, const GemmDesc* descs, const float* part,
+                   double scale, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce, dim3(blocks_for(P, 256)), dim3(256), 0, st, map, P, rptr, (const int2*)ent, descs,
+                       part, scale);
+}
+void launch_reduce_dense(double* map, int P, const GemmDesc* descs, int d_begin, int d_count, const float* part,
+                         double scale, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_dense, dim3(blocks_for(P, 256)), dim3(256), 0, st, map, P, descs, d_begin, d_count,
+                       part, scale);
+}
+
+}  // namespace eels

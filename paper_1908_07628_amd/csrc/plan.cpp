@@ -1,0 +1,533 @@
+// Host planner: validates a problem and lays out every table and buffer the device
+// path needs.  Pure host code (no HIP calls), so plans can be built without a GPU.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace eels {
+
+namespace {
+
+constexpr double kH = 6.62607015e-34;       // Planck constant (J s)
+constexpr double kM0 = 9.1093837015e-31;    // electron rest mass (kg)
+constexpr double kE = 1.602176634e-19;      // elementary charge (C)
+constexpr double kC = 299792458.0;          // speed of light (m/s)
+
+// Relativistic wavelength in Angstrom (Sec. 2: lambda of the relativistic electron).
+double wavelength_A(double eV) {
+    double eE = kE * eV;
+    double p = std::sqrt(2.0 * kM0 * eE * (1.0 + eE / (2.0 * kM0 * kC * kC)));
+    return kH / p * 1e10;
+}
+
+// sigma = 2 pi m e lambda / h^2 with m the relativistic mass, in rad/(V*Angstrom).
+double sigma_VA(double eV, double lam_A) {
+    double gamma = 1.0 + kE * eV / (kM0 * kC * kC);
+    double s = 2.0 * M_PI * gamma * kM0 * kE * (lam_A * 1e-10) / (kH * kH);
+    return s * 1e-10;
+}
+
+bool pow2_ok(int n) { return n >= 16 && n <= 1024 && (n & (n - 1)) == 0; }
+
+// Plane waves k = (f a / lx, f b / ly) with th_lo <= lambda |k| <= th_hi, ordered by (b, a).
+std::vector<int> lattice(double lx, double ly, int f, double lam, double th_lo, double th_hi) {
+    int amax = (int)std::floor(th_hi / lam * lx / f) + 1;
+    int bmax = (int)std::floor(th_hi / lam * ly / f) + 1;
+    std::vector<int> out;
+    for (int b = -bmax; b <= bmax; ++b)
+        for (int a = -amax; a <= amax; ++a) {
+            double kx = (double)(f * a) / lx, ky = (double)(f * b) / ly;
+            double th = lam * std::sqrt(kx * kx + ky * ky);
+            if (th >= th_lo && th <= th_hi) {
+                out.push_back(a);
+                out.push_back(b);
+            }
+        }
+    return out;
+}
+
+int imod(long long a, int n) { long long r = a % n; return (int)(r < 0 ? r + n : r); }
+
+struct Blob {
+    std::vector<int32_t>& v;
+    int64_t append(const int32_t* p, size_t n, size_t align_ints = 4) {
+        while (v.size() % align_ints) v.push_back(0);
+        int64_t off = (int64_t)v.size();
+        v.insert(v.end(), p, p + n);
+        return off;
+    }
+    int64_t append(const std::vector<int32_t>& x, size_t align_ints = 4) { return append(x.data(), x.size(), align_ints); }
+};
+
+}  // namespace
+
+static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_reserve) {
+    auto fail = [&](eels_status s, const std::string& m) { set_error(m); return s; };
+    if (q.nx <= 0 || q.ny <= 0 || !(q.lx_A > 0) || !(q.ly_A > 0) || q.n_slices <= 0 || !q.dz_A)
+        return fail(EELS_ERR_INVALID_ARG, "grid, cell or slices invalid");
+    if (!pow2_ok(q.nx) || !pow2_ok(q.ny))
+        return fail(EELS_ERR_UNSUPPORTED_SIZE, "grid sides must be powers of two in [16, 1024]");
+    if (q.n_probes <= 0 || !q.probe_xy) return fail(EELS_ERR_INVALID_ARG, "no probes");
+    if (q.n_sites < 0 || (q.n_sites > 0 && !q.sites)) return fail(EELS_ERR_INVALID_ARG, "sites");
+    if (q.interp_f < 1) return fail(EELS_ERR_INVALID_ARG, "interp_f must be >= 1");
+    if (!(q.aperture_mrad > 0) || q.det_inner_mrad < 0 || !(q.det_outer_mrad > q.det_inner_mrad))
+        return fail(EELS_ERR_INVALID_ARG, "aperture / detector angles");
+    if (q.precision < EELS_FP32 || q.precision > EELS_FP16_SPLIT) return fail(EELS_ERR_INVALID_ARG, "precision");
+    if (q.order < EELS_ORDER_AUTO || q.order > EELS_ORDER_PROBE_FIRST) return fail(EELS_ERR_INVALID_ARG, "order");
+    if (!(q.energy_eV > 0) && !(q.lambda_A > 0 && q.sigma > 0)) return fail(EELS_ERR_INVALID_ARG, "energy");
+
+    p.nx = q.nx; p.ny = q.ny; p.lx = q.lx_A; p.ly = q.ly_A; p.nz = q.n_slices;
+    p.dz.assign(q.dz_A, q.dz_A + q.n_slices);
+    for (double d : p.dz) if (!(d > 0)) return fail(EELS_ERR_INVALID_ARG, "slice thickness must be > 0");
+    p.energy = q.energy_eV;
+    p.lam = q.lambda_A > 0 ? q.lambda_A : wavelength_A(q.energy_eV);
+    p.sigma = q.sigma > 0 ? q.sigma : sigma_VA(q.energy_eV, p.lam);
+    p.alpha = q.aperture_mrad * 1e-3;
+    p.beta_in = q.det_inner_mrad * 1e-3;
+    p.beta_out = q.det_outer_mrad * 1e-3;
+    p.defocus = q.defocus_A; p.cs = q.cs_A;
+    p.f = q.interp_f;
+    p.bandlimit = q.bandlimit > 0 ? q.bandlimit : 2.0 / 3.0;
+    if (p.bandlimit > 1.0) return fail(EELS_ERR_INVALID_ARG, "bandlimit must be <= 1");
+    p.window_A = q.window_A;
+    p.P = q.n_probes;
+    p.probes.assign(q.probe_xy, q.probe_xy + 2 * (size_t)q.n_probes);
+    p.sites.assign(q.sites, q.sites + q.n_sites);
+    p.n_trans_total = q.n_trans_total;
+    p.precision = q.precision;
+
+    // band limit (circular, inclusive) and the kx columns it keeps
+    p.kmax = p.bandlimit * std::min(p.nx / (2.0 * p.lx), p.ny / (2.0 * p.ly));
+    p.hlx = (int)std::floor(p.kmax * p.lx + 1e-9);
+    if (2 * p.hlx + 1 >= p.nx) { p.hlx = p.nx / 2; p.nlx = p.nx; }
+    else p.nlx = 2 * p.hlx + 1;
+
+    // beams
+    p.ab1 = lattice(p.lx, p.ly, p.f, p.lam, 0.0, p.alpha);
+    p.ab2 = lattice(p.lx, p.ly, p.f, p.lam, p.beta_in, p.beta_out);
+    p.N1 = (int)p.ab1.size() / 2;
+    p.N2 = (int)p.ab2.size() / 2;
+    p.N1fine = (int)lattice(p.lx, p.ly, 1, p.lam, 0.0, p.alpha).size() / 2;
+    if (p.N1 == 0 || p.N2 == 0) return fail(EELS_ERR_INVALID_ARG, "empty aperture or detector beam set");
+    for (int w = 0; w < 2; ++w) {
+        const auto& ab = w == 0 ? p.ab1 : p.ab2;
+        for (size_t i = 0; i < ab.size(); i += 2) {
+            double kx = (double)(p.f * ab[i]) / p.lx, ky = (double)(p.f * ab[i + 1]) / p.ly;
+            if (std::sqrt(kx * kx + ky * ky) > p.kmax)
+                return fail(EELS_ERR_BANDLIMIT, w == 0 ? "aperture beyond the band limit" : "detector beyond the band limit");
+        }
+    }
+    p.N1pad = (int)round_up(p.N1, KPAD_MULT);
+
+    // crop window (Sec. 4.B): half-widths floor(W / (2 dx) + 1/2)
+    p.full_window = true;
+    if (p.window_A > 0) {
+        int hx = (int)std::floor(p.window_A / (2.0 * p.lx / p.nx) + 0.5);
+        int hy = (int)std::floor(p.window_A / (2.0 * p.ly / p.ny) + 0.5);
+        if (2 * hx + 1 < p.nx && 2 * hy + 1 < p.ny) {
+            p.full_window = false;
+            p.hwx = hx; p.hwy = hy;
+        }
+    }
+    if (p.full_window) { p.nwx = p.nx; p.nwy = p.ny; p.hwx = p.hwy = 0; }
+    else { p.nwx = 2 * p.hwx + 1; p.nwy = 2 * p.hwy + 1; }
+    p.K = p.nwx * p.nwy;
+    p.Kpad = (int)round_up(p.K, KPAD_MULT);
+    if (p.f > 1 && p.full_window) return fail(EELS_ERR_INVALID_ARG, "interp_f > 1 needs a crop window");
+
+    // sites: validation, pixels, eligibility
+    const int S = (int)p.sites.size();
+    p.site_ix0.resize(S); p.site_iy0.resize(S); p.site_probes.assign(S, {});
+    const double dx = p.lx / p.nx, dy = p.ly / p.ny;
+    for (int s = 0; s < S; ++s) {
+        const eels_site& st = p.sites[s];
+        if (st.slice < 0 || st.slice >= p.nz || st.n_trans < 0 || st.h_offset < 0 ||
+            st.h_offset + st.n_trans > p.n_trans_total)
+            return fail(EELS_ERR_INVALID_ARG, "site " + std::to_string(s) + " out of range");
+        p.site_ix0[s] = imod((long long)std::floor(st.x_A / (p.lx / p.nx) + 0.5), p.nx);
+        p.site_iy0[s] = imod((long long)std::floor(st.y_A / (p.ly / p.ny) + 0.5), p.ny);
+        if (p.f > 1) {
+            auto& el = p.site_probes[s];
+            for (int r = 0; r < p.P; ++r) {
+                double ddx = p.site_ix0[s] * dx - p.probes[2 * r];
+                double ddy = p.site_iy0[s] * dy - p.probes[2 * r + 1];
+                ddx = ddx - p.lx * std::floor(ddx / p.lx + 0.5);
+                ddy = ddy - p.ly * std::floor(ddy / p.ly + 0.5);
+                if (std::fabs(ddx) + p.hwx * dx <= p.lx / (2.0 * p.f) &&
+                    std::fabs(ddy) + p.hwy * dy <= p.ly / (2.0 * p.f))
+                    el.push_back(r);
+            }
+        }
+    }
+    auto n_elig = [&](int s) { return p.f > 1 ? (int)p.site_probes[s].size() : p.P; };
+
+    // ionised slices and their sites (sites with no transitions or no eligible probe are skipped)
+    p.slices.assign(p.nz, SliceInfo{});
+    std::vector<std::vector<int>> by_slice(p.nz);
+    for (int s = 0; s < S; ++s)
+        if (p.sites[s].n_trans > 0 && n_elig(s) > 0) by_slice[p.sites[s].slice].push_back(s);
+    std::vector<int> ion;
+    for (int j = 0; j < p.nz; ++j)
+        if (!by_slice[j].empty()) { ion.push_back(j); p.slices[j].ion = true; }
+
+    // contraction order (Eq. TPRISM2 terms; both orders compute the same sums)
+    double fl_S = 0, fl_P = 0;
+    for (int j : ion)
+        for (int s : by_slice[j]) {
+            double nt = p.sites[s].n_trans, Ps = n_elig(s);
+            fl_S += 8.0 * p.N2 * (double)p.K * nt * p.N1 + 8.0 * nt * p.N2 * p.N1 * Ps;
+            fl_P += 8.0 * Ps * (double)p.K * p.N1 + 8.0 * p.N2 * (double)p.K * nt * Ps;
+        }
+    p.order = q.order == EELS_ORDER_AUTO ? (fl_S <= fl_P ? EELS_ORDER_S_FIRST : EELS_ORDER_PROBE_FIRST) : q.order;
+    p.gemm_flops = p.order == EELS_ORDER_S_FIRST ? fl_S : fl_P;
+    p.c_scale = p.precision == EELS_FP16_SPLIT ? 256.0f : 1.0f;
+
+    // windows per slice
+    auto slice_windows = [&](int j) -> int { return p.full_window ? 1 : (int)by_slice[j].size(); };
+    int max_w2 = 0;
+    for (int j : ion) max_w2 = std::max(max_w2, slice_windows(j));
+    p.max_w2 = max_w2;
+
+    // fixed workspace
+    auto A = [](size_t x) { return (size_t)round_up((int64_t)x, 256); };
+    const size_t c8 = 8;  // bytes per complex64
+    size_t fixed = A(blob_reserve)  // table blob (refined by the caller's second pass)
+                   + A(c8 * p.nx) + A(c8 * p.ny) + A(c8 * (size_t)p.nz * p.ny * p.nx) +
+                   A(c8 * (size_t)p.nz * p.ny * p.nlx) + A(c8 * (size_t)p.P * p.N1pad) +
+                   A(c8 * (size_t)p.N1 * p.ny * p.nlx) + A(c8 * (size_t)p.N2 * p.ny * p.nlx) +
+                   A(c8 * (size_t)max_w2 * p.N2 * p.Kpad);
+
+    // batches: mid (Z or Psi) and partial sums per site
+    auto site_mid = [&](int s) -> int64_t {
+        int nt = p.sites[s].n_trans;
+        return p.order == EELS_ORDER_S_FIRST ? (int64_t)nt * p.N2 * p.N1pad : (int64_t)n_elig(s) * p.Kpad;
+    };
+    auto site_part = [&](int s) -> int64_t {
+        int nt = p.sites[s].n_trans;
+        int64_t tm = ceil_div(p.N2, GEMM_BM);
+        return tm * nt * (int64_t)n_elig(s);
+    };
+    size_t budget = q.max_workspace_bytes;
+    size_t batch_cap = SIZE_MAX;
+    const size_t win1_bytes = c8 * (size_t)p.N1 * p.Kpad;
+    if (budget > 0) {
+        if (budget <= fixed) return fail(EELS_ERR_OOM, "memory budget below the fixed workspace");
+        // at least one slice's S_1 windows must fit next to the contraction buffers;
+        // the contraction batches get half of what remains beyond that
+        size_t min_w1 = 0;
+        for (int j : ion) min_w1 = std::max(min_w1, (size_t)slice_windows(j) * win1_bytes);
+        size_t avail = budget - fixed;
+        if (avail <= min_w1 + 4096) return fail(EELS_ERR_OOM, "memory budget too small for one slice's windows");
+        batch_cap = (avail - min_w1 - 4096) / 2;
+    }
+    struct PendingBatch { int slice; std::vector<int> sites; };
+    std::vector<PendingBatch> pend;
+    int64_t max_mid = 0, max_part = 0;
+    for (int j : ion) {
+        PendingBatch cur{j, {}};
+        int64_t m = 0, pt = 0;
+        for (int s : by_slice[j]) {
+            int64_t sm = site_mid(s), sp = site_part(s);
+            size_t bytes_new = (size_t)(m + sm) * 8 + (size_t)(pt + sp) * 4;
+            if (!cur.sites.empty() && bytes_new > batch_cap) {
+                pend.push_back(cur);
+                max_mid = std::max(max_mid, m); max_part = std::max(max_part, pt);
+                cur.sites.clear(); m = 0; pt = 0;
+            }
+            if ((size_t)sm * 8 + (size_t)sp * 4 > batch_cap)
+                return fail(EELS_ERR_OOM, "one site's contraction does not fit the budget");
+            cur.sites.push_back(s); m += sm; pt += sp;
+        }
+        pend.push_back(cur);
+        max_mid = std::max(max_mid, m); max_part = std::max(max_part, pt);
+    }
+    p.mid_elems = max_mid;
+    p.part_elems = max_part;
+
+    // slice groups (descending): S_1 windows of a group must fit what is left
+    size_t w1_cap = SIZE_MAX;
+    if (budget > 0) {
+        size_t used = fixed + A((size_t)max_mid * 8) + A((size_t)max_part * 4);
+        if (budget <= used) return fail(EELS_ERR_OOM, "memory budget too small");
+        w1_cap = budget - used;
+    }
+    p.groups.clear();
+    p.site_w1.assign(S, -1);
+    p.site_w2.assign(S, -1);
+    {
+        int gi = -1;
+        size_t gbytes = 0;
+        int gwin = 0;
+        for (int idx = (int)ion.size() - 1; idx >= 0; --idx) {
+            int j = ion[idx];
+            size_t need = (size_t)slice_windows(j) * win1_bytes;
+            if (need > w1_cap) return fail(EELS_ERR_OOM, "one slice's S_1 windows exceed the budget");
+            if (gi < 0 || gbytes + need > w1_cap) {
+                p.groups.push_back(Group{j, j, 0});
+                gi = (int)p.groups.size() - 1;
+                gbytes = 0; gwin = 0;
+            }
+            Group& g = p.groups[gi];
+            g.j_lo = j;
+            p.slices[j].group = gi;
+            int base = gwin;
+            if (p.full_window) {
+                for (int s : by_slice[j]) p.site_w1[s] = base;
+                gwin += 1;
+            } else {
+                for (size_t t = 0; t < by_slice[j].size(); ++t) p.site_w1[by_slice[j][t]] = base + (int)t;
+                gwin += (int)by_slice[j].size();
+            }
+            g.n_windows = gwin;
+            gbytes += need;
+        }
+    }
+    p.max_w1 = 0;
+    for (auto& g : p.groups) p.max_w1 = std::max(p.max_w1, g.n_windows);
+    for (int j : ion) {
+        const auto& v = by_slice[j];
+        for (size_t t = 0; t < v.size(); ++t) p.site_w2[v[t]] = p.full_window ? 0 : (int)t;
+    }
+
+    // ---- table blob
+    p.blob.clear();
+    Blob B{p.blob};
+    auto live_col = [&](int ix) -> int {
+        if (p.nlx == p.nx) return ix;
+        if (ix <= p.hlx) return ix;
+        return ix - p.nx + p.nlx;
+    };
+    {
+        std::vector<int32_t> t;
+        for (int b = 0; b < p.N1; ++b) {
+            int a = p.ab1[2 * b], bb = p.ab1[2 * b + 1];
+            t.push_back(live_col(imod((long long)p.f * a, p.nx)));
+            t.push_back(imod((long long)p.f * bb, p.ny));
+            t.push_back(a); t.push_back(bb);
+        }
+        p.b1_off = B.append(t);
+        t.clear();
+        for (int b = 0; b < p.N2; ++b) {
+            int a = p.ab2[2 * b], bb = p.ab2[2 * b + 1];
+            t.push_back(live_col(imod((long long)p.f * a, p.nx)));
+            t.push_back(imod((long long)p.f * bb, p.ny));
+            t.push_back(a); t.push_back(bb);
+        }
+        p.b2_off = B.append(t);
+        t.resize(p.P);
+        for (int r = 0; r < p.P; ++r) t[r] = r;
+        p.ident_off = B.append(t);
+    }
+    // capture CSRs per ionised slice
+    for (int j : ion) {
+        for (int which = 0; which < 2; ++which) {
+            std::vector<std::vector<CaptureRec>> rows(p.ny);
+            if (p.full_window) {
+                int w = which == 0 ? p.site_w1[by_slice[j][0]] : 0;
+                for (int y = 0; y < p.ny; ++y) rows[y].push_back(CaptureRec{w, y, 0, p.nx});
+            } else {
+                for (int s : by_slice[j]) {
+                    int w = which == 0 ? p.site_w1[s] : p.site_w2[s];
+                    for (int v = 0; v < p.nwy; ++v) {
+                        int y = imod((long long)p.site_iy0[s] - p.hwy + v, p.ny);
+                        rows[y].push_back(CaptureRec{w, v, imod((long long)p.site_ix0[s] - p.hwx, p.nx), p.nwx});
+                    }
+                }
+            }
+            std::vector<int32_t> ptr(p.ny + 1, 0), rec;
+            for (int y = 0; y < p.ny; ++y) {
+                for (auto& r : rows[y]) { rec.push_back(r.win); rec.push_back(r.dy); rec.push_back(r.x0); rec.push_back(r.nwx); }
+                ptr[y + 1] = (int32_t)(rec.size() / 4);
+            }
+            int64_t po = B.append(ptr), ro = B.append(rec);
+            if (which == 0) { p.slices[j].cap1_ptr = po; p.slices[j].cap1_rec = ro; }
+            else { p.slices[j].cap2_ptr = po; p.slices[j].cap2_rec = ro; }
+        }
+    }
+    // eligible-probe lists
+    std::vector<int64_t> site_idx(S, -1);
+    for (int s = 0; s < S; ++s) {
+        if (p.f > 1 && !p.site_probes[s].empty())
+            site_idx[s] = B.append(std::vector<int32_t>(p.site_probes[s].begin(), p.site_probes[s].end()));
+        else site_idx[s] = p.ident_off;
+    }
+    // descriptors and reduction CSRs
+    p.descs.clear();
+    p.batches.clear();
+    const int64_t w1_stride = (int64_t)p.N1 * p.Kpad, w2_stride = (int64_t)p.N2 * p.Kpad;
+    for (auto& pb : pend) {
+        Batch bt{};
+        bt.slice = pb.slice;
+        bt.order = p.order;
+        int64_t moff = 0, poff = 0;
+        std::vector<int> d2_of_site;
+        bt.d1_begin = (int)p.descs.size();
+        int tiles = 0;
+        std::vector<int64_t> site_moff;
+        for (int s : pb.sites) {
+            const eels_site& st = p.sites[s];
+            int Ps = n_elig(s);
+            GemmDesc d{};
+            site_moff.push_back(moff);
+            if (p.order == EELS_ORDER_S_FIRST) {
+                // Z_s[t][q][k] = sum_r S2w[q][r] H_t[r] S1w[k][r]
+                d.a_off = (int64_t)p.site_w2[s] * w2_stride; d.lda = p.Kpad;
+                d.b_off = (int64_t)p.site_w1[s] * w1_stride; d.ldb = p.Kpad;
+                d.h_off = st.h_offset * p.K; d.ldh = p.K;
+                d.c_off = moff; d.ldc_m = p.N1pad; d.ldc_t = (int64_t)p.N2 * p.N1pad;
+                d.M = p.N2; d.N_inner = p.N1; d.n_t = st.n_trans; d.K = p.K;
+                d.idx_off = -1;
+            } else {
+                // Psi_s[i][r] = sum_k C[idx[i]][k] S1w[k][r]   (B operand N-contiguous)
+                d.a_off = 0; d.lda = p.N1pad;
+                d.b_off = (int64_t)p.site_w1[s] * w1_stride; d.ldb = p.Kpad;
+                d.h_off = -1; d.ldh = 0;
+                d.c_off = moff; d.ldc_m = p.Kpad; d.ldc_t = 0;
+                d.M = Ps; d.N_inner = p.K; d.n_t = 1; d.K = p.N1;
+                d.idx_off = (int)site_idx[s];
+            }
+            d.a_tstride = 0;
+            d.tiles_m = (int)ceil_div(d.M, GEMM_BM);
+            d.tiles_n = (int)ceil_div(d.N_inner, GEMM_BN);
+            d.tile_start = tiles;
+            tiles += d.tiles_m * d.tiles_n * d.n_t;
+            p.descs.push_back(d);
+            moff += site_mid(s);
+        }
+        bt.d1_count = (int)p.descs.size() - bt.d1_begin;
+        bt.d1_tiles = tiles;
+        // second GEMM
+        bt.d2_begin = (int)p.descs.size();
+        tiles = 0;
+        std::vector<std::vector<int32_t>> ent(p.P);
+        for (size_t si = 0; si < pb.sites.size(); ++si) {
+            int s = pb.sites[si];
+            const eels_site& st = p.sites[s];
+            int Ps = n_elig(s);
+            const std::vector<int>* pl = p.f > 1 ? &p.site_probes[s] : nullptr;
+            auto add = [&](GemmDesc d) {
+                d.tiles_m = (int)ceil_div(d.M, GEMM_BM);
+                d.tiles_n = (int)ceil_div(d.N_inner, GEMM_BN);
+                d.tile_start = tiles;
+                d.p_off = poff; d.ld_part = (int64_t)d.n_t * d.N_inner;
+                poff += (int64_t)d.tiles_m * d.ld_part;
+                tiles += d.tiles_m * d.tiles_n * d.n_t;
+                int di = (int)p.descs.size();
+                p.descs.push_back(d);
+                if (p.f > 1)
+                    for (int i = 0; i < Ps; ++i) {
+                        int r = pl ? (*pl)[i] : i;
+                        ent[r].push_back(di);
+                        ent[r].push_back(i);
+                    }
+            };
+            GemmDesc d{};
+            if (p.order == EELS_ORDER_S_FIRST) {
+                // A_n(q, R) = sum_k Z_s[t][q][k] C[R][k]
+                d.a_off = site_moff[si]; d.lda = p.N1pad; d.a_tstride = (int64_t)p.N2 * p.N1pad;
+                d.b_off = 0; d.ldb = p.N1pad;
+                d.h_off = -1; d.ldh = 0;
+                d.M = p.N2; d.N_inner = Ps; d.n_t = st.n_trans; d.K = p.N1;
+                d.idx_off = (int)site_idx[s];
+            } else {
+                // A_n(q, R) = sum_r S2w[q][r] H_t[r] Psi_s[i][r]
+                d.a_off = (int64_t)p.site_w2[s] * w2_stride; d.lda = p.Kpad; d.a_tstride = 0;
+                d.b_off = site_moff[si]; d.ldb = p.Kpad;
+                d.h_off = st.h_offset * p.K; d.ldh = p.K;
+                d.M = p.N2; d.N_inner = Ps; d.n_t = st.n_trans; d.K = p.K;
+                d.idx_off = -1;
+            }
+            add(d);
+        }
+        bt.d2_count = (int)p.descs.size() - bt.d2_begin;
+        bt.d2_tiles = tiles;
+        if (p.f > 1) {
+            std::vector<int32_t> ptr(p.P + 1, 0), flat;
+            for (int r = 0; r < p.P; ++r) {
+                flat.insert(flat.end(), ent[r].begin(), ent[r].end());
+                ptr[r + 1] = (int32_t)(flat.size() / 2);
+            }
+            bt.red_ptr = B.append(ptr);
+            bt.red_ent = B.append(flat);
+            bt.n_entries = (int64_t)flat.size() / 2;
+        } else {
+            bt.red_ptr = bt.red_ent = -1;   // every site covers every probe in order
+            bt.n_entries = 0;
+        }
+        p.slices[pb.slice].batches.push_back((int)p.batches.size());
+        p.batches.push_back(bt);
+    }
+
+    // doubles, diagnostics capture table, descriptors
+    {
+        std::vector<int32_t> t(2 * p.dz.size());
+        std::memcpy(t.data(), p.dz.data(), 8 * p.dz.size());
+        p.dz_off = B.append(t);
+        t.resize(2 * p.probes.size());
+        std::memcpy(t.data(), p.probes.data(), 8 * p.probes.size());
+        p.probes_off = B.append(t);
+        std::vector<int32_t> ptr(p.ny + 1), rec;
+        for (int y = 0; y < p.ny; ++y) {
+            rec.push_back(0); rec.push_back(y); rec.push_back(0); rec.push_back(p.nx);
+            ptr[y + 1] = y + 1;
+        }
+        ptr[0] = 0;
+        p.dbg_ptr = B.append(ptr);
+        p.dbg_rec = B.append(rec);
+        std::vector<int32_t> dd(p.descs.size() * sizeof(GemmDesc) / 4);
+        if (!p.descs.empty()) std::memcpy(dd.data(), p.descs.data(), p.descs.size() * sizeof(GemmDesc));
+        p.descs_off = B.append(dd);
+    }
+
+    // algorithmic sweep traffic: two passes per beam-slice, each reading and writing the
+    // live columns of the beam's plane
+    double fwd = 0, rev = 0;
+    if (!ion.empty()) {
+        for (auto& g : p.groups) fwd += (double)(g.j_hi + 1) * p.N1;
+        rev = (double)(p.nz - ion.front()) * p.N2;
+    }
+    p.sweep_beam_slices = fwd + rev;
+    p.sweep_bytes = p.sweep_beam_slices * 32.0 * p.ny * p.nlx;
+
+    // ---- workspace layout
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += A(bytes); return o; };
+    p.off_blob = take(p.blob.size() * 4);
+    p.off_twx = take(c8 * p.nx);
+    p.off_twy = take(c8 * p.ny);
+    p.off_T = take(c8 * (size_t)p.nz * p.ny * p.nx);
+    p.off_P = take(c8 * (size_t)p.nz * p.ny * p.nlx);
+    p.off_C = take(c8 * (size_t)p.P * p.N1pad);
+    p.off_s1 = take(c8 * (size_t)p.N1 * p.ny * p.nlx);
+    p.off_s2 = take(c8 * (size_t)p.N2 * p.ny * p.nlx);
+    p.off_w1 = take(c8 * (size_t)std::max(p.max_w1, 1) * p.N1 * p.Kpad);
+    p.off_w2 = take(c8 * (size_t)std::max(p.max_w2, 1) * p.N2 * p.Kpad);
+    p.off_mid = take(c8 * (size_t)std::max<int64_t>(p.mid_elems, 1) + 4096);
+    p.off_part = take(4 * (size_t)std::max<int64_t>(p.part_elems, 1));
+    p.ws_bytes = off;
+    if (budget > 0 && p.ws_bytes > budget) return fail(EELS_ERR_OOM, "workspace exceeds the memory budget");
+    return EELS_OK;
+}
+
+// The table blob's size is known only after planning; plan with a reserve, then again
+// with the measured size if the budget was missed.
+eels_status build_plan(Plan& p, const eels_problem& q) {
+    size_t reserve = 64 << 10;
+    eels_status s = EELS_OK;
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        p = Plan{};
+        s = build_plan_impl(p, q, reserve);
+        if (s != EELS_ERR_OOM || q.max_workspace_bytes == 0) return s;
+        size_t need = p.blob.size() * 4 + (64 << 10);
+        if (p.blob.empty() || need <= reserve) return s;
+        reserve = need;
+    }
+    return s;
+}
+
+}  // namespace eels

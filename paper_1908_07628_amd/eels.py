@@ -1,0 +1,240 @@
+"""ctypes binding of libeels.so (argument marshalling only).
+
+Every step of the EELS map runs in the library's HIP kernels; PyTorch provides the
+device buffers and the stream.  A missing library raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Any, Dict, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libeels.so")
+
+FP32, BF16_SPLIT, FP16_SPLIT = 0, 1, 2
+ORDER_AUTO, ORDER_S_FIRST, ORDER_PROBE_FIRST = 0, 1, 2
+PRECISIONS = {"fp32": FP32, "bf16_split": BF16_SPLIT, "fp16_split": FP16_SPLIT}
+ORDERS = {"auto": ORDER_AUTO, "s_first": ORDER_S_FIRST, "probe_first": ORDER_PROBE_FIRST}
+
+STATUS = {0: "ok", 1: "invalid argument", 2: "band limit", 3: "unsupported size", 4: "workspace",
+          5: "out of memory budget", 6: "device error", 7: "cancelled", 8: "internal"}
+
+
+class EelsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"eels status {status} ({STATUS.get(status, '?')}): {msg}")
+        self.status = status
+
+
+class Site(C.Structure):
+    _fields_ = [("slice", C.c_int), ("n_trans", C.c_int), ("x_A", C.c_double), ("y_A", C.c_double),
+                ("h_offset", C.c_int64)]
+
+
+class ProblemC(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("lx_A", C.c_double), ("ly_A", C.c_double),
+                ("n_slices", C.c_int), ("dz_A", C.POINTER(C.c_double)), ("energy_eV", C.c_double),
+                ("lambda_A", C.c_double), ("sigma", C.c_double), ("aperture_mrad", C.c_double),
+                ("det_inner_mrad", C.c_double), ("det_outer_mrad", C.c_double), ("defocus_A", C.c_double),
+                ("cs_A", C.c_double), ("interp_f", C.c_int), ("bandlimit", C.c_double),
+                ("window_A", C.c_double), ("n_probes", C.c_int), ("probe_xy", C.POINTER(C.c_double)),
+                ("n_sites", C.c_int), ("sites", C.POINTER(Site)), ("n_trans_total", C.c_int64),
+                ("precision", C.c_int), ("order", C.c_int), ("max_workspace_bytes", C.c_size_t)]
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [("n_beams_in", C.c_int), ("n_beams_out", C.c_int), ("n_beams_in_fine", C.c_int),
+                ("n_live_x", C.c_int), ("window_nx", C.c_int), ("window_ny", C.c_int), ("k_pixels", C.c_int),
+                ("k_stride", C.c_int), ("n_ion_slices", C.c_int), ("n_groups", C.c_int), ("n_batches", C.c_int),
+                ("order", C.c_int), ("lambda_A", C.c_double), ("sigma", C.c_double), ("gemm_flops", C.c_double),
+                ("sweep_bytes", C.c_double), ("sweep_beam_slices", C.c_double), ("workspace_bytes", C.c_size_t)]
+
+
+_LIB: Optional[C.CDLL] = None
+
+EXPORTS = ["eels_get_version", "eels_status_string", "eels_last_error", "eels_plan_create",
+           "eels_plan_workspace_bytes", "eels_plan_info_get", "eels_plan_beams", "eels_plan_destroy",
+           "eels_execute", "eels_debug_s1", "eels_debug_s2", "eels_gemm_work_bytes", "eels_debug_cgemm"]
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise ImportError(f"libeels.so not built ({path}); run __graft_entry__.build()")
+    lib = C.CDLL(path)
+    vp, sz = C.c_void_p, C.c_size_t
+    lib.eels_get_version.argtypes = [C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    lib.eels_status_string.restype = C.c_char_p
+    lib.eels_last_error.restype = C.c_char_p
+    lib.eels_plan_create.argtypes = [C.POINTER(vp), C.POINTER(ProblemC)]
+    lib.eels_plan_workspace_bytes.argtypes = [vp, C.POINTER(sz)]
+    lib.eels_plan_info_get.argtypes = [vp, C.POINTER(PlanInfo)]
+    lib.eels_plan_beams.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.c_int]
+    lib.eels_plan_destroy.argtypes = [vp]
+    lib.eels_execute.argtypes = [vp, vp, vp, vp, vp, sz, vp]
+    lib.eels_debug_s1.argtypes = [vp, vp, C.c_int, vp, vp, sz, vp]
+    lib.eels_debug_s2.argtypes = [vp, vp, C.c_int, vp, vp, sz, vp]
+    lib.eels_gemm_work_bytes.argtypes = [C.c_int, C.c_int]
+    lib.eels_gemm_work_bytes.restype = sz
+    lib.eels_debug_cgemm.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp, C.c_int,
+                                     vp, vp, vp]
+    _LIB = lib
+    return lib
+
+
+def _check(st: int):
+    if st != 0:
+        msg = load_library().eels_last_error().decode(errors="replace")
+        raise EelsError(st, msg)
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def _stream(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+class Plan:
+    """Host plan of one map request.  ``problem`` is any object with the fields of the
+    problem statement (grid, cell, slices, optics, sites, probes; see include/eels.h)."""
+
+    def __init__(self, problem: Any, precision: str = "fp32", order: str = "auto",
+                 max_workspace_bytes: int = 0, lambda_A: float = 0.0, sigma: float = 0.0):
+        lib = load_library()
+        pr = problem
+        self._dz = np.ascontiguousarray(pr.dz, dtype=np.float64)
+        self._probes = np.ascontiguousarray(pr.probes, dtype=np.float64).reshape(-1, 2)
+        S = len(pr.site_slice)
+        self._sites = (Site * max(S, 1))()
+        for s in range(S):
+            self._sites[s] = Site(int(pr.site_slice[s]), int(pr.site_ntrans[s]), float(pr.site_xy[s][0]),
+                                  float(pr.site_xy[s][1]), int(pr.site_hoff[s]))
+        n_trans = int(pr.H.shape[0]) if getattr(pr, "H", None) is not None else int(
+            max([int(pr.site_hoff[s]) + int(pr.site_ntrans[s]) for s in range(S)], default=0))
+        self.problem = ProblemC(
+            nx=int(pr.nx), ny=int(pr.ny), lx_A=float(pr.lx), ly_A=float(pr.ly), n_slices=len(self._dz),
+            dz_A=self._dz.ctypes.data_as(C.POINTER(C.c_double)), energy_eV=float(pr.energy_eV),
+            lambda_A=float(lambda_A), sigma=float(sigma), aperture_mrad=float(pr.aperture_mrad),
+            det_inner_mrad=float(pr.det_inner_mrad), det_outer_mrad=float(pr.det_outer_mrad),
+            defocus_A=float(getattr(pr, "defocus_A", 0.0)), cs_A=float(getattr(pr, "cs_A", 0.0)),
+            interp_f=int(pr.interp_f), bandlimit=float(pr.bandlimit), window_A=float(pr.window_A),
+            n_probes=int(self._probes.shape[0]),
+            probe_xy=self._probes.ctypes.data_as(C.POINTER(C.c_double)), n_sites=S,
+            sites=self._sites, n_trans_total=n_trans, precision=PRECISIONS[precision], order=ORDERS[order],
+            max_workspace_bytes=int(max_workspace_bytes))
+        self.precision = precision
+        h = C.c_void_p()
+        _check(lib.eels_plan_create(C.byref(h), C.byref(self.problem)))
+        self._h = h
+        self.n_probes = int(self._probes.shape[0])
+        self.nx, self.ny, self.n_slices = int(pr.nx), int(pr.ny), len(self._dz)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _LIB is not None:
+            _LIB.eels_plan_destroy(h)
+            self._h = None
+
+    @property
+    def workspace_bytes(self) -> int:
+        v = C.c_size_t()
+        _check(load_library().eels_plan_workspace_bytes(self._h, C.byref(v)))
+        return int(v.value)
+
+    def info(self) -> Dict[str, Any]:
+        inf = PlanInfo()
+        _check(load_library().eels_plan_info_get(self._h, C.byref(inf)))
+        return {name: getattr(inf, name) for name, _ in PlanInfo._fields_}
+
+    def beams(self, which: int) -> np.ndarray:
+        inf = self.info()
+        n = inf["n_beams_in"] if which == 0 else inf["n_beams_out"]
+        buf = (C.c_int * (2 * n))()
+        _check(load_library().eels_plan_beams(self._h, which, buf, n))
+        return np.frombuffer(buf, dtype=np.int32).reshape(n, 2).copy()
+
+    # ------------------------------------------------------------------ device calls
+    def alloc_workspace(self, device="cuda"):
+        import torch
+        ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device)
+        if ws.data_ptr() % 256:
+            raise EelsError(4, "workspace allocation not 256-byte aligned")
+        return ws
+
+    def execute(self, V, H, out_map, workspace, stream=None):
+        """Enqueue the map computation (device tensors; out_map float64 [P])."""
+        _check(load_library().eels_execute(self._h, _ptr(V), _ptr(H), _ptr(out_map), _ptr(workspace),
+                                           workspace.numel(), _stream(stream)))
+
+    def debug_s1(self, V, slice_index: int, workspace, stream=None):
+        import torch
+        out = torch.empty((self.info()["n_beams_in"], self.ny, self.nx), dtype=torch.complex64, device=V.device)
+        _check(load_library().eels_debug_s1(self._h, _ptr(V), int(slice_index), _ptr(out), _ptr(workspace),
+                                            workspace.numel(), _stream(stream)))
+        return out
+
+    def debug_s2(self, V, slice_index: int, workspace, stream=None):
+        import torch
+        out = torch.empty((self.info()["n_beams_out"], self.ny, self.nx), dtype=torch.complex64, device=V.device)
+        _check(load_library().eels_debug_s2(self._h, _ptr(V), int(slice_index), _ptr(out), _ptr(workspace),
+                                            workspace.numel(), _stream(stream)))
+        return out
+
+
+def device_inputs(problem, device="cuda"):
+    """Upload V (float32) and H (complex64) of a problem to the device."""
+    import torch
+    V = torch.from_numpy(np.ascontiguousarray(problem.V, dtype=np.float32)).to(device)
+    H = torch.from_numpy(np.ascontiguousarray(problem.H, dtype=np.complex64)).to(device)
+    return V, H
+
+
+def solve(problem, precision: str = "fp32", order: str = "auto", device="cuda",
+          max_workspace_bytes: int = 0) -> np.ndarray:
+    """Compute one EELS map on the GPU and return it as float64 numpy [n_probes]."""
+    import torch
+    plan = Plan(problem, precision=precision, order=order, max_workspace_bytes=max_workspace_bytes)
+    V, H = device_inputs(problem, device)
+    ws = plan.alloc_workspace(device)
+    out = torch.empty(plan.n_probes, dtype=torch.float64, device=device)
+    plan.execute(V, H, out, ws)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def gemm_work_bytes(m: int, n: int) -> int:
+    return int(load_library().eels_gemm_work_bytes(m, n))
+
+
+def cgemm(A, B, precision: str = "fp32", norm2: bool = False, stream=None):
+    """C = A @ B.T for complex64 device tensors A [m, k], B [n, k] through the contraction
+    kernels; with norm2 returns sum_m |C[m, n]|^2 (float64 [n])."""
+    import torch
+    m, k = A.shape
+    n, k2 = B.shape
+    assert k == k2 and A.dtype == torch.complex64 and B.dtype == torch.complex64
+    lda = ldb = k + (k & 1)
+    Ap = torch.zeros((m, lda), dtype=torch.complex64, device=A.device)
+    Ap[:, :k] = A
+    Bp = torch.zeros((n, ldb), dtype=torch.complex64, device=B.device)
+    Bp[:, :k] = B
+    work = torch.empty(gemm_work_bytes(m, n), dtype=torch.uint8, device=A.device)
+    if norm2:
+        out = torch.empty(n, dtype=torch.float64, device=A.device)
+        _check(load_library().eels_debug_cgemm(PRECISIONS[precision], m, n, k, _ptr(Ap), lda, _ptr(Bp), ldb, None,
+                                               0, _ptr(out), _ptr(work), _stream(stream)))
+    else:
+        out = torch.empty((m, n), dtype=torch.complex64, device=A.device)
+        _check(load_library().eels_debug_cgemm(PRECISIONS[precision], m, n, k, _ptr(Ap), lda, _ptr(Bp), ldb,
+                                               _ptr(out), n, None, _ptr(work), _stream(stream)))
+    return out

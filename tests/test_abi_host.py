@@ -1,0 +1,122 @@
+"""Host-side tests of the C ABI (no GPU needed): the library loads, exports every
+function declared in include/eels.h, and plans problems exactly as the oracle does."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import physics as ph
+from oracle.common import make_setup
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+eels = pytest.importorskip("paper_1908_07628_amd.eels")
+
+
+def _lib():
+    try:
+        return eels.load_library()
+    except ImportError as e:  # library not built
+        pytest.skip(str(e))
+
+
+def test_header_symbols_exported():
+    lib = _lib()
+    hdr = open(os.path.join(ROOT, "include", "eels.h")).read()
+    names = set(re.findall(r"\b(eels_[a-z0-9_]+)\s*\(", hdr))
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(eels.EXPORTS) == names
+
+
+def test_version_and_status_strings():
+    lib = _lib()
+    import ctypes as C
+    a, b = C.c_int(), C.c_int()
+    assert lib.eels_get_version(C.byref(a), C.byref(b)) == 0
+    assert (a.value, b.value) == (0, 3)
+    assert lib.eels_status_string(2) == b"beam outside the band limit"
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: synth.config1(),
+    lambda: synth.random_problem(3, n=32, ny=64, L=8.0, Ly=13.0, nz=3, det_inner_mrad=5.0),
+    lambda: synth.random_problem(4, n=64, L=12.0, nz=3, window_A=3.0, interp_f=2, aperture_mrad=20.0,
+                                 det_outer_mrad=25.0, n_scan=6),
+])
+def test_beam_lists_match_oracle(maker):
+    _lib()
+    p = maker()
+    plan = eels.Plan(p)
+    st = make_setup(p)
+    assert np.array_equal(plan.beams(0), st.ab1)
+    assert np.array_equal(plan.beams(1), st.ab2)
+    inf = plan.info()
+    assert inf["n_beams_in_fine"] == st.n1_fine
+    assert inf["lambda_A"] == pytest.approx(st.lam, rel=1e-15)
+    assert inf["sigma"] == pytest.approx(st.sigma, rel=1e-15)
+
+
+def test_config_plan_shapes():
+    _lib()
+    inf = eels.Plan(synth.config1()).info()
+    assert (inf["n_beams_in"], inf["n_beams_out"]) == (325, 1305)
+    assert inf["n_live_x"] == 43 and inf["k_pixels"] == 64 * 64
+    assert inf["order"] == eels.ORDER_PROBE_FIRST
+
+
+def test_window_and_eligibility_match_oracle():
+    _lib()
+    p = synth.config3_subproblem()
+    plan = eels.Plan(p)
+    inf = plan.info()
+    hx, hy = ph.window_geometry(p.nx, p.ny, p.lx, p.ly, p.window_A)
+    assert (inf["window_nx"], inf["window_ny"]) == (2 * hx + 1, 2 * hy + 1)
+    assert inf["k_pixels"] == (2 * hx + 1) * (2 * hy + 1)
+    assert inf["k_stride"] % 16 == 0 and inf["k_stride"] >= inf["k_pixels"]
+
+
+def test_plan_errors():
+    _lib()
+    p = synth.random_problem(1, n=32, L=8.0, nz=2)
+    with pytest.raises(eels.EelsError) as e:
+        eels.Plan(p.replace(det_outer_mrad=40.0))          # beyond the 26 mrad band
+    assert e.value.status == 2
+    with pytest.raises(eels.EelsError) as e:
+        eels.Plan(p.replace(nx=48))                        # not a power of two
+    assert e.value.status == 3
+    with pytest.raises(eels.EelsError) as e:
+        eels.Plan(p.replace(interp_f=2))                   # f > 1 needs a crop window
+    assert e.value.status == 1
+    with pytest.raises(eels.EelsError) as e:
+        eels.Plan(p, max_workspace_bytes=1 << 20)          # budget below the fixed workspace
+    assert e.value.status == 5
+    bad = p.replace(site_slice=np.array([5, 0], dtype=np.int32))
+    with pytest.raises(eels.EelsError) as e:
+        eels.Plan(bad)
+    assert e.value.status == 1
+
+
+def test_budget_splits_slices_into_groups():
+    _lib()
+    p = synth.random_problem(5, n=64, L=12.0, nz=8, n_sites=6, window_A=3.0, atoms_per_slice=3)
+    full = eels.Plan(p).info()
+    assert full["n_groups"] == 1
+    ws = full["workspace_bytes"]
+    small = eels.Plan(p, max_workspace_bytes=int(ws * 0.93)).info()
+    assert small["workspace_bytes"] <= int(ws * 0.93)
+    assert small["n_groups"] >= 2 or small["n_batches"] > full["n_batches"]
+
+
+def test_contraction_order_choice():
+    _lib()
+    p = synth.config1()
+    a = eels.Plan(p, order="s_first").info()
+    b = eels.Plan(p, order="probe_first").info()
+    auto = eels.Plan(p).info()
+    assert auto["gemm_flops"] == min(a["gemm_flops"], b["gemm_flops"])
+    # order P for config 1: 8 (K N1 P + N2 K n_t P)
+    K, N1, N2, P, nt = 4096, 325, 1305, 16, 3
+    assert b["gemm_flops"] == pytest.approx(8.0 * (K * N1 * P + N2 * K * nt * P))

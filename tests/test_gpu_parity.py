@@ -1,0 +1,211 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: FP32 path rel-L2 <= 1e-4 on the map, split-precision <= 1e-3 (the relative
+L2 norm of Eq. nrmsse as read).  Component checks (FFT sweeps, GEMM) use bounds
+derived from single-precision round-off of the operation.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import conventional, metrics, prism
+from oracle.common import make_setup
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1908_07628_amd import eels
+    return eels
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+# ------------------------------------------------------------------ complex GEMM
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 2e-6), ("bf16_split", 3e-5), ("fp16_split", 3e-6)])
+@pytest.mark.parametrize("m,n,k", [(64, 32, 16), (150, 200, 37), (257, 129, 300)])
+def test_cgemm_against_float64(prec, tol, m, n, k):
+    eels = _need_gpu()
+    _say("cgemm", prec, m, n, k)
+    rng = np.random.default_rng(m * 1000 + n + k)
+    A = (rng.standard_normal((m, k)) + 1j * rng.standard_normal((m, k))).astype(np.complex64)
+    B = (rng.standard_normal((n, k)) + 1j * rng.standard_normal((n, k))).astype(np.complex64)
+    ref = A.astype(np.complex128) @ B.astype(np.complex128).T
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    C = eels.cgemm(dA, dB, prec).cpu().numpy()
+    err = np.linalg.norm(C - ref) / np.linalg.norm(ref)
+    assert err < tol, err
+    nrm = eels.cgemm(dA, dB, prec, norm2=True).cpu().numpy()
+    ref_n = (np.abs(ref) ** 2).sum(axis=0)
+    assert np.max(np.abs(nrm - ref_n) / ref_n) < 10 * tol
+
+
+# ------------------------------------------------------------------ sweeps
+
+def _small(seed=41, **kw):
+    base = dict(n=64, ny=32, L=12.0, Ly=6.5, nz=4, n_sites=2, n_trans=2, det_inner_mrad=4.0,
+                det_outer_mrad=22.0, aperture_mrad=18.0)
+    base.update(kw)
+    return synth.random_problem(seed, **base)
+
+
+def test_s1_rows_match_oracle():
+    eels = _need_gpu()
+    p = _small()
+    st = make_setup(p)
+    plan = eels.Plan(p)
+    V, H = eels.device_inputs(p)
+    ws = plan.alloc_workspace()
+    S1 = prism.forward_s1(p, st, range(p.n_slices))
+    for j in range(p.n_slices):
+        _say("S1 slice", j)
+        g = plan.debug_s1(V, j, ws).cpu().numpy().astype(np.complex128) / (p.nx * p.ny)
+        err = np.linalg.norm(g - S1[j]) / np.linalg.norm(S1[j])
+        assert err < 2e-6 * (j + 1), (j, err)
+
+
+def test_s2_rows_match_oracle():
+    eels = _need_gpu()
+    p = _small()
+    st = make_setup(p)
+    plan = eels.Plan(p)
+    V, H = eels.device_inputs(p)
+    ws = plan.alloc_workspace()
+    for j, S2 in prism.reverse_s2(p, st, 0):
+        _say("S2 slice", j)
+        g = plan.debug_s2(V, j, ws).cpu().numpy().astype(np.complex128)
+        err = np.linalg.norm(g - S2) / np.linalg.norm(S2)
+        assert err < 2e-6 * (p.n_slices - j), (j, err)
+
+
+@pytest.mark.parametrize("n", [16, 32, 128, 256, 512, 1024])
+def test_sweep_sizes(n):
+    """Every compiled transform length: one beam pair through two slices."""
+    eels = _need_gpu()
+    _say("sweep size", n)
+    L = n * 0.1
+    lam_mrad = 0.0196875e3
+    p = synth.random_problem(50 + n, n=n, L=L, nz=2, n_sites=1, n_trans=1, aperture_mrad=lam_mrad * 2.2 / L,
+                             det_outer_mrad=lam_mrad * 3.2 / L, atoms_per_slice=3)
+    st = make_setup(p)
+    plan = eels.Plan(p)
+    V, H = eels.device_inputs(p)
+    ws = plan.alloc_workspace()
+    S1 = prism.forward_s1(p, st, [1])[1]
+    g = plan.debug_s1(V, 1, ws).cpu().numpy().astype(np.complex128) / (p.nx * p.ny)
+    assert np.linalg.norm(g - S1) / np.linalg.norm(S1) < 1e-5
+    for j, S2 in prism.reverse_s2(p, st, 0):
+        if j == 0:
+            g2 = plan.debug_s2(V, 0, ws).cpu().numpy().astype(np.complex128)
+            assert np.linalg.norm(g2 - S2) / np.linalg.norm(S2) < 1e-5
+
+
+# ------------------------------------------------------------------ whole maps
+
+def _map(eels, p, precision="fp32", order="auto", **kw):
+    return eels.solve(p, precision=precision, order=order, **kw)
+
+
+def test_config1_fp32_matches_both_oracles():
+    eels = _need_gpu()
+    p = synth.config1()
+    I1 = conventional.conventional_map(p)
+    I2 = prism.prism_map(p)
+    for order in ("auto", "s_first", "probe_first"):
+        _say("config1", order)
+        g = _map(eels, p, "fp32", order)
+        assert metrics.rel_l2(g, I1) < 1e-4
+        assert metrics.rel_l2(g, I2) < 1e-4
+        assert metrics.max_rel(g, I2) < 1e-4
+
+
+@pytest.mark.parametrize("prec,tol", [("bf16_split", 1e-3), ("fp16_split", 1e-3)])
+def test_config1_split_precision(prec, tol):
+    eels = _need_gpu()
+    p = synth.config1()
+    I2 = prism.prism_map(p)
+    for order in ("s_first", "probe_first"):
+        _say("config1", prec, order)
+        assert metrics.rel_l2(_map(eels, p, prec, order), I2) < tol
+
+
+CASES = {
+    "nonsquare_annulus": dict(seed=61, n=64, ny=32, L=12.0, Ly=6.5, nz=4, n_sites=3, n_trans=3,
+                              det_inner_mrad=4.0, det_outer_mrad=22.0, aperture_mrad=18.0),
+    "crop_window": dict(seed=62, n=128, L=16.0, nz=5, n_sites=4, n_trans=2, window_A=3.0,
+                        aperture_mrad=20.0, det_outer_mrad=30.0, n_scan=5),
+    "crop_defocus": dict(seed=63, n=64, L=10.0, nz=3, n_sites=2, n_trans=3, window_A=4.0, defocus_A=25.0,
+                         aperture_mrad=20.0, det_outer_mrad=28.0),
+    "thin_and_thick": dict(seed=64, n=32, L=6.0, nz=7, n_sites=5, n_trans=1, dz=[1, 2, 3, 1.5, 2, 2.5, 1],
+                           aperture_mrad=15.0, det_outer_mrad=20.0),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("order", ["s_first", "probe_first"])
+def test_random_cases_fp32(name, order):
+    eels = _need_gpu()
+    kw = dict(CASES[name])
+    p = synth.random_problem(kw.pop("seed"), **kw)
+    _say("case", name, order)
+    ref = prism.prism_map(p)
+    g = _map(eels, p, "fp32", order)
+    assert metrics.rel_l2(g, ref) < 1e-4
+
+
+def test_interpolation_factor_case():
+    eels = _need_gpu()
+    p = synth.config3_subproblem(n=128, L=25.0, nz=5, n_scan=6, f=2)
+    ref = prism.prism_map(p)
+    assert np.count_nonzero(ref) > 0
+    for prec, tol in (("fp32", 1e-4), ("bf16_split", 1e-3)):
+        for order in ("s_first", "probe_first"):
+            _say("f=2", prec, order)
+            assert metrics.rel_l2(_map(eels, p, prec, order), ref) < tol
+
+
+def test_repeat_is_bitwise_identical():
+    eels = _need_gpu()
+    p = synth.config1()
+    a = _map(eels, p, "bf16_split")
+    b = _map(eels, p, "bf16_split")
+    assert np.array_equal(a, b)
+
+
+def test_memory_budget_grouping_same_map():
+    eels = _need_gpu()
+    p = synth.random_problem(71, n=64, L=12.0, nz=8, n_sites=6, window_A=3.0, atoms_per_slice=3,
+                             aperture_mrad=18.0, det_outer_mrad=30.0)
+    full = eels.Plan(p)
+    ws = full.info()["workspace_bytes"]
+    small = eels.Plan(p, max_workspace_bytes=int(ws * 0.95))
+    assert small.info()["n_groups"] > 1 or small.info()["n_batches"] > full.info()["n_batches"]
+    a = _map(eels, p)
+    b = _map(eels, p, max_workspace_bytes=int(ws * 0.95))
+    assert metrics.rel_l2(a, b) < 1e-12
+    assert metrics.rel_l2(a, prism.prism_map(p)) < 1e-4
+
+
+def test_zero_transition_potential_gives_zero_map():
+    eels = _need_gpu()
+    p = synth.config1()
+    g = _map(eels, p.replace(H=np.zeros_like(p.H)))
+    assert np.all(g == 0)
+
+
+def test_no_sites_gives_zero_map():
+    eels = _need_gpu()
+    p = synth.config1()
+    q = p.replace(site_slice=p.site_slice[:0], site_xy=p.site_xy[:0], site_ntrans=p.site_ntrans[:0],
+                  site_hoff=p.site_hoff[:0])
+    assert np.all(_map(eels, q) == 0)
