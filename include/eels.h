@@ -74,7 +74,10 @@ typedef struct {
  * (0 -> 2/3).  window_A: side of the crop window of the contraction (Sec. 4.B);
  * 0 -> full cell.  Probes: n_probes (x, y) positions in Angstrom.  Sites: n_sites
  * entries; n_trans_total rows of H.  max_workspace_bytes: memory budget for the plan's
- * workspace (0 -> unlimited); slices are processed in groups to stay within it. */
+ * workspace (0 -> unlimited); slices are processed in groups to stay within it.
+ * Full-cell windows are contracted in the basis of band-limited plane waves: because
+ * S_2(j)[q] = T_j fft2(P_j x) with P_j zero outside the band, sum_r S_2 H S_1 equals
+ * sum over band pixels g of (P_j x)(g) fft2(T_j H S_1)(g), about 1/3 of the pixels. */
 typedef struct {
     int nx, ny;
     double lx_A, ly_A;
@@ -97,6 +100,8 @@ typedef struct {
     int precision;
     int order;
     size_t max_workspace_bytes;
+    int real_space;          /* 1: contract full-cell windows pixel by pixel instead of in the
+                                band basis (same result, about 3x more GEMM work)            */
 } eels_problem;
 
 /* Derived sizes of a plan (filled by eels_plan_info). */
@@ -112,6 +117,8 @@ typedef struct {
     int n_groups;            /* slice groups (forward sweep repeated once per group)      */
     int n_batches;           /* contraction batches                                       */
     int order;               /* EELS_ORDER_S_FIRST or EELS_ORDER_PROBE_FIRST              */
+    int band_basis;          /* 1 if full-cell windows are contracted in the band basis    */
+    int band_pixels;         /* pixels inside the circular band limit                      */
     double lambda_A, sigma;
     double gemm_flops;       /* useful complex-GEMM flops (8 M N K summed)                */
     double sweep_bytes;      /* algorithmic HBM bytes of the two sweeps                   */
@@ -157,14 +164,21 @@ eels_status eels_debug_s2(const eels_plan* p, const float* d_V, int slice, void*
 
 /* Diagnostic complex GEMM through the same kernels as the contraction:
  * C[m][n] = sum_k A[m][k] * B[n][k] (no conjugation), complex64, row-major with
- * leading dimensions lda, ldb, ldc (complex elements, multiples of 2).  If d_norm2 is
+ * leading dimensions lda, ldb, ldc (complex elements; lda and ldb even).  If d_norm2 is
  * not null, d_norm2[n] = sum_m |C[m][n]|^2 (float64) is written instead of C.
- * precision: EELS_FP32 / EELS_BF16_SPLIT / EELS_FP16_SPLIT.  d_work: at least
- * eels_gemm_work_bytes(m, n) bytes. */
-size_t eels_gemm_work_bytes(int m, int n);
+ * precision: EELS_FP32 / EELS_BF16_SPLIT / EELS_FP16_SPLIT (split operands are converted
+ * to the split-complex storage first).  d_work: at least eels_gemm_work_bytes(m, n, k)
+ * bytes, 256-byte aligned.  Synchronises `stream` before returning. */
+size_t eels_gemm_work_bytes(int m, int n, int k);
 eels_status eels_debug_cgemm(int precision, int m, int n, int k, const void* d_A, int lda,
                              const void* d_B, int ldb, void* d_C, int ldc, double* d_norm2,
                              void* d_work, void* stream);
+
+/* Process-wide kernel tuning knobs, read at launch time (the autotuner sets them).
+ * key 0: LDS pipeline depth of the split-precision GEMM (2 or 3; default 3).
+ * Returns EELS_ERR_INVALID_ARG for an unknown key or an out-of-range value. */
+eels_status eels_tune_set(int key, int value);
+int eels_tune_get(int key);
 
 #ifdef __cplusplus
 }

@@ -11,6 +11,8 @@
 // total instead of being rebuilt for every slice (Sec. 3 rebuilds it per slice).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -28,6 +30,9 @@ namespace eels {
 
 static thread_local std::string g_err;
 void set_error(const std::string& m) { g_err = m; }
+
+static std::atomic<int> g_tune[TUNE_COUNT] = {{3}, {0}, {0}, {0}, {0}, {0}, {0}, {0}};
+int tune_get(int key) { return (key >= 0 && key < TUNE_COUNT) ? g_tune[key].load() : 0; }
 
 #define HIPCHK(x)                                                                       \
     do {                                                                                \
@@ -48,7 +53,8 @@ struct Dev {
     const double* dz;
     const double* probes;
     const GemmDesc* descs;
-    float2 *twx, *twy, *T, *P, *C, *s1, *s2, *w1, *w2, *mid;
+    const int *band_h, *band_off;
+    float2 *twx, *twy, *T, *P, *C, *s1, *s2, *w1, *w2, *mid, *mid2, *scratch;
     float* part;
 };
 
@@ -61,6 +67,8 @@ Dev make_dev(const Plan& p, void* ws_) {
     d.dz = (const double*)(d.blob + p.dz_off);
     d.probes = (const double*)(d.blob + p.probes_off);
     d.descs = (const GemmDesc*)(d.blob + p.descs_off);
+    d.band_h = d.blob + p.band_h_off;
+    d.band_off = d.blob + p.band_off_off;
     d.twx = (float2*)(d.ws + p.off_twx);
     d.twy = (float2*)(d.ws + p.off_twy);
     d.T = (float2*)(d.ws + p.off_T);
@@ -71,6 +79,8 @@ Dev make_dev(const Plan& p, void* ws_) {
     d.w1 = (float2*)(d.ws + p.off_w1);
     d.w2 = (float2*)(d.ws + p.off_w2);
     d.mid = (float2*)(d.ws + p.off_mid);
+    d.mid2 = (float2*)(d.ws + p.off_mid2);
+    d.scratch = (float2*)(d.ws + p.off_scratch);
     d.part = (float*)(d.ws + p.off_part);
     return d;
 }
@@ -92,7 +102,7 @@ eels_status setup(const Plan& p, const Dev& d, const float* dV, hipStream_t st) 
     launch_twiddles(d.twx, p.nx, st);
     launch_twiddles(d.twy, p.ny, st);
     launch_transmission(d.T, dV, (int64_t)p.nz * p.ny * p.nx, p.sigma, st);
-    launch_propagator(d.P, d.dz, p, st);
+    launch_propagator(d.P, d.dz, d.band_h, p, st);
     return EELS_OK;
 }
 
@@ -106,7 +116,7 @@ void forward_sweep(const Plan& p, const Dev& d, int j_end, int group, int dbg_sl
                    hipStream_t st) {
     launch_init_forward(d.s1, d.b1, p, st);
     for (int j = 0; j <= j_end; ++j) {
-        RowPassArgs a{d.s1, p.N1, p.ny, p.nlx, p.hlx, Tj(p, d, j), d.twx, nullptr, nullptr, d.w1, p.N1, p.Kpad};
+        RowPassArgs a{d.s1, p.N1, p.ny, p.nlx, p.hlx, Tj(p, d, j), d.twx, nullptr, nullptr, d.w1, p.N1, p.Kpad, 0};
         if (dbg_out && j == dbg_slice) {
             a.cap_ptr = d.blob + p.dbg_ptr;
             a.cap_rec = d.blob + p.dbg_rec;
@@ -117,41 +127,96 @@ void forward_sweep(const Plan& p, const Dev& d, int j_end, int group, int dbg_sl
             a.cap_rec = d.blob + p.slices[j].cap1_rec;
         }
         launch_row_pass(p.nx, 0, a, st);
-        if (j < j_end) launch_col_pass(p.ny, 0, d.s1, p.N1, p.nlx, Pj(p, d, j), d.twy, st);
+        if (j < j_end) launch_col_pass(p.ny, 0, d.s1, p.N1, p.nlx, Pj(p, d, j), d.twy, BandCap{}, st);
     }
 }
 
 // One step of the transposed sweep: bring S_2 to slice j (from j+1, or start at n_z-1)
-// and capture its windows (or the full plane into dbg_out).
+// and capture what the contraction at j needs: the S_2 windows (real-space contraction,
+// in the row pass) or the band coefficients of P_j x_{j+1} (band basis, in the column
+// pass or at the start); dbg_out receives the full real-space S_2(j) instead.
 void reverse_step(const Plan& p, const Dev& d, int j, bool capture, float2* dbg_out, hipStream_t st) {
-    if (j == p.nz - 1) launch_init_reverse(d.s2, d.b2, p, st);
-    else launch_col_pass(p.ny, 1, d.s2, p.N2, p.nlx, Pj(p, d, j), d.twy, st);
-    RowPassArgs a{d.s2, p.N2, p.ny, p.nlx, p.hlx, Tj(p, d, j), d.twx, nullptr, nullptr, d.w2, p.N2, p.Kpad};
+    const bool band = capture && p.recip && !dbg_out;
+    if (j == p.nz - 1) {
+        launch_init_reverse(d.s2, d.b2, p, st);
+        if (band) launch_init_band(d.w2, p.Kbpad, d.b2, d.band_h, d.band_off, p, p.w2_sc, st);
+    } else {
+        BandCap bc{};
+        if (band) bc = BandCap{d.band_h, d.band_off, d.w2, p.Kbpad, p.w2_sc};
+        launch_col_pass(p.ny, 1, d.s2, p.N2, p.nlx, Pj(p, d, j), d.twy, bc, st);
+    }
+    RowPassArgs a{d.s2, p.N2, p.ny, p.nlx, p.hlx, Tj(p, d, j), d.twx, nullptr, nullptr, d.w2, p.N2, p.Kpad, p.w2_sc};
     if (dbg_out) {
         a.cap_ptr = d.blob + p.dbg_ptr;
         a.cap_rec = d.blob + p.dbg_rec;
         a.win = dbg_out;
         a.Kpad = p.nx * p.ny;
-    } else if (capture) {
+        a.sc = 0;
+    } else if (capture && !p.recip) {
         a.cap_ptr = d.blob + p.slices[j].cap2_ptr;
         a.cap_rec = d.blob + p.slices[j].cap2_rec;
     }
     launch_row_pass(p.nx, 1, a, st);
 }
 
+// Producer jobs of a batch: the H-multiplied second operand of every site into mid2.
+void run_jobs(const Plan& p, const Dev& d, const float2* dH, const Batch& b, int j, hipStream_t st) {
+    for (int k = 0; k < b.job_count; ++k) {
+        const Job& jb = p.jobs[b.job_begin + k];
+        const float2* W = (jb.from_mid ? d.mid : d.w1) + jb.w_off;
+        if (p.recip) {
+            BandFft a{};
+            a.dst = d.mid2 + jb.dst_off;
+            a.dstride = p.Kbpad;
+            a.Kb = p.Kb;
+            a.W = W;
+            a.wstride = p.Kpad;
+            a.Ni = jb.Ni; a.nt = jb.nt; a.ny = p.ny; a.nlx = p.nlx; a.hlx = p.hlx;
+            a.Tj = Tj(p, d, j);
+            a.H = dH + jb.h_off;
+            a.hstride = p.K;
+            a.twx = d.twx; a.twy = d.twy;
+            a.band_h = d.band_h; a.band_off = d.band_off;
+            a.scratch = d.scratch;
+            a.sc = p.mid2_sc;
+            launch_band_fft(p.nx, p.ny, a, st);
+        } else {
+            launch_hmul(d.mid2 + jb.dst_off, W, p.Kpad, dH + jb.h_off, p.K, jb.Ni, jb.nt, p.K, p.Kpad, p.mid2_sc, st);
+        }
+    }
+}
+
 void contract(const Plan& p, const Dev& d, const float2* dH, double* map, int bi, hipStream_t st) {
     const Batch& b = p.batches[bi];
     const GemmDesc* dd = d.descs;
+    const bool split = p.precision != EELS_FP32;
+    const int nst = tune_get(TUNE_SC_STAGES);
     if (b.order == EELS_ORDER_S_FIRST) {
-        launch_cgemm(p.precision, 0, 0, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.w2, d.w1, dH, d.mid, nullptr,
-                     d.blob, st);
-        launch_cgemm(p.precision, 0, 1, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.mid, d.C, nullptr, nullptr, d.part,
-                     d.blob, st);
+        run_jobs(p, d, dH, b, b.slice, st);
+        if (split) {
+            launch_cgemm_sc(p.precision, 0, nst, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.w2, d.mid2, d.mid, nullptr,
+                            d.blob, st);
+            launch_cgemm_sc(p.precision, 1, nst, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.mid, d.C, nullptr, d.part,
+                            d.blob, st);
+        } else {
+            const bool h_pro = !p.recip;
+            launch_cgemm(EELS_FP32, 0, 0, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.w2, h_pro ? d.w1 : d.mid2,
+                         h_pro ? dH : nullptr, d.mid, nullptr, d.blob, st);
+            launch_cgemm(EELS_FP32, 0, 1, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.mid, d.C, nullptr, nullptr, d.part,
+                         d.blob, st);
+        }
     } else {
         launch_cgemm(EELS_FP32, 1, 0, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.C, d.w1, nullptr, d.mid, nullptr,
                      d.blob, st);
-        launch_cgemm(p.precision, 0, 1, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.w2, d.mid, dH, nullptr, d.part,
-                     d.blob, st);
+        run_jobs(p, d, dH, b, b.slice, st);
+        if (split) {
+            launch_cgemm_sc(p.precision, 1, nst, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.w2, d.mid2, nullptr, d.part,
+                            d.blob, st);
+        } else {
+            const bool h_pro = !p.recip;
+            launch_cgemm(EELS_FP32, 0, 1, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.w2, h_pro ? d.mid : d.mid2,
+                         h_pro ? dH : nullptr, nullptr, d.part, d.blob, st);
+        }
     }
     double nn = (double)p.nx * (double)p.ny;
     double scale = (double)p.f * p.f / (nn * nn) / ((double)p.c_scale * p.c_scale);
@@ -236,6 +301,8 @@ eels_status eels_plan_info_get(const eels_plan* pl, eels_plan_info* info) {
     info->n_groups = (int)p.groups.size();
     info->n_batches = (int)p.batches.size();
     info->order = p.order;
+    info->band_basis = p.recip ? 1 : 0;
+    info->band_pixels = p.Kb;
     info->lambda_A = p.lam;
     info->sigma = p.sigma;
     info->gemm_flops = p.gemm_flops;
@@ -274,8 +341,10 @@ eels_status eels_execute(const eels_plan* pl, const float* d_V, const void* d_H,
     hipStream_t st = (hipStream_t)stream;
     Dev d = make_dev(p, d_workspace);
     if ((s = setup(p, d, d_V, st))) return s;
-    launch_probe_coefficients(d.C, d.b1, d.probes, p, st);
+    launch_probe_coefficients(d.C, d.b1, d.probes, p, p.c_sc, st);
     launch_fill_zero_d(d_map, p.P, st);
+    // split operands are read in whole 16-element K tiles: the S_2 capture's padding must be zero
+    if (p.precision != EELS_FP32) launch_fill_zero(d.w2, p.off_mid - p.off_w2, st);
     int rev_next = p.nz - 1;
     for (int gi = 0; gi < (int)p.groups.size(); ++gi) {
         const Group& g = p.groups[gi];
@@ -319,9 +388,14 @@ eels_status eels_debug_s2(const eels_plan* pl, const float* d_V, int slice, void
     return EELS_OK;
 }
 
-size_t eels_gemm_work_bytes(int m, int n) {
-    if (m <= 0 || n <= 0) return 0;
-    return 256 + (size_t)ceil_div(m, GEMM_BM) * (size_t)n * 4 + 256;
+size_t eels_gemm_work_bytes(int m, int n, int k) {
+    if (m <= 0 || n <= 0 || k <= 0) return 0;
+    size_t kp = (size_t)round_up(k, KPAD_MULT);
+    size_t part = (size_t)ceil_div(m, GEMM_BM) * (size_t)n * 4;
+    size_t np_ = (size_t)round_up(n, KPAD_MULT);
+    size_t tmp = std::max((size_t)std::max(m, n) * kp, (size_t)m * np_);
+    size_t sc = ((size_t)m * kp + (size_t)n * kp + (size_t)m * np_ + tmp) * 8;
+    return 512 + (size_t)round_up((int64_t)part, 256) + sc + 1024;
 }
 
 eels_status eels_debug_cgemm(int precision, int m, int n, int k, const void* d_A, int lda, const void* d_B, int ldb,
@@ -329,30 +403,70 @@ eels_status eels_debug_cgemm(int precision, int m, int n, int k, const void* d_A
     if (m <= 0 || n <= 0 || k <= 0 || !d_A || !d_B || !d_work || (!d_C && !d_norm2)) return EELS_ERR_INVALID_ARG;
     if (lda < k || ldb < k || (lda & 1) || (ldb & 1) || (d_C && ldc < n)) return EELS_ERR_INVALID_ARG;
     if (precision < EELS_FP32 || precision > EELS_FP16_SPLIT) return EELS_ERR_INVALID_ARG;
+    if (((uintptr_t)d_work) & 255) return EELS_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
     GemmDesc g{};
     g.a_off = 0; g.lda = lda; g.b_off = 0; g.ldb = ldb;
     g.h_off = -1; g.c_off = 0; g.ldc_m = ldc; g.ldc_t = 0; g.p_off = 0; g.ld_part = n; g.a_tstride = 0;
+    g.b_tstride = 0;
     g.M = m; g.N_inner = n; g.n_t = 1; g.K = k; g.idx_off = -1;
     g.tiles_m = (int)ceil_div(m, GEMM_BM);
     g.tiles_n = (int)ceil_div(n, GEMM_BN);
     g.tile_start = 0;
-    GemmDesc* dd = (GemmDesc*)d_work;
-    float* part = (float*)((char*)d_work + 256);
-    HIPCHK(hipMemcpyAsync(dd, &g, sizeof(g), hipMemcpyHostToDevice, st));
+    char* w = (char*)d_work;
+    GemmDesc* dd = (GemmDesc*)w;
+    float* part = (float*)(w + 512);
+    size_t part_bytes = (size_t)round_up((int64_t)g.tiles_m * n * 4, 256);
     int tiles = g.tiles_m * g.tiles_n;
+    if (precision == EELS_FP32) {
+        HIPCHK(hipMemcpyAsync(dd, &g, sizeof(g), hipMemcpyHostToDevice, st));
+        if (d_norm2) {
+            launch_cgemm(precision, 0, 1, dd, 1, tiles, (const float2*)d_A, (const float2*)d_B, nullptr, nullptr, part,
+                         nullptr, st);
+        } else {
+            launch_cgemm(precision, 0, 0, dd, 1, tiles, (const float2*)d_A, (const float2*)d_B, nullptr, (float2*)d_C,
+                         nullptr, nullptr, st);
+        }
+    } else {
+        // convert the operands to split-complex storage with K padded to 16
+        int kp = (int)round_up(k, KPAD_MULT), np_ = (int)round_up(n, KPAD_MULT);
+        char* a_sc = w + 512 + part_bytes;
+        char* b_sc = a_sc + (size_t)m * kp * 8;
+        char* c_sc = b_sc + (size_t)n * kp * 8;
+        char* tmp = c_sc + (size_t)m * np_ * 8;
+        // strided copy: rows of lda -> rows of kp (via complex64 rows; K columns only)
+        g.lda = kp; g.ldb = kp; g.ldc_m = np_;
+        HIPCHK(hipMemcpyAsync(dd, &g, sizeof(g), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpy2DAsync(tmp, (size_t)kp * 8, d_A, (size_t)lda * 8, (size_t)k * 8, m, hipMemcpyDeviceToDevice, st));
+        launch_to_sc(a_sc, (const float2*)tmp, m, k, kp, precision, st);
+        HIPCHK(hipMemcpy2DAsync(tmp, (size_t)kp * 8, d_B, (size_t)ldb * 8, (size_t)k * 8, n, hipMemcpyDeviceToDevice, st));
+        launch_to_sc(b_sc, (const float2*)tmp, n, k, kp, precision, st);
+        int nst = tune_get(TUNE_SC_STAGES);
+        if (d_norm2) {
+            launch_cgemm_sc(precision, 1, nst, dd, 1, tiles, a_sc, b_sc, nullptr, part, nullptr, st);
+        } else {
+            launch_cgemm_sc(precision, 0, nst, dd, 1, tiles, a_sc, b_sc, c_sc, nullptr, nullptr, st);
+            launch_from_sc((float2*)tmp, c_sc, (int64_t)m * np_, precision, st);
+            HIPCHK(hipMemcpy2DAsync(d_C, (size_t)ldc * 8, tmp, (size_t)np_ * 8, (size_t)n * 8, m,
+                                    hipMemcpyDeviceToDevice, st));
+        }
+    }
     if (d_norm2) {
-        launch_cgemm(precision, 0, 1, dd, 1, tiles, (const float2*)d_A, (const float2*)d_B, nullptr, nullptr, part,
-                     nullptr, st);
         launch_fill_zero_d(d_norm2, n, st);
         launch_reduce_dense(d_norm2, n, dd, 0, 1, part, 1.0, st);
-    } else {
-        launch_cgemm(precision, 0, 0, dd, 1, tiles, (const float2*)d_A, (const float2*)d_B, nullptr, (float2*)d_C,
-                     nullptr, nullptr, st);
     }
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipGetLastError());
     return EELS_OK;
 }
+
+eels_status eels_tune_set(int key, int value) {
+    if (key < 0 || key >= TUNE_COUNT) return EELS_ERR_INVALID_ARG;
+    if (key == TUNE_SC_STAGES && (value < 2 || value > 3)) return EELS_ERR_INVALID_ARG;
+    g_tune[key].store(value);
+    return EELS_OK;
+}
+
+int eels_tune_get(int key) { return tune_get(key); }
 
 }  // extern "C"

@@ -23,27 +23,43 @@ struct CaptureRec {
 // partial sums, ints for the index lists).  The output has n_t column blocks of
 // N_inner columns; for block t:
 //   C_t[m][i] = sum_k A_t[m][k] * B_t[i][k],   A_t = A + t*a_tstride,
-//   B_t[i][k] = Bsrc[idx ? idx[i] : i][k] * (H ? H[t*ldh + k] : 1).
+//   B_t[i][k] = Bsrc_t[idx ? idx[i] : i][k] * (H ? H[t*ldh + k] : 1),  Bsrc_t = B + t*b_tstride.
 // Store epilogue: C[c_off + t*ldc_t + m*ldc_m + i].  Norm epilogue:
 // part[p_off + mt*ld_part + t*N_inner + i] = sum over the rows m of tile mt of |C_t[m][i]|^2.
 // Tiles: tiles_m x tiles_n x n_t (m fastest), tiles_n = ceil(N_inner / 128).
 struct GemmDesc {
     int64_t a_off, b_off, h_off, c_off, p_off;
-    int64_t lda, ldb, ldh, ldc_m, ldc_t, ld_part, a_tstride;
+    int64_t lda, ldb, ldh, ldc_m, ldc_t, ld_part, a_tstride, b_tstride;
     int M, N_inner, n_t, K;
     int idx_off;       // offset into the int table, -1 = no gather
     int tiles_m, tiles_n, tile_start;
+    int pad_[2];
 };
-static_assert(sizeof(GemmDesc) == 128, "GemmDesc layout");
+static_assert(sizeof(GemmDesc) == 144, "GemmDesc layout");
+
+// Process-wide tuning knobs (set by eels_tune_set; read at launch time).
+enum TuneKey { TUNE_SC_STAGES = 0, TUNE_COUNT = 8 };
+int tune_get(int key);
 
 struct Batch {
     int slice;
     int order;
     int d1_begin, d1_count, d1_tiles;   // first GEMM (store epilogue)
     int d2_begin, d2_count, d2_tiles;   // second GEMM (norm epilogue)
+    int job_begin, job_count;           // producer jobs run between the two GEMMs (order P) or before
     int64_t red_ptr;                    // int offset of the per-probe CSR row pointers [P+1], -1: dense
     int64_t red_ent;                    // int offset of the CSR entries (pairs: desc, column)
     int64_t n_entries;
+};
+
+// Producer job: write the H-multiplied operand of one site into mid2, either in the band
+// basis (fft2 of T_j H_t W_i) or pixel-wise (H_t W_i), from S_1 windows or from Psi.
+struct Job {
+    int from_mid;       // 0: W = S_1 window buffer, 1: W = mid (Psi)
+    int64_t w_off;      // complex offset of the site's first W row
+    int Ni, nt;
+    int64_t h_off;      // complex offset of the site's first transition potential
+    int64_t dst_off;    // complex offset in mid2
 };
 
 struct SliceInfo {
@@ -82,7 +98,11 @@ struct Plan {
     std::vector<int> ab1, ab2;    // lattice coordinates (a, b) of beams
     int N1, N2, N1fine, N1pad;
     bool full_window;
+    bool recip;                   // band-basis contraction (full-cell windows)
     int hwx, hwy, nwx, nwy, K, Kpad;
+    std::vector<int> band_h, band_off;          // band rows per live column, band slot offsets
+    int Kb, Kbpad;                              // band pixels, padded stride
+    int c_sc, w2_sc, mid2_sc;                   // storage formats (0 complex64, else split precision)
     std::vector<int> site_w1, site_w2;          // window index of each site (S_1 group-local, S_2 slice-local)
     std::vector<int> site_ix0, site_iy0;
     std::vector<std::vector<int>> site_probes;  // eligible probes (empty vector + flag = all)
@@ -90,8 +110,9 @@ struct Plan {
     std::vector<Group> groups;                  // processing order: descending slices
     std::vector<Batch> batches;
     std::vector<GemmDesc> descs;
+    std::vector<Job> jobs;
     int max_w1, max_w2;
-    int64_t mid_elems, part_elems;              // per batch maxima
+    int64_t mid_elems, mid2_elems, part_elems, scratch_elems;   // per batch maxima
     double gemm_flops = 0, sweep_bytes = 0, sweep_beam_slices = 0;
     float c_scale = 1.0f;                       // probe coefficient pre-scale (FP16 range)
 
@@ -99,13 +120,14 @@ struct Plan {
     std::vector<int32_t> blob;
     int64_t b1_off, b2_off;       // int4 per beam: (live column, iy, a, b)
     int64_t ident_off;            // 0..P-1
+    int64_t band_h_off, band_off_off;
     int64_t dz_off, probes_off;   // doubles (int offsets, 16-byte aligned)
     int64_t dbg_ptr, dbg_rec;     // full-plane capture CSR (diagnostics)
     int64_t descs_off;            // GemmDesc array (int offset, 16-byte aligned)
 
     // workspace layout (byte offsets)
     size_t off_blob, off_twx, off_twy, off_T, off_P, off_C, off_s1, off_s2, off_w1, off_w2,
-        off_mid, off_part, ws_bytes;
+        off_mid, off_mid2, off_scratch, off_part, ws_bytes;
 };
 
 eels_status build_plan(Plan& p, const eels_problem& prob);

@@ -102,7 +102,7 @@ __global__ __launch_bounds__(256) void k_cgemm(const GemmDesc* __restrict__ desc
     const int M = d.M, K = d.K, N = d.N_inner;
     const int m0 = tm * BM, n0 = tn * BN;
     const float2* A = Ab + d.a_off + (int64_t)t * d.a_tstride;
-    const float2* B = Bb + d.b_off;
+    const float2* B = Bb + d.b_off + (int64_t)t * d.b_tstride;
     const float2* Hrow = d.h_off >= 0 && Hb ? Hb + d.h_off + (int64_t)t * d.ldh : nullptr;
     const int* idx = d.idx_off >= 0 ? ib + d.idx_off : nullptr;
 
@@ -326,6 +326,211 @@ __global__ __launch_bounds__(256) void k_cgemm(const GemmDesc* __restrict__ desc
     }
 }
 
+// ============================================================================ split GEMM, v2
+//
+// Split-complex ("SC") storage: a row of Kpad complex values (Kpad % 16 == 0) is Kpad / 4
+// units of 32 bytes; unit u holds complex 4u .. 4u+3 as [hi: four u32 (re, im) half pairs]
+// [lo: four u32].  Offsets and strides count 8-byte complex slots exactly as for complex64,
+// so an SC matrix occupies the same bytes as its complex64 form.
+//
+// The kernel streams 128-row x 16-complex tiles of both operands straight from global
+// memory into a ring of NSTAGE LDS buffers (global_load_lds_dwordx4, no registers), so
+// NSTAGE - 1 tiles are in flight while one is multiplied.  Inside a tile row of 128 bytes
+// (eight 16-byte quads) quad q of row r is stored at position q ^ ((r >> 1) & 7), which
+// makes the fragment reads of 16 consecutive rows hit distinct LDS banks.
+// Rows beyond M or N are clamped to the last valid row (their results are discarded or
+// masked); the K padding of every SC operand holds zeros.
+
+__device__ __forceinline__ void sc_store(uint32_t* base, int64_t off, float2 v, int prec) {
+    uint32_t hi, lo;
+    if (prec == EELS_BF16_SPLIT) split2<EELS_BF16_SPLIT>(v.x, v.y, hi, lo);
+    else split2<EELS_FP16_SPLIT>(v.x, v.y, hi, lo);
+    int64_t u = off >> 2;
+    int pos = (int)(off & 3);
+    base[u * 8 + pos] = hi;
+    base[u * 8 + 4 + pos] = lo;
+}
+
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt");
+    // gfx9 s_waitcnt: vmcnt in bits 3:0 and 15:14, expcnt 6:4 and lgkmcnt 11:8 left at max
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+template <int PREC, int EPI, int NSTAGE>
+__global__ __launch_bounds__(256) void k_cgemm_sc(const GemmDesc* __restrict__ descs, int n_desc,
+                                                  const uint32_t* __restrict__ Ab, const uint32_t* __restrict__ Bb,
+                                                  uint32_t* __restrict__ Cb, float* __restrict__ Pb,
+                                                  const int* __restrict__ ib) {
+    constexpr int STAGE = 2 * 128 * 128;  // bytes: A and B tiles of 128 rows x 128 bytes
+    __shared__ __attribute__((aligned(1024))) char smem[NSTAGE * STAGE];
+
+    const int bid = blockIdx.x;
+    int lo = 0, hi = n_desc - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (descs[mid].tile_start <= bid) lo = mid;
+        else hi = mid - 1;
+    }
+    const GemmDesc& d = descs[lo];
+    const int local = bid - d.tile_start;
+    const int tm = local % d.tiles_m;
+    const int rest = local / d.tiles_m;
+    const int tn = rest % d.tiles_n, t = rest / d.tiles_n;
+    const int M = d.M, N = d.N_inner;
+    const int m0 = tm * BM, n0 = tn * BN;
+    const int nk = (d.K + BK - 1) / BK;
+    const char* A = (const char*)Ab + 8 * (d.a_off + (int64_t)t * d.a_tstride);
+    const char* B = (const char*)Bb + 8 * (d.b_off + (int64_t)t * d.b_tstride);
+    const int* idx = d.idx_off >= 0 ? ib + d.idx_off : nullptr;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int li = lane & 31, hl = lane >> 5;
+
+    // this lane's four A and four B source rows (one per 8-row chunk of the wave's 32 rows)
+    const int qpos = lane & 7;
+    const char* asrc[4];
+    const char* bsrc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        int r = wave * 32 + c * 8 + (lane >> 3);
+        int q = qpos ^ ((r >> 1) & 7);
+        int m = min(m0 + r, M - 1);
+        int n = min(n0 + r, N - 1);
+        int nr = idx ? idx[n] : n;
+        asrc[c] = A + (int64_t)m * d.lda * 8 + 16 * q;
+        bsrc[c] = B + (int64_t)nr * d.ldb * 8 + 16 * q;
+    }
+    typedef __attribute__((address_space(3))) char lds_char;
+    lds_char* lds = (lds_char*)smem;
+    auto issue = [&](int kt) {
+        lds_char* st = lds + (kt % NSTAGE) * STAGE;
+        int64_t koff = (int64_t)kt * (BK * 8);
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            __builtin_amdgcn_global_load_lds((const void*)(asrc[c] + koff), (void*)(st + (wave * 32 + c * 8) * 128), 16,
+                                             0, 0);
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            __builtin_amdgcn_global_load_lds((const void*)(bsrc[c] + koff),
+                                             (void*)(st + 128 * 128 + (wave * 32 + c * 8) * 128), 16, 0, 0);
+    };
+
+    floatx16 accR[2][2], accI[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) { accR[a][b][v] = 0.f; accI[a][b][v] = 0.f; }
+
+#pragma unroll
+    for (int s = 0; s < NSTAGE - 1; ++s)
+        if (s < nk) issue(s);
+
+    for (int kt = 0; kt < nk; ++kt) {
+        // this wave's loads of tile kt are done once at most the later tiles' loads remain;
+        // the barrier then covers every wave's part of the tile and frees the stage that was
+        // multiplied in the previous iteration (its LDS reads fed MFMAs, so they completed)
+        if (nk - 1 - kt >= NSTAGE - 2) wait_vmcnt<8 * (NSTAGE - 2)>();
+        else wait_vmcnt<0>();
+        __builtin_amdgcn_s_barrier();
+        if (kt + NSTAGE - 1 < nk) issue(kt + NSTAGE - 1);
+        const char* st = smem + (kt % NSTAGE) * STAGE;
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            const int u = 2 * ks + hl;
+            u32x4 ah[2], al[2];
+#pragma unroll
+            for (int bm = 0; bm < 2; ++bm) {
+                int r = wm * 64 + bm * 32 + li;
+                int sw = (r >> 1) & 7;
+                const char* row = st + r * 128;
+                ah[bm] = *(const u32x4*)(row + 16 * ((2 * u) ^ sw));
+                al[bm] = *(const u32x4*)(row + 16 * ((2 * u + 1) ^ sw));
+            }
+#pragma unroll
+            for (int bn = 0; bn < 2; ++bn) {
+                int r = wn * 64 + bn * 32 + li;
+                int sw = (r >> 1) & 7;
+                const char* row = st + 128 * 128 + r * 128;
+                u32x4 bh = *(const u32x4*)(row + 16 * ((2 * u) ^ sw));
+                u32x4 bl = *(const u32x4*)(row + 16 * ((2 * u + 1) ^ sw));
+                u32x4 brh = neg_imag(bh), brl = neg_imag(bl), bih = swap_halves(bh), bil = swap_halves(bl);
+#pragma unroll
+                for (int bm = 0; bm < 2; ++bm) {
+                    accR[bm][bn] = mfma16<PREC>(ah[bm], brh, accR[bm][bn]);
+                    accR[bm][bn] = mfma16<PREC>(ah[bm], brl, accR[bm][bn]);
+                    accR[bm][bn] = mfma16<PREC>(al[bm], brh, accR[bm][bn]);
+                    accI[bm][bn] = mfma16<PREC>(ah[bm], bih, accI[bm][bn]);
+                    accI[bm][bn] = mfma16<PREC>(ah[bm], bil, accI[bm][bn]);
+                    accI[bm][bn] = mfma16<PREC>(al[bm], bih, accI[bm][bn]);
+                }
+            }
+        }
+    }
+
+    if constexpr (EPI == 0) {
+        // store the product in SC form; the padding columns N .. ceil16(N)-1 get zeros so
+        // that the result can be a K operand of the next product
+        const int64_t cbase = d.c_off + (int64_t)t * d.ldc_t;
+        const int npad = (N + 15) & ~15;
+        if (n0 + BN > N && n0 < npad) {
+            for (int e = tid; e < BM * 16; e += 256) {
+                int m = m0 + e / 16, i = N + e % 16;
+                if (m < M && i < npad && i >= n0 && i < n0 + BN)
+                    sc_store(Cb, cbase + (int64_t)m * d.ldc_m + i, make_float2(0.f, 0.f), PREC);
+            }
+        }
+#pragma unroll
+        for (int bn = 0; bn < 2; ++bn) {
+            int i = n0 + wn * 64 + bn * 32 + li;
+            if (i >= N) continue;
+#pragma unroll
+            for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    int m = m0 + wm * 64 + bm * 32 + 8 * (v >> 2) + 4 * hl + (v & 3);
+                    if (m < M) sc_store(Cb, cbase + (int64_t)m * d.ldc_m + i, make_float2(accR[bm][bn][v], accI[bm][bn][v]), PREC);
+                }
+        }
+    } else {
+        __syncthreads();
+        float* red = (float*)smem;
+#pragma unroll
+        for (int bn = 0; bn < 2; ++bn) {
+            float s = 0.f;
+#pragma unroll
+            for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    int m = m0 + wm * 64 + bm * 32 + 8 * (v >> 2) + 4 * hl + (v & 3);
+                    float x = accR[bm][bn][v] * accR[bm][bn][v] + accI[bm][bn][v] * accI[bm][bn][v];
+                    s += m < M ? x : 0.f;
+                }
+            s += __shfl_xor(s, 32);
+            if (hl == 0) red[wm * BN + wn * 64 + bn * 32 + li] = s;
+        }
+        __syncthreads();
+        if (tid < BN) {
+            int i = n0 + tid;
+            if (i < N) Pb[d.p_off + (int64_t)tm * d.ld_part + (int64_t)t * N + i] = red[tid] + red[BN + tid];
+        }
+    }
+}
+
+// complex64 -> SC conversion of rows [rows][ld] (K padding columns become zero)
+__global__ void k_to_sc(uint32_t* __restrict__ dst, const float2* __restrict__ src, int64_t rows, int K, int ld,
+                        int prec) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows * ld) return;
+    int k = (int)(i % ld);
+    float2 v = k < K ? src[i] : make_float2(0.f, 0.f);
+    sc_store(dst, i, v, prec);
+}
+
 template <int PREC, int KIND, int EPI>
 static void go(const GemmDesc* dd, int nd, int tiles, const float2* A, const float2* B, const float2* H, float2* C,
                float* P, const int* idx, hipStream_t st) {
@@ -354,6 +559,59 @@ void launch_cgemm(int precision, int kind, int epi, const GemmDesc* dd, int nd, 
             else go<EELS_FP16_SPLIT, 0, 1>(dd, nd, tiles, A, B, H, C, part, idx, st);
             break;
     }
+}
+
+
+template <int PREC, int EPI>
+static void go_sc(int nstage, const GemmDesc* dd, int nd, int tiles, const uint32_t* A, const uint32_t* B, uint32_t* C,
+                  float* P, const int* idx, hipStream_t st) {
+    if (nstage >= 3)
+        hipLaunchKernelGGL((k_cgemm_sc<PREC, EPI, 3>), dim3(tiles), dim3(256), 0, st, dd, nd, A, B, C, P, idx);
+    else
+        hipLaunchKernelGGL((k_cgemm_sc<PREC, EPI, 2>), dim3(tiles), dim3(256), 0, st, dd, nd, A, B, C, P, idx);
+}
+
+void launch_cgemm_sc(int precision, int epi, int nstage, const GemmDesc* dd, int nd, int tiles, const void* A,
+                     const void* B, void* C, float* part, const int* idx, hipStream_t st) {
+    if (tiles <= 0 || nd <= 0) return;
+    const uint32_t *a = (const uint32_t*)A, *b = (const uint32_t*)B;
+    uint32_t* c = (uint32_t*)C;
+    if (precision == EELS_BF16_SPLIT) {
+        if (epi == 0) go_sc<EELS_BF16_SPLIT, 0>(nstage, dd, nd, tiles, a, b, c, part, idx, st);
+        else go_sc<EELS_BF16_SPLIT, 1>(nstage, dd, nd, tiles, a, b, c, part, idx, st);
+    } else {
+        if (epi == 0) go_sc<EELS_FP16_SPLIT, 0>(nstage, dd, nd, tiles, a, b, c, part, idx, st);
+        else go_sc<EELS_FP16_SPLIT, 1>(nstage, dd, nd, tiles, a, b, c, part, idx, st);
+    }
+}
+
+__global__ void k_from_sc(float2* __restrict__ dst, const uint32_t* __restrict__ src, int64_t n, int prec) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t u = i >> 2;
+    int pos = (int)(i & 3);
+    uint32_t h = src[u * 8 + pos], l = src[u * 8 + 4 + pos];
+    float2 v;
+    if (prec == EELS_BF16_SPLIT) {
+        v.x = __uint_as_float(h << 16) + __uint_as_float(l << 16);
+        v.y = __uint_as_float(h & 0xFFFF0000u) + __uint_as_float(l & 0xFFFF0000u);
+    } else {
+        v.x = (float)__builtin_bit_cast(_Float16, (uint16_t)(h & 0xFFFF)) + (float)__builtin_bit_cast(_Float16, (uint16_t)(l & 0xFFFF));
+        v.y = (float)__builtin_bit_cast(_Float16, (uint16_t)(h >> 16)) + (float)__builtin_bit_cast(_Float16, (uint16_t)(l >> 16));
+    }
+    dst[i] = v;
+}
+
+void launch_from_sc(float2* dst, const void* src, int64_t n, int prec, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_from_sc, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dst, (const uint32_t*)src, n, prec);
+}
+
+void launch_to_sc(void* dst, const float2* src, int64_t rows, int K, int ld, int prec, hipStream_t st) {
+    int64_t n = rows * ld;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_to_sc, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (uint32_t*)dst, src, rows, K, ld,
+                       prec);
 }
 
 }  // namespace eels

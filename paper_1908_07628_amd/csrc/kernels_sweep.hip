@@ -21,6 +21,36 @@
 
 namespace eels {
 
+// Split-complex store (see the GEMM kernels): slot `off` of an SC array.
+__device__ __forceinline__ uint32_t bf16_rne(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__device__ __forceinline__ void store_c(void* base, int64_t off, float2 v, int sc) {
+    if (sc == 0) {
+        ((float2*)base)[off] = v;
+        return;
+    }
+    uint32_t hi, lo;
+    if (sc == EELS_BF16_SPLIT) {
+        uint32_t ha = bf16_rne(v.x), hb = bf16_rne(v.y);
+        float ra = v.x - __uint_as_float(ha << 16), rb = v.y - __uint_as_float(hb << 16);
+        hi = ha | (hb << 16);
+        lo = bf16_rne(ra) | (bf16_rne(rb) << 16);
+    } else {
+        _Float16 ha = (_Float16)v.x, hb = (_Float16)v.y;
+        _Float16 la = (_Float16)(v.x - (float)ha), lb = (_Float16)(v.y - (float)hb);
+        hi = (uint32_t)__builtin_bit_cast(uint16_t, ha) | ((uint32_t)__builtin_bit_cast(uint16_t, hb) << 16);
+        lo = (uint32_t)__builtin_bit_cast(uint16_t, la) | ((uint32_t)__builtin_bit_cast(uint16_t, lb) << 16);
+    }
+    uint32_t* b = (uint32_t*)base;
+    int64_t u = off >> 2;
+    int pos = (int)(off & 3);
+    b[u * 8 + pos] = hi;
+    b[u * 8 + 4 + pos] = lo;
+}
+
 // --------------------------------------------------------------------- set-up kernels
 
 __global__ void k_twiddles(float2* tw, int n) {
@@ -47,9 +77,11 @@ __device__ __forceinline__ int live_to_kx_signed(int c, int nlx, int hlx, int nx
     return c <= hlx ? c : c - nlx;
 }
 
-// P~_j(kx, ky) = [|k| <= kmax] exp(-i pi lambda dz_j |k|^2) / (nx ny) on the live columns
+// P~_j(kx, ky) = B(k) exp(-i pi lambda dz_j |k|^2) / (nx ny) on the live columns; the band
+// B is |ky index| <= band_h[c] for live column c (the host's table, shared with the band
+// captures so that every kernel agrees on the band pixel set)
 __global__ void k_propagator(float2* P, const double* dz, int nz, int nx, int ny, int nlx, int hlx,
-                             double lx, double ly, double lam, double kmax) {
+                             double lx, double ly, double lam, const int* __restrict__ band_h) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t total = (int64_t)nz * ny * nlx;
     if (i >= total) return;
@@ -60,7 +92,8 @@ __global__ void k_propagator(float2* P, const double* dz, int nz, int nx, int ny
     double ky = signed_index(y, ny) / ly;
     double k2 = kx * kx + ky * ky;
     float2 out = make_float2(0.f, 0.f);
-    if (sqrt(k2) <= kmax) {
+    int ys = signed_index(y, ny);
+    if (ys <= band_h[c] && -ys <= band_h[c]) {
         double s, co;
         sincospi(-lam * dz[j] * k2, &s, &co);
         double sc = 1.0 / ((double)nx * (double)ny);
@@ -71,9 +104,9 @@ __global__ void k_propagator(float2* P, const double* dz, int nz, int nx, int ny
 
 // c_k(R) = s exp(-i chi(k)) exp(-2 pi i k.R), stored [P][N1pad] (zero padding columns).
 // The scan phase is reduced to a fraction of a cycle in double before the sincos.
-__global__ void k_probe_coefficients(float2* C, const int4* beams, int N1, int N1pad, const double* probes, int P,
+__global__ void k_probe_coefficients(void* C, const int4* beams, int N1, int N1pad, const double* probes, int P,
                                      int f, double lx, double ly, double lam, double defocus, double cs,
-                                     double scale) {
+                                     double scale, int sc) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)P * N1pad) return;
     int k = (int)(i % N1pad);
@@ -90,7 +123,7 @@ __global__ void k_probe_coefficients(float2* C, const int4* beams, int N1, int N
         sincos(-2.0 * M_PI * u - chi, &s, &c);
         out = make_float2((float)(c * scale), (float)(s * scale));
     }
-    C[i] = out;
+    store_c(C, i, out, sc);
 }
 
 // Forward sweep start: beam b = plane wave e_k, in (kx, y): column col_b holds exp(2 pi i ky y / ny).
@@ -159,7 +192,7 @@ template <int N, int MODE>
 __global__ __launch_bounds__(256) void k_row_pass(float2* __restrict__ state, int nbeam, int ny, int nlx, int hlx,
                                                   const float2* __restrict__ Tj, const float2* __restrict__ tw,
                                                   const int* __restrict__ cap_ptr, const int4* __restrict__ cap_rec,
-                                                  float2* __restrict__ win, int64_t win_beams, int Kpad) {
+                                                  void* __restrict__ win, int64_t win_beams, int Kpad, int sc) {
     constexpr int E = 8;
     constexpr int T = N / E;
     constexpr int S = 256 / T;
@@ -196,11 +229,11 @@ __global__ __launch_bounds__(256) void k_row_pass(float2* __restrict__ state, in
             int r0 = cap_ptr[y], r1 = cap_ptr[y + 1];
             for (int r = r0; r < r1; ++r) {
                 int4 rec = cap_rec[r];
-                float2* dst = win + ((int64_t)rec.x * win_beams + beam) * Kpad + (int64_t)rec.y * rec.w;
+                int64_t dst = ((int64_t)rec.x * win_beams + beam) * Kpad + (int64_t)rec.y * rec.w;
                 for (int u = t; u < rec.w; u += T) {
                     int x = rec.z + u;
                     if (x >= N) x -= N;
-                    dst[u] = lds[base + x];
+                    store_c(win, dst + u, lds[base + x], sc);
                 }
             }
         }
@@ -243,7 +276,10 @@ struct ColCfg {
 template <int N, int MODE>
 __global__ __launch_bounds__(ColCfg<N>::NT) void k_col_pass(float2* __restrict__ state, int nbeam, int nlx,
                                                             const float2* __restrict__ Pj,
-                                                            const float2* __restrict__ tw) {
+                                                            const float2* __restrict__ tw,
+                                                            const int* __restrict__ band_h,
+                                                            const int* __restrict__ band_off, void* __restrict__ bcap,
+                                                            int64_t bstride, int sc) {
     using C = ColCfg<N>;
     constexpr int CW = C::CW, T = C::T, E = C::E, NT = C::NT;
     __shared__ float2 lds[N * CW];
@@ -267,6 +303,19 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_col_pass(float2* __restrict__
         float2 pv = c < nlx ? Pj[(int64_t)i * nlx + c] : make_float2(0.f, 0.f);
         lds[i * CW + col] = cmul(lds[i * CW + col], pv);
     }
+    if (bcap) {
+        // the band rows are multiplied by other threads of the column: wait for all of them
+        __syncthreads();
+    }
+    if (bcap && c < nlx) {
+        // band coefficients of this column: ky = 0..h, then ny-h..ny-1, at band_off[c] + rank
+        const int h = band_h[c];
+        const int64_t dst = beam * bstride + band_off[c];
+        for (int r = t; r <= 2 * h; r += T) {
+            int ky = r <= h ? r : N - (2 * h + 1 - r);
+            store_c(bcap, dst + r, lds[ky * CW + col], sc);
+        }
+    }
     __syncthreads();
     if constexpr (MODE == 0) fft_lds<N, E, +1>(lds, col, CW, t, tw);
     else fft_lds<N, E, -1>(lds, col, CW, t, tw);
@@ -276,6 +325,117 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_col_pass(float2* __restrict__
         int cg = c0 + cc;
         if (cg < nlx) plane[(int64_t)row * nlx + cg] = lds[idx];
     }
+}
+
+// Band coefficients of P_{nz-1} e_q (the transposed sweep's start): P(q) at q's band slot.
+__global__ void k_init_band(void* bcap, int64_t bstride, int Kb, const int4* beams, int nb, const int* band_h,
+                            const int* band_off, int ny, int f, double lx, double ly, double lam, double dz_last,
+                            int sc) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nb * bstride) return;
+    int g = (int)(i % bstride);
+    int b = (int)(i / bstride);
+    int4 bm = beams[b];
+    int h = band_h[bm.x];
+    int r = bm.y <= h ? bm.y : 2 * h + 1 - (ny - bm.y);
+    float2 v = make_float2(0.f, 0.f);
+    if (g < Kb && g == band_off[bm.x] + r) {
+        double kx = (double)(f * bm.z) / lx, ky = (double)(f * bm.w) / ly;
+        double s, co;
+        sincospi(-lam * dz_last * (kx * kx + ky * ky), &s, &co);
+        v = make_float2((float)co, (float)s);
+    }
+    store_c(bcap, i, v, sc);
+}
+
+// Band FFT, row stage: rows y of T_j * H_t * W_i (real space, planes of `wstride`
+// complex) -> FFT_x -> live columns into scratch [(t Ni + i) ny + y][nlx].
+template <int N>
+__global__ __launch_bounds__(256) void k_band_rows(float2* __restrict__ out, const float2* __restrict__ W,
+                                                   int64_t wstride, int Ni, int nt, int ny, int nlx, int hlx,
+                                                   const float2* __restrict__ Tj, const float2* __restrict__ Hb,
+                                                   int64_t hstride, const float2* __restrict__ tw) {
+    constexpr int E = 8, T = N / E, S = 256 / T;
+    __shared__ float2 lds[S * N];
+    const int tid = threadIdx.x;
+    const int64_t total = (int64_t)nt * Ni * ny;
+    const int64_t g0 = (int64_t)blockIdx.x * S;
+    for (int idx = tid; idx < S * N; idx += 256) {
+        int s = idx / N, x = idx % N;
+        int64_t g = g0 + s;
+        float2 v = make_float2(0.f, 0.f);
+        if (g < total) {
+            int y = (int)(g % ny);
+            int64_t pi = g / ny;
+            int i = (int)(pi % Ni), t = (int)(pi / Ni);
+            int64_t px = (int64_t)y * N + x;
+            v = cmul(cmul(W[i * wstride + px], Hb[t * hstride + px]), Tj[px]);
+        }
+        lds[idx] = v;
+    }
+    __syncthreads();
+    const int s = tid / T, t = tid % T;
+    fft_lds<N, E, -1>(lds, s * N, 1, t, tw);
+    const bool all_live = (nlx == N);
+    for (int idx = tid; idx < S * nlx; idx += 256) {
+        int ss = idx / nlx, c = idx % nlx;
+        int64_t gg = g0 + ss;
+        if (gg >= total) continue;
+        int x = all_live ? c : (c <= hlx ? c : c - nlx + N);
+        out[gg * nlx + c] = lds[ss * N + x];
+    }
+}
+
+// Band FFT, column stage: FFT_y of live-column strips, band coefficients to
+// dst[plane * dstride + g] (SC or complex64); the padding slots Kb .. dstride-1 are zeroed.
+template <int N>
+__global__ __launch_bounds__(ColCfg<N>::NT) void k_band_cols(void* __restrict__ dst, int64_t dstride, int Kb,
+                                                             const float2* __restrict__ src, int nlx,
+                                                             const int* __restrict__ band_h,
+                                                             const int* __restrict__ band_off,
+                                                             const float2* __restrict__ tw, int sc) {
+    using C = ColCfg<N>;
+    constexpr int CW = C::CW, T = C::T, E = C::E, NT = C::NT;
+    __shared__ float2 lds[N * CW];
+    const int tid = threadIdx.x;
+    const int strips = (nlx + CW - 1) / CW;
+    const int64_t plane = blockIdx.x / strips;
+    const int strip = (int)(blockIdx.x % strips);
+    const int c0 = strip * CW;
+    const float2* sp = src + plane * (int64_t)N * nlx;
+    for (int idx = tid; idx < N * CW; idx += NT) {
+        int row = idx / CW, cc = idx % CW;
+        int c = c0 + cc;
+        lds[idx] = c < nlx ? sp[(int64_t)row * nlx + c] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    const int col = tid % CW, t = tid / CW;
+    fft_lds<N, E, -1>(lds, col, CW, t, tw);
+    const int c = c0 + col;
+    if (c < nlx) {
+        const int h = band_h[c];
+        const int64_t o = plane * dstride + band_off[c];
+        for (int r = t; r <= 2 * h; r += T) {
+            int ky = r <= h ? r : N - (2 * h + 1 - r);
+            store_c(dst, o + r, lds[ky * CW + col], sc);
+        }
+    }
+    if (strip == 0)
+        for (int g = Kb + tid; g < dstride; g += NT) store_c(dst, plane * dstride + g, make_float2(0.f, 0.f), sc);
+}
+
+// X[t][i][k] = H_t[k] * W_i[k] for k < K (zero for K <= k < ld), stored SC or complex64.
+__global__ void k_hmul(void* __restrict__ X, const float2* __restrict__ W, int64_t wstride,
+                       const float2* __restrict__ Hb, int64_t hstride, int Ni, int nt, int K, int ld, int sc) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t total = (int64_t)nt * Ni * ld;
+    if (i >= total) return;
+    int k = (int)(i % ld);
+    int64_t pi = i / ld;
+    int r = (int)(pi % Ni), t = (int)(pi / Ni);
+    float2 v = make_float2(0.f, 0.f);
+    if (k < K) v = cmul(Hb[t * hstride + k], W[r * wstride + k]);
+    store_c(X, i, v, sc);
 }
 
 // --------------------------------------------------------------------- deterministic reduction
@@ -322,16 +482,17 @@ void launch_twiddles(float2* tw, int n, hipStream_t st) {
 void launch_transmission(float2* T, const float* V, int64_t n, double sigma, hipStream_t st) {
     hipLaunchKernelGGL(k_transmission, dim3(blocks_for(n, 256)), dim3(256), 0, st, T, V, n, sigma);
 }
-void launch_propagator(float2* P, const double* dz, const Plan& p, hipStream_t st) {
+void launch_propagator(float2* P, const double* dz, const int* band_h, const Plan& p, hipStream_t st) {
     int64_t n = (int64_t)p.nz * p.ny * p.nlx;
     hipLaunchKernelGGL(k_propagator, dim3(blocks_for(n, 256)), dim3(256), 0, st, P, dz, p.nz, p.nx, p.ny, p.nlx, p.hlx,
-                       p.lx, p.ly, p.lam, p.kmax);
+                       p.lx, p.ly, p.lam, band_h);
 }
-void launch_probe_coefficients(float2* C, const int4* beams, const double* probes, const Plan& p, hipStream_t st) {
+void launch_probe_coefficients(void* C, const int4* beams, const double* probes, const Plan& p, int sc,
+                               hipStream_t st) {
     int64_t n = (int64_t)p.P * p.N1pad;
     double scale = (double)p.f * p.f / std::sqrt((double)p.N1fine) * p.c_scale;
     hipLaunchKernelGGL(k_probe_coefficients, dim3(blocks_for(n, 256)), dim3(256), 0, st, C, beams, p.N1, p.N1pad,
-                       probes, p.P, p.f, p.lx, p.ly, p.lam, p.defocus, p.cs, scale);
+                       probes, p.P, p.f, p.lx, p.ly, p.lam, p.defocus, p.cs, scale, sc);
 }
 void launch_init_forward(float2* S, const int4* beams, const Plan& p, hipStream_t st) {
     int64_t n = (int64_t)p.N1 * p.ny * p.nlx;
@@ -360,7 +521,7 @@ static void row_pass_n(const RowPassArgs& a, hipStream_t st) {
     constexpr int S = 256 / (N / 8);
     int64_t rows = (int64_t)a.nbeam * a.ny;
     hipLaunchKernelGGL((k_row_pass<N, MODE>), dim3(blocks_for(rows, S)), dim3(256), 0, st, a.state, a.nbeam, a.ny,
-                       a.nlx, a.hlx, a.Tj, a.tw, a.cap_ptr, (const int4*)a.cap_rec, a.win, a.win_beams, a.Kpad);
+                       a.nlx, a.hlx, a.Tj, a.tw, a.cap_ptr, (const int4*)a.cap_rec, a.win, a.win_beams, a.Kpad, a.sc);
 }
 
 void launch_row_pass(int nx, int mode, const RowPassArgs& a, hipStream_t st) {
@@ -377,25 +538,71 @@ void launch_row_pass(int nx, int mode, const RowPassArgs& a, hipStream_t st) {
 }
 
 template <int N, int MODE>
-static void col_pass_n(float2* state, int nbeam, int nlx, const float2* Pj, const float2* tw, hipStream_t st) {
+static void col_pass_n(float2* state, int nbeam, int nlx, const float2* Pj, const float2* tw, const BandCap& bc,
+                       hipStream_t st) {
     using C = ColCfg<N>;
     int strips = (nlx + C::CW - 1) / C::CW;
     hipLaunchKernelGGL((k_col_pass<N, MODE>), dim3((unsigned)((int64_t)nbeam * strips)), dim3(C::NT), 0, st, state,
-                       nbeam, nlx, Pj, tw);
+                       nbeam, nlx, Pj, tw, bc.band_h, bc.band_off, bc.dst, bc.stride, bc.sc);
 }
 
 void launch_col_pass(int ny, int mode, float2* state, int nbeam, int nlx, const float2* Pj, const float2* tw,
-                     hipStream_t st) {
+                     const BandCap& bc, hipStream_t st) {
 #define COLCASE(NN)                                                   \
     case NN:                                                          \
-        if (mode == 0) col_pass_n<NN, 0>(state, nbeam, nlx, Pj, tw, st); \
-        else col_pass_n<NN, 1>(state, nbeam, nlx, Pj, tw, st);        \
+        if (mode == 0) col_pass_n<NN, 0>(state, nbeam, nlx, Pj, tw, bc, st); \
+        else col_pass_n<NN, 1>(state, nbeam, nlx, Pj, tw, bc, st);    \
         break;
     switch (ny) {
         COLCASE(16) COLCASE(32) COLCASE(64) COLCASE(128) COLCASE(256) COLCASE(512) COLCASE(1024)
         default: break;
     }
 #undef COLCASE
+}
+
+void launch_init_band(void* bcap, int64_t bstride, const int4* beams, const int* band_h, const int* band_off,
+                      const Plan& p, int sc, hipStream_t st) {
+    int64_t n = (int64_t)p.N2 * bstride;
+    hipLaunchKernelGGL(k_init_band, dim3(blocks_for(n, 256)), dim3(256), 0, st, bcap, bstride, p.Kb, beams, p.N2,
+                       band_h, band_off, p.ny, p.f, p.lx, p.ly, p.lam, p.dz[p.nz - 1], sc);
+}
+
+template <int NX, int NY>
+static void band_fft_n(const BandFft& a, hipStream_t st) {
+    constexpr int S = 256 / (NX / 8);
+    int64_t rows = (int64_t)a.nt * a.Ni * a.ny;
+    hipLaunchKernelGGL((k_band_rows<NX>), dim3(blocks_for(rows, S)), dim3(256), 0, st, a.scratch, a.W, a.wstride,
+                       a.Ni, a.nt, a.ny, a.nlx, a.hlx, a.Tj, a.H, a.hstride, a.twx);
+    using C = ColCfg<NY>;
+    int strips = (a.nlx + C::CW - 1) / C::CW;
+    hipLaunchKernelGGL((k_band_cols<NY>), dim3((unsigned)((int64_t)a.nt * a.Ni * strips)), dim3(C::NT), 0, st, a.dst,
+                       a.dstride, a.Kb, a.scratch, a.nlx, a.band_h, a.band_off, a.twy, a.sc);
+}
+
+void launch_band_fft(int nx, int ny, const BandFft& a, hipStream_t st) {
+    if ((int64_t)a.nt * a.Ni <= 0) return;
+#define BF(X)                                              \
+    case X:                                                \
+        switch (nx) {                                      \
+            case 16: band_fft_n<16, X>(a, st); break;     \
+            case 32: band_fft_n<32, X>(a, st); break;     \
+            case 64: band_fft_n<64, X>(a, st); break;     \
+            case 128: band_fft_n<128, X>(a, st); break;   \
+            case 256: band_fft_n<256, X>(a, st); break;   \
+            case 512: band_fft_n<512, X>(a, st); break;   \
+            case 1024: band_fft_n<1024, X>(a, st); break; \
+        }                                                  \
+        break;
+    switch (ny) { BF(16) BF(32) BF(64) BF(128) BF(256) BF(512) BF(1024) }
+#undef BF
+}
+
+void launch_hmul(void* X, const float2* W, int64_t wstride, const float2* H, int64_t hstride, int Ni, int nt, int K,
+                 int ld, int sc, hipStream_t st) {
+    int64_t n = (int64_t)nt * Ni * ld;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_hmul, dim3(blocks_for(n, 256)), dim3(256), 0, st, X, W, wstride, H, hstride, Ni, nt, K, ld,
+                       sc);
 }
 
 void launch_reduce(double* map, int P, const int* rptr, const int* ent, const GemmDesc* descs, const float* part,

@@ -175,23 +175,80 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     for (int j = 0; j < p.nz; ++j)
         if (!by_slice[j].empty()) { ion.push_back(j); p.slices[j].ion = true; }
 
+    // band pixel set of the circular limit |k| <= kmax: live column c keeps |ky index| <= band_h[c]
+    p.band_h.assign(p.nlx, -1);
+    p.band_off.assign(p.nlx, 0);
+    {
+        int off = 0;
+        for (int c = 0; c < p.nlx; ++c) {
+            int cs = p.nlx == p.nx ? (c < (p.nx + 1) / 2 ? c : c - p.nx) : (c <= p.hlx ? c : c - p.nlx);
+            double kx = cs / p.lx;
+            int h = -1;
+            for (int b = 0; b <= p.ny / 2; ++b) {
+                double ky = b / p.ly;
+                if (std::sqrt(kx * kx + ky * ky) <= p.kmax) h = b;
+                else break;
+            }
+            if (2 * h + 1 > p.ny) h = (p.ny - 1) / 2;
+            p.band_h[c] = h;
+            p.band_off[c] = off;
+            off += std::max(0, 2 * h + 1);
+        }
+        p.Kb = off;
+        p.Kbpad = (int)round_up(std::max(p.Kb, 1), KPAD_MULT);
+    }
+    // full-cell windows contract in the band basis (exact): sum_r S_2 H S_1 equals the sum
+    // over band pixels g of (P_j x_{j+1})(g) * fft2(T_j H S_1)(g)
+    p.recip = p.full_window && !q.real_space;
+    const bool split = p.precision != EELS_FP32;
+    const int Kc = p.recip ? p.Kb : p.K;            // contraction length of the big GEMM
+    const int Kcpad = p.recip ? p.Kbpad : p.Kpad;
+
     // contraction order (Eq. TPRISM2 terms; both orders compute the same sums)
     double fl_S = 0, fl_P = 0;
     for (int j : ion)
         for (int s : by_slice[j]) {
             double nt = p.sites[s].n_trans, Ps = n_elig(s);
-            fl_S += 8.0 * p.N2 * (double)p.K * nt * p.N1 + 8.0 * nt * p.N2 * p.N1 * Ps;
-            fl_P += 8.0 * Ps * (double)p.K * p.N1 + 8.0 * p.N2 * (double)p.K * nt * Ps;
+            fl_S += 8.0 * p.N2 * (double)Kc * nt * p.N1 + 8.0 * nt * p.N2 * p.N1 * Ps;
+            fl_P += 8.0 * Ps * (double)p.K * p.N1 + 8.0 * p.N2 * (double)Kc * nt * Ps;
         }
     p.order = q.order == EELS_ORDER_AUTO ? (fl_S <= fl_P ? EELS_ORDER_S_FIRST : EELS_ORDER_PROBE_FIRST) : q.order;
     p.gemm_flops = p.order == EELS_ORDER_S_FIRST ? fl_S : fl_P;
     p.c_scale = p.precision == EELS_FP16_SPLIT ? 256.0f : 1.0f;
+    const bool orderS = p.order == EELS_ORDER_S_FIRST;
+    p.c_sc = (split && orderS) ? p.precision : 0;
+    p.w2_sc = split ? p.precision : 0;
+    p.mid2_sc = split ? p.precision : 0;
 
     // windows per slice
     auto slice_windows = [&](int j) -> int { return p.full_window ? 1 : (int)by_slice[j].size(); };
     int max_w2 = 0;
     for (int j : ion) max_w2 = std::max(max_w2, slice_windows(j));
     p.max_w2 = max_w2;
+    const int64_t w2_elems = p.recip ? (int64_t)p.N2 * p.Kbpad : (int64_t)max_w2 * p.N2 * p.Kpad;
+
+    // per-site intermediates: mid (Z or Psi), mid2 (H-multiplied operand, split or band
+    // basis), band-FFT scratch, norm partial sums
+    auto site_mid = [&](int s) -> int64_t {
+        int nt = p.sites[s].n_trans;
+        return orderS ? (int64_t)nt * p.N2 * p.N1pad : (int64_t)n_elig(s) * p.Kpad;
+    };
+    auto site_ni = [&](int s) -> int64_t { return orderS ? p.N1 : n_elig(s); };
+    auto site_mid2 = [&](int s) -> int64_t {
+        if (!p.recip && !split) return 0;
+        return (int64_t)p.sites[s].n_trans * site_ni(s) * Kcpad;
+    };
+    auto site_part = [&](int s) -> int64_t {
+        int nt = p.sites[s].n_trans;
+        int64_t tm = ceil_div(p.N2, GEMM_BM);
+        return tm * nt * (int64_t)n_elig(s);
+    };
+    int64_t scratch = 0;
+    if (p.recip)
+        for (int j : ion)
+            for (int s : by_slice[j])
+                scratch = std::max(scratch, (int64_t)p.sites[s].n_trans * site_ni(s) * p.ny * p.nlx);
+    p.scratch_elems = scratch;
 
     // fixed workspace
     auto A = [](size_t x) { return (size_t)round_up((int64_t)x, 256); };
@@ -200,18 +257,8 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
                    + A(c8 * p.nx) + A(c8 * p.ny) + A(c8 * (size_t)p.nz * p.ny * p.nx) +
                    A(c8 * (size_t)p.nz * p.ny * p.nlx) + A(c8 * (size_t)p.P * p.N1pad) +
                    A(c8 * (size_t)p.N1 * p.ny * p.nlx) + A(c8 * (size_t)p.N2 * p.ny * p.nlx) +
-                   A(c8 * (size_t)max_w2 * p.N2 * p.Kpad);
+                   A(c8 * (size_t)w2_elems) + A(c8 * (size_t)scratch);
 
-    // batches: mid (Z or Psi) and partial sums per site
-    auto site_mid = [&](int s) -> int64_t {
-        int nt = p.sites[s].n_trans;
-        return p.order == EELS_ORDER_S_FIRST ? (int64_t)nt * p.N2 * p.N1pad : (int64_t)n_elig(s) * p.Kpad;
-    };
-    auto site_part = [&](int s) -> int64_t {
-        int nt = p.sites[s].n_trans;
-        int64_t tm = ceil_div(p.N2, GEMM_BM);
-        return tm * nt * (int64_t)n_elig(s);
-    };
     size_t budget = q.max_workspace_bytes;
     size_t batch_cap = SIZE_MAX;
     const size_t win1_bytes = c8 * (size_t)p.N1 * p.Kpad;
@@ -227,32 +274,33 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     }
     struct PendingBatch { int slice; std::vector<int> sites; };
     std::vector<PendingBatch> pend;
-    int64_t max_mid = 0, max_part = 0;
+    int64_t max_mid = 0, max_mid2 = 0, max_part = 0;
     for (int j : ion) {
         PendingBatch cur{j, {}};
-        int64_t m = 0, pt = 0;
+        int64_t m = 0, m2 = 0, pt = 0;
         for (int s : by_slice[j]) {
-            int64_t sm = site_mid(s), sp = site_part(s);
-            size_t bytes_new = (size_t)(m + sm) * 8 + (size_t)(pt + sp) * 4;
+            int64_t sm = site_mid(s), sm2 = site_mid2(s), sp = site_part(s);
+            size_t bytes_new = (size_t)(m + sm + m2 + sm2) * 8 + (size_t)(pt + sp) * 4;
             if (!cur.sites.empty() && bytes_new > batch_cap) {
                 pend.push_back(cur);
-                max_mid = std::max(max_mid, m); max_part = std::max(max_part, pt);
-                cur.sites.clear(); m = 0; pt = 0;
+                max_mid = std::max(max_mid, m); max_mid2 = std::max(max_mid2, m2); max_part = std::max(max_part, pt);
+                cur.sites.clear(); m = 0; m2 = 0; pt = 0;
             }
-            if ((size_t)sm * 8 + (size_t)sp * 4 > batch_cap)
+            if ((size_t)(sm + sm2) * 8 + (size_t)sp * 4 > batch_cap)
                 return fail(EELS_ERR_OOM, "one site's contraction does not fit the budget");
-            cur.sites.push_back(s); m += sm; pt += sp;
+            cur.sites.push_back(s); m += sm; m2 += sm2; pt += sp;
         }
         pend.push_back(cur);
-        max_mid = std::max(max_mid, m); max_part = std::max(max_part, pt);
+        max_mid = std::max(max_mid, m); max_mid2 = std::max(max_mid2, m2); max_part = std::max(max_part, pt);
     }
     p.mid_elems = max_mid;
+    p.mid2_elems = max_mid2;
     p.part_elems = max_part;
 
     // slice groups (descending): S_1 windows of a group must fit what is left
     size_t w1_cap = SIZE_MAX;
     if (budget > 0) {
-        size_t used = fixed + A((size_t)max_mid * 8) + A((size_t)max_part * 4);
+        size_t used = fixed + A((size_t)max_mid * 8) + A((size_t)max_mid2 * 8) + A((size_t)max_part * 4);
         if (budget <= used) return fail(EELS_ERR_OOM, "memory budget too small");
         w1_cap = budget - used;
     }
@@ -322,10 +370,13 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
         t.resize(p.P);
         for (int r = 0; r < p.P; ++r) t[r] = r;
         p.ident_off = B.append(t);
+        p.band_h_off = B.append(std::vector<int32_t>(p.band_h.begin(), p.band_h.end()));
+        p.band_off_off = B.append(std::vector<int32_t>(p.band_off.begin(), p.band_off.end()));
     }
-    // capture CSRs per ionised slice
+    // capture CSRs per ionised slice (S_2 windows only in the real-space contraction)
     for (int j : ion) {
         for (int which = 0; which < 2; ++which) {
+            if (which == 1 && p.recip) continue;
             std::vector<std::vector<CaptureRec>> rows(p.ny);
             if (p.full_window) {
                 int w = which == 0 ? p.site_w1[by_slice[j][0]] : 0;
@@ -356,48 +407,74 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
             site_idx[s] = B.append(std::vector<int32_t>(p.site_probes[s].begin(), p.site_probes[s].end()));
         else site_idx[s] = p.ident_off;
     }
-    // descriptors and reduction CSRs
+    // descriptors, producer jobs and reduction CSRs
     p.descs.clear();
     p.batches.clear();
+    p.jobs.clear();
     const int64_t w1_stride = (int64_t)p.N1 * p.Kpad, w2_stride = (int64_t)p.N2 * p.Kpad;
+    const bool h_in_gemm = !p.recip && !split;     // FP32 real-space: H applied in the GEMM prologue
     for (auto& pb : pend) {
         Batch bt{};
         bt.slice = pb.slice;
         bt.order = p.order;
-        int64_t moff = 0, poff = 0;
-        std::vector<int> d2_of_site;
+        int64_t moff = 0, m2off = 0, poff = 0;
+        std::vector<int64_t> site_moff, site_m2off;
+        for (int s : pb.sites) {
+            site_moff.push_back(moff); site_m2off.push_back(m2off);
+            moff += site_mid(s); m2off += site_mid2(s);
+        }
+        // producer jobs (band FFT or H multiply) write mid2 from S_1 windows (order S) or Psi (order P)
+        bt.job_begin = (int)p.jobs.size();
+        if (p.recip || split) {
+            for (size_t si = 0; si < pb.sites.size(); ++si) {
+                int s = pb.sites[si];
+                Job jb{};
+                jb.from_mid = orderS ? 0 : 1;
+                jb.w_off = orderS ? (int64_t)p.site_w1[s] * w1_stride : site_moff[si];
+                jb.Ni = (int)site_ni(s);
+                jb.nt = p.sites[s].n_trans;
+                jb.h_off = p.sites[s].h_offset * p.K;
+                jb.dst_off = site_m2off[si];
+                p.jobs.push_back(jb);
+            }
+        }
+        bt.job_count = (int)p.jobs.size() - bt.job_begin;
+
         bt.d1_begin = (int)p.descs.size();
         int tiles = 0;
-        std::vector<int64_t> site_moff;
-        for (int s : pb.sites) {
+        for (size_t si = 0; si < pb.sites.size(); ++si) {
+            int s = pb.sites[si];
             const eels_site& st = p.sites[s];
             int Ps = n_elig(s);
             GemmDesc d{};
-            site_moff.push_back(moff);
-            if (p.order == EELS_ORDER_S_FIRST) {
-                // Z_s[t][q][k] = sum_r S2w[q][r] H_t[r] S1w[k][r]
-                d.a_off = (int64_t)p.site_w2[s] * w2_stride; d.lda = p.Kpad;
-                d.b_off = (int64_t)p.site_w1[s] * w1_stride; d.ldb = p.Kpad;
-                d.h_off = st.h_offset * p.K; d.ldh = p.K;
-                d.c_off = moff; d.ldc_m = p.N1pad; d.ldc_t = (int64_t)p.N2 * p.N1pad;
-                d.M = p.N2; d.N_inner = p.N1; d.n_t = st.n_trans; d.K = p.K;
+            if (orderS) {
+                // Z_s[t][q][k] = sum_r S2w[q][r] H_t[r] S1w[k][r]  (or its band-basis form)
+                if (p.recip) { d.a_off = 0; d.lda = p.Kbpad; }
+                else { d.a_off = (int64_t)p.site_w2[s] * w2_stride; d.lda = p.Kpad; }
+                if (h_in_gemm) {
+                    d.b_off = (int64_t)p.site_w1[s] * w1_stride; d.ldb = p.Kpad;
+                    d.h_off = st.h_offset * p.K; d.ldh = p.K;
+                } else {
+                    d.b_off = site_m2off[si]; d.ldb = Kcpad; d.b_tstride = (int64_t)p.N1 * Kcpad;
+                    d.h_off = -1;
+                }
+                d.c_off = site_moff[si]; d.ldc_m = p.N1pad; d.ldc_t = (int64_t)p.N2 * p.N1pad;
+                d.M = p.N2; d.N_inner = p.N1; d.n_t = st.n_trans; d.K = Kc;
                 d.idx_off = -1;
             } else {
                 // Psi_s[i][r] = sum_k C[idx[i]][k] S1w[k][r]   (B operand N-contiguous)
                 d.a_off = 0; d.lda = p.N1pad;
                 d.b_off = (int64_t)p.site_w1[s] * w1_stride; d.ldb = p.Kpad;
                 d.h_off = -1; d.ldh = 0;
-                d.c_off = moff; d.ldc_m = p.Kpad; d.ldc_t = 0;
+                d.c_off = site_moff[si]; d.ldc_m = p.Kpad; d.ldc_t = 0;
                 d.M = Ps; d.N_inner = p.K; d.n_t = 1; d.K = p.N1;
                 d.idx_off = (int)site_idx[s];
             }
-            d.a_tstride = 0;
             d.tiles_m = (int)ceil_div(d.M, GEMM_BM);
             d.tiles_n = (int)ceil_div(d.N_inner, GEMM_BN);
             d.tile_start = tiles;
             tiles += d.tiles_m * d.tiles_n * d.n_t;
             p.descs.push_back(d);
-            moff += site_mid(s);
         }
         bt.d1_count = (int)p.descs.size() - bt.d1_begin;
         bt.d1_tiles = tiles;
@@ -410,24 +487,8 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
             const eels_site& st = p.sites[s];
             int Ps = n_elig(s);
             const std::vector<int>* pl = p.f > 1 ? &p.site_probes[s] : nullptr;
-            auto add = [&](GemmDesc d) {
-                d.tiles_m = (int)ceil_div(d.M, GEMM_BM);
-                d.tiles_n = (int)ceil_div(d.N_inner, GEMM_BN);
-                d.tile_start = tiles;
-                d.p_off = poff; d.ld_part = (int64_t)d.n_t * d.N_inner;
-                poff += (int64_t)d.tiles_m * d.ld_part;
-                tiles += d.tiles_m * d.tiles_n * d.n_t;
-                int di = (int)p.descs.size();
-                p.descs.push_back(d);
-                if (p.f > 1)
-                    for (int i = 0; i < Ps; ++i) {
-                        int r = pl ? (*pl)[i] : i;
-                        ent[r].push_back(di);
-                        ent[r].push_back(i);
-                    }
-            };
             GemmDesc d{};
-            if (p.order == EELS_ORDER_S_FIRST) {
+            if (orderS) {
                 // A_n(q, R) = sum_k Z_s[t][q][k] C[R][k]
                 d.a_off = site_moff[si]; d.lda = p.N1pad; d.a_tstride = (int64_t)p.N2 * p.N1pad;
                 d.b_off = 0; d.ldb = p.N1pad;
@@ -435,14 +496,33 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
                 d.M = p.N2; d.N_inner = Ps; d.n_t = st.n_trans; d.K = p.N1;
                 d.idx_off = (int)site_idx[s];
             } else {
-                // A_n(q, R) = sum_r S2w[q][r] H_t[r] Psi_s[i][r]
-                d.a_off = (int64_t)p.site_w2[s] * w2_stride; d.lda = p.Kpad; d.a_tstride = 0;
-                d.b_off = site_moff[si]; d.ldb = p.Kpad;
-                d.h_off = st.h_offset * p.K; d.ldh = p.K;
-                d.M = p.N2; d.N_inner = Ps; d.n_t = st.n_trans; d.K = p.K;
+                // A_n(q, R) = sum_r S2w[q][r] H_t[r] Psi_s[i][r]  (or its band-basis form)
+                if (p.recip) { d.a_off = 0; d.lda = p.Kbpad; }
+                else { d.a_off = (int64_t)p.site_w2[s] * w2_stride; d.lda = p.Kpad; }
+                if (h_in_gemm) {
+                    d.b_off = site_moff[si]; d.ldb = p.Kpad;
+                    d.h_off = st.h_offset * p.K; d.ldh = p.K;
+                } else {
+                    d.b_off = site_m2off[si]; d.ldb = Kcpad; d.b_tstride = (int64_t)Ps * Kcpad;
+                    d.h_off = -1;
+                }
+                d.M = p.N2; d.N_inner = Ps; d.n_t = st.n_trans; d.K = Kc;
                 d.idx_off = -1;
             }
-            add(d);
+            d.tiles_m = (int)ceil_div(d.M, GEMM_BM);
+            d.tiles_n = (int)ceil_div(d.N_inner, GEMM_BN);
+            d.tile_start = tiles;
+            d.p_off = poff; d.ld_part = (int64_t)d.n_t * d.N_inner;
+            poff += (int64_t)d.tiles_m * d.ld_part;
+            tiles += d.tiles_m * d.tiles_n * d.n_t;
+            int di = (int)p.descs.size();
+            p.descs.push_back(d);
+            if (p.f > 1)
+                for (int i = 0; i < Ps; ++i) {
+                    int r = pl ? (*pl)[i] : i;
+                    ent[r].push_back(di);
+                    ent[r].push_back(i);
+                }
         }
         bt.d2_count = (int)p.descs.size() - bt.d2_begin;
         bt.d2_tiles = tiles;
@@ -506,8 +586,10 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     p.off_s1 = take(c8 * (size_t)p.N1 * p.ny * p.nlx);
     p.off_s2 = take(c8 * (size_t)p.N2 * p.ny * p.nlx);
     p.off_w1 = take(c8 * (size_t)std::max(p.max_w1, 1) * p.N1 * p.Kpad);
-    p.off_w2 = take(c8 * (size_t)std::max(p.max_w2, 1) * p.N2 * p.Kpad);
-    p.off_mid = take(c8 * (size_t)std::max<int64_t>(p.mid_elems, 1) + 4096);
+    p.off_w2 = take(c8 * (size_t)std::max<int64_t>(w2_elems, 1));
+    p.off_mid = take(c8 * (size_t)std::max<int64_t>(p.mid_elems, 1));
+    p.off_mid2 = take(c8 * (size_t)std::max<int64_t>(p.mid2_elems, 1));
+    p.off_scratch = take(c8 * (size_t)std::max<int64_t>(p.scratch_elems, 1));
     p.off_part = take(4 * (size_t)std::max<int64_t>(p.part_elems, 1));
     p.ws_bytes = off;
     if (budget > 0 && p.ws_bytes > budget) return fail(EELS_ERR_OOM, "workspace exceeds the memory budget");

@@ -42,14 +42,16 @@ class ProblemC(C.Structure):
                 ("cs_A", C.c_double), ("interp_f", C.c_int), ("bandlimit", C.c_double),
                 ("window_A", C.c_double), ("n_probes", C.c_int), ("probe_xy", C.POINTER(C.c_double)),
                 ("n_sites", C.c_int), ("sites", C.POINTER(Site)), ("n_trans_total", C.c_int64),
-                ("precision", C.c_int), ("order", C.c_int), ("max_workspace_bytes", C.c_size_t)]
+                ("precision", C.c_int), ("order", C.c_int), ("max_workspace_bytes", C.c_size_t),
+                ("real_space", C.c_int)]
 
 
 class PlanInfo(C.Structure):
     _fields_ = [("n_beams_in", C.c_int), ("n_beams_out", C.c_int), ("n_beams_in_fine", C.c_int),
                 ("n_live_x", C.c_int), ("window_nx", C.c_int), ("window_ny", C.c_int), ("k_pixels", C.c_int),
                 ("k_stride", C.c_int), ("n_ion_slices", C.c_int), ("n_groups", C.c_int), ("n_batches", C.c_int),
-                ("order", C.c_int), ("lambda_A", C.c_double), ("sigma", C.c_double), ("gemm_flops", C.c_double),
+                ("order", C.c_int), ("band_basis", C.c_int), ("band_pixels", C.c_int),
+                ("lambda_A", C.c_double), ("sigma", C.c_double), ("gemm_flops", C.c_double),
                 ("sweep_bytes", C.c_double), ("sweep_beam_slices", C.c_double), ("workspace_bytes", C.c_size_t)]
 
 
@@ -57,7 +59,8 @@ _LIB: Optional[C.CDLL] = None
 
 EXPORTS = ["eels_get_version", "eels_status_string", "eels_last_error", "eels_plan_create",
            "eels_plan_workspace_bytes", "eels_plan_info_get", "eels_plan_beams", "eels_plan_destroy",
-           "eels_execute", "eels_debug_s1", "eels_debug_s2", "eels_gemm_work_bytes", "eels_debug_cgemm"]
+           "eels_execute", "eels_debug_s1", "eels_debug_s2", "eels_gemm_work_bytes", "eels_debug_cgemm",
+           "eels_tune_set", "eels_tune_get"]
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:
@@ -79,10 +82,12 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.eels_execute.argtypes = [vp, vp, vp, vp, vp, sz, vp]
     lib.eels_debug_s1.argtypes = [vp, vp, C.c_int, vp, vp, sz, vp]
     lib.eels_debug_s2.argtypes = [vp, vp, C.c_int, vp, vp, sz, vp]
-    lib.eels_gemm_work_bytes.argtypes = [C.c_int, C.c_int]
+    lib.eels_gemm_work_bytes.argtypes = [C.c_int, C.c_int, C.c_int]
     lib.eels_gemm_work_bytes.restype = sz
     lib.eels_debug_cgemm.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp, C.c_int,
                                      vp, vp, vp]
+    lib.eels_tune_set.argtypes = [C.c_int, C.c_int]
+    lib.eels_tune_get.argtypes = [C.c_int]
     _LIB = lib
     return lib
 
@@ -109,7 +114,8 @@ class Plan:
     problem statement (grid, cell, slices, optics, sites, probes; see include/eels.h)."""
 
     def __init__(self, problem: Any, precision: str = "fp32", order: str = "auto",
-                 max_workspace_bytes: int = 0, lambda_A: float = 0.0, sigma: float = 0.0):
+                 max_workspace_bytes: int = 0, lambda_A: float = 0.0, sigma: float = 0.0,
+                 real_space: bool = False):
         lib = load_library()
         pr = problem
         self._dz = np.ascontiguousarray(pr.dz, dtype=np.float64)
@@ -131,7 +137,7 @@ class Plan:
             n_probes=int(self._probes.shape[0]),
             probe_xy=self._probes.ctypes.data_as(C.POINTER(C.c_double)), n_sites=S,
             sites=self._sites, n_trans_total=n_trans, precision=PRECISIONS[precision], order=ORDERS[order],
-            max_workspace_bytes=int(max_workspace_bytes))
+            max_workspace_bytes=int(max_workspace_bytes), real_space=int(bool(real_space)))
         self.precision = precision
         h = C.c_void_p()
         _check(lib.eels_plan_create(C.byref(h), C.byref(self.problem)))
@@ -200,10 +206,11 @@ def device_inputs(problem, device="cuda"):
 
 
 def solve(problem, precision: str = "fp32", order: str = "auto", device="cuda",
-          max_workspace_bytes: int = 0) -> np.ndarray:
+          max_workspace_bytes: int = 0, real_space: bool = False) -> np.ndarray:
     """Compute one EELS map on the GPU and return it as float64 numpy [n_probes]."""
     import torch
-    plan = Plan(problem, precision=precision, order=order, max_workspace_bytes=max_workspace_bytes)
+    plan = Plan(problem, precision=precision, order=order, max_workspace_bytes=max_workspace_bytes,
+                real_space=real_space)
     V, H = device_inputs(problem, device)
     ws = plan.alloc_workspace(device)
     out = torch.empty(plan.n_probes, dtype=torch.float64, device=device)
@@ -212,8 +219,19 @@ def solve(problem, precision: str = "fp32", order: str = "auto", device="cuda",
     return out.cpu().numpy()
 
 
-def gemm_work_bytes(m: int, n: int) -> int:
-    return int(load_library().eels_gemm_work_bytes(m, n))
+def gemm_work_bytes(m: int, n: int, k: int) -> int:
+    return int(load_library().eels_gemm_work_bytes(m, n, k))
+
+
+TUNE_SC_STAGES = 0
+
+
+def tune_set(key: int, value: int):
+    _check(load_library().eels_tune_set(int(key), int(value)))
+
+
+def tune_get(key: int) -> int:
+    return int(load_library().eels_tune_get(int(key)))
 
 
 def cgemm(A, B, precision: str = "fp32", norm2: bool = False, stream=None):
@@ -228,7 +246,7 @@ def cgemm(A, B, precision: str = "fp32", norm2: bool = False, stream=None):
     Ap[:, :k] = A
     Bp = torch.zeros((n, ldb), dtype=torch.complex64, device=B.device)
     Bp[:, :k] = B
-    work = torch.empty(gemm_work_bytes(m, n), dtype=torch.uint8, device=A.device)
+    work = torch.empty(gemm_work_bytes(m, n, k), dtype=torch.uint8, device=A.device)
     if norm2:
         out = torch.empty(n, dtype=torch.float64, device=A.device)
         _check(load_library().eels_debug_cgemm(PRECISIONS[precision], m, n, k, _ptr(Ap), lda, _ptr(Bp), ldb, None,

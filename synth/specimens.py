@@ -155,8 +155,9 @@ def transitions_lm(lmax: int = 2, widths=(0.3, 0.4, 0.5)) -> List[Tuple[int, int
 
 
 def transition_potentials(nx, ny, lx, ly, window_A, site_xy, trans: Sequence[Tuple[int, int, float]],
-                          batch=2048) -> np.ndarray:
-    """H for every (site, transition), complex128 [S*len(trans), nwy, nwx] or [.., ny, nx]."""
+                          batch=256, dtype=np.complex64) -> np.ndarray:
+    """H for every (site, transition), [S*len(trans), nwy, nwx] or [.., ny, nx], evaluated in
+    float64 and stored as ``dtype``."""
     dx, dy = lx / nx, ly / ny
     site_xy = np.asarray(site_xy, dtype=np.float64).reshape(-1, 2)
     S = site_xy.shape[0]
@@ -165,7 +166,7 @@ def transition_potentials(nx, ny, lx, ly, window_A, site_xy, trans: Sequence[Tup
         nwy, nwx = ny, nx
     else:
         nwy, nwx = shp
-    out = np.zeros((S * len(trans), nwy, nwx), dtype=np.complex128)
+    out = np.zeros((S * len(trans), nwy, nwx), dtype=dtype)
     for b0 in range(0, S, batch):
         xs = site_xy[b0:b0 + batch, 0]
         ys = site_xy[b0:b0 + batch, 1]
@@ -202,12 +203,12 @@ def _finish(name, nx, ny, lx, ly, dz, atom_slice, atom_xy, atom_amp, atom_w,
     dz = np.asarray(dz, dtype=np.float64)
     V = projected_potential(nx, ny, lx, ly, len(dz), atom_slice, atom_xy, atom_amp, atom_w)
     site_xy = np.asarray(site_xy, dtype=np.float64).reshape(-1, 2)
-    H = transition_potentials(nx, ny, lx, ly, optics.get("window_A", 0.0), site_xy, trans)
+    H = transition_potentials(nx, ny, lx, ly, optics.get("window_A", 0.0), site_xy, trans, dtype=np.complex64)
     S = site_xy.shape[0]
     nt = len(trans)
     return Problem(
         name=name, nx=nx, ny=ny, lx=float(lx), ly=float(ly), dz=dz,
-        V=V.astype(np.float32), H=H.astype(np.complex64),
+        V=V.astype(np.float32), H=H,
         site_slice=np.asarray(site_slice, dtype=np.int32),
         site_xy=site_xy,
         site_ntrans=np.full(S, nt, dtype=np.int32),
@@ -257,7 +258,7 @@ def perovskite_atoms(ncell=5, a=4.0, c=3.9, thickness=100.0, dzs=2.0):
             ((0.5, 0.5, 0.0), 2), ((0.5, 0.0, 0.5), 2), ((0.0, 0.5, 0.5), 2)]
     pairs = {0: (60.0, 15.0), 1: (40.0, 10.0), 2: (15.0, 4.0)}
     sl, xy, amp, wid, sp = [], [], [], [], []
-    nlay = int(math.floor(thickness / c + 1e-9))
+    nlay = int(math.ceil(thickness / c))
     for m in range(nlay):
         for iy in range(ncell):
             for ix in range(ncell):

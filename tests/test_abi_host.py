@@ -117,6 +117,20 @@ def test_contraction_order_choice():
     b = eels.Plan(p, order="probe_first").info()
     auto = eels.Plan(p).info()
     assert auto["gemm_flops"] == min(a["gemm_flops"], b["gemm_flops"])
-    # order P for config 1: 8 (K N1 P + N2 K n_t P)
+    # order P for config 1: 8 (K N1 P + N2 Kc n_t P), Kc = band pixels (band basis) or K
     K, N1, N2, P, nt = 4096, 325, 1305, 16, 3
-    assert b["gemm_flops"] == pytest.approx(8.0 * (K * N1 * P + N2 * K * nt * P))
+    Kb = b["band_pixels"]
+    assert b["band_basis"] == 1 and 0.33 * K < Kb < 0.36 * K   # ~pi/9 of the grid
+    assert b["gemm_flops"] == pytest.approx(8.0 * (K * N1 * P + N2 * Kb * nt * P))
+    r = eels.Plan(p, order="probe_first", real_space=True).info()
+    assert r["band_basis"] == 0
+    assert r["gemm_flops"] == pytest.approx(8.0 * (K * N1 * P + N2 * K * nt * P))
+
+
+def test_band_table_matches_oracle_mask():
+    """Band pixel count equals the oracle's circular mask count (same inclusive rule)."""
+    _lib()
+    from oracle import physics as ph
+    for p in (synth.config1(), synth.random_problem(3, n=32, ny=64, L=8.0, Ly=13.0, nz=2)):
+        inf = eels.Plan(p).info()
+        assert inf["band_pixels"] == int(ph.band_mask(p.nx, p.ny, p.lx, p.ly).sum())

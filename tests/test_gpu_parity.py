@@ -122,11 +122,12 @@ def test_config1_fp32_matches_both_oracles():
     I1 = conventional.conventional_map(p)
     I2 = prism.prism_map(p)
     for order in ("auto", "s_first", "probe_first"):
-        _say("config1", order)
-        g = _map(eels, p, "fp32", order)
-        assert metrics.rel_l2(g, I1) < 1e-4
-        assert metrics.rel_l2(g, I2) < 1e-4
-        assert metrics.max_rel(g, I2) < 1e-4
+        for real in (False, True):
+            _say("config1", order, "real-space" if real else "band basis")
+            g = _map(eels, p, "fp32", order, real_space=real)
+            assert metrics.rel_l2(g, I1) < 1e-4
+            assert metrics.rel_l2(g, I2) < 1e-4
+            assert metrics.max_rel(g, I2) < 1e-4
 
 
 @pytest.mark.parametrize("prec,tol", [("bf16_split", 1e-3), ("fp16_split", 1e-3)])
@@ -135,8 +136,9 @@ def test_config1_split_precision(prec, tol):
     p = synth.config1()
     I2 = prism.prism_map(p)
     for order in ("s_first", "probe_first"):
-        _say("config1", prec, order)
-        assert metrics.rel_l2(_map(eels, p, prec, order), I2) < tol
+        for real in (False, True):
+            _say("config1", prec, order, real)
+            assert metrics.rel_l2(_map(eels, p, prec, order, real_space=real), I2) < tol
 
 
 CASES = {
@@ -153,14 +155,15 @@ CASES = {
 
 @pytest.mark.parametrize("name", sorted(CASES))
 @pytest.mark.parametrize("order", ["s_first", "probe_first"])
-def test_random_cases_fp32(name, order):
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16_split", 1e-3)])
+def test_random_cases(name, order, prec, tol):
     eels = _need_gpu()
     kw = dict(CASES[name])
     p = synth.random_problem(kw.pop("seed"), **kw)
-    _say("case", name, order)
+    _say("case", name, order, prec)
     ref = prism.prism_map(p)
-    g = _map(eels, p, "fp32", order)
-    assert metrics.rel_l2(g, ref) < 1e-4
+    g = _map(eels, p, prec, order)
+    assert metrics.rel_l2(g, ref) < tol
 
 
 def test_interpolation_factor_case():
