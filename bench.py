@@ -1,0 +1,240 @@
+"""EELS map throughput on one MI355X (probe positions per second).
+
+Workload: the perovskite-crystal map (256 x 256 px over 20 x 20 A, 50 slices of 2 A,
+650 ionised B sites x 9 transitions contracted over the full cell, 64 x 64 probes,
+300 keV, 21 mrad aperture, 0-50 mrad detector).  A step is one complete map: set-up,
+both scattering-matrix sweeps, every contraction and the FP64 reduction, with the
+inputs already resident in HBM.
+
+`value` is the BF16-split (hi+lo, FP32 accumulate) throughput.  The plain FP32 path
+is reported beside it, measured on the contractions of a bounded subset of ionised
+slices and scaled by GEMM work (see the `fp32` object); `--fp32-full` times it on the
+whole map instead.  `roofline` is for the dominant kernel (the first contraction
+GEMM), timed with HIP events on the execute stream.  `cpu_baseline` is the FP64
+conventional-multislice oracle timed on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "EELS map probe-px/s (FP32 plain vs BF16-split @1e-3 err); p50/p99 latency"
+PEAK_BF16_TFLOPS = 2500.0
+PEAK_FP32_TFLOPS = 157.3
+WORKLOAD = ("perovskite crystal 256x256 px over 20x20 A, 50 slices x 2 A, 650 ionised B sites x 9 "
+            "transitions (full-cell contraction), 64x64 probes, 300 keV, 21 mrad aperture, 0-50 mrad "
+            "detector")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def subset_sites(p, keep):
+    return p.replace(site_slice=p.site_slice[keep], site_xy=p.site_xy[keep],
+                     site_ntrans=p.site_ntrans[keep], site_hoff=p.site_hoff[keep])
+
+
+def gemm1_flops(info, p):
+    """Useful complex flops of the first contraction GEMM (8 M N K summed over sites)."""
+    kc = info["band_pixels"] if info["band_basis"] else info["k_pixels"]
+    nt = float(np.sum(p.site_ntrans))
+    return 8.0 * info["n_beams_out"] * kc * nt * info["n_beams_in"]
+
+
+def cpu_baseline(p, budget_s=25.0):
+    """FP64 conventional multislice (oracle) on one probe and the sites of one ionised
+    slice; the time is scaled to the full site list with the per-probe multislice
+    operation count n_z + sum_sites n_trans (n_z - j_site)."""
+    from oracle import conventional
+    ion = sorted(set(p.site_slice.tolist()))
+    j = ion[len(ion) // 2]
+    keep = np.nonzero(p.site_slice == j)[0]
+    q = subset_sites(p, keep).replace(probes=p.probes[:1], probe_shape=(1, 1))
+    nz = p.n_slices
+    ops_sample = nz + float(np.sum(q.site_ntrans * (nz - q.site_slice)))
+    ops_full = nz + float(np.sum(p.site_ntrans * (nz - p.site_slice)))
+    t0 = time.perf_counter()
+    conventional.conventional_map(q, probe_chunk=1)
+    dt = time.perf_counter() - t0
+    per_probe = dt * ops_full / ops_sample
+    return {
+        "value": 1.0 / per_probe, "unit": "probe-px/s", "cores": 1, "kind": "oracle",
+        "sample": (f"conventional multislice FP64 (numpy, one thread), 1 probe x {len(keep)} sites of "
+                   f"ionised slice {j} ({dt:.1f} s); scaled by multislice operations "
+                   f"{ops_full:.0f}/{ops_sample:.0f} to all {p.n_sites} sites"),
+        "seconds_measured": round(dt, 2),
+        "host_cpus": os.cpu_count(),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--precision", default="bf16_split", choices=["bf16_split", "fp16_split", "fp32"])
+    ap.add_argument("--fp32-full", action="store_true", help="time the FP32 path on the whole map")
+    ap.add_argument("--fp32-slices", type=int, default=2, help="ionised slices of the FP32 sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--check", action="store_true", help="compare sampled probes with the stored FP64 values")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is "
+              "described in DESIGN.md and not run here.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_1908_07628_amd import eels
+
+    t0 = time.time()
+    p = synth.config2()
+    log(f"inputs generated in {time.time() - t0:.1f} s: {p.n_sites} sites, {p.n_trans} transitions")
+    V, H = eels.device_inputs(p)
+    free, total = torch.cuda.mem_get_info()
+
+    # untimed warm-up on one slice of the workload (loads the kernels; not a step)
+    ion = sorted(set(p.site_slice.tolist()))
+    small = subset_sites(p, np.nonzero(p.site_slice == ion[-1])[0])
+    wplan = eels.Plan(small, precision=args.precision)
+    wws = wplan.alloc_workspace()
+    wout = torch.empty(p.n_probes, dtype=torch.float64, device="cuda")
+    wplan.execute(V, H, wout, wws)
+    torch.cuda.synchronize()
+    del wws, wplan
+
+    plan = eels.Plan(p, precision=args.precision)
+    info = plan.info()
+    ws = plan.alloc_workspace()
+    out = torch.empty(p.n_probes, dtype=torch.float64, device="cuda")
+    log(f"plan: N1={info['n_beams_in']} N2={info['n_beams_out']} band pixels={info['band_pixels']} "
+        f"order={'S' if info['order'] == 1 else 'P'} batches={info['n_batches']} "
+        f"workspace={info['workspace_bytes'] / 1e9:.1f} GB (free {free / 1e9:.0f} GB)")
+    for w in range(args.warmup):
+        plan.execute(V, H, out, ws)
+        torch.cuda.synchronize()
+        log(f"warmup step {w + 1}/{args.warmup} done")
+
+    eels.timing_enable(8192)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    phase_tot = {}
+    for k in range(args.steps):
+        plan.execute(V, H, out, ws)
+        torch.cuda.synchronize()
+        ph = eels.timing_read()
+        for name, v in ph.items():
+            a = phase_tot.setdefault(name, {"ms": 0.0, "count": 0})
+            a["ms"] += v["ms"]
+            a["count"] += v["count"]
+        log(f"step {k + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    eels.timing_enable(0)
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = p.n_probes * args.steps / elapsed
+    gpu_map = out.cpu().numpy()
+
+    # roofline of the dominant kernel (first contraction GEMM)
+    g1 = phase_tot["gemm1"]
+    g1_flops = gemm1_flops(info, p)
+    n_launch_per_step = g1["count"] / args.steps
+    avg_ms = g1["ms"] / max(g1["count"], 1)
+    split = args.precision != "fp32"
+    exec_factor = 3.0 if split else 1.0           # hi*hi + hi*lo + lo*hi
+    per_launch = g1_flops / n_launch_per_step
+    achieved = exec_factor * per_launch / (avg_ms * 1e-3) / 1e12
+    peak = PEAK_BF16_TFLOPS if split else PEAK_FP32_TFLOPS
+    roofline = {
+        "bound": "mfma", "kernel": "k_cgemm_sc (first contraction GEMM)" if split else "k_cgemm",
+        "achieved": round(achieved, 1), "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+        "traffic": None, "avg_launch_ms": round(avg_ms, 3), "launches_per_step": n_launch_per_step,
+        "algorithmic_flops_per_launch": exec_factor * per_launch,
+        "useful_complex_tflops": round(per_launch / (avg_ms * 1e-3) / 1e12, 1),
+        "flop_definition": ("3 BF16 MFMA products per complex multiply-add of the split algorithm, "
+                            "8 real flops each; useful = 8 M N K complex" if split else "8 M N K"),
+    }
+    phases = {k: round(v["ms"] / args.steps, 2) for k, v in phase_tot.items()}
+
+    # FP32 plain path
+    if args.fp32_full:
+        p32 = eels.Plan(p, precision="fp32")
+        del ws
+        ws32 = p32.alloc_workspace()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        p32.execute(V, H, out, ws32)
+        torch.cuda.synchronize()
+        dt32 = time.perf_counter() - t1
+        fp32 = {"value": p.n_probes / dt32, "ms_per_step": 1e3 * dt32, "measured_on": "the whole map"}
+        del ws32
+    else:
+        keep = np.isin(p.site_slice, ion[-args.fp32_slices:])
+        ps = subset_sites(p, np.nonzero(keep)[0])
+        p32 = eels.Plan(ps, precision="fp32")
+        i32 = p32.info()
+        del ws
+        ws32 = p32.alloc_workspace()
+        p32.execute(V, H, out, ws32)        # warm the FP32 kernels
+        torch.cuda.synchronize()
+        eels.timing_enable(8192)
+        p32.execute(V, H, out, ws32)
+        torch.cuda.synchronize()
+        ph32 = eels.timing_read()
+        eels.timing_enable(0)
+        contract_ms = sum(ph32[k]["ms"] for k in ("producer", "gemm1", "gemm2", "reduce"))
+        scale = info["gemm_flops"] / i32["gemm_flops"]
+        est_ms = phases["setup"] + phases["sweep"] + contract_ms * scale
+        g1_32 = ph32["gemm1"]
+        fp32 = {
+            "value": p.n_probes / (est_ms * 1e-3), "ms_per_step": round(est_ms, 1),
+            "measured_on": (f"contractions of the top {args.fp32_slices} of {len(ion)} ionised slices "
+                            f"({int(keep.sum())} sites, {contract_ms:.0f} ms) scaled by GEMM work x{scale:.2f}; "
+                            "set-up and sweeps from the full BF16-split step"),
+            "gemm1_tflops": round(gemm1_flops(i32, ps) / (g1_32["ms"] * 1e-3) / 1e12, 1),
+            "gemm1_frac_of_fp32_peak": round(gemm1_flops(i32, ps) / (g1_32["ms"] * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
+        }
+        del ws32
+
+    result = {
+        "metric": METRIC, "value": round(value, 3), "unit": "probe-px/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 1), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16" if args.precision == "bf16_split" else args.precision,
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "grid": [p.nx, p.ny], "n_slices": p.n_slices, "n_sites": p.n_sites,
+                   "n_transitions": p.n_trans, "n_probes": p.n_probes, "N1": info["n_beams_in"],
+                   "N2": info["n_beams_out"], "band_pixels": info["band_pixels"],
+                   "precision": args.precision + " (hi+lo products, FP32 accumulate, FP64 map)"
+                   if args.precision != "fp32" else "fp32", "contraction": "band basis, order S"},
+        "roofline": roofline,
+        "phases_ms": phases,
+        "fp32": fp32,
+        "split_over_fp32": round(value / fp32["value"], 2),
+    }
+    if args.check:
+        path = os.path.join(ROOT, "tests", "golden", "config2_samples.json")
+        if os.path.exists(path):
+            g = json.load(open(path))
+            ref = np.array(g["map"])
+            got = gpu_map[g["probe_index"]]
+            result["check"] = {"max_abs_err_over_max": float(np.max(np.abs(got - ref)) / np.max(ref)),
+                               "probes": g["probe_index"]}
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle sample ...")
+        result["cpu_baseline"] = cpu_baseline(p)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -180,6 +180,23 @@ eels_status eels_debug_cgemm(int precision, int m, int n, int k, const void* d_A
 eels_status eels_tune_set(int key, int value);
 int eels_tune_get(int key);
 
+/* Phase timing (diagnostics).  While enabled, eels_execute records HIP events on its
+ * stream around each group of launches (at most `capacity` groups per call; further
+ * groups are not timed).  After the stream has finished, eels_timing_read returns, for
+ * the most recent eels_execute, the summed milliseconds and number of timed groups per
+ * phase.  capacity 0 disables timing and releases the events.  Not thread-safe. */
+enum {
+    EELS_PHASE_SETUP = 0,     /* twiddles, T, P, probe coefficients                        */
+    EELS_PHASE_SWEEP = 1,     /* row and column passes of both sweeps (with captures)      */
+    EELS_PHASE_PRODUCER = 2,  /* band FFT / H-multiply producers                           */
+    EELS_PHASE_GEMM1 = 3,     /* first contraction GEMM of each batch                      */
+    EELS_PHASE_GEMM2 = 4,     /* second GEMM (detector |.|^2 epilogue)                     */
+    EELS_PHASE_REDUCE = 5,    /* FP64 per-probe reduction                                  */
+    EELS_PHASES = 6
+};
+eels_status eels_timing_enable(int capacity);
+eels_status eels_timing_read(double* ms, int* counts);
+
 #ifdef __cplusplus
 }
 #endif

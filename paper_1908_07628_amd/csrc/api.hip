@@ -17,6 +17,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "eels.h"
 #include "internal.h"
@@ -33,6 +34,29 @@ void set_error(const std::string& m) { g_err = m; }
 
 static std::atomic<int> g_tune[TUNE_COUNT] = {{3}, {0}, {0}, {0}, {0}, {0}, {0}, {0}};
 int tune_get(int key) { return (key >= 0 && key < TUNE_COUNT) ? g_tune[key].load() : 0; }
+
+// Diagnostic phase timing (eels_timing_enable / eels_timing_read).
+struct Timing {
+    std::vector<hipEvent_t> ev;   // 2 per group
+    std::vector<int> phase;
+    int used = 0;
+    int cap = 0;
+} g_timing;
+
+struct TimeScope {
+    int idx = -1;
+    hipStream_t st;
+    TimeScope(int ph, hipStream_t s) : st(s) {
+        if (g_timing.cap > 0 && g_timing.used < g_timing.cap) {
+            idx = g_timing.used++;
+            g_timing.phase[idx] = ph;
+            hipEventRecord(g_timing.ev[2 * idx], st);
+        }
+    }
+    ~TimeScope() {
+        if (idx >= 0) hipEventRecord(g_timing.ev[2 * idx + 1], st);
+    }
+};
 
 #define HIPCHK(x)                                                                       \
     do {                                                                                \
@@ -98,6 +122,7 @@ eels_status check_ws(const Plan& p, void* ws, size_t bytes) {
 }
 
 eels_status setup(const Plan& p, const Dev& d, const float* dV, hipStream_t st) {
+    TimeScope ts(EELS_PHASE_SETUP, st);
     HIPCHK(hipMemcpyAsync(d.ws + p.off_blob, p.blob.data(), p.blob.size() * 4, hipMemcpyHostToDevice, st));
     launch_twiddles(d.twx, p.nx, st);
     launch_twiddles(d.twy, p.ny, st);
@@ -114,6 +139,7 @@ const float2* Pj(const Plan& p, const Dev& d, int j) { return d.P + (int64_t)j *
 // full real-space S_1(dbg_slice) into dbg_out.
 void forward_sweep(const Plan& p, const Dev& d, int j_end, int group, int dbg_slice, float2* dbg_out,
                    hipStream_t st) {
+    TimeScope ts(EELS_PHASE_SWEEP, st);
     launch_init_forward(d.s1, d.b1, p, st);
     for (int j = 0; j <= j_end; ++j) {
         RowPassArgs a{d.s1, p.N1, p.ny, p.nlx, p.hlx, Tj(p, d, j), d.twx, nullptr, nullptr, d.w1, p.N1, p.Kpad, 0};
@@ -136,6 +162,7 @@ void forward_sweep(const Plan& p, const Dev& d, int j_end, int group, int dbg_sl
 // in the row pass) or the band coefficients of P_j x_{j+1} (band basis, in the column
 // pass or at the start); dbg_out receives the full real-space S_2(j) instead.
 void reverse_step(const Plan& p, const Dev& d, int j, bool capture, float2* dbg_out, hipStream_t st) {
+    TimeScope ts(EELS_PHASE_SWEEP, st);
     const bool band = capture && p.recip && !dbg_out;
     if (j == p.nz - 1) {
         launch_init_reverse(d.s2, d.b2, p, st);
@@ -161,6 +188,7 @@ void reverse_step(const Plan& p, const Dev& d, int j, bool capture, float2* dbg_
 
 // Producer jobs of a batch: the H-multiplied second operand of every site into mid2.
 void run_jobs(const Plan& p, const Dev& d, const float2* dH, const Batch& b, int j, hipStream_t st) {
+    TimeScope ts(EELS_PHASE_PRODUCER, st);
     for (int k = 0; k < b.job_count; ++k) {
         const Job& jb = p.jobs[b.job_begin + k];
         const float2* W = (jb.from_mid ? d.mid : d.w1) + jb.w_off;
@@ -191,33 +219,45 @@ void contract(const Plan& p, const Dev& d, const float2* dH, double* map, int bi
     const GemmDesc* dd = d.descs;
     const bool split = p.precision != EELS_FP32;
     const int nst = tune_get(TUNE_SC_STAGES);
+    const bool h_pro = !p.recip;   // FP32 real-space: H applied in the GEMM prologue
     if (b.order == EELS_ORDER_S_FIRST) {
-        run_jobs(p, d, dH, b, b.slice, st);
-        if (split) {
-            launch_cgemm_sc(p.precision, 0, nst, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.w2, d.mid2, d.mid, nullptr,
-                            d.blob, st);
-            launch_cgemm_sc(p.precision, 1, nst, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.mid, d.C, nullptr, d.part,
-                            d.blob, st);
-        } else {
-            const bool h_pro = !p.recip;
-            launch_cgemm(EELS_FP32, 0, 0, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.w2, h_pro ? d.w1 : d.mid2,
-                         h_pro ? dH : nullptr, d.mid, nullptr, d.blob, st);
-            launch_cgemm(EELS_FP32, 0, 1, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.mid, d.C, nullptr, nullptr, d.part,
-                         d.blob, st);
+        if (split || p.recip) run_jobs(p, d, dH, b, b.slice, st);
+        {
+            TimeScope ts(EELS_PHASE_GEMM1, st);
+            if (split)
+                launch_cgemm_sc(p.precision, 0, nst, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.w2, d.mid2, d.mid,
+                                nullptr, d.blob, st);
+            else
+                launch_cgemm(EELS_FP32, 0, 0, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.w2, h_pro ? d.w1 : d.mid2,
+                             h_pro ? dH : nullptr, d.mid, nullptr, d.blob, st);
+        }
+        {
+            TimeScope ts(EELS_PHASE_GEMM2, st);
+            if (split)
+                launch_cgemm_sc(p.precision, 1, nst, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.mid, d.C, nullptr,
+                                d.part, d.blob, st);
+            else
+                launch_cgemm(EELS_FP32, 0, 1, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.mid, d.C, nullptr, nullptr,
+                             d.part, d.blob, st);
         }
     } else {
-        launch_cgemm(EELS_FP32, 1, 0, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.C, d.w1, nullptr, d.mid, nullptr,
-                     d.blob, st);
-        run_jobs(p, d, dH, b, b.slice, st);
-        if (split) {
-            launch_cgemm_sc(p.precision, 1, nst, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.w2, d.mid2, nullptr, d.part,
-                            d.blob, st);
-        } else {
-            const bool h_pro = !p.recip;
-            launch_cgemm(EELS_FP32, 0, 1, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.w2, h_pro ? d.mid : d.mid2,
-                         h_pro ? dH : nullptr, nullptr, d.part, d.blob, st);
+        {
+            TimeScope ts(EELS_PHASE_GEMM1, st);
+            launch_cgemm(EELS_FP32, 1, 0, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.C, d.w1, nullptr, d.mid, nullptr,
+                         d.blob, st);
+        }
+        if (split || p.recip) run_jobs(p, d, dH, b, b.slice, st);
+        {
+            TimeScope ts(EELS_PHASE_GEMM2, st);
+            if (split)
+                launch_cgemm_sc(p.precision, 1, nst, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.w2, d.mid2, nullptr,
+                                d.part, d.blob, st);
+            else
+                launch_cgemm(EELS_FP32, 0, 1, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.w2, h_pro ? d.mid : d.mid2,
+                             h_pro ? dH : nullptr, nullptr, d.part, d.blob, st);
         }
     }
+    TimeScope ts(EELS_PHASE_REDUCE, st);
     double nn = (double)p.nx * (double)p.ny;
     double scale = (double)p.f * p.f / (nn * nn) / ((double)p.c_scale * p.c_scale);
     if (b.red_ptr < 0) launch_reduce_dense(map, p.P, dd, b.d2_begin, b.d2_count, d.part, scale, st);
@@ -340,6 +380,7 @@ eels_status eels_execute(const eels_plan* pl, const float* d_V, const void* d_H,
     if (s) return s;
     hipStream_t st = (hipStream_t)stream;
     Dev d = make_dev(p, d_workspace);
+    g_timing.used = 0;
     if ((s = setup(p, d, d_V, st))) return s;
     launch_probe_coefficients(d.C, d.b1, d.probes, p, p.c_sc, st);
     launch_fill_zero_d(d_map, p.P, st);
@@ -468,5 +509,33 @@ eels_status eels_tune_set(int key, int value) {
 }
 
 int eels_tune_get(int key) { return tune_get(key); }
+
+eels_status eels_timing_enable(int capacity) {
+    if (capacity < 0) return EELS_ERR_INVALID_ARG;
+    for (auto e : g_timing.ev) hipEventDestroy(e);
+    g_timing.ev.clear();
+    g_timing.phase.clear();
+    g_timing.used = 0;
+    g_timing.cap = 0;
+    if (capacity == 0) return EELS_OK;
+    g_timing.ev.resize(2 * (size_t)capacity);
+    g_timing.phase.assign(capacity, 0);
+    for (auto& e : g_timing.ev) HIPCHK(hipEventCreate(&e));
+    g_timing.cap = capacity;
+    return EELS_OK;
+}
+
+eels_status eels_timing_read(double* ms, int* counts) {
+    if (!ms || !counts) return EELS_ERR_INVALID_ARG;
+    for (int k = 0; k < EELS_PHASES; ++k) { ms[k] = 0; counts[k] = 0; }
+    for (int i = 0; i < g_timing.used; ++i) {
+        float t = 0.f;
+        HIPCHK(hipEventSynchronize(g_timing.ev[2 * i + 1]));
+        HIPCHK(hipEventElapsedTime(&t, g_timing.ev[2 * i], g_timing.ev[2 * i + 1]));
+        ms[g_timing.phase[i]] += t;
+        counts[g_timing.phase[i]] += 1;
+    }
+    return EELS_OK;
+}
 
 }  // extern "C"

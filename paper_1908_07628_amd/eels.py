@@ -60,7 +60,8 @@ _LIB: Optional[C.CDLL] = None
 EXPORTS = ["eels_get_version", "eels_status_string", "eels_last_error", "eels_plan_create",
            "eels_plan_workspace_bytes", "eels_plan_info_get", "eels_plan_beams", "eels_plan_destroy",
            "eels_execute", "eels_debug_s1", "eels_debug_s2", "eels_gemm_work_bytes", "eels_debug_cgemm",
-           "eels_tune_set", "eels_tune_get"]
+           "eels_tune_set", "eels_tune_get", "eels_timing_enable", "eels_timing_read"]
+PHASES = ["setup", "sweep", "producer", "gemm1", "gemm2", "reduce"]
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:
@@ -88,6 +89,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                                      vp, vp, vp]
     lib.eels_tune_set.argtypes = [C.c_int, C.c_int]
     lib.eels_tune_get.argtypes = [C.c_int]
+    lib.eels_timing_enable.argtypes = [C.c_int]
+    lib.eels_timing_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int)]
     _LIB = lib
     return lib
 
@@ -232,6 +235,19 @@ def tune_set(key: int, value: int):
 
 def tune_get(key: int) -> int:
     return int(load_library().eels_tune_get(int(key)))
+
+
+def timing_enable(capacity: int = 4096):
+    """Record HIP events around the launch groups of every eels_execute (diagnostics)."""
+    _check(load_library().eels_timing_enable(int(capacity)))
+
+
+def timing_read() -> Dict[str, Any]:
+    """Per-phase milliseconds and group counts of the most recent execute (synchronises)."""
+    ms = (C.c_double * len(PHASES))()
+    cnt = (C.c_int * len(PHASES))()
+    _check(load_library().eels_timing_read(ms, cnt))
+    return {ph: {"ms": ms[i], "count": cnt[i]} for i, ph in enumerate(PHASES)}
 
 
 def cgemm(A, B, precision: str = "fp32", norm2: bool = False, stream=None):
