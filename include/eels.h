@@ -102,6 +102,9 @@ typedef struct {
     size_t max_workspace_bytes;
     int real_space;          /* 1: contract full-cell windows pixel by pixel instead of in the
                                 band basis (same result, about 3x more GEMM work)            */
+    int resident_s;          /* 1: keep the S_2 capture of every ionised slice in the workspace
+                                (needs one slice group), so that a later eels_execute_ex with
+                                EELS_EXEC_SKIP_SWEEPS can reuse the S-matrices              */
 } eels_problem;
 
 /* Derived sizes of a plan (filled by eels_plan_info). */
@@ -154,6 +157,26 @@ eels_status eels_plan_destroy(eels_plan* p);
 eels_status eels_execute(const eels_plan* p, const float* d_V, const void* d_H, double* d_map,
                          void* d_workspace, size_t workspace_bytes, void* stream);
 
+/* eels_execute with options.  flags:
+ *   EELS_EXEC_SKIP_UPLOAD  the plan's tables are already in this workspace (uploaded by an
+ *                          earlier execute of the same plan on it): enqueue kernels only, so
+ *                          the call can be captured into a HIP graph.
+ *   EELS_EXEC_SKIP_SWEEPS  reuse the S-matrix data (S_1 windows and every slice's S_2
+ *                          capture) left in the workspace by an earlier execute of a plan
+ *                          with the same S signature (eels_plan_s_signature) on the same V
+ *                          and H; needs resident_s.  Only the set-up and the contractions run,
+ *                          e.g. for a new set of probe positions.
+ * Errors as eels_execute; INVALID_ARG for SKIP_SWEEPS without resident_s. */
+enum { EELS_EXEC_SKIP_UPLOAD = 1, EELS_EXEC_SKIP_SWEEPS = 2 };
+eels_status eels_execute_ex(const eels_plan* p, const float* d_V, const void* d_H, double* d_map,
+                            void* d_workspace, size_t workspace_bytes, void* stream, unsigned flags);
+
+/* 64-bit signature of everything the S-matrix data in a workspace depends on (geometry,
+ * slices, optics, beam lattices, windows, sites, storage format and the workspace
+ * offsets of the S data), but not of the probes.  Equal signatures (with equal V and H)
+ * mean the S data of one plan's execute serve the other. */
+eels_status eels_plan_s_signature(const eels_plan* p, uint64_t* sig);
+
 /* Diagnostics (same workspace contract).  Write the real-space rows of S_1(j)
  * (scaled by nx*ny, i.e. unit-modulus plane waves at j = 0) as complex64
  * [N_1][ny][nx], or of S_2(j) as complex64 [N_2][ny][nx]. */
@@ -175,7 +198,10 @@ eels_status eels_debug_cgemm(int precision, int m, int n, int k, const void* d_A
                              void* d_work, void* stream);
 
 /* Process-wide kernel tuning knobs, read at launch time (the autotuner sets them).
- * key 0: LDS pipeline depth of the split-precision GEMM (2 or 3; default 3).
+ * key 0: LDS pipeline depth of the split-precision GEMM: 2 (two workgroups per CU,
+ *        default) or 3 (one workgroup per CU, deeper prefetch).
+ * key 1: tile order of the contraction GEMMs within a problem: 0 m-fastest (default; the
+ *        workgroups in flight share B tiles), 1 n-fastest (they share A tiles).
  * Returns EELS_ERR_INVALID_ARG for an unknown key or an out-of-range value. */
 eels_status eels_tune_set(int key, int value);
 int eels_tune_get(int key);

@@ -1,0 +1,100 @@
+"""Batched maps of many specimens of uneven size in one captured HIP graph.
+
+Every specimen gets its own plan, workspace (one arena, 256-byte aligned slices) and
+output slice.  The first `run_eager` uploads each plan's tables into its workspace;
+`capture` then records all specimens' launches (EELS_EXEC_SKIP_UPLOAD: kernels only)
+into one graph, independent specimens on parallel stream branches so that their
+kernels overlap on the device, with each specimen's tuned knobs set before its
+launches are recorded.  `replay` launches the whole batch with one graph launch.
+"""
+from __future__ import annotations
+
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import autotune, eels
+
+
+def _align(n: int, a: int = 256) -> int:
+    return (n + a - 1) // a * a
+
+
+class Batch:
+    def __init__(self, problems: Sequence, precision: str = "fp32", n_streams: int = 4, device: str = "cuda",
+                 tuned: bool = True):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.problems = list(problems)
+        self.plans = [eels.Plan(p, precision=precision) for p in self.problems]
+        self.tuned = tuned
+        self.inputs = [eels.device_inputs(p, device) for p in self.problems]
+        sizes = [_align(pl.workspace_bytes) for pl in self.plans]
+        self.ws_offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        self.arena = torch.empty(int(self.ws_offsets[-1]), dtype=torch.uint8, device=device)
+        if self.arena.data_ptr() % 256:
+            raise eels.EelsError(4, "arena not 256-byte aligned")
+        self.workspaces = [self.arena[int(self.ws_offsets[i]):int(self.ws_offsets[i + 1])]
+                           for i in range(len(self.plans))]
+        self.map_offsets = np.concatenate([[0], np.cumsum([pl.n_probes for pl in self.plans])]).astype(np.int64)
+        self.maps = torch.zeros(int(self.map_offsets[-1]), dtype=torch.float64, device=device)
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(max(1, n_streams))]
+        self.graph = None
+        # larger specimens first, dealt round-robin to the streams
+        self.order = sorted(range(len(self.plans)), key=lambda i: -self.plans[i].workspace_bytes)
+
+    def out(self, i: int):
+        return self.maps[int(self.map_offsets[i]):int(self.map_offsets[i + 1])]
+
+    def tune(self, reps: int = 1):
+        """Autotune each distinct shape key once (cached across processes)."""
+        seen = set()
+        for i, pl in enumerate(self.plans):
+            k = autotune.key_of(pl)
+            if k not in seen:
+                seen.add(k)
+                autotune.tune(pl, *self.inputs[i], reps=reps)
+        self.tuned = True
+
+    def _enqueue(self, flags: int):
+        torch = self.torch
+        main = torch.cuda.current_stream(self.device)
+        for s in self.streams:
+            s.wait_stream(main)
+        for n, i in enumerate(self.order):
+            s = self.streams[n % len(self.streams)]
+            if self.tuned:
+                autotune.apply(self.plans[i])
+            with torch.cuda.stream(s):
+                V, H = self.inputs[i]
+                self.plans[i].execute(V, H, self.out(i), self.workspaces[i], stream=s, flags=flags)
+        for s in self.streams:
+            main.wait_stream(s)
+        autotune.set_knobs(autotune.DEFAULTS)
+
+    def run_eager(self):
+        """Enqueue every specimen (uploading the tables); returns without waiting."""
+        self._enqueue(0)
+
+    def capture(self):
+        """Record all specimens' kernels into one HIP graph (tables must be uploaded)."""
+        torch = self.torch
+        self.run_eager()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        cap = torch.cuda.Stream(device=self.device)
+        with torch.cuda.graph(g, stream=cap):
+            self._enqueue(eels.EXEC_SKIP_UPLOAD)
+        self.graph = g
+        return g
+
+    def replay(self):
+        if self.graph is None:
+            raise RuntimeError("capture() first")
+        self.graph.replay()
+
+    def maps_host(self) -> List[np.ndarray]:
+        self.torch.cuda.synchronize()
+        m = self.maps.cpu().numpy()
+        return [m[int(self.map_offsets[i]):int(self.map_offsets[i + 1])].copy() for i in range(len(self.plans))]

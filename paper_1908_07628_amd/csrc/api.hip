@@ -32,7 +32,7 @@ namespace eels {
 static thread_local std::string g_err;
 void set_error(const std::string& m) { g_err = m; }
 
-static std::atomic<int> g_tune[TUNE_COUNT] = {{3}, {0}, {0}, {0}, {0}, {0}, {0}, {0}};
+static std::atomic<int> g_tune[TUNE_COUNT] = {{2}, {0}, {0}, {0}, {0}, {0}, {0}, {0}};
 int tune_get(int key) { return (key >= 0 && key < TUNE_COUNT) ? g_tune[key].load() : 0; }
 
 // Diagnostic phase timing (eels_timing_enable / eels_timing_read).
@@ -121,9 +121,10 @@ eels_status check_ws(const Plan& p, void* ws, size_t bytes) {
     return EELS_OK;
 }
 
-eels_status setup(const Plan& p, const Dev& d, const float* dV, hipStream_t st) {
+eels_status setup(const Plan& p, const Dev& d, const float* dV, hipStream_t st, bool upload = true) {
     TimeScope ts(EELS_PHASE_SETUP, st);
-    HIPCHK(hipMemcpyAsync(d.ws + p.off_blob, p.blob.data(), p.blob.size() * 4, hipMemcpyHostToDevice, st));
+    if (upload)
+        HIPCHK(hipMemcpyAsync(d.ws + p.off_blob, p.blob.data(), p.blob.size() * 4, hipMemcpyHostToDevice, st));
     launch_twiddles(d.twx, p.nx, st);
     launch_twiddles(d.twy, p.ny, st);
     launch_transmission(d.T, dV, (int64_t)p.nz * p.ny * p.nx, p.sigma, st);
@@ -164,15 +165,16 @@ void forward_sweep(const Plan& p, const Dev& d, int j_end, int group, int dbg_sl
 void reverse_step(const Plan& p, const Dev& d, int j, bool capture, float2* dbg_out, hipStream_t st) {
     TimeScope ts(EELS_PHASE_SWEEP, st);
     const bool band = capture && p.recip && !dbg_out;
+    float2* w2j = d.w2 + p.slice_w2[j];   // this slice's S_2 capture (resident plans keep one per slice)
     if (j == p.nz - 1) {
         launch_init_reverse(d.s2, d.b2, p, st);
-        if (band) launch_init_band(d.w2, p.Kbpad, d.b2, d.band_h, d.band_off, p, p.w2_sc, st);
+        if (band) launch_init_band(w2j, p.Kbpad, d.b2, d.band_h, d.band_off, p, p.w2_sc, st);
     } else {
         BandCap bc{};
-        if (band) bc = BandCap{d.band_h, d.band_off, d.w2, p.Kbpad, p.w2_sc};
+        if (band) bc = BandCap{d.band_h, d.band_off, w2j, p.Kbpad, p.w2_sc};
         launch_col_pass(p.ny, 1, d.s2, p.N2, p.nlx, Pj(p, d, j), d.twy, bc, st);
     }
-    RowPassArgs a{d.s2, p.N2, p.ny, p.nlx, p.hlx, Tj(p, d, j), d.twx, nullptr, nullptr, d.w2, p.N2, p.Kpad, p.w2_sc};
+    RowPassArgs a{d.s2, p.N2, p.ny, p.nlx, p.hlx, Tj(p, d, j), d.twx, nullptr, nullptr, w2j, p.N2, p.Kpad, p.w2_sc};
     if (dbg_out) {
         a.cap_ptr = d.blob + p.dbg_ptr;
         a.cap_rec = d.blob + p.dbg_rec;
@@ -367,6 +369,11 @@ eels_status eels_plan_destroy(eels_plan* p) {
 
 eels_status eels_execute(const eels_plan* pl, const float* d_V, const void* d_H, double* d_map, void* d_workspace,
                          size_t workspace_bytes, void* stream) {
+    return eels_execute_ex(pl, d_V, d_H, d_map, d_workspace, workspace_bytes, stream, 0u);
+}
+
+eels_status eels_execute_ex(const eels_plan* pl, const float* d_V, const void* d_H, double* d_map, void* d_workspace,
+                            size_t workspace_bytes, void* stream, unsigned flags) {
     if (!pl || !d_V || !d_map) {
         set_error("null argument");
         return EELS_ERR_INVALID_ARG;
@@ -376,16 +383,33 @@ eels_status eels_execute(const eels_plan* pl, const float* d_V, const void* d_H,
         set_error("transition potentials missing");
         return EELS_ERR_INVALID_ARG;
     }
+    if (flags & ~(unsigned)(EELS_EXEC_SKIP_UPLOAD | EELS_EXEC_SKIP_SWEEPS)) {
+        set_error("unknown execute flag");
+        return EELS_ERR_INVALID_ARG;
+    }
+    const bool skip_sweeps = (flags & EELS_EXEC_SKIP_SWEEPS) != 0;
+    if (skip_sweeps && !p.resident) {
+        set_error("EELS_EXEC_SKIP_SWEEPS needs a plan with resident_s");
+        return EELS_ERR_INVALID_ARG;
+    }
     eels_status s = check_ws(p, d_workspace, workspace_bytes);
     if (s) return s;
     hipStream_t st = (hipStream_t)stream;
     Dev d = make_dev(p, d_workspace);
     g_timing.used = 0;
-    if ((s = setup(p, d, d_V, st))) return s;
+    if ((s = setup(p, d, d_V, st, !(flags & EELS_EXEC_SKIP_UPLOAD)))) return s;
     launch_probe_coefficients(d.C, d.b1, d.probes, p, p.c_sc, st);
     launch_fill_zero_d(d_map, p.P, st);
+    if (skip_sweeps) {
+        // the S_1 windows and every slice's S_2 capture are already in the workspace
+        for (int j = p.nz - 1; j >= 0; --j)
+            if (p.slices[j].ion)
+                for (int bi : p.slices[j].batches) contract(p, d, (const float2*)d_H, d_map, bi, st);
+        HIPCHK(hipGetLastError());
+        return EELS_OK;
+    }
     // split operands are read in whole 16-element K tiles: the S_2 capture's padding must be zero
-    if (p.precision != EELS_FP32) launch_fill_zero(d.w2, p.off_mid - p.off_w2, st);
+    if (p.precision != EELS_FP32) launch_fill_zero(d.w2, p.off_C - p.off_w2, st);
     int rev_next = p.nz - 1;
     for (int gi = 0; gi < (int)p.groups.size(); ++gi) {
         const Group& g = p.groups[gi];
@@ -398,6 +422,12 @@ eels_status eels_execute(const eels_plan* pl, const float* d_V, const void* d_H,
         rev_next = g.j_lo - 1;
     }
     HIPCHK(hipGetLastError());
+    return EELS_OK;
+}
+
+eels_status eels_plan_s_signature(const eels_plan* pl, uint64_t* sig) {
+    if (!pl || !sig) return EELS_ERR_INVALID_ARG;
+    *sig = s_signature(pl->p);
     return EELS_OK;
 }
 
@@ -504,6 +534,7 @@ eels_status eels_debug_cgemm(int precision, int m, int n, int k, const void* d_A
 eels_status eels_tune_set(int key, int value) {
     if (key < 0 || key >= TUNE_COUNT) return EELS_ERR_INVALID_ARG;
     if (key == TUNE_SC_STAGES && (value < 2 || value > 3)) return EELS_ERR_INVALID_ARG;
+    if (key == TUNE_TILE_ORDER && (value < 0 || value > 1)) return EELS_ERR_INVALID_ARG;
     g_tune[key].store(value);
     return EELS_OK;
 }

@@ -38,7 +38,7 @@ struct GemmDesc {
 static_assert(sizeof(GemmDesc) == 144, "GemmDesc layout");
 
 // Process-wide tuning knobs (set by eels_tune_set; read at launch time).
-enum TuneKey { TUNE_SC_STAGES = 0, TUNE_COUNT = 8 };
+enum TuneKey { TUNE_SC_STAGES = 0, TUNE_TILE_ORDER = 1, TUNE_COUNT = 8 };
 int tune_get(int key);
 
 struct Batch {
@@ -98,6 +98,8 @@ struct Plan {
     std::vector<int> ab1, ab2;    // lattice coordinates (a, b) of beams
     int N1, N2, N1fine, N1pad;
     bool full_window;
+    bool resident;                // every ionised slice keeps its own S_2 capture
+    std::vector<int64_t> slice_w2;  // complex offset of slice j's S_2 capture in the w2 buffer
     bool recip;                   // band-basis contraction (full-cell windows)
     int hwx, hwy, nwx, nwy, K, Kpad;
     std::vector<int> band_h, band_off;          // band rows per live column, band slot offsets
@@ -131,6 +133,7 @@ struct Plan {
 };
 
 eels_status build_plan(Plan& p, const eels_problem& prob);
+uint64_t s_signature(const Plan& p);
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }

@@ -80,7 +80,7 @@ template <int PREC, int KIND, int EPI>
 __global__ __launch_bounds__(256) void k_cgemm(const GemmDesc* __restrict__ descs, int n_desc,
                                                const float2* __restrict__ Ab, const float2* __restrict__ Bb,
                                                const float2* __restrict__ Hb, float2* __restrict__ Cb,
-                                               float* __restrict__ Pb, const int* __restrict__ ib) {
+                                               float* __restrict__ Pb, const int* __restrict__ ib, int n_fast) {
     constexpr bool SPLIT = PREC != EELS_FP32;
     static_assert(!(SPLIT && KIND == 1), "the [k][n] B layout is single precision only");
     constexpr int LDS_BYTES = SPLIT ? 4 * BM * LDS_ * 4 : 2 * BM * LDF * 8;
@@ -96,9 +96,21 @@ __global__ __launch_bounds__(256) void k_cgemm(const GemmDesc* __restrict__ desc
     }
     const GemmDesc& d = descs[lo];
     const int local = bid - d.tile_start;
-    const int tm = local % d.tiles_m;
-    const int rest = local / d.tiles_m;
-    const int tn = rest % d.tiles_n, t = rest / d.tiles_n;
+    // tile order within a descriptor: m fastest (blocks in flight share B tiles) or n
+    // fastest (they share A tiles); chosen by the tuner
+    int tm, tn, t;
+    if (n_fast) {
+        const int per_t = d.tiles_m * d.tiles_n;
+        t = local / per_t;
+        const int r = local - t * per_t;
+        tn = r % d.tiles_n;
+        tm = r / d.tiles_n;
+    } else {
+        tm = local % d.tiles_m;
+        const int rest = local / d.tiles_m;
+        tn = rest % d.tiles_n;
+        t = rest / d.tiles_n;
+    }
     const int M = d.M, K = d.K, N = d.N_inner;
     const int m0 = tm * BM, n0 = tn * BN;
     const float2* A = Ab + d.a_off + (int64_t)t * d.a_tstride;
@@ -359,10 +371,10 @@ __device__ __forceinline__ void wait_vmcnt() {
 }
 
 template <int PREC, int EPI, int NSTAGE>
-__global__ __launch_bounds__(256) void k_cgemm_sc(const GemmDesc* __restrict__ descs, int n_desc,
+__global__ __launch_bounds__(256, NSTAGE == 2 ? 2 : 1) void k_cgemm_sc(const GemmDesc* __restrict__ descs, int n_desc,
                                                   const uint32_t* __restrict__ Ab, const uint32_t* __restrict__ Bb,
                                                   uint32_t* __restrict__ Cb, float* __restrict__ Pb,
-                                                  const int* __restrict__ ib) {
+                                                  const int* __restrict__ ib, int n_fast) {
     constexpr int STAGE = 2 * 128 * 128;  // bytes: A and B tiles of 128 rows x 128 bytes
     __shared__ __attribute__((aligned(1024))) char smem[NSTAGE * STAGE];
 
@@ -375,9 +387,21 @@ __global__ __launch_bounds__(256) void k_cgemm_sc(const GemmDesc* __restrict__ d
     }
     const GemmDesc& d = descs[lo];
     const int local = bid - d.tile_start;
-    const int tm = local % d.tiles_m;
-    const int rest = local / d.tiles_m;
-    const int tn = rest % d.tiles_n, t = rest / d.tiles_n;
+    // tile order within a descriptor: m fastest (blocks in flight share B tiles) or n
+    // fastest (they share A tiles); chosen by the tuner
+    int tm, tn, t;
+    if (n_fast) {
+        const int per_t = d.tiles_m * d.tiles_n;
+        t = local / per_t;
+        const int r = local - t * per_t;
+        tn = r % d.tiles_n;
+        tm = r / d.tiles_n;
+    } else {
+        tm = local % d.tiles_m;
+        const int rest = local / d.tiles_m;
+        tn = rest % d.tiles_n;
+        t = rest / d.tiles_n;
+    }
     const int M = d.M, N = d.N_inner;
     const int m0 = tm * BM, n0 = tn * BN;
     const int nk = (d.K + BK - 1) / BK;
@@ -534,7 +558,8 @@ __global__ void k_to_sc(uint32_t* __restrict__ dst, const float2* __restrict__ s
 template <int PREC, int KIND, int EPI>
 static void go(const GemmDesc* dd, int nd, int tiles, const float2* A, const float2* B, const float2* H, float2* C,
                float* P, const int* idx, hipStream_t st) {
-    hipLaunchKernelGGL((k_cgemm<PREC, KIND, EPI>), dim3(tiles), dim3(256), 0, st, dd, nd, A, B, H, C, P, idx);
+    hipLaunchKernelGGL((k_cgemm<PREC, KIND, EPI>), dim3(tiles), dim3(256), 0, st, dd, nd, A, B, H, C, P, idx,
+                       tune_get(TUNE_TILE_ORDER));
 }
 
 void launch_cgemm(int precision, int kind, int epi, const GemmDesc* dd, int nd, int tiles, const float2* A,
@@ -566,9 +591,11 @@ template <int PREC, int EPI>
 static void go_sc(int nstage, const GemmDesc* dd, int nd, int tiles, const uint32_t* A, const uint32_t* B, uint32_t* C,
                   float* P, const int* idx, hipStream_t st) {
     if (nstage >= 3)
-        hipLaunchKernelGGL((k_cgemm_sc<PREC, EPI, 3>), dim3(tiles), dim3(256), 0, st, dd, nd, A, B, C, P, idx);
+        hipLaunchKernelGGL((k_cgemm_sc<PREC, EPI, 3>), dim3(tiles), dim3(256), 0, st, dd, nd, A, B, C, P, idx,
+                           tune_get(TUNE_TILE_ORDER));
     else
-        hipLaunchKernelGGL((k_cgemm_sc<PREC, EPI, 2>), dim3(tiles), dim3(256), 0, st, dd, nd, A, B, C, P, idx);
+        hipLaunchKernelGGL((k_cgemm_sc<PREC, EPI, 2>), dim3(tiles), dim3(256), 0, st, dd, nd, A, B, C, P, idx,
+                           tune_get(TUNE_TILE_ORDER));
 }
 
 void launch_cgemm_sc(int precision, int epi, int nstage, const GemmDesc* dd, int nd, int tiles, const void* A,

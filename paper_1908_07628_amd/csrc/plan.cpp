@@ -225,7 +225,15 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     int max_w2 = 0;
     for (int j : ion) max_w2 = std::max(max_w2, slice_windows(j));
     p.max_w2 = max_w2;
-    const int64_t w2_elems = p.recip ? (int64_t)p.N2 * p.Kbpad : (int64_t)max_w2 * p.N2 * p.Kpad;
+    const int64_t w2_slice = p.recip ? (int64_t)p.N2 * p.Kbpad : (int64_t)max_w2 * p.N2 * p.Kpad;
+    p.resident = q.resident_s != 0;
+    p.slice_w2.assign(p.nz, 0);
+    int64_t w2_elems = w2_slice;
+    if (p.resident) {
+        int64_t off = 0;
+        for (int j : ion) { p.slice_w2[j] = off; off += w2_slice; }
+        w2_elems = std::max<int64_t>(off, 1);
+    }
 
     // per-site intermediates: mid (Z or Psi), mid2 (H-multiplied operand, split or band
     // basis), band-FFT scratch, norm partial sums
@@ -335,6 +343,8 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
             gbytes += need;
         }
     }
+    if (p.resident && p.groups.size() > 1)
+        return fail(EELS_ERR_OOM, "resident S-matrices need every S_1 window in one slice group");
     p.max_w1 = 0;
     for (auto& g : p.groups) p.max_w1 = std::max(p.max_w1, g.n_windows);
     for (int j : ion) {
@@ -449,8 +459,8 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
             GemmDesc d{};
             if (orderS) {
                 // Z_s[t][q][k] = sum_r S2w[q][r] H_t[r] S1w[k][r]  (or its band-basis form)
-                if (p.recip) { d.a_off = 0; d.lda = p.Kbpad; }
-                else { d.a_off = (int64_t)p.site_w2[s] * w2_stride; d.lda = p.Kpad; }
+                if (p.recip) { d.a_off = p.slice_w2[pb.slice]; d.lda = p.Kbpad; }
+                else { d.a_off = p.slice_w2[pb.slice] + (int64_t)p.site_w2[s] * w2_stride; d.lda = p.Kpad; }
                 if (h_in_gemm) {
                     d.b_off = (int64_t)p.site_w1[s] * w1_stride; d.ldb = p.Kpad;
                     d.h_off = st.h_offset * p.K; d.ldh = p.K;
@@ -497,8 +507,8 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
                 d.idx_off = (int)site_idx[s];
             } else {
                 // A_n(q, R) = sum_r S2w[q][r] H_t[r] Psi_s[i][r]  (or its band-basis form)
-                if (p.recip) { d.a_off = 0; d.lda = p.Kbpad; }
-                else { d.a_off = (int64_t)p.site_w2[s] * w2_stride; d.lda = p.Kpad; }
+                if (p.recip) { d.a_off = p.slice_w2[pb.slice]; d.lda = p.Kbpad; }
+                else { d.a_off = p.slice_w2[pb.slice] + (int64_t)p.site_w2[s] * w2_stride; d.lda = p.Kpad; }
                 if (h_in_gemm) {
                     d.b_off = site_moff[si]; d.ldb = p.Kpad;
                     d.h_off = st.h_offset * p.K; d.ldh = p.K;
@@ -574,26 +584,50 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     p.sweep_beam_slices = fwd + rev;
     p.sweep_bytes = p.sweep_beam_slices * 32.0 * p.ny * p.nlx;
 
-    // ---- workspace layout
+    // ---- workspace layout: the S-matrix data first (their offsets do not depend on the
+    // probes), then the probe-dependent buffers and the table blob
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += A(bytes); return o; };
-    p.off_blob = take(p.blob.size() * 4);
     p.off_twx = take(c8 * p.nx);
     p.off_twy = take(c8 * p.ny);
     p.off_T = take(c8 * (size_t)p.nz * p.ny * p.nx);
     p.off_P = take(c8 * (size_t)p.nz * p.ny * p.nlx);
-    p.off_C = take(c8 * (size_t)p.P * p.N1pad);
     p.off_s1 = take(c8 * (size_t)p.N1 * p.ny * p.nlx);
     p.off_s2 = take(c8 * (size_t)p.N2 * p.ny * p.nlx);
     p.off_w1 = take(c8 * (size_t)std::max(p.max_w1, 1) * p.N1 * p.Kpad);
     p.off_w2 = take(c8 * (size_t)std::max<int64_t>(w2_elems, 1));
+    p.off_C = take(c8 * (size_t)p.P * p.N1pad);
     p.off_mid = take(c8 * (size_t)std::max<int64_t>(p.mid_elems, 1));
     p.off_mid2 = take(c8 * (size_t)std::max<int64_t>(p.mid2_elems, 1));
     p.off_scratch = take(c8 * (size_t)std::max<int64_t>(p.scratch_elems, 1));
     p.off_part = take(4 * (size_t)std::max<int64_t>(p.part_elems, 1));
+    p.off_blob = take(p.blob.size() * 4);
     p.ws_bytes = off;
     if (budget > 0 && p.ws_bytes > budget) return fail(EELS_ERR_OOM, "workspace exceeds the memory budget");
     return EELS_OK;
+}
+
+static void fnv(uint64_t& h, const void* data, size_t n) {
+    const unsigned char* c = (const unsigned char*)data;
+    for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
+}
+
+uint64_t s_signature(const Plan& p) {
+    uint64_t h = 1469598103934665603ull;
+    auto add = [&](const auto& v) { fnv(h, &v, sizeof(v)); };
+    add(p.nx); add(p.ny); add(p.lx); add(p.ly); add(p.nz);
+    fnv(h, p.dz.data(), p.dz.size() * sizeof(double));
+    add(p.lam); add(p.sigma); add(p.alpha); add(p.beta_in); add(p.beta_out); add(p.f); add(p.kmax);
+    add(p.full_window); add(p.recip); add(p.resident); add(p.hwx); add(p.hwy); add(p.Kpad); add(p.Kbpad);
+    add(p.w2_sc); add(p.N1); add(p.N2);
+    fnv(h, p.ab1.data(), p.ab1.size() * sizeof(int));
+    fnv(h, p.ab2.data(), p.ab2.size() * sizeof(int));
+    for (size_t s = 0; s < p.sites.size(); ++s) {
+        add(p.sites[s].slice); add(p.site_ix0[s]); add(p.site_iy0[s]); add(p.site_w1[s]); add(p.site_w2[s]);
+    }
+    fnv(h, p.slice_w2.data(), p.slice_w2.size() * sizeof(int64_t));
+    add(p.off_T); add(p.off_P); add(p.off_s1); add(p.off_s2); add(p.off_w1); add(p.off_w2);
+    return h;
 }
 
 // The table blob's size is known only after planning; plan with a reserve, then again

@@ -43,7 +43,7 @@ class ProblemC(C.Structure):
                 ("window_A", C.c_double), ("n_probes", C.c_int), ("probe_xy", C.POINTER(C.c_double)),
                 ("n_sites", C.c_int), ("sites", C.POINTER(Site)), ("n_trans_total", C.c_int64),
                 ("precision", C.c_int), ("order", C.c_int), ("max_workspace_bytes", C.c_size_t),
-                ("real_space", C.c_int)]
+                ("real_space", C.c_int), ("resident_s", C.c_int)]
 
 
 class PlanInfo(C.Structure):
@@ -60,7 +60,9 @@ _LIB: Optional[C.CDLL] = None
 EXPORTS = ["eels_get_version", "eels_status_string", "eels_last_error", "eels_plan_create",
            "eels_plan_workspace_bytes", "eels_plan_info_get", "eels_plan_beams", "eels_plan_destroy",
            "eels_execute", "eels_debug_s1", "eels_debug_s2", "eels_gemm_work_bytes", "eels_debug_cgemm",
-           "eels_tune_set", "eels_tune_get", "eels_timing_enable", "eels_timing_read"]
+           "eels_tune_set", "eels_tune_get", "eels_timing_enable", "eels_timing_read", "eels_execute_ex",
+           "eels_plan_s_signature"]
+EXEC_SKIP_UPLOAD, EXEC_SKIP_SWEEPS = 1, 2
 PHASES = ["setup", "sweep", "producer", "gemm1", "gemm2", "reduce"]
 
 
@@ -81,6 +83,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.eels_plan_beams.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.c_int]
     lib.eels_plan_destroy.argtypes = [vp]
     lib.eels_execute.argtypes = [vp, vp, vp, vp, vp, sz, vp]
+    lib.eels_execute_ex.argtypes = [vp, vp, vp, vp, vp, sz, vp, C.c_uint]
+    lib.eels_plan_s_signature.argtypes = [vp, C.POINTER(C.c_uint64)]
     lib.eels_debug_s1.argtypes = [vp, vp, C.c_int, vp, vp, sz, vp]
     lib.eels_debug_s2.argtypes = [vp, vp, C.c_int, vp, vp, sz, vp]
     lib.eels_gemm_work_bytes.argtypes = [C.c_int, C.c_int, C.c_int]
@@ -118,7 +122,7 @@ class Plan:
 
     def __init__(self, problem: Any, precision: str = "fp32", order: str = "auto",
                  max_workspace_bytes: int = 0, lambda_A: float = 0.0, sigma: float = 0.0,
-                 real_space: bool = False):
+                 real_space: bool = False, resident_s: bool = False):
         lib = load_library()
         pr = problem
         self._dz = np.ascontiguousarray(pr.dz, dtype=np.float64)
@@ -140,7 +144,8 @@ class Plan:
             n_probes=int(self._probes.shape[0]),
             probe_xy=self._probes.ctypes.data_as(C.POINTER(C.c_double)), n_sites=S,
             sites=self._sites, n_trans_total=n_trans, precision=PRECISIONS[precision], order=ORDERS[order],
-            max_workspace_bytes=int(max_workspace_bytes), real_space=int(bool(real_space)))
+            max_workspace_bytes=int(max_workspace_bytes), real_space=int(bool(real_space)),
+            resident_s=int(bool(resident_s)))
         self.precision = precision
         h = C.c_void_p()
         _check(lib.eels_plan_create(C.byref(h), C.byref(self.problem)))
@@ -180,10 +185,17 @@ class Plan:
             raise EelsError(4, "workspace allocation not 256-byte aligned")
         return ws
 
-    def execute(self, V, H, out_map, workspace, stream=None):
-        """Enqueue the map computation (device tensors; out_map float64 [P])."""
-        _check(load_library().eels_execute(self._h, _ptr(V), _ptr(H), _ptr(out_map), _ptr(workspace),
-                                           workspace.numel(), _stream(stream)))
+    def execute(self, V, H, out_map, workspace, stream=None, flags: int = 0):
+        """Enqueue the map computation (device tensors; out_map float64 [P]).  flags:
+        EXEC_SKIP_UPLOAD (tables already in this workspace; kernels only, graph-capturable),
+        EXEC_SKIP_SWEEPS (reuse resident S-matrix data of a plan with the same signature)."""
+        _check(load_library().eels_execute_ex(self._h, _ptr(V), _ptr(H), _ptr(out_map), _ptr(workspace),
+                                              workspace.numel(), _stream(stream), int(flags)))
+
+    def s_signature(self) -> int:
+        v = C.c_uint64()
+        _check(load_library().eels_plan_s_signature(self._h, C.byref(v)))
+        return int(v.value)
 
     def debug_s1(self, V, slice_index: int, workspace, stream=None):
         import torch
@@ -227,6 +239,7 @@ def gemm_work_bytes(m: int, n: int, k: int) -> int:
 
 
 TUNE_SC_STAGES = 0
+TUNE_TILE_ORDER = 1
 
 
 def tune_set(key: int, value: int):

@@ -11,6 +11,9 @@ from .specimens import (  # noqa: F401
     config2,
     config3,
     config3_subproblem,
+    config4,
+    config5_stream,
+    random_lattice_specimen,
     random_problem,
     probe_grid,
     transitions_lm,

@@ -432,3 +432,74 @@ def random_problem(seed: int, n: int = 32, ny: Optional[int] = None, L: float = 
                    energy_eV=energy_eV, aperture_mrad=aperture_mrad,
                    det_inner_mrad=det_inner_mrad, det_outer_mrad=det_outer_mrad,
                    interp_f=interp_f, window_A=window_A, defocus_A=defocus_A, cs_A=cs_A)
+
+
+def random_lattice_specimen(rng, n, nz, n_ion, nt_range=(3, 9), px=0.1, dz=2.0, window_A=4.0,
+                            aperture_mrad=20.0, det_outer_mrad=40.0, n_scan=None, name="specimen"):
+    """One specimen of the batching workload: a random rectangular lattice (spacing
+    U(2.5, 4) A, amplitudes U(15, 60) V*A) on an n x n grid at `px` A/px, f = n/128,
+    n_ion ionised lattice atoms with a random number of transitions each."""
+    L = n * px
+    f = max(1, n // 128)
+    a = rng.uniform(2.5, 4.0)
+    nc = max(1, int(L // a))
+    a = L / nc
+    sl, xy, amp = [], [], []
+    for j in range(nz):
+        off = rng.uniform(0, a, 2)
+        for iy in range(nc):
+            for ix in range(nc):
+                sl.append(j)
+                xy.append(((ix * a + off[0]) % L, (iy * a + off[1]) % L))
+                A = rng.uniform(15.0, 60.0)
+                amp.append((A, A / 4.0))
+    sl, xy, amp = np.array(sl), np.array(xy), np.array(amp)
+    wid = np.tile([[0.3, 0.8]], (len(sl), 1))
+    ion = np.sort(rng.choice(len(sl), size=min(n_ion, len(sl)), replace=False))
+    allt = transitions_lm(2)
+    nt = int(rng.integers(nt_range[0], nt_range[1] + 1))
+    trans = allt[:nt]
+    ns = int(n_scan) if n_scan is not None else int(rng.integers(16, 65))
+    probes = probe_grid(ns, ns, L / ns, L / ns)
+    return _finish(name, n, n, L, L, [dz] * nz, sl, xy, amp, wid, sl[ion], xy[ion], trans, probes,
+                   (ns, ns), energy_eV=ENERGY_300KEV, aperture_mrad=aperture_mrad, det_inner_mrad=0.0,
+                   det_outer_mrad=det_outer_mrad, interp_f=f, window_A=window_A)
+
+
+def config4(seed: int = 4, n_specimens: int = 64, sizes=(128, 256, 512), slices=(10, 80),
+            ions=(1, 20), scans=(16, 64)) -> List[Problem]:
+    """The batching workload: specimens of uneven size drawn from a seed (grids 128^2 to
+    512^2 at 0.1 A/px with f = N/128, 10-80 slices of 2 A, 1-20 ionised atoms with 3-9
+    transitions each, 16^2 to 64^2 probes, 4 A crop, 20 mrad aperture, 0-40 mrad detector)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for k in range(n_specimens):
+        n = int(rng.choice(sizes))
+        nz = int(rng.integers(slices[0], slices[1] + 1))
+        ni = int(rng.integers(ions[0], ions[1] + 1))
+        ns = int(rng.integers(scans[0], scans[1] + 1))
+        out.append(random_lattice_specimen(rng, n, nz, ni, n_scan=ns, name=f"config4_{k}"))
+    return out
+
+
+def config5_stream(seed: int = 5, rate_per_s: float = 1.0, n_requests: int = 40, repeat_frac: float = 0.3,
+                   pool=None):
+    """Poisson request stream for the serving workload: (arrival time, specimen index,
+    probe shift).  A fraction `repeat_frac` of requests repeats an earlier specimen with
+    a shifted probe raster (S-matrix residency)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = 0.0
+    reqs = []
+    seen = []
+    n_pool = len(pool) if pool is not None else n_requests
+    for i in range(n_requests):
+        t += rng.exponential(1.0 / rate_per_s)
+        if seen and rng.uniform() < repeat_frac:
+            k = int(rng.choice(seen))
+            shift = float(rng.uniform(0.0, 1.0))
+        else:
+            k = int(rng.integers(0, n_pool))
+            shift = 0.0
+        seen.append(k)
+        reqs.append((t, k, shift))
+    return reqs

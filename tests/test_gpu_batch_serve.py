@@ -1,0 +1,132 @@
+"""GPU tests of the extensions: batched maps in a captured HIP graph, the autotuner,
+S-matrix residency (EELS_EXEC_SKIP_SWEEPS) and the serving loop."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import metrics, prism
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1908_07628_amd import eels
+    return eels
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _specimens(n=5, seed=7):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for k in range(n):
+        size = [64, 128][k % 2]
+        out.append(synth.random_lattice_specimen(rng, size, int(rng.integers(3, 7)), int(rng.integers(1, 4)),
+                                                 nt_range=(1, 3), n_scan=int(rng.integers(4, 9)),
+                                                 det_outer_mrad=30.0, name=f"b{k}"))
+    return out
+
+
+def test_batch_graph_replays_match_eager_and_solo():
+    eels = _gpu()
+    from paper_1908_07628_amd.batch import Batch
+    sp = _specimens()
+    b = Batch(sp, precision="fp32", n_streams=3, tuned=False)
+    b.run_eager()
+    eager = b.maps_host()
+    for i, p in enumerate(sp):
+        solo = eels.solve(p, precision="fp32")
+        assert np.array_equal(eager[i], solo), i
+    ref = prism.prism_map(sp[0])
+    assert metrics.rel_l2(eager[0], ref) < 1e-4
+    b.capture()
+    for rep in range(3):
+        b.maps.zero_()                                  # eager work between replays
+        torch.cuda.synchronize()
+        b.replay()
+        got = b.maps_host()
+        _say("replay", rep)
+        for i in range(len(sp)):
+            assert np.array_equal(got[i], eager[i]), (rep, i)
+
+
+def test_autotuner_caches_a_valid_setting(tmp_path, monkeypatch):
+    eels = _gpu()
+    from paper_1908_07628_amd import autotune
+    monkeypatch.setenv("EELS_TUNE_CACHE", str(tmp_path / "tune.json"))
+    p = _specimens(1, seed=11)[0]
+    plan = eels.Plan(p, precision="bf16_split")
+    V, H = eels.device_inputs(p)
+    best, times = autotune.tune(plan, V, H, reps=1)
+    assert len(times) == 4 and best in autotune.candidates(plan)
+    assert autotune.load_cache()[autotune.key_of(plan)] == best
+    assert autotune.apply(plan) == best
+    ws = plan.alloc_workspace()
+    out = torch.empty(plan.n_probes, dtype=torch.float64, device="cuda")
+    plan.execute(V, H, out, ws)
+    autotune.set_knobs(autotune.DEFAULTS)
+    assert metrics.rel_l2(out.cpu().numpy(), prism.prism_map(p)) < 1e-3
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16_split"])
+def test_resident_s_matrices_serve_new_probes(prec):
+    eels = _gpu()
+    p = synth.config1()
+    q = p.replace(probes=p.probes[:9] + [0.7, 0.4], probe_shape=(1, 9))
+    a = eels.Plan(p, precision=prec, resident_s=True)
+    b = eels.Plan(q, precision=prec, resident_s=True)
+    assert a.s_signature() == b.s_signature()
+    V, H = eels.device_inputs(p)
+    ws = torch.empty(max(a.workspace_bytes, b.workspace_bytes), dtype=torch.uint8, device="cuda")
+    outa = torch.empty(a.n_probes, dtype=torch.float64, device="cuda")
+    outb = torch.empty(b.n_probes, dtype=torch.float64, device="cuda")
+    a.execute(V, H, outa, ws)
+    b.execute(V, H, outb, ws, flags=eels.EXEC_SKIP_SWEEPS)   # reuses the S-matrices of a
+    torch.cuda.synchronize()
+    ref = eels.solve(q, precision=prec)
+    assert np.array_equal(outb.cpu().numpy(), ref)
+    tol = 1e-4 if prec == "fp32" else 1e-3
+    assert metrics.rel_l2(outb.cpu().numpy(), prism.prism_map(q)) < tol
+
+
+def test_server_results_equal_alone_and_in_the_mix():
+    eels = _gpu()
+    from paper_1908_07628_amd.serve import Server
+    sp = _specimens(4, seed=13)
+    reqs = [sp[0], sp[1], sp[2], sp[0].replace(probes=sp[0].probes + 0.37), sp[3],
+            sp[1].replace(probes=sp[1].probes + 0.11)]
+    solo = [eels.solve(r, precision="fp32") for r in reqs]
+    srv = Server(hbm_budget_bytes=int(40e9), max_slots=3, precision="fp32", residency=True)
+    try:
+        tickets = [srv.submit(r) for r in reqs]
+        res = [srv.wait(t, timeout=300) for t in tickets]
+        for k, r in enumerate(res):
+            assert r.error is None, r.error
+            assert np.array_equal(r.map, solo[k]), k
+        st = srv.latency_stats()
+        _say("serve stats", st)
+        assert st["n"] == len(reqs) and st["p99_s"] >= st["p50_s"] > 0
+        assert st["resident_hits"] >= 1
+    finally:
+        srv.close()
+
+
+def test_server_rejects_request_over_budget():
+    eels = _gpu()
+    from paper_1908_07628_amd.serve import Server
+    srv = Server(hbm_budget_bytes=int(1e6), max_slots=1, precision="fp32", residency=False)
+    try:
+        t = srv.submit(synth.config1())
+        r = srv.wait(t, timeout=30)
+        assert r.error is not None and "budget" in r.error
+    finally:
+        srv.close()
