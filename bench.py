@@ -78,6 +78,100 @@ def cpu_baseline(p, budget_s=25.0):
     }
 
 
+def bench_batch(args):
+    """Batching workload: 64 specimens of uneven size, one captured HIP graph."""
+    import torch
+    import synth
+    from paper_1908_07628_amd import eels
+    from paper_1908_07628_amd.batch import Batch
+    t0 = time.time()
+    specs = synth.config4(n_specimens=args.n_specimens, workers=min(16, os.cpu_count() or 1))
+    log(f"{len(specs)} specimens generated in {time.time() - t0:.1f} s")
+    b = Batch(specs, precision=args.precision, n_streams=4, tuned=False)
+    log(f"arena {b.arena.numel() / 1e9:.1f} GB")
+    t0 = time.time()
+    b.tune(reps=1)
+    log(f"autotuned in {time.time() - t0:.1f} s")
+    # eager, one stream, one specimen after another (tables uploaded)
+    b.tuned = False
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for i, pl in enumerate(b.plans):
+        V, H = b.inputs[i]
+        pl.execute(V, H, b.out(i), b.workspaces[i])
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t1
+    ref = b.maps_host()
+    b.tuned = True
+    b.capture()
+    b.replay()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        b.replay()
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t2) / args.steps
+    got = b.maps_host()
+    worst = max(float(np.max(np.abs(g - r)) / max(np.max(np.abs(r)), 1e-300)) for g, r in zip(got, ref))
+    probes = int(sum(p.n_probes for p in specs))
+    return {
+        "metric": METRIC, "value": round(probes / t_graph, 2), "unit": "probe-px/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": round(1e3 * t_graph, 1), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": (f"batch of {len(specs)} specimens, grids {sorted(set(p.nx for p in specs))} "
+                                "at 0.1 A/px, f = N/128, 10-80 slices, 1-20 ionised atoms x 3-9 transitions, "
+                                "4 A crop, 16^2-64^2 probes; one captured HIP graph on 4 stream branches"),
+                   "n_specimens": len(specs), "total_probes": probes},
+        "eager_sequential_ms": round(1e3 * t_seq, 1), "graph_speedup": round(t_seq / t_graph, 2),
+        "graph_vs_eager_max_rel_diff": worst,
+    }
+
+
+def bench_serve(args):
+    """Serving workload: Poisson arrivals, continuous batching, residency, p50/p99."""
+    import torch
+    import synth
+    from paper_1908_07628_amd import eels
+    from paper_1908_07628_amd.serve import Server, specimen_key
+    t0 = time.time()
+    pool = synth.specimen_pool(55, args.pool, (128, 256, 512, 1024), (10, 60), (1, 20), (16, 64), "req",
+                               workers=min(16, os.cpu_count() or 1))
+    log(f"{len(pool)} specimens generated in {time.time() - t0:.1f} s")
+    keys = [specimen_key(p) for p in pool]
+    free, _ = torch.cuda.mem_get_info()
+    out = {"metric": METRIC, "unit": "probe-px/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+           "dtype": args.precision, "vs_baseline": None,
+           "config": {"workload": (f"Poisson stream of {args.n_requests} requests per rate over a pool of "
+                                   f"{len(pool)} specimens (grids 128^2-1024^2, 10-60 slices), 30% repeats of "
+                                   "(specimen, sites) with shifted probes; 4 slots"),
+                      "budget_GB": round(0.8 * free / 1e9, 1)}, "rates": {}}
+    for rate in args.rates:
+        reqs = synth.config5_stream(seed=5, rate_per_s=rate, n_requests=args.n_requests, pool=pool)
+        srv = Server(int(0.8 * free), max_slots=4, precision=args.precision, residency=True)
+        t0 = time.perf_counter()
+        tickets = []
+        for (t_arr, k, shift) in reqs:
+            dt = t_arr - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            p = pool[k].replace(probes=pool[k].probes + shift)
+            tickets.append(srv.submit(p, key=keys[k]))
+        res = [srv.wait(t, timeout=900) for t in tickets]
+        wall = time.perf_counter() - t0
+        srv.close()
+        st = srv.latency_stats(tickets)
+        probes = sum(pool[k].n_probes for (_, k, _) in reqs)
+        out["rates"][str(rate)] = {"p50_s": round(st["p50_s"], 3), "p99_s": round(st["p99_s"], 3),
+                                   "mean_s": round(st["mean_s"], 3), "resident_hits": st["resident_hits"],
+                                   "requests": st["n"], "errors": sum(r.error is not None for r in res),
+                                   "throughput_probe_px_s": round(probes / wall, 1),
+                                   "maps_per_s": round(len(reqs) / wall, 3)}
+        log(f"rate {rate}: {out['rates'][str(rate)]}")
+    best = max(out["rates"].values(), key=lambda r: r["throughput_probe_px_s"])
+    out["value"] = best["throughput_probe_px_s"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,11 +182,24 @@ def main():
     ap.add_argument("--fp32-slices", type=int, default=2, help="ionised slices of the FP32 sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", action="store_true", help="compare sampled probes with the stored FP64 values")
+    ap.add_argument("--workload", default="crystal", choices=["crystal", "batch", "serve"],
+                    help="crystal: the benchmark map (default); batch: 64 uneven specimens in one graph; "
+                         "serve: Poisson request stream with p50/p99 latency")
+    ap.add_argument("--n-specimens", type=int, default=64)
+    ap.add_argument("--pool", type=int, default=10)
+    ap.add_argument("--n-requests", type=int, default=40)
+    ap.add_argument("--rates", type=float, nargs="+", default=[1.0, 4.0])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is "
               "described in DESIGN.md and not run here.", file=sys.stderr)
         sys.exit(2)
+    if args.workload != "crystal":
+        if args.precision == "bf16_split" and args.workload == "batch":
+            args.precision = "fp16_split"
+        res = bench_batch(args) if args.workload == "batch" else bench_serve(args)
+        print(json.dumps(res), flush=True)
+        return
 
     import torch
     import synth

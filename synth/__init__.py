@@ -14,6 +14,7 @@ from .specimens import (  # noqa: F401
     config4,
     config5_stream,
     random_lattice_specimen,
+    specimen_pool,
     random_problem,
     probe_grid,
     transitions_lm,

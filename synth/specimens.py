@@ -466,20 +466,37 @@ def random_lattice_specimen(rng, n, nz, n_ion, nt_range=(3, 9), px=0.1, dz=2.0, 
                    det_outer_mrad=det_outer_mrad, interp_f=f, window_A=window_A)
 
 
-def config4(seed: int = 4, n_specimens: int = 64, sizes=(128, 256, 512), slices=(10, 80),
-            ions=(1, 20), scans=(16, 64)) -> List[Problem]:
-    """The batching workload: specimens of uneven size drawn from a seed (grids 128^2 to
-    512^2 at 0.1 A/px with f = N/128, 10-80 slices of 2 A, 1-20 ionised atoms with 3-9
-    transitions each, 16^2 to 64^2 probes, 4 A crop, 20 mrad aperture, 0-40 mrad detector)."""
+def _pool_one(args):
+    seed, n, nz, ni, ns, name = args
+    return random_lattice_specimen(np.random.Generator(np.random.PCG64(seed)), n, nz, ni, n_scan=ns, name=name)
+
+
+def specimen_pool(seed: int, n_specimens: int, sizes, slices, ions, scans, prefix: str = "specimen",
+                  workers: int = 1) -> List[Problem]:
+    """Random-lattice specimens with sizes, slice counts, ionised atoms and probe rasters
+    drawn from a seed; every specimen has its own sub-seed, so `workers` processes give
+    the same result as one."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    out = []
+    args = []
     for k in range(n_specimens):
         n = int(rng.choice(sizes))
         nz = int(rng.integers(slices[0], slices[1] + 1))
         ni = int(rng.integers(ions[0], ions[1] + 1))
         ns = int(rng.integers(scans[0], scans[1] + 1))
-        out.append(random_lattice_specimen(rng, n, nz, ni, n_scan=ns, name=f"config4_{k}"))
-    return out
+        args.append((int(rng.integers(0, 2**62)), n, nz, ni, ns, f"{prefix}_{k}"))
+    if workers > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            return pool.map(_pool_one, args)
+    return [_pool_one(a) for a in args]
+
+
+def config4(seed: int = 4, n_specimens: int = 64, sizes=(128, 256, 512), slices=(10, 80),
+            ions=(1, 20), scans=(16, 64), workers: int = 1) -> List[Problem]:
+    """The batching workload: specimens of uneven size drawn from a seed (grids 128^2 to
+    512^2 at 0.1 A/px with f = N/128, 10-80 slices of 2 A, 1-20 ionised atoms with 3-9
+    transitions each, 16^2 to 64^2 probes, 4 A crop, 20 mrad aperture, 0-40 mrad detector)."""
+    return specimen_pool(seed, n_specimens, sizes, slices, ions, scans, "config4", workers)
 
 
 def config5_stream(seed: int = 5, rate_per_s: float = 1.0, n_requests: int = 40, repeat_frac: float = 0.3,
