@@ -1,0 +1,121 @@
+// Register-resident Stockham FFT (radix 16 first, then 16/8/4/2), LDS only between stages.
+//
+// T = N / E threads cooperate on one sequence of length N; thread t holds the E elements
+// t + T m (m = 0 .. E-1) in v[m], both on entry and on exit.  The first stage has radix
+// E, so its butterfly j = t reads exactly v (inputs j + r N / E = t + r T); the last
+// stage's outputs j + r N / R (j = t + b T) are again t + T (b + r E / R).  Middle
+// stages exchange through lds[base + i * es] with a barrier on each side, so every
+// thread of the block must call the transform the same number of times.
+// DIR = -1: forward exp(-2 pi i n k / N); DIR = +1: unnormalised inverse.
+#pragma once
+
+#include "fft_lds.h"
+
+namespace eels {
+
+template <int DIR>
+__device__ __forceinline__ void dft16(float2* v) {
+    // 16 = 4 x 4: x[4 n1 + n2] -> DFT4 over n1, twiddle W16^(n2 k1), DFT4 over n2
+    float2 a[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+        float2 x0 = v[n2], x1 = v[4 + n2], x2 = v[8 + n2], x3 = v[12 + n2];
+        dft4<DIR>(x0, x1, x2, x3);
+        a[n2][0] = x0; a[n2][1] = x1; a[n2][2] = x2; a[n2][3] = x3;
+    }
+    constexpr float c1 = 0.92387953251128674f, s1 = 0.38268343236508978f, h = 0.70710678118654752f;
+    // W16^p = exp(DIR 2 pi i p / 16), p = n2 k1 in {1, 2, 3, 2, 4, 6, 3, 6, 9}
+    const float2 w1 = make_float2(c1, DIR * s1), w2 = make_float2(h, DIR * h), w3 = make_float2(s1, DIR * c1);
+    const float2 w6 = make_float2(-h, DIR * h), w9 = make_float2(-c1, -DIR * s1);
+    a[1][1] = cmul(a[1][1], w1); a[1][2] = cmul(a[1][2], w2); a[1][3] = cmul(a[1][3], w3);
+    a[2][1] = cmul(a[2][1], w2); a[2][2] = mul_i<DIR>(a[2][2]); a[2][3] = cmul(a[2][3], w6);
+    a[3][1] = cmul(a[3][1], w3); a[3][2] = cmul(a[3][2], w6); a[3][3] = cmul(a[3][3], w9);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        float2 x0 = a[0][k1], x1 = a[1][k1], x2 = a[2][k1], x3 = a[3][k1];
+        dft4<DIR>(x0, x1, x2, x3);
+        v[k1] = x0; v[k1 + 4] = x1; v[k1 + 8] = x2; v[k1 + 12] = x3;
+    }
+}
+
+template <int R, int DIR>
+__device__ __forceinline__ void dft_any(float2* v) {
+    if constexpr (R == 16) dft16<DIR>(v);
+    else dft<R, DIR>(v);
+}
+
+template <int N>
+struct RegCfg {
+    static constexpr int E = N >= 16 ? 16 : N;
+    static constexpr int T = N / E;
+};
+
+template <int N, int Ns, int E>
+struct RegRadix {
+    static constexpr int REM = N / Ns;
+    static constexpr int R = REM >= 16 && E >= 16 ? 16 : (REM >= 8 ? 8 : (REM >= 4 ? 4 : 2));
+};
+
+// stage with butterfly radix R on elements in registers (first stage) or LDS (later)
+template <int N, int E, int DIR, int Ns>
+__device__ __forceinline__ void fft_reg_stages(float2 (&v)[E], float2* lds, int base, int es, int t,
+                                               const float2* __restrict__ tw) {
+    constexpr int T = N / E;
+    constexpr int R = (Ns == 1) ? E : RegRadix<N, Ns, E>::R;
+    constexpr int NB = E / R;
+    static_assert(NB * R == E && NB * T * R == N, "register fft decomposition");
+    constexpr bool first = (Ns == 1);
+    constexpr bool last = (Ns * R == N);
+    float2 u[NB][R];
+    if constexpr (first) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) u[0][r] = v[r];
+    } else {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            int j = t + b * T;
+#pragma unroll
+            for (int r = 0; r < R; ++r) u[b][r] = lds[base + (j + r * (N / R)) * es];
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        int j = t + b * T;
+        int k = j & (Ns - 1);
+        if constexpr (Ns > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                float2 w = tw[(r * k) * (N / (Ns * R))];
+                if (DIR > 0) w.y = -w.y;
+                u[b][r] = cmul(u[b][r], w);
+            }
+        }
+        dft_any<R, DIR>(u[b]);
+    }
+    if constexpr (last) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[b + r * NB] = u[b][r];
+    } else {
+        __syncthreads();  // earlier readers of lds are done
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            int j = t + b * T;
+            int k = j & (Ns - 1);
+            int idxD = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[base + (idxD + r * Ns) * es] = u[b][r];
+        }
+        __syncthreads();
+        fft_reg_stages<N, E, DIR, Ns * R>(v, lds, base, es, t, tw);
+    }
+}
+
+template <int N, int DIR>
+__device__ __forceinline__ void fft_reg(float2 (&v)[RegCfg<N>::E], float2* lds, int base, int es, int t,
+                                        const float2* __restrict__ tw) {
+    fft_reg_stages<N, RegCfg<N>::E, DIR, 1>(v, lds, base, es, t, tw);
+}
+
+}  // namespace eels

@@ -16,6 +16,7 @@
 #include <cstdint>
 
 #include "fft_lds.h"
+#include "fft_reg.h"
 #include "internal.h"
 #include "kernels.h"
 
@@ -186,91 +187,76 @@ __global__ void k_copy(float2* dst, const float2* src, int64_t n) {
 
 // --------------------------------------------------------------------- row pass
 //
-// One thread group of T = N/8 threads per row; a block holds S = 256/T rows of the flat
-// row index g = beam * ny + y.  mode 0: forward sweep, mode 1: transposed sweep.
+// T = N/16 threads per row, 16 elements each (pixel / column t + T m in v[m]); a block
+// holds S = 256/T rows of the flat row index g = beam * ny + y.  Loads and stores go
+// straight between HBM and registers; only the middle FFT stages use LDS.
+// mode 0: forward sweep, mode 1: transposed sweep.
+__device__ __forceinline__ int live_col_of(int x, int N, int nlx, int hlx) {
+    if (nlx == N) return x;
+    return x <= hlx ? x : (x >= N - hlx ? x - N + nlx : -1);
+}
+
 template <int N, int MODE>
 __global__ __launch_bounds__(256) void k_row_pass(float2* __restrict__ state, int nbeam, int ny, int nlx, int hlx,
                                                   const float2* __restrict__ Tj, const float2* __restrict__ tw,
                                                   const int* __restrict__ cap_ptr, const int4* __restrict__ cap_rec,
                                                   void* __restrict__ win, int64_t win_beams, int Kpad, int sc) {
-    constexpr int E = 8;
-    constexpr int T = N / E;
-    constexpr int S = 256 / T;
+    constexpr int E = RegCfg<N>::E, T = RegCfg<N>::T, S = 256 / T;
     __shared__ float2 lds[S * N];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, s = tid / T, t = tid % T;
     const int64_t total = (int64_t)nbeam * ny;
-    const int64_t g0 = (int64_t)blockIdx.x * S;
-    const bool all_live = (nlx == N);
-
-    // load live columns, zero the rest
-    for (int idx = tid; idx < S * N; idx += 256) {
-        int s = idx / N, x = idx % N;
-        int64_t g = g0 + s;
-        int c = all_live ? x : (x <= hlx ? x : (x >= N - hlx ? x - N + nlx : -1));
-        float2 v = make_float2(0.f, 0.f);
-        if (g < total && c >= 0) v = state[g * nlx + c];
-        lds[idx] = v;
-    }
-    __syncthreads();
-
-    const int s = tid / T, t = tid % T;
-    const int64_t g = g0 + s;
+    const int64_t g = (int64_t)blockIdx.x * S + s;
     const bool valid = g < total;
     const int y = valid ? (int)(g % ny) : 0;
     const int64_t beam = valid ? g / ny : 0;
-    const int base = s * N;
+    float2 v[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        int c = live_col_of(t + T * m, N, nlx, hlx);
+        v[m] = (valid && c >= 0) ? state[g * nlx + c] : make_float2(0.f, 0.f);
+    }
+    fft_reg<N, MODE == 0 ? +1 : -1>(v, lds, s * N, 1, t, tw);
 
-    if constexpr (MODE == 0) fft_lds<N, E, +1>(lds, base, 1, t, tw);
-    else fft_lds<N, E, -1>(lds, base, 1, t, tw);
-
-    // capture (forward: before T; transposed: after T)
     auto capture = [&]() {
         if (cap_ptr && valid) {
             int r0 = cap_ptr[y], r1 = cap_ptr[y + 1];
             for (int r = r0; r < r1; ++r) {
                 int4 rec = cap_rec[r];
                 int64_t dst = ((int64_t)rec.x * win_beams + beam) * Kpad + (int64_t)rec.y * rec.w;
-                for (int u = t; u < rec.w; u += T) {
-                    int x = rec.z + u;
-                    if (x >= N) x -= N;
-                    store_c(win, dst + u, lds[base + x], sc);
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    int u = t + T * m - rec.z;
+                    if (u < 0) u += N;
+                    if (u < rec.w) store_c(win, dst + u, v[m], sc);
                 }
             }
         }
     };
-    // capture and the T multiply touch pixels owned by other threads of the row: keep
-    // them apart with barriers
-    if constexpr (MODE == 0) {
-        capture();
-        __syncthreads();
-    }
+    if constexpr (MODE == 0) capture();
     const float2* Trow = Tj + (int64_t)y * N;
-    for (int x = t; x < N; x += T) lds[base + x] = cmul(lds[base + x], Trow[x]);
-    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = cmul(v[m], Trow[t + T * m]);
     if constexpr (MODE == 1) capture();
 
-    if constexpr (MODE == 0) fft_lds<N, E, -1>(lds, base, 1, t, tw);
-    else fft_lds<N, E, +1>(lds, base, 1, t, tw);
-
-    for (int idx = tid; idx < S * nlx; idx += 256) {
-        int ss = idx / nlx, c = idx % nlx;
-        int64_t gg = g0 + ss;
-        if (gg >= total) continue;
-        int x = all_live ? c : (c <= hlx ? c : c - nlx + N);
-        state[gg * nlx + c] = lds[ss * N + x];
+    fft_reg<N, MODE == 0 ? -1 : +1>(v, lds, s * N, 1, t, tw);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        int c = live_col_of(t + T * m, N, nlx, hlx);
+        if (valid && c >= 0) state[g * nlx + c] = v[m];
     }
 }
 
 // --------------------------------------------------------------------- column pass
 //
-// A block transforms CW live columns of one beam along y.  Thread (col, t) with
-// col = tid % CW works on column col; T threads per column, E = N / T elements each.
+// A block transforms CW live columns of one beam along y: thread (col, t), col = tid % CW,
+// holds rows t + T m of its column in registers (rows of the strip are CW * 8 bytes
+// contiguous in HBM).
 template <int N>
 struct ColCfg {
-    static constexpr int NT = N >= 1024 ? 512 : 256;
-    static constexpr int T = N >= 1024 ? 64 : (N >= 512 ? 32 : (N / 8 < 16 ? N / 8 : 16));
+    static constexpr int T = RegCfg<N>::T;
+    static constexpr int E = RegCfg<N>::E;
+    static constexpr int NT = N >= 512 ? 512 : 256;
     static constexpr int CW = NT / T;
-    static constexpr int E = N / T;
 };
 
 template <int N, int MODE>
@@ -281,49 +267,37 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_col_pass(float2* __restrict__
                                                             const int* __restrict__ band_off, void* __restrict__ bcap,
                                                             int64_t bstride, int sc) {
     using C = ColCfg<N>;
-    constexpr int CW = C::CW, T = C::T, E = C::E, NT = C::NT;
+    constexpr int CW = C::CW, T = C::T, E = C::E;
     __shared__ float2 lds[N * CW];
     const int tid = threadIdx.x;
     const int strips = (nlx + CW - 1) / CW;
     const int64_t beam = blockIdx.x / strips;
     const int c0 = (int)(blockIdx.x % strips) * CW;
-    float2* plane = state + beam * (int64_t)N * nlx;
-
-    for (int idx = tid; idx < N * CW; idx += NT) {
-        int row = idx / CW, cc = idx % CW;
-        int c = c0 + cc;
-        lds[idx] = c < nlx ? plane[(int64_t)row * nlx + c] : make_float2(0.f, 0.f);
-    }
-    __syncthreads();
     const int col = tid % CW, t = tid / CW;
-    if constexpr (MODE == 0) fft_lds<N, E, -1>(lds, col, CW, t, tw);
-    else fft_lds<N, E, +1>(lds, col, CW, t, tw);
     const int c = c0 + col;
-    for (int i = t; i < N; i += T) {
-        float2 pv = c < nlx ? Pj[(int64_t)i * nlx + c] : make_float2(0.f, 0.f);
-        lds[i * CW + col] = cmul(lds[i * CW + col], pv);
-    }
-    if (bcap) {
-        // the band rows are multiplied by other threads of the column: wait for all of them
-        __syncthreads();
-    }
-    if (bcap && c < nlx) {
+    const bool live = c < nlx;
+    float2* plane = state + beam * (int64_t)N * nlx;
+    float2 v[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = live ? plane[(int64_t)(t + T * m) * nlx + c] : make_float2(0.f, 0.f);
+    fft_reg<N, MODE == 0 ? -1 : +1>(v, lds, col, CW, t, tw);
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = cmul(v[m], live ? Pj[(int64_t)(t + T * m) * nlx + c] : make_float2(0.f, 0.f));
+    if (bcap && live) {
         // band coefficients of this column: ky = 0..h, then ny-h..ny-1, at band_off[c] + rank
         const int h = band_h[c];
         const int64_t dst = beam * bstride + band_off[c];
-        for (int r = t; r <= 2 * h; r += T) {
-            int ky = r <= h ? r : N - (2 * h + 1 - r);
-            store_c(bcap, dst + r, lds[ky * CW + col], sc);
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            int ky = t + T * m;
+            int r = ky <= h ? ky : (ky >= N - h ? 2 * h + 1 - (N - ky) : -1);
+            if (r >= 0) store_c(bcap, dst + r, v[m], sc);
         }
     }
-    __syncthreads();
-    if constexpr (MODE == 0) fft_lds<N, E, +1>(lds, col, CW, t, tw);
-    else fft_lds<N, E, -1>(lds, col, CW, t, tw);
-
-    for (int idx = tid; idx < N * CW; idx += NT) {
-        int row = idx / CW, cc = idx % CW;
-        int cg = c0 + cc;
-        if (cg < nlx) plane[(int64_t)row * nlx + cg] = lds[idx];
+    fft_reg<N, MODE == 0 ? +1 : -1>(v, lds, col, CW, t, tw);
+    if (live) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) plane[(int64_t)(t + T * m) * nlx + c] = v[m];
     }
 }
 
@@ -355,34 +329,29 @@ __global__ __launch_bounds__(256) void k_band_rows(float2* __restrict__ out, con
                                                    int64_t wstride, int Ni, int nt, int ny, int nlx, int hlx,
                                                    const float2* __restrict__ Tj, const float2* __restrict__ Hb,
                                                    int64_t hstride, const float2* __restrict__ tw) {
-    constexpr int E = 8, T = N / E, S = 256 / T;
+    constexpr int E = RegCfg<N>::E, T = RegCfg<N>::T, S = 256 / T;
     __shared__ float2 lds[S * N];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, s = tid / T, t = tid % T;
     const int64_t total = (int64_t)nt * Ni * ny;
-    const int64_t g0 = (int64_t)blockIdx.x * S;
-    for (int idx = tid; idx < S * N; idx += 256) {
-        int s = idx / N, x = idx % N;
-        int64_t g = g0 + s;
-        float2 v = make_float2(0.f, 0.f);
-        if (g < total) {
-            int y = (int)(g % ny);
-            int64_t pi = g / ny;
-            int i = (int)(pi % Ni), t = (int)(pi / Ni);
-            int64_t px = (int64_t)y * N + x;
-            v = cmul(cmul(W[i * wstride + px], Hb[t * hstride + px]), Tj[px]);
-        }
-        lds[idx] = v;
+    const int64_t g = (int64_t)blockIdx.x * S + s;
+    const bool valid = g < total;
+    const int y = valid ? (int)(g % ny) : 0;
+    const int64_t pi = valid ? g / ny : 0;
+    const int i = (int)(pi % Ni), tt = (int)(pi / Ni);
+    const float2* wr = W + i * wstride + (int64_t)y * N;
+    const float2* hr = Hb + tt * hstride + (int64_t)y * N;
+    const float2* trow = Tj + (int64_t)y * N;
+    float2 v[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        int x = t + T * m;
+        v[m] = valid ? cmul(cmul(wr[x], hr[x]), trow[x]) : make_float2(0.f, 0.f);
     }
-    __syncthreads();
-    const int s = tid / T, t = tid % T;
-    fft_lds<N, E, -1>(lds, s * N, 1, t, tw);
-    const bool all_live = (nlx == N);
-    for (int idx = tid; idx < S * nlx; idx += 256) {
-        int ss = idx / nlx, c = idx % nlx;
-        int64_t gg = g0 + ss;
-        if (gg >= total) continue;
-        int x = all_live ? c : (c <= hlx ? c : c - nlx + N);
-        out[gg * nlx + c] = lds[ss * N + x];
+    fft_reg<N, -1>(v, lds, s * N, 1, t, tw);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        int c = live_col_of(t + T * m, N, nlx, hlx);
+        if (valid && c >= 0) out[g * nlx + c] = v[m];
     }
 }
 
@@ -401,23 +370,22 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_band_cols(void* __restrict__ 
     const int strips = (nlx + CW - 1) / CW;
     const int64_t plane = blockIdx.x / strips;
     const int strip = (int)(blockIdx.x % strips);
-    const int c0 = strip * CW;
-    const float2* sp = src + plane * (int64_t)N * nlx;
-    for (int idx = tid; idx < N * CW; idx += NT) {
-        int row = idx / CW, cc = idx % CW;
-        int c = c0 + cc;
-        lds[idx] = c < nlx ? sp[(int64_t)row * nlx + c] : make_float2(0.f, 0.f);
-    }
-    __syncthreads();
     const int col = tid % CW, t = tid / CW;
-    fft_lds<N, E, -1>(lds, col, CW, t, tw);
-    const int c = c0 + col;
-    if (c < nlx) {
+    const int c = strip * CW + col;
+    const bool live = c < nlx;
+    const float2* sp = src + plane * (int64_t)N * nlx;
+    float2 v[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = live ? sp[(int64_t)(t + T * m) * nlx + c] : make_float2(0.f, 0.f);
+    fft_reg<N, -1>(v, lds, col, CW, t, tw);
+    if (live) {
         const int h = band_h[c];
         const int64_t o = plane * dstride + band_off[c];
-        for (int r = t; r <= 2 * h; r += T) {
-            int ky = r <= h ? r : N - (2 * h + 1 - r);
-            store_c(dst, o + r, lds[ky * CW + col], sc);
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            int ky = t + T * m;
+            int r = ky <= h ? ky : (ky >= N - h ? 2 * h + 1 - (N - ky) : -1);
+            if (r >= 0) store_c(dst, o + r, v[m], sc);
         }
     }
     if (strip == 0)
@@ -518,7 +486,7 @@ void launch_copy(float2* dst, const float2* src, int64_t n, hipStream_t st) {
 
 template <int N, int MODE>
 static void row_pass_n(const RowPassArgs& a, hipStream_t st) {
-    constexpr int S = 256 / (N / 8);
+    constexpr int S = 256 / RegCfg<N>::T;
     int64_t rows = (int64_t)a.nbeam * a.ny;
     hipLaunchKernelGGL((k_row_pass<N, MODE>), dim3(blocks_for(rows, S)), dim3(256), 0, st, a.state, a.nbeam, a.ny,
                        a.nlx, a.hlx, a.Tj, a.tw, a.cap_ptr, (const int4*)a.cap_rec, a.win, a.win_beams, a.Kpad, a.sc);
@@ -569,7 +537,7 @@ void launch_init_band(void* bcap, int64_t bstride, const int4* beams, const int*
 
 template <int NX, int NY>
 static void band_fft_n(const BandFft& a, hipStream_t st) {
-    constexpr int S = 256 / (NX / 8);
+    constexpr int S = 256 / RegCfg<NX>::T;
     int64_t rows = (int64_t)a.nt * a.Ni * a.ny;
     hipLaunchKernelGGL((k_band_rows<NX>), dim3(blocks_for(rows, S)), dim3(256), 0, st, a.scratch, a.W, a.wstride,
                        a.Ni, a.nt, a.ny, a.nlx, a.hlx, a.Tj, a.H, a.hstride, a.twx);
