@@ -105,7 +105,17 @@ typedef struct {
     int resident_s;          /* 1: keep the S_2 capture of every ionised slice in the workspace
                                 (needs one slice group), so that a later eels_execute_ex with
                                 EELS_EXEC_SKIP_SWEEPS can reuse the S-matrices              */
+    int detector_sum;        /* EELS_DETSUM_*: how sum_{n,q} |A_n(q,R)|^2 is formed (order S)  */
 } eels_problem;
+
+/* Detector sum of the S-first order.  DIRECT: A_n(q, R) = sum_k Z_n(q, k) c_k(R) by a second
+ * GEMM per transition with |.|^2 summed over q in its epilogue.  GRAM: with every probe
+ * covering every site (interp_f = 1), sum_{n,q} |A_n(q,R)|^2 = c(R)^H G c(R) with the
+ * Hermitian G = sum_n Z_n^H Z_n (N_1 x N_1, accumulated in FP64); the second GEMM forms
+ * the upper-triangle tiles of each site's Z^H Z and one FP64 quadratic form per probe
+ * finishes the map (about 5x fewer flops than DIRECT for the crystal maps).  AUTO picks
+ * GRAM where it applies (order S, interp_f = 1, band basis or split precision). */
+enum { EELS_DETSUM_AUTO = 0, EELS_DETSUM_DIRECT = 1, EELS_DETSUM_GRAM = 2 };
 
 /* Derived sizes of a plan (filled by eels_plan_info). */
 typedef struct {
@@ -127,6 +137,7 @@ typedef struct {
     double sweep_bytes;      /* algorithmic HBM bytes of the two sweeps                   */
     double sweep_beam_slices;/* beam-slice passes of the two sweeps                       */
     size_t workspace_bytes;
+    int gram_form;           /* 1 if the detector sum uses the Gram form (EELS_DETSUM_GRAM) */
 } eels_plan_info;
 
 typedef struct eels_plan eels_plan;
@@ -198,10 +209,16 @@ eels_status eels_debug_cgemm(int precision, int m, int n, int k, const void* d_A
                              void* d_work, void* stream);
 
 /* Process-wide kernel tuning knobs, read at launch time (the autotuner sets them).
- * key 0: LDS pipeline depth of the split-precision GEMM: 2 (two workgroups per CU,
- *        default) or 3 (one workgroup per CU, deeper prefetch).
- * key 1: tile order of the contraction GEMMs within a problem: 0 m-fastest (default; the
- *        workgroups in flight share B tiles), 1 n-fastest (they share A tiles).
+ * key 0: LDS pipeline of the split-precision GEMM: 2 (two stages of 16-complex tiles, two
+ *        workgroups per CU, default), 3 (three such stages, one workgroup per CU), 4 or 5
+ *        (four or five stages of 8-complex tiles, two workgroups per CU).
+ * key 1: tile order of the contraction GEMMs within a problem: 0 m-fastest (the workgroups
+ *        in flight share B tiles), 1 n-fastest (they share A tiles), 2 XCD-aware (default;
+ *        each of the 8 XCDs takes one contiguous range of tiles in groups of 8 m tiles, so
+ *        the workgroups sharing one L2 cover a compact patch of the output).
+ * key 2: instruction schedule of the two-stage split GEMM: bit 0 reads the next 8-complex
+ *        step's operand fragments from LDS before the current step's MFMAs, bit 1 raises
+ *        the wave's issue priority while it issues MFMAs (0 default).
  * Returns EELS_ERR_INVALID_ARG for an unknown key or an out-of-range value. */
 eels_status eels_tune_set(int key, int value);
 int eels_tune_get(int key);

@@ -20,9 +20,9 @@ from . import eels
 
 KNOBS = {
     "sc_stages": (eels.TUNE_SC_STAGES, (2, 3)),
-    "tile_order": (eels.TUNE_TILE_ORDER, (0, 1)),
+    "tile_order": (eels.TUNE_TILE_ORDER, (0, 1, 2)),
 }
-DEFAULTS = {"sc_stages": 2, "tile_order": 0}
+DEFAULTS = {"sc_stages": 2, "tile_order": 2}
 _lock = threading.Lock()
 
 

@@ -32,7 +32,7 @@ namespace eels {
 static thread_local std::string g_err;
 void set_error(const std::string& m) { g_err = m; }
 
-static std::atomic<int> g_tune[TUNE_COUNT] = {{2}, {0}, {0}, {0}, {0}, {0}, {0}, {0}};
+static std::atomic<int> g_tune[TUNE_COUNT] = {{2}, {2}, {0}, {0}, {0}, {0}, {0}, {0}};
 int tune_get(int key) { return (key >= 0 && key < TUNE_COUNT) ? g_tune[key].load() : 0; }
 
 // Diagnostic phase timing (eels_timing_enable / eels_timing_read).
@@ -80,6 +80,8 @@ struct Dev {
     const int *band_h, *band_off;
     float2 *twx, *twy, *T, *P, *C, *s1, *s2, *w1, *w2, *mid, *mid2, *scratch;
     float* part;
+    double* gtot;     // Gram form: sum of Z^H Z, FP64 complex [N_1][N_1]
+    double* qpart;    // Gram form: per-probe partial quadratic forms
 };
 
 Dev make_dev(const Plan& p, void* ws_) {
@@ -106,6 +108,8 @@ Dev make_dev(const Plan& p, void* ws_) {
     d.mid2 = (float2*)(d.ws + p.off_mid2);
     d.scratch = (float2*)(d.ws + p.off_scratch);
     d.part = (float*)(d.ws + p.off_part);
+    d.gtot = (double*)(d.ws + p.off_gtot);
+    d.qpart = (double*)(d.ws + p.off_qpart);
     return d;
 }
 
@@ -222,6 +226,32 @@ void contract(const Plan& p, const Dev& d, const float2* dH, double* map, int bi
     const bool split = p.precision != EELS_FP32;
     const int nst = tune_get(TUNE_SC_STAGES);
     const bool h_pro = !p.recip;   // FP32 real-space: H applied in the GEMM prologue
+    if (p.gram) {
+        // Gram form: Z^T = (H S_1) S_2^T per site, then the upper tiles of Z^H Z, summed
+        // over the batch's sites into G in FP64
+        run_jobs(p, d, dH, b, b.slice, st);
+        {
+            TimeScope ts(EELS_PHASE_GEMM1, st);
+            if (split)
+                launch_cgemm_sc(p.precision, 0, nst, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.mid2, d.w2, d.mid,
+                                nullptr, d.blob, st);
+            else
+                launch_cgemm(EELS_FP32, 0, 0, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.mid2, d.w2, nullptr, d.mid,
+                             nullptr, d.blob, st);
+        }
+        {
+            TimeScope ts(EELS_PHASE_GEMM2, st);
+            if (split)
+                launch_cgemm_sc(p.precision, 2, nst, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.mid, d.mid, nullptr,
+                                d.part, d.blob, st);
+            else
+                launch_cgemm(EELS_FP32, 0, 2, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.mid, d.mid, nullptr, nullptr,
+                             d.part, d.blob, st);
+        }
+        TimeScope ts(EELS_PHASE_REDUCE, st);
+        launch_gram_reduce(d.gtot, (const float2*)d.part, b.n_parts, (int64_t)p.N1pad * p.N1pad, p.N1, p.N1pad, st);
+        return;
+    }
     if (b.order == EELS_ORDER_S_FIRST) {
         if (split || p.recip) run_jobs(p, d, dH, b, b.slice, st);
         {
@@ -264,6 +294,15 @@ void contract(const Plan& p, const Dev& d, const float2* dH, double* map, int bi
     double scale = (double)p.f * p.f / (nn * nn) / ((double)p.c_scale * p.c_scale);
     if (b.red_ptr < 0) launch_reduce_dense(map, p.P, dd, b.d2_begin, b.d2_count, d.part, scale, st);
     else launch_reduce(map, p.P, d.blob + b.red_ptr, d.blob + b.red_ent, dd, d.part, scale, st);
+}
+
+// Gram form: I(R) = scale * c(R)^H G c(R) once every batch has added its Z^H Z to G.
+void finish_map(const Plan& p, const Dev& d, double* map, hipStream_t st) {
+    if (!p.gram) return;
+    TimeScope ts(EELS_PHASE_REDUCE, st);
+    double nn = (double)p.nx * (double)p.ny;
+    double scale = (double)p.f * p.f / (nn * nn) / ((double)p.c_scale * p.c_scale);
+    launch_quadform(map, p.P, d.gtot, p.N1, d.C, p.N1pad, d.qpart, scale, st);
 }
 
 }  // namespace
@@ -351,6 +390,7 @@ eels_status eels_plan_info_get(const eels_plan* pl, eels_plan_info* info) {
     info->sweep_bytes = p.sweep_bytes;
     info->sweep_beam_slices = p.sweep_beam_slices;
     info->workspace_bytes = p.ws_bytes;
+    info->gram_form = p.gram ? 1 : 0;
     return EELS_OK;
 }
 
@@ -400,11 +440,13 @@ eels_status eels_execute_ex(const eels_plan* pl, const float* d_V, const void* d
     if ((s = setup(p, d, d_V, st, !(flags & EELS_EXEC_SKIP_UPLOAD)))) return s;
     launch_probe_coefficients(d.C, d.b1, d.probes, p, p.c_sc, st);
     launch_fill_zero_d(d_map, p.P, st);
+    if (p.gram) launch_fill_zero_d(d.gtot, 2 * (int64_t)p.N1 * p.N1, st);
     if (skip_sweeps) {
         // the S_1 windows and every slice's S_2 capture are already in the workspace
         for (int j = p.nz - 1; j >= 0; --j)
             if (p.slices[j].ion)
                 for (int bi : p.slices[j].batches) contract(p, d, (const float2*)d_H, d_map, bi, st);
+        finish_map(p, d, d_map, st);
         HIPCHK(hipGetLastError());
         return EELS_OK;
     }
@@ -421,6 +463,7 @@ eels_status eels_execute_ex(const eels_plan* pl, const float* d_V, const void* d
         }
         rev_next = g.j_lo - 1;
     }
+    finish_map(p, d, d_map, st);
     HIPCHK(hipGetLastError());
     return EELS_OK;
 }
@@ -533,8 +576,9 @@ eels_status eels_debug_cgemm(int precision, int m, int n, int k, const void* d_A
 
 eels_status eels_tune_set(int key, int value) {
     if (key < 0 || key >= TUNE_COUNT) return EELS_ERR_INVALID_ARG;
-    if (key == TUNE_SC_STAGES && (value < 2 || value > 3)) return EELS_ERR_INVALID_ARG;
-    if (key == TUNE_TILE_ORDER && (value < 0 || value > 1)) return EELS_ERR_INVALID_ARG;
+    if (key == TUNE_SC_STAGES && (value < 2 || value > 5)) return EELS_ERR_INVALID_ARG;
+    if (key == TUNE_TILE_ORDER && (value < 0 || value > 2)) return EELS_ERR_INVALID_ARG;
+    if (key == TUNE_SC_SCHED && (value < 0 || value > 3)) return EELS_ERR_INVALID_ARG;
     g_tune[key].store(value);
     return EELS_OK;
 }

@@ -33,12 +33,16 @@ struct GemmDesc {
     int M, N_inner, n_t, K;
     int idx_off;       // offset into the int table, -1 = no gather
     int tiles_m, tiles_n, tile_start;
-    int pad_[2];
+    int flags;         // GD_* bits
+    int pad_;
 };
+// descriptor flags: the plain FP32 store epilogue also zeroes the padding columns
+// N .. ceil16(N)-1 of every stored row (they are K padding of a later product)
+enum { GD_ZERO_PAD = 1 };
 static_assert(sizeof(GemmDesc) == 144, "GemmDesc layout");
 
 // Process-wide tuning knobs (set by eels_tune_set; read at launch time).
-enum TuneKey { TUNE_SC_STAGES = 0, TUNE_TILE_ORDER = 1, TUNE_COUNT = 8 };
+enum TuneKey { TUNE_SC_STAGES = 0, TUNE_TILE_ORDER = 1, TUNE_SC_SCHED = 2, TUNE_COUNT = 8 };
 int tune_get(int key);
 
 struct Batch {
@@ -50,6 +54,7 @@ struct Batch {
     int64_t red_ptr;                    // int offset of the per-probe CSR row pointers [P+1], -1: dense
     int64_t red_ent;                    // int offset of the CSR entries (pairs: desc, column)
     int64_t n_entries;
+    int n_parts;                        // Gram form: FP32 partials of Z^H Z written by the second GEMM
 };
 
 // Producer job: write the H-multiplied operand of one site into mid2, either in the band
@@ -105,6 +110,8 @@ struct Plan {
     std::vector<int> band_h, band_off;          // band rows per live column, band slot offsets
     int Kb, Kbpad;                              // band pixels, padded stride
     int c_sc, w2_sc, mid2_sc;                   // storage formats (0 complex64, else split precision)
+    bool gram;                                  // detector sum in the Gram form (order S, f = 1)
+    int N2p;                                    // N_2 rounded up to 16 (row blocks of Z^T)
     std::vector<int> site_w1, site_w2;          // window index of each site (S_1 group-local, S_2 slice-local)
     std::vector<int> site_ix0, site_iy0;
     std::vector<std::vector<int>> site_probes;  // eligible probes (empty vector + flag = all)
@@ -129,7 +136,7 @@ struct Plan {
 
     // workspace layout (byte offsets)
     size_t off_blob, off_twx, off_twy, off_T, off_P, off_C, off_s1, off_s2, off_w1, off_w2,
-        off_mid, off_mid2, off_scratch, off_part, ws_bytes;
+        off_mid, off_mid2, off_scratch, off_part, off_gtot, off_qpart, ws_bytes;
 };
 
 eels_status build_plan(Plan& p, const eels_problem& prob);

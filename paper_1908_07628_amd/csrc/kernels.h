@@ -73,18 +73,31 @@ void launch_reduce_dense(double* map, int P, const GemmDesc* descs, int d_begin,
                          double scale, hipStream_t st);
 
 // Grouped complex GEMM (see GemmDesc).  kind 0: B rows are K-contiguous ("NT"); kind 1:
-// B is [k][n] ("NN", single precision only).  epi 0: store, epi 1: norm partial sums.
+// B is [k][n] ("NN", single precision only).  epi 0: store, epi 1: norm partial sums,
+// epi 2: Gram tile conj(A) B^T (upper tiles only) stored as FP32 complex into `part`.
 void launch_cgemm(int precision, int kind, int epi, const GemmDesc* d_descs, int n_desc, int total_tiles,
                   const float2* A, const float2* B, const float2* H, float2* C, float* part, const int* idx,
                   hipStream_t st);
 
 // Split-precision grouped GEMM on SC operands (see kernels_gemm.hip); B rows of column
-// block t start at b_off + t * ldh.  epi 0 stores C in SC form, epi 1 writes norm partials.
+// block t start at b_off + t * ldh.  epi 0 stores C in SC form, epi 1 writes norm partials,
+// epi 2 the Gram tile conj(A) B^T as FP32 complex (as launch_cgemm).
 void launch_cgemm_sc(int precision, int epi, int nstage, const GemmDesc* d_descs, int n_desc, int total_tiles,
                      const void* A, const void* B, void* C, float* part, const int* idx, hipStream_t st);
 // complex64 [rows][ld] -> SC (columns >= K written as zero)
 void launch_to_sc(void* dst, const float2* src, int64_t rows, int K, int ld, int prec, hipStream_t st);
 // SC -> complex64 of n contiguous complex slots
 void launch_from_sc(float2* dst, const void* src, int64_t n, int prec, hipStream_t st);
+
+// Gram form of the detector sum (kernels_gram.hip).  The upper 128 x 128 tiles of
+// G [n1][n1] (FP64 complex) += the sum of `nparts` partials (FP32 complex, [n1][ldp] each,
+// part_stride apart; only their upper tiles are read).
+void launch_gram_reduce(double* G, const float2* part, int nparts, int64_t part_stride, int n1, int ldp,
+                        hipStream_t st);
+// Fills the lower tiles of G from the upper ones (Hermitian), then map[R] += scale *
+// Re(c(R)^H G c(R)) for the P probes; C complex64 [P][ldc]; qpart holds P * ceil(n1 / 64)
+// doubles of partial sums (summed in a fixed order).
+void launch_quadform(double* map, int P, double* G, int n1, const float2* C, int ldc, double* qpart,
+                     double scale, hipStream_t st);
 
 }  // namespace eels

@@ -76,18 +76,21 @@ __device__ __forceinline__ u32x4 swap_halves(u32x4 v) {  // (re, im) -> (im, re)
     return (v >> 16) | (v << 16);
 }
 
-template <int PREC, int KIND, int EPI>
-__global__ __launch_bounds__(256) void k_cgemm(const GemmDesc* __restrict__ descs, int n_desc,
-                                               const float2* __restrict__ Ab, const float2* __restrict__ Bb,
-                                               const float2* __restrict__ Hb, float2* __restrict__ Cb,
-                                               float* __restrict__ Pb, const int* __restrict__ ib, int n_fast) {
-    constexpr bool SPLIT = PREC != EELS_FP32;
-    static_assert(!(SPLIT && KIND == 1), "the [k][n] B layout is single precision only");
-    constexpr int LDS_BYTES = SPLIT ? 4 * BM * LDS_ * 4 : 2 * BM * LDF * 8;
-    __shared__ __attribute__((aligned(16))) char smem[LDS_BYTES > 2048 ? LDS_BYTES : 2048];
-
-    // ---- locate this block's problem and tile
-    const int bid = blockIdx.x;
+// Block -> (descriptor, m tile, n tile, t).  Tile orders within a descriptor and t:
+//   0  m fastest (the blocks in flight share B tiles)
+//   1  n fastest (they share A tiles)
+//   2  XCD-aware: workgroups are dispatched to the 8 XCDs round-robin, so block b runs
+//      on XCD b % 8; each XCD is given one contiguous range of tiles, walked in groups of
+//      8 m tiles with m fastest, so the blocks resident on one XCD cover a compact
+//      8 x 8 patch of the output and its L2 holds only their A and B rows.
+// Returns the descriptor index.
+__device__ __forceinline__ int locate_tile(const GemmDesc* __restrict__ descs, int n_desc, int order, int& tm,
+                                           int& tn, int& t) {
+    int bid = blockIdx.x;
+    if (order == 2) {
+        const int nt = gridDim.x, x = bid & 7, s = bid >> 3, q = nt >> 3, r = nt & 7;
+        bid = x * q + min(x, r) + s;
+    }
     int lo = 0, hi = n_desc - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
@@ -96,20 +99,42 @@ __global__ __launch_bounds__(256) void k_cgemm(const GemmDesc* __restrict__ desc
     }
     const GemmDesc& d = descs[lo];
     const int local = bid - d.tile_start;
-    // tile order within a descriptor: m fastest (blocks in flight share B tiles) or n
-    // fastest (they share A tiles); chosen by the tuner
-    int tm, tn, t;
-    if (n_fast) {
-        const int per_t = d.tiles_m * d.tiles_n;
-        t = local / per_t;
-        const int r = local - t * per_t;
+    const int per_t = d.tiles_m * d.tiles_n;
+    t = local / per_t;
+    const int r = local - t * per_t;
+    if (order == 1) {
         tn = r % d.tiles_n;
         tm = r / d.tiles_n;
+    } else if (order == 0) {
+        tm = r % d.tiles_m;
+        tn = r / d.tiles_m;
     } else {
-        tm = local % d.tiles_m;
-        const int rest = local / d.tiles_m;
-        tn = rest % d.tiles_n;
-        t = rest / d.tiles_n;
+        constexpr int G = 8;
+        const int grp = r / (G * d.tiles_n), fm = grp * G;
+        const int gs = min(d.tiles_m - fm, G);
+        const int w = r - grp * G * d.tiles_n;
+        tm = fm + w % gs;
+        tn = w / gs;
+    }
+    return lo;
+}
+
+template <int PREC, int KIND, int EPI>
+__global__ __launch_bounds__(256) void k_cgemm(const GemmDesc* __restrict__ descs, int n_desc,
+                                               const float2* __restrict__ Ab, const float2* __restrict__ Bb,
+                                               const float2* __restrict__ Hb, float2* __restrict__ Cb,
+                                               float* __restrict__ Pb, const int* __restrict__ ib, int order) {
+    constexpr bool SPLIT = PREC != EELS_FP32;
+    static_assert(!(SPLIT && KIND == 1), "the [k][n] B layout is single precision only");
+    static_assert(!(SPLIT && EPI == 2), "split Gram tiles run in the SC kernel");
+    constexpr int LDS_BYTES = SPLIT ? 4 * BM * LDS_ * 4 : 2 * BM * LDF * 8;
+    __shared__ __attribute__((aligned(16))) char smem[LDS_BYTES > 2048 ? LDS_BYTES : 2048];
+
+    // ---- locate this block's problem and tile
+    int tm, tn, t;
+    const GemmDesc& d = descs[locate_tile(descs, n_desc, order, tm, tn, t)];
+    if constexpr (EPI == 2) {
+        if (tn < tm) return;   // Gram tiles: the lower triangle is the conjugate transpose
     }
     const int M = d.M, K = d.K, N = d.N_inner;
     const int m0 = tm * BM, n0 = tn * BN;
@@ -251,8 +276,13 @@ __global__ __launch_bounds__(256) void k_cgemm(const GemmDesc* __restrict__ desc
 #pragma unroll
                 for (int bn = 0; bn < 2; ++bn) {
                     float2 b = Bs[(wn * 64 + bn * 32 + li) * LDF + kk];
-                    br[bn] = hl ? -b.y : b.x;
-                    bi[bn] = hl ? b.x : b.y;
+                    if constexpr (EPI == 2) {   // conj(a) b
+                        br[bn] = hl ? b.y : b.x;
+                        bi[bn] = hl ? -b.x : b.y;
+                    } else {
+                        br[bn] = hl ? -b.y : b.x;
+                        bi[bn] = hl ? b.x : b.y;
+                    }
                 }
 #pragma unroll
                 for (int bm = 0; bm < 2; ++bm)
@@ -303,8 +333,30 @@ __global__ __launch_bounds__(256) void k_cgemm(const GemmDesc* __restrict__ desc
 
     // ---- epilogues.  32x32 accumulator layout: element v of lane l is row
     // 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32.
-    if constexpr (EPI == 0) {
+    if constexpr (EPI == 2) {
+        float2* G = (float2*)Pb + d.p_off + (int64_t)t * d.ldc_t;
+#pragma unroll
+        for (int bn = 0; bn < 2; ++bn) {
+            int i = n0 + wn * 64 + bn * 32 + li;
+            if (i >= N) continue;
+#pragma unroll
+            for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    int m = m0 + wm * 64 + bm * 32 + 8 * (v >> 2) + 4 * hl + (v & 3);
+                    if (m < M) G[(int64_t)m * d.ldc_m + i] = make_float2(accR[bm][bn][v], accI[bm][bn][v]);
+                }
+        }
+    } else if constexpr (EPI == 0) {
         float2* C = Cb + d.c_off + (int64_t)t * d.ldc_t;
+        if (d.flags & GD_ZERO_PAD) {
+            const int npad = (N + 15) & ~15;
+            if (n0 + BN > N && n0 < npad)
+                for (int e = tid; e < BM * 16; e += 256) {
+                    int m = m0 + e / 16, i = N + e % 16;
+                    if (m < M && i < npad && i >= n0 && i < n0 + BN) C[(int64_t)m * d.ldc_m + i] = make_float2(0.f, 0.f);
+                }
+        }
 #pragma unroll
         for (int bn = 0; bn < 2; ++bn) {
             int i = n0 + wn * 64 + bn * 32 + li;
@@ -345,11 +397,13 @@ __global__ __launch_bounds__(256) void k_cgemm(const GemmDesc* __restrict__ desc
 // [lo: four u32].  Offsets and strides count 8-byte complex slots exactly as for complex64,
 // so an SC matrix occupies the same bytes as its complex64 form.
 //
-// The kernel streams 128-row x 16-complex tiles of both operands straight from global
-// memory into a ring of NSTAGE LDS buffers (global_load_lds_dwordx4, no registers), so
-// NSTAGE - 1 tiles are in flight while one is multiplied.  Inside a tile row of 128 bytes
-// (eight 16-byte quads) quad q of row r is stored at position q ^ ((r >> 1) & 7), which
-// makes the fragment reads of 16 consecutive rows hit distinct LDS banks.
+// The kernel streams 128-row x BK-complex tiles of both operands (BK = 4 UNITS: 16 or 8)
+// straight from global memory into a ring of NSTAGE LDS buffers (global_load_lds_dwordx4,
+// no registers), so NSTAGE - 1 tiles are in flight while one is multiplied.  A tile row
+// holds QUADS = 2 UNITS 16-byte quads; quad q of row r is stored at position
+// q ^ ((r >> 1) & (QUADS - 1)), which makes the fragment reads of consecutive rows hit
+// distinct LDS banks.  Two workgroups share a CU when their rings fit in half the LDS
+// (16-complex tiles: 2 stages; 8-complex tiles: up to 5 stages).
 // Rows beyond M or N are clamped to the last valid row (their results are discarded or
 // masked); the K padding of every SC operand holds zeros.
 
@@ -370,41 +424,34 @@ __device__ __forceinline__ void wait_vmcnt() {
     __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
-template <int PREC, int EPI, int NSTAGE>
-__global__ __launch_bounds__(256, NSTAGE == 2 ? 2 : 1) void k_cgemm_sc(const GemmDesc* __restrict__ descs, int n_desc,
+template <int UNITS, int NSTAGE>
+struct ScPipe {
+    static constexpr int ROWB = 32 * UNITS;              // bytes of one tile row
+    static constexpr int QUADS = 2 * UNITS;
+    static constexpr int STAGE = 2 * 128 * ROWB;         // A and B tiles
+    static constexpr int RPI = 1024 / ROWB;              // rows per wave-wide 16-byte load
+    static constexpr int NI = 32 / RPI;                  // loads per wave per operand
+    static constexpr int WAVES_PER_EU = 2 * NSTAGE * STAGE <= 160 * 1024 ? 2 : 1;
+};
+
+template <int PREC, int EPI, int NSTAGE, int UNITS, int SCHED>
+__global__ __launch_bounds__(256, (ScPipe<UNITS, NSTAGE>::WAVES_PER_EU)) void k_cgemm_sc(const GemmDesc* __restrict__ descs, int n_desc,
                                                   const uint32_t* __restrict__ Ab, const uint32_t* __restrict__ Bb,
                                                   uint32_t* __restrict__ Cb, float* __restrict__ Pb,
-                                                  const int* __restrict__ ib, int n_fast) {
-    constexpr int STAGE = 2 * 128 * 128;  // bytes: A and B tiles of 128 rows x 128 bytes
+                                                  const int* __restrict__ ib, int order) {
+    using SP = ScPipe<UNITS, NSTAGE>;
+    constexpr int STAGE = SP::STAGE, ROWB = SP::ROWB, QUADS = SP::QUADS, RPI = SP::RPI, NI = SP::NI;
+    constexpr int BKS = 4 * UNITS;  // complex per tile row
     __shared__ __attribute__((aligned(1024))) char smem[NSTAGE * STAGE];
 
-    const int bid = blockIdx.x;
-    int lo = 0, hi = n_desc - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (descs[mid].tile_start <= bid) lo = mid;
-        else hi = mid - 1;
-    }
-    const GemmDesc& d = descs[lo];
-    const int local = bid - d.tile_start;
-    // tile order within a descriptor: m fastest (blocks in flight share B tiles) or n
-    // fastest (they share A tiles); chosen by the tuner
     int tm, tn, t;
-    if (n_fast) {
-        const int per_t = d.tiles_m * d.tiles_n;
-        t = local / per_t;
-        const int r = local - t * per_t;
-        tn = r % d.tiles_n;
-        tm = r / d.tiles_n;
-    } else {
-        tm = local % d.tiles_m;
-        const int rest = local / d.tiles_m;
-        tn = rest % d.tiles_n;
-        t = rest / d.tiles_n;
+    const GemmDesc& d = descs[locate_tile(descs, n_desc, order, tm, tn, t)];
+    if constexpr (EPI == 2) {
+        if (tn < tm) return;   // Gram tiles: the lower triangle is the conjugate transpose
     }
     const int M = d.M, N = d.N_inner;
     const int m0 = tm * BM, n0 = tn * BN;
-    const int nk = (d.K + BK - 1) / BK;
+    const int nk = (d.K + BKS - 1) / BKS;
     const char* A = (const char*)Ab + 8 * (d.a_off + (int64_t)t * d.a_tstride);
     const char* B = (const char*)Bb + 8 * (d.b_off + (int64_t)t * d.b_tstride);
     const int* idx = d.idx_off >= 0 ? ib + d.idx_off : nullptr;
@@ -413,14 +460,14 @@ __global__ __launch_bounds__(256, NSTAGE == 2 ? 2 : 1) void k_cgemm_sc(const Gem
     const int wm = wave & 1, wn = wave >> 1;
     const int li = lane & 31, hl = lane >> 5;
 
-    // this lane's four A and four B source rows (one per 8-row chunk of the wave's 32 rows)
-    const int qpos = lane & 7;
-    const char* asrc[4];
-    const char* bsrc[4];
+    // this lane's NI A and NI B source rows (one per RPI-row chunk of the wave's 32 rows)
+    const int qpos = lane % QUADS;
+    const char* asrc[NI];
+    const char* bsrc[NI];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        int r = wave * 32 + c * 8 + (lane >> 3);
-        int q = qpos ^ ((r >> 1) & 7);
+    for (int c = 0; c < NI; ++c) {
+        int r = wave * 32 + c * RPI + lane / QUADS;
+        int q = qpos ^ ((r >> 1) & (QUADS - 1));
         int m = min(m0 + r, M - 1);
         int n = min(n0 + r, N - 1);
         int nr = idx ? idx[n] : n;
@@ -431,15 +478,15 @@ __global__ __launch_bounds__(256, NSTAGE == 2 ? 2 : 1) void k_cgemm_sc(const Gem
     lds_char* lds = (lds_char*)smem;
     auto issue = [&](int kt) {
         lds_char* st = lds + (kt % NSTAGE) * STAGE;
-        int64_t koff = (int64_t)kt * (BK * 8);
+        int64_t koff = (int64_t)kt * ROWB;
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-            __builtin_amdgcn_global_load_lds((const void*)(asrc[c] + koff), (void*)(st + (wave * 32 + c * 8) * 128), 16,
-                                             0, 0);
+        for (int c = 0; c < NI; ++c)
+            __builtin_amdgcn_global_load_lds((const void*)(asrc[c] + koff), (void*)(st + (wave * 32 + c * RPI) * ROWB),
+                                             16, 0, 0);
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+        for (int c = 0; c < NI; ++c)
             __builtin_amdgcn_global_load_lds((const void*)(bsrc[c] + koff),
-                                             (void*)(st + 128 * 128 + (wave * 32 + c * 8) * 128), 16, 0, 0);
+                                             (void*)(st + 128 * ROWB + (wave * 32 + c * RPI) * ROWB), 16, 0, 0);
     };
 
     floatx16 accR[2][2], accI[2][2];
@@ -450,6 +497,56 @@ __global__ __launch_bounds__(256, NSTAGE == 2 ? 2 : 1) void k_cgemm_sc(const Gem
 #pragma unroll
             for (int v = 0; v < 16; ++v) { accR[a][b][v] = 0.f; accI[a][b][v] = 0.f; }
 
+    // operand fragments of one 8-complex step: hi and lo quads of this lane's A and B rows
+    struct Frag {
+        u32x4 ah[2], al[2], bh[2], bl[2];
+    };
+    auto load_frag = [&](const char* st, int ks, Frag& f) {
+        const int u = 2 * ks + hl;
+#pragma unroll
+        for (int bm = 0; bm < 2; ++bm) {
+            int r = wm * 64 + bm * 32 + li;
+            int sw = (r >> 1) & (QUADS - 1);
+            const char* row = st + r * ROWB;
+            f.ah[bm] = *(const u32x4*)(row + 16 * ((2 * u) ^ sw));
+            f.al[bm] = *(const u32x4*)(row + 16 * ((2 * u + 1) ^ sw));
+        }
+#pragma unroll
+        for (int bn = 0; bn < 2; ++bn) {
+            int r = wn * 64 + bn * 32 + li;
+            int sw = (r >> 1) & (QUADS - 1);
+            const char* row = st + 128 * ROWB + r * ROWB;
+            f.bh[bn] = *(const u32x4*)(row + 16 * ((2 * u) ^ sw));
+            f.bl[bn] = *(const u32x4*)(row + 16 * ((2 * u + 1) ^ sw));
+        }
+    };
+    auto mma = [&](const Frag& f) {
+        if constexpr (SCHED & 2) __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+        for (int bn = 0; bn < 2; ++bn) {
+            // Re C = A'.(Br, -Bi), Im C = A'.(Bi, Br); with conj(A) (Gram tiles):
+            // Re C = A'.(Br, Bi), Im C = A'.(Bi, -Br)
+            u32x4 brh, brl, bih, bil;
+            if constexpr (EPI == 2) {
+                brh = f.bh[bn]; brl = f.bl[bn];
+                bih = neg_imag(swap_halves(f.bh[bn])); bil = neg_imag(swap_halves(f.bl[bn]));
+            } else {
+                brh = neg_imag(f.bh[bn]); brl = neg_imag(f.bl[bn]);
+                bih = swap_halves(f.bh[bn]); bil = swap_halves(f.bl[bn]);
+            }
+#pragma unroll
+            for (int bm = 0; bm < 2; ++bm) {
+                accR[bm][bn] = mfma16<PREC>(f.ah[bm], brh, accR[bm][bn]);
+                accR[bm][bn] = mfma16<PREC>(f.ah[bm], brl, accR[bm][bn]);
+                accR[bm][bn] = mfma16<PREC>(f.al[bm], brh, accR[bm][bn]);
+                accI[bm][bn] = mfma16<PREC>(f.ah[bm], bih, accI[bm][bn]);
+                accI[bm][bn] = mfma16<PREC>(f.ah[bm], bil, accI[bm][bn]);
+                accI[bm][bn] = mfma16<PREC>(f.al[bm], bih, accI[bm][bn]);
+            }
+        }
+        if constexpr (SCHED & 2) __builtin_amdgcn_s_setprio(0);
+    };
+
 #pragma unroll
     for (int s = 0; s < NSTAGE - 1; ++s)
         if (s < nk) issue(s);
@@ -458,45 +555,45 @@ __global__ __launch_bounds__(256, NSTAGE == 2 ? 2 : 1) void k_cgemm_sc(const Gem
         // this wave's loads of tile kt are done once at most the later tiles' loads remain;
         // the barrier then covers every wave's part of the tile and frees the stage that was
         // multiplied in the previous iteration (its LDS reads fed MFMAs, so they completed)
-        if (nk - 1 - kt >= NSTAGE - 2) wait_vmcnt<8 * (NSTAGE - 2)>();
+        if (nk - 1 - kt >= NSTAGE - 2) wait_vmcnt<2 * NI * (NSTAGE - 2)>();
         else wait_vmcnt<0>();
         __builtin_amdgcn_s_barrier();
         if (kt + NSTAGE - 1 < nk) issue(kt + NSTAGE - 1);
         const char* st = smem + (kt % NSTAGE) * STAGE;
+        if constexpr (SCHED & 1) {
+            // fragments of the next 8-complex step are read while this step's MFMAs run
+            Frag f[2];
+            load_frag(st, 0, f[0]);
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-            const int u = 2 * ks + hl;
-            u32x4 ah[2], al[2];
-#pragma unroll
-            for (int bm = 0; bm < 2; ++bm) {
-                int r = wm * 64 + bm * 32 + li;
-                int sw = (r >> 1) & 7;
-                const char* row = st + r * 128;
-                ah[bm] = *(const u32x4*)(row + 16 * ((2 * u) ^ sw));
-                al[bm] = *(const u32x4*)(row + 16 * ((2 * u + 1) ^ sw));
+            for (int ks = 0; ks < UNITS / 2; ++ks) {
+                if (ks + 1 < UNITS / 2) load_frag(st, ks + 1, f[(ks + 1) & 1]);
+                mma(f[ks & 1]);
             }
+        } else {
 #pragma unroll
-            for (int bn = 0; bn < 2; ++bn) {
-                int r = wn * 64 + bn * 32 + li;
-                int sw = (r >> 1) & 7;
-                const char* row = st + 128 * 128 + r * 128;
-                u32x4 bh = *(const u32x4*)(row + 16 * ((2 * u) ^ sw));
-                u32x4 bl = *(const u32x4*)(row + 16 * ((2 * u + 1) ^ sw));
-                u32x4 brh = neg_imag(bh), brl = neg_imag(bl), bih = swap_halves(bh), bil = swap_halves(bl);
-#pragma unroll
-                for (int bm = 0; bm < 2; ++bm) {
-                    accR[bm][bn] = mfma16<PREC>(ah[bm], brh, accR[bm][bn]);
-                    accR[bm][bn] = mfma16<PREC>(ah[bm], brl, accR[bm][bn]);
-                    accR[bm][bn] = mfma16<PREC>(al[bm], brh, accR[bm][bn]);
-                    accI[bm][bn] = mfma16<PREC>(ah[bm], bih, accI[bm][bn]);
-                    accI[bm][bn] = mfma16<PREC>(ah[bm], bil, accI[bm][bn]);
-                    accI[bm][bn] = mfma16<PREC>(al[bm], bih, accI[bm][bn]);
-                }
+            for (int ks = 0; ks < UNITS / 2; ++ks) {
+                Frag f;
+                load_frag(st, ks, f);
+                mma(f);
             }
         }
     }
 
-    if constexpr (EPI == 0) {
+    if constexpr (EPI == 2) {
+        float2* G = (float2*)Pb + d.p_off + (int64_t)t * d.ldc_t;
+#pragma unroll
+        for (int bn = 0; bn < 2; ++bn) {
+            int i = n0 + wn * 64 + bn * 32 + li;
+            if (i >= N) continue;
+#pragma unroll
+            for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    int m = m0 + wm * 64 + bm * 32 + 8 * (v >> 2) + 4 * hl + (v & 3);
+                    if (m < M) G[(int64_t)m * d.ldc_m + i] = make_float2(accR[bm][bn][v], accI[bm][bn][v]);
+                }
+        }
+    } else if constexpr (EPI == 0) {
         // store the product in SC form; the padding columns N .. ceil16(N)-1 get zeros so
         // that the result can be a K operand of the next product
         const int64_t cbase = d.c_off + (int64_t)t * d.ldc_t;
@@ -573,6 +670,7 @@ void launch_cgemm(int precision, int kind, int epi, const GemmDesc* dd, int nd, 
     switch (precision) {
         case EELS_FP32:
             if (epi == 0) go<EELS_FP32, 0, 0>(dd, nd, tiles, A, B, H, C, part, idx, st);
+            else if (epi == 2) go<EELS_FP32, 0, 2>(dd, nd, tiles, A, B, H, C, part, idx, st);
             else go<EELS_FP32, 0, 1>(dd, nd, tiles, A, B, H, C, part, idx, st);
             break;
         case EELS_BF16_SPLIT:
@@ -590,12 +688,24 @@ void launch_cgemm(int precision, int kind, int epi, const GemmDesc* dd, int nd, 
 template <int PREC, int EPI>
 static void go_sc(int nstage, const GemmDesc* dd, int nd, int tiles, const uint32_t* A, const uint32_t* B, uint32_t* C,
                   float* P, const int* idx, hipStream_t st) {
-    if (nstage >= 3)
-        hipLaunchKernelGGL((k_cgemm_sc<PREC, EPI, 3>), dim3(tiles), dim3(256), 0, st, dd, nd, A, B, C, P, idx,
-                           tune_get(TUNE_TILE_ORDER));
-    else
-        hipLaunchKernelGGL((k_cgemm_sc<PREC, EPI, 2>), dim3(tiles), dim3(256), 0, st, dd, nd, A, B, C, P, idx,
-                           tune_get(TUNE_TILE_ORDER));
+    // pipeline variants: 2 / 3 stages of 16-complex tiles, 4 / 5 stages of 8-complex tiles
+    const int order = tune_get(TUNE_TILE_ORDER);
+#define SCV(NS, U, SC) \
+    hipLaunchKernelGGL((k_cgemm_sc<PREC, EPI, NS, U, SC>), dim3(tiles), dim3(256), 0, st, dd, nd, A, B, C, P, idx, order)
+    switch (nstage) {
+        case 3: SCV(3, 4, 0); break;
+        case 4: SCV(4, 2, 0); break;
+        case 5: SCV(5, 2, 0); break;
+        default:
+            switch (tune_get(TUNE_SC_SCHED)) {
+                case 1: SCV(2, 4, 1); break;
+                case 2: SCV(2, 4, 2); break;
+                case 3: SCV(2, 4, 3); break;
+                default: SCV(2, 4, 0); break;
+            }
+            break;
+    }
+#undef SCV
 }
 
 void launch_cgemm_sc(int precision, int epi, int nstage, const GemmDesc* dd, int nd, int tiles, const void* A,
@@ -605,9 +715,11 @@ void launch_cgemm_sc(int precision, int epi, int nstage, const GemmDesc* dd, int
     uint32_t* c = (uint32_t*)C;
     if (precision == EELS_BF16_SPLIT) {
         if (epi == 0) go_sc<EELS_BF16_SPLIT, 0>(nstage, dd, nd, tiles, a, b, c, part, idx, st);
+        else if (epi == 2) go_sc<EELS_BF16_SPLIT, 2>(nstage, dd, nd, tiles, a, b, c, part, idx, st);
         else go_sc<EELS_BF16_SPLIT, 1>(nstage, dd, nd, tiles, a, b, c, part, idx, st);
     } else {
         if (epi == 0) go_sc<EELS_FP16_SPLIT, 0>(nstage, dd, nd, tiles, a, b, c, part, idx, st);
+        else if (epi == 2) go_sc<EELS_FP16_SPLIT, 2>(nstage, dd, nd, tiles, a, b, c, part, idx, st);
         else go_sc<EELS_FP16_SPLIT, 1>(nstage, dd, nd, tiles, a, b, c, part, idx, st);
     }
 }

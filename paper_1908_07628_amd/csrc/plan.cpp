@@ -79,6 +79,8 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
         return fail(EELS_ERR_INVALID_ARG, "aperture / detector angles");
     if (q.precision < EELS_FP32 || q.precision > EELS_FP16_SPLIT) return fail(EELS_ERR_INVALID_ARG, "precision");
     if (q.order < EELS_ORDER_AUTO || q.order > EELS_ORDER_PROBE_FIRST) return fail(EELS_ERR_INVALID_ARG, "order");
+    if (q.detector_sum < EELS_DETSUM_AUTO || q.detector_sum > EELS_DETSUM_GRAM)
+        return fail(EELS_ERR_INVALID_ARG, "detector_sum");
     if (!(q.energy_eV > 0) && !(q.lambda_A > 0 && q.sigma > 0)) return fail(EELS_ERR_INVALID_ARG, "energy");
 
     p.nx = q.nx; p.ny = q.ny; p.lx = q.lx_A; p.ly = q.ly_A; p.nz = q.n_slices;
@@ -204,19 +206,37 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     const int Kc = p.recip ? p.Kb : p.K;            // contraction length of the big GEMM
     const int Kcpad = p.recip ? p.Kbpad : p.Kpad;
 
-    // contraction order (Eq. TPRISM2 terms; both orders compute the same sums)
-    double fl_S = 0, fl_P = 0;
+    // Gram form of the detector sum: every probe must cover every site (f = 1), and the
+    // first product must not carry H in its prologue (FP32 real-space contraction)
+    const bool gram_ok = p.f == 1 && (p.recip || split) && q.order != EELS_ORDER_PROBE_FIRST;
+    if (q.detector_sum == EELS_DETSUM_GRAM && !gram_ok)
+        return fail(EELS_ERR_INVALID_ARG, "the Gram detector sum needs interp_f = 1, order S and the band basis "
+                                          "or a split precision");
+    const bool want_gram = gram_ok && q.detector_sum != EELS_DETSUM_DIRECT;
+
+    // contraction order (Eq. TPRISM2 terms; both orders compute the same sums).  Gram form:
+    // the Hermitian half of each site's Z^H Z plus one quadratic form per probe.
+    double fl_S = 0, fl_P = 0, fl_G = 0;
     for (int j : ion)
         for (int s : by_slice[j]) {
             double nt = p.sites[s].n_trans, Ps = n_elig(s);
-            fl_S += 8.0 * p.N2 * (double)Kc * nt * p.N1 + 8.0 * nt * p.N2 * p.N1 * Ps;
+            double g1 = 8.0 * p.N2 * (double)Kc * nt * p.N1;
+            fl_S += g1 + 8.0 * nt * p.N2 * p.N1 * Ps;
+            fl_G += g1 + 8.0 * nt * p.N2 * 0.5 * p.N1 * (p.N1 + 1.0);
             fl_P += 8.0 * Ps * (double)p.K * p.N1 + 8.0 * p.N2 * (double)Kc * nt * Ps;
         }
-    p.order = q.order == EELS_ORDER_AUTO ? (fl_S <= fl_P ? EELS_ORDER_S_FIRST : EELS_ORDER_PROBE_FIRST) : q.order;
-    p.gemm_flops = p.order == EELS_ORDER_S_FIRST ? fl_S : fl_P;
+    if (!ion.empty()) fl_G += 8.0 * p.N1 * (double)p.N1 * p.P;
+    if (want_gram) fl_S = std::min(fl_S, fl_G);
+    if (q.order != EELS_ORDER_AUTO) p.order = q.order;
+    else if (q.detector_sum == EELS_DETSUM_GRAM) p.order = EELS_ORDER_S_FIRST;   // the Gram form is order S
+    else p.order = fl_S <= fl_P ? EELS_ORDER_S_FIRST : EELS_ORDER_PROBE_FIRST;
+    p.gram = want_gram && p.order == EELS_ORDER_S_FIRST &&
+             (q.detector_sum == EELS_DETSUM_GRAM || fl_G <= fl_S);
+    p.N2p = (int)round_up(p.N2, KPAD_MULT);
+    p.gemm_flops = p.order == EELS_ORDER_S_FIRST ? (p.gram ? fl_G : fl_S) : fl_P;
     p.c_scale = p.precision == EELS_FP16_SPLIT ? 256.0f : 1.0f;
     const bool orderS = p.order == EELS_ORDER_S_FIRST;
-    p.c_sc = (split && orderS) ? p.precision : 0;
+    p.c_sc = (split && orderS && !p.gram) ? p.precision : 0;   // the Gram quadratic form reads complex64
     p.w2_sc = split ? p.precision : 0;
     p.mid2_sc = split ? p.precision : 0;
 
@@ -239,6 +259,7 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     // basis), band-FFT scratch, norm partial sums
     auto site_mid = [&](int s) -> int64_t {
         int nt = p.sites[s].n_trans;
+        if (p.gram) return (int64_t)p.N1 * nt * p.N2p;     // Z^T rows [k][t][q]
         return orderS ? (int64_t)nt * p.N2 * p.N1pad : (int64_t)n_elig(s) * p.Kpad;
     };
     auto site_ni = [&](int s) -> int64_t { return orderS ? p.N1 : n_elig(s); };
@@ -247,6 +268,7 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
         return (int64_t)p.sites[s].n_trans * site_ni(s) * Kcpad;
     };
     auto site_part = [&](int s) -> int64_t {
+        if (p.gram) return 2 * (int64_t)p.sites[s].n_trans * p.N1pad * p.N1pad;   // FP32 partials of Z_t^H Z_t
         int nt = p.sites[s].n_trans;
         int64_t tm = ceil_div(p.N2, GEMM_BM);
         return tm * nt * (int64_t)n_elig(s);
@@ -265,7 +287,8 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
                    + A(c8 * p.nx) + A(c8 * p.ny) + A(c8 * (size_t)p.nz * p.ny * p.nx) +
                    A(c8 * (size_t)p.nz * p.ny * p.nlx) + A(c8 * (size_t)p.P * p.N1pad) +
                    A(c8 * (size_t)p.N1 * p.ny * p.nlx) + A(c8 * (size_t)p.N2 * p.ny * p.nlx) +
-                   A(c8 * (size_t)w2_elems) + A(c8 * (size_t)scratch);
+                   A(c8 * (size_t)w2_elems) + A(c8 * (size_t)scratch) +
+                   (p.gram ? A(16 * (size_t)p.N1 * p.N1) + A(8 * (size_t)p.P * ceil_div(p.N1, 64)) : 0);
 
     size_t budget = q.max_workspace_bytes;
     size_t batch_cap = SIZE_MAX;
@@ -457,7 +480,18 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
             const eels_site& st = p.sites[s];
             int Ps = n_elig(s);
             GemmDesc d{};
-            if (orderS) {
+            if (orderS && p.gram) {
+                // Z_s^T[k][t][q] = sum_r (H_t S1w)[k][r] S2w[q][r]  (or its band-basis form)
+                d.a_off = site_m2off[si]; d.lda = Kcpad; d.a_tstride = (int64_t)p.N1 * Kcpad;
+                if (p.recip) { d.b_off = p.slice_w2[pb.slice]; d.ldb = p.Kbpad; }
+                else { d.b_off = p.slice_w2[pb.slice] + (int64_t)p.site_w2[s] * w2_stride; d.ldb = p.Kpad; }
+                d.b_tstride = 0;
+                d.h_off = -1;
+                d.c_off = site_moff[si]; d.ldc_m = (int64_t)st.n_trans * p.N2p; d.ldc_t = p.N2p;
+                d.M = p.N1; d.N_inner = p.N2; d.n_t = st.n_trans; d.K = Kc;
+                d.idx_off = -1;
+                d.flags = GD_ZERO_PAD;
+            } else if (orderS) {
                 // Z_s[t][q][k] = sum_r S2w[q][r] H_t[r] S1w[k][r]  (or its band-basis form)
                 if (p.recip) { d.a_off = p.slice_w2[pb.slice]; d.lda = p.Kbpad; }
                 else { d.a_off = p.slice_w2[pb.slice] + (int64_t)p.site_w2[s] * w2_stride; d.lda = p.Kpad; }
@@ -498,6 +532,25 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
             int Ps = n_elig(s);
             const std::vector<int>* pl = p.f > 1 ? &p.site_probes[s] : nullptr;
             GemmDesc d{};
+            if (orderS && p.gram) {
+                // G_t[k][k'] = sum_q conj(Z_s^T[k][t][q]) Z_s^T[k'][t][q]  (upper tiles), one
+                // FP32 partial per transition; the partials are summed in FP64
+                d.a_off = site_moff[si]; d.lda = (int64_t)st.n_trans * p.N2p; d.a_tstride = p.N2p;
+                d.b_off = site_moff[si]; d.ldb = d.lda; d.b_tstride = p.N2p;
+                d.h_off = -1; d.ldh = 0;
+                d.c_off = 0; d.ldc_m = p.N1pad; d.ldc_t = (int64_t)p.N1pad * p.N1pad;
+                d.M = p.N1; d.N_inner = p.N1; d.n_t = st.n_trans; d.K = p.N2p;
+                d.idx_off = -1;
+                d.tiles_m = (int)ceil_div(d.M, GEMM_BM);
+                d.tiles_n = (int)ceil_div(d.N_inner, GEMM_BN);
+                d.tile_start = tiles;
+                d.p_off = poff; d.ld_part = 0;     // float2 offset of the site's first partial
+                poff += (int64_t)st.n_trans * p.N1pad * p.N1pad;
+                tiles += d.tiles_m * d.tiles_n * d.n_t;
+                bt.n_parts += st.n_trans;
+                p.descs.push_back(d);
+                continue;
+            }
             if (orderS) {
                 // A_n(q, R) = sum_k Z_s[t][q][k] C[R][k]
                 d.a_off = site_moff[si]; d.lda = p.N1pad; d.a_tstride = (int64_t)p.N2 * p.N1pad;
@@ -601,6 +654,8 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     p.off_mid2 = take(c8 * (size_t)std::max<int64_t>(p.mid2_elems, 1));
     p.off_scratch = take(c8 * (size_t)std::max<int64_t>(p.scratch_elems, 1));
     p.off_part = take(4 * (size_t)std::max<int64_t>(p.part_elems, 1));
+    p.off_gtot = take(p.gram ? 16 * (size_t)p.N1 * p.N1 : 16);
+    p.off_qpart = take(p.gram ? 8 * (size_t)p.P * ceil_div(p.N1, 64) : 8);
     p.off_blob = take(p.blob.size() * 4);
     p.ws_bytes = off;
     if (budget > 0 && p.ws_bytes > budget) return fail(EELS_ERR_OOM, "workspace exceeds the memory budget");

@@ -18,6 +18,7 @@ FP32, BF16_SPLIT, FP16_SPLIT = 0, 1, 2
 ORDER_AUTO, ORDER_S_FIRST, ORDER_PROBE_FIRST = 0, 1, 2
 PRECISIONS = {"fp32": FP32, "bf16_split": BF16_SPLIT, "fp16_split": FP16_SPLIT}
 ORDERS = {"auto": ORDER_AUTO, "s_first": ORDER_S_FIRST, "probe_first": ORDER_PROBE_FIRST}
+DETSUMS = {"auto": 0, "direct": 1, "gram": 2}
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "band limit", 3: "unsupported size", 4: "workspace",
           5: "out of memory budget", 6: "device error", 7: "cancelled", 8: "internal"}
@@ -43,7 +44,7 @@ class ProblemC(C.Structure):
                 ("window_A", C.c_double), ("n_probes", C.c_int), ("probe_xy", C.POINTER(C.c_double)),
                 ("n_sites", C.c_int), ("sites", C.POINTER(Site)), ("n_trans_total", C.c_int64),
                 ("precision", C.c_int), ("order", C.c_int), ("max_workspace_bytes", C.c_size_t),
-                ("real_space", C.c_int), ("resident_s", C.c_int)]
+                ("real_space", C.c_int), ("resident_s", C.c_int), ("detector_sum", C.c_int)]
 
 
 class PlanInfo(C.Structure):
@@ -52,7 +53,8 @@ class PlanInfo(C.Structure):
                 ("k_stride", C.c_int), ("n_ion_slices", C.c_int), ("n_groups", C.c_int), ("n_batches", C.c_int),
                 ("order", C.c_int), ("band_basis", C.c_int), ("band_pixels", C.c_int),
                 ("lambda_A", C.c_double), ("sigma", C.c_double), ("gemm_flops", C.c_double),
-                ("sweep_bytes", C.c_double), ("sweep_beam_slices", C.c_double), ("workspace_bytes", C.c_size_t)]
+                ("sweep_bytes", C.c_double), ("sweep_beam_slices", C.c_double), ("workspace_bytes", C.c_size_t),
+                ("gram_form", C.c_int)]
 
 
 _LIB: Optional[C.CDLL] = None
@@ -122,7 +124,7 @@ class Plan:
 
     def __init__(self, problem: Any, precision: str = "fp32", order: str = "auto",
                  max_workspace_bytes: int = 0, lambda_A: float = 0.0, sigma: float = 0.0,
-                 real_space: bool = False, resident_s: bool = False):
+                 real_space: bool = False, resident_s: bool = False, detector_sum: str = "auto"):
         lib = load_library()
         pr = problem
         self._dz = np.ascontiguousarray(pr.dz, dtype=np.float64)
@@ -145,7 +147,7 @@ class Plan:
             probe_xy=self._probes.ctypes.data_as(C.POINTER(C.c_double)), n_sites=S,
             sites=self._sites, n_trans_total=n_trans, precision=PRECISIONS[precision], order=ORDERS[order],
             max_workspace_bytes=int(max_workspace_bytes), real_space=int(bool(real_space)),
-            resident_s=int(bool(resident_s)))
+            resident_s=int(bool(resident_s)), detector_sum=DETSUMS[detector_sum])
         self.precision = precision
         h = C.c_void_p()
         _check(lib.eels_plan_create(C.byref(h), C.byref(self.problem)))
@@ -221,11 +223,11 @@ def device_inputs(problem, device="cuda"):
 
 
 def solve(problem, precision: str = "fp32", order: str = "auto", device="cuda",
-          max_workspace_bytes: int = 0, real_space: bool = False) -> np.ndarray:
+          max_workspace_bytes: int = 0, real_space: bool = False, detector_sum: str = "auto") -> np.ndarray:
     """Compute one EELS map on the GPU and return it as float64 numpy [n_probes]."""
     import torch
     plan = Plan(problem, precision=precision, order=order, max_workspace_bytes=max_workspace_bytes,
-                real_space=real_space)
+                real_space=real_space, detector_sum=detector_sum)
     V, H = device_inputs(problem, device)
     ws = plan.alloc_workspace(device)
     out = torch.empty(plan.n_probes, dtype=torch.float64, device=device)
@@ -240,6 +242,7 @@ def gemm_work_bytes(m: int, n: int, k: int) -> int:
 
 TUNE_SC_STAGES = 0
 TUNE_TILE_ORDER = 1
+TUNE_SC_SCHED = 2
 
 
 def tune_set(key: int, value: int):

@@ -127,6 +127,36 @@ def test_contraction_order_choice():
     assert r["gemm_flops"] == pytest.approx(8.0 * (K * N1 * P + N2 * K * nt * P))
 
 
+def test_gram_detector_sum_plan():
+    """Gram form: chosen automatically where it is cheaper (order S, f = 1), its flop count
+    is the first product plus the Hermitian half of each site's Z^H Z plus one quadratic
+    form per probe, and it is refused where it does not apply."""
+    _lib()
+    p = synth.config1()
+    K, N1, N2, P, nt = 4096, 325, 1305, 16, 3
+    d = eels.Plan(p, order="s_first", detector_sum="direct").info()
+    g = eels.Plan(p, order="s_first", detector_sum="gram").info()
+    assert d["gram_form"] == 0 and g["gram_form"] == 1
+    Kb = g["band_pixels"]
+    g1 = 8.0 * N2 * Kb * nt * N1
+    assert d["gemm_flops"] == pytest.approx(g1 + 8.0 * nt * N2 * N1 * P)
+    assert g["gemm_flops"] == pytest.approx(g1 + 8.0 * nt * N2 * N1 * (N1 + 1) / 2 + 8.0 * N1 * N1 * P)
+    # 16 probes: the direct sum is cheaper, so auto keeps it
+    assert eels.Plan(p, order="s_first").info()["gram_form"] == 0
+    # many probes: auto switches to the Gram form
+    many = p.replace(probes=np.tile(p.probes, (64, 1)), probe_shape=(32, 32))
+    assert eels.Plan(many, order="s_first").info()["gram_form"] == 1
+    assert eels.Plan(many, order="s_first", precision="bf16_split", real_space=True).info()["gram_form"] == 1
+    for kw in (dict(order="probe_first"), dict(real_space=True)):          # FP32 real space: H in the prologue
+        with pytest.raises(eels.EelsError) as e:
+            eels.Plan(p, detector_sum="gram", **kw)
+        assert e.value.status == 1
+    f2 = synth.config3_subproblem(n=128, L=25.0, nz=3, n_scan=4, f=2)
+    with pytest.raises(eels.EelsError):
+        eels.Plan(f2, detector_sum="gram", precision="bf16_split")
+    assert eels.Plan(f2, precision="bf16_split", order="s_first").info()["gram_form"] == 0
+
+
 def test_band_table_matches_oracle_mask():
     """Band pixel count equals the oracle's circular mask count (same inclusive rule)."""
     _lib()

@@ -50,6 +50,37 @@ def test_cgemm_against_float64(prec, tol, m, n, k):
     assert np.max(np.abs(nrm - ref_n) / ref_n) < 10 * tol
 
 
+@pytest.mark.parametrize("stages", [2, 3, 4, 5])
+@pytest.mark.parametrize("order", [0, 1, 2])
+def test_cgemm_split_pipelines_agree(stages, order):
+    """Every LDS pipeline variant and tile order of the split GEMM gives the same product
+    (same accumulation order along k), and it matches FP64 within the split tolerance."""
+    eels = _need_gpu()
+    _say("cgemm pipeline", stages, order)
+    m, n, k = 300, 270, 203            # several tiles, ragged in every dimension
+    rng = np.random.default_rng(7)
+    A = (rng.standard_normal((m, k)) + 1j * rng.standard_normal((m, k))).astype(np.complex64)
+    B = (rng.standard_normal((n, k)) + 1j * rng.standard_normal((n, k))).astype(np.complex64)
+    ref = A.astype(np.complex128) @ B.astype(np.complex128).T
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    s0, o0 = eels.tune_get(eels.TUNE_SC_STAGES), eels.tune_get(eels.TUNE_TILE_ORDER)
+    try:
+        eels.tune_set(eels.TUNE_SC_STAGES, 2)
+        eels.tune_set(eels.TUNE_TILE_ORDER, 0)
+        base = eels.cgemm(dA, dB, "bf16_split").cpu().numpy()
+        base_n = eels.cgemm(dA, dB, "bf16_split", norm2=True).cpu().numpy()
+        eels.tune_set(eels.TUNE_SC_STAGES, stages)
+        eels.tune_set(eels.TUNE_TILE_ORDER, order)
+        C = eels.cgemm(dA, dB, "bf16_split").cpu().numpy()
+        nrm = eels.cgemm(dA, dB, "bf16_split", norm2=True).cpu().numpy()
+    finally:
+        eels.tune_set(eels.TUNE_SC_STAGES, s0)
+        eels.tune_set(eels.TUNE_TILE_ORDER, o0)
+    assert np.array_equal(C, base)
+    assert np.array_equal(nrm, base_n)
+    assert np.linalg.norm(C - ref) / np.linalg.norm(ref) < 3e-5
+
+
 # ------------------------------------------------------------------ sweeps
 
 def _small(seed=41, **kw):
@@ -164,6 +195,41 @@ def test_random_cases(name, order, prec, tol):
     ref = prism.prism_map(p)
     g = _map(eels, p, prec, order)
     assert metrics.rel_l2(g, ref) < tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16_split", 1e-3), ("fp16_split", 1e-3)])
+def test_gram_detector_sum(prec, tol):
+    """Gram form of the detector sum against the oracle and against the direct sum.  Config 1
+    has N_1 = 325: three 128-row tiles with a ragged last one, so the lower tiles of G come
+    from the conjugate transposes of upper ones."""
+    eels = _need_gpu()
+    p = synth.config1()
+    ref = prism.prism_map(p)
+    for real in ((False, True) if prec != "fp32" else (False,)):
+        _say("gram", prec, "real-space" if real else "band basis")
+        plan = eels.Plan(p, precision=prec, order="s_first", real_space=real, detector_sum="gram")
+        assert plan.info()["gram_form"] == 1
+        g = _map(eels, p, prec, "s_first", real_space=real, detector_sum="gram")
+        d = _map(eels, p, prec, "s_first", real_space=real, detector_sum="direct")
+        assert metrics.rel_l2(g, ref) < tol
+        assert metrics.rel_l2(g, d) < tol
+
+
+def test_gram_detector_sum_many_sites_and_batches():
+    """Several sites in several slices, cropped windows (split precision), and a memory budget
+    that splits the contraction into more batches: same map within FP64 reduction order."""
+    eels = _need_gpu()
+    p = synth.random_problem(72, n=64, L=12.0, nz=6, n_sites=6, n_trans=3, window_A=3.0, atoms_per_slice=3,
+                             aperture_mrad=18.0, det_outer_mrad=30.0)
+    ref = prism.prism_map(p)
+    full = eels.Plan(p, precision="bf16_split", detector_sum="gram")
+    ws = full.info()["workspace_bytes"]
+    small = eels.Plan(p, precision="bf16_split", detector_sum="gram", max_workspace_bytes=int(ws * 0.96))
+    assert small.info()["n_batches"] > full.info()["n_batches"] or small.info()["n_groups"] > 1
+    a = _map(eels, p, "bf16_split", detector_sum="gram")
+    b = _map(eels, p, "bf16_split", detector_sum="gram", max_workspace_bytes=int(ws * 0.96))
+    assert metrics.rel_l2(a, ref) < 1e-3
+    assert metrics.rel_l2(a, b) < 1e-10
 
 
 def test_interpolation_factor_case():
