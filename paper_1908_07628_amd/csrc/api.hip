@@ -147,7 +147,8 @@ void forward_sweep(const Plan& p, const Dev& d, int j_end, int group, int dbg_sl
     TimeScope ts(EELS_PHASE_SWEEP, st);
     launch_init_forward(d.s1, d.b1, p, st);
     for (int j = 0; j <= j_end; ++j) {
-        RowPassArgs a{d.s1, p.N1, p.ny, p.nlx, p.hlx, Tj(p, d, j), d.twx, nullptr, nullptr, d.w1, p.N1, p.Kpad, 0};
+        RowPassArgs a{d.s1, p.N1, p.ny, p.nlx, p.hlx, Tj(p, d, j), d.twx, nullptr, nullptr, d.w1, p.N1, p.Kpad, 0,
+                      p.ldx};
         if (dbg_out && j == dbg_slice) {
             a.cap_ptr = d.blob + p.dbg_ptr;
             a.cap_rec = d.blob + p.dbg_rec;
@@ -158,7 +159,7 @@ void forward_sweep(const Plan& p, const Dev& d, int j_end, int group, int dbg_sl
             a.cap_rec = d.blob + p.slices[j].cap1_rec;
         }
         launch_row_pass(p.nx, 0, a, st);
-        if (j < j_end) launch_col_pass(p.ny, 0, d.s1, p.N1, p.nlx, Pj(p, d, j), d.twy, BandCap{}, st);
+        if (j < j_end) launch_col_pass(p.ny, 0, d.s1, p.N1, p.nlx, p.ldx, Pj(p, d, j), d.twy, BandCap{}, st);
     }
 }
 
@@ -176,9 +177,10 @@ void reverse_step(const Plan& p, const Dev& d, int j, bool capture, float2* dbg_
     } else {
         BandCap bc{};
         if (band) bc = BandCap{d.band_h, d.band_off, w2j, p.Kbpad, p.w2_sc};
-        launch_col_pass(p.ny, 1, d.s2, p.N2, p.nlx, Pj(p, d, j), d.twy, bc, st);
+        launch_col_pass(p.ny, 1, d.s2, p.N2, p.nlx, p.ldx, Pj(p, d, j), d.twy, bc, st);
     }
-    RowPassArgs a{d.s2, p.N2, p.ny, p.nlx, p.hlx, Tj(p, d, j), d.twx, nullptr, nullptr, w2j, p.N2, p.Kpad, p.w2_sc};
+    RowPassArgs a{d.s2, p.N2, p.ny, p.nlx, p.hlx, Tj(p, d, j), d.twx, nullptr, nullptr, w2j, p.N2, p.Kpad, p.w2_sc,
+                  p.ldx};
     if (dbg_out) {
         a.cap_ptr = d.blob + p.dbg_ptr;
         a.cap_rec = d.blob + p.dbg_rec;
@@ -212,6 +214,7 @@ void run_jobs(const Plan& p, const Dev& d, const float2* dH, const Batch& b, int
             a.twx = d.twx; a.twy = d.twy;
             a.band_h = d.band_h; a.band_off = d.band_off;
             a.scratch = d.scratch;
+            a.ldx = p.ldx;
             a.sc = p.mid2_sc;
             launch_band_fft(p.nx, p.ny, a, st);
         } else {

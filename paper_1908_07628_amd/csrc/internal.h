@@ -100,6 +100,7 @@ struct Plan {
     // derived
     double kmax;
     int hlx, nlx;                 // live kx columns: |kx index| <= hlx, count 2*hlx+1
+    int ldx;                      // row stride of the sweep state and band scratch (nlx rounded up to 16)
     std::vector<int> ab1, ab2;    // lattice coordinates (a, b) of beams
     int N1, N2, N1fine, N1pad;
     bool full_window;

@@ -20,6 +20,7 @@ struct RowPassArgs {
     int64_t win_beams;      // beams per window (N_1 or N_2)
     int Kpad;
     int sc;                 // capture format: 0 complex64, else the split precision
+    int ldx;                // row stride of the state (live columns padded to 16)
 };
 
 // Band capture of the transposed column pass (after the P multiply): beam b's band
@@ -47,6 +48,7 @@ struct BandFft {
     const int *band_h, *band_off;
     float2* scratch;
     int sc;
+    int ldx;                // row stride of the scratch rows
 };
 
 void launch_twiddles(float2* tw, int n, hipStream_t st);
@@ -65,7 +67,7 @@ void launch_fill_zero(void* ptr, size_t bytes, hipStream_t st);
 void launch_fill_zero_d(double* p, int64_t n, hipStream_t st);
 void launch_copy(float2* dst, const float2* src, int64_t n, hipStream_t st);
 void launch_row_pass(int nx, int mode, const RowPassArgs& a, hipStream_t st);
-void launch_col_pass(int ny, int mode, float2* state, int nbeam, int nlx, const float2* Pj, const float2* tw,
+void launch_col_pass(int ny, int mode, float2* state, int nbeam, int nlx, int ldx, const float2* Pj, const float2* tw,
                      const BandCap& bc, hipStream_t st);
 void launch_reduce(double* map, int P, const int* rptr, const int* ent, const GemmDesc* descs, const float* part,
                    double scale, hipStream_t st);

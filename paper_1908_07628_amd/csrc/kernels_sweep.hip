@@ -127,8 +127,29 @@ __global__ void k_probe_coefficients(void* C, const int4* beams, int N1, int N1p
     store_c(C, i, out, sc);
 }
 
+// Live kx columns are stored in rows of ldx (nlx rounded up to 16) complex: |kx| <= hlx
+// at x for x <= hlx and at x - N + ldx for x >= N - hlx (right-aligned), so a physical
+// column is congruent to its pixel x modulo 16 and 16-column segments are 128-byte aligned.
+// Returns -1 for the dead columns.  (Without pruning, nlx = ldx = N and this is x.)
+__device__ __forceinline__ int phys_col_of(int x, int N, int hlx, int ldx) {
+    return x <= hlx ? x : (x >= N - hlx ? x - N + ldx : -1);
+}
+// physical column -> logical live column index (0 .. nlx-1), -1 in the gap or beyond ldx
+// (nlx == ldx only without pruning, where both maps are the identity; otherwise nlx is odd
+// and hlx = (nlx - 1) / 2)
+__device__ __forceinline__ int logical_of_phys(int pc, int nlx, int ldx) {
+    if (pc >= ldx) return -1;
+    if (nlx == ldx) return pc;
+    const int hlx = (nlx - 1) / 2;
+    return pc <= hlx ? pc : (pc >= ldx - hlx ? pc - (ldx - nlx) : -1);
+}
+__device__ __forceinline__ int phys_of_logical(int c, int nlx, int ldx) {
+    if (nlx == ldx) return c;
+    return c <= (nlx - 1) / 2 ? c : c + (ldx - nlx);
+}
+
 // Forward sweep start: beam b = plane wave e_k, in (kx, y): column col_b holds exp(2 pi i ky y / ny).
-__global__ void k_init_forward(float2* S, const int4* beams, int nb, int ny, int nlx) {
+__global__ void k_init_forward(float2* S, const int4* beams, int nb, int ny, int nlx, int ldx) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t total = (int64_t)nb * ny * nlx;
     if (i >= total) return;
@@ -143,11 +164,11 @@ __global__ void k_init_forward(float2* S, const int4* beams, int nb, int ny, int
         sincospi(2.0 * (double)m / (double)ny, &s, &co);
         out = make_float2((float)co, (float)s);
     }
-    S[i] = out;
+    S[((int64_t)b * ny + y) * ldx + phys_of_logical(c, nlx, ldx)] = out;
 }
 
 // Reverse sweep start: w = fft_y(P_{nz-1} e_q): column col_q holds P(q) exp(-2 pi i qy y / ny).
-__global__ void k_init_reverse(float2* S, const int4* beams, int nb, int ny, int nlx, int f, double lx, double ly,
+__global__ void k_init_reverse(float2* S, const int4* beams, int nb, int ny, int nlx, int ldx, int f, double lx, double ly,
                                double lam, double dz_last) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t total = (int64_t)nb * ny * nlx;
@@ -165,7 +186,7 @@ __global__ void k_init_reverse(float2* S, const int4* beams, int nb, int ny, int
         sincospi(ph, &s, &co);
         out = make_float2((float)co, (float)s);
     }
-    S[i] = out;
+    S[((int64_t)b * ny + y) * ldx + phys_of_logical(c, nlx, ldx)] = out;
 }
 
 __global__ void k_fill_zero(float4* p, int64_t n4) {
@@ -191,13 +212,8 @@ __global__ void k_copy(float2* dst, const float2* src, int64_t n) {
 // holds S = 256/T rows of the flat row index g = beam * ny + y.  Loads and stores go
 // straight between HBM and registers; only the middle FFT stages use LDS.
 // mode 0: forward sweep, mode 1: transposed sweep.
-__device__ __forceinline__ int live_col_of(int x, int N, int nlx, int hlx) {
-    if (nlx == N) return x;
-    return x <= hlx ? x : (x >= N - hlx ? x - N + nlx : -1);
-}
-
 template <int N, int MODE>
-__global__ __launch_bounds__(256) void k_row_pass(float2* __restrict__ state, int nbeam, int ny, int nlx, int hlx,
+__global__ __launch_bounds__(256) void k_row_pass(float2* __restrict__ state, int nbeam, int ny, int nlx, int hlx, int ldx,
                                                   const float2* __restrict__ Tj, const float2* __restrict__ tw,
                                                   const int* __restrict__ cap_ptr, const int4* __restrict__ cap_rec,
                                                   void* __restrict__ win, int64_t win_beams, int Kpad, int sc) {
@@ -212,8 +228,8 @@ __global__ __launch_bounds__(256) void k_row_pass(float2* __restrict__ state, in
     float2 v[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-        int c = live_col_of(t + T * m, N, nlx, hlx);
-        v[m] = (valid && c >= 0) ? state[g * nlx + c] : make_float2(0.f, 0.f);
+        int c = phys_col_of(t + T * m, N, hlx, ldx);
+        v[m] = (valid && c >= 0) ? state[g * ldx + c] : make_float2(0.f, 0.f);
     }
     fft_reg<N, MODE == 0 ? +1 : -1>(v, lds, s * N, 1, t, tw);
 
@@ -241,8 +257,8 @@ __global__ __launch_bounds__(256) void k_row_pass(float2* __restrict__ state, in
     fft_reg<N, MODE == 0 ? -1 : +1>(v, lds, s * N, 1, t, tw);
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-        int c = live_col_of(t + T * m, N, nlx, hlx);
-        if (valid && c >= 0) state[g * nlx + c] = v[m];
+        int c = phys_col_of(t + T * m, N, hlx, ldx);
+        if (valid && c >= 0) state[g * ldx + c] = v[m];
     }
 }
 
@@ -260,7 +276,7 @@ struct ColCfg {
 };
 
 template <int N, int MODE>
-__global__ __launch_bounds__(ColCfg<N>::NT) void k_col_pass(float2* __restrict__ state, int nbeam, int nlx,
+__global__ __launch_bounds__(ColCfg<N>::NT) void k_col_pass(float2* __restrict__ state, int nbeam, int nlx, int ldx,
                                                             const float2* __restrict__ Pj,
                                                             const float2* __restrict__ tw,
                                                             const int* __restrict__ band_h,
@@ -270,16 +286,17 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_col_pass(float2* __restrict__
     constexpr int CW = C::CW, T = C::T, E = C::E;
     __shared__ float2 lds[N * CW];
     const int tid = threadIdx.x;
-    const int strips = (nlx + CW - 1) / CW;
+    const int strips = (ldx + CW - 1) / CW;
     const int64_t beam = blockIdx.x / strips;
     const int c0 = (int)(blockIdx.x % strips) * CW;
     const int col = tid % CW, t = tid / CW;
-    const int c = c0 + col;
-    const bool live = c < nlx;
-    float2* plane = state + beam * (int64_t)N * nlx;
+    const int pc = c0 + col;                                     // physical column (state)
+    const int c = logical_of_phys(pc, nlx, ldx);  // live column (P, band tables)
+    const bool live = c >= 0;
+    float2* plane = state + beam * (int64_t)N * ldx;
     float2 v[E];
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = live ? plane[(int64_t)(t + T * m) * nlx + c] : make_float2(0.f, 0.f);
+    for (int m = 0; m < E; ++m) v[m] = live ? plane[(int64_t)(t + T * m) * ldx + pc] : make_float2(0.f, 0.f);
     fft_reg<N, MODE == 0 ? -1 : +1>(v, lds, col, CW, t, tw);
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = cmul(v[m], live ? Pj[(int64_t)(t + T * m) * nlx + c] : make_float2(0.f, 0.f));
@@ -297,7 +314,7 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_col_pass(float2* __restrict__
     fft_reg<N, MODE == 0 ? +1 : -1>(v, lds, col, CW, t, tw);
     if (live) {
 #pragma unroll
-        for (int m = 0; m < E; ++m) plane[(int64_t)(t + T * m) * nlx + c] = v[m];
+        for (int m = 0; m < E; ++m) plane[(int64_t)(t + T * m) * ldx + pc] = v[m];
     }
 }
 
@@ -322,36 +339,51 @@ __global__ void k_init_band(void* bcap, int64_t bstride, int Kb, const int4* bea
     store_c(bcap, i, v, sc);
 }
 
-// Band FFT, row stage: rows y of T_j * H_t * W_i (real space, planes of `wstride`
-// complex) -> FFT_x -> live columns into scratch [(t Ni + i) ny + y][nlx].
+// Band FFT, row stage: rows y of T_j * W_i (real space, planes of `wstride` complex) times
+// each transition potential H_t -> FFT_x -> live columns into scratch [(t Ni + i) ny + y][nlx].
+// A thread group loads its row of W_i and T_j once and loops over the nt transitions (their
+// H rows stay in L2), so the S_1 window is read once per site instead of once per transition.
 template <int N>
 __global__ __launch_bounds__(256) void k_band_rows(float2* __restrict__ out, const float2* __restrict__ W,
-                                                   int64_t wstride, int Ni, int nt, int ny, int nlx, int hlx,
+                                                   int64_t wstride, int Ni, int nt, int ny, int nlx, int hlx, int ldx,
                                                    const float2* __restrict__ Tj, const float2* __restrict__ Hb,
                                                    int64_t hstride, const float2* __restrict__ tw) {
     constexpr int E = RegCfg<N>::E, T = RegCfg<N>::T, S = 256 / T;
     __shared__ float2 lds[S * N];
     const int tid = threadIdx.x, s = tid / T, t = tid % T;
-    const int64_t total = (int64_t)nt * Ni * ny;
+    const int64_t rows = (int64_t)Ni * ny;
     const int64_t g = (int64_t)blockIdx.x * S + s;
-    const bool valid = g < total;
+    const bool valid = g < rows;
     const int y = valid ? (int)(g % ny) : 0;
-    const int64_t pi = valid ? g / ny : 0;
-    const int i = (int)(pi % Ni), tt = (int)(pi / Ni);
+    const int i = valid ? (int)(g / ny) : 0;
     const float2* wr = W + i * wstride + (int64_t)y * N;
-    const float2* hr = Hb + tt * hstride + (int64_t)y * N;
     const float2* trow = Tj + (int64_t)y * N;
-    float2 v[E];
+    float2 u[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         int x = t + T * m;
-        v[m] = valid ? cmul(cmul(wr[x], hr[x]), trow[x]) : make_float2(0.f, 0.f);
+        u[m] = valid ? cmul(wr[x], trow[x]) : make_float2(0.f, 0.f);
     }
-    fft_reg<N, -1>(v, lds, s * N, 1, t, tw);
+    // the next transition's H row is loaded while this one is transformed
+    float2 h[E];
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-        int c = live_col_of(t + T * m, N, nlx, hlx);
-        if (valid && c >= 0) out[g * nlx + c] = v[m];
+    for (int m = 0; m < E; ++m) h[m] = valid ? Hb[(int64_t)y * N + t + T * m] : make_float2(0.f, 0.f);
+    for (int tt = 0; tt < nt; ++tt) {
+        float2 v[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = cmul(u[m], h[m]);
+        if (tt + 1 < nt) {
+            const float2* hr = Hb + (tt + 1) * hstride + (int64_t)y * N;
+#pragma unroll
+            for (int m = 0; m < E; ++m) h[m] = valid ? hr[t + T * m] : make_float2(0.f, 0.f);
+        }
+        fft_reg<N, -1>(v, lds, s * N, 1, t, tw);
+        const int64_t o = (((int64_t)tt * Ni + i) * ny + y) * ldx;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            int c = phys_col_of(t + T * m, N, hlx, ldx);
+            if (valid && c >= 0) out[o + c] = v[m];
+        }
     }
 }
 
@@ -359,7 +391,7 @@ __global__ __launch_bounds__(256) void k_band_rows(float2* __restrict__ out, con
 // dst[plane * dstride + g] (SC or complex64); the padding slots Kb .. dstride-1 are zeroed.
 template <int N>
 __global__ __launch_bounds__(ColCfg<N>::NT) void k_band_cols(void* __restrict__ dst, int64_t dstride, int Kb,
-                                                             const float2* __restrict__ src, int nlx,
+                                                             const float2* __restrict__ src, int nlx, int ldx,
                                                              const int* __restrict__ band_h,
                                                              const int* __restrict__ band_off,
                                                              const float2* __restrict__ tw, int sc) {
@@ -367,16 +399,17 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_band_cols(void* __restrict__ 
     constexpr int CW = C::CW, T = C::T, E = C::E, NT = C::NT;
     __shared__ float2 lds[N * CW];
     const int tid = threadIdx.x;
-    const int strips = (nlx + CW - 1) / CW;
+    const int strips = (ldx + CW - 1) / CW;
     const int64_t plane = blockIdx.x / strips;
     const int strip = (int)(blockIdx.x % strips);
     const int col = tid % CW, t = tid / CW;
-    const int c = strip * CW + col;
-    const bool live = c < nlx;
-    const float2* sp = src + plane * (int64_t)N * nlx;
+    const int pc = strip * CW + col;
+    const int c = logical_of_phys(pc, nlx, ldx);
+    const bool live = c >= 0;
+    const float2* sp = src + plane * (int64_t)N * ldx;
     float2 v[E];
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = live ? sp[(int64_t)(t + T * m) * nlx + c] : make_float2(0.f, 0.f);
+    for (int m = 0; m < E; ++m) v[m] = live ? sp[(int64_t)(t + T * m) * ldx + pc] : make_float2(0.f, 0.f);
     fft_reg<N, -1>(v, lds, col, CW, t, tw);
     if (live) {
         const int h = band_h[c];
@@ -464,11 +497,11 @@ void launch_probe_coefficients(void* C, const int4* beams, const double* probes,
 }
 void launch_init_forward(float2* S, const int4* beams, const Plan& p, hipStream_t st) {
     int64_t n = (int64_t)p.N1 * p.ny * p.nlx;
-    hipLaunchKernelGGL(k_init_forward, dim3(blocks_for(n, 256)), dim3(256), 0, st, S, beams, p.N1, p.ny, p.nlx);
+    hipLaunchKernelGGL(k_init_forward, dim3(blocks_for(n, 256)), dim3(256), 0, st, S, beams, p.N1, p.ny, p.nlx, p.ldx);
 }
 void launch_init_reverse(float2* S, const int4* beams, const Plan& p, hipStream_t st) {
     int64_t n = (int64_t)p.N2 * p.ny * p.nlx;
-    hipLaunchKernelGGL(k_init_reverse, dim3(blocks_for(n, 256)), dim3(256), 0, st, S, beams, p.N2, p.ny, p.nlx, p.f,
+    hipLaunchKernelGGL(k_init_reverse, dim3(blocks_for(n, 256)), dim3(256), 0, st, S, beams, p.N2, p.ny, p.nlx, p.ldx, p.f,
                        p.lx, p.ly, p.lam, p.dz[p.nz - 1]);
 }
 void launch_fill_zero(void* ptr, size_t bytes, hipStream_t st) {
@@ -489,7 +522,8 @@ static void row_pass_n(const RowPassArgs& a, hipStream_t st) {
     constexpr int S = 256 / RegCfg<N>::T;
     int64_t rows = (int64_t)a.nbeam * a.ny;
     hipLaunchKernelGGL((k_row_pass<N, MODE>), dim3(blocks_for(rows, S)), dim3(256), 0, st, a.state, a.nbeam, a.ny,
-                       a.nlx, a.hlx, a.Tj, a.tw, a.cap_ptr, (const int4*)a.cap_rec, a.win, a.win_beams, a.Kpad, a.sc);
+                       a.nlx, a.hlx, a.ldx, a.Tj, a.tw, a.cap_ptr, (const int4*)a.cap_rec, a.win, a.win_beams, a.Kpad,
+                       a.sc);
 }
 
 void launch_row_pass(int nx, int mode, const RowPassArgs& a, hipStream_t st) {
@@ -506,20 +540,20 @@ void launch_row_pass(int nx, int mode, const RowPassArgs& a, hipStream_t st) {
 }
 
 template <int N, int MODE>
-static void col_pass_n(float2* state, int nbeam, int nlx, const float2* Pj, const float2* tw, const BandCap& bc,
+static void col_pass_n(float2* state, int nbeam, int nlx, int ldx, const float2* Pj, const float2* tw, const BandCap& bc,
                        hipStream_t st) {
     using C = ColCfg<N>;
-    int strips = (nlx + C::CW - 1) / C::CW;
+    int strips = (ldx + C::CW - 1) / C::CW;
     hipLaunchKernelGGL((k_col_pass<N, MODE>), dim3((unsigned)((int64_t)nbeam * strips)), dim3(C::NT), 0, st, state,
-                       nbeam, nlx, Pj, tw, bc.band_h, bc.band_off, bc.dst, bc.stride, bc.sc);
+                       nbeam, nlx, ldx, Pj, tw, bc.band_h, bc.band_off, bc.dst, bc.stride, bc.sc);
 }
 
-void launch_col_pass(int ny, int mode, float2* state, int nbeam, int nlx, const float2* Pj, const float2* tw,
+void launch_col_pass(int ny, int mode, float2* state, int nbeam, int nlx, int ldx, const float2* Pj, const float2* tw,
                      const BandCap& bc, hipStream_t st) {
 #define COLCASE(NN)                                                   \
     case NN:                                                          \
-        if (mode == 0) col_pass_n<NN, 0>(state, nbeam, nlx, Pj, tw, bc, st); \
-        else col_pass_n<NN, 1>(state, nbeam, nlx, Pj, tw, bc, st);    \
+        if (mode == 0) col_pass_n<NN, 0>(state, nbeam, nlx, ldx, Pj, tw, bc, st); \
+        else col_pass_n<NN, 1>(state, nbeam, nlx, ldx, Pj, tw, bc, st);    \
         break;
     switch (ny) {
         COLCASE(16) COLCASE(32) COLCASE(64) COLCASE(128) COLCASE(256) COLCASE(512) COLCASE(1024)
@@ -538,13 +572,13 @@ void launch_init_band(void* bcap, int64_t bstride, const int4* beams, const int*
 template <int NX, int NY>
 static void band_fft_n(const BandFft& a, hipStream_t st) {
     constexpr int S = 256 / RegCfg<NX>::T;
-    int64_t rows = (int64_t)a.nt * a.Ni * a.ny;
+    int64_t rows = (int64_t)a.Ni * a.ny;
     hipLaunchKernelGGL((k_band_rows<NX>), dim3(blocks_for(rows, S)), dim3(256), 0, st, a.scratch, a.W, a.wstride,
-                       a.Ni, a.nt, a.ny, a.nlx, a.hlx, a.Tj, a.H, a.hstride, a.twx);
+                       a.Ni, a.nt, a.ny, a.nlx, a.hlx, a.ldx, a.Tj, a.H, a.hstride, a.twx);
     using C = ColCfg<NY>;
-    int strips = (a.nlx + C::CW - 1) / C::CW;
+    int strips = (a.ldx + C::CW - 1) / C::CW;
     hipLaunchKernelGGL((k_band_cols<NY>), dim3((unsigned)((int64_t)a.nt * a.Ni * strips)), dim3(C::NT), 0, st, a.dst,
-                       a.dstride, a.Kb, a.scratch, a.nlx, a.band_h, a.band_off, a.twy, a.sc);
+                       a.dstride, a.Kb, a.scratch, a.nlx, a.ldx, a.band_h, a.band_off, a.twy, a.sc);
 }
 
 void launch_band_fft(int nx, int ny, const BandFft& a, hipStream_t st) {

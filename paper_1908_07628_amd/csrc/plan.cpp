@@ -108,6 +108,7 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     p.hlx = (int)std::floor(p.kmax * p.lx + 1e-9);
     if (2 * p.hlx + 1 >= p.nx) { p.hlx = p.nx / 2; p.nlx = p.nx; }
     else p.nlx = 2 * p.hlx + 1;
+    p.ldx = (int)round_up(p.nlx, 16);   // 128-byte aligned rows of live columns
 
     // beams
     p.ab1 = lattice(p.lx, p.ly, p.f, p.lam, 0.0, p.alpha);
@@ -277,7 +278,7 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     if (p.recip)
         for (int j : ion)
             for (int s : by_slice[j])
-                scratch = std::max(scratch, (int64_t)p.sites[s].n_trans * site_ni(s) * p.ny * p.nlx);
+                scratch = std::max(scratch, (int64_t)p.sites[s].n_trans * site_ni(s) * p.ny * p.ldx);
     p.scratch_elems = scratch;
 
     // fixed workspace
@@ -286,7 +287,7 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     size_t fixed = A(blob_reserve)  // table blob (refined by the caller's second pass)
                    + A(c8 * p.nx) + A(c8 * p.ny) + A(c8 * (size_t)p.nz * p.ny * p.nx) +
                    A(c8 * (size_t)p.nz * p.ny * p.nlx) + A(c8 * (size_t)p.P * p.N1pad) +
-                   A(c8 * (size_t)p.N1 * p.ny * p.nlx) + A(c8 * (size_t)p.N2 * p.ny * p.nlx) +
+                   A(c8 * (size_t)p.N1 * p.ny * p.ldx) + A(c8 * (size_t)p.N2 * p.ny * p.ldx) +
                    A(c8 * (size_t)w2_elems) + A(c8 * (size_t)scratch) +
                    (p.gram ? A(16 * (size_t)p.N1 * p.N1) + A(8 * (size_t)p.P * ceil_div(p.N1, 64)) : 0);
 
@@ -645,8 +646,8 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     p.off_twy = take(c8 * p.ny);
     p.off_T = take(c8 * (size_t)p.nz * p.ny * p.nx);
     p.off_P = take(c8 * (size_t)p.nz * p.ny * p.nlx);
-    p.off_s1 = take(c8 * (size_t)p.N1 * p.ny * p.nlx);
-    p.off_s2 = take(c8 * (size_t)p.N2 * p.ny * p.nlx);
+    p.off_s1 = take(c8 * (size_t)p.N1 * p.ny * p.ldx);
+    p.off_s2 = take(c8 * (size_t)p.N2 * p.ny * p.ldx);
     p.off_w1 = take(c8 * (size_t)std::max(p.max_w1, 1) * p.N1 * p.Kpad);
     p.off_w2 = take(c8 * (size_t)std::max<int64_t>(w2_elems, 1));
     p.off_C = take(c8 * (size_t)p.P * p.N1pad);
