@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 METRIC = "EELS map probe-px/s (FP32 plain vs BF16-split @1e-3 err); p50/p99 latency"
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBPS = 8000.0
 WORKLOAD = ("perovskite crystal 256x256 px over 20x20 A, 50 slices x 2 A, 650 ionised B sites x 9 "
             "transitions (full-cell contraction), 64x64 probes, 300 keV, 21 mrad aperture, 0-50 mrad "
             "detector")
@@ -76,6 +77,52 @@ def cpu_baseline(p, budget_s=25.0):
         "seconds_measured": round(dt, 2),
         "host_cpus": os.cpu_count(),
     }
+
+
+def profile_sample(args):
+    """Workload for hardware-counter runs: a plain 1 GiB device-to-device copy (known bytes,
+    to calibrate FETCH_SIZE / WRITE_SIZE) and one map on the sites of the top N ionised
+    slices of the crystal workload, whose contraction launches have the full map's shapes."""
+    import torch
+    import synth
+    from paper_1908_07628_amd import eels
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    p = synth.config2()
+    ion = sorted(set(p.site_slice.tolist()))
+    q = subset_sites(p, np.nonzero(np.isin(p.site_slice, ion[-args.profile_sample:]))[0])
+    V, H = eels.device_inputs(q)
+    plan = eels.Plan(q, precision=args.precision)
+    ws = plan.alloc_workspace()
+    out = torch.empty(q.n_probes, dtype=torch.float64, device="cuda")
+    plan.execute(V, H, out, ws)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_sample": args.profile_sample, "sites": int(q.n_sites),
+                      "copy_bytes": 2 * a.numel() * 4}), flush=True)
+
+
+def gemm_traffic():
+    """HBM bytes per launch of the first contraction GEMM from the committed counter summary,
+    if it was taken with the current GEMM source (else None)."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_1908_07628_amd", "csrc", "kernels_gemm.hip")
+    summ = os.path.join(ROOT, "profiles", "k_cgemm_sc__config2_traffic_pmc.md")
+    if not os.path.exists(summ):
+        return None
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    vals = {}
+    for line in open(summ):
+        if ":" in line and line.lstrip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernels_gemm.hip sha256") != digest:
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def bench_batch(args):
@@ -185,6 +232,9 @@ def main():
     ap.add_argument("--workload", default="crystal", choices=["crystal", "batch", "serve"],
                     help="crystal: the benchmark map (default); batch: 64 uneven specimens in one graph; "
                          "serve: Poisson request stream with p50/p99 latency")
+    ap.add_argument("--profile-sample", type=int, default=0, metavar="N",
+                    help="for counter runs: a 1 GiB device copy (calibration), then one map on the "
+                         "top N ionised slices; prints one line")
     ap.add_argument("--n-specimens", type=int, default=64)
     ap.add_argument("--pool", type=int, default=10)
     ap.add_argument("--n-requests", type=int, default=40)
@@ -204,6 +254,10 @@ def main():
     import torch
     import synth
     from paper_1908_07628_amd import eels
+
+    if args.profile_sample > 0:
+        profile_sample(args)
+        return
 
     t0 = time.time()
     p = synth.config2()
@@ -266,13 +320,39 @@ def main():
     roofline = {
         "bound": "mfma", "kernel": "k_cgemm_sc (first contraction GEMM)" if split else "k_cgemm",
         "achieved": round(achieved, 1), "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-        "traffic": None, "avg_launch_ms": round(avg_ms, 3), "launches_per_step": n_launch_per_step,
+        "traffic": gemm_traffic() if split else None, "avg_launch_ms": round(avg_ms, 3),
+        "launches_per_step": n_launch_per_step,
         "algorithmic_flops_per_launch": exec_factor * per_launch,
         "useful_complex_tflops": round(per_launch / (avg_ms * 1e-3) / 1e12, 1),
         "flop_definition": ("3 BF16 MFMA products per complex multiply-add of the split algorithm, "
                             "8 real flops each; useful = 8 M N K complex" if split else "8 M N K"),
     }
     phases = {k: round(v["ms"] / args.steps, 2) for k, v in phase_tot.items()}
+
+    # HBM rooflines of the FFT passes: both sweeps (row + column passes with their window
+    # and band captures) and the producer (band FFT of T H S_1 per site and transition)
+    n_ion = info["n_ion_slices"]
+    kwin = info["k_pixels"]
+    cap_bytes = 8.0 * n_ion * (info["n_beams_in"] * kwin + info["n_beams_out"] * info["band_pixels"])
+    sweep_bytes = info["sweep_bytes"] + cap_bytes
+    sweep_s = phases["sweep"] * 1e-3
+    nt_tot = float(np.sum(p.site_ntrans))
+    prod_bytes = 8.0 * ((p.n_sites * info["n_beams_in"] + nt_tot) * kwin
+                        + nt_tot * info["n_beams_in"] * info["band_pixels"])
+    prod_s = phases["producer"] * 1e-3
+    roofline_fft = {
+        "sweeps": {"bound": "hbm", "kernels": "k_row_pass + k_col_pass (with S_1 window and S_2 band captures)",
+                   "achieved": round(sweep_bytes / sweep_s / 1e9, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                   "frac": round(sweep_bytes / sweep_s / 1e9 / PEAK_HBM_GBPS, 4), "traffic": None,
+                   "algorithmic_bytes_per_step": sweep_bytes,
+                   "byte_definition": "32 B x n_y x n_live_x per beam-slice (2 passes, read + write) + captures"},
+        "producer": {"bound": "hbm", "kernels": "k_band_rows + k_band_cols",
+                     "achieved": round(prod_bytes / prod_s / 1e9, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": round(prod_bytes / prod_s / 1e9 / PEAK_HBM_GBPS, 4), "traffic": None,
+                     "algorithmic_bytes_per_step": prod_bytes,
+                     "byte_definition": ("read S_1 windows and H once per site, write the band-basis operand; "
+                                         "the row-to-column scratch round trip is not counted")},
+    }
 
     # FP32 plain path
     if args.fp32_full:
@@ -325,6 +405,7 @@ def main():
                    "precision": args.precision + " (hi+lo products, FP32 accumulate, FP64 map)"
                    if args.precision != "fp32" else "fp32", "contraction": "band basis, order S"},
         "roofline": roofline,
+        "roofline_fft": roofline_fft,
         "phases_ms": phases,
         "fp32": fp32,
         "split_over_fp32": round(value / fp32["value"], 2),
