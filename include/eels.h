@@ -106,7 +106,19 @@ typedef struct {
                                 (needs one slice group), so that a later eels_execute_ex with
                                 EELS_EXEC_SKIP_SWEEPS can reuse the S-matrices              */
     int detector_sum;        /* EELS_DETSUM_*: how sum_{n,q} |A_n(q,R)|^2 is formed (order S)  */
+    int n_images;            /* elastic companion images (0 .. EELS_MAX_IMAGES), interp_f = 1  */
+    const double* image_detectors_mrad;  /* [n_images][2] inner, outer semi-angle (inclusive);
+                                outer <= 0 means the band limit                              */
 } eels_problem;
+
+/* Elastic companion images (the incoherent bright-field and annular dark-field images shown
+ * beside the EELS map in the Results' nanoparticle discussion, which also divides the EELS
+ * map by the iBF image with the EELS detector's angles).  Image d is
+ *     I_d(R) = sum_{q in D_d} |psi_exit(q, R)|^2,  psi_exit(., R) = sum_k c_k(R) S_1^exit[k],
+ * the elastic exit wave of probe R on the pixels of the ring D_d, as a fraction of the
+ * incident beam.  With interp_f = 1 it equals c(R)^H G_d c(R), G_d = S_d^H S_d over the
+ * ring's pixels, which is how it is computed (FP32 Gram GEMM, FP64 quadratic form). */
+enum { EELS_MAX_IMAGES = 8 };
 
 /* Detector sum of the S-first order.  DIRECT: A_n(q, R) = sum_k Z_n(q, k) c_k(R) by a second
  * GEMM per transition with |.|^2 summed over q in its epilogue.  GRAM: with every probe
@@ -186,6 +198,14 @@ eels_status eels_execute_ex(const eels_plan* p, const float* d_V, const void* d_
  * slices, optics, beam lattices, windows, sites, storage format and the workspace
  * offsets of the S data), but not of the probes.  Equal signatures (with equal V and H)
  * mean the S data of one plan's execute serve the other. */
+/* As eels_execute_ex, and also writes the plan's elastic companion images:
+ * d_images float64 [n_images][n_probes], overwritten (may be null when n_images = 0).  The
+ * forward sweep then continues to the exit plane and captures the exit wave's band
+ * coefficients.  With EELS_EXEC_SKIP_SWEEPS the forward sweep is rerun for the images (the
+ * S_2 data stay resident).  Errors as eels_execute_ex. */
+eels_status eels_execute_images(const eels_plan* p, const float* d_V, const void* d_H, double* d_map, double* d_images,
+                                void* d_workspace, size_t workspace_bytes, void* stream, unsigned flags);
+
 eels_status eels_plan_s_signature(const eels_plan* p, uint64_t* sig);
 
 /* Diagnostics (same workspace contract).  Write the real-space rows of S_1(j)
@@ -235,7 +255,8 @@ enum {
     EELS_PHASE_GEMM1 = 3,     /* first contraction GEMM of each batch                      */
     EELS_PHASE_GEMM2 = 4,     /* second GEMM (detector |.|^2 epilogue)                     */
     EELS_PHASE_REDUCE = 5,    /* FP64 per-probe reduction                                  */
-    EELS_PHASES = 6
+    EELS_PHASE_IMAGES = 6,    /* elastic companion images (exit capture excluded)          */
+    EELS_PHASES = 7
 };
 eels_status eels_timing_enable(int capacity);
 eels_status eels_timing_read(double* ms, int* counts);

@@ -82,6 +82,8 @@ struct Dev {
     float* part;
     double* gtot;     // Gram form: sum of Z^H Z, FP64 complex [N_1][N_1]
     double* qpart;    // Gram form: per-probe partial quadratic forms
+    float2 *img_exit, *img_masked, *img_part, *img_C;   // companion images
+    double *img_G, *img_qpart;
 };
 
 Dev make_dev(const Plan& p, void* ws_) {
@@ -110,6 +112,12 @@ Dev make_dev(const Plan& p, void* ws_) {
     d.part = (float*)(d.ws + p.off_part);
     d.gtot = (double*)(d.ws + p.off_gtot);
     d.qpart = (double*)(d.ws + p.off_qpart);
+    d.img_exit = (float2*)(d.ws + p.off_img_exit);
+    d.img_masked = (float2*)(d.ws + p.off_img_masked);
+    d.img_part = (float2*)(d.ws + p.off_img_part);
+    d.img_C = (float2*)(d.ws + p.off_img_C);
+    d.img_G = (double*)(d.ws + p.off_img_G);
+    d.img_qpart = (double*)(d.ws + p.off_img_qpart);
     return d;
 }
 
@@ -141,9 +149,11 @@ const float2* Pj(const Plan& p, const Dev& d, int j) { return d.P + (int64_t)j *
 
 // Forward sweep of S_1 through slices 0..j_end (row pass of j_end included, its column
 // pass not).  Captures the windows of the ionised slices of `group` (if >= 0), or the
-// full real-space S_1(dbg_slice) into dbg_out.
+// full real-space S_1(dbg_slice) into dbg_out.  With exit_cap (j_end = n_z - 1) the last
+// column pass also runs and captures the band coefficients of the exit wave
+// P_{nz-1} fft2(T_{nz-1} psi) of every beam into exit_cap [N_1][Kb pad].
 void forward_sweep(const Plan& p, const Dev& d, int j_end, int group, int dbg_slice, float2* dbg_out,
-                   hipStream_t st) {
+                   hipStream_t st, float2* exit_cap = nullptr) {
     TimeScope ts(EELS_PHASE_SWEEP, st);
     launch_init_forward(d.s1, d.b1, p, st);
     for (int j = 0; j <= j_end; ++j) {
@@ -160,6 +170,9 @@ void forward_sweep(const Plan& p, const Dev& d, int j_end, int group, int dbg_sl
         }
         launch_row_pass(p.nx, 0, a, st);
         if (j < j_end) launch_col_pass(p.ny, 0, d.s1, p.N1, p.nlx, p.ldx, Pj(p, d, j), d.twy, BandCap{}, st);
+        else if (exit_cap)
+            launch_col_pass(p.ny, 0, d.s1, p.N1, p.nlx, p.ldx, Pj(p, d, j), d.twy,
+                            BandCap{d.band_h, d.band_off, exit_cap, p.Kbpad, 0}, st);
     }
 }
 
@@ -299,6 +312,26 @@ void contract(const Plan& p, const Dev& d, const float2* dH, double* map, int bi
     else launch_reduce(map, p.P, d.blob + b.red_ptr, d.blob + b.red_ent, dd, d.part, scale, st);
 }
 
+// Companion images from the exit-wave band coefficients in img_exit: for each ring d,
+// X = the coefficients masked to the ring, G_d = X^H X (FP32 Gram tiles, FP64 sum) and
+// I_d(R) = c(R)^H G_d c(R) / c_scale^2 (interp_f = 1).
+void companion_images(const Plan& p, const Dev& d, double* images, hipStream_t st) {
+    TimeScope ts(EELS_PHASE_IMAGES, st);
+    launch_probe_coefficients(d.img_C, d.b1, d.probes, p, 0, st);
+    const GemmDesc* dd = d.descs + p.img_desc;
+    const int tiles = (int)(ceil_div(p.N1, GEMM_BM) * ceil_div(p.N1, GEMM_BN));
+    const double scale = 1.0 / ((double)p.c_scale * p.c_scale);
+    for (int k = 0; k < p.n_img; ++k) {
+        launch_mask_band(d.img_masked, d.img_exit, p.N1, p.Kbpad, d.blob + p.img_mask_off, 1 << k, st);
+        launch_cgemm(EELS_FP32, 0, 2, dd, 1, tiles, d.img_masked, d.img_masked, nullptr, nullptr, (float*)d.img_part,
+                     d.blob, st);
+        launch_fill_zero_d(d.img_G, 2 * (int64_t)p.N1 * p.N1, st);
+        launch_gram_reduce(d.img_G, d.img_part, 1, 0, p.N1, p.N1pad, st);
+        launch_fill_zero_d(images + (int64_t)k * p.P, p.P, st);
+        launch_quadform(images + (int64_t)k * p.P, p.P, d.img_G, p.N1, d.img_C, p.N1pad, d.img_qpart, scale, st);
+    }
+}
+
 // Gram form: I(R) = scale * c(R)^H G c(R) once every batch has added its Z^H Z to G.
 void finish_map(const Plan& p, const Dev& d, double* map, hipStream_t st) {
     if (!p.gram) return;
@@ -417,6 +450,12 @@ eels_status eels_execute(const eels_plan* pl, const float* d_V, const void* d_H,
 
 eels_status eels_execute_ex(const eels_plan* pl, const float* d_V, const void* d_H, double* d_map, void* d_workspace,
                             size_t workspace_bytes, void* stream, unsigned flags) {
+    return eels_execute_images(pl, d_V, d_H, d_map, nullptr, d_workspace, workspace_bytes, stream, flags);
+}
+
+eels_status eels_execute_images(const eels_plan* pl, const float* d_V, const void* d_H, double* d_map,
+                                double* d_images, void* d_workspace, size_t workspace_bytes, void* stream,
+                                unsigned flags) {
     if (!pl || !d_V || !d_map) {
         set_error("null argument");
         return EELS_ERR_INVALID_ARG;
@@ -444,6 +483,12 @@ eels_status eels_execute_ex(const eels_plan* pl, const float* d_V, const void* d
     launch_probe_coefficients(d.C, d.b1, d.probes, p, p.c_sc, st);
     launch_fill_zero_d(d_map, p.P, st);
     if (p.gram) launch_fill_zero_d(d.gtot, 2 * (int64_t)p.N1 * p.N1, st);
+    const bool images = d_images && p.n_img > 0;
+    if (images && (skip_sweeps || p.groups.empty())) {
+        // no forward sweep runs below (resident S-matrices, or no sites): sweep for the images
+        forward_sweep(p, d, p.nz - 1, -1, -1, nullptr, st, d.img_exit);
+        companion_images(p, d, d_images, st);
+    }
     if (skip_sweeps) {
         // the S_1 windows and every slice's S_2 capture are already in the workspace
         for (int j = p.nz - 1; j >= 0; --j)
@@ -458,7 +503,10 @@ eels_status eels_execute_ex(const eels_plan* pl, const float* d_V, const void* d
     int rev_next = p.nz - 1;
     for (int gi = 0; gi < (int)p.groups.size(); ++gi) {
         const Group& g = p.groups[gi];
-        forward_sweep(p, d, g.j_hi, gi, -1, nullptr, st);
+        // the first (highest) group's forward sweep continues to the exit for the images
+        const bool exit_here = images && gi == 0;
+        forward_sweep(p, d, exit_here ? p.nz - 1 : g.j_hi, gi, -1, nullptr, st, exit_here ? d.img_exit : nullptr);
+        if (exit_here) companion_images(p, d, d_images, st);
         for (int j = rev_next; j >= g.j_lo; --j) {
             reverse_step(p, d, j, p.slices[j].ion, nullptr, st);
             if (p.slices[j].ion)

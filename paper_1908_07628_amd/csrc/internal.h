@@ -112,6 +112,10 @@ struct Plan {
     int Kb, Kbpad;                              // band pixels, padded stride
     int c_sc, w2_sc, mid2_sc;                   // storage formats (0 complex64, else split precision)
     bool gram;                                  // detector sum in the Gram form (order S, f = 1)
+    int n_img = 0;                              // elastic companion images
+    std::vector<double> img_in, img_out;        // their ring angles (rad; out < 0: band limit)
+    int img_desc = -1;                          // descriptor of the images' Gram GEMM
+    int64_t img_mask_off = -1;                  // int offset: per band slot, bit d = inside ring d
     int N2p;                                    // N_2 rounded up to 16 (row blocks of Z^T)
     std::vector<int> site_w1, site_w2;          // window index of each site (S_1 group-local, S_2 slice-local)
     std::vector<int> site_ix0, site_iy0;
@@ -137,7 +141,8 @@ struct Plan {
 
     // workspace layout (byte offsets)
     size_t off_blob, off_twx, off_twy, off_T, off_P, off_C, off_s1, off_s2, off_w1, off_w2,
-        off_mid, off_mid2, off_scratch, off_part, off_gtot, off_qpart, ws_bytes;
+        off_mid, off_mid2, off_scratch, off_part, off_gtot, off_qpart, off_img_exit, off_img_masked, off_img_part,
+        off_img_G, off_img_qpart, off_img_C, ws_bytes;
 };
 
 eels_status build_plan(Plan& p, const eels_problem& prob);

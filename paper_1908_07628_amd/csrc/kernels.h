@@ -96,6 +96,8 @@ void launch_from_sc(float2* dst, const void* src, int64_t n, int prec, hipStream
 // part_stride apart; only their upper tiles are read).
 void launch_gram_reduce(double* G, const float2* part, int nparts, int64_t part_stride, int n1, int ldp,
                         hipStream_t st);
+// dst[b][g] = src[b][g] where mask[g] has `bit`, else 0 (rows of ld complex, n_rows rows).
+void launch_mask_band(float2* dst, const float2* src, int n_rows, int ld, const int* mask, int bit, hipStream_t st);
 // Fills the lower tiles of G from the upper ones (Hermitian), then map[R] += scale *
 // Re(c(R)^H G c(R)) for the P probes; C complex64 [P][ldc]; qpart holds P * ceil(n1 / 64)
 // doubles of partial sums (summed in a fixed order).

@@ -120,6 +120,19 @@ __global__ void k_quadform_finish(double* __restrict__ map, int P, const double*
     map[R] += scale * s;
 }
 
+__global__ void k_mask_band(float2* __restrict__ dst, const float2* __restrict__ src, int64_t n, int ld,
+                            const int* __restrict__ mask, int bit) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    dst[i] = (mask[i % ld] & bit) ? src[i] : make_float2(0.f, 0.f);
+}
+
+void launch_mask_band(float2* dst, const float2* src, int n_rows, int ld, const int* mask, int bit, hipStream_t st) {
+    const int64_t n = (int64_t)n_rows * ld;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_mask_band, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dst, src, n, ld, mask, bit);
+}
+
 void launch_gram_reduce(double* G, const float2* part, int nparts, int64_t part_stride, int n1, int ldp,
                         hipStream_t st) {
     const int64_t n = (int64_t)n1 * n1;

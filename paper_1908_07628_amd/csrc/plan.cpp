@@ -81,6 +81,10 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     if (q.order < EELS_ORDER_AUTO || q.order > EELS_ORDER_PROBE_FIRST) return fail(EELS_ERR_INVALID_ARG, "order");
     if (q.detector_sum < EELS_DETSUM_AUTO || q.detector_sum > EELS_DETSUM_GRAM)
         return fail(EELS_ERR_INVALID_ARG, "detector_sum");
+    if (q.n_images < 0 || q.n_images > EELS_MAX_IMAGES || (q.n_images > 0 && !q.image_detectors_mrad))
+        return fail(EELS_ERR_INVALID_ARG, "n_images / image_detectors_mrad");
+    if (q.n_images > 0 && q.interp_f != 1)
+        return fail(EELS_ERR_INVALID_ARG, "companion images need interp_f = 1");
     if (!(q.energy_eV > 0) && !(q.lambda_A > 0 && q.sigma > 0)) return fail(EELS_ERR_INVALID_ARG, "energy");
 
     p.nx = q.nx; p.ny = q.ny; p.lx = q.lx_A; p.ly = q.ly_A; p.nz = q.n_slices;
@@ -200,6 +204,35 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
         p.Kb = off;
         p.Kbpad = (int)round_up(std::max(p.Kb, 1), KPAD_MULT);
     }
+    // companion-image rings: angles, band-limit check, and the ring bits of every band slot
+    p.n_img = q.n_images;
+    p.img_in.clear();
+    p.img_out.clear();
+    std::vector<int32_t> img_mask;
+    if (p.n_img > 0) {
+        const double band_ang = p.lam * p.kmax;
+        for (int d = 0; d < p.n_img; ++d) {
+            double a = q.image_detectors_mrad[2 * d] * 1e-3, b = q.image_detectors_mrad[2 * d + 1] * 1e-3;
+            if (!(a >= 0) || (b > 0 && !(b > a))) return fail(EELS_ERR_INVALID_ARG, "image detector angles");
+            if (b > band_ang * (1 + 1e-12)) return fail(EELS_ERR_BANDLIMIT, "image detector beyond the band limit");
+            p.img_in.push_back(a);
+            p.img_out.push_back(b > 0 ? b : -1.0);
+        }
+        img_mask.assign(p.Kbpad, 0);
+        for (int c = 0; c < p.nlx; ++c) {
+            int cs = p.nlx == p.nx ? (c < (p.nx + 1) / 2 ? c : c - p.nx) : (c <= p.hlx ? c : c - p.nlx);
+            int h = p.band_h[c];
+            for (int r = 0; r <= 2 * h; ++r) {
+                int ks = r <= h ? r : -(2 * h + 1 - r);
+                double kx = cs / p.lx, ky = ks / p.ly;
+                double th = p.lam * std::sqrt(kx * kx + ky * ky);
+                int bits = 0;
+                for (int d = 0; d < p.n_img; ++d)
+                    if (th >= p.img_in[d] && (p.img_out[d] < 0 || th <= p.img_out[d])) bits |= 1 << d;
+                img_mask[p.band_off[c] + r] = bits;
+            }
+        }
+    }
     // full-cell windows contract in the band basis (exact): sum_r S_2 H S_1 equals the sum
     // over band pixels g of (P_j x_{j+1})(g) * fft2(T_j H S_1)(g)
     p.recip = p.full_window && !q.real_space;
@@ -289,7 +322,11 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
                    A(c8 * (size_t)p.nz * p.ny * p.nlx) + A(c8 * (size_t)p.P * p.N1pad) +
                    A(c8 * (size_t)p.N1 * p.ny * p.ldx) + A(c8 * (size_t)p.N2 * p.ny * p.ldx) +
                    A(c8 * (size_t)w2_elems) + A(c8 * (size_t)scratch) +
-                   (p.gram ? A(16 * (size_t)p.N1 * p.N1) + A(8 * (size_t)p.P * ceil_div(p.N1, 64)) : 0);
+                   (p.gram ? A(16 * (size_t)p.N1 * p.N1) + A(8 * (size_t)p.P * ceil_div(p.N1, 64)) : 0) +
+                   (p.n_img > 0 ? 2 * A(c8 * (size_t)p.N1 * p.Kbpad) + A(c8 * (size_t)p.N1pad * p.N1pad) +
+                                      A(16 * (size_t)p.N1 * p.N1) + A(8 * (size_t)p.P * ceil_div(p.N1, 64)) +
+                                      A(c8 * (size_t)p.P * p.N1pad)
+                                : 0);
 
     size_t budget = q.max_workspace_bytes;
     size_t batch_cap = SIZE_MAX;
@@ -623,6 +660,20 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
         ptr[0] = 0;
         p.dbg_ptr = B.append(ptr);
         p.dbg_rec = B.append(rec);
+        if (p.n_img > 0) {
+            p.img_mask_off = B.append(img_mask);
+            // Gram GEMM of the companion images: G[k][k'] = sum_g conj(X[k][g]) X[k'][g] over the
+            // ring-masked exit band coefficients X [N_1][Kb pad]
+            GemmDesc d{};
+            d.a_off = 0; d.lda = p.Kbpad; d.b_off = 0; d.ldb = p.Kbpad;
+            d.h_off = -1; d.c_off = 0; d.ldc_m = p.N1pad; d.p_off = 0;
+            d.M = p.N1; d.N_inner = p.N1; d.n_t = 1; d.K = p.Kbpad; d.idx_off = -1;
+            d.tiles_m = (int)ceil_div(p.N1, GEMM_BM);
+            d.tiles_n = (int)ceil_div(p.N1, GEMM_BN);
+            d.tile_start = 0;
+            p.img_desc = (int)p.descs.size();
+            p.descs.push_back(d);
+        }
         std::vector<int32_t> dd(p.descs.size() * sizeof(GemmDesc) / 4);
         if (!p.descs.empty()) std::memcpy(dd.data(), p.descs.data(), p.descs.size() * sizeof(GemmDesc));
         p.descs_off = B.append(dd);
@@ -657,6 +708,13 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     p.off_part = take(4 * (size_t)std::max<int64_t>(p.part_elems, 1));
     p.off_gtot = take(p.gram ? 16 * (size_t)p.N1 * p.N1 : 16);
     p.off_qpart = take(p.gram ? 8 * (size_t)p.P * ceil_div(p.N1, 64) : 8);
+    const bool img = p.n_img > 0;
+    p.off_img_exit = take(img ? c8 * (size_t)p.N1 * p.Kbpad : 16);
+    p.off_img_masked = take(img ? c8 * (size_t)p.N1 * p.Kbpad : 16);
+    p.off_img_part = take(img ? c8 * (size_t)p.N1pad * p.N1pad : 16);
+    p.off_img_G = take(img ? 16 * (size_t)p.N1 * p.N1 : 16);
+    p.off_img_qpart = take(img ? 8 * (size_t)p.P * ceil_div(p.N1, 64) : 16);
+    p.off_img_C = take(img ? c8 * (size_t)p.P * p.N1pad : 16);
     p.off_blob = take(p.blob.size() * 4);
     p.ws_bytes = off;
     if (budget > 0 && p.ws_bytes > budget) return fail(EELS_ERR_OOM, "workspace exceeds the memory budget");

@@ -44,7 +44,8 @@ class ProblemC(C.Structure):
                 ("window_A", C.c_double), ("n_probes", C.c_int), ("probe_xy", C.POINTER(C.c_double)),
                 ("n_sites", C.c_int), ("sites", C.POINTER(Site)), ("n_trans_total", C.c_int64),
                 ("precision", C.c_int), ("order", C.c_int), ("max_workspace_bytes", C.c_size_t),
-                ("real_space", C.c_int), ("resident_s", C.c_int), ("detector_sum", C.c_int)]
+                ("real_space", C.c_int), ("resident_s", C.c_int), ("detector_sum", C.c_int),
+                ("n_images", C.c_int), ("image_detectors_mrad", C.POINTER(C.c_double))]
 
 
 class PlanInfo(C.Structure):
@@ -63,9 +64,9 @@ EXPORTS = ["eels_get_version", "eels_status_string", "eels_last_error", "eels_pl
            "eels_plan_workspace_bytes", "eels_plan_info_get", "eels_plan_beams", "eels_plan_destroy",
            "eels_execute", "eels_debug_s1", "eels_debug_s2", "eels_gemm_work_bytes", "eels_debug_cgemm",
            "eels_tune_set", "eels_tune_get", "eels_timing_enable", "eels_timing_read", "eels_execute_ex",
-           "eels_plan_s_signature"]
+           "eels_plan_s_signature", "eels_execute_images"]
 EXEC_SKIP_UPLOAD, EXEC_SKIP_SWEEPS = 1, 2
-PHASES = ["setup", "sweep", "producer", "gemm1", "gemm2", "reduce"]
+PHASES = ["setup", "sweep", "producer", "gemm1", "gemm2", "reduce", "images"]
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:
@@ -86,6 +87,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.eels_plan_destroy.argtypes = [vp]
     lib.eels_execute.argtypes = [vp, vp, vp, vp, vp, sz, vp]
     lib.eels_execute_ex.argtypes = [vp, vp, vp, vp, vp, sz, vp, C.c_uint]
+    lib.eels_execute_images.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp, C.c_uint]
     lib.eels_plan_s_signature.argtypes = [vp, C.POINTER(C.c_uint64)]
     lib.eels_debug_s1.argtypes = [vp, vp, C.c_int, vp, vp, sz, vp]
     lib.eels_debug_s2.argtypes = [vp, vp, C.c_int, vp, vp, sz, vp]
@@ -124,8 +126,13 @@ class Plan:
 
     def __init__(self, problem: Any, precision: str = "fp32", order: str = "auto",
                  max_workspace_bytes: int = 0, lambda_A: float = 0.0, sigma: float = 0.0,
-                 real_space: bool = False, resident_s: bool = False, detector_sum: str = "auto"):
+                 real_space: bool = False, resident_s: bool = False, detector_sum: str = "auto",
+                 images=()):
+        """images: elastic companion-image rings [(inner_mrad, outer_mrad), ...]; outer <= 0
+        means the band limit (e.g. ((0, det_outer), (60, 0)) for iBF and ADF)."""
         lib = load_library()
+        self._img = np.ascontiguousarray(np.asarray(images, dtype=np.float64).reshape(-1, 2))
+        self.n_images = int(self._img.shape[0])
         pr = problem
         self._dz = np.ascontiguousarray(pr.dz, dtype=np.float64)
         self._probes = np.ascontiguousarray(pr.probes, dtype=np.float64).reshape(-1, 2)
@@ -147,7 +154,8 @@ class Plan:
             probe_xy=self._probes.ctypes.data_as(C.POINTER(C.c_double)), n_sites=S,
             sites=self._sites, n_trans_total=n_trans, precision=PRECISIONS[precision], order=ORDERS[order],
             max_workspace_bytes=int(max_workspace_bytes), real_space=int(bool(real_space)),
-            resident_s=int(bool(resident_s)), detector_sum=DETSUMS[detector_sum])
+            resident_s=int(bool(resident_s)), detector_sum=DETSUMS[detector_sum], n_images=self.n_images,
+            image_detectors_mrad=self._img.ctypes.data_as(C.POINTER(C.c_double)))
         self.precision = precision
         h = C.c_void_p()
         _check(lib.eels_plan_create(C.byref(h), C.byref(self.problem)))
@@ -194,6 +202,12 @@ class Plan:
         _check(load_library().eels_execute_ex(self._h, _ptr(V), _ptr(H), _ptr(out_map), _ptr(workspace),
                                               workspace.numel(), _stream(stream), int(flags)))
 
+    def execute_images(self, V, H, out_map, out_images, workspace, stream=None, flags: int = 0):
+        """As execute, and writes the companion images (float64 [n_images, P])."""
+        _check(load_library().eels_execute_images(self._h, _ptr(V), _ptr(H), _ptr(out_map), _ptr(out_images),
+                                                  _ptr(workspace), workspace.numel(), _stream(stream),
+                                                  int(flags)))
+
     def s_signature(self) -> int:
         v = C.c_uint64()
         _check(load_library().eels_plan_s_signature(self._h, C.byref(v)))
@@ -234,6 +248,24 @@ def solve(problem, precision: str = "fp32", order: str = "auto", device="cuda",
     plan.execute(V, H, out, ws)
     torch.cuda.synchronize()
     return out.cpu().numpy()
+
+
+def solve_with_images(problem, images, precision: str = "fp32", device="cuda", **kw):
+    """EELS map and elastic companion images of one problem: (map [P], images [n, P])."""
+    import torch
+    plan = Plan(problem, precision=precision, images=images, **kw)
+    V, H = device_inputs(problem, device)
+    ws = plan.alloc_workspace(device)
+    out = torch.empty(plan.n_probes, dtype=torch.float64, device=device)
+    img = torch.empty((plan.n_images, plan.n_probes), dtype=torch.float64, device=device)
+    plan.execute_images(V, H, out, img, ws)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), img.cpu().numpy()
+
+
+def bf_corrected(eels_map, ibf):
+    """EELS map divided by the incoherent bright-field image of the EELS detector's angles."""
+    return np.asarray(eels_map) / np.asarray(ibf)
 
 
 def gemm_work_bytes(m: int, n: int, k: int) -> int:

@@ -406,8 +406,10 @@ def random_problem(seed: int, n: int = 32, ny: Optional[int] = None, L: float = 
                    det_inner_mrad: float = 0.0, det_outer_mrad: float = 20.0,
                    n_scan: int = 3, amp=(30.0, 8.0), dz=None, probes=None,
                    energy_eV: float = ENERGY_300KEV, defocus_A: float = 0.0,
-                   cs_A: float = 0.0) -> Problem:
-    """Random atoms and sites on a small periodic cell (test workloads)."""
+                   cs_A: float = 0.0, widths=(0.3, 0.8)) -> Problem:
+    """Random atoms and sites on a small periodic cell (test workloads).  `widths`: the two
+    Gaussian widths (A) of every atom's projected potential; narrow ones scatter to high
+    angles (a 0.3 A Gaussian sends ~1e-14 of the beam beyond 60 mrad at 300 keV)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     ny = n if ny is None else ny
     Ly = L if Ly is None else Ly
@@ -415,7 +417,7 @@ def random_problem(seed: int, n: int = 32, ny: Optional[int] = None, L: float = 
     a_slice = np.repeat(np.arange(nz), atoms_per_slice)
     a_xy = np.stack([rng.uniform(0, L, na), rng.uniform(0, Ly, na)], axis=1)
     amp_arr = np.tile([list(amp)], (na, 1)) * rng.uniform(0.5, 1.5, (na, 1))
-    wid = np.tile([[0.3, 0.8]], (na, 1))
+    wid = np.tile([list(widths)], (na, 1))
     sites = rng.choice(na, size=min(n_sites, na), replace=False)
     allt = transitions_lm(2)
     trans = [allt[i] for i in rng.choice(len(allt), size=n_trans, replace=False)]

@@ -157,6 +157,21 @@ def test_gram_detector_sum_plan():
     assert eels.Plan(f2, precision="bf16_split", order="s_first").info()["gram_form"] == 0
 
 
+def test_image_detector_plan_rules():
+    """Companion images: f = 1 only, at most EELS_MAX_IMAGES rings, inside the band limit."""
+    _lib()
+    p = synth.random_problem(3, n=64, L=9.0, nz=2, aperture_mrad=20.0, det_outer_mrad=30.0)
+    ws0 = eels.Plan(p).info()["workspace_bytes"]
+    ws1 = eels.Plan(p, images=[(0.0, 30.0), (35.0, 0.0)]).info()["workspace_bytes"]
+    assert ws1 > ws0
+    for bad, status in (([(0.0, 80.0)], 2),             # beyond the ~45 mrad band
+                        ([(20.0, 10.0)], 1),            # outer below inner
+                        ([(0.0, 5.0)] * 9, 1)):          # too many rings
+        with pytest.raises(eels.EelsError) as e:
+            eels.Plan(p, images=bad)
+        assert e.value.status == status
+
+
 def test_band_table_matches_oracle_mask():
     """Band pixel count equals the oracle's circular mask count (same inclusive rule)."""
     _lib()

@@ -1,0 +1,85 @@
+"""GPU parity of the elastic companion images (iBF with the EELS detector's angles, ADF from
+60 mrad to the band limit, and other rings) against the FP64 oracle, through the C ABI."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import images as oimg, metrics, prism
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1908_07628_amd import eels
+    return eels
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _cell(seed=81, **kw):
+    # 128 px over 12 A: band limit ~70 mrad, so a 60 mrad ADF ring exists; narrow atoms so
+    # that it collects a measurable part of the beam
+    base = dict(n=128, L=12.0, nz=4, n_sites=3, n_trans=2, aperture_mrad=20.0, det_outer_mrad=30.0,
+                det_inner_mrad=0.0, n_scan=5, widths=(0.12, 0.4))
+    base.update(kw)
+    return synth.random_problem(seed, **base)
+
+
+RINGS = [(0.0, 30.0), (60.0, 0.0), (8.0, 25.0), (30.5, 0.0)]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16_split"])
+def test_images_match_oracle_and_leave_the_map_unchanged(prec):
+    eels = _gpu()
+    p = _cell()
+    _say("images", prec, p.nx, p.n_probes)
+    m, img = eels.solve_with_images(p, RINGS, precision=prec)
+    ref = oimg.detector_images(p, [(a, b if b > 0 else None) for a, b in RINGS])
+    for d in range(len(RINGS)):
+        assert np.all(np.isfinite(img[d]))
+        assert metrics.rel_l2(img[d], ref[d]) < 1e-4, (RINGS[d], metrics.rel_l2(img[d], ref[d]))
+    assert np.all(img[1] > 1e-9)                    # the ADF ring collects scattered intensity
+    plain = eels.solve(p, precision=prec)
+    assert np.array_equal(m, plain)                 # the map does not depend on the images
+    tol = 1e-4 if prec == "fp32" else 1e-3
+    assert metrics.rel_l2(m, prism.prism_map(p)) < tol
+    bf = eels.bf_corrected(m, img[0])
+    assert np.allclose(bf, oimg.bf_corrected(m, ref[0]), rtol=1e-3)
+
+
+def test_images_with_resident_s_and_without_sites():
+    eels = _gpu()
+    p = _cell(seed=82, n_sites=2)
+    a = eels.Plan(p, resident_s=True, images=RINGS[:2])
+    V, H = eels.device_inputs(p)
+    ws = a.alloc_workspace()
+    m1 = torch.empty(a.n_probes, dtype=torch.float64, device="cuda")
+    i1 = torch.empty((2, a.n_probes), dtype=torch.float64, device="cuda")
+    a.execute_images(V, H, m1, i1, ws)
+    m2 = torch.empty_like(m1)
+    i2 = torch.empty_like(i1)
+    a.execute_images(V, H, m2, i2, ws, flags=eels.EXEC_SKIP_SWEEPS)
+    torch.cuda.synchronize()
+    assert np.array_equal(m1.cpu().numpy(), m2.cpu().numpy())
+    assert np.array_equal(i1.cpu().numpy(), i2.cpu().numpy())
+    q = p.replace(site_slice=p.site_slice[:0], site_xy=p.site_xy[:0], site_ntrans=p.site_ntrans[:0],
+                  site_hoff=p.site_hoff[:0])
+    m, img = eels.solve_with_images(q, RINGS[:2])
+    assert np.all(m == 0)
+    ref = oimg.detector_images(q, [(0.0, 30.0), (60.0, None)])
+    assert metrics.rel_l2(img[0], ref[0]) < 1e-4 and metrics.rel_l2(img[1], ref[1]) < 1e-4
+
+
+def test_images_need_interpolation_factor_one():
+    eels = _gpu()
+    p = synth.config3_subproblem(n=128, L=25.0, nz=3, n_scan=4, f=2)
+    with pytest.raises(eels.EelsError):
+        eels.Plan(p, images=[(0.0, 10.0)])
