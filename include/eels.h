@@ -106,6 +106,7 @@ typedef struct {
                                 (needs one slice group), so that a later eels_execute_ex with
                                 EELS_EXEC_SKIP_SWEEPS can reuse the S-matrices              */
     int detector_sum;        /* EELS_DETSUM_*: how sum_{n,q} |A_n(q,R)|^2 is formed (order S)  */
+    int s1_mode;             /* EELS_S1_STORED (exact) or EELS_S1_INVERSE (Sec. 4.C)        */
     int n_images;            /* elastic companion images (0 .. EELS_MAX_IMAGES), interp_f = 1  */
     const double* image_detectors_mrad;  /* [n_images][2] inner, outer semi-angle (inclusive);
                                 outer <= 0 means the band limit                              */
@@ -128,6 +129,15 @@ enum { EELS_MAX_IMAGES = 8 };
  * finishes the map (about 5x fewer flops than DIRECT for the crystal maps).  AUTO picks
  * GRAM where it applies (order S, interp_f = 1, band basis or split precision). */
 enum { EELS_DETSUM_AUTO = 0, EELS_DETSUM_DIRECT = 1, EELS_DETSUM_GRAM = 2 };
+
+/* How S_1 reaches the ionised slices.  STORED: the forward sweep captures S_1 at every
+ * ionised slice on the way down and keeps the windows until the transposed S_2 sweep
+ * reaches them (exact; slice groups bound the memory).  INVERSE: the inverse multislice of
+ * Sec. 4.C, Eq. MSinvop: S_1 is swept to the exit plane and then retreated slice by slice
+ * with M_j^-1 = F conj(T_j) F^-1 conj(P_j) in step with the S_2 sweep, so only one slice's
+ * windows are ever held.  Approximate: intensity that multislice pushed beyond the band
+ * limit is not recovered.  Not combinable with resident_s. */
+enum { EELS_S1_STORED = 0, EELS_S1_INVERSE = 1 };
 
 /* Derived sizes of a plan (filled by eels_plan_info). */
 typedef struct {

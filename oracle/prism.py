@@ -52,6 +52,29 @@ def forward_s1(prob, st, slices) -> Dict[int, np.ndarray]:
     return out
 
 
+def inverse_s1(prob, st, slices) -> Dict[int, np.ndarray]:
+    """S_1(j) the inverse-multislice way (Sec. 4.C, Eq. MSinvop): the aperture plane waves
+    are multisliced through all slices to the exit, then retreated one slice at a time with
+    the conjugated operators in reverse order,
+        x_j = M_j^-1 x_{j+1} = fft2(conj(T_j) * ifft2(conj(P_j) * x_{j+1})),
+    and S_1(j) = ifft2(x_j).  Exact where no intensity left the band limit (P_j unitary on
+    what it meets); otherwise approximate."""
+    need = set(int(j) for j in slices)
+    out: Dict[int, np.ndarray] = {}
+    if not need:
+        return out
+    N1 = st.ab1.shape[0]
+    x = np.zeros((N1, prob.ny, prob.nx), dtype=np.complex128)
+    x[np.arange(N1), st.iy1, st.ix1] = 1.0
+    for j in range(prob.n_slices):
+        x = st.P[j] * np.fft.fft2(st.T[j] * np.fft.ifft2(x))
+    for j in range(prob.n_slices - 1, min(need) - 1, -1):
+        x = np.fft.fft2(np.conj(st.T[j]) * np.fft.ifft2(np.conj(st.P[j]) * x))
+        if j in need:
+            out[j] = np.fft.ifft2(x)
+    return out
+
+
 def reverse_s2(prob, st, j_stop: int = 0):
     """Yield (j, S_2(j)) for j = n_z-1 down to j_stop (exact transposed multislice)."""
     N2 = st.ab2.shape[0]
@@ -80,13 +103,15 @@ def contract_site(prob, st, s: int, S1j: np.ndarray, S2j: np.ndarray, I: np.ndar
         I[el] += f2 * (np.abs(A) ** 2).sum(axis=0)
 
 
-def prism_map(prob, lam=None, sigma=None, st=None) -> np.ndarray:
+def prism_map(prob, lam=None, sigma=None, st=None, s1_mode: str = "stored") -> np.ndarray:
+    """The map; s1_mode "stored" uses the forward S_1 (exact), "inverse" the inverse-multislice
+    S_1 (Sec. 4.C)."""
     st = make_setup(prob, lam, sigma) if st is None else st
     I = np.zeros(prob.n_probes, dtype=np.float64)
     ion = sorted(st.sites_by_slice.keys())
     if not ion:
         return I
-    S1 = forward_s1(prob, st, ion)
+    S1 = forward_s1(prob, st, ion) if s1_mode == "stored" else inverse_s1(prob, st, ion)
     for j, S2 in reverse_s2(prob, st, j_stop=min(ion)):
         for s in st.sites_by_slice.get(j, []):
             contract_site(prob, st, s, S1[j], S2, I)

@@ -153,7 +153,7 @@ const float2* Pj(const Plan& p, const Dev& d, int j) { return d.P + (int64_t)j *
 // column pass also runs and captures the band coefficients of the exit wave
 // P_{nz-1} fft2(T_{nz-1} psi) of every beam into exit_cap [N_1][Kb pad].
 void forward_sweep(const Plan& p, const Dev& d, int j_end, int group, int dbg_slice, float2* dbg_out,
-                   hipStream_t st, float2* exit_cap = nullptr) {
+                   hipStream_t st, float2* exit_cap = nullptr, bool last_col = false) {
     TimeScope ts(EELS_PHASE_SWEEP, st);
     launch_init_forward(d.s1, d.b1, p, st);
     for (int j = 0; j <= j_end; ++j) {
@@ -170,10 +170,25 @@ void forward_sweep(const Plan& p, const Dev& d, int j_end, int group, int dbg_sl
         }
         launch_row_pass(p.nx, 0, a, st);
         if (j < j_end) launch_col_pass(p.ny, 0, d.s1, p.N1, p.nlx, p.ldx, Pj(p, d, j), d.twy, BandCap{}, st);
-        else if (exit_cap)
+        else if (exit_cap || last_col)
             launch_col_pass(p.ny, 0, d.s1, p.N1, p.nlx, p.ldx, Pj(p, d, j), d.twy,
-                            BandCap{d.band_h, d.band_off, exit_cap, p.Kbpad, 0}, st);
+                            exit_cap ? BandCap{d.band_h, d.band_off, exit_cap, p.Kbpad, 0} : BandCap{}, st);
     }
+}
+
+// One step of the inverse multislice (Sec. 4.C): S_1 from the entrance of slice j+1 back to
+// the entrance of slice j, x_j = F conj(T_j) F^-1 conj(P_j) x_{j+1}, capturing the windows of
+// slice j's sites when `capture`.
+void inverse_step(const Plan& p, const Dev& d, int j, bool capture, hipStream_t st) {
+    TimeScope ts(EELS_PHASE_SWEEP, st);
+    launch_col_pass(p.ny, 2, d.s1, p.N1, p.nlx, p.ldx, Pj(p, d, j), d.twy, BandCap{}, st);
+    RowPassArgs a{d.s1, p.N1, p.ny, p.nlx, p.hlx, Tj(p, d, j), d.twx, nullptr, nullptr, d.w1, p.N1, p.Kpad, 0,
+                  p.ldx};
+    if (capture) {
+        a.cap_ptr = d.blob + p.slices[j].cap1_ptr;
+        a.cap_rec = d.blob + p.slices[j].cap1_rec;
+    }
+    launch_row_pass(p.nx, 2, a, st);
 }
 
 // One step of the transposed sweep: bring S_2 to slice j (from j+1, or start at n_z-1)
@@ -500,6 +515,21 @@ eels_status eels_execute_images(const eels_plan* pl, const float* d_V, const voi
     }
     // split operands are read in whole 16-element K tiles: the S_2 capture's padding must be zero
     if (p.precision != EELS_FP32) launch_fill_zero(d.w2, p.off_C - p.off_w2, st);
+    if (p.s1_inverse && !p.groups.empty()) {
+        // S_1 through every slice to the exit (capturing the exit wave for the images), then
+        // back down with the inverse multislice beside the transposed S_2 sweep
+        forward_sweep(p, d, p.nz - 1, -1, -1, nullptr, st, images ? d.img_exit : nullptr, true);
+        if (images) companion_images(p, d, d_images, st);
+        for (int j = p.nz - 1; j >= p.groups[0].j_lo; --j) {
+            reverse_step(p, d, j, p.slices[j].ion, nullptr, st);
+            inverse_step(p, d, j, p.slices[j].ion, st);
+            if (p.slices[j].ion)
+                for (int bi : p.slices[j].batches) contract(p, d, (const float2*)d_H, d_map, bi, st);
+        }
+        finish_map(p, d, d_map, st);
+        HIPCHK(hipGetLastError());
+        return EELS_OK;
+    }
     int rev_next = p.nz - 1;
     for (int gi = 0; gi < (int)p.groups.size(); ++gi) {
         const Group& g = p.groups[gi];

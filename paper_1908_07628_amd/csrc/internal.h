@@ -112,6 +112,7 @@ struct Plan {
     int Kb, Kbpad;                              // band pixels, padded stride
     int c_sc, w2_sc, mid2_sc;                   // storage formats (0 complex64, else split precision)
     bool gram;                                  // detector sum in the Gram form (order S, f = 1)
+    bool s1_inverse = false;                    // S_1 retreated with the inverse multislice
     int n_img = 0;                              // elastic companion images
     std::vector<double> img_in, img_out;        // their ring angles (rad; out < 0: band limit)
     int img_desc = -1;                          // descriptor of the images' Gram GEMM

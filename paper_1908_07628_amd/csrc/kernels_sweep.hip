@@ -1,14 +1,17 @@
 // Multislice sweeps of the scattering matrices and the small set-up kernels.
 //
 // A beam's wave is kept between slices in the hybrid (kx, y) representation, stored
-// as [beam][y][c] over the nlx kx columns inside the band limit (column c <-> kx index
-// c for c <= hlx, c - nlx + nx otherwise).  One slice of the forward operator
-// M_j = P_j F T_j F^-1 (Eq. MSop) is two passes over HBM:
+// as [beam][y][ldx] over the nlx kx columns inside the band limit (see phys_col_of).
+// One slice of the forward operator M_j = P_j F T_j F^-1 (Eq. MSop) is two passes over HBM:
 //   row pass     iFFT_x -> (capture S_1 windows) -> * T_j -> FFT_x
 //   column pass  FFT_y  -> * P_j / (nx ny)       -> iFFT_y
-// and one slice of the exact transpose M_j^T = F^-1 T_j F P_j used for S_2 is
+// one slice of the exact transpose M_j^T = F^-1 T_j F P_j used for S_2 is
 //   column pass  iFFT_y -> * P_j / (nx ny)       -> FFT_y
 //   row pass     FFT_x  -> * T_j -> (capture S_2 windows) -> iFFT_x
+// and one slice of the inverse multislice M_j^-1 = F conj(T_j) F^-1 conj(P_j) (Eq. MSinvop),
+// which retreats S_1 by a slice, is
+//   column pass  FFT_y  -> * conj(P_j) / (nx ny) -> iFFT_y
+//   row pass     iFFT_x -> * conj(T_j) -> (capture S_1 windows) -> FFT_x
 // Transforms are unnormalised; the 1/(nx ny) folded into P keeps S_2 exactly at the
 // scale of its definition and S_1 at nx*ny times it (unit-modulus plane waves at j = 0).
 #include <hip/hip_runtime.h>
@@ -211,7 +214,9 @@ __global__ void k_copy(float2* dst, const float2* src, int64_t n) {
 // T = N/16 threads per row, 16 elements each (pixel / column t + T m in v[m]); a block
 // holds S = 256/T rows of the flat row index g = beam * ny + y.  Loads and stores go
 // straight between HBM and registers; only the middle FFT stages use LDS.
-// mode 0: forward sweep, mode 1: transposed sweep.
+// mode 0: forward sweep (iFFT_x, capture, x T, FFT_x); mode 1: transposed sweep (FFT_x, x T,
+// capture, iFFT_x); mode 2: inverse multislice, Eq. MSinvop (iFFT_x, x conj(T), capture the
+// slice's entrance wave, FFT_x).
 template <int N, int MODE>
 __global__ __launch_bounds__(256) void k_row_pass(float2* __restrict__ state, int nbeam, int ny, int nlx, int hlx, int ldx,
                                                   const float2* __restrict__ Tj, const float2* __restrict__ tw,
@@ -231,8 +236,13 @@ __global__ __launch_bounds__(256) void k_row_pass(float2* __restrict__ state, in
         int c = phys_col_of(t + T * m, N, hlx, ldx);
         v[m] = (valid && c >= 0) ? state[g * ldx + c] : make_float2(0.f, 0.f);
     }
-    fft_reg<N, MODE == 0 ? +1 : -1>(v, lds, s * N, 1, t, tw);
+    constexpr int S1 = MODE == 1 ? -1 : +1;   // first transform's sign (+1: inverse FFT_x)
+    fft_reg<N, S1>(v, lds, s * N, 1, t, tw);
 
+    // In mode 2 the column pass's conj(P_j) / (nx ny) leaves this pass's input 1/nx of the
+    // forward row pass's output (the state after the final FFT_x is exact), so the captured
+    // entrance wave is scaled by nx (exact) to match the forward capture.
+    constexpr float cap_scale = MODE == 2 ? (float)N : 1.0f;
     auto capture = [&]() {
         if (cap_ptr && valid) {
             int r0 = cap_ptr[y], r1 = cap_ptr[y + 1];
@@ -243,7 +253,7 @@ __global__ __launch_bounds__(256) void k_row_pass(float2* __restrict__ state, in
                 for (int m = 0; m < E; ++m) {
                     int u = t + T * m - rec.z;
                     if (u < 0) u += N;
-                    if (u < rec.w) store_c(win, dst + u, v[m], sc);
+                    if (u < rec.w) store_c(win, dst + u, make_float2(v[m].x * cap_scale, v[m].y * cap_scale), sc);
                 }
             }
         }
@@ -251,10 +261,14 @@ __global__ __launch_bounds__(256) void k_row_pass(float2* __restrict__ state, in
     if constexpr (MODE == 0) capture();
     const float2* Trow = Tj + (int64_t)y * N;
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = cmul(v[m], Trow[t + T * m]);
-    if constexpr (MODE == 1) capture();
+    for (int m = 0; m < E; ++m) {
+        float2 tv = Trow[t + T * m];
+        if constexpr (MODE == 2) tv.y = -tv.y;
+        v[m] = cmul(v[m], tv);
+    }
+    if constexpr (MODE != 0) capture();
 
-    fft_reg<N, MODE == 0 ? -1 : +1>(v, lds, s * N, 1, t, tw);
+    fft_reg<N, -S1>(v, lds, s * N, 1, t, tw);
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         int c = phys_col_of(t + T * m, N, hlx, ldx);
@@ -297,9 +311,14 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_col_pass(float2* __restrict__
     float2 v[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = live ? plane[(int64_t)(t + T * m) * ldx + pc] : make_float2(0.f, 0.f);
-    fft_reg<N, MODE == 0 ? -1 : +1>(v, lds, col, CW, t, tw);
+    constexpr int S1 = MODE == 1 ? +1 : -1;   // first transform's sign (-1: FFT_y)
+    fft_reg<N, S1>(v, lds, col, CW, t, tw);
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = cmul(v[m], live ? Pj[(int64_t)(t + T * m) * nlx + c] : make_float2(0.f, 0.f));
+    for (int m = 0; m < E; ++m) {
+        float2 pv = live ? Pj[(int64_t)(t + T * m) * nlx + c] : make_float2(0.f, 0.f);
+        if constexpr (MODE == 2) pv.y = -pv.y;   // inverse multislice: conj(P)
+        v[m] = cmul(v[m], pv);
+    }
     if (bcap && live) {
         // band coefficients of this column: ky = 0..h, then ny-h..ny-1, at band_off[c] + rank
         const int h = band_h[c];
@@ -311,7 +330,7 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_col_pass(float2* __restrict__
             if (r >= 0) store_c(bcap, dst + r, v[m], sc);
         }
     }
-    fft_reg<N, MODE == 0 ? +1 : -1>(v, lds, col, CW, t, tw);
+    fft_reg<N, -S1>(v, lds, col, CW, t, tw);
     if (live) {
 #pragma unroll
         for (int m = 0; m < E; ++m) plane[(int64_t)(t + T * m) * ldx + pc] = v[m];
@@ -530,7 +549,8 @@ void launch_row_pass(int nx, int mode, const RowPassArgs& a, hipStream_t st) {
 #define ROWCASE(NN)                                   \
     case NN:                                          \
         if (mode == 0) row_pass_n<NN, 0>(a, st);      \
-        else row_pass_n<NN, 1>(a, st);                \
+        else if (mode == 1) row_pass_n<NN, 1>(a, st); \
+        else row_pass_n<NN, 2>(a, st);                \
         break;
     switch (nx) {
         ROWCASE(16) ROWCASE(32) ROWCASE(64) ROWCASE(128) ROWCASE(256) ROWCASE(512) ROWCASE(1024)
@@ -553,7 +573,8 @@ void launch_col_pass(int ny, int mode, float2* state, int nbeam, int nlx, int ld
 #define COLCASE(NN)                                                   \
     case NN:                                                          \
         if (mode == 0) col_pass_n<NN, 0>(state, nbeam, nlx, ldx, Pj, tw, bc, st); \
-        else col_pass_n<NN, 1>(state, nbeam, nlx, ldx, Pj, tw, bc, st);    \
+        else if (mode == 1) col_pass_n<NN, 1>(state, nbeam, nlx, ldx, Pj, tw, bc, st); \
+        else col_pass_n<NN, 2>(state, nbeam, nlx, ldx, Pj, tw, bc, st);    \
         break;
     switch (ny) {
         COLCASE(16) COLCASE(32) COLCASE(64) COLCASE(128) COLCASE(256) COLCASE(512) COLCASE(1024)

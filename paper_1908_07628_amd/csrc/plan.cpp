@@ -81,6 +81,9 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     if (q.order < EELS_ORDER_AUTO || q.order > EELS_ORDER_PROBE_FIRST) return fail(EELS_ERR_INVALID_ARG, "order");
     if (q.detector_sum < EELS_DETSUM_AUTO || q.detector_sum > EELS_DETSUM_GRAM)
         return fail(EELS_ERR_INVALID_ARG, "detector_sum");
+    if (q.s1_mode != EELS_S1_STORED && q.s1_mode != EELS_S1_INVERSE) return fail(EELS_ERR_INVALID_ARG, "s1_mode");
+    if (q.s1_mode == EELS_S1_INVERSE && q.resident_s)
+        return fail(EELS_ERR_INVALID_ARG, "the inverse multislice keeps no S_1 windows to make resident");
     if (q.n_images < 0 || q.n_images > EELS_MAX_IMAGES || (q.n_images > 0 && !q.image_detectors_mrad))
         return fail(EELS_ERR_INVALID_ARG, "n_images / image_detectors_mrad");
     if (q.n_images > 0 && q.interp_f != 1)
@@ -376,7 +379,20 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     p.groups.clear();
     p.site_w1.assign(S, -1);
     p.site_w2.assign(S, -1);
-    {
+    p.s1_inverse = q.s1_mode == EELS_S1_INVERSE;
+    if (p.s1_inverse) {
+        // one pass; the windows of one slice at a time
+        int maxw = 0;
+        for (int j : ion) {
+            if ((size_t)slice_windows(j) * win1_bytes > w1_cap)
+                return fail(EELS_ERR_OOM, "one slice's S_1 windows exceed the budget");
+            p.slices[j].group = 0;
+            if (p.full_window) for (int s : by_slice[j]) p.site_w1[s] = 0;
+            else for (size_t t = 0; t < by_slice[j].size(); ++t) p.site_w1[by_slice[j][t]] = (int)t;
+            maxw = std::max(maxw, slice_windows(j));
+        }
+        if (!ion.empty()) p.groups.push_back(Group{ion.front(), ion.back(), maxw});
+    } else {
         int gi = -1;
         size_t gbytes = 0;
         int gwin = 0;
@@ -683,7 +699,8 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     // live columns of the beam's plane
     double fwd = 0, rev = 0;
     if (!ion.empty()) {
-        for (auto& g : p.groups) fwd += (double)(g.j_hi + 1) * p.N1;
+        if (p.s1_inverse) fwd = (double)(2 * p.nz - ion.front()) * p.N1;   // to the exit and back
+        else for (auto& g : p.groups) fwd += (double)(g.j_hi + 1) * p.N1;
         rev = (double)(p.nz - ion.front()) * p.N2;
     }
     p.sweep_beam_slices = fwd + rev;

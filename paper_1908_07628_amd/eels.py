@@ -45,7 +45,7 @@ class ProblemC(C.Structure):
                 ("n_sites", C.c_int), ("sites", C.POINTER(Site)), ("n_trans_total", C.c_int64),
                 ("precision", C.c_int), ("order", C.c_int), ("max_workspace_bytes", C.c_size_t),
                 ("real_space", C.c_int), ("resident_s", C.c_int), ("detector_sum", C.c_int),
-                ("n_images", C.c_int), ("image_detectors_mrad", C.POINTER(C.c_double))]
+                ("s1_mode", C.c_int), ("n_images", C.c_int), ("image_detectors_mrad", C.POINTER(C.c_double))]
 
 
 class PlanInfo(C.Structure):
@@ -127,9 +127,10 @@ class Plan:
     def __init__(self, problem: Any, precision: str = "fp32", order: str = "auto",
                  max_workspace_bytes: int = 0, lambda_A: float = 0.0, sigma: float = 0.0,
                  real_space: bool = False, resident_s: bool = False, detector_sum: str = "auto",
-                 images=()):
+                 images=(), s1_mode: str = "stored"):
         """images: elastic companion-image rings [(inner_mrad, outer_mrad), ...]; outer <= 0
-        means the band limit (e.g. ((0, det_outer), (60, 0)) for iBF and ADF)."""
+        means the band limit (e.g. ((0, det_outer), (60, 0)) for iBF and ADF).  s1_mode:
+        "stored" (exact) or "inverse" (inverse multislice, Sec. 4.C)."""
         lib = load_library()
         self._img = np.ascontiguousarray(np.asarray(images, dtype=np.float64).reshape(-1, 2))
         self.n_images = int(self._img.shape[0])
@@ -154,7 +155,8 @@ class Plan:
             probe_xy=self._probes.ctypes.data_as(C.POINTER(C.c_double)), n_sites=S,
             sites=self._sites, n_trans_total=n_trans, precision=PRECISIONS[precision], order=ORDERS[order],
             max_workspace_bytes=int(max_workspace_bytes), real_space=int(bool(real_space)),
-            resident_s=int(bool(resident_s)), detector_sum=DETSUMS[detector_sum], n_images=self.n_images,
+            resident_s=int(bool(resident_s)), detector_sum=DETSUMS[detector_sum],
+            s1_mode={"stored": 0, "inverse": 1}[s1_mode], n_images=self.n_images,
             image_detectors_mrad=self._img.ctypes.data_as(C.POINTER(C.c_double)))
         self.precision = precision
         h = C.c_void_p()
@@ -237,11 +239,12 @@ def device_inputs(problem, device="cuda"):
 
 
 def solve(problem, precision: str = "fp32", order: str = "auto", device="cuda",
-          max_workspace_bytes: int = 0, real_space: bool = False, detector_sum: str = "auto") -> np.ndarray:
+          max_workspace_bytes: int = 0, real_space: bool = False, detector_sum: str = "auto",
+          s1_mode: str = "stored") -> np.ndarray:
     """Compute one EELS map on the GPU and return it as float64 numpy [n_probes]."""
     import torch
     plan = Plan(problem, precision=precision, order=order, max_workspace_bytes=max_workspace_bytes,
-                real_space=real_space, detector_sum=detector_sum)
+                real_space=real_space, detector_sum=detector_sum, s1_mode=s1_mode)
     V, H = device_inputs(problem, device)
     ws = plan.alloc_workspace(device)
     out = torch.empty(plan.n_probes, dtype=torch.float64, device=device)

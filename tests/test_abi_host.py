@@ -172,6 +172,22 @@ def test_image_detector_plan_rules():
         assert e.value.status == status
 
 
+def test_inverse_multislice_plan():
+    """Inverse multislice: one slice's windows, a sweep to the exit and back, and no
+    resident S-matrices."""
+    _lib()
+    p = synth.random_problem(6, n=64, L=10.0, nz=8, n_sites=6, atoms_per_slice=3, window_A=0.0)
+    a = eels.Plan(p).info()
+    b = eels.Plan(p, s1_mode="inverse").info()
+    assert b["n_groups"] == 1 and b["workspace_bytes"] < a["workspace_bytes"]
+    lowest = int(np.min(p.site_slice))
+    assert b["sweep_beam_slices"] == (2 * p.n_slices - lowest) * b["n_beams_in"] + \
+        (p.n_slices - lowest) * b["n_beams_out"]
+    with pytest.raises(eels.EelsError) as e:
+        eels.Plan(p, s1_mode="inverse", resident_s=True)
+    assert e.value.status == 1
+
+
 def test_band_table_matches_oracle_mask():
     """Band pixel count equals the oracle's circular mask count (same inclusive rule)."""
     _lib()
