@@ -354,10 +354,54 @@ def main():
                                          "the row-to-column scratch round trip is not counted")},
     }
 
+    del ws
+    # Extras, on the sites of the top ionised slices (their costs do not grow with the site
+    # count except the contractions): companion images (iBF with the EELS detector's angles,
+    # ADF from 60 mrad to the band limit) computed with the map, and the inverse-multislice
+    # S_1 (Sec. 4.C) against the exact path.
+    ps = subset_sites(p, np.nonzero(np.isin(p.site_slice, ion[-args.fp32_slices:]))[0])
+    rings = [(p.det_inner_mrad, p.det_outer_mrad), (60.0, 0.0)]
+
+    def timed(plan, with_images=False):
+        wsx = plan.alloc_workspace()
+        o = torch.empty(p.n_probes, dtype=torch.float64, device="cuda")
+        im = torch.empty((max(plan.n_images, 1), p.n_probes), dtype=torch.float64, device="cuda")
+        run = (lambda: plan.execute_images(V, H, o, im, wsx)) if with_images else (lambda: plan.execute(V, H, o, wsx))
+        run()                                       # warm
+        eels.timing_enable(8192)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        run()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        ph = eels.timing_read()
+        eels.timing_enable(0)
+        return dt, ph, o.cpu().numpy(), im.cpu().numpy(), plan.workspace_bytes
+
+    base_plan = eels.Plan(ps, precision=args.precision)
+    dt0, ph0, m0, _, ws0 = timed(base_plan)
+    del base_plan
+    dti, phi, mi, imgs, _ = timed(eels.Plan(ps, precision=args.precision, images=rings), with_images=True)
+    companion = {
+        "measured_on": f"sites of the top {args.fp32_slices} ionised slices",
+        "rings_mrad": [[a, b if b > 0 else "band limit"] for a, b in rings],
+        "images_phase_ms": round(phi["images"]["ms"], 2),
+        "extra_sweep_ms": round(phi["sweep"]["ms"] - ph0["sweep"]["ms"], 2),
+        "map_unchanged": bool(np.array_equal(mi, m0)),
+        "ibf_mean": float(imgs[0].mean()), "adf_mean": float(imgs[1].mean()),
+    }
+    dtv, phv, mv, _, wsv = timed(eels.Plan(ps, precision=args.precision, s1_mode="inverse"))
+    inverse = {
+        "measured_on": f"sites of the top {args.fp32_slices} ionised slices",
+        "map_rel_l2_vs_exact": float(np.linalg.norm(mv - m0) / np.linalg.norm(m0)),
+        "ms_exact": round(1e3 * dt0, 1), "ms_inverse": round(1e3 * dtv, 1),
+        "sweep_ms_exact": round(ph0["sweep"]["ms"], 1), "sweep_ms_inverse": round(phv["sweep"]["ms"], 1),
+        "workspace_GB_exact": round(ws0 / 1e9, 2), "workspace_GB_inverse": round(wsv / 1e9, 2),
+    }
+
     # FP32 plain path
     if args.fp32_full:
         p32 = eels.Plan(p, precision="fp32")
-        del ws
         ws32 = p32.alloc_workspace()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -368,10 +412,8 @@ def main():
         del ws32
     else:
         keep = np.isin(p.site_slice, ion[-args.fp32_slices:])
-        ps = subset_sites(p, np.nonzero(keep)[0])
         p32 = eels.Plan(ps, precision="fp32")
         i32 = p32.info()
-        del ws
         ws32 = p32.alloc_workspace()
         p32.execute(V, H, out, ws32)        # warm the FP32 kernels
         torch.cuda.synchronize()
@@ -406,6 +448,8 @@ def main():
                    if args.precision != "fp32" else "fp32", "contraction": "band basis, order S"},
         "roofline": roofline,
         "roofline_fft": roofline_fft,
+        "companion_images": companion,
+        "inverse_multislice": inverse,
         "phases_ms": phases,
         "fp32": fp32,
         "split_over_fp32": round(value / fp32["value"], 2),

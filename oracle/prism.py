@@ -118,6 +118,11 @@ def prism_map(prob, lam=None, sigma=None, st=None, s1_mode: str = "stored") -> n
     return I
 
 
+def frozen_phonon_map(configs) -> np.ndarray:
+    """Average of the maps of the given thermal configurations (same probes)."""
+    return np.mean([prism_map(c) for c in configs], axis=0)
+
+
 def site_maps(prob, lam=None, sigma=None) -> np.ndarray:
     """Per-site contributions [S, P] (for additivity tests)."""
     st = make_setup(prob, lam, sigma)

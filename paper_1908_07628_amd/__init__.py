@@ -11,8 +11,10 @@ from .eels import (  # noqa: F401
     Plan,
     cgemm,
     device_inputs,
+    bf_corrected,
     load_library,
     solve,
+    solve_with_images,
 )
 
 __version__ = "0.3"

@@ -18,4 +18,5 @@ from .specimens import (  # noqa: F401
     random_problem,
     probe_grid,
     transitions_lm,
+    thermal_displacement,
 )

@@ -198,6 +198,21 @@ def probe_grid(nsx, nsy, step_x, step_y, x0=0.0, y0=0.0) -> np.ndarray:
     return np.stack([X.ravel(), Y.ravel()], axis=1).astype(np.float64)
 
 
+def thermal_displacement(atom_xy, lx, ly, u_rms_A: float, seed: int) -> np.ndarray:
+    """Frozen-phonon configuration: every atom displaced in-plane by independent Gaussian
+    offsets of rms u_rms_A per axis (seeded), wrapped into the periodic cell.  u = 0 returns
+    the positions unchanged."""
+    xy = np.asarray(atom_xy, dtype=np.float64)
+    if not u_rms_A > 0:
+        return xy
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d = rng.normal(0.0, u_rms_A, size=xy.shape)
+    out = xy + d
+    out[:, 0] %= lx
+    out[:, 1] %= ly
+    return out
+
+
 def _finish(name, nx, ny, lx, ly, dz, atom_slice, atom_xy, atom_amp, atom_w,
             site_slice, site_xy, trans, probes, probe_shape, **optics) -> Problem:
     dz = np.asarray(dz, dtype=np.float64)
@@ -274,12 +289,15 @@ def perovskite_atoms(ncell=5, a=4.0, c=3.9, thickness=100.0, dzs=2.0):
     return (np.array(sl), np.array(xy), np.array(amp), np.array(wid), np.array(sp))
 
 
-def config2(seed: int = 2, n_scan: int = 64, window_A: float = 0.0) -> Problem:
+def config2(seed: int = 2, n_scan: int = 64, window_A: float = 0.0, displace_A: float = 0.0,
+            displace_seed: int = 0) -> Problem:
     """256x256 px, 20x20 A cell (5x5 perovskite cells of 4.0 A, 3.9 A along z),
     50 slices of 2 A; 21 mrad aperture; detector 0-50 mrad; every B atom ionised
-    with the 9 (l' <= 2, m') transitions; 64x64 probes at 0.3125 A steps."""
+    with the 9 (l' <= 2, m') transitions; 64x64 probes at 0.3125 A steps.
+    displace_A > 0: one frozen-phonon configuration (see thermal_displacement)."""
     del seed  # the crystal is deterministic (no jitter); kept for a uniform signature
     sl, xy, amp, wid, sp = perovskite_atoms()
+    xy = thermal_displacement(xy, 20.0, 20.0, displace_A, displace_seed)
     b = np.nonzero(sp == 1)[0]
     trans = transitions_lm(2)
     L = 20.0
@@ -406,10 +424,13 @@ def random_problem(seed: int, n: int = 32, ny: Optional[int] = None, L: float = 
                    det_inner_mrad: float = 0.0, det_outer_mrad: float = 20.0,
                    n_scan: int = 3, amp=(30.0, 8.0), dz=None, probes=None,
                    energy_eV: float = ENERGY_300KEV, defocus_A: float = 0.0,
-                   cs_A: float = 0.0, widths=(0.3, 0.8)) -> Problem:
+                   cs_A: float = 0.0, widths=(0.3, 0.8), displace_A: float = 0.0,
+                   displace_seed: int = 0) -> Problem:
     """Random atoms and sites on a small periodic cell (test workloads).  `widths`: the two
     Gaussian widths (A) of every atom's projected potential; narrow ones scatter to high
-    angles (a 0.3 A Gaussian sends ~1e-14 of the beam beyond 60 mrad at 300 keV)."""
+    angles (a 0.3 A Gaussian sends ~1e-14 of the beam beyond 60 mrad at 300 keV).
+    displace_A > 0: one frozen-phonon configuration, every atom (and with it its transition
+    potentials) displaced in-plane by N(0, displace_A^2) per axis, seeded by displace_seed."""
     rng = np.random.Generator(np.random.PCG64(seed))
     ny = n if ny is None else ny
     Ly = L if Ly is None else Ly
@@ -419,6 +440,7 @@ def random_problem(seed: int, n: int = 32, ny: Optional[int] = None, L: float = 
     amp_arr = np.tile([list(amp)], (na, 1)) * rng.uniform(0.5, 1.5, (na, 1))
     wid = np.tile([list(widths)], (na, 1))
     sites = rng.choice(na, size=min(n_sites, na), replace=False)
+    a_xy = thermal_displacement(a_xy, L, Ly, displace_A, displace_seed)
     allt = transitions_lm(2)
     trans = [allt[i] for i in rng.choice(len(allt), size=n_trans, replace=False)]
     if probes is None:
