@@ -218,6 +218,22 @@ eels_status eels_execute_images(const eels_plan* p, const float* d_V, const void
 
 eels_status eels_plan_s_signature(const eels_plan* p, uint64_t* sig);
 
+/* Conventional multislice STEM-EELS (Sec. 3, first algorithm) on the same GPU, for comparing
+ * the two algorithms on equal hardware.  For every probe the elastic wave is multisliced;
+ * at the entrance of every ionised slice each transition n of each site spawns the inelastic
+ * wave H_n psi, which is multisliced to the exit plane and summed as |.|^2 over the detector
+ * beams.  Probes are processed probe_chunk at a time (all their inelastic waves at once).
+ * FP32 waves, FP64 map written to d_map [n_probes] (overwritten).  Needs interp_f = 1;
+ * windowed transition potentials are placed into full planes first.  d_workspace: 256-byte
+ * aligned, at least eels_conventional_workspace_bytes(p, probe_chunk) bytes (its own layout:
+ * tables, T_j, P_j, and for one chunk the entrance waves, (1 + n_trans) waves per probe of
+ * ny * ldx complex64 and their exit band coefficients), caller-owned; 0 is returned for
+ * probe_chunk < 1.  Errors: INVALID_ARG for null pointers, probe_chunk < 1 or interp_f > 1,
+ * WORKSPACE for a small or misaligned workspace, DEVICE for a failed launch. */
+size_t eels_conventional_workspace_bytes(const eels_plan* p, int probe_chunk);
+eels_status eels_conventional_map(const eels_plan* p, const float* d_V, const void* d_H, double* d_map,
+                                  int probe_chunk, void* d_workspace, size_t workspace_bytes, void* stream);
+
 /* Diagnostics (same workspace contract).  Write the real-space rows of S_1(j)
  * (scaled by nx*ny, i.e. unit-modulus plane waves at j = 0) as complex64
  * [N_1][ny][nx], or of S_2(j) as complex64 [N_2][ny][nx]. */

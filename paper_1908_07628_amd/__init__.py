@@ -14,6 +14,7 @@ from .eels import (  # noqa: F401
     bf_corrected,
     load_library,
     solve,
+    solve_conventional,
     solve_with_images,
 )
 

@@ -136,7 +136,7 @@ eels_status check_ws(const Plan& p, void* ws, size_t bytes) {
 eels_status setup(const Plan& p, const Dev& d, const float* dV, hipStream_t st, bool upload = true) {
     TimeScope ts(EELS_PHASE_SETUP, st);
     if (upload)
-        HIPCHK(hipMemcpyAsync(d.ws + p.off_blob, p.blob.data(), p.blob.size() * 4, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync((void*)d.blob, p.blob.data(), p.blob.size() * 4, hipMemcpyHostToDevice, st));
     launch_twiddles(d.twx, p.nx, st);
     launch_twiddles(d.twy, p.ny, st);
     launch_transmission(d.T, dV, (int64_t)p.nz * p.ny * p.nx, p.sigma, st);
@@ -356,6 +356,32 @@ void finish_map(const Plan& p, const Dev& d, double* map, hipStream_t st) {
     launch_quadform(map, p.P, d.gtot, p.N1, d.C, p.N1pad, d.qpart, scale, st);
 }
 
+// Workspace of the conventional multislice: its own compact layout (tables, T, P, the
+// elastic and inelastic waves of one probe chunk), none of the scattering-matrix buffers.
+struct ConvLayout {
+    size_t blob, twx, twy, T, P, Hfull, psi, waves, exit_band, wnorm, total;
+};
+
+ConvLayout conv_layout(const Plan& p, int chunk) {
+    ConvLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += (size_t)round_up((int64_t)std::max<size_t>(bytes, 16), 256); return o; };
+    const size_t c8 = 8, plane = (size_t)p.ny * p.ldx;
+    const size_t n_inel = (size_t)chunk * p.n_trans_all;
+    L.blob = take(p.blob.size() * 4);
+    L.twx = take(c8 * p.nx);
+    L.twy = take(c8 * p.ny);
+    L.T = take(c8 * (size_t)p.nz * p.ny * p.nx);
+    L.P = take(c8 * (size_t)p.nz * p.ny * p.nlx);
+    L.Hfull = take(p.full_window ? 16 : c8 * (size_t)p.n_trans_all * p.ny * p.nx);
+    L.psi = take(c8 * (size_t)chunk * p.ny * p.nx);
+    L.waves = take(c8 * ((size_t)chunk + n_inel) * plane);
+    L.exit_band = take(c8 * n_inel * p.Kbpad);
+    L.wnorm = take(8 * n_inel);
+    L.total = off;
+    return L;
+}
+
 }  // namespace
 }  // namespace eels
 
@@ -545,6 +571,142 @@ eels_status eels_execute_images(const eels_plan* pl, const float* d_V, const voi
         rev_next = g.j_lo - 1;
     }
     finish_map(p, d, d_map, st);
+    HIPCHK(hipGetLastError());
+    return EELS_OK;
+}
+
+size_t eels_conventional_workspace_bytes(const eels_plan* pl, int probe_chunk) {
+    if (!pl || probe_chunk < 1) return 0;
+    return conv_layout(pl->p, probe_chunk).total;
+}
+
+// Conventional multislice EELS map.  Per chunk of probes, slice by slice:
+//   row pass of the elastic waves (capturing their real-space entrance wave psi at an
+//     ionised slice) and of the inelastic waves alive so far;
+//   at an ionised slice, each site's transitions spawn T_j H_n psi through the row stage
+//     of the band FFT (the same result as a row pass of H_n psi), appended to the waves;
+//   column pass (x P_j) of all waves; the last slice's captures the exit band of the
+//     inelastic waves, whose detector sums give the map.
+// The elastic wave stops after the last ionised slice.
+eels_status eels_conventional_map(const eels_plan* pl, const float* d_V, const void* d_H, double* d_map,
+                                  int probe_chunk, void* d_workspace, size_t workspace_bytes, void* stream) {
+    if (!pl || !d_V || !d_map || probe_chunk < 1) {
+        set_error("null argument or probe_chunk < 1");
+        return EELS_ERR_INVALID_ARG;
+    }
+    const Plan& p = pl->p;
+    if (p.f != 1) {
+        set_error("conventional multislice needs interp_f = 1");
+        return EELS_ERR_INVALID_ARG;
+    }
+    if (p.n_trans_total > 0 && !d_H) {
+        set_error("transition potentials missing");
+        return EELS_ERR_INVALID_ARG;
+    }
+    const ConvLayout L = conv_layout(p, probe_chunk);
+    if (!d_workspace || workspace_bytes < L.total) {
+        set_error("workspace smaller than eels_conventional_workspace_bytes");
+        return EELS_ERR_WORKSPACE;
+    }
+    if (((uintptr_t)d_workspace) & 255) {
+        set_error("workspace must be 256-byte aligned");
+        return EELS_ERR_WORKSPACE;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    char* ws = (char*)d_workspace;
+    Dev d{};
+    d.ws = ws;
+    d.blob = (const int*)(ws + L.blob);
+    d.b1 = (const int4*)(d.blob + p.b1_off);
+    d.dz = (const double*)(d.blob + p.dz_off);
+    d.probes = (const double*)(d.blob + p.probes_off);
+    d.band_h = d.blob + p.band_h_off;
+    d.band_off = d.blob + p.band_off_off;
+    d.twx = (float2*)(ws + L.twx);
+    d.twy = (float2*)(ws + L.twy);
+    d.T = (float2*)(ws + L.T);
+    d.P = (float2*)(ws + L.P);
+    float2* psi = (float2*)(ws + L.psi);
+    float2* waves = (float2*)(ws + L.waves);
+    float2* exit_band = (float2*)(ws + L.exit_band);
+    double* wnorm = (double*)(ws + L.wnorm);
+    g_timing.used = 0;
+    eels_status s = setup(p, d, d_V, st);
+    if (s) return s;
+    const int64_t plane_nx = (int64_t)p.nx * p.ny, plane = (int64_t)p.ny * p.ldx;
+    const float2* Hb = (const float2*)d_H;
+    std::vector<int64_t> site_plane(p.sites.size(), 0);   // first H plane of each site
+    {
+        int64_t acc = 0;
+        for (size_t k = 0; k < p.sites.size(); ++k) {
+            site_plane[k] = p.full_window ? p.sites[k].h_offset : acc;
+            acc += p.sites[k].n_trans;
+        }
+    }
+    if (!p.full_window && p.n_trans_all > 0) {
+        TimeScope ts(EELS_PHASE_SETUP, st);
+        launch_conv_scatter_h((float2*)(ws + L.Hfull), Hb, d.blob + p.conv_org_off, p.n_trans_all, p, st);
+        Hb = (const float2*)(ws + L.Hfull);
+    }
+    std::vector<std::vector<int>> by_slice(p.nz);
+    int j_last = -1;
+    for (size_t k = 0; k < p.sites.size(); ++k)
+        if (p.sites[k].n_trans > 0) {
+            by_slice[p.sites[k].slice].push_back((int)k);
+            j_last = std::max(j_last, p.sites[k].slice);
+        }
+    launch_fill_zero_d(d_map, p.P, st);
+    for (int p0 = 0; p0 < p.P && j_last >= 0; p0 += probe_chunk) {
+        const int Ni = std::min(probe_chunk, p.P - p0);
+        float2* inel = waves + (int64_t)Ni * plane;
+        int64_t n_inel = 0;
+        {
+            TimeScope ts(EELS_PHASE_SWEEP, st);
+            launch_conv_init(waves, Ni, p0, p, d.blob + p.col_ptr_off, d.blob + p.col_beam_off, d.b1, d.probes, st);
+        }
+        for (int j = 0; j < p.nz; ++j) {
+            const bool ion = !by_slice[j].empty();
+            {
+                TimeScope ts(EELS_PHASE_SWEEP, st);
+                if (j <= j_last) {
+                    RowPassArgs a{waves, Ni, p.ny, p.nlx, p.hlx, Tj(p, d, j), d.twx, nullptr, nullptr, psi, Ni,
+                                  (int)plane_nx, 0, p.ldx};
+                    if (ion) {
+                        a.cap_ptr = d.blob + p.dbg_ptr;
+                        a.cap_rec = d.blob + p.dbg_rec;
+                    }
+                    launch_row_pass(p.nx, 0, a, st);
+                }
+                if (n_inel > 0) {
+                    RowPassArgs a{inel, (int)n_inel, p.ny, p.nlx, p.hlx, Tj(p, d, j), d.twx, nullptr, nullptr, nullptr,
+                                  0, 0, 0, p.ldx};
+                    launch_row_pass(p.nx, 0, a, st);
+                }
+            }
+            if (ion) {
+                TimeScope ts(EELS_PHASE_PRODUCER, st);
+                for (int k : by_slice[j]) {
+                    const int nt = p.sites[k].n_trans;
+                    launch_band_rows(inel + n_inel * plane, psi, plane_nx, Ni, nt, p, Tj(p, d, j),
+                                     Hb + site_plane[k] * plane_nx, plane_nx, d.twx, st);
+                    n_inel += (int64_t)nt * Ni;
+                }
+            }
+            TimeScope ts(EELS_PHASE_SWEEP, st);
+            if (j == p.nz - 1) {
+                if (n_inel > 0)
+                    launch_col_pass(p.ny, 0, inel, (int)n_inel, p.nlx, p.ldx, Pj(p, d, j), d.twy,
+                                    BandCap{d.band_h, d.band_off, exit_band, p.Kbpad, 0}, st);
+            } else if (j < j_last) {
+                launch_col_pass(p.ny, 0, waves, (int)(Ni + n_inel), p.nlx, p.ldx, Pj(p, d, j), d.twy, BandCap{}, st);
+            } else if (n_inel > 0) {
+                launch_col_pass(p.ny, 0, inel, (int)n_inel, p.nlx, p.ldx, Pj(p, d, j), d.twy, BandCap{}, st);
+            }
+        }
+        TimeScope ts(EELS_PHASE_REDUCE, st);
+        launch_conv_norm(wnorm, exit_band, p.Kbpad, p.Kb, d.blob + p.det_mask_off, n_inel, st);
+        launch_conv_map(d_map + p0, wnorm, Ni, n_inel / Ni, st);
+    }
     HIPCHK(hipGetLastError());
     return EELS_OK;
 }

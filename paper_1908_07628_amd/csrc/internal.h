@@ -117,6 +117,10 @@ struct Plan {
     std::vector<double> img_in, img_out;        // their ring angles (rad; out < 0: band limit)
     int img_desc = -1;                          // descriptor of the images' Gram GEMM
     int64_t img_mask_off = -1;                  // int offset: per band slot, bit d = inside ring d
+    int64_t det_mask_off = -1;                  // int offset: per band slot, 1 = EELS detector beam
+    int64_t col_ptr_off = -1, col_beam_off = -1;// aperture beams grouped by live column (CSR)
+    int n_trans_all = 0;                        // transitions of all sites
+    int64_t conv_org_off = -1;                  // per site transition plane: (H row, x0, y0, 0) of its window
     int N2p;                                    // N_2 rounded up to 16 (row blocks of Z^T)
     std::vector<int> site_w1, site_w2;          // window index of each site (S_1 group-local, S_2 slice-local)
     std::vector<int> site_ix0, site_iy0;

@@ -59,6 +59,10 @@ void launch_probe_coefficients(void* C, const int4* beams, const double* probes,
 void launch_init_band(void* bcap, int64_t bstride, const int4* beams, const int* band_h, const int* band_off,
                       const Plan& p, int sc, hipStream_t st);
 void launch_band_fft(int nx, int ny, const BandFft& a, hipStream_t st);
+// Row stage of the band FFT alone: rows of FFT_x(T_j * H_t * W_i) (live columns, rows of
+// p.ldx) into out[((t Ni + i) ny + y) ldx]; H planes hstride apart, W planes wstride apart.
+void launch_band_rows(float2* out, const float2* W, int64_t wstride, int Ni, int nt, const Plan& p, const float2* Tj,
+                      const float2* H, int64_t hstride, const float2* tw, hipStream_t st);
 void launch_hmul(void* X, const float2* W, int64_t wstride, const float2* H, int64_t hstride, int Ni, int nt, int K,
                  int ld, int sc, hipStream_t st);
 void launch_init_forward(float2* S, const int4* beams, const Plan& p, hipStream_t st);
@@ -103,5 +107,19 @@ void launch_mask_band(float2* dst, const float2* src, int n_rows, int ld, const 
 // doubles of partial sums (summed in a fixed order).
 void launch_quadform(double* map, int P, double* G, int n1, const float2* C, int ldc, double* qpart,
                      double scale, hipStream_t st);
+
+// Conventional multislice (kernels_conv.hip).  Elastic waves of probes p0 .. p0+Ni-1 at the
+// entrance of slice 0 in the hybrid layout; col_ptr / col_beam group the aperture beams by
+// live column.
+void launch_conv_init(float2* state, int Ni, int p0, const Plan& p, const int* col_ptr, const int* col_beam,
+                      const int4* beams, const double* probes, hipStream_t st);
+// Full-plane copies of windowed transition potentials (org: int4 per plane, see Plan).
+void launch_conv_scatter_h(float2* Hfull, const float2* H, const int* org, int n_planes, const Plan& p,
+                           hipStream_t st);
+// wnorm[w] = sum over band slots g < Kb with mask[g] of |exit[w * stride + g]|^2 (FP64).
+void launch_conv_norm(double* wnorm, const float2* exit_band, int64_t stride, int Kb, const int* mask, int64_t n_waves,
+                      hipStream_t st);
+// map[i] = sum over k < n_k of wnorm[k Ni + i].
+void launch_conv_map(double* map, const double* wnorm, int Ni, int64_t n_k, hipStream_t st);
 
 }  // namespace eels

@@ -620,6 +620,30 @@ void launch_band_fft(int nx, int ny, const BandFft& a, hipStream_t st) {
 #undef BF
 }
 
+template <int NX>
+static void band_rows_n(float2* out, const float2* W, int64_t wstride, int Ni, int nt, const Plan& p,
+                        const float2* Tj, const float2* H, int64_t hstride, const float2* tw, hipStream_t st) {
+    constexpr int S = 256 / RegCfg<NX>::T;
+    int64_t rows = (int64_t)Ni * p.ny;
+    hipLaunchKernelGGL((k_band_rows<NX>), dim3(blocks_for(rows, S)), dim3(256), 0, st, out, W, wstride, Ni, nt, p.ny,
+                       p.nlx, p.hlx, p.ldx, Tj, H, hstride, tw);
+}
+
+void launch_band_rows(float2* out, const float2* W, int64_t wstride, int Ni, int nt, const Plan& p, const float2* Tj,
+                      const float2* H, int64_t hstride, const float2* tw, hipStream_t st) {
+    if ((int64_t)Ni * nt <= 0) return;
+    switch (p.nx) {
+        case 16: band_rows_n<16>(out, W, wstride, Ni, nt, p, Tj, H, hstride, tw, st); break;
+        case 32: band_rows_n<32>(out, W, wstride, Ni, nt, p, Tj, H, hstride, tw, st); break;
+        case 64: band_rows_n<64>(out, W, wstride, Ni, nt, p, Tj, H, hstride, tw, st); break;
+        case 128: band_rows_n<128>(out, W, wstride, Ni, nt, p, Tj, H, hstride, tw, st); break;
+        case 256: band_rows_n<256>(out, W, wstride, Ni, nt, p, Tj, H, hstride, tw, st); break;
+        case 512: band_rows_n<512>(out, W, wstride, Ni, nt, p, Tj, H, hstride, tw, st); break;
+        case 1024: band_rows_n<1024>(out, W, wstride, Ni, nt, p, Tj, H, hstride, tw, st); break;
+        default: break;
+    }
+}
+
 void launch_hmul(void* X, const float2* W, int64_t wstride, const float2* H, int64_t hstride, int Ni, int nt, int K,
                  int ld, int sc, hipStream_t st) {
     int64_t n = (int64_t)nt * Ni * ld;

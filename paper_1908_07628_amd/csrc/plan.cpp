@@ -676,6 +676,43 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
         ptr[0] = 0;
         p.dbg_ptr = B.append(ptr);
         p.dbg_rec = B.append(rec);
+        {
+            // EELS detector beams among the band slots, and the aperture beams by live column
+            // (conventional multislice)
+            std::vector<int32_t> dm(p.Kbpad, 0);
+            for (int c = 0; c < p.nlx; ++c) {
+                int cs = p.nlx == p.nx ? (c < (p.nx + 1) / 2 ? c : c - p.nx) : (c <= p.hlx ? c : c - p.nlx);
+                int h = p.band_h[c];
+                for (int r = 0; r <= 2 * h; ++r) {
+                    int ks = r <= h ? r : -(2 * h + 1 - r);
+                    double kx = cs / p.lx, ky = ks / p.ly;
+                    double th = p.lam * std::sqrt(kx * kx + ky * ky);
+                    dm[p.band_off[c] + r] = (th >= p.beta_in && th <= p.beta_out) ? 1 : 0;
+                }
+            }
+            p.det_mask_off = B.append(dm);
+            std::vector<int32_t> ptr(p.nlx + 1, 0), beams;
+            std::vector<std::vector<int32_t>> by_col(p.nlx);
+            for (int b = 0; b < p.N1; ++b) by_col[live_col(imod((long long)p.f * p.ab1[2 * b], p.nx))].push_back(b);
+            for (int c = 0; c < p.nlx; ++c) {
+                beams.insert(beams.end(), by_col[c].begin(), by_col[c].end());
+                ptr[c + 1] = (int32_t)beams.size();
+            }
+            p.col_ptr_off = B.append(ptr);
+            p.col_beam_off = B.append(beams.empty() ? std::vector<int32_t>{0} : beams);
+            p.n_trans_all = 0;
+            std::vector<int32_t> org;
+            for (size_t s = 0; s < p.sites.size(); ++s) {
+                p.n_trans_all += p.sites[s].n_trans;
+                for (int t = 0; t < p.sites[s].n_trans; ++t) {
+                    org.push_back(p.sites[s].h_offset + t);
+                    org.push_back(imod((long long)p.site_ix0[s] - p.hwx, p.nx));
+                    org.push_back(imod((long long)p.site_iy0[s] - p.hwy, p.ny));
+                    org.push_back(0);
+                }
+            }
+            p.conv_org_off = B.append(org.empty() ? std::vector<int32_t>{0, 0, 0, 0} : org);
+        }
         if (p.n_img > 0) {
             p.img_mask_off = B.append(img_mask);
             // Gram GEMM of the companion images: G[k][k'] = sum_g conj(X[k][g]) X[k'][g] over the

@@ -64,7 +64,8 @@ EXPORTS = ["eels_get_version", "eels_status_string", "eels_last_error", "eels_pl
            "eels_plan_workspace_bytes", "eels_plan_info_get", "eels_plan_beams", "eels_plan_destroy",
            "eels_execute", "eels_debug_s1", "eels_debug_s2", "eels_gemm_work_bytes", "eels_debug_cgemm",
            "eels_tune_set", "eels_tune_get", "eels_timing_enable", "eels_timing_read", "eels_execute_ex",
-           "eels_plan_s_signature", "eels_execute_images"]
+           "eels_plan_s_signature", "eels_execute_images", "eels_conventional_workspace_bytes",
+           "eels_conventional_map"]
 EXEC_SKIP_UPLOAD, EXEC_SKIP_SWEEPS = 1, 2
 PHASES = ["setup", "sweep", "producer", "gemm1", "gemm2", "reduce", "images"]
 
@@ -89,6 +90,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.eels_execute_ex.argtypes = [vp, vp, vp, vp, vp, sz, vp, C.c_uint]
     lib.eels_execute_images.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp, C.c_uint]
     lib.eels_plan_s_signature.argtypes = [vp, C.POINTER(C.c_uint64)]
+    lib.eels_conventional_workspace_bytes.argtypes = [vp, C.c_int]
+    lib.eels_conventional_workspace_bytes.restype = sz
+    lib.eels_conventional_map.argtypes = [vp, vp, vp, vp, C.c_int, vp, sz, vp]
     lib.eels_debug_s1.argtypes = [vp, vp, C.c_int, vp, vp, sz, vp]
     lib.eels_debug_s2.argtypes = [vp, vp, C.c_int, vp, vp, sz, vp]
     lib.eels_gemm_work_bytes.argtypes = [C.c_int, C.c_int, C.c_int]
@@ -210,6 +214,26 @@ class Plan:
                                                   _ptr(workspace), workspace.numel(), _stream(stream),
                                                   int(flags)))
 
+    def conventional_workspace_bytes(self, probe_chunk: int) -> int:
+        return int(load_library().eels_conventional_workspace_bytes(self._h, int(probe_chunk)))
+
+    def conventional_map(self, V, H, out_map, probe_chunk: int, workspace, stream=None):
+        """Enqueue the conventional multislice map (Sec. 3, first algorithm; interp_f = 1),
+        probe_chunk probes at a time, into out_map (float64 [P])."""
+        _check(load_library().eels_conventional_map(self._h, _ptr(V), _ptr(H), _ptr(out_map), int(probe_chunk),
+                                                    _ptr(workspace), workspace.numel(), _stream(stream)))
+
+    def conventional_chunk(self, max_bytes: int) -> int:
+        """Largest probe chunk whose conventional workspace fits max_bytes (at least 1)."""
+        lo, hi = 1, max(1, self.n_probes)
+        while lo < hi:
+            mid = (lo + hi + 1) // 2
+            if self.conventional_workspace_bytes(mid) <= max_bytes:
+                lo = mid
+            else:
+                hi = mid - 1
+        return lo
+
     def s_signature(self) -> int:
         v = C.c_uint64()
         _check(load_library().eels_plan_s_signature(self._h, C.byref(v)))
@@ -249,6 +273,25 @@ def solve(problem, precision: str = "fp32", order: str = "auto", device="cuda",
     ws = plan.alloc_workspace(device)
     out = torch.empty(plan.n_probes, dtype=torch.float64, device=device)
     plan.execute(V, H, out, ws)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def solve_conventional(problem, probe_chunk: int = 0, device="cuda", max_bytes: int = 0) -> np.ndarray:
+    """EELS map by conventional multislice on the GPU (interp_f = 1), float64 numpy [n_probes].
+    probe_chunk 0: as many probes at a time as fit max_bytes (default: half the free
+    device memory)."""
+    import torch
+    plan = Plan(problem)
+    if probe_chunk <= 0:
+        if max_bytes <= 0:
+            free, _ = torch.cuda.mem_get_info()
+            max_bytes = free // 2
+        probe_chunk = plan.conventional_chunk(max_bytes)
+    V, H = device_inputs(problem, device)
+    ws = torch.empty(plan.conventional_workspace_bytes(probe_chunk), dtype=torch.uint8, device=device)
+    out = torch.empty(plan.n_probes, dtype=torch.float64, device=device)
+    plan.conventional_map(V, H, out, probe_chunk, ws)
     torch.cuda.synchronize()
     return out.cpu().numpy()
 

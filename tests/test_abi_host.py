@@ -195,3 +195,25 @@ def test_band_table_matches_oracle_mask():
     for p in (synth.config1(), synth.random_problem(3, n=32, ny=64, L=8.0, Ly=13.0, nz=2)):
         inf = eels.Plan(p).info()
         assert inf["band_pixels"] == int(ph.band_mask(p.nx, p.ny, p.lx, p.ly).sum())
+
+
+def test_conventional_entry_host_checks():
+    """Conventional multislice: the workspace grows with the probe chunk by whole wave sets,
+    and plans it cannot run (f > 1) or a missing workspace are refused before any device
+    work."""
+    import ctypes as C
+    lib = _lib()
+    p = synth.random_problem(4, n=32, nz=3, n_sites=2, n_trans=2)
+    plan = eels.Plan(p)
+    w1, w2, w3 = (plan.conventional_workspace_bytes(c) for c in (1, 2, 3))
+    assert 0 < w1 < w2 < w3
+    assert plan.conventional_workspace_bytes(0) == 0
+    assert plan.conventional_chunk(w2) == 2 and plan.conventional_chunk(w2 - 1) == 1
+    dummy = C.c_void_p(256)   # never dereferenced: the call fails its checks first
+    st = lib.eels_conventional_map(plan._h, dummy, dummy, dummy, 2, None, 0, None)
+    assert st == 4   # EELS_ERR_WORKSPACE
+    q = synth.random_problem(4, n=64, L=16.0, nz=3, n_sites=2, n_trans=2, interp_f=2, window_A=3.0)
+    plan2 = eels.Plan(q)
+    st = lib.eels_conventional_map(plan2._h, dummy, dummy, dummy, 2, dummy, 1 << 40, None)
+    assert st == 1   # EELS_ERR_INVALID_ARG
+    assert "interp_f" in lib.eels_last_error().decode()
