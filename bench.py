@@ -235,6 +235,8 @@ def main():
     ap.add_argument("--profile-sample", type=int, default=0, metavar="N",
                     help="for counter runs: a 1 GiB device copy (calibration), then one map on the "
                          "top N ionised slices; prints one line")
+    ap.add_argument("--conv-probes", type=int, default=32,
+                    help="probes of the conventional-multislice comparison (0: skip)")
     ap.add_argument("--n-specimens", type=int, default=64)
     ap.add_argument("--pool", type=int, default=10)
     ap.add_argument("--n-requests", type=int, default=40)
@@ -399,6 +401,59 @@ def main():
         "workspace_GB_exact": round(ws0 / 1e9, 2), "workspace_GB_inverse": round(wsv / 1e9, 2),
     }
 
+    # Conventional multislice (Sec. 3, first algorithm) on the same GPU and the same specimen:
+    # every transition's inelastic wave of every probe multisliced to the exit, on a block of
+    # probes (its cost per probe does not depend on the probe)
+    conv = None
+    if args.conv_probes > 0:
+        idx = np.arange(args.conv_probes) * (p.n_probes // args.conv_probes)
+        q = p.replace(probes=p.probes[idx], probe_shape=(1, len(idx)))
+        cplan = eels.Plan(q)
+        torch.cuda.empty_cache()
+        free_now, _ = torch.cuda.mem_get_info()
+        chunk = min(len(idx), cplan.conventional_chunk(int(0.7 * free_now)))
+        wsc = torch.empty(cplan.conventional_workspace_bytes(chunk), dtype=torch.uint8, device="cuda")
+        oc = torch.empty(len(idx), dtype=torch.float64, device="cuda")
+        eels.timing_enable(8192)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        cplan.conventional_map(V, H, oc, chunk, wsc)
+        torch.cuda.synchronize()
+        dtc = time.perf_counter() - t1
+        phc = eels.timing_read()
+        eels.timing_enable(0)
+        del wsc
+        mc = oc.cpu().numpy()
+        # algorithmic HBM bytes: every row or column pass reads and writes one wave plane of
+        # n_y x n_live_x complex64 (elastic: rows of slices 0..j_last, columns of 0..j_last-1;
+        # a transition of slice s: columns of s..n_z-1, rows of s+1..n_z-1); the entrance wave
+        # written once per ionised slice and read once per site; H read once per chunk; the
+        # new waves written; the exit band coefficients written
+        nlx = info["n_live_x"]
+        plane = 8.0 * p.ny * nlx
+        full = 8.0 * p.nx * p.ny
+        n_c = len(idx)
+        j_last = int(np.max(p.site_slice))
+        nt_s = p.site_ntrans.astype(np.float64)
+        passes = n_c * (2 * j_last + 1 + float(np.sum(nt_s * (2 * (p.n_slices - p.site_slice) - 1))))
+        n_ion = len(set(p.site_slice.tolist()))
+        spawn = n_c * (n_ion * full + p.n_sites * full + nt_s.sum() * plane) + \
+            -(-n_c // chunk) * nt_s.sum() * full
+        conv_bytes = 2.0 * plane * passes + spawn + n_c * nt_s.sum() * 8.0 * info["band_pixels"]
+        conv_rate = len(idx) / dtc
+        conv = {
+            "measured_on": f"{len(idx)} probes of the raster, {chunk} at a time, all {p.n_sites} sites",
+            "value": round(conv_rate, 3), "unit": "probe-px/s", "ms": round(1e3 * dtc, 1),
+            "phases_ms": {k: round(v["ms"], 1) for k, v in phc.items() if v["count"]},
+            "prism_speedup": round(value / conv_rate, 2),
+            "prism_fp32_speedup": None,
+            "map_rel_l2_vs_prism": float(np.linalg.norm(mc - gpu_map[idx]) / np.linalg.norm(gpu_map[idx])),
+            "hbm": {"achieved": round(conv_bytes / dtc / 1e9, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                    "frac": round(conv_bytes / dtc / 1e9 / PEAK_HBM_GBPS, 4),
+                    "byte_definition": ("read + write of 8 B x n_y x n_live_x per row or column pass of a "
+                                        "wave, entrance waves, H once per chunk, new waves, exit band")},
+        }
+
     # FP32 plain path
     if args.fp32_full:
         p32 = eels.Plan(p, precision="fp32")
@@ -436,6 +491,8 @@ def main():
         }
         del ws32
 
+    if conv is not None:
+        conv["prism_fp32_speedup"] = round(fp32["value"] / conv["value"], 2)
     result = {
         "metric": METRIC, "value": round(value, 3), "unit": "probe-px/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 1), "higher_is_better": True, "scaling": "weak",
@@ -450,6 +507,7 @@ def main():
         "roofline_fft": roofline_fft,
         "companion_images": companion,
         "inverse_multislice": inverse,
+        "conventional_multislice": conv,
         "phases_ms": phases,
         "fp32": fp32,
         "split_over_fp32": round(value / fp32["value"], 2),
