@@ -32,7 +32,7 @@ namespace eels {
 static thread_local std::string g_err;
 void set_error(const std::string& m) { g_err = m; }
 
-static std::atomic<int> g_tune[TUNE_COUNT] = {{2}, {2}, {0}, {0}, {0}, {0}, {0}, {0}};
+static std::atomic<int> g_tune[TUNE_COUNT] = {{2}, {2}, {0}, {1}, {0}, {0}, {0}, {0}};
 int tune_get(int key) { return (key >= 0 && key < TUNE_COUNT) ? g_tune[key].load() : 0; }
 
 // Diagnostic phase timing (eels_timing_enable / eels_timing_read).
@@ -258,7 +258,7 @@ void contract(const Plan& p, const Dev& d, const float2* dH, double* map, int bi
     const int nst = tune_get(TUNE_SC_STAGES);
     const bool h_pro = !p.recip;   // FP32 real-space: H applied in the GEMM prologue
     if (p.gram) {
-        // Gram form: Z^T = (H S_1) S_2^T per site, then the upper tiles of Z^H Z, summed
+        // Gram form: Z = (H S_1) S_2^T per site, then the upper tiles of Z^H Z, summed
         // over the batch's sites into G in FP64
         run_jobs(p, d, dH, b, b.slice, st);
         {
@@ -822,6 +822,7 @@ eels_status eels_tune_set(int key, int value) {
     if (key == TUNE_SC_STAGES && (value < 2 || value > 5)) return EELS_ERR_INVALID_ARG;
     if (key == TUNE_TILE_ORDER && (value < 0 || value > 2)) return EELS_ERR_INVALID_ARG;
     if (key == TUNE_SC_SCHED && (value < 0 || value > 3)) return EELS_ERR_INVALID_ARG;
+    if (key == TUNE_GRAM_STACK && (value < 0 || value > 1)) return EELS_ERR_INVALID_ARG;
     g_tune[key].store(value);
     return EELS_OK;
 }

@@ -15,8 +15,11 @@
 
 namespace eels {
 
+// The fused form is written out, so every kernel that inlines it rounds the same way
+// (left to contraction, the compiler may fuse either product depending on the code
+// around it, and variants of one pass would then differ in the last bit).
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+    return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }

@@ -6,6 +6,9 @@
 // stage's outputs j + r N / R (j = t + b T) are again t + T (b + r E / R).  Middle
 // stages exchange through lds[base + i * es] with a barrier on each side, so every
 // thread of the block must call the transform the same number of times.
+// PAD (es = 1 only): element i sits at lds[base + i + i / 16].  A contiguous sequence's first
+// exchange writes elements 16 t + r from thread t; unpadded, all lanes of a wave would hit one
+// LDS bank, padded they spread over all banks.  The sequence then needs N + N / 16 slots.
 // DIR = -1: forward exp(-2 pi i n k / N); DIR = +1: unnormalised inverse.
 #pragma once
 
@@ -57,9 +60,10 @@ struct RegRadix {
 };
 
 // stage with butterfly radix R on elements in registers (first stage) or LDS (later)
-template <int N, int E, int DIR, int Ns>
+template <int N, int E, int DIR, int Ns, bool PAD>
 __device__ __forceinline__ void fft_reg_stages(float2 (&v)[E], float2* lds, int base, int es, int t,
                                                const float2* __restrict__ tw) {
+    auto at = [&](int i) -> float2& { return PAD ? lds[base + i + (i >> 4)] : lds[base + i * es]; };
     constexpr int T = N / E;
     constexpr int R = (Ns == 1) ? E : RegRadix<N, Ns, E>::R;
     constexpr int NB = E / R;
@@ -75,7 +79,7 @@ __device__ __forceinline__ void fft_reg_stages(float2 (&v)[E], float2* lds, int 
         for (int b = 0; b < NB; ++b) {
             int j = t + b * T;
 #pragma unroll
-            for (int r = 0; r < R; ++r) u[b][r] = lds[base + (j + r * (N / R)) * es];
+            for (int r = 0; r < R; ++r) u[b][r] = at(j + r * (N / R));
         }
     }
 #pragma unroll
@@ -105,17 +109,23 @@ __device__ __forceinline__ void fft_reg_stages(float2 (&v)[E], float2* lds, int 
             int k = j & (Ns - 1);
             int idxD = (j - k) * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) lds[base + (idxD + r * Ns) * es] = u[b][r];
+            for (int r = 0; r < R; ++r) at(idxD + r * Ns) = u[b][r];
         }
         __syncthreads();
-        fft_reg_stages<N, E, DIR, Ns * R>(v, lds, base, es, t, tw);
+        fft_reg_stages<N, E, DIR, Ns * R, PAD>(v, lds, base, es, t, tw);
     }
 }
 
-template <int N, int DIR>
+template <int N, int DIR, bool PAD = false>
 __device__ __forceinline__ void fft_reg(float2 (&v)[RegCfg<N>::E], float2* lds, int base, int es, int t,
                                         const float2* __restrict__ tw) {
-    fft_reg_stages<N, RegCfg<N>::E, DIR, 1>(v, lds, base, es, t, tw);
+    fft_reg_stages<N, RegCfg<N>::E, DIR, 1, PAD>(v, lds, base, es, t, tw);
 }
+
+// LDS slots of one padded contiguous sequence
+template <int N>
+struct PadLen {
+    static constexpr int value = N + N / 16;
+};
 
 }  // namespace eels

@@ -42,7 +42,7 @@ enum { GD_ZERO_PAD = 1 };
 static_assert(sizeof(GemmDesc) == 144, "GemmDesc layout");
 
 // Process-wide tuning knobs (set by eels_tune_set; read at launch time).
-enum TuneKey { TUNE_SC_STAGES = 0, TUNE_TILE_ORDER = 1, TUNE_SC_SCHED = 2, TUNE_COUNT = 8 };
+enum TuneKey { TUNE_SC_STAGES = 0, TUNE_TILE_ORDER = 1, TUNE_SC_SCHED = 2, TUNE_GRAM_STACK = 3, TUNE_COUNT = 8 };
 int tune_get(int key);
 
 struct Batch {
@@ -121,7 +121,7 @@ struct Plan {
     int64_t col_ptr_off = -1, col_beam_off = -1;// aperture beams grouped by live column (CSR)
     int n_trans_all = 0;                        // transitions of all sites
     int64_t conv_org_off = -1;                  // per site transition plane: (H row, x0, y0, 0) of its window
-    int N2p;                                    // N_2 rounded up to 16 (row blocks of Z^T)
+    int N2p;                                    // N_2 rounded up to 16 (row length of Z)
     std::vector<int> site_w1, site_w2;          // window index of each site (S_1 group-local, S_2 slice-local)
     std::vector<int> site_ix0, site_iy0;
     std::vector<std::vector<int>> site_probes;  // eligible probes (empty vector + flag = all)

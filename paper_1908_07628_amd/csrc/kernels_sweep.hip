@@ -16,6 +16,7 @@
 // scale of its definition and S_1 at nx*ny times it (unit-modulus plane waves at j = 0).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "fft_lds.h"
@@ -211,69 +212,105 @@ __global__ void k_copy(float2* dst, const float2* src, int64_t n) {
 
 // --------------------------------------------------------------------- row pass
 //
-// T = N/16 threads per row, 16 elements each (pixel / column t + T m in v[m]); a block
-// holds S = 256/T rows of the flat row index g = beam * ny + y.  Loads and stores go
-// straight between HBM and registers; only the middle FFT stages use LDS.
+// T = N/16 threads per row, 16 elements each (pixel / column t + T m in v[m]); a group of
+// S = 256/T rows of the flat row index g = beam * ny + y per block iteration.  Loads and
+// stores go straight between HBM and registers; only the middle FFT stages use LDS.  A
+// block walks the row groups blockIdx.x, blockIdx.x + gridDim.x, ... and loads the next
+// group's rows into registers while it transforms the current one, so HBM traffic
+// overlaps the FFT arithmetic of the same wave (the grid is capped, see row_grid).
 // mode 0: forward sweep (iFFT_x, capture, x T, FFT_x); mode 1: transposed sweep (FFT_x, x T,
 // capture, iFFT_x); mode 2: inverse multislice, Eq. MSinvop (iFFT_x, x conj(T), capture the
-// slice's entrance wave, FFT_x).
-template <int N, int MODE>
-__global__ __launch_bounds__(256) void k_row_pass(float2* __restrict__ state, int nbeam, int ny, int nlx, int hlx, int ldx,
-                                                  const float2* __restrict__ Tj, const float2* __restrict__ tw,
-                                                  const int* __restrict__ cap_ptr, const int4* __restrict__ cap_rec,
-                                                  void* __restrict__ win, int64_t win_beams, int Kpad, int sc) {
-    constexpr int E = RegCfg<N>::E, T = RegCfg<N>::T, S = 256 / T;
-    __shared__ float2 lds[S * N];
+// slice's entrance wave, FFT_x).  CAP = false: no capture (its code and registers left out).
+template <int N, int MODE, bool CAP>
+__device__ __forceinline__ void row_pass_body(float2* __restrict__ state, int nbeam, int ny, int nlx, int hlx, int ldx,
+                                              const float2* __restrict__ Tj, const float2* __restrict__ tw,
+                                              const int* __restrict__ cap_ptr, const int4* __restrict__ cap_rec,
+                                              void* __restrict__ win, int64_t win_beams, int Kpad, int sc,
+                                              float2* lds) {
+    constexpr int E = RegCfg<N>::E, T = RegCfg<N>::T, S = 256 / T, L = PadLen<N>::value;
     const int tid = threadIdx.x, s = tid / T, t = tid % T;
     const int64_t total = (int64_t)nbeam * ny;
-    const int64_t g = (int64_t)blockIdx.x * S + s;
-    const bool valid = g < total;
-    const int y = valid ? (int)(g % ny) : 0;
-    const int64_t beam = valid ? g / ny : 0;
-    float2 v[E];
+    const int64_t ngroups = (total + S - 1) / S;
+    float2 nxt[E];
+    auto load = [&](int64_t grp) {
+        const int64_t g = grp * S + s;
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-        int c = phys_col_of(t + T * m, N, hlx, ldx);
-        v[m] = (valid && c >= 0) ? state[g * ldx + c] : make_float2(0.f, 0.f);
-    }
-    constexpr int S1 = MODE == 1 ? -1 : +1;   // first transform's sign (+1: inverse FFT_x)
-    fft_reg<N, S1>(v, lds, s * N, 1, t, tw);
-
-    // In mode 2 the column pass's conj(P_j) / (nx ny) leaves this pass's input 1/nx of the
-    // forward row pass's output (the state after the final FFT_x is exact), so the captured
-    // entrance wave is scaled by nx (exact) to match the forward capture.
-    constexpr float cap_scale = MODE == 2 ? (float)N : 1.0f;
-    auto capture = [&]() {
-        if (cap_ptr && valid) {
-            int r0 = cap_ptr[y], r1 = cap_ptr[y + 1];
-            for (int r = r0; r < r1; ++r) {
-                int4 rec = cap_rec[r];
-                int64_t dst = ((int64_t)rec.x * win_beams + beam) * Kpad + (int64_t)rec.y * rec.w;
-#pragma unroll
-                for (int m = 0; m < E; ++m) {
-                    int u = t + T * m - rec.z;
-                    if (u < 0) u += N;
-                    if (u < rec.w) store_c(win, dst + u, make_float2(v[m].x * cap_scale, v[m].y * cap_scale), sc);
-                }
-            }
+        for (int m = 0; m < E; ++m) {
+            int c = phys_col_of(t + T * m, N, hlx, ldx);
+            nxt[m] = (g < total && c >= 0) ? state[g * ldx + c] : make_float2(0.f, 0.f);
         }
     };
-    if constexpr (MODE == 0) capture();
-    const float2* Trow = Tj + (int64_t)y * N;
+    if ((int64_t)blockIdx.x < ngroups) load(blockIdx.x);
+    for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+        float2 v[E];
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-        float2 tv = Trow[t + T * m];
-        if constexpr (MODE == 2) tv.y = -tv.y;
-        v[m] = cmul(v[m], tv);
-    }
-    if constexpr (MODE != 0) capture();
+        for (int m = 0; m < E; ++m) v[m] = nxt[m];
+        const int64_t g = grp * S + s;
+        const bool valid = g < total;
+        const int y = valid ? (int)(g % ny) : 0;
+        const int64_t beam = valid ? g / ny : 0;
+        if (grp + gridDim.x < ngroups) load(grp + gridDim.x);
+        constexpr int S1 = MODE == 1 ? -1 : +1;   // first transform's sign (+1: inverse FFT_x)
+        fft_reg<N, S1, true>(v, lds, s * L, 1, t, tw);
 
-    fft_reg<N, -S1>(v, lds, s * N, 1, t, tw);
+        // In mode 2 the column pass's conj(P_j) / (nx ny) leaves this pass's input 1/nx of the
+        // forward row pass's output (the state after the final FFT_x is exact), so the captured
+        // entrance wave is scaled by nx (exact) to match the forward capture.
+        constexpr float cap_scale = MODE == 2 ? (float)N : 1.0f;
+        auto capture = [&]() {
+            if (CAP && valid) {
+                int r0 = cap_ptr[y], r1 = cap_ptr[y + 1];
+                for (int r = r0; r < r1; ++r) {
+                    int4 rec = cap_rec[r];
+                    int64_t dst = ((int64_t)rec.x * win_beams + beam) * Kpad + (int64_t)rec.y * rec.w;
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-        int c = phys_col_of(t + T * m, N, hlx, ldx);
-        if (valid && c >= 0) state[g * ldx + c] = v[m];
+                    for (int m = 0; m < E; ++m) {
+                        int u = t + T * m - rec.z;
+                        if (u < 0) u += N;
+                        if (u < rec.w)
+                            store_c(win, dst + u, make_float2(v[m].x * cap_scale, v[m].y * cap_scale), sc);
+                    }
+                }
+            }
+        };
+        if constexpr (MODE == 0) capture();
+        const float2* Trow = Tj + (int64_t)y * N;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            float2 tv = Trow[t + T * m];
+            if constexpr (MODE == 2) tv.y = -tv.y;
+            v[m] = cmul(v[m], tv);
+        }
+        if constexpr (MODE != 0) capture();
+
+        fft_reg<N, -S1, true>(v, lds, s * L, 1, t, tw);
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            int c = phys_col_of(t + T * m, N, hlx, ldx);
+            if (valid && c >= 0) state[g * ldx + c] = v[m];
+        }
     }
+}
+
+// Two waves per SIMD without capture (201 VGPRs at N = 256, no spills); the capturing
+// variant keeps the compiler's register budget, where forcing two waves would spill.
+template <int N, int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_row_pass(
+    float2* __restrict__ state, int nbeam, int ny, int nlx, int hlx, int ldx, const float2* __restrict__ Tj,
+    const float2* __restrict__ tw) {
+    __shared__ float2 lds[(256 / RegCfg<N>::T) * PadLen<N>::value];
+    row_pass_body<N, MODE, false>(state, nbeam, ny, nlx, hlx, ldx, Tj, tw, nullptr, nullptr, nullptr, 0, 0, 0, lds);
+}
+
+template <int N, int MODE>
+__global__ __launch_bounds__(256) void k_row_pass_cap(float2* __restrict__ state, int nbeam, int ny, int nlx, int hlx,
+                                                      int ldx, const float2* __restrict__ Tj,
+                                                      const float2* __restrict__ tw, const int* __restrict__ cap_ptr,
+                                                      const int4* __restrict__ cap_rec, void* __restrict__ win,
+                                                      int64_t win_beams, int Kpad, int sc) {
+    __shared__ float2 lds[(256 / RegCfg<N>::T) * PadLen<N>::value];
+    row_pass_body<N, MODE, true>(state, nbeam, ny, nlx, hlx, ldx, Tj, tw, cap_ptr, cap_rec, win, win_beams, Kpad, sc,
+                                 lds);
 }
 
 // --------------------------------------------------------------------- column pass
@@ -289,52 +326,83 @@ struct ColCfg {
     static constexpr int CW = NT / T;
 };
 
-template <int N, int MODE>
-__global__ __launch_bounds__(ColCfg<N>::NT) void k_col_pass(float2* __restrict__ state, int nbeam, int nlx, int ldx,
-                                                            const float2* __restrict__ Pj,
-                                                            const float2* __restrict__ tw,
-                                                            const int* __restrict__ band_h,
-                                                            const int* __restrict__ band_off, void* __restrict__ bcap,
-                                                            int64_t bstride, int sc) {
+template <int N, int MODE, bool CAP>
+__device__ __forceinline__ void col_pass_body(float2* __restrict__ state, int nbeam, int nlx, int ldx,
+                                              const float2* __restrict__ Pj, const float2* __restrict__ tw,
+                                              const int* __restrict__ band_h, const int* __restrict__ band_off,
+                                              void* __restrict__ bcap, int64_t bstride, int sc, float2* lds) {
     using C = ColCfg<N>;
     constexpr int CW = C::CW, T = C::T, E = C::E;
-    __shared__ float2 lds[N * CW];
     const int tid = threadIdx.x;
     const int strips = (ldx + CW - 1) / CW;
-    const int64_t beam = blockIdx.x / strips;
-    const int c0 = (int)(blockIdx.x % strips) * CW;
+    const int64_t items = (int64_t)nbeam * strips;
     const int col = tid % CW, t = tid / CW;
-    const int pc = c0 + col;                                     // physical column (state)
-    const int c = logical_of_phys(pc, nlx, ldx);  // live column (P, band tables)
-    const bool live = c >= 0;
-    float2* plane = state + beam * (int64_t)N * ldx;
-    float2 v[E];
+    // items (beam, strip) walked with stride gridDim.x; the next item's strip is loaded
+    // while the current one is transformed
+    float2 nxt[E];
+    auto load = [&](int64_t it) {
+        const int64_t beam = it / strips;
+        const int pc = (int)(it % strips) * CW + col;
+        const bool live = logical_of_phys(pc, nlx, ldx) >= 0;
+        const float2* plane = state + beam * (int64_t)N * ldx;
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = live ? plane[(int64_t)(t + T * m) * ldx + pc] : make_float2(0.f, 0.f);
-    constexpr int S1 = MODE == 1 ? +1 : -1;   // first transform's sign (-1: FFT_y)
-    fft_reg<N, S1>(v, lds, col, CW, t, tw);
+        for (int m = 0; m < E; ++m) nxt[m] = live ? plane[(int64_t)(t + T * m) * ldx + pc] : make_float2(0.f, 0.f);
+    };
+    if ((int64_t)blockIdx.x < items) load(blockIdx.x);
+    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        float2 v[E];
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-        float2 pv = live ? Pj[(int64_t)(t + T * m) * nlx + c] : make_float2(0.f, 0.f);
-        if constexpr (MODE == 2) pv.y = -pv.y;   // inverse multislice: conj(P)
-        v[m] = cmul(v[m], pv);
-    }
-    if (bcap && live) {
-        // band coefficients of this column: ky = 0..h, then ny-h..ny-1, at band_off[c] + rank
-        const int h = band_h[c];
-        const int64_t dst = beam * bstride + band_off[c];
+        for (int m = 0; m < E; ++m) v[m] = nxt[m];
+        const int64_t beam = it / strips;
+        const int pc = (int)(it % strips) * CW + col;  // physical column (state)
+        const int c = logical_of_phys(pc, nlx, ldx);   // live column (P, band tables)
+        const bool live = c >= 0;
+        float2* plane = state + beam * (int64_t)N * ldx;
+        if (it + gridDim.x < items) load(it + gridDim.x);
+        constexpr int S1 = MODE == 1 ? +1 : -1;   // first transform's sign (-1: FFT_y)
+        fft_reg<N, S1>(v, lds, col, CW, t, tw);
 #pragma unroll
         for (int m = 0; m < E; ++m) {
-            int ky = t + T * m;
-            int r = ky <= h ? ky : (ky >= N - h ? 2 * h + 1 - (N - ky) : -1);
-            if (r >= 0) store_c(bcap, dst + r, v[m], sc);
+            float2 pv = live ? Pj[(int64_t)(t + T * m) * nlx + c] : make_float2(0.f, 0.f);
+            if constexpr (MODE == 2) pv.y = -pv.y;   // inverse multislice: conj(P)
+            v[m] = cmul(v[m], pv);
+        }
+        if (CAP && live) {
+            // band coefficients of this column: ky = 0..h, then ny-h..ny-1, at band_off[c] + rank
+            const int h = band_h[c];
+            const int64_t dst = beam * bstride + band_off[c];
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                int ky = t + T * m;
+                int r = ky <= h ? ky : (ky >= N - h ? 2 * h + 1 - (N - ky) : -1);
+                if (r >= 0) store_c(bcap, dst + r, v[m], sc);
+            }
+        }
+        fft_reg<N, -S1>(v, lds, col, CW, t, tw);
+        if (live) {
+#pragma unroll
+            for (int m = 0; m < E; ++m) plane[(int64_t)(t + T * m) * ldx + pc] = v[m];
         }
     }
-    fft_reg<N, -S1>(v, lds, col, CW, t, tw);
-    if (live) {
-#pragma unroll
-        for (int m = 0; m < E; ++m) plane[(int64_t)(t + T * m) * ldx + pc] = v[m];
-    }
+}
+
+template <int N, int MODE>
+__global__ __launch_bounds__(ColCfg<N>::NT) __attribute__((amdgpu_waves_per_eu(2))) void k_col_pass(
+    float2* __restrict__ state, int nbeam, int nlx, int ldx, const float2* __restrict__ Pj,
+    const float2* __restrict__ tw) {
+    __shared__ float2 lds[N * ColCfg<N>::CW];
+    col_pass_body<N, MODE, false>(state, nbeam, nlx, ldx, Pj, tw, nullptr, nullptr, nullptr, 0, 0, lds);
+}
+
+template <int N, int MODE>
+__global__ __launch_bounds__(ColCfg<N>::NT) void k_col_pass_cap(float2* __restrict__ state, int nbeam, int nlx, int ldx,
+                                                                const float2* __restrict__ Pj,
+                                                                const float2* __restrict__ tw,
+                                                                const int* __restrict__ band_h,
+                                                                const int* __restrict__ band_off,
+                                                                void* __restrict__ bcap, int64_t bstride, int sc) {
+    __shared__ float2 lds[N * ColCfg<N>::CW];
+    col_pass_body<N, MODE, true>(state, nbeam, nlx, ldx, Pj, tw, band_h, band_off, bcap, bstride, sc, lds);
 }
 
 // Band coefficients of P_{nz-1} e_q (the transposed sweep's start): P(q) at q's band slot.
@@ -362,56 +430,67 @@ __global__ void k_init_band(void* bcap, int64_t bstride, int Kb, const int4* bea
 // each transition potential H_t -> FFT_x -> live columns into scratch [(t Ni + i) ny + y][nlx].
 // A thread group loads its row of W_i and T_j once and loops over the nt transitions (their
 // H rows stay in L2), so the S_1 window is read once per site instead of once per transition.
+// Row groups are walked with stride gridDim.x, the next group's W rows loaded meanwhile.
 template <int N>
-__global__ __launch_bounds__(256) void k_band_rows(float2* __restrict__ out, const float2* __restrict__ W,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_band_rows(float2* __restrict__ out, const float2* __restrict__ W,
                                                    int64_t wstride, int Ni, int nt, int ny, int nlx, int hlx, int ldx,
                                                    const float2* __restrict__ Tj, const float2* __restrict__ Hb,
                                                    int64_t hstride, const float2* __restrict__ tw) {
-    constexpr int E = RegCfg<N>::E, T = RegCfg<N>::T, S = 256 / T;
-    __shared__ float2 lds[S * N];
+    constexpr int E = RegCfg<N>::E, T = RegCfg<N>::T, S = 256 / T, L = PadLen<N>::value;
+    __shared__ float2 lds[S * L];
     const int tid = threadIdx.x, s = tid / T, t = tid % T;
     const int64_t rows = (int64_t)Ni * ny;
-    const int64_t g = (int64_t)blockIdx.x * S + s;
-    const bool valid = g < rows;
-    const int y = valid ? (int)(g % ny) : 0;
-    const int i = valid ? (int)(g / ny) : 0;
-    const float2* wr = W + i * wstride + (int64_t)y * N;
-    const float2* trow = Tj + (int64_t)y * N;
-    float2 u[E];
+    const int64_t ngroups = (rows + S - 1) / S;
+    float2 nxt[E];
+    auto load = [&](int64_t grp) {
+        const int64_t g = grp * S + s;
+        const bool ok = g < rows;
+        const float2* wr = W + (ok ? (g / ny) * wstride + (g % ny) * N : 0);
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-        int x = t + T * m;
-        u[m] = valid ? cmul(wr[x], trow[x]) : make_float2(0.f, 0.f);
-    }
-    // the next transition's H row is loaded while this one is transformed
-    float2 h[E];
+        for (int m = 0; m < E; ++m) nxt[m] = ok ? wr[t + T * m] : make_float2(0.f, 0.f);
+    };
+    if ((int64_t)blockIdx.x < ngroups) load(blockIdx.x);
+    for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+        const int64_t g = grp * S + s;
+        const bool valid = g < rows;
+        const int y = valid ? (int)(g % ny) : 0;
+        const int i = valid ? (int)(g / ny) : 0;
+        const float2* trow = Tj + (int64_t)y * N;
+        float2 u[E];
 #pragma unroll
-    for (int m = 0; m < E; ++m) h[m] = valid ? Hb[(int64_t)y * N + t + T * m] : make_float2(0.f, 0.f);
-    for (int tt = 0; tt < nt; ++tt) {
-        float2 v[E];
+        for (int m = 0; m < E; ++m) u[m] = valid ? cmul(nxt[m], trow[t + T * m]) : make_float2(0.f, 0.f);
+        if (grp + gridDim.x < ngroups) load(grp + gridDim.x);
+        // the next transition's H row is loaded while this one is transformed
+        float2 h[E];
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = cmul(u[m], h[m]);
-        if (tt + 1 < nt) {
-            const float2* hr = Hb + (tt + 1) * hstride + (int64_t)y * N;
+        for (int m = 0; m < E; ++m) h[m] = valid ? Hb[(int64_t)y * N + t + T * m] : make_float2(0.f, 0.f);
+        for (int tt = 0; tt < nt; ++tt) {
+            float2 v[E];
 #pragma unroll
-            for (int m = 0; m < E; ++m) h[m] = valid ? hr[t + T * m] : make_float2(0.f, 0.f);
-        }
-        fft_reg<N, -1>(v, lds, s * N, 1, t, tw);
-        const int64_t o = (((int64_t)tt * Ni + i) * ny + y) * ldx;
+            for (int m = 0; m < E; ++m) v[m] = cmul(u[m], h[m]);
+            if (tt + 1 < nt) {
+                const float2* hr = Hb + (tt + 1) * hstride + (int64_t)y * N;
 #pragma unroll
-        for (int m = 0; m < E; ++m) {
-            int c = phys_col_of(t + T * m, N, hlx, ldx);
-            if (valid && c >= 0) out[o + c] = v[m];
+                for (int m = 0; m < E; ++m) h[m] = valid ? hr[t + T * m] : make_float2(0.f, 0.f);
+            }
+            fft_reg<N, -1, true>(v, lds, s * L, 1, t, tw);
+            const int64_t o = (((int64_t)tt * Ni + i) * ny + y) * ldx;
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                int c = phys_col_of(t + T * m, N, hlx, ldx);
+                if (valid && c >= 0) out[o + c] = v[m];
+            }
         }
     }
 }
 
 // Band FFT, column stage: FFT_y of live-column strips, band coefficients to
 // dst[plane * dstride + g] (SC or complex64); the padding slots Kb .. dstride-1 are zeroed.
+// Items (plane, strip) are walked with stride gridDim.x, the next strip loaded meanwhile.
 template <int N>
-__global__ __launch_bounds__(ColCfg<N>::NT) void k_band_cols(void* __restrict__ dst, int64_t dstride, int Kb,
-                                                             const float2* __restrict__ src, int nlx, int ldx,
-                                                             const int* __restrict__ band_h,
+__global__ __launch_bounds__(ColCfg<N>::NT) __attribute__((amdgpu_waves_per_eu(2))) void k_band_cols(void* __restrict__ dst, int64_t dstride, int Kb,
+                                                             const float2* __restrict__ src, int64_t n_planes,
+                                                             int nlx, int ldx, const int* __restrict__ band_h,
                                                              const int* __restrict__ band_off,
                                                              const float2* __restrict__ tw, int sc) {
     using C = ColCfg<N>;
@@ -419,29 +498,41 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_band_cols(void* __restrict__ 
     __shared__ float2 lds[N * CW];
     const int tid = threadIdx.x;
     const int strips = (ldx + CW - 1) / CW;
-    const int64_t plane = blockIdx.x / strips;
-    const int strip = (int)(blockIdx.x % strips);
+    const int64_t items = n_planes * strips;
     const int col = tid % CW, t = tid / CW;
-    const int pc = strip * CW + col;
-    const int c = logical_of_phys(pc, nlx, ldx);
-    const bool live = c >= 0;
-    const float2* sp = src + plane * (int64_t)N * ldx;
-    float2 v[E];
+    float2 nxt[E];
+    auto load = [&](int64_t it) {
+        const int pc = (int)(it % strips) * CW + col;
+        const bool live = logical_of_phys(pc, nlx, ldx) >= 0;
+        const float2* sp = src + (it / strips) * (int64_t)N * ldx;
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = live ? sp[(int64_t)(t + T * m) * ldx + pc] : make_float2(0.f, 0.f);
-    fft_reg<N, -1>(v, lds, col, CW, t, tw);
-    if (live) {
-        const int h = band_h[c];
-        const int64_t o = plane * dstride + band_off[c];
+        for (int m = 0; m < E; ++m) nxt[m] = live ? sp[(int64_t)(t + T * m) * ldx + pc] : make_float2(0.f, 0.f);
+    };
+    if ((int64_t)blockIdx.x < items) load(blockIdx.x);
+    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        float2 v[E];
 #pragma unroll
-        for (int m = 0; m < E; ++m) {
-            int ky = t + T * m;
-            int r = ky <= h ? ky : (ky >= N - h ? 2 * h + 1 - (N - ky) : -1);
-            if (r >= 0) store_c(dst, o + r, v[m], sc);
+        for (int m = 0; m < E; ++m) v[m] = nxt[m];
+        const int64_t plane = it / strips;
+        const int strip = (int)(it % strips);
+        const int pc = strip * CW + col;
+        const int c = logical_of_phys(pc, nlx, ldx);
+        const bool live = c >= 0;
+        if (it + gridDim.x < items) load(it + gridDim.x);
+        fft_reg<N, -1>(v, lds, col, CW, t, tw);
+        if (live) {
+            const int h = band_h[c];
+            const int64_t o = plane * dstride + band_off[c];
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                int ky = t + T * m;
+                int r = ky <= h ? ky : (ky >= N - h ? 2 * h + 1 - (N - ky) : -1);
+                if (r >= 0) store_c(dst, o + r, v[m], sc);
+            }
         }
+        if (strip == 0)
+            for (int g = Kb + tid; g < dstride; g += NT) store_c(dst, plane * dstride + g, make_float2(0.f, 0.f), sc);
     }
-    if (strip == 0)
-        for (int g = Kb + tid; g < dstride; g += NT) store_c(dst, plane * dstride + g, make_float2(0.f, 0.f), sc);
 }
 
 // X[t][i][k] = H_t[k] * W_i[k] for k < K (zero for K <= k < ld), stored SC or complex64.
@@ -536,13 +627,22 @@ void launch_copy(float2* dst, const float2* src, int64_t n, hipStream_t st) {
     hipLaunchKernelGGL(k_copy, dim3(blocks_for(n, 256)), dim3(256), 0, st, dst, src, n);
 }
 
+// Grid of the block-strided pass kernels: every block walks several items so that its
+// register prefetch overlaps; 2048 blocks (8 per CU) balance the tail.
+static inline unsigned strided_grid(int64_t items) { return (unsigned)std::min<int64_t>(items, 2048); }
+
 template <int N, int MODE>
 static void row_pass_n(const RowPassArgs& a, hipStream_t st) {
     constexpr int S = 256 / RegCfg<N>::T;
     int64_t rows = (int64_t)a.nbeam * a.ny;
-    hipLaunchKernelGGL((k_row_pass<N, MODE>), dim3(blocks_for(rows, S)), dim3(256), 0, st, a.state, a.nbeam, a.ny,
-                       a.nlx, a.hlx, a.ldx, a.Tj, a.tw, a.cap_ptr, (const int4*)a.cap_rec, a.win, a.win_beams, a.Kpad,
-                       a.sc);
+    if (rows <= 0) return;
+    const dim3 grid(strided_grid(blocks_for(rows, S)));
+    if (a.cap_ptr)
+        hipLaunchKernelGGL((k_row_pass_cap<N, MODE>), grid, dim3(256), 0, st, a.state, a.nbeam, a.ny, a.nlx, a.hlx,
+                           a.ldx, a.Tj, a.tw, a.cap_ptr, (const int4*)a.cap_rec, a.win, a.win_beams, a.Kpad, a.sc);
+    else
+        hipLaunchKernelGGL((k_row_pass<N, MODE>), grid, dim3(256), 0, st, a.state, a.nbeam, a.ny, a.nlx, a.hlx, a.ldx,
+                           a.Tj, a.tw);
 }
 
 void launch_row_pass(int nx, int mode, const RowPassArgs& a, hipStream_t st) {
@@ -564,8 +664,13 @@ static void col_pass_n(float2* state, int nbeam, int nlx, int ldx, const float2*
                        hipStream_t st) {
     using C = ColCfg<N>;
     int strips = (ldx + C::CW - 1) / C::CW;
-    hipLaunchKernelGGL((k_col_pass<N, MODE>), dim3((unsigned)((int64_t)nbeam * strips)), dim3(C::NT), 0, st, state,
-                       nbeam, nlx, ldx, Pj, tw, bc.band_h, bc.band_off, bc.dst, bc.stride, bc.sc);
+    if (nbeam <= 0) return;
+    const dim3 grid(strided_grid((int64_t)nbeam * strips));
+    if (bc.dst)
+        hipLaunchKernelGGL((k_col_pass_cap<N, MODE>), grid, dim3(C::NT), 0, st, state, nbeam, nlx, ldx, Pj, tw,
+                           bc.band_h, bc.band_off, bc.dst, bc.stride, bc.sc);
+    else
+        hipLaunchKernelGGL((k_col_pass<N, MODE>), grid, dim3(C::NT), 0, st, state, nbeam, nlx, ldx, Pj, tw);
 }
 
 void launch_col_pass(int ny, int mode, float2* state, int nbeam, int nlx, int ldx, const float2* Pj, const float2* tw,
@@ -594,12 +699,13 @@ template <int NX, int NY>
 static void band_fft_n(const BandFft& a, hipStream_t st) {
     constexpr int S = 256 / RegCfg<NX>::T;
     int64_t rows = (int64_t)a.Ni * a.ny;
-    hipLaunchKernelGGL((k_band_rows<NX>), dim3(blocks_for(rows, S)), dim3(256), 0, st, a.scratch, a.W, a.wstride,
-                       a.Ni, a.nt, a.ny, a.nlx, a.hlx, a.ldx, a.Tj, a.H, a.hstride, a.twx);
+    hipLaunchKernelGGL((k_band_rows<NX>), dim3(strided_grid(blocks_for(rows, S))), dim3(256), 0, st, a.scratch, a.W,
+                       a.wstride, a.Ni, a.nt, a.ny, a.nlx, a.hlx, a.ldx, a.Tj, a.H, a.hstride, a.twx);
     using C = ColCfg<NY>;
     int strips = (a.ldx + C::CW - 1) / C::CW;
-    hipLaunchKernelGGL((k_band_cols<NY>), dim3((unsigned)((int64_t)a.nt * a.Ni * strips)), dim3(C::NT), 0, st, a.dst,
-                       a.dstride, a.Kb, a.scratch, a.nlx, a.ldx, a.band_h, a.band_off, a.twy, a.sc);
+    const int64_t planes = (int64_t)a.nt * a.Ni;
+    hipLaunchKernelGGL((k_band_cols<NY>), dim3(strided_grid(planes * strips)), dim3(C::NT), 0, st, a.dst, a.dstride,
+                       a.Kb, a.scratch, planes, a.nlx, a.ldx, a.band_h, a.band_off, a.twy, a.sc);
 }
 
 void launch_band_fft(int nx, int ny, const BandFft& a, hipStream_t st) {
@@ -625,8 +731,8 @@ static void band_rows_n(float2* out, const float2* W, int64_t wstride, int Ni, i
                         const float2* Tj, const float2* H, int64_t hstride, const float2* tw, hipStream_t st) {
     constexpr int S = 256 / RegCfg<NX>::T;
     int64_t rows = (int64_t)Ni * p.ny;
-    hipLaunchKernelGGL((k_band_rows<NX>), dim3(blocks_for(rows, S)), dim3(256), 0, st, out, W, wstride, Ni, nt, p.ny,
-                       p.nlx, p.hlx, p.ldx, Tj, H, hstride, tw);
+    hipLaunchKernelGGL((k_band_rows<NX>), dim3(strided_grid(blocks_for(rows, S))), dim3(256), 0, st, out, W, wstride,
+                       Ni, nt, p.ny, p.nlx, p.hlx, p.ldx, Tj, H, hstride, tw);
 }
 
 void launch_band_rows(float2* out, const float2* W, int64_t wstride, int Ni, int nt, const Plan& p, const float2* Tj,

@@ -296,7 +296,7 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     // basis), band-FFT scratch, norm partial sums
     auto site_mid = [&](int s) -> int64_t {
         int nt = p.sites[s].n_trans;
-        if (p.gram) return (int64_t)p.N1 * nt * p.N2p;     // Z^T rows [k][t][q]
+        if (p.gram) return (int64_t)p.N1 * nt * p.N2p;     // Z rows [t k][q]
         return orderS ? (int64_t)nt * p.N2 * p.N1pad : (int64_t)n_elig(s) * p.Kpad;
     };
     auto site_ni = [&](int s) -> int64_t { return orderS ? p.N1 : n_elig(s); };
@@ -500,6 +500,7 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     p.jobs.clear();
     const int64_t w1_stride = (int64_t)p.N1 * p.Kpad, w2_stride = (int64_t)p.N2 * p.Kpad;
     const bool h_in_gemm = !p.recip && !split;     // FP32 real-space: H applied in the GEMM prologue
+    const bool gram_stack = tune_get(TUNE_GRAM_STACK) != 0;
     for (auto& pb : pend) {
         Batch bt{};
         bt.slice = pb.slice;
@@ -535,14 +536,23 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
             int Ps = n_elig(s);
             GemmDesc d{};
             if (orderS && p.gram) {
-                // Z_s^T[k][t][q] = sum_r (H_t S1w)[k][r] S2w[q][r]  (or its band-basis form)
-                d.a_off = site_m2off[si]; d.lda = Kcpad; d.a_tstride = (int64_t)p.N1 * Kcpad;
+                // Z_s[t k][q] = sum_r (H_t S1w)[k][r] S2w[q][r]  (or its band-basis form): the
+                // transitions' rows stacked into one M = n_t N_1 (S_2 is shared, and the
+                // stacked rows fill the 128-row tiles), or one problem per transition
+                d.a_off = site_m2off[si]; d.lda = Kcpad;
                 if (p.recip) { d.b_off = p.slice_w2[pb.slice]; d.ldb = p.Kbpad; }
                 else { d.b_off = p.slice_w2[pb.slice] + (int64_t)p.site_w2[s] * w2_stride; d.ldb = p.Kpad; }
                 d.b_tstride = 0;
                 d.h_off = -1;
-                d.c_off = site_moff[si]; d.ldc_m = (int64_t)st.n_trans * p.N2p; d.ldc_t = p.N2p;
-                d.M = p.N1; d.N_inner = p.N2; d.n_t = st.n_trans; d.K = Kc;
+                d.c_off = site_moff[si]; d.ldc_m = p.N2p;
+                if (gram_stack) {
+                    d.a_tstride = 0; d.ldc_t = 0;
+                    d.M = st.n_trans * p.N1; d.n_t = 1;
+                } else {
+                    d.a_tstride = (int64_t)p.N1 * Kcpad; d.ldc_t = (int64_t)p.N1 * p.N2p;
+                    d.M = p.N1; d.n_t = st.n_trans;
+                }
+                d.N_inner = p.N2; d.K = Kc;
                 d.idx_off = -1;
                 d.flags = GD_ZERO_PAD;
             } else if (orderS) {
@@ -587,10 +597,10 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
             const std::vector<int>* pl = p.f > 1 ? &p.site_probes[s] : nullptr;
             GemmDesc d{};
             if (orderS && p.gram) {
-                // G_t[k][k'] = sum_q conj(Z_s^T[k][t][q]) Z_s^T[k'][t][q]  (upper tiles), one
-                // FP32 partial per transition; the partials are summed in FP64
-                d.a_off = site_moff[si]; d.lda = (int64_t)st.n_trans * p.N2p; d.a_tstride = p.N2p;
-                d.b_off = site_moff[si]; d.ldb = d.lda; d.b_tstride = p.N2p;
+                // G_t[k][k'] = sum_q conj(Z_s[t k][q]) Z_s[t k'][q]  (upper tiles), one FP32
+                // partial per transition; the partials are summed in FP64
+                d.a_off = site_moff[si]; d.lda = p.N2p; d.a_tstride = (int64_t)p.N1 * p.N2p;
+                d.b_off = site_moff[si]; d.ldb = d.lda; d.b_tstride = d.a_tstride;
                 d.h_off = -1; d.ldh = 0;
                 d.c_off = 0; d.ldc_m = p.N1pad; d.ldc_t = (int64_t)p.N1pad * p.N1pad;
                 d.M = p.N1; d.N_inner = p.N1; d.n_t = st.n_trans; d.K = p.N2p;

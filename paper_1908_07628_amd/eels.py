@@ -321,6 +321,7 @@ def gemm_work_bytes(m: int, n: int, k: int) -> int:
 TUNE_SC_STAGES = 0
 TUNE_TILE_ORDER = 1
 TUNE_SC_SCHED = 2
+TUNE_GRAM_STACK = 3
 
 
 def tune_set(key: int, value: int):

@@ -217,3 +217,13 @@ def test_conventional_entry_host_checks():
     st = lib.eels_conventional_map(plan2._h, dummy, dummy, dummy, 2, dummy, 1 << 40, None)
     assert st == 1   # EELS_ERR_INVALID_ARG
     assert "interp_f" in lib.eels_last_error().decode()
+
+
+def test_tuning_knob_ranges_and_gram_stack_plan():
+    """Knob values are range-checked; the Gram form's first GEMM stacks the transitions'
+    rows by default (plan-time knob 3)."""
+    _lib()
+    for key, bad in ((0, 1), (0, 6), (1, 3), (2, 4), (3, 2), (3, -1), (9, 0)):
+        with pytest.raises(eels.EelsError):
+            eels.tune_set(key, bad)
+    assert eels.tune_get(eels.TUNE_GRAM_STACK) == 1

@@ -232,6 +232,26 @@ def test_gram_detector_sum_many_sites_and_batches():
     assert metrics.rel_l2(a, b) < 1e-10
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16_split"])
+def test_gram_stacked_rows_match_per_transition(prec):
+    """The Gram form's first GEMM with the transitions' rows stacked into one problem (the
+    default) and with one problem per transition computes every output element with the
+    same accumulation order: the maps are bitwise equal.  Config 1: 3 transitions of 325
+    rows, 975 stacked rows in 8 tiles instead of 3 x 3."""
+    eels = _need_gpu()
+    p = synth.config1()
+    maps = []
+    try:
+        for stack in (1, 0):
+            eels.tune_set(eels.TUNE_GRAM_STACK, stack)
+            _say("gram stack", stack, prec)
+            maps.append(_map(eels, p, prec, "s_first", detector_sum="gram"))
+    finally:
+        eels.tune_set(eels.TUNE_GRAM_STACK, 1)
+    assert np.array_equal(maps[0], maps[1])
+    assert metrics.rel_l2(maps[0], prism.prism_map(p)) < (1e-4 if prec == "fp32" else 1e-3)
+
+
 def test_interpolation_factor_case():
     eels = _need_gpu()
     p = synth.config3_subproblem(n=128, L=25.0, nz=5, n_scan=6, f=2)
