@@ -103,26 +103,38 @@ def profile_sample(args):
                       "copy_bytes": 2 * a.numel() * 4}), flush=True)
 
 
-def gemm_traffic():
-    """HBM bytes per launch of the first contraction GEMM from the committed counter summary,
-    if it was taken with the current GEMM source (else None)."""
+# sources whose change invalidates the committed counter figures (kernels and launch shapes)
+TRAFFIC_SOURCES = ["kernels_gemm.hip", "kernels_sweep.hip", "fft_reg.h", "fft_lds.h", "plan.cpp"]
+
+
+def sources_digest():
     import hashlib
-    src = os.path.join(ROOT, "paper_1908_07628_amd", "csrc", "kernels_gemm.hip")
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1908_07628_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
+def counter_values():
+    """Calibrated HBM bytes per launch from the committed counter summary, if it was taken with
+    the current kernel and planner sources (else an empty dict)."""
     summ = os.path.join(ROOT, "profiles", "k_cgemm_sc__config2_traffic_pmc.md")
     if not os.path.exists(summ):
-        return None
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        return {}
     vals = {}
     for line in open(summ):
         if ":" in line and line.lstrip().startswith("- "):
             k, v = line.strip()[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
-    if vals.get("kernels_gemm.hip sha256") != digest:
-        return None
-    try:
-        return float(vals["traffic_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+    if vals.get("sources sha256") != sources_digest():
+        return {}
+    out = {}
+    for k, v in vals.items():
+        try:
+            out[k] = float(v)
+        except ValueError:
+            pass
+    return out
 
 
 def bench_batch(args):
@@ -309,6 +321,7 @@ def main():
     value = p.n_probes * args.steps / elapsed
     gpu_map = out.cpu().numpy()
 
+    counters = counter_values()
     # roofline of the dominant kernel (first contraction GEMM)
     g1 = phase_tot["gemm1"]
     g1_flops = gemm1_flops(info, p)
@@ -322,7 +335,8 @@ def main():
     roofline = {
         "bound": "mfma", "kernel": "k_cgemm_sc (first contraction GEMM)" if split else "k_cgemm",
         "achieved": round(achieved, 1), "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-        "traffic": gemm_traffic() if split else None, "avg_launch_ms": round(avg_ms, 3),
+        "traffic": counters.get("gemm1_traffic_bytes_per_launch") if split else None,
+        "avg_launch_ms": round(avg_ms, 3),
         "launches_per_step": n_launch_per_step,
         "algorithmic_flops_per_launch": exec_factor * per_launch,
         "useful_complex_tflops": round(per_launch / (avg_ms * 1e-3) / 1e12, 1),
@@ -345,7 +359,11 @@ def main():
     roofline_fft = {
         "sweeps": {"bound": "hbm", "kernels": "k_row_pass + k_col_pass (with S_1 window and S_2 band captures)",
                    "achieved": round(sweep_bytes / sweep_s / 1e9, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                   "frac": round(sweep_bytes / sweep_s / 1e9 / PEAK_HBM_GBPS, 4), "traffic": None,
+                   "frac": round(sweep_bytes / sweep_s / 1e9 / PEAK_HBM_GBPS, 4),
+                   "traffic": ({"k_row_pass<256,1>": counters["row_pass_traffic_bytes_per_launch"],
+                                "k_col_pass<256,1>": counters["col_pass_traffic_bytes_per_launch"],
+                                "algorithmic_bytes_per_launch": 16.0 * info["n_beams_out"] * p.ny * info["n_live_x"]}
+                               if "row_pass_traffic_bytes_per_launch" in counters else None),
                    "algorithmic_bytes_per_step": sweep_bytes,
                    "byte_definition": "32 B x n_y x n_live_x per beam-slice (2 passes, read + write) + captures"},
         "producer": {"bound": "hbm", "kernels": "k_band_rows + k_band_cols",
