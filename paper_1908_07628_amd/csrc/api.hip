@@ -32,7 +32,7 @@ namespace eels {
 static thread_local std::string g_err;
 void set_error(const std::string& m) { g_err = m; }
 
-static std::atomic<int> g_tune[TUNE_COUNT] = {{2}, {2}, {0}, {1}, {0}, {0}, {0}, {0}};
+static std::atomic<int> g_tune[TUNE_COUNT] = {{2}, {2}, {0}, {1}, {1}, {0}, {0}, {0}};
 int tune_get(int key) { return (key >= 0 && key < TUNE_COUNT) ? g_tune[key].load() : 0; }
 
 // Diagnostic phase timing (eels_timing_enable / eels_timing_read).
@@ -265,7 +265,7 @@ void contract(const Plan& p, const Dev& d, const float2* dH, double* map, int bi
             TimeScope ts(EELS_PHASE_GEMM1, st);
             if (split)
                 launch_cgemm_sc(p.precision, 0, nst, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.mid2, d.w2, d.mid,
-                                nullptr, d.blob, st);
+                                nullptr, d.blob, st, b.d1_rows);
             else
                 launch_cgemm(EELS_FP32, 0, 0, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.mid2, d.w2, nullptr, d.mid,
                              nullptr, d.blob, st);
@@ -289,7 +289,7 @@ void contract(const Plan& p, const Dev& d, const float2* dH, double* map, int bi
             TimeScope ts(EELS_PHASE_GEMM1, st);
             if (split)
                 launch_cgemm_sc(p.precision, 0, nst, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.w2, d.mid2, d.mid,
-                                nullptr, d.blob, st);
+                                nullptr, d.blob, st, b.d1_rows);
             else
                 launch_cgemm(EELS_FP32, 0, 0, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.w2, h_pro ? d.w1 : d.mid2,
                              h_pro ? dH : nullptr, d.mid, nullptr, d.blob, st);
@@ -823,6 +823,7 @@ eels_status eels_tune_set(int key, int value) {
     if (key == TUNE_TILE_ORDER && (value < 0 || value > 2)) return EELS_ERR_INVALID_ARG;
     if (key == TUNE_SC_SCHED && (value < 0 || value > 3)) return EELS_ERR_INVALID_ARG;
     if (key == TUNE_GRAM_STACK && (value < 0 || value > 1)) return EELS_ERR_INVALID_ARG;
+    if (key == TUNE_GEMM1_ROWS && (value < 0 || value > 1)) return EELS_ERR_INVALID_ARG;
     g_tune[key].store(value);
     return EELS_OK;
 }

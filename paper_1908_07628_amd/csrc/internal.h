@@ -42,13 +42,17 @@ enum { GD_ZERO_PAD = 1 };
 static_assert(sizeof(GemmDesc) == 144, "GemmDesc layout");
 
 // Process-wide tuning knobs (set by eels_tune_set; read at launch time).
-enum TuneKey { TUNE_SC_STAGES = 0, TUNE_TILE_ORDER = 1, TUNE_SC_SCHED = 2, TUNE_GRAM_STACK = 3, TUNE_COUNT = 8 };
+enum TuneKey {
+    TUNE_SC_STAGES = 0, TUNE_TILE_ORDER = 1, TUNE_SC_SCHED = 2, TUNE_GRAM_STACK = 3, TUNE_GEMM1_ROWS = 4,
+    TUNE_COUNT = 8
+};
 int tune_get(int key);
 
 struct Batch {
     int slice;
     int order;
     int d1_begin, d1_count, d1_tiles;   // first GEMM (store epilogue)
+    int d1_rows = 128;                  // A rows per tile of the first GEMM (128 or 256)
     int d2_begin, d2_count, d2_tiles;   // second GEMM (norm epilogue)
     int job_begin, job_count;           // producer jobs run between the two GEMMs (order P) or before
     int64_t red_ptr;                    // int offset of the per-probe CSR row pointers [P+1], -1: dense

@@ -14,7 +14,9 @@
 //
 // Block: 256 threads = 4 waves in a 2 x 2 grid over a 128 x 128 complex output tile;
 // each wave owns 64 x 64 = 2 x 2 MFMA blocks of 32 x 32.  K advances 16 complex per
-// step through LDS with the next step's global loads issued before the MFMAs.
+// step through LDS with the next step's global loads issued before the MFMAs.  The split
+// kernel also has a 512-thread form, 8 waves in a 4 x 2 grid over a 256 x 128 tile, for
+// the store epilogue.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -84,6 +86,7 @@ __device__ __forceinline__ u32x4 swap_halves(u32x4 v) {  // (re, im) -> (im, re)
 //      8 m tiles with m fastest, so the blocks resident on one XCD cover a compact
 //      8 x 8 patch of the output and its L2 holds only their A and B rows.
 // Returns the descriptor index.
+template <int G = 8>
 __device__ __forceinline__ int locate_tile(const GemmDesc* __restrict__ descs, int n_desc, int order, int& tm,
                                            int& tn, int& t) {
     int bid = blockIdx.x;
@@ -109,7 +112,6 @@ __device__ __forceinline__ int locate_tile(const GemmDesc* __restrict__ descs, i
         tm = r % d.tiles_m;
         tn = r / d.tiles_m;
     } else {
-        constexpr int G = 8;
         const int grp = r / (G * d.tiles_n), fm = grp * G;
         const int gs = min(d.tiles_m - fm, G);
         const int w = r - grp * G * d.tiles_n;
@@ -424,54 +426,69 @@ __device__ __forceinline__ void wait_vmcnt() {
     __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
-template <int UNITS, int NSTAGE>
+// WM = 2: 4 waves on a 128 x 128 tile; WM = 4: 8 waves on a 256 x 128 tile (each wave still
+// 64 x 64, so its MFMA and LDS work per step is the same, while the block's operand loads per
+// flop drop by a quarter; one block per CU)
+template <int UNITS, int NSTAGE, int WM>
 struct ScPipe {
     static constexpr int ROWB = 32 * UNITS;              // bytes of one tile row
     static constexpr int QUADS = 2 * UNITS;
-    static constexpr int STAGE = 2 * 128 * ROWB;         // A and B tiles
+    static constexpr int BMX = 64 * WM;                  // A rows of the tile
+    static constexpr int NW = 2 * WM;                    // waves
+    static constexpr int STAGE = (BMX + 128) * ROWB;     // A and B tiles
     static constexpr int RPI = 1024 / ROWB;              // rows per wave-wide 16-byte load
-    static constexpr int NI = 32 / RPI;                  // loads per wave per operand
-    static constexpr int WAVES_PER_EU = 2 * NSTAGE * STAGE <= 160 * 1024 ? 2 : 1;
+    static constexpr int NIA = 32 / RPI;                 // A loads per wave (32 rows each)
+    static constexpr int NIB = 128 / NW / RPI;           // B loads per wave
+    static constexpr int WAVES_PER_EU = WM == 2 && 2 * NSTAGE * STAGE <= 160 * 1024 ? 2 : 1;
+    static constexpr int G = WM == 2 ? 8 : 4;            // m tiles per group of the XCD-aware order
 };
 
-template <int PREC, int EPI, int NSTAGE, int UNITS, int SCHED>
-__global__ __launch_bounds__(256, (ScPipe<UNITS, NSTAGE>::WAVES_PER_EU)) void k_cgemm_sc(const GemmDesc* __restrict__ descs, int n_desc,
-                                                  const uint32_t* __restrict__ Ab, const uint32_t* __restrict__ Bb,
-                                                  uint32_t* __restrict__ Cb, float* __restrict__ Pb,
-                                                  const int* __restrict__ ib, int order) {
-    using SP = ScPipe<UNITS, NSTAGE>;
-    constexpr int STAGE = SP::STAGE, ROWB = SP::ROWB, QUADS = SP::QUADS, RPI = SP::RPI, NI = SP::NI;
+template <int PREC, int EPI, int NSTAGE, int UNITS, int SCHED, int WM>
+__global__ __launch_bounds__(128 * WM, (ScPipe<UNITS, NSTAGE, WM>::WAVES_PER_EU)) void k_cgemm_sc(
+    const GemmDesc* __restrict__ descs, int n_desc, const uint32_t* __restrict__ Ab, const uint32_t* __restrict__ Bb,
+    uint32_t* __restrict__ Cb, float* __restrict__ Pb, const int* __restrict__ ib, int order) {
+    using SP = ScPipe<UNITS, NSTAGE, WM>;
+    constexpr int STAGE = SP::STAGE, ROWB = SP::ROWB, QUADS = SP::QUADS, RPI = SP::RPI, NIA = SP::NIA, NIB = SP::NIB;
+    constexpr int BMX = SP::BMX, NT = 128 * WM;
     constexpr int BKS = 4 * UNITS;  // complex per tile row
+    static_assert(WM == 2 || EPI == 0, "the 256-row tile has only the store epilogue");
     __shared__ __attribute__((aligned(1024))) char smem[NSTAGE * STAGE];
 
     int tm, tn, t;
-    const GemmDesc& d = descs[locate_tile(descs, n_desc, order, tm, tn, t)];
+    const GemmDesc& d = descs[locate_tile<SP::G>(descs, n_desc, order, tm, tn, t)];
     if constexpr (EPI == 2) {
         if (tn < tm) return;   // Gram tiles: the lower triangle is the conjugate transpose
     }
     const int M = d.M, N = d.N_inner;
-    const int m0 = tm * BM, n0 = tn * BN;
+    const int m0 = tm * BMX, n0 = tn * BN;
     const int nk = (d.K + BKS - 1) / BKS;
     const char* A = (const char*)Ab + 8 * (d.a_off + (int64_t)t * d.a_tstride);
     const char* B = (const char*)Bb + 8 * (d.b_off + (int64_t)t * d.b_tstride);
     const int* idx = d.idx_off >= 0 ? ib + d.idx_off : nullptr;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave & 1, wn = wave >> 1;
+    const int wm = wave % WM, wn = wave / WM;
     const int li = lane & 31, hl = lane >> 5;
 
-    // this lane's NI A and NI B source rows (one per RPI-row chunk of the wave's 32 rows)
+    // this lane's A and B source rows (one per RPI-row chunk of the wave's 32 A rows and
+    // 128 / NW B rows)
+    constexpr int BRW = 128 / SP::NW;   // B rows loaded per wave
     const int qpos = lane % QUADS;
-    const char* asrc[NI];
-    const char* bsrc[NI];
+    const char* asrc[NIA];
+    const char* bsrc[NIB];
 #pragma unroll
-    for (int c = 0; c < NI; ++c) {
+    for (int c = 0; c < NIA; ++c) {
         int r = wave * 32 + c * RPI + lane / QUADS;
         int q = qpos ^ ((r >> 1) & (QUADS - 1));
         int m = min(m0 + r, M - 1);
+        asrc[c] = A + (int64_t)m * d.lda * 8 + 16 * q;
+    }
+#pragma unroll
+    for (int c = 0; c < NIB; ++c) {
+        int r = wave * BRW + c * RPI + lane / QUADS;
+        int q = qpos ^ ((r >> 1) & (QUADS - 1));
         int n = min(n0 + r, N - 1);
         int nr = idx ? idx[n] : n;
-        asrc[c] = A + (int64_t)m * d.lda * 8 + 16 * q;
         bsrc[c] = B + (int64_t)nr * d.ldb * 8 + 16 * q;
     }
     typedef __attribute__((address_space(3))) char lds_char;
@@ -480,13 +497,13 @@ __global__ __launch_bounds__(256, (ScPipe<UNITS, NSTAGE>::WAVES_PER_EU)) void k_
         lds_char* st = lds + (kt % NSTAGE) * STAGE;
         int64_t koff = (int64_t)kt * ROWB;
 #pragma unroll
-        for (int c = 0; c < NI; ++c)
+        for (int c = 0; c < NIA; ++c)
             __builtin_amdgcn_global_load_lds((const void*)(asrc[c] + koff), (void*)(st + (wave * 32 + c * RPI) * ROWB),
                                              16, 0, 0);
 #pragma unroll
-        for (int c = 0; c < NI; ++c)
+        for (int c = 0; c < NIB; ++c)
             __builtin_amdgcn_global_load_lds((const void*)(bsrc[c] + koff),
-                                             (void*)(st + 128 * ROWB + (wave * 32 + c * RPI) * ROWB), 16, 0, 0);
+                                             (void*)(st + BMX * ROWB + (wave * BRW + c * RPI) * ROWB), 16, 0, 0);
     };
 
     floatx16 accR[2][2], accI[2][2];
@@ -515,7 +532,7 @@ __global__ __launch_bounds__(256, (ScPipe<UNITS, NSTAGE>::WAVES_PER_EU)) void k_
         for (int bn = 0; bn < 2; ++bn) {
             int r = wn * 64 + bn * 32 + li;
             int sw = (r >> 1) & (QUADS - 1);
-            const char* row = st + 128 * ROWB + r * ROWB;
+            const char* row = st + BMX * ROWB + r * ROWB;
             f.bh[bn] = *(const u32x4*)(row + 16 * ((2 * u) ^ sw));
             f.bl[bn] = *(const u32x4*)(row + 16 * ((2 * u + 1) ^ sw));
         }
@@ -555,7 +572,7 @@ __global__ __launch_bounds__(256, (ScPipe<UNITS, NSTAGE>::WAVES_PER_EU)) void k_
         // this wave's loads of tile kt are done once at most the later tiles' loads remain;
         // the barrier then covers every wave's part of the tile and frees the stage that was
         // multiplied in the previous iteration (its LDS reads fed MFMAs, so they completed)
-        if (nk - 1 - kt >= NSTAGE - 2) wait_vmcnt<2 * NI * (NSTAGE - 2)>();
+        if (nk - 1 - kt >= NSTAGE - 2) wait_vmcnt<(NIA + NIB) * (NSTAGE - 2)>();
         else wait_vmcnt<0>();
         __builtin_amdgcn_s_barrier();
         if (kt + NSTAGE - 1 < nk) issue(kt + NSTAGE - 1);
@@ -599,7 +616,7 @@ __global__ __launch_bounds__(256, (ScPipe<UNITS, NSTAGE>::WAVES_PER_EU)) void k_
         const int64_t cbase = d.c_off + (int64_t)t * d.ldc_t;
         const int npad = (N + 15) & ~15;
         if (n0 + BN > N && n0 < npad) {
-            for (int e = tid; e < BM * 16; e += 256) {
+            for (int e = tid; e < BMX * 16; e += NT) {
                 int m = m0 + e / 16, i = N + e % 16;
                 if (m < M && i < npad && i >= n0 && i < n0 + BN)
                     sc_store(Cb, cbase + (int64_t)m * d.ldc_m + i, make_float2(0.f, 0.f), PREC);
@@ -686,12 +703,20 @@ void launch_cgemm(int precision, int kind, int epi, const GemmDesc* dd, int nd, 
 
 
 template <int PREC, int EPI>
-static void go_sc(int nstage, const GemmDesc* dd, int nd, int tiles, const uint32_t* A, const uint32_t* B, uint32_t* C,
-                  float* P, const int* idx, hipStream_t st) {
-    // pipeline variants: 2 / 3 stages of 16-complex tiles, 4 / 5 stages of 8-complex tiles
+static void go_sc(int nstage, int rows, const GemmDesc* dd, int nd, int tiles, const uint32_t* A, const uint32_t* B,
+                  uint32_t* C, float* P, const int* idx, hipStream_t st) {
+    // pipeline variants: 2 / 3 stages of 16-complex tiles, 4 / 5 stages of 8-complex tiles;
+    // 256-row tiles (store epilogue) with two stages of 16-complex tiles
     const int order = tune_get(TUNE_TILE_ORDER);
 #define SCV(NS, U, SC) \
-    hipLaunchKernelGGL((k_cgemm_sc<PREC, EPI, NS, U, SC>), dim3(tiles), dim3(256), 0, st, dd, nd, A, B, C, P, idx, order)
+    hipLaunchKernelGGL((k_cgemm_sc<PREC, EPI, NS, U, SC, 2>), dim3(tiles), dim3(256), 0, st, dd, nd, A, B, C, P, idx, order)
+    if constexpr (EPI == 0) {
+        if (rows == 256) {
+            hipLaunchKernelGGL((k_cgemm_sc<PREC, 0, 2, 4, 0, 4>), dim3(tiles), dim3(512), 0, st, dd, nd, A, B, C, P, idx,
+                               order);
+            return;
+        }
+    }
     switch (nstage) {
         case 3: SCV(3, 4, 0); break;
         case 4: SCV(4, 2, 0); break;
@@ -709,18 +734,18 @@ static void go_sc(int nstage, const GemmDesc* dd, int nd, int tiles, const uint3
 }
 
 void launch_cgemm_sc(int precision, int epi, int nstage, const GemmDesc* dd, int nd, int tiles, const void* A,
-                     const void* B, void* C, float* part, const int* idx, hipStream_t st) {
+                     const void* B, void* C, float* part, const int* idx, hipStream_t st, int rows) {
     if (tiles <= 0 || nd <= 0) return;
     const uint32_t *a = (const uint32_t*)A, *b = (const uint32_t*)B;
     uint32_t* c = (uint32_t*)C;
     if (precision == EELS_BF16_SPLIT) {
-        if (epi == 0) go_sc<EELS_BF16_SPLIT, 0>(nstage, dd, nd, tiles, a, b, c, part, idx, st);
-        else if (epi == 2) go_sc<EELS_BF16_SPLIT, 2>(nstage, dd, nd, tiles, a, b, c, part, idx, st);
-        else go_sc<EELS_BF16_SPLIT, 1>(nstage, dd, nd, tiles, a, b, c, part, idx, st);
+        if (epi == 0) go_sc<EELS_BF16_SPLIT, 0>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st);
+        else if (epi == 2) go_sc<EELS_BF16_SPLIT, 2>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st);
+        else go_sc<EELS_BF16_SPLIT, 1>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st);
     } else {
-        if (epi == 0) go_sc<EELS_FP16_SPLIT, 0>(nstage, dd, nd, tiles, a, b, c, part, idx, st);
-        else if (epi == 2) go_sc<EELS_FP16_SPLIT, 2>(nstage, dd, nd, tiles, a, b, c, part, idx, st);
-        else go_sc<EELS_FP16_SPLIT, 1>(nstage, dd, nd, tiles, a, b, c, part, idx, st);
+        if (epi == 0) go_sc<EELS_FP16_SPLIT, 0>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st);
+        else if (epi == 2) go_sc<EELS_FP16_SPLIT, 2>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st);
+        else go_sc<EELS_FP16_SPLIT, 1>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st);
     }
 }
 

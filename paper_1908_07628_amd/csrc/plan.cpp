@@ -501,6 +501,8 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     const int64_t w1_stride = (int64_t)p.N1 * p.Kpad, w2_stride = (int64_t)p.N2 * p.Kpad;
     const bool h_in_gemm = !p.recip && !split;     // FP32 real-space: H applied in the GEMM prologue
     const bool gram_stack = tune_get(TUNE_GRAM_STACK) != 0;
+    // the split first GEMM of order S may use 256-row tiles (store epilogue only)
+    const int rows1 = (split && orderS && tune_get(TUNE_GEMM1_ROWS) != 0) ? 256 : GEMM_BM;
     for (auto& pb : pend) {
         Batch bt{};
         bt.slice = pb.slice;
@@ -578,7 +580,7 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
                 d.M = Ps; d.N_inner = p.K; d.n_t = 1; d.K = p.N1;
                 d.idx_off = (int)site_idx[s];
             }
-            d.tiles_m = (int)ceil_div(d.M, GEMM_BM);
+            d.tiles_m = (int)ceil_div(d.M, rows1);
             d.tiles_n = (int)ceil_div(d.N_inner, GEMM_BN);
             d.tile_start = tiles;
             tiles += d.tiles_m * d.tiles_n * d.n_t;
@@ -586,6 +588,7 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
         }
         bt.d1_count = (int)p.descs.size() - bt.d1_begin;
         bt.d1_tiles = tiles;
+        bt.d1_rows = rows1;
         // second GEMM
         bt.d2_begin = (int)p.descs.size();
         tiles = 0;

@@ -252,6 +252,29 @@ def test_gram_stacked_rows_match_per_transition(prec):
     assert metrics.rel_l2(maps[0], prism.prism_map(p)) < (1e-4 if prec == "fp32" else 1e-3)
 
 
+@pytest.mark.parametrize("prec", ["bf16_split", "fp16_split"])
+@pytest.mark.parametrize("detsum", ["gram", "direct"])
+def test_gemm1_tile_rows_match(prec, detsum):
+    """The split first GEMM with 256-row tiles (8 waves, the default) and with 128-row tiles
+    accumulates every output element in the same order: bitwise-equal maps.  Config 1 (Gram:
+    975 stacked rows, 4 tiles of 256 with a ragged last one; direct: M = N_2 = 1305) and a
+    random cell with a crop window (real-space K)."""
+    eels = _need_gpu()
+    cases = [synth.config1(),
+             synth.random_problem(77, n=64, L=12.0, nz=4, n_sites=3, n_trans=3, window_A=3.0, atoms_per_slice=3)]
+    for p in cases:
+        maps = []
+        try:
+            for rows in (1, 0):
+                eels.tune_set(eels.TUNE_GEMM1_ROWS, rows)
+                _say("gemm1 rows", rows, prec, detsum)
+                maps.append(_map(eels, p, prec, "s_first", detector_sum=detsum))
+        finally:
+            eels.tune_set(eels.TUNE_GEMM1_ROWS, 1)
+        assert np.array_equal(maps[0], maps[1])
+        assert metrics.rel_l2(maps[0], prism.prism_map(p)) < 1e-3
+
+
 def test_interpolation_factor_case():
     eels = _need_gpu()
     p = synth.config3_subproblem(n=128, L=25.0, nz=5, n_scan=6, f=2)
