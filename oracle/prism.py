@@ -135,3 +135,95 @@ def site_maps(prob, lam=None, sigma=None) -> np.ndarray:
         for s in st.sites_by_slice.get(j, []):
             contract_site(prob, st, s, S1[j], S2, out[s])
     return out
+
+
+# ---------------------------------------------------------------------------------------
+# The same map with the two sweeps split over disjoint beam subsets.  Each beam is
+# multisliced on its own, so the map of Eq. SHn0 regroups exactly:
+#   Psi_s(r, R) = sum_k S_1(j)[k](r) c_k(R) is a sum over aperture beams, and
+#   I(R) = f^2 sum_n sum_q |A_n(q, R)|^2 is a sum over detector beams.
+# This bounds memory for large cells (a few beams at a time); prism_map is the reference.
+
+def _beam_subset(st, which: int, beams):
+    import dataclasses
+    b = np.asarray(beams, dtype=np.int64)
+    if which == 1:
+        return dataclasses.replace(st, ab1=st.ab1[b], ix1=st.ix1[b], iy1=st.iy1[b], C=st.C[b])
+    return dataclasses.replace(st, ab2=st.ab2[b], ix2=st.ix2[b], iy2=st.iy2[b])
+
+
+def probe_waves_partial(prob, beams, chunk: int = 16, st=None) -> Dict[int, np.ndarray]:
+    """For every site s: the part of Psi_s = S_1w^T c (window pixels x eligible probes) that
+    comes from the aperture beams `beams`, processed `chunk` beams at a time."""
+    st = make_setup(prob) if st is None else st
+    ion = sorted(st.sites_by_slice.keys())
+    out: Dict[int, np.ndarray] = {}
+    beams = np.asarray(beams, dtype=np.int64)
+    for c0 in range(0, len(beams), chunk):
+        sub = _beam_subset(st, 1, beams[c0:c0 + chunk])
+        S1 = forward_s1(prob, sub, ion)
+        for j in ion:
+            for s in st.sites_by_slice[j]:
+                el = site_eligible(prob, st, s)
+                if not np.any(el):
+                    continue
+                rows, cols = site_window(prob, st, s)
+                S1w = S1[j][:, rows][:, :, cols].reshape(sub.C.shape[0], -1)
+                part = S1w.T @ sub.C[:, el]
+                out[s] = out[s] + part if s in out else part
+        del S1
+    return out
+
+
+def intensity_partial(prob, psi: Dict[int, np.ndarray], beams, chunk: int = 16, st=None) -> np.ndarray:
+    """f^2 sum_n sum_{q in beams} |A_n(q, R)|^2 for every probe, with A_n = S_2w (H_n * Psi_s)
+    and the complete Psi of every site; detector beams `beams`, `chunk` at a time."""
+    st = make_setup(prob) if st is None else st
+    I = np.zeros(prob.n_probes, dtype=np.float64)
+    ion = sorted(st.sites_by_slice.keys())
+    if not ion:
+        return I
+    f2 = float(int(prob.interp_f) ** 2)
+    beams = np.asarray(beams, dtype=np.int64)
+    for c0 in range(0, len(beams), chunk):
+        sub = _beam_subset(st, 2, beams[c0:c0 + chunk])
+        for j, S2 in reverse_s2(prob, sub, j_stop=min(ion)):
+            for s in st.sites_by_slice.get(j, []):
+                if s not in psi:
+                    continue
+                el = site_eligible(prob, st, s)
+                rows, cols = site_window(prob, st, s)
+                S2w = S2[:, rows][:, :, cols].reshape(S2.shape[0], -1)
+                for n in range(int(prob.site_ntrans[s])):
+                    h = site_H(prob, s, n).reshape(-1)
+                    A = S2w @ (h[:, None] * psi[s])
+                    I[el] += f2 * (np.abs(A) ** 2).sum(axis=0)
+    return I
+
+
+def _psi_job(args):
+    prob, beams, chunk = args
+    return probe_waves_partial(prob, beams, chunk)
+
+
+def _int_job(args):
+    prob, psi, beams, chunk = args
+    return intensity_partial(prob, psi, beams, chunk)
+
+
+def prism_map_by_beams(prob, n_parts: int = 1, chunk: int = 16, map_fn=map) -> np.ndarray:
+    """prism_map regrouped by beams: the aperture beams in n_parts disjoint sets (their Psi
+    parts summed), then the detector beams in n_parts sets (their intensities summed).
+    map_fn runs the independent parts (the builtin map, or a process pool's map)."""
+    st = make_setup(prob)
+    n1, n2 = st.ab1.shape[0], st.ab2.shape[0]
+    parts1 = [b for b in np.array_split(np.arange(n1), n_parts) if len(b)]
+    psi: Dict[int, np.ndarray] = {}
+    for part in map_fn(_psi_job, [(prob, b, chunk) for b in parts1]):
+        for s, v in part.items():
+            psi[s] = psi[s] + v if s in psi else v
+    parts2 = [b for b in np.array_split(np.arange(n2), n_parts) if len(b)]
+    I = np.zeros(prob.n_probes, dtype=np.float64)
+    for part in map_fn(_int_job, [(prob, psi, b, chunk) for b in parts2]):
+        I += part
+    return I

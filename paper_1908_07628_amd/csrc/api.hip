@@ -304,10 +304,23 @@ void contract(const Plan& p, const Dev& d, const float2* dH, double* map, int bi
                              d.part, d.blob, st);
         }
     } else {
+        if (split) {
+            // SC transposes of the sites' S_1 windows (mid2 holds them until the producer runs)
+            TimeScope ts(EELS_PHASE_PRODUCER, st);
+            for (int k = 0; k < b.job_count; ++k) {
+                const Job& jb = p.jobs[b.job_begin + k];
+                launch_window_t_sc(d.mid2 + jb.dst_off, d.w1 + jb.win_off, p.Kpad, p.N1, p.K, p.N1pad, p.precision,
+                                   st);
+            }
+        }
         {
             TimeScope ts(EELS_PHASE_GEMM1, st);
-            launch_cgemm(EELS_FP32, 1, 0, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.C, d.w1, nullptr, d.mid, nullptr,
-                         d.blob, st);
+            if (split)
+                launch_cgemm_sc(p.precision, 3, nst, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.C, d.mid2, d.mid,
+                                nullptr, d.blob, st, b.d1_rows);
+            else
+                launch_cgemm(EELS_FP32, 1, 0, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.C, d.w1, nullptr, d.mid,
+                             nullptr, d.blob, st);
         }
         if (split || p.recip) run_jobs(p, d, dH, b, b.slice, st);
         {

@@ -36,9 +36,10 @@ struct GemmDesc {
     int flags;         // GD_* bits
     int pad_;
 };
-// descriptor flags: the plain FP32 store epilogue also zeroes the padding columns
-// N .. ceil16(N)-1 of every stored row (they are K padding of a later product)
-enum { GD_ZERO_PAD = 1 };
+// descriptor flags: GD_ZERO_PAD: the plain FP32 store epilogue also zeroes the padding
+// columns N .. ceil16(N)-1 of every stored row (they are K padding of a later product);
+// GD_IDX_A: the split kernel gathers the A rows through idx (instead of the B rows)
+enum { GD_ZERO_PAD = 1, GD_IDX_A = 2 };
 static_assert(sizeof(GemmDesc) == 144, "GemmDesc layout");
 
 // Process-wide tuning knobs (set by eels_tune_set; read at launch time).
@@ -66,6 +67,7 @@ struct Batch {
 struct Job {
     int from_mid;       // 0: W = S_1 window buffer, 1: W = mid (Psi)
     int64_t w_off;      // complex offset of the site's first W row
+    int64_t win_off;    // complex offset of the site's S_1 window (order P, split: transposed first)
     int Ni, nt;
     int64_t h_off;      // complex offset of the site's first transition potential
     int64_t dst_off;    // complex offset in mid2

@@ -87,12 +87,17 @@ void launch_cgemm(int precision, int kind, int epi, const GemmDesc* d_descs, int
 
 // Split-precision grouped GEMM on SC operands (see kernels_gemm.hip); B rows of column
 // block t start at b_off + t * ldh.  epi 0 stores C in SC form, epi 1 writes norm partials,
-// epi 2 the Gram tile conj(A) B^T as FP32 complex (as launch_cgemm).
-// rows: A rows of a tile, 128, or 256 (epi 0 only; the descriptors' tiles_m must count
-// 256-row tiles).
+// epi 2 the Gram tile conj(A) B^T as FP32 complex (as launch_cgemm), epi 3 stores C as
+// complex64.  The index list gathers B rows, or A rows with GD_IDX_A.
+// rows: A rows of a tile, 128, or 256 (epi 0 and 3 only; the descriptors' tiles_m must
+// count 256-row tiles).
 void launch_cgemm_sc(int precision, int epi, int nstage, const GemmDesc* d_descs, int n_desc, int total_tiles,
                      const void* A, const void* B, void* C, float* part, const int* idx, hipStream_t st,
                      int rows = 128);
+// S_1 window [n_beams][K] (complex64, rows wstride apart) -> SC [K][ldo] (its transpose,
+// beams n_beams .. ldo-1 zero; ldo a multiple of 4, dst 32-byte aligned)
+void launch_window_t_sc(void* dst, const float2* src, int64_t wstride, int n_beams, int K, int ldo, int prec,
+                        hipStream_t st);
 // complex64 [rows][ld] -> SC (columns >= K written as zero)
 void launch_to_sc(void* dst, const float2* src, int64_t rows, int K, int ld, int prec, hipStream_t st);
 // SC -> complex64 of n contiguous complex slots

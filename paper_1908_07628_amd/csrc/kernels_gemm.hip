@@ -451,7 +451,7 @@ __global__ __launch_bounds__(128 * WM, (ScPipe<UNITS, NSTAGE, WM>::WAVES_PER_EU)
     constexpr int STAGE = SP::STAGE, ROWB = SP::ROWB, QUADS = SP::QUADS, RPI = SP::RPI, NIA = SP::NIA, NIB = SP::NIB;
     constexpr int BMX = SP::BMX, NT = 128 * WM;
     constexpr int BKS = 4 * UNITS;  // complex per tile row
-    static_assert(WM == 2 || EPI == 0, "the 256-row tile has only the store epilogue");
+    static_assert(WM == 2 || EPI == 0 || EPI == 3, "the 256-row tile has only the store epilogues");
     __shared__ __attribute__((aligned(1024))) char smem[NSTAGE * STAGE];
 
     int tm, tn, t;
@@ -465,6 +465,8 @@ __global__ __launch_bounds__(128 * WM, (ScPipe<UNITS, NSTAGE, WM>::WAVES_PER_EU)
     const char* A = (const char*)Ab + 8 * (d.a_off + (int64_t)t * d.a_tstride);
     const char* B = (const char*)Bb + 8 * (d.b_off + (int64_t)t * d.b_tstride);
     const int* idx = d.idx_off >= 0 ? ib + d.idx_off : nullptr;
+    const int* idx_a = (d.flags & GD_IDX_A) ? idx : nullptr;
+    const int* idx_b = (d.flags & GD_IDX_A) ? nullptr : idx;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WM, wn = wave / WM;
@@ -481,14 +483,15 @@ __global__ __launch_bounds__(128 * WM, (ScPipe<UNITS, NSTAGE, WM>::WAVES_PER_EU)
         int r = wave * 32 + c * RPI + lane / QUADS;
         int q = qpos ^ ((r >> 1) & (QUADS - 1));
         int m = min(m0 + r, M - 1);
-        asrc[c] = A + (int64_t)m * d.lda * 8 + 16 * q;
+        int mr = idx_a ? idx_a[m] : m;
+        asrc[c] = A + (int64_t)mr * d.lda * 8 + 16 * q;
     }
 #pragma unroll
     for (int c = 0; c < NIB; ++c) {
         int r = wave * BRW + c * RPI + lane / QUADS;
         int q = qpos ^ ((r >> 1) & (QUADS - 1));
         int n = min(n0 + r, N - 1);
-        int nr = idx ? idx[n] : n;
+        int nr = idx_b ? idx_b[n] : n;
         bsrc[c] = B + (int64_t)nr * d.ldb * 8 + 16 * q;
     }
     typedef __attribute__((address_space(3))) char lds_char;
@@ -634,6 +637,29 @@ __global__ __launch_bounds__(128 * WM, (ScPipe<UNITS, NSTAGE, WM>::WAVES_PER_EU)
                     if (m < M) sc_store(Cb, cbase + (int64_t)m * d.ldc_m + i, make_float2(accR[bm][bn][v], accI[bm][bn][v]), PREC);
                 }
         }
+    } else if constexpr (EPI == 3) {
+        // store the product as complex64, zeroing the padding columns N .. ceil16(N)-1
+        float2* Cf = (float2*)Cb;
+        const int64_t cbase = d.c_off + (int64_t)t * d.ldc_t;
+        const int npad = (N + 15) & ~15;
+        if (n0 + BN > N && n0 < npad) {
+            for (int e = tid; e < BMX * 16; e += NT) {
+                int m = m0 + e / 16, i = N + e % 16;
+                if (m < M && i < npad && i >= n0 && i < n0 + BN) Cf[cbase + (int64_t)m * d.ldc_m + i] = make_float2(0.f, 0.f);
+            }
+        }
+#pragma unroll
+        for (int bn = 0; bn < 2; ++bn) {
+            int i = n0 + wn * 64 + bn * 32 + li;
+            if (i >= N) continue;
+#pragma unroll
+            for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    int m = m0 + wm * 64 + bm * 32 + 8 * (v >> 2) + 4 * hl + (v & 3);
+                    if (m < M) Cf[cbase + (int64_t)m * d.ldc_m + i] = make_float2(accR[bm][bn][v], accI[bm][bn][v]);
+                }
+        }
     } else {
         __syncthreads();
         float* red = (float*)smem;
@@ -667,6 +693,52 @@ __global__ void k_to_sc(uint32_t* __restrict__ dst, const float2* __restrict__ s
     int k = (int)(i % ld);
     float2 v = k < K ? src[i] : make_float2(0.f, 0.f);
     sc_store(dst, i, v, prec);
+}
+
+// S_1 windows to the B operand of the split probe-wave product Psi = C S_1w: the window
+// [beam][pixel] (complex64, rows wstride apart) becomes SC rows [pixel][beam] of ldo
+// complex, beams n_beams .. ldo-1 zero.  A block moves a 64-pixel x 64-beam tile through
+// LDS, reading whole pixel runs of a beam and writing whole 4-beam SC groups of a pixel.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_window_t_sc(uint32_t* __restrict__ dst, const float2* __restrict__ src,
+                                                     int64_t wstride, int n_beams, int K, int ldo) {
+    __shared__ float2 tile[64][65];
+    const int p0 = blockIdx.x * 64, b0 = blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4) {
+        const int b = b0 + r, px = p0 + tx;
+        tile[r][tx] = (b < n_beams && px < K) ? src[(int64_t)b * wstride + px] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    for (int w = threadIdx.x; w < 64 * 16; w += 256) {
+        const int px = w >> 4, g = w & 15;
+        const int pix = p0 + px, b = b0 + 4 * g;
+        if (pix >= K || b >= ldo) continue;
+        u32x4 hi, lo;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float2 v = tile[4 * g + e][px];
+            uint32_t h, l;
+            split2<PREC>(v.x, v.y, h, l);
+            hi[e] = h;
+            lo[e] = l;
+        }
+        uint32_t* o = dst + (((int64_t)pix * ldo + b) >> 2) * 8;
+        *(u32x4*)o = hi;
+        *(u32x4*)(o + 4) = lo;
+    }
+}
+
+void launch_window_t_sc(void* dst, const float2* src, int64_t wstride, int n_beams, int K, int ldo, int prec,
+                        hipStream_t st) {
+    if (n_beams <= 0 || K <= 0) return;
+    dim3 grid((unsigned)ceil_div(K, 64), (unsigned)ceil_div(ldo, 64));
+    if (prec == EELS_BF16_SPLIT)
+        hipLaunchKernelGGL(k_window_t_sc<EELS_BF16_SPLIT>, grid, dim3(256), 0, st, (uint32_t*)dst, src, wstride,
+                           n_beams, K, ldo);
+    else
+        hipLaunchKernelGGL(k_window_t_sc<EELS_FP16_SPLIT>, grid, dim3(256), 0, st, (uint32_t*)dst, src, wstride,
+                           n_beams, K, ldo);
 }
 
 template <int PREC, int KIND, int EPI>
@@ -710,10 +782,10 @@ static void go_sc(int nstage, int rows, const GemmDesc* dd, int nd, int tiles, c
     const int order = tune_get(TUNE_TILE_ORDER);
 #define SCV(NS, U, SC) \
     hipLaunchKernelGGL((k_cgemm_sc<PREC, EPI, NS, U, SC, 2>), dim3(tiles), dim3(256), 0, st, dd, nd, A, B, C, P, idx, order)
-    if constexpr (EPI == 0) {
+    if constexpr (EPI == 0 || EPI == 3) {
         if (rows == 256) {
-            hipLaunchKernelGGL((k_cgemm_sc<PREC, 0, 2, 4, 0, 4>), dim3(tiles), dim3(512), 0, st, dd, nd, A, B, C, P, idx,
-                               order);
+            hipLaunchKernelGGL((k_cgemm_sc<PREC, EPI, 2, 4, 0, 4>), dim3(tiles), dim3(512), 0, st, dd, nd, A, B, C, P,
+                               idx, order);
             return;
         }
     }
@@ -741,10 +813,12 @@ void launch_cgemm_sc(int precision, int epi, int nstage, const GemmDesc* dd, int
     if (precision == EELS_BF16_SPLIT) {
         if (epi == 0) go_sc<EELS_BF16_SPLIT, 0>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st);
         else if (epi == 2) go_sc<EELS_BF16_SPLIT, 2>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st);
+        else if (epi == 3) go_sc<EELS_BF16_SPLIT, 3>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st);
         else go_sc<EELS_BF16_SPLIT, 1>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st);
     } else {
         if (epi == 0) go_sc<EELS_FP16_SPLIT, 0>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st);
         else if (epi == 2) go_sc<EELS_FP16_SPLIT, 2>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st);
+        else if (epi == 3) go_sc<EELS_FP16_SPLIT, 3>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st);
         else go_sc<EELS_FP16_SPLIT, 1>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st);
     }
 }

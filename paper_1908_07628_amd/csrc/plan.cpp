@@ -273,7 +273,7 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     p.gemm_flops = p.order == EELS_ORDER_S_FIRST ? (p.gram ? fl_G : fl_S) : fl_P;
     p.c_scale = p.precision == EELS_FP16_SPLIT ? 256.0f : 1.0f;
     const bool orderS = p.order == EELS_ORDER_S_FIRST;
-    p.c_sc = (split && orderS && !p.gram) ? p.precision : 0;   // the Gram quadratic form reads complex64
+    p.c_sc = (split && !p.gram) ? p.precision : 0;   // the Gram quadratic form reads complex64
     p.w2_sc = split ? p.precision : 0;
     p.mid2_sc = split ? p.precision : 0;
 
@@ -302,7 +302,10 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     auto site_ni = [&](int s) -> int64_t { return orderS ? p.N1 : n_elig(s); };
     auto site_mid2 = [&](int s) -> int64_t {
         if (!p.recip && !split) return 0;
-        return (int64_t)p.sites[s].n_trans * site_ni(s) * Kcpad;
+        int64_t m2 = (int64_t)p.sites[s].n_trans * site_ni(s) * Kcpad;
+        // order P, split: the site's S_1 window is first transposed here for the product C S_1w
+        if (split && !orderS) m2 = std::max(m2, (int64_t)p.K * p.N1pad);
+        return m2;
     };
     auto site_part = [&](int s) -> int64_t {
         if (p.gram) return 2 * (int64_t)p.sites[s].n_trans * p.N1pad * p.N1pad;   // FP32 partials of Z_t^H Z_t
@@ -501,8 +504,8 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     const int64_t w1_stride = (int64_t)p.N1 * p.Kpad, w2_stride = (int64_t)p.N2 * p.Kpad;
     const bool h_in_gemm = !p.recip && !split;     // FP32 real-space: H applied in the GEMM prologue
     const bool gram_stack = tune_get(TUNE_GRAM_STACK) != 0;
-    // the split first GEMM of order S may use 256-row tiles (store epilogue only)
-    const int rows1 = (split && orderS && tune_get(TUNE_GEMM1_ROWS) != 0) ? 256 : GEMM_BM;
+    // the split first GEMM (a store epilogue in both orders) may use 256-row tiles
+    const int rows1 = (split && tune_get(TUNE_GEMM1_ROWS) != 0) ? 256 : GEMM_BM;
     for (auto& pb : pend) {
         Batch bt{};
         bt.slice = pb.slice;
@@ -521,6 +524,7 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
                 Job jb{};
                 jb.from_mid = orderS ? 0 : 1;
                 jb.w_off = orderS ? (int64_t)p.site_w1[s] * w1_stride : site_moff[si];
+                jb.win_off = (int64_t)p.site_w1[s] * w1_stride;
                 jb.Ni = (int)site_ni(s);
                 jb.nt = p.sites[s].n_trans;
                 jb.h_off = p.sites[s].h_offset * p.K;
@@ -572,9 +576,15 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
                 d.M = p.N2; d.N_inner = p.N1; d.n_t = st.n_trans; d.K = Kc;
                 d.idx_off = -1;
             } else {
-                // Psi_s[i][r] = sum_k C[idx[i]][k] S1w[k][r]   (B operand N-contiguous)
+                // Psi_s[i][r] = sum_k C[idx[i]][k] S1w[k][r]: FP32 reads S1w as an N-contiguous
+                // B operand; split reads the SC transpose of the window written into mid2
                 d.a_off = 0; d.lda = p.N1pad;
-                d.b_off = (int64_t)p.site_w1[s] * w1_stride; d.ldb = p.Kpad;
+                if (split) {
+                    d.b_off = site_m2off[si]; d.ldb = p.N1pad;
+                    d.flags = GD_IDX_A;
+                } else {
+                    d.b_off = (int64_t)p.site_w1[s] * w1_stride; d.ldb = p.Kpad;
+                }
                 d.h_off = -1; d.ldh = 0;
                 d.c_off = site_moff[si]; d.ldc_m = p.Kpad; d.ldc_t = 0;
                 d.M = Ps; d.N_inner = p.K; d.n_t = 1; d.K = p.N1;
