@@ -362,3 +362,35 @@ def test_interpolation_factor_one_matches_fine_lattice_reference():
     # f = 1 with a crop equals the conventional map with H zero outside the window
     p = synth.random_problem(12, n=48, L=10.0, nz=3, window_A=4.0, n_sites=2, interp_f=1)
     assert metrics.rel_l2(prism.prism_map(p), conventional.conventional_map(p)) < 1e-12
+
+
+@pytest.mark.parametrize("kw", [
+    dict(seed=31, n=32, L=8.0, nz=4, n_sites=3, n_trans=3),
+    dict(seed=32, n=48, ny=32, L=10.0, Ly=7.0, nz=3, window_A=3.0, n_sites=2, det_inner_mrad=6.0,
+         det_outer_mrad=24.0),
+])
+def test_beam_split_map_equals_conventional(kw):
+    """The map regrouped by beams (disjoint aperture and detector beam sets, uneven parts)
+    equals the conventional multislice map (the plain definition) to rounding."""
+    kw = dict(kw)
+    p = synth.random_problem(kw.pop("seed"), **kw)
+    I1 = conventional.conventional_map(p)
+    for parts, chunk in ((1, 1000), (3, 5), (7, 2)):
+        assert metrics.rel_l2(prism.prism_map_by_beams(p, n_parts=parts, chunk=chunk), I1) < 1e-12
+
+
+def test_beam_split_map_with_interpolation_and_crop():
+    """f = 2 with cropped windows (the nanoparticle form): the beam-split map equals the
+    stored-S map, and probes that see no site get exactly zero."""
+    p = synth.config3_subproblem(n=128, L=25.0, nz=3, n_scan=4, f=2)
+    far = np.array([[1.0, 1.0]])          # a probe whose L/f box holds no crop box
+    p = p.replace(probes=np.concatenate([p.probes, far]), probe_shape=(1, p.n_probes + 1))
+    ref = prism.prism_map(p)
+    got = prism.prism_map_by_beams(p, n_parts=4, chunk=7)
+    assert np.max(ref) > 0
+    assert metrics.rel_l2(got, ref) < 1e-12
+    st = make_setup(p)
+    from oracle.common import site_eligible
+    seen = np.any([site_eligible(p, st, s) for s in range(p.n_sites)], axis=0)
+    assert not seen[-1] and seen.sum() >= 1
+    assert np.all(got[~seen] == 0.0) and np.all(got[seen] > 0)
