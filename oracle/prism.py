@@ -86,6 +86,18 @@ def reverse_s2(prob, st, j_stop: int = 0):
         x = np.fft.ifft2(S2)
 
 
+def contract_windows(S1w: np.ndarray, S2w: np.ndarray, C_el: np.ndarray, Hs, f2: float) -> np.ndarray:
+    """One site's contribution to its eligible probes, f^2 sum_n sum_q |A_n(q, R)|^2, from
+    its windows S1w [N1, K] and S2w [N2, K], the probe coefficients C_el [N1, Pe] and the
+    transition potentials Hs (each [K]) on the window pixels."""
+    Psi = S1w.T @ C_el                                       # [K, Pe]  probe waves on the window
+    out = np.zeros(C_el.shape[1], dtype=np.float64)
+    for h in Hs:
+        A = S2w @ (h[:, None] * Psi)                         # [N2, Pe]
+        out += f2 * (np.abs(A) ** 2).sum(axis=0)
+    return out
+
+
 def contract_site(prob, st, s: int, S1j: np.ndarray, S2j: np.ndarray, I: np.ndarray):
     """Add site s's transitions to the map I (in place)."""
     rows, cols = site_window(prob, st, s)
@@ -95,12 +107,8 @@ def contract_site(prob, st, s: int, S1j: np.ndarray, S2j: np.ndarray, I: np.ndar
     el = site_eligible(prob, st, s)
     if not np.any(el):
         return
-    Psi = S1w.T @ st.C[:, el]                                # [K, Pe]  probe waves on the window
-    f2 = float(int(prob.interp_f) ** 2)
-    for n in range(int(prob.site_ntrans[s])):
-        h = site_H(prob, s, n).reshape(-1)
-        A = S2w @ (h[:, None] * Psi)                         # [N2, Pe]
-        I[el] += f2 * (np.abs(A) ** 2).sum(axis=0)
+    Hs = [site_H(prob, s, n).reshape(-1) for n in range(int(prob.site_ntrans[s]))]
+    I[el] += contract_windows(S1w, S2w, st.C[:, el], Hs, float(int(prob.interp_f) ** 2))
 
 
 def prism_map(prob, lam=None, sigma=None, st=None, s1_mode: str = "stored") -> np.ndarray:
