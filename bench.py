@@ -232,6 +232,213 @@ def bench_serve(args):
     return out
 
 
+NANO_WORKLOAD = ("nanoparticle 1024x1024 px over 100x100 A, 50 slices x 2 A: 80 A bcc sphere (22,659 atoms, "
+                 "all ionised x 9 transitions) on a 20 A amorphous support (20,000 atoms); PRISM f = 4, 4 A crop "
+                 "windows, 256x256 probes, 300 keV, 20 mrad aperture, 0-20 mrad detector")
+
+
+def cpu_baseline_nanoparticle(p, info, sample_beams=3, sample_probes=1024):
+    """FP64 PRISM oracle (one BLAS thread) on a bounded sample, scaled by its operation counts:
+    `sample_beams` aperture beams swept to the deepest ionised slice and as many detector beams
+    swept from the exit to the shallowest (the oracle sweeps every beam this way), and one
+    site's contraction (oracle.prism.contract_windows) on windows of the real shapes with
+    `sample_probes` eligible probes.  Full map = N_1 / sample_beams x S_1 sample + N_2 /
+    sample_beams x S_2 sample + the contraction of every site, which is linear in its
+    eligible-probe count."""
+    import dataclasses
+    import threadpoolctl
+    from oracle import prism
+    from oracle.common import make_setup, site_eligible
+    ion = sorted(set(p.site_slice.tolist()))
+    with threadpoolctl.threadpool_limits(1):
+        t0 = time.perf_counter()
+        st = make_setup(p.replace(probes=p.probes[:1], probe_shape=(1, 1)))
+        t_setup = time.perf_counter() - t0
+        b = slice(0, sample_beams)
+        st1 = dataclasses.replace(st, ab1=st.ab1[b], ix1=st.ix1[b], iy1=st.iy1[b], C=st.C[b])
+        t0 = time.perf_counter()
+        prism.forward_s1(p, st1, [ion[-1]])
+        t_s1 = time.perf_counter() - t0
+        st2 = dataclasses.replace(st, ab2=st.ab2[b], ix2=st.ix2[b], iy2=st.iy2[b])
+        t0 = time.perf_counter()
+        for _ in prism.reverse_s2(p, st2, j_stop=ion[0]):
+            pass
+        t_s2 = time.perf_counter() - t0
+        rng = np.random.default_rng(0)
+        K, N1, N2 = info["k_pixels"], info["n_beams_in"], info["n_beams_out"]
+        cplx = lambda *sh: rng.standard_normal(sh) + 1j * rng.standard_normal(sh)
+        S1w, S2w, C = cplx(N1, K), cplx(N2, K), cplx(N1, sample_probes)
+        Hs = [cplx(K) for _ in range(int(p.site_ntrans[0]))]
+        t0 = time.perf_counter()
+        prism.contract_windows(S1w, S2w, C, Hs, 16.0)
+        t_site = time.perf_counter() - t0
+    # mean eligible-probe count per site on the full raster (the oracle's f > 1 rule), over
+    # a seeded sample of sites
+    pick = np.random.default_rng(1).choice(p.n_sites, size=min(64, p.n_sites), replace=False)
+    ps_mean = float(np.mean([np.sum(site_eligible(p, st, int(s))) for s in pick]))
+    full = t_setup + (N1 * t_s1 + N2 * t_s2) / sample_beams + p.n_sites * t_site * ps_mean / sample_probes
+    measured = t_setup + t_s1 + t_s2 + t_site
+    return {
+        "value": p.n_probes / full, "unit": "probe-px/s", "cores": 1, "kind": "oracle",
+        "sample": (f"PRISM oracle FP64 (numpy FFT, one BLAS thread): set-up {t_setup:.1f} s, {sample_beams} "
+                   f"aperture beams to slice {ion[-1]} {t_s1:.1f} s, {sample_beams} detector beams from the exit to "
+                   f"slice {ion[0]} {t_s2:.1f} s, one site's contraction with {sample_probes} probes "
+                   f"{t_site:.1f} s; scaled to "
+                   f"{N1} + {N2} beams and {p.n_sites} sites x {ps_mean:.0f} eligible probes "
+                   f"(estimated {full / 3600:.0f} h per map)"),
+        "seconds_measured": round(measured, 1),
+        "host_cpus": os.cpu_count(),
+    }
+
+
+def bench_nanoparticle(args):
+    """Nanoparticle workload: the f = 4, 4 A-crop map (order P) at full size."""
+    import torch
+    import synth
+    from paper_1908_07628_amd import eels
+    t0 = time.time()
+    p = synth.config3()
+    log(f"inputs generated in {time.time() - t0:.1f} s: {p.n_sites} sites, {p.n_trans} transitions")
+    V, H = eels.device_inputs(p)
+    free, total = torch.cuda.mem_get_info()
+    budget = int(free - (8 << 30))
+    ion = sorted(set(p.site_slice.tolist()))
+
+    # untimed warm-up on the top ionised slice (loads the kernels; not a step)
+    small = subset_sites(p, np.nonzero(p.site_slice == ion[-1])[0])
+    wplan = eels.Plan(small, precision=args.precision, max_workspace_bytes=budget)
+    wws = wplan.alloc_workspace()
+    wout = torch.empty(p.n_probes, dtype=torch.float64, device="cuda")
+    wplan.execute(V, H, wout, wws)
+    torch.cuda.synchronize()
+    del wws, wplan
+    torch.cuda.empty_cache()
+
+    plan = eels.Plan(p, precision=args.precision, max_workspace_bytes=budget)
+    info = plan.info()
+    ws = plan.alloc_workspace()
+    out = torch.empty(p.n_probes, dtype=torch.float64, device="cuda")
+    log(f"plan: N1={info['n_beams_in']} N2={info['n_beams_out']} K={info['k_pixels']} "
+        f"order={'S' if info['order'] == 1 else 'P'} groups={info['n_groups']} batches={info['n_batches']} "
+        f"workspace={info['workspace_bytes'] / 1e9:.1f} GB (budget {budget / 1e9:.0f} GB)")
+    for w in range(args.warmup):
+        plan.execute(V, H, out, ws)
+        torch.cuda.synchronize()
+        log(f"warmup step {w + 1}/{args.warmup} done")
+    eels.timing_enable(1 << 16)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    phase_tot = {}
+    for k in range(args.steps):
+        plan.execute(V, H, out, ws)
+        torch.cuda.synchronize()
+        for name, v in eels.timing_read().items():
+            a = phase_tot.setdefault(name, {"ms": 0.0, "count": 0})
+            a["ms"] += v["ms"]
+            a["count"] += v["count"]
+        log(f"step {k + 1}/{args.steps} done")
+    elapsed = time.perf_counter() - t_start
+    eels.timing_enable(0)
+    value = p.n_probes * args.steps / elapsed
+    gpu_map = out.cpu().numpy()
+    del ws
+    torch.cuda.empty_cache()
+    phases = {k: round(v["ms"] / args.steps, 1) for k, v in phase_tot.items()}
+
+    # dominant kernel: the second contraction GEMM, A_n = S_2w (H_n Psi), 8 N_2 K n_t P_s
+    # useful flops per site; with one transition count for every site its share of the
+    # plan's flops is N_2 n_t / (N_1 + N_2 n_t) (the first product is 8 P_s K N_1)
+    nt = set(p.site_ntrans.tolist())
+    assert len(nt) == 1, "the GEMM-2 flop split assumes one transition count"
+    nt = float(nt.pop())
+    N1, N2, K = info["n_beams_in"], info["n_beams_out"], info["k_pixels"]
+    g2_flops = info["gemm_flops"] * N2 * nt / (N1 + N2 * nt)
+    g1_flops = info["gemm_flops"] - g2_flops
+    split = args.precision != "fp32"
+    exec_factor = 3.0 if split else 1.0
+    g2 = phase_tot["gemm2"]
+    n_launch = g2["count"] / args.steps
+    avg_ms = g2["ms"] / max(g2["count"], 1)
+    per_launch = g2_flops / n_launch
+    achieved = exec_factor * per_launch / (avg_ms * 1e-3) / 1e12
+    peak = PEAK_BF16_TFLOPS if split else PEAK_FP32_TFLOPS
+    roofline = {
+        "bound": "mfma", "kernel": ("k_cgemm_sc, norm epilogue (second contraction GEMM)" if split
+                                    else "k_cgemm, norm epilogue"),
+        "achieved": round(achieved, 1), "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+        "traffic": None, "avg_launch_ms": round(avg_ms, 3), "launches_per_step": n_launch,
+        "algorithmic_flops_per_launch": exec_factor * per_launch,
+        "useful_complex_tflops": round(per_launch / (avg_ms * 1e-3) / 1e12, 1),
+        "flop_definition": ("3 BF16 MFMA products per complex multiply-add of the split algorithm, 8 real flops "
+                            "each; useful = 8 M N K complex" if split else "8 M N K"),
+    }
+    g1 = phase_tot["gemm1"]
+    gemm1 = {"useful_complex_tflops": round(g1_flops * args.steps / (g1["ms"] * 1e-3) / 1e12, 1),
+             "executed_frac": round(exec_factor * g1_flops * args.steps / (g1["ms"] * 1e-3) / 1e12 / peak, 4)}
+    nlx = info["n_live_x"]
+    cap_bytes = 8.0 * p.n_sites * K * (N1 + N2)
+    sweep_bytes = info["sweep_bytes"] + cap_bytes
+    roofline_fft = {"sweeps": {
+        "bound": "hbm", "kernels": "k_row_pass + k_col_pass (with S_1 and S_2 window captures)",
+        "achieved": round(sweep_bytes / (phases["sweep"] * 1e-3) / 1e9, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+        "frac": round(sweep_bytes / (phases["sweep"] * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4),
+        "algorithmic_bytes_per_step": sweep_bytes,
+        "byte_definition": (f"32 B x n_y x n_live_x ({nlx}) per beam-slice (2 passes, read + write; S_1 swept "
+                            f"once per slice group) + 8 B per window pixel per beam captured")}}
+
+    # FP32 on the top ionised slices (contractions scaled by GEMM work; set-up and sweeps
+    # from the full step)
+    ps = subset_sites(p, np.nonzero(np.isin(p.site_slice, ion[-args.fp32_slices:]))[0])
+    p32 = eels.Plan(ps, precision="fp32", max_workspace_bytes=budget)
+    i32 = p32.info()
+    ws32 = p32.alloc_workspace()
+    o32 = torch.empty(p.n_probes, dtype=torch.float64, device="cuda")
+    p32.execute(V, H, o32, ws32)
+    torch.cuda.synchronize()
+    eels.timing_enable(1 << 16)
+    p32.execute(V, H, o32, ws32)
+    torch.cuda.synchronize()
+    ph32 = eels.timing_read()
+    eels.timing_enable(0)
+    del ws32
+    contract_ms = sum(ph32[k]["ms"] for k in ("producer", "gemm1", "gemm2", "reduce"))
+    scale = info["gemm_flops"] / i32["gemm_flops"]
+    est_ms = phases["setup"] + phases["sweep"] + contract_ms * scale
+    fp32 = {"value": p.n_probes / (est_ms * 1e-3), "ms_per_step": round(est_ms, 1),
+            "measured_on": (f"contractions of the top {args.fp32_slices} ionised slices ({ps.n_sites} sites, "
+                            f"{contract_ms:.0f} ms) scaled by GEMM work x{scale:.1f}; set-up and sweeps from "
+                            "the full split step")}
+    # the same sites in the split precision, against the FP32 map
+    psp = eels.Plan(ps, precision=args.precision, max_workspace_bytes=budget)
+    wsp = psp.alloc_workspace()
+    osp = torch.empty(p.n_probes, dtype=torch.float64, device="cuda")
+    psp.execute(V, H, osp, wsp)
+    torch.cuda.synchronize()
+    del wsp
+    m32, msp = o32.cpu().numpy(), osp.cpu().numpy()
+    fp32["split_rel_l2_vs_fp32"] = float(np.linalg.norm(msp - m32) / np.linalg.norm(m32))
+
+    result = {
+        "metric": METRIC, "value": round(value, 2), "unit": "probe-px/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 1), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16" if args.precision == "bf16_split" else args.precision,
+        "data": "synthetic",
+        "config": {"workload": NANO_WORKLOAD, "grid": [p.nx, p.ny], "n_slices": p.n_slices, "n_sites": p.n_sites,
+                   "n_transitions": p.n_trans, "n_probes": p.n_probes, "N1": N1, "N2": N2, "window_pixels": K,
+                   "interp_f": p.interp_f, "slice_groups": info["n_groups"], "batches": info["n_batches"],
+                   "workspace_GB": round(info["workspace_bytes"] / 1e9, 1),
+                   "precision": args.precision + " (hi+lo products, FP32 accumulate, FP64 map)"
+                   if split else "fp32", "contraction": "cropped windows, order P"},
+        "roofline": roofline, "gemm1": gemm1, "roofline_fft": roofline_fft, "phases_ms": phases, "fp32": fp32,
+        "split_over_fp32": round(value / fp32["value"], 2),
+        "map_sum": float(np.sum(gpu_map)),
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle sample ...")
+        result["cpu_baseline"] = cpu_baseline_nanoparticle(p, info)
+    return result
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -242,9 +449,10 @@ def main():
     ap.add_argument("--fp32-slices", type=int, default=2, help="ionised slices of the FP32 sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", action="store_true", help="compare sampled probes with the stored FP64 values")
-    ap.add_argument("--workload", default="crystal", choices=["crystal", "batch", "serve"],
-                    help="crystal: the benchmark map (default); batch: 64 uneven specimens in one graph; "
-                         "serve: Poisson request stream with p50/p99 latency")
+    ap.add_argument("--workload", default="crystal", choices=["crystal", "nanoparticle", "batch", "serve"],
+                    help="crystal: the benchmark map (default); nanoparticle: the f = 4 cropped-window map; "
+                         "batch: 64 uneven specimens in one graph; serve: Poisson request stream with p50/p99 "
+                         "latency")
     ap.add_argument("--profile-sample", type=int, default=0, metavar="N",
                     help="for counter runs: a 1 GiB device copy (calibration), then one map on the "
                          "top N ionised slices; prints one line")
@@ -262,7 +470,7 @@ def main():
     if args.workload != "crystal":
         if args.precision == "bf16_split" and args.workload == "batch":
             args.precision = "fp16_split"
-        res = bench_batch(args) if args.workload == "batch" else bench_serve(args)
+        res = {"batch": bench_batch, "serve": bench_serve, "nanoparticle": bench_nanoparticle}[args.workload](args)
         print(json.dumps(res), flush=True)
         return
 

@@ -254,7 +254,7 @@ eels_status eels_debug_cgemm(int precision, int m, int n, int k, const void* d_A
                              const void* d_B, int ldb, void* d_C, int ldc, double* d_norm2,
                              void* d_work, void* stream);
 
-/* Process-wide kernel tuning knobs, read at launch time (keys 3 and 4: at plan time; the
+/* Process-wide kernel tuning knobs, read at launch time (keys 3, 4 and 5: at plan time; the
  * autotuner sets them).
  * key 0: LDS pipeline of the split-precision GEMM: 2 (two stages of 16-complex tiles, two
  *        workgroups per CU, default), 3 (three such stages, one workgroup per CU), 4 or 5
@@ -268,8 +268,11 @@ eels_status eels_debug_cgemm(int precision, int m, int n, int k, const void* d_A
  *        the wave's issue priority while it issues MFMAs (0 default).
  * key 3: rows of the Gram form's first GEMM: 1 (default) the transitions of a site stacked
  *        into one M = n_t N_1, 0 one N_1-row problem per transition.
- * key 4: tiles of the first contraction GEMM in split precision (order S): 1 (default) 256 x 128
- *        tiles of 8 waves, one workgroup per CU; 0 128 x 128 tiles of 4 waves.
+ * key 4: tiles of the first contraction GEMM in split precision (both orders): 1 (default)
+ *        256 x 128 tiles of 8 waves, one workgroup per CU; 0 128 x 128 tiles of 4 waves.
+ * key 5: tiles of the second contraction GEMM in split precision with the per-probe
+ *        detector sum (not the Gram form): 1 (default) 256 x 128 tiles of 8 waves; 0
+ *        128 x 128 tiles of 4 waves.
  * Returns EELS_ERR_INVALID_ARG for an unknown key or an out-of-range value. */
 eels_status eels_tune_set(int key, int value);
 int eels_tune_get(int key);

@@ -32,7 +32,7 @@ namespace eels {
 static thread_local std::string g_err;
 void set_error(const std::string& m) { g_err = m; }
 
-static std::atomic<int> g_tune[TUNE_COUNT] = {{2}, {2}, {0}, {1}, {1}, {0}, {0}, {0}};
+static std::atomic<int> g_tune[TUNE_COUNT] = {{2}, {2}, {0}, {1}, {1}, {1}, {0}, {0}};
 int tune_get(int key) { return (key >= 0 && key < TUNE_COUNT) ? g_tune[key].load() : 0; }
 
 // Diagnostic phase timing (eels_timing_enable / eels_timing_read).
@@ -298,7 +298,7 @@ void contract(const Plan& p, const Dev& d, const float2* dH, double* map, int bi
             TimeScope ts(EELS_PHASE_GEMM2, st);
             if (split)
                 launch_cgemm_sc(p.precision, 1, nst, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.mid, d.C, nullptr,
-                                d.part, d.blob, st);
+                                d.part, d.blob, st, b.d2_rows);
             else
                 launch_cgemm(EELS_FP32, 0, 1, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.mid, d.C, nullptr, nullptr,
                              d.part, d.blob, st);
@@ -327,7 +327,7 @@ void contract(const Plan& p, const Dev& d, const float2* dH, double* map, int bi
             TimeScope ts(EELS_PHASE_GEMM2, st);
             if (split)
                 launch_cgemm_sc(p.precision, 1, nst, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.w2, d.mid2, nullptr,
-                                d.part, d.blob, st);
+                                d.part, d.blob, st, b.d2_rows);
             else
                 launch_cgemm(EELS_FP32, 0, 1, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.w2, h_pro ? d.mid : d.mid2,
                              h_pro ? dH : nullptr, nullptr, d.part, d.blob, st);
@@ -837,6 +837,7 @@ eels_status eels_tune_set(int key, int value) {
     if (key == TUNE_SC_SCHED && (value < 0 || value > 3)) return EELS_ERR_INVALID_ARG;
     if (key == TUNE_GRAM_STACK && (value < 0 || value > 1)) return EELS_ERR_INVALID_ARG;
     if (key == TUNE_GEMM1_ROWS && (value < 0 || value > 1)) return EELS_ERR_INVALID_ARG;
+    if (key == TUNE_GEMM2_ROWS && (value < 0 || value > 1)) return EELS_ERR_INVALID_ARG;
     g_tune[key].store(value);
     return EELS_OK;
 }

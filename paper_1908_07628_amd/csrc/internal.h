@@ -45,7 +45,7 @@ static_assert(sizeof(GemmDesc) == 144, "GemmDesc layout");
 // Process-wide tuning knobs (set by eels_tune_set; read at launch time).
 enum TuneKey {
     TUNE_SC_STAGES = 0, TUNE_TILE_ORDER = 1, TUNE_SC_SCHED = 2, TUNE_GRAM_STACK = 3, TUNE_GEMM1_ROWS = 4,
-    TUNE_COUNT = 8
+    TUNE_GEMM2_ROWS = 5, TUNE_COUNT = 8
 };
 int tune_get(int key);
 
@@ -55,6 +55,7 @@ struct Batch {
     int d1_begin, d1_count, d1_tiles;   // first GEMM (store epilogue)
     int d1_rows = 128;                  // A rows per tile of the first GEMM (128 or 256)
     int d2_begin, d2_count, d2_tiles;   // second GEMM (norm epilogue)
+    int d2_rows = 128;                  // A rows per tile of the second GEMM (split norm epilogue: 128 or 256)
     int job_begin, job_count;           // producer jobs run between the two GEMMs (order P) or before
     int64_t red_ptr;                    // int offset of the per-probe CSR row pointers [P+1], -1: dense
     int64_t red_ent;                    // int offset of the CSR entries (pairs: desc, column)

@@ -451,7 +451,7 @@ __global__ __launch_bounds__(128 * WM, (ScPipe<UNITS, NSTAGE, WM>::WAVES_PER_EU)
     constexpr int STAGE = SP::STAGE, ROWB = SP::ROWB, QUADS = SP::QUADS, RPI = SP::RPI, NIA = SP::NIA, NIB = SP::NIB;
     constexpr int BMX = SP::BMX, NT = 128 * WM;
     constexpr int BKS = 4 * UNITS;  // complex per tile row
-    static_assert(WM == 2 || EPI == 0 || EPI == 3, "the 256-row tile has only the store epilogues");
+    static_assert(WM == 2 || EPI != 2, "the 256-row tile has no Gram epilogue");
     __shared__ __attribute__((aligned(1024))) char smem[NSTAGE * STAGE];
 
     int tm, tn, t;
@@ -680,7 +680,10 @@ __global__ __launch_bounds__(128 * WM, (ScPipe<UNITS, NSTAGE, WM>::WAVES_PER_EU)
         __syncthreads();
         if (tid < BN) {
             int i = n0 + tid;
-            if (i < N) Pb[d.p_off + (int64_t)tm * d.ld_part + (int64_t)t * N + i] = red[tid] + red[BN + tid];
+            float acc = red[tid];
+#pragma unroll
+            for (int w = 1; w < WM; ++w) acc += red[w * BN + tid];
+            if (i < N) Pb[d.p_off + (int64_t)tm * d.ld_part + (int64_t)t * N + i] = acc;
         }
     }
 }
@@ -782,7 +785,7 @@ static void go_sc(int nstage, int rows, const GemmDesc* dd, int nd, int tiles, c
     const int order = tune_get(TUNE_TILE_ORDER);
 #define SCV(NS, U, SC) \
     hipLaunchKernelGGL((k_cgemm_sc<PREC, EPI, NS, U, SC, 2>), dim3(tiles), dim3(256), 0, st, dd, nd, A, B, C, P, idx, order)
-    if constexpr (EPI == 0 || EPI == 3) {
+    if constexpr (EPI != 2) {
         if (rows == 256) {
             hipLaunchKernelGGL((k_cgemm_sc<PREC, EPI, 2, 4, 0, 4>), dim3(tiles), dim3(512), 0, st, dd, nd, A, B, C, P,
                                idx, order);

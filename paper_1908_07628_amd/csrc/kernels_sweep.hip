@@ -257,20 +257,30 @@ __device__ __forceinline__ void row_pass_body(float2* __restrict__ state, int nb
         // forward row pass's output (the state after the final FFT_x is exact), so the captured
         // entrance wave is scaled by nx (exact) to match the forward capture.
         constexpr float cap_scale = MODE == 2 ? (float)N : 1.0f;
+        // Capture: the row is put in pixel order into its own exchange slots (free between the
+        // two transforms; a row's T <= 64 threads are one wave, whose LDS operations complete
+        // in order), then each record's window row is written with one coalesced store per
+        // T pixels.
         auto capture = [&]() {
-            if (CAP && valid) {
-                int r0 = cap_ptr[y], r1 = cap_ptr[y + 1];
-                for (int r = r0; r < r1; ++r) {
-                    int4 rec = cap_rec[r];
-                    int64_t dst = ((int64_t)rec.x * win_beams + beam) * Kpad + (int64_t)rec.y * rec.w;
+            if constexpr (CAP) {
+                float2* crow = lds + s * L;
+                __builtin_amdgcn_wave_barrier();
 #pragma unroll
-                    for (int m = 0; m < E; ++m) {
-                        int u = t + T * m - rec.z;
-                        if (u < 0) u += N;
-                        if (u < rec.w)
-                            store_c(win, dst + u, make_float2(v[m].x * cap_scale, v[m].y * cap_scale), sc);
+                for (int m = 0; m < E; ++m) crow[t + T * m] = make_float2(v[m].x * cap_scale, v[m].y * cap_scale);
+                __builtin_amdgcn_wave_barrier();
+                if (valid) {
+                    const int r0 = cap_ptr[y], r1 = cap_ptr[y + 1];
+                    for (int r = r0; r < r1; ++r) {
+                        const int4 rec = cap_rec[r];
+                        const int64_t dst = ((int64_t)rec.x * win_beams + beam) * Kpad + (int64_t)rec.y * rec.w;
+                        for (int u = t; u < rec.w; u += T) {
+                            int px = rec.z + u;
+                            if (px >= N) px -= N;
+                            store_c(win, dst + u, crow[px], sc);
+                        }
                     }
                 }
+                __builtin_amdgcn_wave_barrier();
             }
         };
         if constexpr (MODE == 0) capture();

@@ -506,6 +506,8 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     const bool gram_stack = tune_get(TUNE_GRAM_STACK) != 0;
     // the split first GEMM (a store epilogue in both orders) may use 256-row tiles
     const int rows1 = (split && tune_get(TUNE_GEMM1_ROWS) != 0) ? 256 : GEMM_BM;
+    // and so may the split second GEMM with the norm epilogue (not the Gram tiles)
+    const int rows2 = (split && !p.gram && tune_get(TUNE_GEMM2_ROWS) != 0) ? 256 : GEMM_BM;
     for (auto& pb : pend) {
         Batch bt{};
         bt.slice = pb.slice;
@@ -649,7 +651,7 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
                 d.M = p.N2; d.N_inner = Ps; d.n_t = st.n_trans; d.K = Kc;
                 d.idx_off = -1;
             }
-            d.tiles_m = (int)ceil_div(d.M, GEMM_BM);
+            d.tiles_m = (int)ceil_div(d.M, rows2);
             d.tiles_n = (int)ceil_div(d.N_inner, GEMM_BN);
             d.tile_start = tiles;
             d.p_off = poff; d.ld_part = (int64_t)d.n_t * d.N_inner;
@@ -666,6 +668,7 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
         }
         bt.d2_count = (int)p.descs.size() - bt.d2_begin;
         bt.d2_tiles = tiles;
+        bt.d2_rows = p.gram ? GEMM_BM : rows2;
         if (p.f > 1) {
             std::vector<int32_t> ptr(p.P + 1, 0), flat;
             for (int r = 0; r < p.P; ++r) {

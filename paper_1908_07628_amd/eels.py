@@ -323,6 +323,7 @@ TUNE_TILE_ORDER = 1
 TUNE_SC_SCHED = 2
 TUNE_GRAM_STACK = 3
 TUNE_GEMM1_ROWS = 4
+TUNE_GEMM2_ROWS = 5
 
 
 def tune_set(key: int, value: int):

@@ -223,7 +223,8 @@ def test_tuning_knob_ranges_and_gram_stack_plan():
     """Knob values are range-checked; the Gram form's first GEMM stacks the transitions'
     rows by default (plan-time knob 3)."""
     _lib()
-    for key, bad in ((0, 1), (0, 6), (1, 3), (2, 4), (3, 2), (3, -1), (4, 2), (9, 0)):
+    for key, bad in ((0, 1), (0, 6), (1, 3), (2, 4), (3, 2), (3, -1), (4, 2), (5, 2), (5, -1), (9, 0)):
         with pytest.raises(eels.EelsError):
             eels.tune_set(key, bad)
     assert eels.tune_get(eels.TUNE_GRAM_STACK) == 1 and eels.tune_get(eels.TUNE_GEMM1_ROWS) == 1
+    assert eels.tune_get(eels.TUNE_GEMM2_ROWS) == 1

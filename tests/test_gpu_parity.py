@@ -275,6 +275,33 @@ def test_gemm1_tile_rows_match(prec, detsum):
         assert metrics.rel_l2(maps[0], prism.prism_map(p)) < 1e-3
 
 
+@pytest.mark.parametrize("prec", ["bf16_split", "fp16_split"])
+def test_order_p_split_tile_rows(prec):
+    """Order P in split precision (the first product reads SC transposes of the S_1
+    windows and gathers the eligible probes' rows of C).  256- and 128-row tiles of the first
+    GEMM accumulate every element in the same order (bitwise-equal maps); 256- and 128-row
+    tiles of the second GEMM group the FP32 partial sums differently (equal to 1e-6).  Both
+    meet the split bar against the oracle.  Config 1 forced to order P, and the f = 2 cell
+    with crop windows."""
+    eels = _need_gpu()
+    for p in (synth.config1(), synth.config3_subproblem(n=128, L=25.0, nz=5, n_scan=6, f=2)):
+        ref = prism.prism_map(p)
+        maps = {}
+        try:
+            for r1, r2 in ((1, 1), (0, 1), (1, 0)):
+                eels.tune_set(eels.TUNE_GEMM1_ROWS, r1)
+                eels.tune_set(eels.TUNE_GEMM2_ROWS, r2)
+                _say("order P rows", r1, r2, prec, p.name)
+                maps[(r1, r2)] = _map(eels, p, prec, "probe_first")
+        finally:
+            eels.tune_set(eels.TUNE_GEMM1_ROWS, 1)
+            eels.tune_set(eels.TUNE_GEMM2_ROWS, 1)
+        assert np.array_equal(maps[(1, 1)], maps[(0, 1)])
+        assert np.max(np.abs(maps[(1, 1)] - maps[(1, 0)])) <= 1e-6 * np.max(maps[(1, 0)])
+        for m in maps.values():
+            assert metrics.rel_l2(m, ref) < 1e-3
+
+
 def test_interpolation_factor_case():
     eels = _need_gpu()
     p = synth.config3_subproblem(n=128, L=25.0, nz=5, n_scan=6, f=2)
