@@ -10,11 +10,21 @@
 // exchange writes elements 16 t + r from thread t; unpadded, all lanes of a wave would hit one
 // LDS bank, padded they spread over all banks.  The sequence then needs N + N / 16 slots.
 // DIR = -1: forward exp(-2 pi i n k / N); DIR = +1: unnormalised inverse.
+// WAVE: every sequence's T <= 64 threads lie in one wavefront (contiguous sequences of a
+// row pass), so the exchanges need only wave-level ordering: a wavefront's LDS operations
+// execute in program order, and the fences keep the compiler from moving LDS accesses
+// across the exchange.  Otherwise block barriers separate the stages.
 #pragma once
 
 #include "fft_lds.h"
 
 namespace eels {
+
+__device__ __forceinline__ void lds_sync_wave() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 template <int DIR>
 __device__ __forceinline__ void dft16(float2* v) {
@@ -60,9 +70,10 @@ struct RegRadix {
 };
 
 // stage with butterfly radix R on elements in registers (first stage) or LDS (later)
-template <int N, int E, int DIR, int Ns, bool PAD>
+template <int N, int E, int DIR, int Ns, bool PAD, bool WAVE>
 __device__ __forceinline__ void fft_reg_stages(float2 (&v)[E], float2* lds, int base, int es, int t,
                                                const float2* __restrict__ tw) {
+    static_assert(!WAVE || N / E <= 64, "wave-local exchange needs the sequence in one wavefront");
     auto at = [&](int i) -> float2& { return PAD ? lds[base + i + (i >> 4)] : lds[base + i * es]; };
     constexpr int T = N / E;
     constexpr int R = (Ns == 1) ? E : RegRadix<N, Ns, E>::R;
@@ -102,7 +113,9 @@ __device__ __forceinline__ void fft_reg_stages(float2 (&v)[E], float2* lds, int 
 #pragma unroll
             for (int r = 0; r < R; ++r) v[b + r * NB] = u[b][r];
     } else {
-        __syncthreads();  // earlier readers of lds are done
+        // earlier readers of lds are done
+        if constexpr (WAVE) lds_sync_wave();
+        else __syncthreads();
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             int j = t + b * T;
@@ -111,15 +124,16 @@ __device__ __forceinline__ void fft_reg_stages(float2 (&v)[E], float2* lds, int 
 #pragma unroll
             for (int r = 0; r < R; ++r) at(idxD + r * Ns) = u[b][r];
         }
-        __syncthreads();
-        fft_reg_stages<N, E, DIR, Ns * R, PAD>(v, lds, base, es, t, tw);
+        if constexpr (WAVE) lds_sync_wave();
+        else __syncthreads();
+        fft_reg_stages<N, E, DIR, Ns * R, PAD, WAVE>(v, lds, base, es, t, tw);
     }
 }
 
-template <int N, int DIR, bool PAD = false>
+template <int N, int DIR, bool PAD = false, bool WAVE = false>
 __device__ __forceinline__ void fft_reg(float2 (&v)[RegCfg<N>::E], float2* lds, int base, int es, int t,
                                         const float2* __restrict__ tw) {
-    fft_reg_stages<N, RegCfg<N>::E, DIR, 1, PAD>(v, lds, base, es, t, tw);
+    fft_reg_stages<N, RegCfg<N>::E, DIR, 1, PAD, WAVE>(v, lds, base, es, t, tw);
 }
 
 // LDS slots of one padded contiguous sequence

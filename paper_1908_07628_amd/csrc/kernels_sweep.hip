@@ -251,7 +251,7 @@ __device__ __forceinline__ void row_pass_body(float2* __restrict__ state, int nb
         const int64_t beam = valid ? g / ny : 0;
         if (grp + gridDim.x < ngroups) load(grp + gridDim.x);
         constexpr int S1 = MODE == 1 ? -1 : +1;   // first transform's sign (+1: inverse FFT_x)
-        fft_reg<N, S1, true>(v, lds, s * L, 1, t, tw);
+        fft_reg<N, S1, true, true>(v, lds, s * L, 1, t, tw);
 
         // In mode 2 the column pass's conj(P_j) / (nx ny) leaves this pass's input 1/nx of the
         // forward row pass's output (the state after the final FFT_x is exact), so the captured
@@ -264,10 +264,10 @@ __device__ __forceinline__ void row_pass_body(float2* __restrict__ state, int nb
         auto capture = [&]() {
             if constexpr (CAP) {
                 float2* crow = lds + s * L;
-                __builtin_amdgcn_wave_barrier();
+                lds_sync_wave();
 #pragma unroll
                 for (int m = 0; m < E; ++m) crow[t + T * m] = make_float2(v[m].x * cap_scale, v[m].y * cap_scale);
-                __builtin_amdgcn_wave_barrier();
+                lds_sync_wave();
                 if (valid) {
                     const int r0 = cap_ptr[y], r1 = cap_ptr[y + 1];
                     for (int r = r0; r < r1; ++r) {
@@ -280,7 +280,7 @@ __device__ __forceinline__ void row_pass_body(float2* __restrict__ state, int nb
                         }
                     }
                 }
-                __builtin_amdgcn_wave_barrier();
+                lds_sync_wave();
             }
         };
         if constexpr (MODE == 0) capture();
@@ -293,7 +293,7 @@ __device__ __forceinline__ void row_pass_body(float2* __restrict__ state, int nb
         }
         if constexpr (MODE != 0) capture();
 
-        fft_reg<N, -S1, true>(v, lds, s * L, 1, t, tw);
+        fft_reg<N, -S1, true, true>(v, lds, s * L, 1, t, tw);
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             int c = phys_col_of(t + T * m, N, hlx, ldx);
@@ -483,7 +483,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
                 for (int m = 0; m < E; ++m) h[m] = valid ? hr[t + T * m] : make_float2(0.f, 0.f);
             }
-            fft_reg<N, -1, true>(v, lds, s * L, 1, t, tw);
+            fft_reg<N, -1, true, true>(v, lds, s * L, 1, t, tw);
             const int64_t o = (((int64_t)tt * Ni + i) * ny + y) * ldx;
 #pragma unroll
             for (int m = 0; m < E; ++m) {
