@@ -227,7 +227,7 @@ void run_jobs(const Plan& p, const Dev& d, const float2* dH, const Batch& b, int
     TimeScope ts(EELS_PHASE_PRODUCER, st);
     for (int k = 0; k < b.job_count; ++k) {
         const Job& jb = p.jobs[b.job_begin + k];
-        const float2* W = (jb.from_mid ? d.mid : d.w1) + jb.w_off;
+        const float2* W = (jb.from_mid == 2 ? d.w2 : jb.from_mid ? d.mid : d.w1) + jb.w_off;
         if (p.recip) {
             BandFft a{};
             a.dst = d.mid2 + jb.dst_off;
@@ -315,9 +315,9 @@ void contract(const Plan& p, const Dev& d, const float2* dH, double* map, int bi
         }
         {
             TimeScope ts(EELS_PHASE_GEMM1, st);
-            if (split)
-                launch_cgemm_sc(p.precision, 3, nst, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.C, d.mid2, d.mid,
-                                nullptr, d.blob, st, b.d1_rows);
+            if (split)   // Psi in SC form when it is the shared operand of the second GEMM
+                launch_cgemm_sc(p.precision, p.hs2 ? 0 : 3, nst, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.C, d.mid2,
+                                d.mid, nullptr, d.blob, st, b.d1_rows);
             else
                 launch_cgemm(EELS_FP32, 1, 0, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.C, d.w1, nullptr, d.mid,
                              nullptr, d.blob, st);
@@ -325,7 +325,10 @@ void contract(const Plan& p, const Dev& d, const float2* dH, double* map, int bi
         if (split || p.recip) run_jobs(p, d, dH, b, b.slice, st);
         {
             TimeScope ts(EELS_PHASE_GEMM2, st);
-            if (split)
+            if (split && p.hs2)
+                launch_cgemm_sc(p.precision, 1, nst, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.mid2, d.mid, nullptr,
+                                d.part, d.blob, st, b.d2_rows);
+            else if (split)
                 launch_cgemm_sc(p.precision, 1, nst, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.w2, d.mid2, nullptr,
                                 d.part, d.blob, st, b.d2_rows);
             else

@@ -66,7 +66,7 @@ struct Batch {
 // Producer job: write the H-multiplied operand of one site into mid2, either in the band
 // basis (fft2 of T_j H_t W_i) or pixel-wise (H_t W_i), from S_1 windows or from Psi.
 struct Job {
-    int from_mid;       // 0: W = S_1 window buffer, 1: W = mid (Psi)
+    int from_mid;       // 0: W = S_1 window buffer, 1: W = mid (Psi), 2: W = the S_2 window buffer
     int64_t w_off;      // complex offset of the site's first W row
     int64_t win_off;    // complex offset of the site's S_1 window (order P, split: transposed first)
     int Ni, nt;
@@ -119,6 +119,8 @@ struct Plan {
     int Kb, Kbpad;                              // band pixels, padded stride
     int c_sc, w2_sc, mid2_sc;                   // storage formats (0 complex64, else split precision)
     bool gram;                                  // detector sum in the Gram form (order S, f = 1)
+    bool hs2 = false;                           // order P, split, cropped windows: H multiplies the S_2
+                                                // windows (N_2 rows) and Psi is the shared operand
     bool s1_inverse = false;                    // S_1 retreated with the inverse multislice
     int n_img = 0;                              // elastic companion images
     std::vector<double> img_in, img_out;        // their ring angles (rad; out < 0: band limit)

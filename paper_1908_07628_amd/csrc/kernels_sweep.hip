@@ -32,12 +32,7 @@ __device__ __forceinline__ uint32_t bf16_rne(float x) {
     u += 0x7FFFu + ((u >> 16) & 1u);
     return u >> 16;
 }
-__device__ __forceinline__ void store_c(void* base, int64_t off, float2 v, int sc) {
-    if (sc == 0) {
-        ((float2*)base)[off] = v;
-        return;
-    }
-    uint32_t hi, lo;
+__device__ __forceinline__ void split_c(float2 v, int sc, uint32_t& hi, uint32_t& lo) {
     if (sc == EELS_BF16_SPLIT) {
         uint32_t ha = bf16_rne(v.x), hb = bf16_rne(v.y);
         float ra = v.x - __uint_as_float(ha << 16), rb = v.y - __uint_as_float(hb << 16);
@@ -49,6 +44,14 @@ __device__ __forceinline__ void store_c(void* base, int64_t off, float2 v, int s
         hi = (uint32_t)__builtin_bit_cast(uint16_t, ha) | ((uint32_t)__builtin_bit_cast(uint16_t, hb) << 16);
         lo = (uint32_t)__builtin_bit_cast(uint16_t, la) | ((uint32_t)__builtin_bit_cast(uint16_t, lb) << 16);
     }
+}
+__device__ __forceinline__ void store_c(void* base, int64_t off, float2 v, int sc) {
+    if (sc == 0) {
+        ((float2*)base)[off] = v;
+        return;
+    }
+    uint32_t hi, lo;
+    split_c(v, sc, hi, lo);
     uint32_t* b = (uint32_t*)base;
     int64_t u = off >> 2;
     int pos = (int)(off & 3);
@@ -546,17 +549,36 @@ __global__ __launch_bounds__(ColCfg<N>::NT) __attribute__((amdgpu_waves_per_eu(2
 }
 
 // X[t][i][k] = H_t[k] * W_i[k] for k < K (zero for K <= k < ld), stored SC or complex64.
-__global__ void k_hmul(void* __restrict__ X, const float2* __restrict__ W, int64_t wstride,
-                       const float2* __restrict__ Hb, int64_t hstride, int Ni, int nt, int K, int ld, int sc) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t total = (int64_t)nt * Ni * ld;
-    if (i >= total) return;
-    int k = (int)(i % ld);
-    int64_t pi = i / ld;
-    int r = (int)(pi % Ni), t = (int)(pi / Ni);
-    float2 v = make_float2(0.f, 0.f);
-    if (k < K) v = cmul(Hb[t * hstride + k], W[r * wstride + k]);
-    store_c(X, i, v, sc);
+// X[(t Ni + r) ld + k] = H_t[k] W_r[k] for k < K, zero for K <= k < ld (ld a multiple of 4,
+// X 32-byte aligned).  A block covers 1024 slots of one output row, 4 per thread, stored as
+// whole 32-byte SC groups (or two complex64 pairs).
+__global__ __launch_bounds__(256) void k_hmul(void* __restrict__ X, const float2* __restrict__ W, int64_t wstride,
+                                              const float2* __restrict__ Hb, int64_t hstride, int Ni, int K, int ld,
+                                              int sc, int xblocks) {
+    const int64_t row = blockIdx.x / xblocks;
+    const int k0 = (int)(blockIdx.x % xblocks) * 1024 + 4 * threadIdx.x;
+    if (k0 >= ld) return;
+    const int t = (int)(row / Ni), r = (int)(row % Ni);
+    const float2* w = W + r * wstride;
+    const float2* h = Hb + t * hstride;
+    float2 v[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = k0 + e < K ? cmul(h[k0 + e], w[k0 + e]) : make_float2(0.f, 0.f);
+    const int64_t off = row * ld + k0;
+    if (sc == 0) {
+        float4* o = (float4*)((float2*)X + off);
+        o[0] = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
+        o[1] = make_float4(v[2].x, v[2].y, v[3].x, v[3].y);
+    } else {
+        uint4 hi, lo;
+        split_c(v[0], sc, hi.x, lo.x);
+        split_c(v[1], sc, hi.y, lo.y);
+        split_c(v[2], sc, hi.z, lo.z);
+        split_c(v[3], sc, hi.w, lo.w);
+        uint4* o = (uint4*)((uint32_t*)X + (off >> 2) * 8);
+        o[0] = hi;
+        o[1] = lo;
+    }
 }
 
 // --------------------------------------------------------------------- deterministic reduction
@@ -762,10 +784,11 @@ void launch_band_rows(float2* out, const float2* W, int64_t wstride, int Ni, int
 
 void launch_hmul(void* X, const float2* W, int64_t wstride, const float2* H, int64_t hstride, int Ni, int nt, int K,
                  int ld, int sc, hipStream_t st) {
-    int64_t n = (int64_t)nt * Ni * ld;
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_hmul, dim3(blocks_for(n, 256)), dim3(256), 0, st, X, W, wstride, H, hstride, Ni, nt, K, ld,
-                       sc);
+    const int64_t rows = (int64_t)nt * Ni;
+    if (rows <= 0 || ld <= 0) return;
+    const int xblocks = (int)ceil_div(ld, 1024);
+    hipLaunchKernelGGL(k_hmul, dim3((unsigned)(rows * xblocks)), dim3(256), 0, st, X, W, wstride, H, hstride, Ni, K, ld,
+                       sc, xblocks);
 }
 
 void launch_reduce(double* map, int P, const int* rptr, const int* ent, const GemmDesc* descs, const float* part,

@@ -274,7 +274,11 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     p.c_scale = p.precision == EELS_FP16_SPLIT ? 256.0f : 1.0f;
     const bool orderS = p.order == EELS_ORDER_S_FIRST;
     p.c_sc = (split && !p.gram) ? p.precision : 0;   // the Gram quadratic form reads complex64
-    p.w2_sc = split ? p.precision : 0;
+    // order P in split precision with cropped windows: A_n = (S_2w H_n) Psi, so the producer
+    // writes n_t x N_2 window rows instead of n_t x P_s probe rows (N_2 < P_s on large scans)
+    // and reads the S_2 windows captured in complex64
+    p.hs2 = split && !orderS && !p.recip;
+    p.w2_sc = (split && !p.hs2) ? p.precision : 0;
     p.mid2_sc = split ? p.precision : 0;
 
     // windows per slice
@@ -299,7 +303,7 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
         if (p.gram) return (int64_t)p.N1 * nt * p.N2p;     // Z rows [t k][q]
         return orderS ? (int64_t)nt * p.N2 * p.N1pad : (int64_t)n_elig(s) * p.Kpad;
     };
-    auto site_ni = [&](int s) -> int64_t { return orderS ? p.N1 : n_elig(s); };
+    auto site_ni = [&](int s) -> int64_t { return orderS ? p.N1 : (p.hs2 ? p.N2 : n_elig(s)); };
     auto site_mid2 = [&](int s) -> int64_t {
         if (!p.recip && !split) return 0;
         int64_t m2 = (int64_t)p.sites[s].n_trans * site_ni(s) * Kcpad;
@@ -524,8 +528,9 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
             for (size_t si = 0; si < pb.sites.size(); ++si) {
                 int s = pb.sites[si];
                 Job jb{};
-                jb.from_mid = orderS ? 0 : 1;
-                jb.w_off = orderS ? (int64_t)p.site_w1[s] * w1_stride : site_moff[si];
+                jb.from_mid = orderS ? 0 : (p.hs2 ? 2 : 1);
+                jb.w_off = orderS ? (int64_t)p.site_w1[s] * w1_stride
+                                  : (p.hs2 ? p.slice_w2[pb.slice] + (int64_t)p.site_w2[s] * w2_stride : site_moff[si]);
                 jb.win_off = (int64_t)p.site_w1[s] * w1_stride;
                 jb.Ni = (int)site_ni(s);
                 jb.nt = p.sites[s].n_trans;
@@ -637,6 +642,14 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
                 d.h_off = -1; d.ldh = 0;
                 d.M = p.N2; d.N_inner = Ps; d.n_t = st.n_trans; d.K = p.N1;
                 d.idx_off = (int)site_idx[s];
+            } else if (p.hs2) {
+                // A_n(q, R) = sum_r (H_t S2w)[q][r] Psi_s[i][r]: the producer's H_t S_2w rows
+                // (one block per transition), Psi shared by the transitions
+                d.a_off = site_m2off[si]; d.lda = p.Kpad; d.a_tstride = (int64_t)p.N2 * p.Kpad;
+                d.b_off = site_moff[si]; d.ldb = p.Kpad; d.b_tstride = 0;
+                d.h_off = -1; d.ldh = 0;
+                d.M = p.N2; d.N_inner = Ps; d.n_t = st.n_trans; d.K = p.K;
+                d.idx_off = -1;
             } else {
                 // A_n(q, R) = sum_r S2w[q][r] H_t[r] Psi_s[i][r]  (or its band-basis form)
                 if (p.recip) { d.a_off = p.slice_w2[pb.slice]; d.lda = p.Kbpad; }

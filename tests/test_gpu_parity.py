@@ -281,18 +281,21 @@ def test_order_p_split_tile_rows(prec):
     windows and gathers the eligible probes' rows of C).  256- and 128-row tiles of the first
     GEMM accumulate every element in the same order (bitwise-equal maps); 256- and 128-row
     tiles of the second GEMM group the FP32 partial sums differently (equal to 1e-6).  Both
-    meet the split bar against the oracle.  Config 1 forced to order P, and the f = 2 cell
-    with crop windows."""
+    meet the split bar against the oracle.  Config 1 forced to order P in the band basis and
+    in real space (where H multiplies the S_2 windows and Psi is the shared operand), and the
+    f = 2 cell with crop windows (the same real-space form)."""
     eels = _need_gpu()
-    for p in (synth.config1(), synth.config3_subproblem(n=128, L=25.0, nz=5, n_scan=6, f=2)):
+    c1 = synth.config1()
+    for p, kw in ((c1, {}), (c1, dict(real_space=True)),
+                  (synth.config3_subproblem(n=128, L=25.0, nz=5, n_scan=6, f=2), {})):
         ref = prism.prism_map(p)
         maps = {}
         try:
             for r1, r2 in ((1, 1), (0, 1), (1, 0)):
                 eels.tune_set(eels.TUNE_GEMM1_ROWS, r1)
                 eels.tune_set(eels.TUNE_GEMM2_ROWS, r2)
-                _say("order P rows", r1, r2, prec, p.name)
-                maps[(r1, r2)] = _map(eels, p, prec, "probe_first")
+                _say("order P rows", r1, r2, prec, p.name, kw)
+                maps[(r1, r2)] = _map(eels, p, prec, "probe_first", **kw)
         finally:
             eels.tune_set(eels.TUNE_GEMM1_ROWS, 1)
             eels.tune_set(eels.TUNE_GEMM2_ROWS, 1)
