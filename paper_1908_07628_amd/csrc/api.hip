@@ -140,12 +140,13 @@ eels_status setup(const Plan& p, const Dev& d, const float* dV, hipStream_t st, 
     launch_twiddles(d.twx, p.nx, st);
     launch_twiddles(d.twy, p.ny, st);
     launch_transmission(d.T, dV, (int64_t)p.nz * p.ny * p.nx, p.sigma, st);
-    launch_propagator(d.P, d.dz, d.band_h, p, st);
+    launch_propagator(d.P, d.dz, p, st);
     return EELS_OK;
 }
 
 const float2* Tj(const Plan& p, const Dev& d, int j) { return d.T + (int64_t)j * p.ny * p.nx; }
-const float2* Pj(const Plan& p, const Dev& d, int j) { return d.P + (int64_t)j * p.ny * p.nlx; }
+// slice j's propagator factor tables (nlx column factors, then ny row factors)
+const float2* Pj(const Plan& p, const Dev& d, int j) { return d.P + (int64_t)j * (p.nlx + p.ny); }
 
 // Forward sweep of S_1 through slices 0..j_end (row pass of j_end included, its column
 // pass not).  Captures the windows of the ionised slices of `group` (if >= 0), or the
@@ -169,9 +170,9 @@ void forward_sweep(const Plan& p, const Dev& d, int j_end, int group, int dbg_sl
             a.cap_rec = d.blob + p.slices[j].cap1_rec;
         }
         launch_row_pass(p.nx, 0, a, st);
-        if (j < j_end) launch_col_pass(p.ny, 0, d.s1, p.N1, p.nlx, p.ldx, Pj(p, d, j), d.twy, BandCap{}, st);
+        if (j < j_end) launch_col_pass(p.ny, 0, d.s1, p.N1, p.nlx, p.ldx, Pj(p, d, j), d.twy, d.band_h, BandCap{}, st);
         else if (exit_cap || last_col)
-            launch_col_pass(p.ny, 0, d.s1, p.N1, p.nlx, p.ldx, Pj(p, d, j), d.twy,
+            launch_col_pass(p.ny, 0, d.s1, p.N1, p.nlx, p.ldx, Pj(p, d, j), d.twy, d.band_h,
                             exit_cap ? BandCap{d.band_h, d.band_off, exit_cap, p.Kbpad, 0} : BandCap{}, st);
     }
 }
@@ -181,7 +182,7 @@ void forward_sweep(const Plan& p, const Dev& d, int j_end, int group, int dbg_sl
 // slice j's sites when `capture`.
 void inverse_step(const Plan& p, const Dev& d, int j, bool capture, hipStream_t st) {
     TimeScope ts(EELS_PHASE_SWEEP, st);
-    launch_col_pass(p.ny, 2, d.s1, p.N1, p.nlx, p.ldx, Pj(p, d, j), d.twy, BandCap{}, st);
+    launch_col_pass(p.ny, 2, d.s1, p.N1, p.nlx, p.ldx, Pj(p, d, j), d.twy, d.band_h, BandCap{}, st);
     RowPassArgs a{d.s1, p.N1, p.ny, p.nlx, p.hlx, Tj(p, d, j), d.twx, nullptr, nullptr, d.w1, p.N1, p.Kpad, 0,
                   p.ldx};
     if (capture) {
@@ -205,7 +206,7 @@ void reverse_step(const Plan& p, const Dev& d, int j, bool capture, float2* dbg_
     } else {
         BandCap bc{};
         if (band) bc = BandCap{d.band_h, d.band_off, w2j, p.Kbpad, p.w2_sc};
-        launch_col_pass(p.ny, 1, d.s2, p.N2, p.nlx, p.ldx, Pj(p, d, j), d.twy, bc, st);
+        launch_col_pass(p.ny, 1, d.s2, p.N2, p.nlx, p.ldx, Pj(p, d, j), d.twy, d.band_h, bc, st);
     }
     RowPassArgs a{d.s2, p.N2, p.ny, p.nlx, p.hlx, Tj(p, d, j), d.twx, nullptr, nullptr, w2j, p.N2, p.Kpad, p.w2_sc,
                   p.ldx};
@@ -388,7 +389,7 @@ ConvLayout conv_layout(const Plan& p, int chunk) {
     L.twx = take(c8 * p.nx);
     L.twy = take(c8 * p.ny);
     L.T = take(c8 * (size_t)p.nz * p.ny * p.nx);
-    L.P = take(c8 * (size_t)p.nz * p.ny * p.nlx);
+    L.P = take(c8 * (size_t)p.nz * (p.nlx + p.ny));
     L.Hfull = take(p.full_window ? 16 : c8 * (size_t)p.n_trans_all * p.ny * p.nx);
     L.psi = take(c8 * (size_t)chunk * p.ny * p.nx);
     L.waves = take(c8 * ((size_t)chunk + n_inel) * plane);
@@ -711,12 +712,12 @@ eels_status eels_conventional_map(const eels_plan* pl, const float* d_V, const v
             TimeScope ts(EELS_PHASE_SWEEP, st);
             if (j == p.nz - 1) {
                 if (n_inel > 0)
-                    launch_col_pass(p.ny, 0, inel, (int)n_inel, p.nlx, p.ldx, Pj(p, d, j), d.twy,
+                    launch_col_pass(p.ny, 0, inel, (int)n_inel, p.nlx, p.ldx, Pj(p, d, j), d.twy, d.band_h,
                                     BandCap{d.band_h, d.band_off, exit_band, p.Kbpad, 0}, st);
             } else if (j < j_last) {
-                launch_col_pass(p.ny, 0, waves, (int)(Ni + n_inel), p.nlx, p.ldx, Pj(p, d, j), d.twy, BandCap{}, st);
+                launch_col_pass(p.ny, 0, waves, (int)(Ni + n_inel), p.nlx, p.ldx, Pj(p, d, j), d.twy, d.band_h, BandCap{}, st);
             } else if (n_inel > 0) {
-                launch_col_pass(p.ny, 0, inel, (int)n_inel, p.nlx, p.ldx, Pj(p, d, j), d.twy, BandCap{}, st);
+                launch_col_pass(p.ny, 0, inel, (int)n_inel, p.nlx, p.ldx, Pj(p, d, j), d.twy, d.band_h, BandCap{}, st);
             }
         }
         TimeScope ts(EELS_PHASE_REDUCE, st);

@@ -53,7 +53,8 @@ struct BandFft {
 
 void launch_twiddles(float2* tw, int n, hipStream_t st);
 void launch_transmission(float2* T, const float* V, int64_t n, double sigma, hipStream_t st);
-void launch_propagator(float2* P, const double* dz, const int* band_h, const Plan& p, hipStream_t st);
+// Propagator factor tables, slice j at P + j (nlx + ny): column factors then row factors.
+void launch_propagator(float2* P, const double* dz, const Plan& p, hipStream_t st);
 void launch_probe_coefficients(void* C, const int4* beams, const double* probes, const Plan& p, int sc,
                                hipStream_t st);
 void launch_init_band(void* bcap, int64_t bstride, const int4* beams, const int* band_h, const int* band_off,
@@ -71,8 +72,9 @@ void launch_fill_zero(void* ptr, size_t bytes, hipStream_t st);
 void launch_fill_zero_d(double* p, int64_t n, hipStream_t st);
 void launch_copy(float2* dst, const float2* src, int64_t n, hipStream_t st);
 void launch_row_pass(int nx, int mode, const RowPassArgs& a, hipStream_t st);
+// Column pass of slice j: Pj = slice j's propagator tables, band_h = band rows per live column.
 void launch_col_pass(int ny, int mode, float2* state, int nbeam, int nlx, int ldx, const float2* Pj, const float2* tw,
-                     const BandCap& bc, hipStream_t st);
+                     const int* band_h, const BandCap& bc, hipStream_t st);
 void launch_reduce(double* map, int P, const int* rptr, const int* ent, const GemmDesc* descs, const float* part,
                    double scale, hipStream_t st);
 void launch_reduce_dense(double* map, int P, const GemmDesc* descs, int d_begin, int d_count, const float* part,

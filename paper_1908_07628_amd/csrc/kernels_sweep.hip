@@ -88,26 +88,27 @@ __device__ __forceinline__ int live_to_kx_signed(int c, int nlx, int hlx, int nx
 // P~_j(kx, ky) = B(k) exp(-i pi lambda dz_j |k|^2) / (nx ny) on the live columns; the band
 // B is |ky index| <= band_h[c] for live column c (the host's table, shared with the band
 // captures so that every kernel agrees on the band pixel set)
-__global__ void k_propagator(float2* P, const double* dz, int nz, int nx, int ny, int nlx, int hlx,
-                             double lx, double ly, double lam, const int* __restrict__ band_h) {
+// Separable propagator of slice j (Eq. MSop with the band limit): P_j(kx, ky) = px_j[c] py_j[y]
+// inside the band (|signed y| <= band_h[c]), 0 outside, with px_j[c] = exp(-i pi lam dz kx^2) /
+// (nx ny) on the live columns and py_j[y] = exp(-i pi lam dz ky^2).  Slice j's tables sit at
+// P + j (nlx + ny): nlx column factors, then ny row factors (phases in double).
+__global__ void k_propagator(float2* P, const double* dz, int nz, int nx, int ny, int nlx, int hlx, double lx,
+                             double ly, double lam) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t total = (int64_t)nz * ny * nlx;
-    if (i >= total) return;
-    int c = (int)(i % nlx);
-    int y = (int)((i / nlx) % ny);
-    int j = (int)(i / ((int64_t)nlx * ny));
-    double kx = live_to_kx_signed(c, nlx, hlx, nx) / lx;
-    double ky = signed_index(y, ny) / ly;
-    double k2 = kx * kx + ky * ky;
-    float2 out = make_float2(0.f, 0.f);
-    int ys = signed_index(y, ny);
-    if (ys <= band_h[c] && -ys <= band_h[c]) {
-        double s, co;
-        sincospi(-lam * dz[j] * k2, &s, &co);
-        double sc = 1.0 / ((double)nx * (double)ny);
-        out = make_float2((float)(co * sc), (float)(s * sc));
+    const int per = nlx + ny;
+    if (i >= (int64_t)nz * per) return;
+    const int j = (int)(i / per), r = (int)(i % per);
+    double k, sc;
+    if (r < nlx) {
+        k = live_to_kx_signed(r, nlx, hlx, nx) / lx;
+        sc = 1.0 / ((double)nx * (double)ny);
+    } else {
+        k = signed_index(r - nlx, ny) / ly;
+        sc = 1.0;
     }
-    P[i] = out;
+    double s, co;
+    sincospi(-lam * dz[j] * k * k, &s, &co);
+    P[i] = make_float2((float)(co * sc), (float)(s * sc));
 }
 
 // c_k(R) = s exp(-i chi(k)) exp(-2 pi i k.R), stored [P][N1pad] (zero padding columns).
@@ -350,8 +351,12 @@ __device__ __forceinline__ void col_pass_body(float2* __restrict__ state, int nb
     const int strips = (ldx + CW - 1) / CW;
     const int64_t items = (int64_t)nbeam * strips;
     const int col = tid % CW, t = tid / CW;
-    // items (beam, strip) walked with stride gridDim.x; the next item's strip is loaded
-    // while the current one is transformed
+    // Items (beam, strip), it = beam * strips + strip, are walked in chunks of gridDim.x; the
+    // next chunk's strip is loaded while the current one is transformed.  Within a chunk the
+    // 8 XCDs (block b runs on XCD b % 8) each take one contiguous range of items, so the
+    // neighbouring strips that share 128-byte lines of a beam's rows run on one L2.
+    const int G = gridDim.x, b = blockIdx.x;
+    const int64_t slot = (G % 8 == 0) ? (int64_t)(b % 8) * (G / 8) + b / 8 : b;
     float2 nxt[E];
     auto load = [&](int64_t it) {
         const int64_t beam = it / strips;
@@ -361,8 +366,11 @@ __device__ __forceinline__ void col_pass_body(float2* __restrict__ state, int nb
 #pragma unroll
         for (int m = 0; m < E; ++m) nxt[m] = live ? plane[(int64_t)(t + T * m) * ldx + pc] : make_float2(0.f, 0.f);
     };
-    if ((int64_t)blockIdx.x < items) load(blockIdx.x);
-    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const float2* __restrict__ px = Pj;         // column factors of the propagator
+    const float2* __restrict__ py = Pj + nlx;   // row factors
+    if (slot < items) load(slot);
+    for (int64_t base = 0; base + slot < items; base += G) {
+        const int64_t it = base + slot;
         float2 v[E];
 #pragma unroll
         for (int m = 0; m < E; ++m) v[m] = nxt[m];
@@ -370,13 +378,16 @@ __device__ __forceinline__ void col_pass_body(float2* __restrict__ state, int nb
         const int pc = (int)(it % strips) * CW + col;  // physical column (state)
         const int c = logical_of_phys(pc, nlx, ldx);   // live column (P, band tables)
         const bool live = c >= 0;
+        const int h = live ? band_h[c] : -1;
+        const float2 pxc = live ? px[c] : make_float2(0.f, 0.f);
         float2* plane = state + beam * (int64_t)N * ldx;
-        if (it + gridDim.x < items) load(it + gridDim.x);
+        if (it + G < items) load(it + G);
         constexpr int S1 = MODE == 1 ? +1 : -1;   // first transform's sign (-1: FFT_y)
         fft_reg<N, S1>(v, lds, col, CW, t, tw);
 #pragma unroll
         for (int m = 0; m < E; ++m) {
-            float2 pv = live ? Pj[(int64_t)(t + T * m) * nlx + c] : make_float2(0.f, 0.f);
+            const int ys = signed_index(t + T * m, N);
+            float2 pv = (ys <= h && -ys <= h) ? cmul(pxc, py[t + T * m]) : make_float2(0.f, 0.f);
             if constexpr (MODE == 2) pv.y = -pv.y;   // inverse multislice: conj(P)
             v[m] = cmul(v[m], pv);
         }
@@ -402,9 +413,9 @@ __device__ __forceinline__ void col_pass_body(float2* __restrict__ state, int nb
 template <int N, int MODE>
 __global__ __launch_bounds__(ColCfg<N>::NT) __attribute__((amdgpu_waves_per_eu(2))) void k_col_pass(
     float2* __restrict__ state, int nbeam, int nlx, int ldx, const float2* __restrict__ Pj,
-    const float2* __restrict__ tw) {
+    const float2* __restrict__ tw, const int* __restrict__ band_h) {
     __shared__ float2 lds[N * ColCfg<N>::CW];
-    col_pass_body<N, MODE, false>(state, nbeam, nlx, ldx, Pj, tw, nullptr, nullptr, nullptr, 0, 0, lds);
+    col_pass_body<N, MODE, false>(state, nbeam, nlx, ldx, Pj, tw, band_h, nullptr, nullptr, 0, 0, lds);
 }
 
 template <int N, int MODE>
@@ -625,10 +636,10 @@ void launch_twiddles(float2* tw, int n, hipStream_t st) {
 void launch_transmission(float2* T, const float* V, int64_t n, double sigma, hipStream_t st) {
     hipLaunchKernelGGL(k_transmission, dim3(blocks_for(n, 256)), dim3(256), 0, st, T, V, n, sigma);
 }
-void launch_propagator(float2* P, const double* dz, const int* band_h, const Plan& p, hipStream_t st) {
-    int64_t n = (int64_t)p.nz * p.ny * p.nlx;
+void launch_propagator(float2* P, const double* dz, const Plan& p, hipStream_t st) {
+    int64_t n = (int64_t)p.nz * (p.nlx + p.ny);
     hipLaunchKernelGGL(k_propagator, dim3(blocks_for(n, 256)), dim3(256), 0, st, P, dz, p.nz, p.nx, p.ny, p.nlx, p.hlx,
-                       p.lx, p.ly, p.lam, band_h);
+                       p.lx, p.ly, p.lam);
 }
 void launch_probe_coefficients(void* C, const int4* beams, const double* probes, const Plan& p, int sc,
                                hipStream_t st) {
@@ -692,26 +703,26 @@ void launch_row_pass(int nx, int mode, const RowPassArgs& a, hipStream_t st) {
 }
 
 template <int N, int MODE>
-static void col_pass_n(float2* state, int nbeam, int nlx, int ldx, const float2* Pj, const float2* tw, const BandCap& bc,
-                       hipStream_t st) {
+static void col_pass_n(float2* state, int nbeam, int nlx, int ldx, const float2* Pj, const float2* tw,
+                       const int* band_h, const BandCap& bc, hipStream_t st) {
     using C = ColCfg<N>;
     int strips = (ldx + C::CW - 1) / C::CW;
     if (nbeam <= 0) return;
     const dim3 grid(strided_grid((int64_t)nbeam * strips));
     if (bc.dst)
         hipLaunchKernelGGL((k_col_pass_cap<N, MODE>), grid, dim3(C::NT), 0, st, state, nbeam, nlx, ldx, Pj, tw,
-                           bc.band_h, bc.band_off, bc.dst, bc.stride, bc.sc);
+                           band_h, bc.band_off, bc.dst, bc.stride, bc.sc);
     else
-        hipLaunchKernelGGL((k_col_pass<N, MODE>), grid, dim3(C::NT), 0, st, state, nbeam, nlx, ldx, Pj, tw);
+        hipLaunchKernelGGL((k_col_pass<N, MODE>), grid, dim3(C::NT), 0, st, state, nbeam, nlx, ldx, Pj, tw, band_h);
 }
 
 void launch_col_pass(int ny, int mode, float2* state, int nbeam, int nlx, int ldx, const float2* Pj, const float2* tw,
-                     const BandCap& bc, hipStream_t st) {
+                     const int* band_h, const BandCap& bc, hipStream_t st) {
 #define COLCASE(NN)                                                   \
     case NN:                                                          \
-        if (mode == 0) col_pass_n<NN, 0>(state, nbeam, nlx, ldx, Pj, tw, bc, st); \
-        else if (mode == 1) col_pass_n<NN, 1>(state, nbeam, nlx, ldx, Pj, tw, bc, st); \
-        else col_pass_n<NN, 2>(state, nbeam, nlx, ldx, Pj, tw, bc, st);    \
+        if (mode == 0) col_pass_n<NN, 0>(state, nbeam, nlx, ldx, Pj, tw, band_h, bc, st); \
+        else if (mode == 1) col_pass_n<NN, 1>(state, nbeam, nlx, ldx, Pj, tw, band_h, bc, st); \
+        else col_pass_n<NN, 2>(state, nbeam, nlx, ldx, Pj, tw, band_h, bc, st);    \
         break;
     switch (ny) {
         COLCASE(16) COLCASE(32) COLCASE(64) COLCASE(128) COLCASE(256) COLCASE(512) COLCASE(1024)

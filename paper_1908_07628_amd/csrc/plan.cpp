@@ -329,7 +329,7 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     const size_t c8 = 8;  // bytes per complex64
     size_t fixed = A(blob_reserve)  // table blob (refined by the caller's second pass)
                    + A(c8 * p.nx) + A(c8 * p.ny) + A(c8 * (size_t)p.nz * p.ny * p.nx) +
-                   A(c8 * (size_t)p.nz * p.ny * p.nlx) + A(c8 * (size_t)p.P * p.N1pad) +
+                   A(c8 * (size_t)p.nz * (p.nlx + p.ny)) + A(c8 * (size_t)p.P * p.N1pad) +
                    A(c8 * (size_t)p.N1 * p.ny * p.ldx) + A(c8 * (size_t)p.N2 * p.ny * p.ldx) +
                    A(c8 * (size_t)w2_elems) + A(c8 * (size_t)scratch) +
                    (p.gram ? A(16 * (size_t)p.N1 * p.N1) + A(8 * (size_t)p.P * ceil_div(p.N1, 64)) : 0) +
@@ -789,7 +789,7 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     p.off_twx = take(c8 * p.nx);
     p.off_twy = take(c8 * p.ny);
     p.off_T = take(c8 * (size_t)p.nz * p.ny * p.nx);
-    p.off_P = take(c8 * (size_t)p.nz * p.ny * p.nlx);
+    p.off_P = take(c8 * (size_t)p.nz * (p.nlx + p.ny));   // separable propagator tables
     p.off_s1 = take(c8 * (size_t)p.N1 * p.ny * p.ldx);
     p.off_s2 = take(c8 * (size_t)p.N2 * p.ny * p.ldx);
     p.off_w1 = take(c8 * (size_t)std::max(p.max_w1, 1) * p.N1 * p.Kpad);
