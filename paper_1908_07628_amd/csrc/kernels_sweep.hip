@@ -561,34 +561,39 @@ __global__ __launch_bounds__(ColCfg<N>::NT) __attribute__((amdgpu_waves_per_eu(2
 
 // X[t][i][k] = H_t[k] * W_i[k] for k < K (zero for K <= k < ld), stored SC or complex64.
 // X[(t Ni + r) ld + k] = H_t[k] W_r[k] for k < K, zero for K <= k < ld (ld a multiple of 4,
-// X 32-byte aligned).  A block covers 1024 slots of one output row, 4 per thread, stored as
-// whole 32-byte SC groups (or two complex64 pairs).
+// X 32-byte aligned).  A block covers 1024 slots of one row r, 4 per thread: W_r is read
+// once and the thread writes the nt transitions' products (H stays in cache), as whole
+// 32-byte SC groups (or two complex64 pairs).
 __global__ __launch_bounds__(256) void k_hmul(void* __restrict__ X, const float2* __restrict__ W, int64_t wstride,
-                                              const float2* __restrict__ Hb, int64_t hstride, int Ni, int K, int ld,
-                                              int sc, int xblocks) {
-    const int64_t row = blockIdx.x / xblocks;
+                                              const float2* __restrict__ Hb, int64_t hstride, int Ni, int nt, int K,
+                                              int ld, int sc, int xblocks) {
+    const int r = (int)(blockIdx.x / xblocks);
     const int k0 = (int)(blockIdx.x % xblocks) * 1024 + 4 * threadIdx.x;
     if (k0 >= ld) return;
-    const int t = (int)(row / Ni), r = (int)(row % Ni);
     const float2* w = W + r * wstride;
-    const float2* h = Hb + t * hstride;
-    float2 v[4];
+    float2 wv[4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) v[e] = k0 + e < K ? cmul(h[k0 + e], w[k0 + e]) : make_float2(0.f, 0.f);
-    const int64_t off = row * ld + k0;
-    if (sc == 0) {
-        float4* o = (float4*)((float2*)X + off);
-        o[0] = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
-        o[1] = make_float4(v[2].x, v[2].y, v[3].x, v[3].y);
-    } else {
-        uint4 hi, lo;
-        split_c(v[0], sc, hi.x, lo.x);
-        split_c(v[1], sc, hi.y, lo.y);
-        split_c(v[2], sc, hi.z, lo.z);
-        split_c(v[3], sc, hi.w, lo.w);
-        uint4* o = (uint4*)((uint32_t*)X + (off >> 2) * 8);
-        o[0] = hi;
-        o[1] = lo;
+    for (int e = 0; e < 4; ++e) wv[e] = k0 + e < K ? w[k0 + e] : make_float2(0.f, 0.f);
+    for (int t = 0; t < nt; ++t) {
+        const float2* h = Hb + t * hstride;
+        float2 v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = k0 + e < K ? cmul(h[k0 + e], wv[e]) : make_float2(0.f, 0.f);
+        const int64_t off = ((int64_t)t * Ni + r) * ld + k0;
+        if (sc == 0) {
+            float4* o = (float4*)((float2*)X + off);
+            o[0] = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
+            o[1] = make_float4(v[2].x, v[2].y, v[3].x, v[3].y);
+        } else {
+            uint4 hi, lo;
+            split_c(v[0], sc, hi.x, lo.x);
+            split_c(v[1], sc, hi.y, lo.y);
+            split_c(v[2], sc, hi.z, lo.z);
+            split_c(v[3], sc, hi.w, lo.w);
+            uint4* o = (uint4*)((uint32_t*)X + (off >> 2) * 8);
+            o[0] = hi;
+            o[1] = lo;
+        }
     }
 }
 
@@ -795,11 +800,10 @@ void launch_band_rows(float2* out, const float2* W, int64_t wstride, int Ni, int
 
 void launch_hmul(void* X, const float2* W, int64_t wstride, const float2* H, int64_t hstride, int Ni, int nt, int K,
                  int ld, int sc, hipStream_t st) {
-    const int64_t rows = (int64_t)nt * Ni;
-    if (rows <= 0 || ld <= 0) return;
+    if ((int64_t)nt * Ni <= 0 || ld <= 0) return;
     const int xblocks = (int)ceil_div(ld, 1024);
-    hipLaunchKernelGGL(k_hmul, dim3((unsigned)(rows * xblocks)), dim3(256), 0, st, X, W, wstride, H, hstride, Ni, K, ld,
-                       sc, xblocks);
+    hipLaunchKernelGGL(k_hmul, dim3((unsigned)((int64_t)Ni * xblocks)), dim3(256), 0, st, X, W, wstride, H, hstride, Ni,
+                       nt, K, ld, sc, xblocks);
 }
 
 void launch_reduce(double* map, int P, const int* rptr, const int* ent, const GemmDesc* descs, const float* part,
