@@ -83,7 +83,8 @@ def cpu_baseline(p, budget_s=25.0):
 def profile_sample(args):
     """Workload for hardware-counter runs: a plain 1 GiB device-to-device copy (known bytes,
     to calibrate FETCH_SIZE / WRITE_SIZE) and one map on the sites of the top N ionised
-    slices of the crystal workload, whose contraction launches have the full map's shapes."""
+    slices of the crystal workload, whose contraction launches have the full map's shapes
+    (nanoparticle workload: the sites of its N most populated ionised slices)."""
     import torch
     import synth
     from paper_1908_07628_amd import eels
@@ -91,11 +92,20 @@ def profile_sample(args):
     b = torch.empty_like(a)
     b.copy_(a)
     torch.cuda.synchronize()
-    p = synth.config2()
-    ion = sorted(set(p.site_slice.tolist()))
-    q = subset_sites(p, np.nonzero(np.isin(p.site_slice, ion[-args.profile_sample:]))[0])
+    budget = 0
+    if args.workload == "nanoparticle":
+        p = synth.config3()
+        counts = np.bincount(p.site_slice, minlength=p.n_slices)
+        top = np.argsort(-counts, kind="stable")[:args.profile_sample]
+        q = subset_sites(p, np.nonzero(np.isin(p.site_slice, top))[0])
+        free, _ = torch.cuda.mem_get_info()
+        budget = int(free - (12 << 30))
+    else:
+        p = synth.config2()
+        ion = sorted(set(p.site_slice.tolist()))
+        q = subset_sites(p, np.nonzero(np.isin(p.site_slice, ion[-args.profile_sample:]))[0])
     V, H = eels.device_inputs(q)
-    plan = eels.Plan(q, precision=args.precision)
+    plan = eels.Plan(q, precision=args.precision, max_workspace_bytes=budget)
     ws = plan.alloc_workspace()
     out = torch.empty(q.n_probes, dtype=torch.float64, device="cuda")
     plan.execute(V, H, out, ws)
@@ -116,10 +126,10 @@ def sources_digest():
     return h.hexdigest()
 
 
-def counter_values():
-    """Calibrated HBM bytes per launch from the committed counter summary, if it was taken with
-    the current kernel and planner sources (else an empty dict)."""
-    summ = os.path.join(ROOT, "profiles", "k_cgemm_sc__config2_traffic_pmc.md")
+def counter_values(name="k_cgemm_sc__config2_traffic_pmc.md"):
+    """Calibrated HBM bytes from a committed counter summary under profiles/, if it was taken
+    with the current kernel and planner sources (else an empty dict)."""
+    summ = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(summ):
         return {}
     vals = {}
@@ -191,8 +201,7 @@ def bench_serve(args):
     """Serving workload: Poisson arrivals, continuous batching, residency, p50/p99."""
     import torch
     import synth
-    from paper_1908_07628_amd import eels
-    from paper_1908_07628_amd.serve import Server, specimen_key
+    from paper_1908_07628_amd.serve import specimen_key
     t0 = time.time()
     pool = synth.specimen_pool(55, args.pool, (128, 256, 512, 1024), (10, 60), (1, 20), (16, 64), "req",
                                workers=min(16, os.cpu_count() or 1))
@@ -205,9 +214,26 @@ def bench_serve(args):
                                    f"{len(pool)} specimens (grids 128^2-1024^2, 10-60 slices), 30% repeats of "
                                    "(specimen, sites) with shifted probes; 4 slots"),
                       "budget_GB": round(0.8 * free / 1e9, 1)}, "rates": {}}
+    precisions = args.serve_precisions or [args.precision]
+    out["by_precision"] = {}
+    for prec in precisions:
+        out["rates"] = {}
+        serve_rates(args, pool, keys, free, prec, out)
+        out["by_precision"][prec] = out["rates"]
+    out["rates"] = out["by_precision"][precisions[0]]
+    out["dtype"] = precisions[0]
+    best = max(out["rates"].values(), key=lambda r: r["throughput_probe_px_s"])
+    out["value"] = best["throughput_probe_px_s"]
+    return out
+
+
+def serve_rates(args, pool, keys, free, precision, out):
+    """One Poisson stream per rate through a fresh server in the given precision."""
+    import synth
+    from paper_1908_07628_amd.serve import Server
     for rate in args.rates:
         reqs = synth.config5_stream(seed=5, rate_per_s=rate, n_requests=args.n_requests, pool=pool)
-        srv = Server(int(0.8 * free), max_slots=4, precision=args.precision, residency=True)
+        srv = Server(int(0.8 * free), max_slots=4, precision=precision, residency=True)
         t0 = time.perf_counter()
         tickets = []
         for (t_arr, k, shift) in reqs:
@@ -226,10 +252,7 @@ def bench_serve(args):
                                    "requests": st["n"], "errors": sum(r.error is not None for r in res),
                                    "throughput_probe_px_s": round(probes / wall, 1),
                                    "maps_per_s": round(len(reqs) / wall, 3)}
-        log(f"rate {rate}: {out['rates'][str(rate)]}")
-    best = max(out["rates"].values(), key=lambda r: r["throughput_probe_px_s"])
-    out["value"] = best["throughput_probe_px_s"]
-    return out
+        log(f"{precision} rate {rate}: {out['rates'][str(rate)]}")
 
 
 NANO_WORKLOAD = ("nanoparticle 1024x1024 px over 100x100 A, 50 slices x 2 A: 80 A bcc sphere (22,659 atoms, "
@@ -362,11 +385,16 @@ def bench_nanoparticle(args):
     per_launch = g2_flops / n_launch
     achieved = exec_factor * per_launch / (avg_ms * 1e-3) / 1e12
     peak = PEAK_BF16_TFLOPS if split else PEAK_FP32_TFLOPS
+    # counter bytes per site of this kernel (profiling sample: the most populated slice, same
+    # per-site shapes) times the full map's sites per launch
+    cv = counter_values("k_cgemm_sc__nanoparticle_traffic_pmc.md") if split else {}
+    traffic = (cv["gemm2_traffic_bytes_per_site"] * p.n_sites / n_launch
+               if "gemm2_traffic_bytes_per_site" in cv else None)
     roofline = {
         "bound": "mfma", "kernel": ("k_cgemm_sc, norm epilogue (second contraction GEMM)" if split
                                     else "k_cgemm, norm epilogue"),
         "achieved": round(achieved, 1), "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-        "traffic": None, "avg_launch_ms": round(avg_ms, 3), "launches_per_step": n_launch,
+        "traffic": traffic, "avg_launch_ms": round(avg_ms, 3), "launches_per_step": n_launch,
         "algorithmic_flops_per_launch": exec_factor * per_launch,
         "useful_complex_tflops": round(per_launch / (avg_ms * 1e-3) / 1e12, 1),
         "flop_definition": ("3 BF16 MFMA products per complex multiply-add of the split algorithm, 8 real flops "
@@ -462,11 +490,16 @@ def main():
     ap.add_argument("--pool", type=int, default=10)
     ap.add_argument("--n-requests", type=int, default=40)
     ap.add_argument("--rates", type=float, nargs="+", default=[1.0, 4.0])
+    ap.add_argument("--serve-precisions", nargs="+", choices=["bf16_split", "fp16_split", "fp32"], default=None,
+                    help="serving workload: run the request streams once per precision (default: --precision)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is "
               "described in DESIGN.md and not run here.", file=sys.stderr)
         sys.exit(2)
+    if args.profile_sample > 0:
+        profile_sample(args)
+        return
     if args.workload != "crystal":
         if args.precision == "bf16_split" and args.workload == "batch":
             args.precision = "fp16_split"
@@ -478,9 +511,6 @@ def main():
     import synth
     from paper_1908_07628_amd import eels
 
-    if args.profile_sample > 0:
-        profile_sample(args)
-        return
 
     t0 = time.time()
     p = synth.config2()
