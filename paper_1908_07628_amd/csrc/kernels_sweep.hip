@@ -273,14 +273,21 @@ __device__ __forceinline__ void row_pass_body(float2* __restrict__ state, int nb
                 for (int m = 0; m < E; ++m) crow[t + T * m] = make_float2(v[m].x * cap_scale, v[m].y * cap_scale);
                 lds_sync_wave();
                 if (valid) {
-                    const int r0 = cap_ptr[y], r1 = cap_ptr[y + 1];
-                    for (int r = r0; r < r1; ++r) {
-                        const int4 rec = cap_rec[r];
-                        const int64_t dst = ((int64_t)rec.x * win_beams + beam) * Kpad + (int64_t)rec.y * rec.w;
-                        for (int u = t; u < rec.w; u += T) {
-                            int px = rec.z + u;
-                            if (px >= N) px -= N;
-                            store_c(win, dst + u, crow[px], sc);
+                    // the row's records are fetched T at a time, one per thread, and handed
+                    // round by shuffles within the row's threads (no load latency per record)
+                    const int r0 = cap_ptr[y], cnt = cap_ptr[y + 1] - r0;
+                    for (int c0 = 0; c0 < cnt; c0 += T) {
+                        const int4 mine = c0 + t < cnt ? cap_rec[r0 + c0 + t] : make_int4(0, 0, 0, 0);
+                        const int n = min(T, cnt - c0);
+                        for (int i = 0; i < n; ++i) {
+                            const int win_i = __shfl(mine.x, i, T), dy = __shfl(mine.y, i, T);
+                            const int x0 = __shfl(mine.z, i, T), nw = __shfl(mine.w, i, T);
+                            const int64_t dst = ((int64_t)win_i * win_beams + beam) * Kpad + (int64_t)dy * nw;
+                            for (int u = t; u < nw; u += T) {
+                                int px = x0 + u;
+                                if (px >= N) px -= N;
+                                store_c(win, dst + u, crow[px], sc);
+                            }
                         }
                     }
                 }
