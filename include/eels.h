@@ -199,15 +199,15 @@ eels_status eels_execute(const eels_plan* p, const float* d_V, const void* d_H, 
  *                          with the same S signature (eels_plan_s_signature) on the same V
  *                          and H; needs resident_s.  Only the set-up and the contractions run,
  *                          e.g. for a new set of probe positions.
- * Errors as eels_execute; INVALID_ARG for SKIP_SWEEPS without resident_s. */
-enum { EELS_EXEC_SKIP_UPLOAD = 1, EELS_EXEC_SKIP_SWEEPS = 2 };
+ *   EELS_EXEC_SWEEPS_ONLY  the set-up and both sweeps only (every S_1 window and every
+ *                          slice's S_2 capture left in the workspace, d_map zeroed); the
+ *                          contractions follow in eels_batch_contract.  Needs resident_s.
+ * Errors as eels_execute; INVALID_ARG for SKIP_SWEEPS or SWEEPS_ONLY without resident_s, or
+ * both together. */
+enum { EELS_EXEC_SKIP_UPLOAD = 1, EELS_EXEC_SKIP_SWEEPS = 2, EELS_EXEC_SWEEPS_ONLY = 4 };
 eels_status eels_execute_ex(const eels_plan* p, const float* d_V, const void* d_H, double* d_map,
                             void* d_workspace, size_t workspace_bytes, void* stream, unsigned flags);
 
-/* 64-bit signature of everything the S-matrix data in a workspace depends on (geometry,
- * slices, optics, beam lattices, windows, sites, storage format and the workspace
- * offsets of the S data), but not of the probes.  Equal signatures (with equal V and H)
- * mean the S data of one plan's execute serve the other. */
 /* As eels_execute_ex, and also writes the plan's elastic companion images:
  * d_images float64 [n_images][n_probes], overwritten (may be null when n_images = 0).  The
  * forward sweep then continues to the exit plane and captures the exit wave's band
@@ -216,7 +216,44 @@ eels_status eels_execute_ex(const eels_plan* p, const float* d_V, const void* d_
 eels_status eels_execute_images(const eels_plan* p, const float* d_V, const void* d_H, double* d_map, double* d_images,
                                 void* d_workspace, size_t workspace_bytes, void* stream, unsigned flags);
 
+/* 64-bit signature of everything the S-matrix data in a workspace depends on (geometry,
+ * slices, optics, beam lattices, windows, sites, storage format and the workspace
+ * offsets of the S data), but not of the probes.  Equal signatures (with equal V and H)
+ * mean the S data of one plan's execute serve the other. */
 eels_status eels_plan_s_signature(const eels_plan* p, uint64_t* sig);
+
+/* Fused contraction of a batch of maps (many specimens of uneven size).  Each map's
+ * contraction is the per-site sum of Eq. SHn0 (Sec. 3, second algorithm); the plans'
+ * site batches are taken level by level (the k-th batch of every plan in its execute
+ * order), and each level's first and second GEMMs of all plans run as one grouped launch
+ * per kernel variant over a merged descriptor table, so that small specimens share the
+ * matrix cores instead of launching one small grid each.
+ * Plans: split precision (all the same), resident_s, one slice group.  Workspaces are
+ * regions of one caller-owned arena: plan i at d_arena + ws_offsets[i] (256-byte aligned,
+ * eels_plan_workspace_bytes long, not overlapping, within arena_bytes).
+ *   eels_batch_create   host only: checks the plans, builds and bounds-checks the merged
+ *                       descriptors (their offsets count from the arena base).  The plans
+ *                       must outlive the batch.
+ *   eels_batch_table_bytes  device bytes of the merged table.
+ *   eels_batch_upload   copies the table to d_table (256-byte aligned, caller-owned) on
+ *                       `stream`; once, before any (captured) contraction.
+ *   eels_batch_contract enqueues on `stream`, after every plan's eels_execute_ex with
+ *                       EELS_EXEC_SWEEPS_ONLY on its workspace has completed (or precedes
+ *                       it on the stream): the producers per plan, the grouped GEMMs per
+ *                       level, the FP64 reductions into d_maps[i] (float64 [n_probes of plan
+ *                       i], zeroed by the sweeps-only execute).  d_H[i]: plan i's transition
+ *                       potentials.  No allocation, no host synchronisation (capturable).
+ * Results equal each plan's own eels_execute bit for bit.  Errors: INVALID_ARG (null
+ * pointers, mixed or FP32 precision, non-resident plans, workspace regions), INTERNAL (a
+ * merged descriptor outside its plan's workspace), DEVICE. */
+typedef struct eels_batch eels_batch;
+eels_status eels_batch_create(eels_batch** out, const eels_plan* const* plans, int n_plans, const size_t* ws_offsets,
+                              size_t arena_bytes);
+eels_status eels_batch_table_bytes(const eels_batch* b, size_t* bytes);
+eels_status eels_batch_upload(const eels_batch* b, void* d_table, void* stream);
+eels_status eels_batch_contract(const eels_batch* b, void* d_arena, const void* d_table, const void* const* d_H,
+                                double* const* d_maps, void* stream);
+eels_status eels_batch_destroy(eels_batch* b);
 
 /* Conventional multislice STEM-EELS (Sec. 3, first algorithm) on the same GPU, for comparing
  * the two algorithms on equal hardware.  For every probe the elastic wave is multisliced;

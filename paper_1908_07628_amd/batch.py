@@ -6,6 +6,11 @@ output slice.  The first `run_eager` uploads each plan's tables into its workspa
 into one graph, independent specimens on parallel stream branches so that their
 kernels overlap on the device, with each specimen's tuned knobs set before its
 launches are recorded.  `replay` launches the whole batch with one graph launch.
+
+fused=True (split precisions): the branches run only the specimens' set-up and sweeps
+(resident S-matrices), and the contractions of all specimens follow on one stream, level
+by level, each level's GEMMs one grouped launch over every specimen's sites
+(eels_batch_contract).
 """
 from __future__ import annotations
 
@@ -22,12 +27,13 @@ def _align(n: int, a: int = 256) -> int:
 
 class Batch:
     def __init__(self, problems: Sequence, precision: str = "fp32", n_streams: int = 4, device: str = "cuda",
-                 tuned: bool = True):
+                 tuned: bool = True, fused: bool = False):
         import torch
         self.torch = torch
         self.device = device
         self.problems = list(problems)
-        self.plans = [eels.Plan(p, precision=precision) for p in self.problems]
+        self.fused = fused
+        self.plans = [eels.Plan(p, precision=precision, resident_s=fused) for p in self.problems]
         self.tuned = tuned
         self.inputs = [eels.device_inputs(p, device) for p in self.problems]
         sizes = [_align(pl.workspace_bytes) for pl in self.plans]
@@ -41,6 +47,11 @@ class Batch:
         self.maps = torch.zeros(int(self.map_offsets[-1]), dtype=torch.float64, device=device)
         self.streams = [torch.cuda.Stream(device=device) for _ in range(max(1, n_streams))]
         self.graph = None
+        self.contraction = None
+        if fused:
+            self.contraction = eels.FusedContraction(self.plans, self.ws_offsets[:-1], int(self.ws_offsets[-1]))
+            self.table = torch.empty(self.contraction.table_bytes, dtype=torch.uint8, device=device)
+            self._table_uploaded = False
         # larger specimens first, dealt round-robin to the streams
         self.order = sorted(range(len(self.plans)), key=lambda i: -self.plans[i].workspace_bytes)
 
@@ -60,6 +71,11 @@ class Batch:
     def _enqueue(self, flags: int):
         torch = self.torch
         main = torch.cuda.current_stream(self.device)
+        if self.fused:
+            if not self._table_uploaded:
+                self.contraction.upload(self.table, stream=main)   # once, before any capture
+                self._table_uploaded = True
+            flags |= eels.EXEC_SWEEPS_ONLY
         for s in self.streams:
             s.wait_stream(main)
         for n, i in enumerate(self.order):
@@ -72,6 +88,9 @@ class Batch:
         for s in self.streams:
             main.wait_stream(s)
         autotune.set_knobs(autotune.DEFAULTS)
+        if self.fused:
+            self.contraction.contract(self.arena, self.table, [h for _, h in self.inputs],
+                                      [self.out(i) for i in range(len(self.plans))], stream=main)
 
     def run_eager(self):
         """Enqueue every specimen (uploading the tables); returns without waiting."""

@@ -15,6 +15,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
@@ -252,96 +253,106 @@ void run_jobs(const Plan& p, const Dev& d, const float2* dH, const Batch& b, int
     }
 }
 
+// Operands of a batch's split-precision GEMMs as contract launches them: epilogue, A and B
+// bases, and the store (C) or partial-sum (P) target.  The descriptors' offsets are relative
+// to these bases.
+struct SplitCall {
+    int epi;
+    const void *A, *B;
+    void* C;
+    float* P;
+};
+SplitCall split_gemm1(const Plan& p, const Dev& d) {
+    if (p.gram) return {0, d.mid2, d.w2, d.mid, nullptr};                  // Z = (H S_1) S_2^T
+    if (p.order == EELS_ORDER_S_FIRST) return {0, d.w2, d.mid2, d.mid, nullptr};
+    return {p.hs2 ? 0 : 3, d.C, d.mid2, d.mid, nullptr};                    // Psi = C S_1w
+}
+SplitCall split_gemm2(const Plan& p, const Dev& d) {
+    if (p.gram) return {2, d.mid, d.mid, nullptr, d.part};                 // Gram tiles of Z
+    if (p.order == EELS_ORDER_S_FIRST) return {1, d.mid, d.C, nullptr, d.part};
+    if (p.hs2) return {1, d.mid2, d.mid, nullptr, d.part};                 // (H S_2w) Psi
+    return {1, d.w2, d.mid2, nullptr, d.part};
+}
+
+// Producers a batch needs before its first GEMM: the H-multiplied operand (order S, Gram
+// form), or the SC transposes of the S_1 windows (order P in split precision).
+void producers_before_gemm1(const Plan& p, const Dev& d, const float2* dH, const Batch& b, hipStream_t st) {
+    const bool split = p.precision != EELS_FP32;
+    if (p.gram || p.order == EELS_ORDER_S_FIRST) {
+        if (split || p.recip) run_jobs(p, d, dH, b, b.slice, st);
+    } else if (split) {
+        // SC transposes of the sites' S_1 windows (mid2 holds them until the producer runs)
+        TimeScope ts(EELS_PHASE_PRODUCER, st);
+        for (int k = 0; k < b.job_count; ++k) {
+            const Job& jb = p.jobs[b.job_begin + k];
+            launch_window_t_sc(d.mid2 + jb.dst_off, d.w1 + jb.win_off, p.Kpad, p.N1, p.K, p.N1pad, p.precision, st);
+        }
+    }
+}
+
+// ... and between the two GEMMs (order P: the H-multiplied operand from Psi or S_2w).
+void producers_after_gemm1(const Plan& p, const Dev& d, const float2* dH, const Batch& b, hipStream_t st) {
+    const bool split = p.precision != EELS_FP32;
+    if (!p.gram && p.order != EELS_ORDER_S_FIRST && (split || p.recip)) run_jobs(p, d, dH, b, b.slice, st);
+}
+
+// The batch's partial sums into the map (direct detector sum) or into G (Gram form).
+void reduce_batch(const Plan& p, const Dev& d, double* map, const Batch& b, hipStream_t st) {
+    TimeScope ts(EELS_PHASE_REDUCE, st);
+    if (p.gram) {
+        launch_gram_reduce(d.gtot, (const float2*)d.part, b.n_parts, (int64_t)p.N1pad * p.N1pad, p.N1, p.N1pad, st);
+        return;
+    }
+    double nn = (double)p.nx * (double)p.ny;
+    double scale = (double)p.f * p.f / (nn * nn) / ((double)p.c_scale * p.c_scale);
+    if (b.red_ptr < 0) launch_reduce_dense(map, p.P, d.descs, b.d2_begin, b.d2_count, d.part, scale, st);
+    else launch_reduce(map, p.P, d.blob + b.red_ptr, d.blob + b.red_ent, d.descs, d.part, scale, st);
+}
+
 void contract(const Plan& p, const Dev& d, const float2* dH, double* map, int bi, hipStream_t st) {
     const Batch& b = p.batches[bi];
     const GemmDesc* dd = d.descs;
     const bool split = p.precision != EELS_FP32;
     const int nst = tune_get(TUNE_SC_STAGES);
     const bool h_pro = !p.recip;   // FP32 real-space: H applied in the GEMM prologue
-    if (p.gram) {
-        // Gram form: Z = (H S_1) S_2^T per site, then the upper tiles of Z^H Z, summed
-        // over the batch's sites into G in FP64
-        run_jobs(p, d, dH, b, b.slice, st);
-        {
-            TimeScope ts(EELS_PHASE_GEMM1, st);
-            if (split)
-                launch_cgemm_sc(p.precision, 0, nst, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.mid2, d.w2, d.mid,
-                                nullptr, d.blob, st, b.d1_rows);
-            else
-                launch_cgemm(EELS_FP32, 0, 0, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.mid2, d.w2, nullptr, d.mid,
-                             nullptr, d.blob, st);
-        }
-        {
-            TimeScope ts(EELS_PHASE_GEMM2, st);
-            if (split)
-                launch_cgemm_sc(p.precision, 2, nst, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.mid, d.mid, nullptr,
-                                d.part, d.blob, st);
-            else
-                launch_cgemm(EELS_FP32, 0, 2, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.mid, d.mid, nullptr, nullptr,
-                             d.part, d.blob, st);
-        }
-        TimeScope ts(EELS_PHASE_REDUCE, st);
-        launch_gram_reduce(d.gtot, (const float2*)d.part, b.n_parts, (int64_t)p.N1pad * p.N1pad, p.N1, p.N1pad, st);
-        return;
-    }
-    if (b.order == EELS_ORDER_S_FIRST) {
-        if (split || p.recip) run_jobs(p, d, dH, b, b.slice, st);
-        {
-            TimeScope ts(EELS_PHASE_GEMM1, st);
-            if (split)
-                launch_cgemm_sc(p.precision, 0, nst, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.w2, d.mid2, d.mid,
-                                nullptr, d.blob, st, b.d1_rows);
-            else
-                launch_cgemm(EELS_FP32, 0, 0, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.w2, h_pro ? d.w1 : d.mid2,
-                             h_pro ? dH : nullptr, d.mid, nullptr, d.blob, st);
-        }
-        {
-            TimeScope ts(EELS_PHASE_GEMM2, st);
-            if (split)
-                launch_cgemm_sc(p.precision, 1, nst, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.mid, d.C, nullptr,
-                                d.part, d.blob, st, b.d2_rows);
-            else
-                launch_cgemm(EELS_FP32, 0, 1, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.mid, d.C, nullptr, nullptr,
-                             d.part, d.blob, st);
-        }
-    } else {
+    const bool orderS = p.order == EELS_ORDER_S_FIRST;
+    producers_before_gemm1(p, d, dH, b, st);
+    {
+        TimeScope ts(EELS_PHASE_GEMM1, st);
         if (split) {
-            // SC transposes of the sites' S_1 windows (mid2 holds them until the producer runs)
-            TimeScope ts(EELS_PHASE_PRODUCER, st);
-            for (int k = 0; k < b.job_count; ++k) {
-                const Job& jb = p.jobs[b.job_begin + k];
-                launch_window_t_sc(d.mid2 + jb.dst_off, d.w1 + jb.win_off, p.Kpad, p.N1, p.K, p.N1pad, p.precision,
-                                   st);
-            }
-        }
-        {
-            TimeScope ts(EELS_PHASE_GEMM1, st);
-            if (split)   // Psi in SC form when it is the shared operand of the second GEMM
-                launch_cgemm_sc(p.precision, p.hs2 ? 0 : 3, nst, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.C, d.mid2,
-                                d.mid, nullptr, d.blob, st, b.d1_rows);
-            else
-                launch_cgemm(EELS_FP32, 1, 0, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.C, d.w1, nullptr, d.mid,
-                             nullptr, d.blob, st);
-        }
-        if (split || p.recip) run_jobs(p, d, dH, b, b.slice, st);
-        {
-            TimeScope ts(EELS_PHASE_GEMM2, st);
-            if (split && p.hs2)
-                launch_cgemm_sc(p.precision, 1, nst, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.mid2, d.mid, nullptr,
-                                d.part, d.blob, st, b.d2_rows);
-            else if (split)
-                launch_cgemm_sc(p.precision, 1, nst, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.w2, d.mid2, nullptr,
-                                d.part, d.blob, st, b.d2_rows);
-            else
-                launch_cgemm(EELS_FP32, 0, 1, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.w2, h_pro ? d.mid : d.mid2,
-                             h_pro ? dH : nullptr, nullptr, d.part, d.blob, st);
+            const SplitCall c = split_gemm1(p, d);
+            launch_cgemm_sc(p.precision, c.epi, nst, dd + b.d1_begin, b.d1_count, b.d1_tiles, c.A, c.B, c.C, c.P,
+                            d.blob, st, b.d1_rows);
+        } else if (p.gram) {
+            launch_cgemm(EELS_FP32, 0, 0, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.mid2, d.w2, nullptr, d.mid,
+                         nullptr, d.blob, st);
+        } else if (orderS) {
+            launch_cgemm(EELS_FP32, 0, 0, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.w2, h_pro ? d.w1 : d.mid2,
+                         h_pro ? dH : nullptr, d.mid, nullptr, d.blob, st);
+        } else {
+            launch_cgemm(EELS_FP32, 1, 0, dd + b.d1_begin, b.d1_count, b.d1_tiles, d.C, d.w1, nullptr, d.mid, nullptr,
+                         d.blob, st);
         }
     }
-    TimeScope ts(EELS_PHASE_REDUCE, st);
-    double nn = (double)p.nx * (double)p.ny;
-    double scale = (double)p.f * p.f / (nn * nn) / ((double)p.c_scale * p.c_scale);
-    if (b.red_ptr < 0) launch_reduce_dense(map, p.P, dd, b.d2_begin, b.d2_count, d.part, scale, st);
-    else launch_reduce(map, p.P, d.blob + b.red_ptr, d.blob + b.red_ent, dd, d.part, scale, st);
+    producers_after_gemm1(p, d, dH, b, st);
+    {
+        TimeScope ts(EELS_PHASE_GEMM2, st);
+        if (split) {
+            const SplitCall c = split_gemm2(p, d);
+            launch_cgemm_sc(p.precision, c.epi, nst, dd + b.d2_begin, b.d2_count, b.d2_tiles, c.A, c.B, c.C, c.P,
+                            d.blob, st, b.d2_rows);
+        } else if (p.gram) {
+            launch_cgemm(EELS_FP32, 0, 2, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.mid, d.mid, nullptr, nullptr,
+                         d.part, d.blob, st);
+        } else if (orderS) {
+            launch_cgemm(EELS_FP32, 0, 1, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.mid, d.C, nullptr, nullptr,
+                         d.part, d.blob, st);
+        } else {
+            launch_cgemm(EELS_FP32, 0, 1, dd + b.d2_begin, b.d2_count, b.d2_tiles, d.w2, h_pro ? d.mid : d.mid2,
+                         h_pro ? dH : nullptr, nullptr, d.part, d.blob, st);
+        }
+    }
+    reduce_batch(p, d, map, b, st);
 }
 
 // Companion images from the exit-wave band coefficients in img_exit: for each ring d,
@@ -523,13 +534,22 @@ eels_status eels_execute_images(const eels_plan* pl, const float* d_V, const voi
         set_error("transition potentials missing");
         return EELS_ERR_INVALID_ARG;
     }
-    if (flags & ~(unsigned)(EELS_EXEC_SKIP_UPLOAD | EELS_EXEC_SKIP_SWEEPS)) {
+    if (flags & ~(unsigned)(EELS_EXEC_SKIP_UPLOAD | EELS_EXEC_SKIP_SWEEPS | EELS_EXEC_SWEEPS_ONLY)) {
         set_error("unknown execute flag");
         return EELS_ERR_INVALID_ARG;
     }
     const bool skip_sweeps = (flags & EELS_EXEC_SKIP_SWEEPS) != 0;
-    if (skip_sweeps && !p.resident) {
-        set_error("EELS_EXEC_SKIP_SWEEPS needs a plan with resident_s");
+    const bool sweeps_only = (flags & EELS_EXEC_SWEEPS_ONLY) != 0;
+    if ((skip_sweeps || sweeps_only) && !p.resident) {
+        set_error("EELS_EXEC_SKIP_SWEEPS and EELS_EXEC_SWEEPS_ONLY need a plan with resident_s");
+        return EELS_ERR_INVALID_ARG;
+    }
+    if (skip_sweeps && sweeps_only) {
+        set_error("EELS_EXEC_SKIP_SWEEPS and EELS_EXEC_SWEEPS_ONLY exclude each other");
+        return EELS_ERR_INVALID_ARG;
+    }
+    if (sweeps_only && d_images && p.n_img > 0) {
+        set_error("EELS_EXEC_SWEEPS_ONLY does not compute companion images");
         return EELS_ERR_INVALID_ARG;
     }
     eels_status s = check_ws(p, d_workspace, workspace_bytes);
@@ -582,12 +602,12 @@ eels_status eels_execute_images(const eels_plan* pl, const float* d_V, const voi
         if (exit_here) companion_images(p, d, d_images, st);
         for (int j = rev_next; j >= g.j_lo; --j) {
             reverse_step(p, d, j, p.slices[j].ion, nullptr, st);
-            if (p.slices[j].ion)
+            if (p.slices[j].ion && !sweeps_only)
                 for (int bi : p.slices[j].batches) contract(p, d, (const float2*)d_H, d_map, bi, st);
         }
         rev_next = g.j_lo - 1;
     }
-    finish_map(p, d, d_map, st);
+    if (!sweeps_only) finish_map(p, d, d_map, st);
     HIPCHK(hipGetLastError());
     return EELS_OK;
 }
@@ -873,6 +893,249 @@ eels_status eels_timing_read(double* ms, int* counts) {
         ms[g_timing.phase[i]] += t;
         counts[g_timing.phase[i]] += 1;
     }
+    return EELS_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ fused batch contraction
+
+struct eels_batch {
+    struct Launch {
+        int epi, rows, begin, count, tiles;
+    };
+    struct Member {
+        int plan, batch;
+    };
+    struct Level {
+        std::vector<Member> members;
+        std::vector<Launch> g1, g2;
+    };
+    int precision = 0;
+    std::vector<const eels_plan*> plans;
+    std::vector<size_t> ws_off;
+    std::vector<Level> levels;
+    std::vector<GemmDesc> table;
+};
+
+namespace {
+
+// Bounds of a rebased descriptor's operands, in elements from the arena base, against its
+// plan's workspace region [lo, hi) bytes.  rows_a / rows_b: rows read (the probe count when
+// rows are gathered through the index list).
+bool desc_in_region(const GemmDesc& d, int epi, int64_t rows_a, int64_t rows_b, size_t lo, size_t hi) {
+    auto inside = [&](int64_t first, int64_t last_excl, int64_t unit) {
+        return first >= 0 && (size_t)(first * unit) >= lo && (size_t)(last_excl * unit) <= hi;
+    };
+    const int64_t kp = round_up(d.K, 16);
+    const int64_t nt1 = std::max(d.n_t, 1) - 1;
+    if (!inside(d.a_off, d.a_off + nt1 * d.a_tstride + (rows_a - 1) * d.lda + kp, 8)) return false;
+    if (!inside(d.b_off, d.b_off + nt1 * d.b_tstride + (rows_b - 1) * d.ldb + kp, 8)) return false;
+    const int64_t np = round_up(d.N_inner, 16);
+    if (epi == 0 || epi == 3) return inside(d.c_off, d.c_off + nt1 * d.ldc_t + (int64_t)(d.M - 1) * d.ldc_m + np, 8);
+    if (epi == 2) return inside(d.p_off, d.p_off + nt1 * d.ldc_t + (int64_t)(d.M - 1) * d.ldc_m + d.N_inner, 8);
+    return inside(d.p_off, d.p_off + (int64_t)(d.tiles_m - 1) * d.ld_part + nt1 * d.N_inner + d.N_inner, 4);
+}
+
+}  // namespace
+
+extern "C" {
+
+eels_status eels_batch_create(eels_batch** out, const eels_plan* const* plans, int n_plans, const size_t* ws_offsets,
+                              size_t arena_bytes) {
+    if (!out || !plans || !ws_offsets || n_plans < 1) {
+        set_error("null argument or no plans");
+        return EELS_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    try {
+        auto b = std::make_unique<eels_batch>();
+        std::vector<std::pair<size_t, size_t>> regions;
+        for (int i = 0; i < n_plans; ++i) {
+            if (!plans[i]) {
+                set_error("null plan");
+                return EELS_ERR_INVALID_ARG;
+            }
+            const Plan& p = plans[i]->p;
+            if (p.precision == EELS_FP32 || (i > 0 && p.precision != b->precision)) {
+                set_error("a fused batch needs one split precision for every plan");
+                return EELS_ERR_INVALID_ARG;
+            }
+            if (!p.resident || p.groups.size() > 1) {
+                set_error("a fused batch needs plans with resident_s (one slice group)");
+                return EELS_ERR_INVALID_ARG;
+            }
+            if ((ws_offsets[i] & 255) || ws_offsets[i] + p.ws_bytes > arena_bytes) {
+                set_error("workspace region misaligned or outside the arena");
+                return EELS_ERR_INVALID_ARG;
+            }
+            b->precision = p.precision;
+            b->plans.push_back(plans[i]);
+            b->ws_off.push_back(ws_offsets[i]);
+            regions.push_back({ws_offsets[i], ws_offsets[i] + p.ws_bytes});
+        }
+        std::sort(regions.begin(), regions.end());
+        for (size_t i = 1; i < regions.size(); ++i)
+            if (regions[i].first < regions[i - 1].second) {
+                set_error("workspace regions overlap");
+                return EELS_ERR_INVALID_ARG;
+            }
+        // each plan's batches in its execute order (slices descending)
+        std::vector<std::vector<int>> seq(n_plans);
+        size_t n_levels = 0;
+        for (int i = 0; i < n_plans; ++i) {
+            const Plan& p = b->plans[i]->p;
+            for (int j = p.nz - 1; j >= 0; --j)
+                if (p.slices[j].ion)
+                    for (int bi : p.slices[j].batches) seq[i].push_back(bi);
+            n_levels = std::max(n_levels, seq[i].size());
+        }
+        for (size_t k = 0; k < n_levels; ++k) {
+            eels_batch::Level lv;
+            // descriptors per launch group (epilogue, rows), in member order
+            std::vector<std::vector<GemmDesc>> d1, d2;
+            auto group = [](std::vector<eels_batch::Launch>& g, std::vector<std::vector<GemmDesc>>& dv, int epi,
+                             int rows) -> int {
+                for (size_t q = 0; q < g.size(); ++q)
+                    if (g[q].epi == epi && g[q].rows == rows) return (int)q;
+                g.push_back({epi, rows, 0, 0, 0});
+                dv.emplace_back();
+                return (int)g.size() - 1;
+            };
+            for (int i = 0; i < n_plans; ++i) {
+                if (k >= seq[i].size()) continue;
+                const Plan& p = b->plans[i]->p;
+                const Batch& bt = p.batches[seq[i][k]];
+                lv.members.push_back({i, seq[i][k]});
+                // the device bases of this plan's launches, as byte offsets from the arena
+                const Dev hd = make_dev(p, (void*)(uintptr_t)b->ws_off[i]);
+                const size_t lo = b->ws_off[i], hi = b->ws_off[i] + p.ws_bytes;
+                const int64_t blob_i = (int64_t)((uintptr_t)hd.blob / 4);
+                for (int gemm = 1; gemm <= 2; ++gemm) {
+                    const SplitCall c = gemm == 1 ? split_gemm1(p, hd) : split_gemm2(p, hd);
+                    const int rows = gemm == 1 ? bt.d1_rows : bt.d2_rows;
+                    const int q = gemm == 1 ? group(lv.g1, d1, c.epi, rows) : group(lv.g2, d2, c.epi, rows);
+                    std::vector<GemmDesc>& dst = gemm == 1 ? d1[q] : d2[q];
+                    eels_batch::Launch& L = gemm == 1 ? lv.g1[q] : lv.g2[q];
+                    const int begin = gemm == 1 ? bt.d1_begin : bt.d2_begin;
+                    const int count = gemm == 1 ? bt.d1_count : bt.d2_count;
+                    for (int e = 0; e < count; ++e) {
+                        GemmDesc d = p.descs[begin + e];
+                        if (d.h_off >= 0) {
+                            set_error("fused batch: descriptor with an H prologue");
+                            return EELS_ERR_INTERNAL;
+                        }
+                        const bool gather_a = d.idx_off >= 0 && (d.flags & GD_IDX_A);
+                        const bool gather_b = d.idx_off >= 0 && !(d.flags & GD_IDX_A);
+                        d.a_off += (int64_t)((uintptr_t)c.A / 8);
+                        d.b_off += (int64_t)((uintptr_t)c.B / 8);
+                        if (c.epi == 0 || c.epi == 3) d.c_off += (int64_t)((uintptr_t)c.C / 8);
+                        else if (c.epi == 2) d.p_off += (int64_t)((uintptr_t)c.P / 8);
+                        else d.p_off += (int64_t)((uintptr_t)c.P / 4);
+                        if (d.idx_off >= 0) d.idx_off += blob_i;
+                        if (!desc_in_region(d, c.epi, gather_a ? p.P : d.M, gather_b ? p.P : d.N_inner, lo, hi)) {
+                            set_error("fused batch: a merged descriptor leaves its plan's workspace");
+                            return EELS_ERR_INTERNAL;
+                        }
+                        if (d.idx_off >= 0 &&
+                            (size_t)(d.idx_off + (gather_a ? d.M : d.N_inner)) * 4 > lo + p.off_blob + p.blob.size() * 4) {
+                            set_error("fused batch: an index list leaves its plan's table");
+                            return EELS_ERR_INTERNAL;
+                        }
+                        d.tile_start = L.tiles;
+                        L.tiles += d.tiles_m * d.tiles_n * d.n_t;
+                        dst.push_back(d);
+                    }
+                }
+            }
+            for (int gemm = 1; gemm <= 2; ++gemm) {
+                auto& g = gemm == 1 ? lv.g1 : lv.g2;
+                auto& dv = gemm == 1 ? d1 : d2;
+                for (size_t q = 0; q < g.size(); ++q) {
+                    g[q].begin = (int)b->table.size();
+                    g[q].count = (int)dv[q].size();
+                    b->table.insert(b->table.end(), dv[q].begin(), dv[q].end());
+                }
+            }
+            b->levels.push_back(std::move(lv));
+        }
+        *out = b.release();
+        return EELS_OK;
+    } catch (const std::exception& e) {
+        set_error(e.what());
+        return EELS_ERR_INTERNAL;
+    }
+}
+
+eels_status eels_batch_table_bytes(const eels_batch* b, size_t* bytes) {
+    if (!b || !bytes) return EELS_ERR_INVALID_ARG;
+    *bytes = std::max<size_t>(b->table.size(), 1) * sizeof(GemmDesc);
+    return EELS_OK;
+}
+
+eels_status eels_batch_upload(const eels_batch* b, void* d_table, void* stream) {
+    if (!b || !d_table || ((uintptr_t)d_table & 255)) {
+        set_error("null batch or table, or table not 256-byte aligned");
+        return EELS_ERR_INVALID_ARG;
+    }
+    if (!b->table.empty())
+        HIPCHK(hipMemcpyAsync(d_table, b->table.data(), b->table.size() * sizeof(GemmDesc), hipMemcpyHostToDevice,
+                              (hipStream_t)stream));
+    return EELS_OK;
+}
+
+eels_status eels_batch_contract(const eels_batch* b, void* d_arena, const void* d_table, const void* const* d_H,
+                                double* const* d_maps, void* stream) {
+    if (!b || !d_arena || !d_table || !d_maps || ((uintptr_t)d_arena & 255)) {
+        set_error("null argument or arena not 256-byte aligned");
+        return EELS_ERR_INVALID_ARG;
+    }
+    const int n = (int)b->plans.size();
+    for (int i = 0; i < n; ++i)
+        if (!d_maps[i] || (b->plans[i]->p.n_trans_total > 0 && (!d_H || !d_H[i]))) {
+            set_error("null map or transition potentials");
+            return EELS_ERR_INVALID_ARG;
+        }
+    hipStream_t st = (hipStream_t)stream;
+    char* arena = (char*)d_arena;
+    const GemmDesc* table = (const GemmDesc*)d_table;
+    std::vector<Dev> devs;
+    for (int i = 0; i < n; ++i) devs.push_back(make_dev(b->plans[i]->p, arena + b->ws_off[i]));
+    const int nst = tune_get(TUNE_SC_STAGES);
+    g_timing.used = 0;
+    for (const auto& lv : b->levels) {
+        for (const auto& m : lv.members) {
+            const Plan& p = b->plans[m.plan]->p;
+            producers_before_gemm1(p, devs[m.plan], (const float2*)d_H[m.plan], p.batches[m.batch], st);
+        }
+        {
+            TimeScope ts(EELS_PHASE_GEMM1, st);
+            for (const auto& g : lv.g1)
+                launch_cgemm_sc(b->precision, g.epi, nst, table + g.begin, g.count, g.tiles, arena, arena, arena,
+                                (float*)arena, (const int*)arena, st, g.rows);
+        }
+        for (const auto& m : lv.members) {
+            const Plan& p = b->plans[m.plan]->p;
+            producers_after_gemm1(p, devs[m.plan], (const float2*)d_H[m.plan], p.batches[m.batch], st);
+        }
+        {
+            TimeScope ts(EELS_PHASE_GEMM2, st);
+            for (const auto& g : lv.g2)
+                launch_cgemm_sc(b->precision, g.epi, nst, table + g.begin, g.count, g.tiles, arena, arena, arena,
+                                (float*)arena, (const int*)arena, st, g.rows);
+        }
+        for (const auto& m : lv.members) {
+            const Plan& p = b->plans[m.plan]->p;
+            reduce_batch(p, devs[m.plan], d_maps[m.plan], p.batches[m.batch], st);
+        }
+    }
+    for (int i = 0; i < n; ++i) finish_map(b->plans[i]->p, devs[i], d_maps[i], st);
+    HIPCHK(hipGetLastError());
+    return EELS_OK;
+}
+
+eels_status eels_batch_destroy(eels_batch* b) {
+    delete b;
     return EELS_OK;
 }
 

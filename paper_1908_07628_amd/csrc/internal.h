@@ -31,10 +31,9 @@ struct GemmDesc {
     int64_t a_off, b_off, h_off, c_off, p_off;
     int64_t lda, ldb, ldh, ldc_m, ldc_t, ld_part, a_tstride, b_tstride;
     int M, N_inner, n_t, K;
-    int idx_off;       // offset into the int table, -1 = no gather
+    int64_t idx_off;   // offset into the int table, -1 = no gather
     int tiles_m, tiles_n, tile_start;
     int flags;         // GD_* bits
-    int pad_;
 };
 // descriptor flags: GD_ZERO_PAD: the plain FP32 store epilogue also zeroes the padding
 // columns N .. ceil16(N)-1 of every stored row (they are K padding of a later product);

@@ -595,7 +595,7 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
                 d.h_off = -1; d.ldh = 0;
                 d.c_off = site_moff[si]; d.ldc_m = p.Kpad; d.ldc_t = 0;
                 d.M = Ps; d.N_inner = p.K; d.n_t = 1; d.K = p.N1;
-                d.idx_off = (int)site_idx[s];
+                d.idx_off = site_idx[s];
             }
             d.tiles_m = (int)ceil_div(d.M, rows1);
             d.tiles_n = (int)ceil_div(d.N_inner, GEMM_BN);
@@ -641,7 +641,7 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
                 d.b_off = 0; d.ldb = p.N1pad;
                 d.h_off = -1; d.ldh = 0;
                 d.M = p.N2; d.N_inner = Ps; d.n_t = st.n_trans; d.K = p.N1;
-                d.idx_off = (int)site_idx[s];
+                d.idx_off = site_idx[s];
             } else if (p.hs2) {
                 // A_n(q, R) = sum_r (H_t S2w)[q][r] Psi_s[i][r]: the producer's H_t S_2w rows
                 // (one block per transition), Psi shared by the transitions

@@ -65,8 +65,9 @@ EXPORTS = ["eels_get_version", "eels_status_string", "eels_last_error", "eels_pl
            "eels_execute", "eels_debug_s1", "eels_debug_s2", "eels_gemm_work_bytes", "eels_debug_cgemm",
            "eels_tune_set", "eels_tune_get", "eels_timing_enable", "eels_timing_read", "eels_execute_ex",
            "eels_plan_s_signature", "eels_execute_images", "eels_conventional_workspace_bytes",
-           "eels_conventional_map"]
-EXEC_SKIP_UPLOAD, EXEC_SKIP_SWEEPS = 1, 2
+           "eels_conventional_map", "eels_batch_create", "eels_batch_table_bytes", "eels_batch_upload",
+           "eels_batch_contract", "eels_batch_destroy"]
+EXEC_SKIP_UPLOAD, EXEC_SKIP_SWEEPS, EXEC_SWEEPS_ONLY = 1, 2, 4
 PHASES = ["setup", "sweep", "producer", "gemm1", "gemm2", "reduce", "images"]
 
 
@@ -99,6 +100,11 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.eels_gemm_work_bytes.restype = sz
     lib.eels_debug_cgemm.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp, C.c_int,
                                      vp, vp, vp]
+    lib.eels_batch_create.argtypes = [C.POINTER(vp), C.POINTER(vp), C.c_int, C.POINTER(sz), sz]
+    lib.eels_batch_table_bytes.argtypes = [vp, C.POINTER(sz)]
+    lib.eels_batch_upload.argtypes = [vp, vp, vp]
+    lib.eels_batch_contract.argtypes = [vp, vp, vp, C.POINTER(vp), C.POINTER(vp), vp]
+    lib.eels_batch_destroy.argtypes = [vp]
     lib.eels_tune_set.argtypes = [C.c_int, C.c_int]
     lib.eels_tune_get.argtypes = [C.c_int]
     lib.eels_timing_enable.argtypes = [C.c_int]
@@ -252,6 +258,44 @@ class Plan:
         _check(load_library().eels_debug_s2(self._h, _ptr(V), int(slice_index), _ptr(out), _ptr(workspace),
                                             workspace.numel(), _stream(stream)))
         return out
+
+
+class FusedContraction:
+    """The contractions of several resident split-precision plans, level by level in grouped
+    launches over one merged descriptor table (eels_batch_*).  The plans' workspaces are
+    regions of one arena at ws_offsets (bytes)."""
+
+    def __init__(self, plans, ws_offsets, arena_bytes: int):
+        lib = load_library()
+        self.plans = list(plans)                        # kept alive for the batch's lifetime
+        arr = (C.c_void_p * len(self.plans))(*[pl._h.value for pl in self.plans])
+        offs = (C.c_size_t * len(self.plans))(*[int(o) for o in ws_offsets])
+        h = C.c_void_p()
+        _check(lib.eels_batch_create(C.byref(h), arr, len(self.plans), offs, int(arena_bytes)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _LIB is not None:
+            _LIB.eels_batch_destroy(h)
+            self._h = None
+
+    @property
+    def table_bytes(self) -> int:
+        v = C.c_size_t()
+        _check(load_library().eels_batch_table_bytes(self._h, C.byref(v)))
+        return int(v.value)
+
+    def upload(self, table, stream=None):
+        """Copy the merged descriptors into `table` (device uint8 tensor of table_bytes)."""
+        _check(load_library().eels_batch_upload(self._h, _ptr(table), _stream(stream)))
+
+    def contract(self, arena, table, H_list, maps, stream=None):
+        """Enqueue the fused contractions after every plan's EXEC_SWEEPS_ONLY execute."""
+        n = len(self.plans)
+        hs = (C.c_void_p * n)(*[_ptr(h) for h in H_list])
+        ms = (C.c_void_p * n)(*[_ptr(m) for m in maps])
+        _check(load_library().eels_batch_contract(self._h, _ptr(arena), _ptr(table), hs, ms, _stream(stream)))
 
 
 def device_inputs(problem, device="cuda"):

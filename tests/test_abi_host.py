@@ -228,3 +228,35 @@ def test_tuning_knob_ranges_and_gram_stack_plan():
             eels.tune_set(key, bad)
     assert eels.tune_get(eels.TUNE_GRAM_STACK) == 1 and eels.tune_get(eels.TUNE_GEMM1_ROWS) == 1
     assert eels.tune_get(eels.TUNE_GEMM2_ROWS) == 1
+
+
+def test_fused_batch_plan_checks():
+    """Host side of the fused batch contraction: merged descriptors are built and bounds-
+    checked against each plan's workspace region; mixed or FP32 precision, non-resident plans
+    and overlapping or misaligned regions are refused."""
+    _lib()
+    probs = [synth.random_problem(40 + i, n=n, L=L, nz=3, n_sites=2, n_trans=2, window_A=w, interp_f=f)
+             for i, (n, L, w, f) in enumerate([(32, 8.0, 0.0, 1), (64, 12.0, 3.0, 1), (64, 16.0, 3.0, 2),
+                                                (32, 8.0, 3.0, 1)])]
+    for prec in ("bf16_split", "fp16_split"):
+        plans = [eels.Plan(p, precision=prec, resident_s=True) for p in probs]
+        sizes = [(pl.workspace_bytes + 255) // 256 * 256 for pl in plans]
+        offs = np.concatenate([[0], np.cumsum(sizes)])
+        fc = eels.FusedContraction(plans, offs[:-1], int(offs[-1]))
+        assert fc.table_bytes >= 144 * len(plans) * 2
+        with pytest.raises(eels.EelsError) as e:                       # overlapping regions
+            eels.FusedContraction(plans, [0] * len(plans), int(offs[-1]))
+        assert e.value.status == 1
+        with pytest.raises(eels.EelsError):                            # misaligned region
+            eels.FusedContraction(plans, offs[:-1] + 8, int(offs[-1]) + 8)
+        with pytest.raises(eels.EelsError):                            # beyond the arena
+            eels.FusedContraction(plans, offs[:-1], int(offs[-1]) - 256)
+    mixed = [eels.Plan(probs[0], precision="bf16_split", resident_s=True),
+             eels.Plan(probs[1], precision="fp16_split", resident_s=True)]
+    for bad in (mixed, [eels.Plan(probs[0], precision="fp32", resident_s=True)],
+                [eels.Plan(probs[0], precision="bf16_split")]):
+        sizes = [(pl.workspace_bytes + 255) // 256 * 256 for pl in bad]
+        offs = np.concatenate([[0], np.cumsum(sizes)])
+        with pytest.raises(eels.EelsError) as e:
+            eels.FusedContraction(bad, offs[:-1], int(offs[-1]))
+        assert e.value.status == 1

@@ -59,6 +59,38 @@ def test_batch_graph_replays_match_eager_and_solo():
             assert np.array_equal(got[i], eager[i]), (rep, i)
 
 
+@pytest.mark.parametrize("prec", ["bf16_split", "fp16_split"])
+def test_fused_batch_contraction_matches_per_specimen(prec):
+    """Fused batch: every specimen's set-up and sweeps on parallel branches, then the
+    contractions of all specimens level by level, each level's GEMMs one grouped launch over
+    a merged descriptor table.  Specimens of three kinds (cropped windows, f = 2 order P, and
+    a full-cell band-basis cell) give launches of different epilogues in one level.  Maps
+    equal each specimen's own execute bit for bit, eagerly and in three graph replays, and
+    meet the split bar against the oracle."""
+    eels = _gpu()
+    from paper_1908_07628_amd.batch import Batch
+    sp = _specimens() + [synth.config3_subproblem(n=128, L=25.0, nz=3, n_scan=4, f=2),
+                         synth.random_problem(41, n=32, L=8.0, nz=3, n_sites=2, n_trans=2)]
+    b = Batch(sp, precision=prec, n_streams=3, tuned=False, fused=True)
+    _say("fused batch", prec, len(sp), "specimens, table bytes", b.contraction.table_bytes)
+    b.run_eager()
+    fused = b.maps_host()
+    for i, p in enumerate(sp):
+        solo = eels.solve(p, precision=prec)
+        assert np.array_equal(fused[i], solo), i
+    for i in (0, len(sp) - 2, len(sp) - 1):
+        assert metrics.rel_l2(fused[i], prism.prism_map(sp[i])) < 1e-3, i
+    b.capture()
+    for rep in range(3):
+        b.maps.zero_()                                  # eager work between replays
+        torch.cuda.synchronize()
+        b.replay()
+        got = b.maps_host()
+        _say("fused replay", rep)
+        for i in range(len(sp)):
+            assert np.array_equal(got[i], fused[i]), (rep, i)
+
+
 def test_autotuner_caches_a_valid_setting(tmp_path, monkeypatch):
     eels = _gpu()
     from paper_1908_07628_amd import autotune
