@@ -184,6 +184,28 @@ def bench_batch(args):
     got = b.maps_host()
     worst = max(float(np.max(np.abs(g - r)) / max(np.max(np.abs(r)), 1e-300)) for g, r in zip(got, ref))
     probes = int(sum(p.n_probes for p in specs))
+    arena_gb = b.arena.numel() / 1e9
+    del b
+    torch.cuda.empty_cache()
+    # fused: the specimens' sweeps on the branches, then every level's GEMMs of all specimens
+    # in one grouped launch (resident S-matrices; same tuned knobs for the sweeps)
+    bf = Batch(specs, precision=args.precision, n_streams=4, tuned=True, fused=True)
+    log(f"fused arena {bf.arena.numel() / 1e9:.1f} GB, merged table {bf.contraction.table_bytes} bytes")
+    bf.run_eager()
+    fused_eager = bf.maps_host()
+    fused_vs = max(float(np.max(np.abs(g - r)) / max(np.max(np.abs(r)), 1e-300)) for g, r in zip(fused_eager, ref))
+    bf.capture()
+    bf.replay()
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    for _ in range(args.steps):
+        bf.replay()
+    torch.cuda.synchronize()
+    t_fused = (time.perf_counter() - t3) / args.steps
+    fused_graph = bf.maps_host()
+    fused_stable = all(np.array_equal(g, r) for g, r in zip(fused_graph, fused_eager))
+    del bf
+    torch.cuda.empty_cache()
     return {
         "metric": METRIC, "value": round(probes / t_graph, 2), "unit": "probe-px/s", "n_gpus": 1,
         "steps": args.steps, "warmup": 1, "ms_per_step": round(1e3 * t_graph, 1), "higher_is_better": True,
@@ -193,7 +215,13 @@ def bench_batch(args):
                                 "4 A crop, 16^2-64^2 probes; one captured HIP graph on 4 stream branches"),
                    "n_specimens": len(specs), "total_probes": probes},
         "eager_sequential_ms": round(1e3 * t_seq, 1), "graph_speedup": round(t_seq / t_graph, 2),
-        "graph_vs_eager_max_rel_diff": worst,
+        "graph_vs_eager_max_rel_diff": worst, "arena_GB": round(arena_gb, 1),
+        "fused": {"value": round(probes / t_fused, 2), "ms_per_step": round(1e3 * t_fused, 1),
+                  "speedup_vs_graph": round(t_graph / t_fused, 3),
+                  "max_rel_diff_vs_per_specimen": fused_vs, "graph_replays_equal_eager": fused_stable,
+                  "what": ("specimens' sweeps on 4 stream branches, then each contraction level's GEMMs of "
+                           "all specimens in one grouped launch per kernel variant (eels_batch_contract); "
+                           "one captured graph")},
     }
 
 
