@@ -313,8 +313,8 @@ __device__ __forceinline__ void row_pass_body(float2* __restrict__ state, int nb
     }
 }
 
-// Two waves per SIMD without capture (201 VGPRs at N = 256, no spills); the capturing
-// variant keeps the compiler's register budget, where forcing two waves would spill.
+// Two waves per SIMD, with and without capture (at N = 1024 the capturing variant spills
+// 36 bytes per lane to get there, and is faster for it than at one wave).
 template <int N, int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_row_pass(
     float2* __restrict__ state, int nbeam, int ny, int nlx, int hlx, int ldx, const float2* __restrict__ Tj,
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 }
 
 template <int N, int MODE>
-__global__ __launch_bounds__(256) void k_row_pass_cap(float2* __restrict__ state, int nbeam, int ny, int nlx, int hlx,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_row_pass_cap(float2* __restrict__ state, int nbeam, int ny, int nlx, int hlx,
                                                       int ldx, const float2* __restrict__ Tj,
                                                       const float2* __restrict__ tw, const int* __restrict__ cap_ptr,
                                                       const int4* __restrict__ cap_rec, void* __restrict__ win,
