@@ -37,7 +37,7 @@ def test_config2_bf16_split_sampled_probes():
 GOLD3 = os.path.join(os.path.dirname(__file__), "golden", "config3_samples.json")
 
 
-@pytest.mark.parametrize("precision,bar", [("bf16_split", 1e-3), ("fp32", 1e-4)])
+@pytest.mark.parametrize("precision,bar", [("bf16_split", 1e-3), ("fp16_split", 1e-3), ("fp32", 1e-4)])
 def test_config3_sampled_probes(precision, bar):
     """Full-size nanoparticle geometry (1024^2, 50 slices, f = 4, 4 A crop, N_1 = N_2 = 2025)
     in the launch configuration of bench.py's nanoparticle workload (order P, memory budget
