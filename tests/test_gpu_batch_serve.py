@@ -91,6 +91,38 @@ def test_fused_batch_contraction_matches_per_specimen(prec):
             assert np.array_equal(got[i], fused[i]), (rep, i)
 
 
+GOLD4 = os.path.join(os.path.dirname(__file__), "golden", "config4_samples.json")
+
+
+def test_config4_batch_sampled_probes():
+    """The 64-specimen batch workload in bench.py's fused configuration (FP16 split, four
+    stream branches, fused contraction, one captured graph, replayed): two of its specimens
+    (128^2 with f = 1 and 256^2 with f = 2) at sampled probes against the FP64 PRISM oracle
+    (tests/golden/config4_samples.json, written by make_config4_samples.py)."""
+    import json
+    eels = _gpu()
+    from paper_1908_07628_amd.batch import Batch
+    g = json.load(open(GOLD4))
+    specs = synth.config4(n_specimens=64, workers=1)       # no fork from a GPU process
+    torch.cuda.empty_cache()
+    _say("config4 generated; fused batch of", len(specs))
+    bf = Batch(specs, precision="fp16_split", n_streams=4, tuned=False, fused=True)
+    bf.run_eager()
+    bf.capture()
+    bf.maps.zero_()
+    torch.cuda.synchronize()
+    bf.replay()
+    maps = bf.maps_host()
+    del bf
+    torch.cuda.empty_cache()
+    for s in g["specimens"]:
+        got = maps[s["index"]][s["probe_index"]]
+        ref = np.asarray(s["map"])
+        _say("specimen", s["index"], "max rel err", float(np.max(np.abs(got - ref)) / np.max(ref)))
+        assert np.all(np.isfinite(got)) and np.max(ref) > 0
+        assert np.max(np.abs(got - ref)) / np.max(ref) < 1e-3
+
+
 def test_autotuner_caches_a_valid_setting(tmp_path, monkeypatch):
     eels = _gpu()
     from paper_1908_07628_amd import autotune
