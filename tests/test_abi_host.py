@@ -260,3 +260,27 @@ def test_fused_batch_plan_checks():
         with pytest.raises(eels.EelsError) as e:
             eels.FusedContraction(bad, offs[:-1], int(offs[-1]))
         assert e.value.status == 1
+
+
+def test_execute_flag_checks():
+    """Execute flags are checked before any device work: unknown bits, SKIP_SWEEPS or
+    SWEEPS_ONLY without resident S-matrices, both together, and SWEEPS_ONLY with companion
+    images are refused."""
+    import ctypes as C
+    lib = _lib()
+    p = synth.random_problem(5, n=32, nz=3, n_sites=2, n_trans=2)
+    plain = eels.Plan(p, precision="bf16_split")
+    res = eels.Plan(p, precision="bf16_split", resident_s=True)
+    img = eels.Plan(p, precision="bf16_split", resident_s=True, images=[(0.0, 20.0)])
+    dummy = C.c_void_p(256)   # never dereferenced: the calls fail their checks first
+    ws = 1 << 40
+
+    def run(plan, flags, images=None):
+        return lib.eels_execute_images(plan._h, dummy, dummy, dummy, images, dummy, ws, None, flags)
+
+    assert run(plain, 8) == 1
+    assert run(plain, eels.EXEC_SKIP_SWEEPS) == 1
+    assert run(plain, eels.EXEC_SWEEPS_ONLY) == 1
+    assert run(res, eels.EXEC_SKIP_SWEEPS | eels.EXEC_SWEEPS_ONLY) == 1
+    assert run(img, eels.EXEC_SWEEPS_ONLY, dummy) == 1
+    assert "images" in lib.eels_last_error().decode()
