@@ -394,3 +394,44 @@ def test_beam_split_map_with_interpolation_and_crop():
     seen = np.any([site_eligible(p, st, s) for s in range(p.n_sites)], axis=0)
     assert not seen[-1] and seen.sum() >= 1
     assert np.all(got[~seen] == 0.0) and np.all(got[seen] > 0)
+
+
+def test_mirror_maps_m_to_minus_m():
+    """A cell mirror-symmetric under y -> L - y (no jitter; atoms asymmetric in x) with the
+    ionised atom on the mirror line: the map of transition m at probe R equals the map of
+    -m at the mirrored probe, since the mirror takes the azimuth phi to -phi.  The maps of m
+    and -m themselves differ, so the pin checks the sign of the azimuth through the whole
+    method."""
+    from synth.specimens import _finish, ENERGY_300KEV, probe_grid
+    L, n, nz, ns = 10.0, 48, 3, 6
+    xs = (1.0, 4.0, 7.5)
+    a_slice, a_xy = [], []
+    for j in range(nz):
+        for x in xs:
+            for iy in range(3):
+                a_slice.append(j)
+                a_xy.append((x, (iy + 0.5) * L / 3))
+    amp = np.tile([[40.0, 10.0]], (len(a_slice), 1))
+    wid = np.tile([[0.3, 0.8]], (len(a_slice), 1))
+    probes = probe_grid(ns, ns, L / ns, L / ns)
+    maps = {}
+    for m in (-1, 1, -2, 2):
+        p = _finish("mirror", n, n, L, L, [2.0] * nz, a_slice, a_xy, amp, wid, [1], [(4.0, L / 2)],
+                    [(abs(m), m, 0.4)], probes, (ns, ns), energy_eV=ENERGY_300KEV, aperture_mrad=20.0,
+                    det_inner_mrad=0.0, det_outer_mrad=30.0, interp_f=1, window_A=0.0)
+        maps[m] = prism.prism_map(p)
+    iy, ix = np.divmod(np.arange(ns * ns), ns)
+    mirror = ((ns - iy) % ns) * ns + ix
+    for m in (1, 2):
+        top = np.max(maps[m])
+        assert np.max(np.abs(maps[m] - maps[-m][mirror])) < 1e-9 * top
+        assert np.max(np.abs(maps[m] - maps[-m])) > 1e-5 * top      # 4 orders above rounding
+
+
+def test_window_not_smaller_than_cell_is_the_full_cell():
+    """A crop window at least as large as the cell means the full cell: the map equals the
+    uncropped map exactly."""
+    full = synth.random_problem(13, n=32, L=8.0, nz=3, n_sites=2, n_trans=2, window_A=0.0)
+    big = synth.random_problem(13, n=32, L=8.0, nz=3, n_sites=2, n_trans=2, window_A=8.0)
+    assert big.H.shape == full.H.shape
+    assert np.array_equal(prism.prism_map(big), prism.prism_map(full))
