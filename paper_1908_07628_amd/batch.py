@@ -34,6 +34,8 @@ class Batch:
         self.problems = list(problems)
         self.fused = fused
         self.plans = [eels.Plan(p, precision=precision, resident_s=fused) for p in self.problems]
+        if tuned:
+            self.plans = [autotune.tuned_plan(pl) for pl in self.plans]
         self.tuned = tuned
         self.inputs = [eels.device_inputs(p, device) for p in self.problems]
         sizes = [_align(pl.workspace_bytes) for pl in self.plans]
@@ -59,13 +61,24 @@ class Batch:
         return self.maps[int(self.map_offsets[i]):int(self.map_offsets[i + 1])]
 
     def tune(self, reps: int = 1):
-        """Autotune each distinct shape key once (cached across processes)."""
+        """Autotune each distinct shape key once (cached across processes), then rebuild the
+        plans whose key chose other macro tiles (same workspace size)."""
         seen = set()
         for i, pl in enumerate(self.plans):
             k = autotune.key_of(pl)
             if k not in seen:
                 seen.add(k)
                 autotune.tune(pl, *self.inputs[i], reps=reps)
+        for i, pl in enumerate(self.plans):
+            p2 = autotune.tuned_plan(pl)
+            if p2 is not pl:
+                if p2.workspace_bytes > self.workspaces[i].numel():
+                    raise eels.EelsError(4, "retuned plan needs a larger workspace")
+                self.plans[i] = p2
+        if self.contraction is not None:
+            self.contraction = eels.FusedContraction(self.plans, self.ws_offsets[:-1], int(self.ws_offsets[-1]))
+            self.table = self.torch.empty(self.contraction.table_bytes, dtype=self.torch.uint8, device=self.device)
+            self._table_uploaded = False
         self.tuned = True
 
     def _enqueue(self, flags: int):

@@ -142,6 +142,9 @@ class Plan:
         means the band limit (e.g. ((0, det_outer), (60, 0)) for iBF and ADF).  s1_mode:
         "stored" (exact) or "inverse" (inverse multislice, Sec. 4.C)."""
         lib = load_library()
+        self._source = (problem, dict(precision=precision, order=order, max_workspace_bytes=max_workspace_bytes,
+                                      lambda_A=lambda_A, sigma=sigma, real_space=real_space, resident_s=resident_s,
+                                      detector_sum=detector_sum, images=images, s1_mode=s1_mode))
         self._img = np.ascontiguousarray(np.asarray(images, dtype=np.float64).reshape(-1, 2))
         self.n_images = int(self._img.shape[0])
         pr = problem
@@ -180,6 +183,12 @@ class Plan:
         if h is not None and h.value and _LIB is not None:
             _LIB.eels_plan_destroy(h)
             self._h = None
+
+    def replan(self) -> "Plan":
+        """A new plan of the same request under the current plan-time knobs (tile rows, Gram
+        stacking)."""
+        problem, kw = self._source
+        return Plan(problem, **kw)
 
     @property
     def workspace_bytes(self) -> int:

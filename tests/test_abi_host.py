@@ -284,3 +284,31 @@ def test_execute_flag_checks():
     assert run(res, eels.EXEC_SKIP_SWEEPS | eels.EXEC_SWEEPS_ONLY) == 1
     assert run(img, eels.EXEC_SWEEPS_ONLY, dummy) == 1
     assert "images" in lib.eels_last_error().decode()
+
+
+def test_autotuner_plan_time_knobs(tmp_path, monkeypatch):
+    """The tuner's macro-tile candidates (split precision only), the cache lookups, and the plan
+    rebuilt with cached tile shapes, which leaves the global knobs at their defaults."""
+    _lib()
+    import json
+    from paper_1908_07628_amd import autotune
+    monkeypatch.setenv("EELS_TUNE_CACHE", str(tmp_path / "tune.json"))
+    p = synth.config1()
+    sp = eels.Plan(p, precision="bf16_split")
+    fp = eels.Plan(p, precision="fp32")
+    assert autotune.plan_candidates(fp) == [autotune.PLAN_DEFAULTS]
+    pcs = autotune.plan_candidates(sp)
+    assert len(pcs) == 4 and autotune.PLAN_DEFAULTS in pcs
+    assert len({json.dumps(c, sort_keys=True) for c in pcs}) == 4
+    assert autotune.plan_knobs(sp) == autotune.PLAN_DEFAULTS and autotune.tuned_plan(sp) is sp
+    cfg = {"gemm1_rows": 0, "gemm2_rows": 1, "sc_stages": 3, "tile_order": 1}
+    autotune.save_cache({autotune.key_of(sp): cfg})
+    assert autotune.plan_knobs(sp) == {"gemm1_rows": 0, "gemm2_rows": 1}
+    q = autotune.tuned_plan(sp)
+    assert q is not sp and q.info() == sp.info() and q.workspace_bytes <= sp.workspace_bytes
+    assert eels.tune_get(eels.TUNE_GEMM1_ROWS) == 1 and eels.tune_get(eels.TUNE_GEMM2_ROWS) == 1
+    try:
+        assert autotune.apply(sp) == {"sc_stages": 3, "tile_order": 1}
+        assert eels.tune_get(eels.TUNE_SC_STAGES) == 3 and eels.tune_get(eels.TUNE_TILE_ORDER) == 1
+    finally:
+        autotune.set_knobs(autotune.DEFAULTS)

@@ -131,14 +131,27 @@ def test_autotuner_caches_a_valid_setting(tmp_path, monkeypatch):
     plan = eels.Plan(p, precision="bf16_split")
     V, H = eels.device_inputs(p)
     best, times = autotune.tune(plan, V, H, reps=1)
-    assert len(times) == len(autotune.candidates(plan)) and best in autotune.candidates(plan)
+    pcs, lcs = autotune.plan_candidates(plan), autotune.candidates(plan)
+    assert len(pcs) == 4 and len(times) == len(pcs) + len(lcs) - 1
+    assert {k: best[k] for k in autotune.PLAN_KNOBS} in pcs
+    assert {k: best[k] for k in autotune.KNOBS} in lcs
     assert autotune.load_cache()[autotune.key_of(plan)] == best
-    assert autotune.apply(plan) == best
-    ws = plan.alloc_workspace()
-    out = torch.empty(plan.n_probes, dtype=torch.float64, device="cuda")
-    plan.execute(V, H, out, ws)
+    assert autotune.plan_knobs(plan) == {k: best[k] for k in autotune.PLAN_KNOBS}
+    assert autotune.apply(plan) == {k: best[k] for k in autotune.KNOBS}
+    tp = autotune.tuned_plan(plan)
+    ws = tp.alloc_workspace()
+    out = torch.empty(tp.n_probes, dtype=torch.float64, device="cuda")
+    tp.execute(V, H, out, ws)
     autotune.set_knobs(autotune.DEFAULTS)
-    assert metrics.rel_l2(out.cpu().numpy(), prism.prism_map(p)) < 1e-3
+    ref = prism.prism_map(p)
+    assert metrics.rel_l2(out.cpu().numpy(), ref) < 1e-3
+    # every macro-tile shape gives the map to the same bar
+    for pc in pcs:
+        autotune.set_knobs(pc)
+        q = plan.replan()
+        autotune.set_knobs(autotune.PLAN_DEFAULTS)
+        q.execute(V, H, out, q.alloc_workspace())
+        assert metrics.rel_l2(out.cpu().numpy(), ref) < 1e-3, pc
 
 
 @pytest.mark.parametrize("prec,detsum", [("fp32", "auto"), ("bf16_split", "auto"), ("bf16_split", "gram")])
