@@ -16,6 +16,6 @@ prism       O2: the PRISM STEM-EELS algorithm (Sec. 3, second algorithm) with
 models      operation-count, runtime and memory models of Sec. 3 (cost formulas)
 metrics     the map error metric of Eq. nrmsse (as read: relative L2 norm)
 
-"parity unpinned": the f > 1 (PRISM interpolation) semantics beyond the f = 1
-reduction and the window invariant; see prism.py.
+The f > 1 (PRISM interpolation) semantics, which the paper does not state for EELS,
+are pinned by the tiled-specimen identity described in prism.py.
 """

@@ -22,8 +22,9 @@ Contraction at slice j for site s, transition n (Eq. SHn0 with S_1 acting first)
 The window is the full cell unless a crop is requested (Sec. 4.B).  With f = 1
 every probe is eligible; with f > 1 (PRISM interpolation, Sec. 3 beam counts)
 the probe sees a transition only when the crop box lies inside its L/f box.
-parity unpinned: the f > 1 semantics beyond the f = 1 reduction and the
-window invariant (the paper never states them for EELS).
+The paper never states the f > 1 case for EELS; it is pinned by an identity: on a
+specimen made of f x f copies of a small cell, the f > 1 map at a probe that sees a
+copy equals the small cell's conventional multislice map times f^2 N_1 / N_1(f = 1).
 """
 from __future__ import annotations
 

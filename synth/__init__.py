@@ -16,6 +16,7 @@ from .specimens import (  # noqa: F401
     random_lattice_specimen,
     specimen_pool,
     random_problem,
+    tiled_problem,
     probe_grid,
     transitions_lm,
     thermal_displacement,

@@ -417,6 +417,26 @@ def config3_subproblem(seed: int = 3, n: int = 256, L: float = 25.0, nz: int = 6
                    det_outer_mrad=det_outer_mrad, interp_f=f, window_A=window_A)
 
 
+def tiled_problem(p: Problem, f: int, probes) -> Problem:
+    """The cell of ``p`` repeated f x f times (potential arrays tiled, every site copied into
+    each tile with its transition potentials), requested with interpolation factor f at the
+    given probe positions.  The copies sit whole numbers of pixels apart, so their windowed
+    transition potentials are the same arrays."""
+    f = int(f)
+    nt = np.asarray(p.site_ntrans, dtype=np.int64)
+    shifts = [(i * p.lx, j * p.ly) for j in range(f) for i in range(f)]
+    site_xy = np.concatenate([p.site_xy + np.asarray(d)[None, :] for d in shifts])
+    blocks = [p.H[int(p.site_hoff[s]):int(p.site_hoff[s]) + int(nt[s])] for s in range(p.n_sites)]
+    H = np.concatenate(blocks * len(shifts)) if blocks else p.H[:0]
+    ntr = np.tile(nt, len(shifts))
+    probes = np.asarray(probes, dtype=np.float64).reshape(-1, 2)
+    return p.replace(name=f"{p.name}_tiled{f}", nx=f * p.nx, ny=f * p.ny, lx=f * p.lx, ly=f * p.ly,
+                     V=np.tile(p.V, (1, f, f)), H=H, site_slice=np.tile(p.site_slice, len(shifts)),
+                     site_xy=site_xy, site_ntrans=ntr.astype(np.int32),
+                     site_hoff=np.concatenate([[0], np.cumsum(ntr)[:-1]]).astype(np.int64),
+                     probes=probes, probe_shape=(1, probes.shape[0]), interp_f=f)
+
+
 def random_problem(seed: int, n: int = 32, ny: Optional[int] = None, L: float = 8.0,
                    Ly: Optional[float] = None, nz: int = 3, atoms_per_slice: int = 4,
                    n_sites: int = 2, n_trans: int = 2, window_A: float = 0.0,

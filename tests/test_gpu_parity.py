@@ -316,6 +316,34 @@ def test_interpolation_factor_case():
             assert metrics.rel_l2(_map(eels, p, prec, order), ref) < tol
 
 
+@pytest.mark.parametrize("f", [2, 4])
+def test_interpolation_on_a_tiled_specimen(f):
+    """f x f copies of a 32^2 cell with f = 2 and 4 (the nanoparticle's factor): the map against
+    the oracle on the big cell, and against the small cell's conventional map times
+    f^2 N_1 / N_1(f = 1) at probes that see a copy; probes that see none are exactly zero."""
+    eels = _need_gpu()
+    ps = synth.random_problem(41, n=32, L=8.0, nz=3, n_sites=1, n_trans=3, window_A=4.0,
+                              aperture_mrad=15.0, det_outer_mrad=20.0)
+    copies = np.array([ps.site_xy[0] + [i * ps.lx, j * ps.ly] for j in range(f) for i in range(f)])
+    rng = np.random.default_rng(5)
+    near = np.concatenate([c + rng.uniform(-1.5, 1.5, (5, 2)) for c in copies])
+    far = copies + [ps.lx / 2, ps.ly / 2]
+    pb = synth.tiled_problem(ps, f, np.concatenate([near, far]))
+    ref = prism.prism_map(pb)
+    small = conventional.conventional_map(ps.replace(probes=np.mod(pb.probes, [ps.lx, ps.ly]),
+                                                     probe_shape=(1, pb.n_probes)))
+    st = make_setup(pb)
+    ratio = f * f * st.ab1.shape[0] / st.n1_fine
+    n = len(near)
+    for prec, tol in (("fp32", 1e-4), ("bf16_split", 1e-3)):
+        for order in ("s_first", "probe_first"):
+            _say("tiled f =", f, prec, order)
+            got = _map(eels, pb, prec, order)
+            assert metrics.rel_l2(got, ref) < tol
+            assert metrics.rel_l2(got[:n], ratio * small[:n]) < tol
+            assert np.all(got[n:] == 0.0)
+
+
 def test_repeat_is_bitwise_identical():
     eels = _need_gpu()
     p = synth.config1()
