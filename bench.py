@@ -396,41 +396,59 @@ def bench_nanoparticle(args):
     torch.cuda.empty_cache()
     phases = {k: round(v["ms"] / args.steps, 1) for k, v in phase_tot.items()}
 
-    # dominant kernel: the second contraction GEMM, A_n = S_2w (H_n Psi), 8 N_2 K n_t P_s
-    # useful flops per site; with one transition count for every site its share of the
-    # plan's flops is N_2 n_t / (N_1 + N_2 n_t) (the first product is 8 P_s K N_1)
+    # contraction kernels.  The plan's flop count is the per-transition form's,
+    # sum over sites of 8 P_s K (N_1 + N_2 n_t), which gives the eligible probe-site pairs.
+    # Per-transition form: the first product Psi = C S_1w (8 P_s K N_1 useful flops per site)
+    # and the second A_n = (S_2w H_n) Psi (8 N_2 K n_t P_s).  Window-Gram form: the same first
+    # product, the Gram GEMM M = S_2w^H S_2w (8 N_2 K (K + 1) / 2, the Hermitian half) and
+    # G Psi (8 P_s K^2).  The roofline is that of the kernel with the most time.
     nt = set(p.site_ntrans.tolist())
-    assert len(nt) == 1, "the GEMM-2 flop split assumes one transition count"
+    assert len(nt) == 1, "the flop split assumes one transition count"
     nt = float(nt.pop())
     N1, N2, K = info["n_beams_in"], info["n_beams_out"], info["k_pixels"]
-    g2_flops = info["gemm_flops"] * N2 * nt / (N1 + N2 * nt)
-    g1_flops = info["gemm_flops"] - g2_flops
+    pairs = info["gemm_flops"] / (8.0 * K * (N1 + N2 * nt))
     split = args.precision != "fp32"
     exec_factor = 3.0 if split else 1.0
-    g2 = phase_tot["gemm2"]
-    n_launch = g2["count"] / args.steps
-    avg_ms = g2["ms"] / max(g2["count"], 1)
-    per_launch = g2_flops / n_launch
-    achieved = exec_factor * per_launch / (avg_ms * 1e-3) / 1e12
     peak = PEAK_BF16_TFLOPS if split else PEAK_FP32_TFLOPS
+    wgram = phase_tot.get("gram", {"count": 0})["count"] > 0
+    kern = {"gemm1": ("first product Psi = C S_1w (k_cgemm_sc, store epilogue)", 8.0 * K * N1 * pairs,
+                      "gemm1_traffic_bytes_per_site")}
+    if wgram:
+        kern["gemm2"] = ("G Psi product of the window-Gram form (k_cgemm_sc, complex64 store)", 8.0 * K * K * pairs,
+                         "gpsi_traffic_bytes_per_site")
+        kern["gram"] = ("Gram GEMM M = S_2w^H S_2w of the window-Gram form (k_cgemm_sc, Gram tiles)",
+                        8.0 * N2 * K * (K + 1) / 2.0 * p.n_sites, "gram_traffic_bytes_per_site")
+    else:
+        kern["gemm2"] = ("second product (S_2w H_n) Psi (k_cgemm_sc, norm epilogue)" if split
+                         else "second product (k_cgemm, norm epilogue)", 8.0 * N2 * K * nt * pairs,
+                         "gemm2_traffic_bytes_per_site")
+    cv = counter_values("k_cgemm_sc__nanoparticle_traffic_pmc.md") if split else {}
+    contraction = {}
+    for ph, (what, fl, _) in kern.items():
+        t = phase_tot[ph]
+        contraction[ph] = {"kernel": what, "ms": round(t["ms"] / args.steps, 1),
+                           "useful_complex_tflops": round(fl * args.steps / (t["ms"] * 1e-3) / 1e12, 1),
+                           "executed_frac": round(exec_factor * fl * args.steps / (t["ms"] * 1e-3) / 1e12 / peak, 4)}
+    dom = max(kern, key=lambda k: phase_tot[k]["ms"])
+    what, dom_flops, ckey = kern[dom]
+    g = phase_tot[dom]
+    n_launch = g["count"] / args.steps
+    avg_ms = g["ms"] / max(g["count"], 1)
+    per_launch = dom_flops / n_launch
+    achieved = exec_factor * per_launch / (avg_ms * 1e-3) / 1e12
     # counter bytes per site of this kernel (profiling sample: the most populated slice, same
     # per-site shapes) times the full map's sites per launch
-    cv = counter_values("k_cgemm_sc__nanoparticle_traffic_pmc.md") if split else {}
-    traffic = (cv["gemm2_traffic_bytes_per_site"] * p.n_sites / n_launch
-               if "gemm2_traffic_bytes_per_site" in cv else None)
+    traffic = cv[ckey] * p.n_sites / n_launch if ckey in cv else None
     roofline = {
-        "bound": "mfma", "kernel": ("k_cgemm_sc, norm epilogue (second contraction GEMM)" if split
-                                    else "k_cgemm, norm epilogue"),
+        "bound": "mfma", "kernel": what,
         "achieved": round(achieved, 1), "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
         "traffic": traffic, "avg_launch_ms": round(avg_ms, 3), "launches_per_step": n_launch,
         "algorithmic_flops_per_launch": exec_factor * per_launch,
         "useful_complex_tflops": round(per_launch / (avg_ms * 1e-3) / 1e12, 1),
         "flop_definition": ("3 BF16 MFMA products per complex multiply-add of the split algorithm, 8 real flops "
-                            "each; useful = 8 M N K complex" if split else "8 M N K"),
+                            "each; useful = 8 M N K complex (Gram GEMM: its Hermitian half)" if split
+                            else "8 M N K"),
     }
-    g1 = phase_tot["gemm1"]
-    gemm1 = {"useful_complex_tflops": round(g1_flops * args.steps / (g1["ms"] * 1e-3) / 1e12, 1),
-             "executed_frac": round(exec_factor * g1_flops * args.steps / (g1["ms"] * 1e-3) / 1e12 / peak, 4)}
     nlx = info["n_live_x"]
     cap_bytes = 8.0 * p.n_sites * K * (N1 + N2)
     sweep_bytes = info["sweep_bytes"] + cap_bytes
@@ -457,7 +475,7 @@ def bench_nanoparticle(args):
     ph32 = eels.timing_read()
     eels.timing_enable(0)
     del ws32
-    contract_ms = sum(ph32[k]["ms"] for k in ("producer", "gemm1", "gemm2", "reduce"))
+    contract_ms = sum(ph32[k]["ms"] for k in ("producer", "gemm1", "gemm2", "reduce", "gram"))
     scale = info["gemm_flops"] / i32["gemm_flops"]
     est_ms = phases["setup"] + phases["sweep"] + contract_ms * scale
     fp32 = {"value": p.n_probes / (est_ms * 1e-3), "ms_per_step": round(est_ms, 1),
@@ -484,8 +502,10 @@ def bench_nanoparticle(args):
                    "interp_f": p.interp_f, "slice_groups": info["n_groups"], "batches": info["n_batches"],
                    "workspace_GB": round(info["workspace_bytes"] / 1e9, 1),
                    "precision": args.precision + " (hi+lo products, FP32 accumulate, FP64 map)"
-                   if split else "fp32", "contraction": "cropped windows, order P"},
-        "roofline": roofline, "gemm1": gemm1, "roofline_fft": roofline_fft, "phases_ms": phases, "fp32": fp32,
+                   if split else "fp32",
+                   "contraction": "cropped windows, order P" + (", window-Gram detector sum" if wgram else "")},
+        "roofline": roofline, "contraction_kernels": contraction, "roofline_fft": roofline_fft,
+        "phases_ms": phases, "fp32": fp32,
         "split_over_fp32": round(value / fp32["value"], 2),
         "map_sum": float(np.sum(gpu_map)),
     }
@@ -762,7 +782,7 @@ def main():
         torch.cuda.synchronize()
         ph32 = eels.timing_read()
         eels.timing_enable(0)
-        contract_ms = sum(ph32[k]["ms"] for k in ("producer", "gemm1", "gemm2", "reduce"))
+        contract_ms = sum(ph32[k]["ms"] for k in ("producer", "gemm1", "gemm2", "reduce", "gram"))
         scale = info["gemm_flops"] / i32["gemm_flops"]
         est_ms = phases["setup"] + phases["sweep"] + contract_ms * scale
         g1_32 = ph32["gemm1"]

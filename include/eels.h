@@ -291,8 +291,8 @@ eels_status eels_debug_cgemm(int precision, int m, int n, int k, const void* d_A
                              const void* d_B, int ldb, void* d_C, int ldc, double* d_norm2,
                              void* d_work, void* stream);
 
-/* Process-wide kernel tuning knobs, read at launch time (keys 3, 4 and 5: at plan time; the
- * autotuner sets them).
+/* Process-wide kernel tuning knobs, read at launch time (keys 3 to 6: at plan time; the
+ * autotuner sets keys 0, 1, 4 and 5).
  * key 0: LDS pipeline of the split-precision GEMM: 2 (two stages of 16-complex tiles, two
  *        workgroups per CU, default), 3 (three such stages, one workgroup per CU), 4 or 5
  *        (four or five stages of 8-complex tiles, two workgroups per CU).
@@ -310,6 +310,13 @@ eels_status eels_debug_cgemm(int precision, int m, int n, int k, const void* d_A
  * key 5: tiles of the second contraction GEMM in split precision with the per-probe
  *        detector sum (not the Gram form): 1 (default) 256 x 128 tiles of 8 waves; 0
  *        128 x 128 tiles of 4 waves.
+ * key 6: detector sum of order P in split precision with cropped windows (Sec. 3 second
+ *        algorithm, Eq. SHn0): 1 the window-Gram form.  Per site, M = S_2w^H S_2w over the
+ *        detector beams (K x K window pixels, one Gram GEMM for all transitions), G = M o
+ *        sum_t conj(H_t) H_t^T, and I(R) = f^2 Psi_R^H G Psi_R (one GEMM G Psi and a
+ *        per-probe dot product) instead of n_t products (S_2w o H_t) Psi.  Used when the
+ *        window has at most 4096 pixels.  1 (default) this form; 0 the per-transition
+ *        products.  A fused batch (eels_batch_create) takes plans made with 0.
  * Returns EELS_ERR_INVALID_ARG for an unknown key or an out-of-range value. */
 eels_status eels_tune_set(int key, int value);
 int eels_tune_get(int key);
@@ -324,10 +331,11 @@ enum {
     EELS_PHASE_SWEEP = 1,     /* row and column passes of both sweeps (with captures)      */
     EELS_PHASE_PRODUCER = 2,  /* band FFT / H-multiply producers                           */
     EELS_PHASE_GEMM1 = 3,     /* first contraction GEMM of each batch                      */
-    EELS_PHASE_GEMM2 = 4,     /* second GEMM (detector |.|^2 epilogue)                     */
+    EELS_PHASE_GEMM2 = 4,     /* second GEMM (detector |.|^2 epilogue; window Gram: G Psi)  */
     EELS_PHASE_REDUCE = 5,    /* FP64 per-probe reduction                                  */
     EELS_PHASE_IMAGES = 6,    /* elastic companion images (exit capture excluded)          */
-    EELS_PHASES = 7
+    EELS_PHASE_GRAM = 7,      /* window-Gram form: Gram GEMM of each site's S_2 window     */
+    EELS_PHASES = 8
 };
 eels_status eels_timing_enable(int capacity);
 eels_status eels_timing_read(double* ms, int* counts);

@@ -33,7 +33,14 @@ class Batch:
         self.device = device
         self.problems = list(problems)
         self.fused = fused
-        self.plans = [eels.Plan(p, precision=precision, resident_s=fused) for p in self.problems]
+        # the fused contraction groups the per-transition products of all specimens, so its
+        # plans use that form of the detector sum (tuning key 6 = 0)
+        keep = eels.tune_get(eels.TUNE_WINDOW_GRAM)
+        eels.tune_set(eels.TUNE_WINDOW_GRAM, 0 if fused else keep)
+        try:
+            self.plans = [eels.Plan(p, precision=precision, resident_s=fused) for p in self.problems]
+        finally:
+            eels.tune_set(eels.TUNE_WINDOW_GRAM, keep)
         if tuned:
             self.plans = [autotune.tuned_plan(pl) for pl in self.plans]
         self.tuned = tuned

@@ -33,7 +33,7 @@ namespace eels {
 static thread_local std::string g_err;
 void set_error(const std::string& m) { g_err = m; }
 
-static std::atomic<int> g_tune[TUNE_COUNT] = {{2}, {2}, {0}, {1}, {1}, {1}, {0}, {0}};
+static std::atomic<int> g_tune[TUNE_COUNT] = {{2}, {2}, {0}, {1}, {1}, {1}, {1}, {0}};
 int tune_get(int key) { return (key >= 0 && key < TUNE_COUNT) ? g_tune[key].load() : 0; }
 
 // Diagnostic phase timing (eels_timing_enable / eels_timing_read).
@@ -293,7 +293,51 @@ void producers_before_gemm1(const Plan& p, const Dev& d, const float2* dH, const
 // ... and between the two GEMMs (order P: the H-multiplied operand from Psi or S_2w).
 void producers_after_gemm1(const Plan& p, const Dev& d, const float2* dH, const Batch& b, hipStream_t st) {
     const bool split = p.precision != EELS_FP32;
+    if (p.wgram) {
+        // window-Gram form: each site's S_2 window [N_2][K] becomes SC rows [K][N_2p]
+        TimeScope ts(EELS_PHASE_PRODUCER, st);
+        for (int k = 0; k < b.job_count; ++k) {
+            const Job& jb = p.jobs[b.job_begin + k];
+            launch_window_t_sc(d.mid2 + jb.s2t_off, d.w2 + jb.w_off, p.Kpad, p.N2, p.K, p.N2p, p.precision, st);
+        }
+        return;
+    }
     if (!p.gram && p.order != EELS_ORDER_S_FIRST && (split || p.recip)) run_jobs(p, d, dH, b, b.slice, st);
+}
+
+// Window-Gram form of the second product: M = S_2w^H S_2w per site (Gram tiles), G = M o
+// sum_t conj(H_t) H_t^T, Y^T = Psi G^T, and the per-probe dot products Re(Psi^H Y).
+void wgram_contract(const Plan& p, const Dev& d, const float2* dH, const Batch& b, hipStream_t st) {
+    const int nst = tune_get(TUNE_SC_STAGES);
+    // G's diagonal is about N_2 sum_t |H_t|^2 (unit-modulus S_2 rows): scale it by an exact power
+    // of two into the FP16 range, and the dot products back
+    const float gscale = std::ldexp(1.0f, -(int)std::ceil(std::log2((double)std::max(p.N2, 1))));
+    {
+        TimeScope ts(EELS_PHASE_GRAM, st);
+        launch_cgemm_sc(p.precision, 2, nst, d.descs + b.dm_begin, b.dm_count, b.dm_tiles, d.mid2, d.mid2, nullptr,
+                        (float*)d.mid2, d.blob, st, GEMM_BM);
+    }
+    {
+        TimeScope ts(EELS_PHASE_PRODUCER, st);
+        for (int k = 0; k < b.job_count; ++k) {
+            const Job& jb = p.jobs[b.job_begin + k];
+            launch_wgram_combine(d.mid2 + jb.g_off, d.mid2 + jb.m_off, dH + jb.h_off, jb.nt, p.K, p.Kpad, p.Kpad,
+                                 gscale, p.precision, st);
+        }
+    }
+    {
+        TimeScope ts(EELS_PHASE_GEMM2, st);
+        launch_cgemm_sc(p.precision, 3, nst, d.descs + b.dy_begin, b.dy_count, b.dy_tiles, d.mid, d.mid2, d.mid2,
+                        nullptr, d.blob, st, b.dy_rows);
+    }
+    {
+        TimeScope ts(EELS_PHASE_REDUCE, st);
+        for (int k = 0; k < b.job_count; ++k) {
+            const Job& jb = p.jobs[b.job_begin + k];
+            launch_wgram_dot(d.part + jb.part_off, d.mid + jb.psi_off, d.mid2 + jb.y_off, jb.ps, p.K, p.Kpad,
+                             1.0f / gscale, p.precision, st);
+        }
+    }
 }
 
 // The batch's partial sums into the map (direct detector sum) or into G (Gram form).
@@ -335,6 +379,11 @@ void contract(const Plan& p, const Dev& d, const float2* dH, double* map, int bi
         }
     }
     producers_after_gemm1(p, d, dH, b, st);
+    if (p.wgram) {
+        wgram_contract(p, d, dH, b, st);
+        reduce_batch(p, d, map, b, st);
+        return;
+    }
     {
         TimeScope ts(EELS_PHASE_GEMM2, st);
         if (split) {
@@ -862,6 +911,7 @@ eels_status eels_tune_set(int key, int value) {
     if (key == TUNE_GRAM_STACK && (value < 0 || value > 1)) return EELS_ERR_INVALID_ARG;
     if (key == TUNE_GEMM1_ROWS && (value < 0 || value > 1)) return EELS_ERR_INVALID_ARG;
     if (key == TUNE_GEMM2_ROWS && (value < 0 || value > 1)) return EELS_ERR_INVALID_ARG;
+    if (key == TUNE_WINDOW_GRAM && (value < 0 || value > 1)) return EELS_ERR_INVALID_ARG;
     g_tune[key].store(value);
     return EELS_OK;
 }
@@ -963,6 +1013,10 @@ eels_status eels_batch_create(eels_batch** out, const eels_plan* const* plans, i
             }
             if (!p.resident || p.groups.size() > 1) {
                 set_error("a fused batch needs plans with resident_s (one slice group)");
+                return EELS_ERR_INVALID_ARG;
+            }
+            if (p.wgram) {
+                set_error("a fused batch takes plans of the per-transition detector sum (tuning key 6 = 0)");
                 return EELS_ERR_INVALID_ARG;
             }
             if ((ws_offsets[i] & 255) || ws_offsets[i] + p.ws_bytes > arena_bytes) {

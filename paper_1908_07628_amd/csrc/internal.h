@@ -44,7 +44,7 @@ static_assert(sizeof(GemmDesc) == 144, "GemmDesc layout");
 // Process-wide tuning knobs (set by eels_tune_set; read at launch time).
 enum TuneKey {
     TUNE_SC_STAGES = 0, TUNE_TILE_ORDER = 1, TUNE_SC_SCHED = 2, TUNE_GRAM_STACK = 3, TUNE_GEMM1_ROWS = 4,
-    TUNE_GEMM2_ROWS = 5, TUNE_COUNT = 8
+    TUNE_GEMM2_ROWS = 5, TUNE_WINDOW_GRAM = 6, TUNE_COUNT = 8
 };
 int tune_get(int key);
 
@@ -60,6 +60,10 @@ struct Batch {
     int64_t red_ent;                    // int offset of the CSR entries (pairs: desc, column)
     int64_t n_entries;
     int n_parts;                        // Gram form: FP32 partials of Z^H Z written by the second GEMM
+    // window-Gram form (order P, split, cropped windows): per site the Gram GEMM of the S_2
+    // window (dm) and the product of G with Psi (dy); the d2 range then only drives the reduction
+    int dm_begin = 0, dm_count = 0, dm_tiles = 0;
+    int dy_begin = 0, dy_count = 0, dy_tiles = 0, dy_rows = 128;
 };
 
 // Producer job: write the H-multiplied operand of one site into mid2, either in the band
@@ -71,6 +75,11 @@ struct Job {
     int Ni, nt;
     int64_t h_off;      // complex offset of the site's first transition potential
     int64_t dst_off;    // complex offset in mid2
+    // window-Gram form: complex offsets in mid2 of the site's S_2 window transpose [K][N_2p],
+    // the FP32 complex Gram tiles M [K][Kpad], G [K][Kpad] and Y^T [P_s][Kpad]; Psi in mid;
+    // the site's first float in part; eligible probes P_s
+    int64_t s2t_off = 0, m_off = 0, g_off = 0, y_off = 0, psi_off = 0, part_off = 0;
+    int ps = 0;
 };
 
 struct SliceInfo {
@@ -120,6 +129,8 @@ struct Plan {
     bool gram;                                  // detector sum in the Gram form (order S, f = 1)
     bool hs2 = false;                           // order P, split, cropped windows: H multiplies the S_2
                                                 // windows (N_2 rows) and Psi is the shared operand
+    bool wgram = false;                         // order P, split, cropped windows: the detector sum as
+                                                // Psi^H (M o sum_t conj(H_t) H_t^T) Psi, M = S_2w^H S_2w
     bool s1_inverse = false;                    // S_1 retreated with the inverse multislice
     int n_img = 0;                              // elastic companion images
     std::vector<double> img_in, img_out;        // their ring angles (rad; out < 0: band limit)

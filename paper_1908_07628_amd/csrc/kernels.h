@@ -100,6 +100,13 @@ void launch_cgemm_sc(int precision, int epi, int nstage, const GemmDesc* d_descs
 // beams n_beams .. ldo-1 zero; ldo a multiple of 4, dst 32-byte aligned)
 void launch_window_t_sc(void* dst, const float2* src, int64_t wstride, int n_beams, int K, int ldo, int prec,
                         hipStream_t st);
+// Window-Gram detector sum: G = gscale M o sum_t conj(H_t) H_t^T as SC rows [K][ldg] from
+// the FP32 complex Gram tiles M [K][ldm] (upper 128-tiles valid); and out[i] = oscale sum_r
+// Re(conj(Psi)Y) over the rows of Psi (SC) and Y (complex64), both ld complex apart.
+void launch_wgram_combine(void* G, const float2* M, const float2* H, int nt, int K, int ldm, int ldg, float gscale,
+                          int prec, hipStream_t st);
+void launch_wgram_dot(float* out, const void* psi, const float2* Y, int rows, int K, int ld, float oscale, int prec,
+                      hipStream_t st);
 // complex64 [rows][ld] -> SC (columns >= K written as zero)
 void launch_to_sc(void* dst, const float2* src, int64_t rows, int K, int ld, int prec, hipStream_t st);
 // SC -> complex64 of n contiguous complex slots

@@ -744,6 +744,147 @@ void launch_window_t_sc(void* dst, const float2* src, int64_t wstride, int n_bea
                            n_beams, K, ldo);
 }
 
+// Window-Gram form of the detector sum: G = gscale M o S with S[r][c] = sum_t conj(H_t[r]) H_t[c]
+// (H_t the site's transition potentials on its K window pixels), written as SC rows
+// [K][ldg] (columns K .. ldg-1 zero).  M holds FP32 complex Gram tiles [K][ldm] of the
+// 128 x 128 grid with tile column >= tile row only; the others are the conjugate transpose.
+// A block forms a 64 x 64 tile, both of whose 128-tiles are on one side of the diagonal,
+// so it reads either M's tile or the transposed tile (through LDS), and stages the H values
+// of its rows and columns 16 transitions at a time.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_wgram_combine(uint32_t* __restrict__ dst, const float2* __restrict__ Mg,
+                                                       const float2* __restrict__ H, int nt, int K, int ldm,
+                                                       int ldg, float gscale) {
+    __shared__ float2 tile[64][65];
+    __shared__ float2 hr[16][64], hc[16][64];
+    const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const bool mirror = (r0 >> 7) > (c0 >> 7);
+    for (int a = ty; a < 64; a += 4) {
+        if (!mirror) {
+            const int r = r0 + a, c = c0 + tx;
+            tile[a][tx] = (r < K && c < K) ? Mg[(int64_t)r * ldm + c] : make_float2(0.f, 0.f);
+        } else {   // M(r, c) = conj(M(c, r)): read row c0 + a of M along r
+            const int c = c0 + a, r = r0 + tx;
+            const float2 v = (r < K && c < K) ? Mg[(int64_t)c * ldm + r] : make_float2(0.f, 0.f);
+            tile[tx][a] = make_float2(v.x, -v.y);
+        }
+    }
+    // each thread owns 4 rows x one 4-column group: rows ty + 4 j' (j' = 0..15 over 4 passes)
+    float sr[4][4], si[4][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) { sr[j][e] = 0.f; si[j][e] = 0.f; }
+    const int g = threadIdx.x & 15, rb = threadIdx.x >> 4;   // column group, row base 0..15
+    for (int t0 = 0; t0 < nt; t0 += 16) {
+        __syncthreads();
+        for (int w = threadIdx.x; w < 16 * 64; w += 256) {
+            const int tt = w >> 6, x = w & 63;
+            const bool ok = t0 + tt < nt;
+            hr[tt][x] = (ok && r0 + x < K) ? H[(int64_t)(t0 + tt) * K + r0 + x] : make_float2(0.f, 0.f);
+            hc[tt][x] = (ok && c0 + x < K) ? H[(int64_t)(t0 + tt) * K + c0 + x] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+        const int tn = min(16, nt - t0);
+        for (int tt = 0; tt < tn; ++tt) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float2 a = hr[tt][rb + 16 * j];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float2 b = hc[tt][4 * g + e];
+                    sr[j][e] += a.x * b.x + a.y * b.y;     // conj(a) b
+                    si[j][e] += a.x * b.y - a.y * b.x;
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int y = rb + 16 * j, r = r0 + y, c = c0 + 4 * g;
+        if (r >= K || c >= ldg) continue;
+        u32x4 hi, lo;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float2 m = tile[y][4 * g + e];
+            float vr = gscale * (m.x * sr[j][e] - m.y * si[j][e]);
+            float vi = gscale * (m.x * si[j][e] + m.y * sr[j][e]);
+            if (c + e >= K) { vr = 0.f; vi = 0.f; }
+            uint32_t h, l;
+            split2<PREC>(vr, vi, h, l);
+            hi[e] = h;
+            lo[e] = l;
+        }
+        uint32_t* o = dst + (((int64_t)r * ldg + c) >> 2) * 8;
+        *(u32x4*)o = hi;
+        *(u32x4*)(o + 4) = lo;
+    }
+}
+
+// Window-Gram form: out[i] = oscale sum_r Re(conj(Psi[i][r]) Y[i][r]) over the K window pixels,
+// Psi in SC rows of ld complex, Y complex64 rows of ld; one wave per probe row.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_wgram_dot(float* __restrict__ out, const uint32_t* __restrict__ psi,
+                                                   const float2* __restrict__ Y, int rows, int K, int ld,
+                                                   float oscale) {
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= rows) return;
+    const uint32_t* prow = psi + ((int64_t)i * ld >> 2) * 8;
+    const float2* yrow = Y + (int64_t)i * ld;
+    float acc = 0.f;
+    for (int gi = lane; gi * 4 < K; gi += 64) {
+        const u32x4 h = *(const u32x4*)(prow + 8 * gi);
+        const u32x4 l = *(const u32x4*)(prow + 8 * gi + 4);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int r = 4 * gi + e;
+            if (r >= K) break;
+            float pr, pi;
+            if constexpr (PREC == EELS_BF16_SPLIT) {
+                pr = __uint_as_float(h[e] << 16) + __uint_as_float(l[e] << 16);
+                pi = __uint_as_float(h[e] & 0xFFFF0000u) + __uint_as_float(l[e] & 0xFFFF0000u);
+            } else {
+                pr = (float)__builtin_bit_cast(_Float16, (uint16_t)(h[e] & 0xFFFF)) +
+                     (float)__builtin_bit_cast(_Float16, (uint16_t)(l[e] & 0xFFFF));
+                pi = (float)__builtin_bit_cast(_Float16, (uint16_t)(h[e] >> 16)) +
+                     (float)__builtin_bit_cast(_Float16, (uint16_t)(l[e] >> 16));
+            }
+            const float2 y = yrow[r];
+            acc += pr * y.x + pi * y.y;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) out[i] = oscale * acc;
+}
+
+void launch_wgram_combine(void* G, const float2* M, const float2* H, int nt, int K, int ldm, int ldg, float gscale,
+                          int prec, hipStream_t st) {
+    if (K <= 0) return;
+    dim3 grid((unsigned)ceil_div(ldg, 64), (unsigned)ceil_div(K, 64));
+    if (prec == EELS_BF16_SPLIT)
+        hipLaunchKernelGGL(k_wgram_combine<EELS_BF16_SPLIT>, grid, dim3(256), 0, st, (uint32_t*)G, M, H, nt, K, ldm,
+                           ldg, gscale);
+    else
+        hipLaunchKernelGGL(k_wgram_combine<EELS_FP16_SPLIT>, grid, dim3(256), 0, st, (uint32_t*)G, M, H, nt, K, ldm,
+                           ldg, gscale);
+}
+
+void launch_wgram_dot(float* out, const void* psi, const float2* Y, int rows, int K, int ld, float oscale, int prec,
+                      hipStream_t st) {
+    if (rows <= 0) return;
+    dim3 grid((unsigned)ceil_div(rows, 4));
+    if (prec == EELS_BF16_SPLIT)
+        hipLaunchKernelGGL(k_wgram_dot<EELS_BF16_SPLIT>, grid, dim3(256), 0, st, out, (const uint32_t*)psi, Y, rows,
+                           K, ld, oscale);
+    else
+        hipLaunchKernelGGL(k_wgram_dot<EELS_FP16_SPLIT>, grid, dim3(256), 0, st, out, (const uint32_t*)psi, Y, rows,
+                           K, ld, oscale);
+}
+
 template <int PREC, int KIND, int EPI>
 static void go(const GemmDesc* dd, int nd, int tiles, const float2* A, const float2* B, const float2* H, float2* C,
                float* P, const int* idx, hipStream_t st) {

@@ -278,6 +278,9 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     // writes n_t x N_2 window rows instead of n_t x P_s probe rows (N_2 < P_s on large scans)
     // and reads the S_2 windows captured in complex64
     p.hs2 = split && !orderS && !p.recip;
+    // window-Gram form (plan-time knob 6): I(R) = f^2 Psi_R^H (M o sum_t conj(H_t) H_t^T) Psi_R
+    // with M = S_2w^H S_2w, one Gram GEMM per site instead of n_t products with N_2 rows
+    p.wgram = p.hs2 && !p.full_window && tune_get(TUNE_WINDOW_GRAM) != 0 && p.Kpad <= 4096;
     p.w2_sc = (split && !p.hs2) ? p.precision : 0;
     p.mid2_sc = split ? p.precision : 0;
 
@@ -304,15 +307,21 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
         return orderS ? (int64_t)nt * p.N2 * p.N1pad : (int64_t)n_elig(s) * p.Kpad;
     };
     auto site_ni = [&](int s) -> int64_t { return orderS ? p.N1 : (p.hs2 ? p.N2 : n_elig(s)); };
+    // window-Gram layout of a site's mid2 region (complex units): S_2w transposed [K][N_2p],
+    // M [K][Kpad] (FP32 complex), G [K][Kpad], Y^T [P_s][Kpad]
+    const int64_t wg_m = (int64_t)p.K * p.N2p, wg_g = wg_m + (int64_t)p.K * p.Kpad,
+                  wg_y = wg_g + (int64_t)p.K * p.Kpad;
     auto site_mid2 = [&](int s) -> int64_t {
         if (!p.recip && !split) return 0;
-        int64_t m2 = (int64_t)p.sites[s].n_trans * site_ni(s) * Kcpad;
+        int64_t m2 = p.wgram ? wg_y + (int64_t)n_elig(s) * p.Kpad
+                             : (int64_t)p.sites[s].n_trans * site_ni(s) * Kcpad;
         // order P, split: the site's S_1 window is first transposed here for the product C S_1w
         if (split && !orderS) m2 = std::max(m2, (int64_t)p.K * p.N1pad);
         return m2;
     };
     auto site_part = [&](int s) -> int64_t {
         if (p.gram) return 2 * (int64_t)p.sites[s].n_trans * p.N1pad * p.N1pad;   // FP32 partials of Z_t^H Z_t
+        if (p.wgram) return n_elig(s);                                            // one per eligible probe
         int nt = p.sites[s].n_trans;
         int64_t tm = ceil_div(p.N2, GEMM_BM);
         return tm * nt * (int64_t)n_elig(s);
@@ -536,6 +545,14 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
                 jb.nt = p.sites[s].n_trans;
                 jb.h_off = p.sites[s].h_offset * p.K;
                 jb.dst_off = site_m2off[si];
+                if (p.wgram) {
+                    jb.s2t_off = site_m2off[si];
+                    jb.m_off = site_m2off[si] + wg_m;
+                    jb.g_off = site_m2off[si] + wg_g;
+                    jb.y_off = site_m2off[si] + wg_y;
+                    jb.psi_off = site_moff[si];
+                    jb.ps = n_elig(s);
+                }
                 p.jobs.push_back(jb);
             }
         }
@@ -635,6 +652,25 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
                 p.descs.push_back(d);
                 continue;
             }
+            if (p.wgram) {
+                // the site's per-probe results of the window-Gram form, one FP32 partial per
+                // eligible probe (this descriptor only drives the reduction)
+                d.h_off = -1; d.idx_off = -1;
+                d.M = 0; d.N_inner = Ps; d.n_t = 1; d.K = 0;
+                d.tiles_m = 1; d.tiles_n = 0; d.tile_start = tiles;
+                d.p_off = poff; d.ld_part = Ps;
+                p.jobs[bt.job_begin + si].part_off = poff;
+                poff += Ps;
+                int di = (int)p.descs.size();
+                p.descs.push_back(d);
+                if (p.f > 1)
+                    for (int i = 0; i < Ps; ++i) {
+                        int r = pl ? (*pl)[i] : i;
+                        ent[r].push_back(di);
+                        ent[r].push_back(i);
+                    }
+                continue;
+            }
             if (orderS) {
                 // A_n(q, R) = sum_k Z_s[t][q][k] C[R][k]
                 d.a_off = site_moff[si]; d.lda = p.N1pad; d.a_tstride = (int64_t)p.N2 * p.N1pad;
@@ -682,6 +718,59 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
         bt.d2_count = (int)p.descs.size() - bt.d2_begin;
         bt.d2_tiles = tiles;
         bt.d2_rows = p.gram ? GEMM_BM : rows2;
+        if (p.wgram) {
+            // M_s[r][r'] = sum_q conj(S2w[q][r]) S2w[q][r']  (upper 128-tiles, FP32 complex)
+            bt.dm_begin = (int)p.descs.size();
+            int tl = 0;
+            for (size_t si = 0; si < pb.sites.size(); ++si) {
+                const Job& jb = p.jobs[bt.job_begin + si];
+                GemmDesc d{};
+                d.a_off = jb.s2t_off; d.lda = p.N2p; d.b_off = jb.s2t_off; d.ldb = p.N2p;
+                d.h_off = -1; d.idx_off = -1;
+                d.p_off = jb.m_off; d.ldc_m = p.Kpad; d.ldc_t = 0;
+                d.M = p.K; d.N_inner = p.K; d.n_t = 1; d.K = p.N2;
+                d.tiles_m = (int)ceil_div(p.K, GEMM_BM);
+                d.tiles_n = (int)ceil_div(p.K, GEMM_BN);
+                d.tile_start = tl;
+                tl += d.tiles_m * d.tiles_n;
+                p.descs.push_back(d);
+            }
+            bt.dm_count = (int)p.descs.size() - bt.dm_begin;
+            bt.dm_tiles = tl;
+            // Y_s^T[i][r] = sum_r' Psi_s[i][r'] G_s[r][r']  (complex64 store)
+            bt.dy_begin = (int)p.descs.size();
+            tl = 0;
+            for (size_t si = 0; si < pb.sites.size(); ++si) {
+                const Job& jb = p.jobs[bt.job_begin + si];
+                GemmDesc d{};
+                d.a_off = jb.psi_off; d.lda = p.Kpad; d.b_off = jb.g_off; d.ldb = p.Kpad;
+                d.h_off = -1; d.idx_off = -1;
+                d.c_off = jb.y_off; d.ldc_m = p.Kpad; d.ldc_t = 0;
+                d.M = jb.ps; d.N_inner = p.K; d.n_t = 1; d.K = p.K;
+                d.tiles_m = (int)ceil_div(jb.ps, rows2);
+                d.tiles_n = (int)ceil_div(p.K, GEMM_BN);
+                d.tile_start = tl;
+                tl += d.tiles_m * d.tiles_n;
+                p.descs.push_back(d);
+            }
+            bt.dy_count = (int)p.descs.size() - bt.dy_begin;
+            bt.dy_tiles = tl;
+            bt.dy_rows = rows2;
+            // every operand of the form stays inside the batch's mid, mid2 and part buffers
+            const int64_t k16 = round_up(p.K, 16), n16 = round_up(p.N2, 16);
+            for (int k = 0; k < bt.job_count; ++k) {
+                const Job& jb = p.jobs[bt.job_begin + k];
+                const int64_t rows_y = std::max(jb.ps, 1) - 1;
+                const bool ok = jb.s2t_off + (int64_t)(p.K - 1) * p.N2p + n16 <= m2off &&
+                                jb.m_off + (int64_t)(p.K - 1) * p.Kpad + p.K <= m2off &&
+                                jb.g_off + (int64_t)(p.K - 1) * p.Kpad + k16 <= m2off &&
+                                jb.y_off + rows_y * p.Kpad + k16 <= m2off &&
+                                jb.psi_off + rows_y * p.Kpad + k16 <= moff && jb.part_off + jb.ps <= poff &&
+                                n16 <= p.N2p && k16 <= p.Kpad && m2off <= p.mid2_elems && moff <= p.mid_elems &&
+                                poff <= p.part_elems;
+                if (!ok) return fail(EELS_ERR_INTERNAL, "window-Gram operands leave their buffers");
+            }
+        }
         if (p.f > 1) {
             std::vector<int32_t> ptr(p.P + 1, 0), flat;
             for (int r = 0; r < p.P; ++r) {

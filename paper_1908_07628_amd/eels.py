@@ -68,7 +68,7 @@ EXPORTS = ["eels_get_version", "eels_status_string", "eels_last_error", "eels_pl
            "eels_conventional_map", "eels_batch_create", "eels_batch_table_bytes", "eels_batch_upload",
            "eels_batch_contract", "eels_batch_destroy"]
 EXEC_SKIP_UPLOAD, EXEC_SKIP_SWEEPS, EXEC_SWEEPS_ONLY = 1, 2, 4
-PHASES = ["setup", "sweep", "producer", "gemm1", "gemm2", "reduce", "images"]
+PHASES = ["setup", "sweep", "producer", "gemm1", "gemm2", "reduce", "images", "gram"]
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:
@@ -142,6 +142,7 @@ class Plan:
         means the band limit (e.g. ((0, det_outer), (60, 0)) for iBF and ADF).  s1_mode:
         "stored" (exact) or "inverse" (inverse multislice, Sec. 4.C)."""
         lib = load_library()
+        self._window_gram = tune_get(TUNE_WINDOW_GRAM)     # plan-time form of the detector sum
         self._source = (problem, dict(precision=precision, order=order, max_workspace_bytes=max_workspace_bytes,
                                       lambda_A=lambda_A, sigma=sigma, real_space=real_space, resident_s=resident_s,
                                       detector_sum=detector_sum, images=images, s1_mode=s1_mode))
@@ -185,10 +186,15 @@ class Plan:
             self._h = None
 
     def replan(self) -> "Plan":
-        """A new plan of the same request under the current plan-time knobs (tile rows, Gram
-        stacking)."""
+        """A new plan of the same request under the current plan-time tile knobs (tile rows,
+        Gram stacking) and this plan's form of the detector sum."""
         problem, kw = self._source
-        return Plan(problem, **kw)
+        keep = tune_get(TUNE_WINDOW_GRAM)
+        tune_set(TUNE_WINDOW_GRAM, self._window_gram)
+        try:
+            return Plan(problem, **kw)
+        finally:
+            tune_set(TUNE_WINDOW_GRAM, keep)
 
     @property
     def workspace_bytes(self) -> int:
@@ -377,6 +383,7 @@ TUNE_SC_SCHED = 2
 TUNE_GRAM_STACK = 3
 TUNE_GEMM1_ROWS = 4
 TUNE_GEMM2_ROWS = 5
+TUNE_WINDOW_GRAM = 6
 
 
 def tune_set(key: int, value: int):

@@ -223,11 +223,12 @@ def test_tuning_knob_ranges_and_gram_stack_plan():
     """Knob values are range-checked; the Gram form's first GEMM stacks the transitions'
     rows by default (plan-time knob 3)."""
     _lib()
-    for key, bad in ((0, 1), (0, 6), (1, 3), (2, 4), (3, 2), (3, -1), (4, 2), (5, 2), (5, -1), (9, 0)):
+    for key, bad in ((0, 1), (0, 6), (1, 3), (2, 4), (3, 2), (3, -1), (4, 2), (5, 2), (5, -1), (6, 2), (6, -1),
+                     (9, 0)):
         with pytest.raises(eels.EelsError):
             eels.tune_set(key, bad)
     assert eels.tune_get(eels.TUNE_GRAM_STACK) == 1 and eels.tune_get(eels.TUNE_GEMM1_ROWS) == 1
-    assert eels.tune_get(eels.TUNE_GEMM2_ROWS) == 1
+    assert eels.tune_get(eels.TUNE_GEMM2_ROWS) == 1 and eels.tune_get(eels.TUNE_WINDOW_GRAM) == 1
 
 
 def test_fused_batch_plan_checks():
@@ -238,6 +239,19 @@ def test_fused_batch_plan_checks():
     probs = [synth.random_problem(40 + i, n=n, L=L, nz=3, n_sites=2, n_trans=2, window_A=w, interp_f=f)
              for i, (n, L, w, f) in enumerate([(32, 8.0, 0.0, 1), (64, 12.0, 3.0, 1), (64, 16.0, 3.0, 2),
                                                 (32, 8.0, 3.0, 1)])]
+    eels.tune_set(eels.TUNE_WINDOW_GRAM, 0)     # a fused batch takes the per-transition form
+    try:
+        _fused_batch_plan_checks(probs)
+    finally:
+        eels.tune_set(eels.TUNE_WINDOW_GRAM, 1)
+    # the window-Gram form (order P, split, cropped windows) is refused
+    wg = [eels.Plan(probs[2], precision="bf16_split", order="probe_first", resident_s=True)]
+    with pytest.raises(eels.EelsError) as e:
+        eels.FusedContraction(wg, [0], (wg[0].workspace_bytes + 255) // 256 * 256)
+    assert e.value.status == 1 and "key 6" in str(e.value)
+
+
+def _fused_batch_plan_checks(probs):
     for prec in ("bf16_split", "fp16_split"):
         plans = [eels.Plan(p, precision=prec, resident_s=True) for p in probs]
         sizes = [(pl.workspace_bytes + 255) // 256 * 256 for pl in plans]

@@ -37,13 +37,15 @@ def test_config2_bf16_split_sampled_probes():
 GOLD3 = os.path.join(os.path.dirname(__file__), "golden", "config3_samples.json")
 
 
-@pytest.mark.parametrize("precision,bar", [("bf16_split", 1e-3), ("fp16_split", 1e-3), ("fp32", 1e-4)])
-def test_config3_sampled_probes(precision, bar):
+@pytest.mark.parametrize("precision,bar,wgram", [("bf16_split", 1e-3, 0), ("fp16_split", 1e-3, 0), ("fp32", 1e-4, 0),
+                                                 ("bf16_split", 1e-3, 1), ("fp16_split", 1e-3, 1)])
+def test_config3_sampled_probes(precision, bar, wgram):
     """Full-size nanoparticle geometry (1024^2, 50 slices, f = 4, 4 A crop, N_1 = N_2 = 2025)
     in the launch configuration of bench.py's nanoparticle workload (order P, memory budget
     from the free HBM), on the 1217 sites of the most populated ionised slice; sampled
     probes against the FP64 PRISM oracle (tests/golden/config3_samples.json, written by
-    make_config3_samples.py).  Probes whose L/f box holds no crop box are exactly zero."""
+    make_config3_samples.py), with the per-transition and the window-Gram detector sums.
+    Probes whose L/f box holds no crop box are exactly zero."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     if not os.path.exists(GOLD3):
@@ -58,7 +60,12 @@ def test_config3_sampled_probes(precision, bar):
     torch.cuda.empty_cache()
     free, _ = torch.cuda.mem_get_info()
     print(f"config3 slice {g['slice']} ({len(sel)} sites) generated; solving {precision}", flush=True)
-    m = eels.solve(q, precision=precision, max_workspace_bytes=int(free - (8 << 30) - (4 << 30)))
+    keep = eels.tune_get(eels.TUNE_WINDOW_GRAM)
+    try:
+        eels.tune_set(eels.TUNE_WINDOW_GRAM, wgram)     # detector sum: per transition or window Gram
+        m = eels.solve(q, precision=precision, max_workspace_bytes=int(free - (8 << 30) - (4 << 30)))
+    finally:
+        eels.tune_set(eels.TUNE_WINDOW_GRAM, keep)
     torch.cuda.empty_cache()
     ref = np.asarray(g["map"])
     got = m[g["probe_index"]]

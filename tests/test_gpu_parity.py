@@ -344,6 +344,37 @@ def test_interpolation_on_a_tiled_specimen(f):
             assert np.all(got[n:] == 0.0)
 
 
+@pytest.mark.parametrize("prec", ["bf16_split", "fp16_split"])
+def test_window_gram_form(prec):
+    """Order P with cropped windows in the window-Gram form (knob 6): per site one Gram GEMM
+    of the S_2 window, G = M o sum_t conj(H_t) H_t^T, and Re(Psi^H G Psi) per probe.  Against
+    the oracle at the split bar and against the per-transition products (f = 1, 2, 4)."""
+    eels = _need_gpu()
+    ps = synth.random_problem(41, n=32, L=8.0, nz=3, n_sites=1, n_trans=3, window_A=4.0,
+                              aperture_mrad=15.0, det_outer_mrad=20.0)
+    rng = np.random.default_rng(6)
+    cases = [("nanoparticle-like f=2", synth.config3_subproblem(n=128, L=25.0, nz=5, n_scan=6, f=2)),
+             ("random f=1 crop", synth.random_problem(12, n=64, L=12.0, nz=3, window_A=4.0, n_sites=3)),
+             ("tiled f=4", synth.tiled_problem(ps, 4, rng.uniform(0.0, 32.0, (40, 2))))]
+    for name, p in cases:
+        ref = prism.prism_map(p)
+        assert np.max(ref) > 0
+        keep = eels.tune_get(eels.TUNE_WINDOW_GRAM)
+        try:
+            eels.tune_set(eels.TUNE_WINDOW_GRAM, 1)
+            _say("window Gram", name, prec)
+            got = _map(eels, p, prec, "probe_first")
+            eels.tune_set(eels.TUNE_WINDOW_GRAM, 0)
+            direct = _map(eels, p, prec, "probe_first")
+        finally:
+            eels.tune_set(eels.TUNE_WINDOW_GRAM, keep)
+        _say("  rel-L2 vs oracle", metrics.rel_l2(got, ref), "vs direct", metrics.rel_l2(got, direct))
+        assert np.all(np.isfinite(got))
+        assert metrics.rel_l2(got, ref) < 1e-3
+        assert np.max(np.abs(got - ref)) <= 1e-3 * np.max(ref)
+        assert np.all(got[ref == 0] == 0)
+
+
 def test_repeat_is_bitwise_identical():
     eels = _need_gpu()
     p = synth.config1()
