@@ -375,6 +375,29 @@ def test_window_gram_form(prec):
         assert np.all(got[ref == 0] == 0)
 
 
+def test_window_gram_fp16_range_at_many_detector_beams():
+    """N_2 = 8093 detector beams and 9 transitions: unscaled, the window Gram matrix's
+    diagonal (about N_2 sum_t |H_t|^2, rows of S_2 of unit mean square) would reach about
+    7e4 at a site's centre pixel, above the FP16 maximum 65504.  The FP16 window-Gram map
+    (scaled by 2^-13) is finite and equals the BF16 per-transition map well within the
+    split bar."""
+    eels = _need_gpu()
+    p = synth.random_problem(7, n=256, L=20.0, nz=3, n_sites=2, n_trans=9, window_A=4.0, aperture_mrad=20.0,
+                             det_outer_mrad=50.0, n_scan=4)
+    keep = eels.tune_get(eels.TUNE_WINDOW_GRAM)
+    try:
+        eels.tune_set(eels.TUNE_WINDOW_GRAM, 1)
+        _say("window Gram FP16, N2 = 8093")
+        wg = _map(eels, p, "fp16_split", "probe_first")
+        eels.tune_set(eels.TUNE_WINDOW_GRAM, 0)
+        direct = _map(eels, p, "bf16_split", "probe_first")
+    finally:
+        eels.tune_set(eels.TUNE_WINDOW_GRAM, keep)
+    _say("  rel-L2 vs BF16 per-transition", metrics.rel_l2(wg, direct))
+    assert np.all(np.isfinite(wg)) and np.max(direct) > 0
+    assert metrics.rel_l2(wg, direct) < 1e-4
+
+
 def test_repeat_is_bitwise_identical():
     eels = _need_gpu()
     p = synth.config1()
