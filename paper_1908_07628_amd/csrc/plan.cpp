@@ -353,12 +353,14 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     if (budget > 0) {
         if (budget <= fixed) return fail(EELS_ERR_OOM, "memory budget below the fixed workspace");
         // at least one slice's S_1 windows must fit next to the contraction buffers;
-        // the contraction batches get half of what remains beyond that
+        // the contraction batches get half of what remains beyond that, a quarter in the
+        // window-Gram form (its per-site buffers are smaller, and the room left to the S_1
+        // windows means fewer slice groups, each of which reruns the forward sweep)
         size_t min_w1 = 0;
         for (int j : ion) min_w1 = std::max(min_w1, (size_t)slice_windows(j) * win1_bytes);
         size_t avail = budget - fixed;
         if (avail <= min_w1 + 4096) return fail(EELS_ERR_OOM, "memory budget too small for one slice's windows");
-        batch_cap = (avail - min_w1 - 4096) / 2;
+        batch_cap = (avail - min_w1 - 4096) / (p.wgram ? 4 : 2);
     }
     struct PendingBatch { int slice; std::vector<int> sites; };
     std::vector<PendingBatch> pend;
