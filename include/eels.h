@@ -315,8 +315,10 @@ eels_status eels_debug_cgemm(int precision, int m, int n, int k, const void* d_A
  *        detector beams (K x K window pixels, one Gram GEMM for all transitions), G = M o
  *        sum_t conj(H_t) H_t^T, and I(R) = f^2 Psi_R^H G Psi_R (one GEMM G Psi and a
  *        per-probe dot product) instead of n_t products (S_2w o H_t) Psi.  Used when the
- *        window has at most 4096 pixels.  1 (default) this form; 0 the per-transition
- *        products.  A fused batch (eels_batch_create) takes plans made with 0.
+ *        window has at most 4096 pixels and the form needs fewer flops over the plan's
+ *        sites (it does with many eligible probes per site): 1 (default) this form where
+ *        it needs fewer flops, 2 wherever it applies, 0 never (the per-transition
+ *        products).  A fused batch (eels_batch_create) takes plans made with 0.
  * Returns EELS_ERR_INVALID_ARG for an unknown key or an out-of-range value. */
 eels_status eels_tune_set(int key, int value);
 int eels_tune_get(int key);

@@ -911,7 +911,7 @@ eels_status eels_tune_set(int key, int value) {
     if (key == TUNE_GRAM_STACK && (value < 0 || value > 1)) return EELS_ERR_INVALID_ARG;
     if (key == TUNE_GEMM1_ROWS && (value < 0 || value > 1)) return EELS_ERR_INVALID_ARG;
     if (key == TUNE_GEMM2_ROWS && (value < 0 || value > 1)) return EELS_ERR_INVALID_ARG;
-    if (key == TUNE_WINDOW_GRAM && (value < 0 || value > 1)) return EELS_ERR_INVALID_ARG;
+    if (key == TUNE_WINDOW_GRAM && (value < 0 || value > 2)) return EELS_ERR_INVALID_ARG;
     g_tune[key].store(value);
     return EELS_OK;
 }

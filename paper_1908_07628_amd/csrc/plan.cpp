@@ -253,10 +253,14 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
 
     // contraction order (Eq. TPRISM2 terms; both orders compute the same sums).  Gram form:
     // the Hermitian half of each site's Z^H Z plus one quadratic form per probe.
-    double fl_S = 0, fl_P = 0, fl_G = 0;
+    double fl_S = 0, fl_P = 0, fl_G = 0, fl_D = 0, fl_W = 0;
     for (int j : ion)
         for (int s : by_slice[j]) {
             double nt = p.sites[s].n_trans, Ps = n_elig(s);
+            // order P's second product: per transition (S_2w H_n) Psi, or in the window-Gram
+            // form the Hermitian half of S_2w^H S_2w plus G Psi
+            fl_D += 8.0 * p.N2 * (double)Kc * nt * Ps;
+            fl_W += 4.0 * p.N2 * (double)Kc * (Kc + 1.0) + 8.0 * Ps * (double)Kc * Kc;
             double g1 = 8.0 * p.N2 * (double)Kc * nt * p.N1;
             fl_S += g1 + 8.0 * nt * p.N2 * p.N1 * Ps;
             fl_G += g1 + 8.0 * nt * p.N2 * 0.5 * p.N1 * (p.N1 + 1.0);
@@ -280,7 +284,8 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     p.hs2 = split && !orderS && !p.recip;
     // window-Gram form (plan-time knob 6): I(R) = f^2 Psi_R^H (M o sum_t conj(H_t) H_t^T) Psi_R
     // with M = S_2w^H S_2w, one Gram GEMM per site instead of n_t products with N_2 rows
-    p.wgram = p.hs2 && !p.full_window && tune_get(TUNE_WINDOW_GRAM) != 0 && p.Kpad <= 4096;
+    const int wg_knob = tune_get(TUNE_WINDOW_GRAM);    // 0 never, 1 with fewer flops, 2 wherever it applies
+    p.wgram = p.hs2 && !p.full_window && p.Kpad <= 4096 && (wg_knob == 2 || (wg_knob == 1 && fl_W < fl_D));
     p.w2_sc = (split && !p.hs2) ? p.precision : 0;
     p.mid2_sc = split ? p.precision : 0;
 

@@ -223,7 +223,7 @@ def test_tuning_knob_ranges_and_gram_stack_plan():
     """Knob values are range-checked; the Gram form's first GEMM stacks the transitions'
     rows by default (plan-time knob 3)."""
     _lib()
-    for key, bad in ((0, 1), (0, 6), (1, 3), (2, 4), (3, 2), (3, -1), (4, 2), (5, 2), (5, -1), (6, 2), (6, -1),
+    for key, bad in ((0, 1), (0, 6), (1, 3), (2, 4), (3, 2), (3, -1), (4, 2), (5, 2), (5, -1), (6, 3), (6, -1),
                      (9, 0)):
         with pytest.raises(eels.EelsError):
             eels.tune_set(key, bad)
@@ -244,8 +244,12 @@ def test_fused_batch_plan_checks():
         _fused_batch_plan_checks(probs)
     finally:
         eels.tune_set(eels.TUNE_WINDOW_GRAM, 1)
-    # the window-Gram form (order P, split, cropped windows) is refused
-    wg = [eels.Plan(probs[2], precision="bf16_split", order="probe_first", resident_s=True)]
+    # the window-Gram form (order P, split, cropped windows; forced on this few-probe cell) is refused
+    eels.tune_set(eels.TUNE_WINDOW_GRAM, 2)
+    try:
+        wg = [eels.Plan(probs[2], precision="bf16_split", order="probe_first", resident_s=True)]
+    finally:
+        eels.tune_set(eels.TUNE_WINDOW_GRAM, 1)
     with pytest.raises(eels.EelsError) as e:
         eels.FusedContraction(wg, [0], (wg[0].workspace_bytes + 255) // 256 * 256)
     assert e.value.status == 1 and "key 6" in str(e.value)

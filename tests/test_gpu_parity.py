@@ -346,7 +346,8 @@ def test_interpolation_on_a_tiled_specimen(f):
 
 @pytest.mark.parametrize("prec", ["bf16_split", "fp16_split"])
 def test_window_gram_form(prec):
-    """Order P with cropped windows in the window-Gram form (knob 6): per site one Gram GEMM
+    """Order P with cropped windows in the window-Gram form (knob 6 = 2, forced on these
+    few-probe cells, where the default picks the per-transition form): per site one Gram GEMM
     of the S_2 window, G = M o sum_t conj(H_t) H_t^T, and Re(Psi^H G Psi) per probe.  Against
     the oracle at the split bar and against the per-transition products (f = 1, 2, 4)."""
     eels = _need_gpu()
@@ -361,7 +362,7 @@ def test_window_gram_form(prec):
         assert np.max(ref) > 0
         keep = eels.tune_get(eels.TUNE_WINDOW_GRAM)
         try:
-            eels.tune_set(eels.TUNE_WINDOW_GRAM, 1)
+            eels.tune_set(eels.TUNE_WINDOW_GRAM, 2)     # wherever it applies
             _say("window Gram", name, prec)
             got = _map(eels, p, prec, "probe_first")
             eels.tune_set(eels.TUNE_WINDOW_GRAM, 0)
@@ -386,7 +387,7 @@ def test_window_gram_fp16_range_at_many_detector_beams():
                              det_outer_mrad=50.0, n_scan=4)
     keep = eels.tune_get(eels.TUNE_WINDOW_GRAM)
     try:
-        eels.tune_set(eels.TUNE_WINDOW_GRAM, 1)
+        eels.tune_set(eels.TUNE_WINDOW_GRAM, 2)     # wherever it applies
         _say("window Gram FP16, N2 = 8093")
         wg = _map(eels, p, "fp16_split", "probe_first")
         eels.tune_set(eels.TUNE_WINDOW_GRAM, 0)
