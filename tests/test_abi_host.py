@@ -330,3 +330,30 @@ def test_autotuner_plan_time_knobs(tmp_path, monkeypatch):
         assert eels.tune_get(eels.TUNE_SC_STAGES) == 3 and eels.tune_get(eels.TUNE_TILE_ORDER) == 1
     finally:
         autotune.set_knobs(autotune.DEFAULTS)
+
+
+def test_window_gram_form_chosen_by_flops():
+    """Order P in split precision with cropped windows: the default (knob 6 = 1) takes the
+    window-Gram form where it needs fewer flops than the per-transition products (many
+    eligible probes and transitions per site), and the per-transition form where few
+    probes see each site; knob 2 forces the form and 0 turns it off.  The two forms lay
+    out the contraction buffers differently, so the workspace size tells them apart."""
+    _lib()
+
+    def sizes(p):
+        out = {}
+        try:
+            for k in (0, 1, 2):
+                eels.tune_set(eels.TUNE_WINDOW_GRAM, k)
+                out[k] = eels.Plan(p, precision="bf16_split", order="probe_first").workspace_bytes
+        finally:
+            eels.tune_set(eels.TUNE_WINDOW_GRAM, 1)
+        return out
+
+    many = synth.random_problem(23, n=128, L=25.0, nz=3, n_sites=2, n_trans=9, window_A=4.0,
+                                det_outer_mrad=25.0, n_scan=40)
+    few = many.replace(probes=many.probes[:4], probe_shape=(1, 4))
+    s = sizes(many)
+    assert s[1] == s[2] != s[0]
+    s = sizes(few)
+    assert s[1] == s[0] != s[2]
