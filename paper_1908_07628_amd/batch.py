@@ -34,7 +34,8 @@ class Batch:
         self.problems = list(problems)
         self.fused = fused
         # the fused contraction groups the per-transition products of all specimens, so its
-        # plans use that form of the detector sum (tuning key 6 = 0)
+        # plans use that form of the detector sum (tuning key 6 = 0; the process-wide knob is
+        # set while the plans are built, so no other thread may build plans meanwhile)
         keep = eels.tune_get(eels.TUNE_WINDOW_GRAM)
         eels.tune_set(eels.TUNE_WINDOW_GRAM, 0 if fused else keep)
         try:

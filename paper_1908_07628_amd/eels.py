@@ -187,7 +187,9 @@ class Plan:
 
     def replan(self) -> "Plan":
         """A new plan of the same request under the current plan-time tile knobs (tile rows,
-        Gram stacking) and this plan's form of the detector sum."""
+        Gram stacking) and this plan's form of the detector sum.  It sets the process-wide
+        knob 6 for the duration of the call, so it must not run while another thread
+        creates plans."""
         problem, kw = self._source
         keep = tune_get(TUNE_WINDOW_GRAM)
         tune_set(TUNE_WINDOW_GRAM, self._window_gram)
