@@ -180,6 +180,34 @@ def test_resident_s_matrices_serve_new_probes(prec, detsum):
     assert metrics.rel_l2(outb.cpu().numpy(), prism.prism_map(q)) < tol
 
 
+def test_resident_s_matrices_serve_new_probes_window_gram():
+    """Resident S-matrices reused for new probes (EXEC_SKIP_SWEEPS) in the window-Gram form
+    (f = 2, cropped windows, the form forced): bitwise equal to a fresh solve of the new
+    probes, and within the split bar of the oracle."""
+    eels = _gpu()
+    p = synth.config3_subproblem(n=128, L=25.0, nz=3, n_scan=5, f=2)
+    q = p.replace(probes=p.probes + [0.31, -0.17])
+    keep = eels.tune_get(eels.TUNE_WINDOW_GRAM)
+    try:
+        eels.tune_set(eels.TUNE_WINDOW_GRAM, 2)
+        a = eels.Plan(p, precision="bf16_split", order="probe_first", resident_s=True)
+        b = eels.Plan(q, precision="bf16_split", order="probe_first", resident_s=True)
+        ref = eels.solve(q, precision="bf16_split", order="probe_first")
+    finally:
+        eels.tune_set(eels.TUNE_WINDOW_GRAM, keep)
+    assert a.s_signature() == b.s_signature()
+    V, H = eels.device_inputs(p)
+    ws = torch.empty(max(a.workspace_bytes, b.workspace_bytes), dtype=torch.uint8, device="cuda")
+    outa = torch.empty(a.n_probes, dtype=torch.float64, device="cuda")
+    outb = torch.empty(b.n_probes, dtype=torch.float64, device="cuda")
+    a.execute(V, H, outa, ws)
+    b.execute(V, H, outb, ws, flags=eels.EXEC_SKIP_SWEEPS)
+    torch.cuda.synchronize()
+    got = outb.cpu().numpy()
+    assert np.array_equal(got, ref)
+    assert metrics.rel_l2(got, prism.prism_map(q)) < 1e-3
+
+
 def test_server_results_equal_alone_and_in_the_mix():
     eels = _gpu()
     from paper_1908_07628_amd.serve import Server
