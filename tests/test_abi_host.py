@@ -357,3 +357,14 @@ def test_window_gram_form_chosen_by_flops():
     assert s[1] == s[2] != s[0]
     s = sizes(few)
     assert s[1] == s[0] != s[2]
+
+
+def test_phase_names_match_the_header():
+    """The binding's phase names are the header's EELS_PHASE_* in order (eels_timing_read
+    fills one slot per phase)."""
+    text = open(os.path.join(ROOT, "include", "eels.h")).read()
+    ph = dict((m.group(1).lower(), int(m.group(2))) for m in re.finditer(r"EELS_PHASE_([A-Z0-9]+)\s*=\s*(\d+)", text))
+    n = int(re.search(r"EELS_PHASES\s*=\s*(\d+)", text).group(1))
+    assert len(eels.PHASES) == n == len(ph)
+    for i, name in enumerate(eels.PHASES):
+        assert ph[name] == i, name
