@@ -437,16 +437,19 @@ def test_window_not_smaller_than_cell_is_the_full_cell():
     assert np.array_equal(prism.prism_map(big), prism.prism_map(full))
 
 
-@pytest.mark.parametrize("f,ny,Ly", [(2, 32, 8.0), (3, 24, 6.0), (4, 32, 8.0)])
-def test_interpolation_on_a_tiled_specimen_equals_the_small_cell(f, ny, Ly):
+@pytest.mark.parametrize("f,ny,Ly,aberr", [(2, 32, 8.0, {}), (3, 24, 6.0, {}), (4, 32, 8.0, {}),
+                                           (2, 32, 8.0, dict(defocus_A=40.0, cs_A=2.0e6))])
+def test_interpolation_on_a_tiled_specimen_equals_the_small_cell(f, ny, Ly, aberr):
     """A specimen made of f x f copies of a small cell (every ionised site copied too): the
     coarse PRISM lattice of the big cell is the full lattice of the small cell and every
     S-matrix row repeats with the small cell's period, so for a probe R that sees a copy the
     f > 1 map equals the conventional multislice map of the small cell at R mod (L/f), times
     f^2 N_1 / N_1(f = 1) (the f^2 detector weight and the probe scale s_f against the small
-    cell's unit-norm probe).  A probe whose L/f box holds no crop box gets exactly zero."""
+    cell's unit-norm probe).  A probe whose L/f box holds no crop box gets exactly zero.
+    The identity also holds with defocus and spherical aberration (the same phase at the
+    same beams)."""
     ps = synth.random_problem(41, n=32, ny=ny, L=8.0, Ly=Ly, nz=3, n_sites=1, n_trans=3, window_A=4.0,
-                              aperture_mrad=15.0, det_outer_mrad=20.0)
+                              aperture_mrad=15.0, det_outer_mrad=20.0, **aberr)
     copies = np.array([ps.site_xy[0] + [i * ps.lx, j * ps.ly] for j in range(f) for i in range(f)])
     rng = np.random.default_rng(5)
     # the crop box (2 A half-width) lies inside the probe's L/f box for |dx| <= 2 A, |dy| <= Ly/2 - 2 A
