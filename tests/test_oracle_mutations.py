@@ -100,3 +100,32 @@ def test_dropped_transition_potential_is_caught(monkeypatch):
     monkeypatch.setattr(pr, "site_H", lambda prob, s, n: np.ones(prob.H.shape[1:], dtype=complex))
     with pytest.raises(AssertionError):
         pins.test_zero_transition_gives_zero()
+
+
+# --- interpolation f > 1: the tiled-specimen identity bites ----------------------------
+
+def test_dropped_f2_detector_weight_is_caught(monkeypatch):
+    orig = prism.contract_windows
+    monkeypatch.setattr(prism, "contract_windows", lambda S1w, S2w, C, Hs, f2: orig(S1w, S2w, C, Hs, 1.0))
+    assert pins.tiled_identity_gaps(2)[0] > 1e-3
+
+
+def test_wrong_probe_scale_for_interpolation_is_caught(monkeypatch):
+    """s = f / sqrt(N_1(f = 1)) instead of f^2 / sqrt(N_1(f = 1))."""
+    orig = ph.probe_coefficients
+
+    def scaled(ab, lx, ly, f, *a, **k):
+        c = orig(ab, lx, ly, f, *a, **k)
+        return c / f if f > 1 else c
+    monkeypatch.setattr(ph, "probe_coefficients", scaled)
+    assert pins.tiled_identity_gaps(2)[0] > 1e-3
+
+
+def test_wrong_eligibility_box_is_caught(monkeypatch):
+    """The crop box compared with an L/(2f) box instead of the L/f box."""
+    orig = ph.eligible
+
+    def halved(ix0, iy0, hx, hy, nx, ny, lx, ly, f, probes):
+        return orig(ix0, iy0, hx, hy, nx, ny, lx, ly, 2 * f if f > 1 else f, probes)
+    monkeypatch.setattr(ph, "eligible", halved)
+    assert pins.tiled_identity_gaps(2)[0] > 1e-3
