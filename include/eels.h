@@ -229,8 +229,9 @@ eels_status eels_plan_s_signature(const eels_plan* p, uint64_t* sig);
  * per kernel variant over a merged descriptor table, so that small specimens share the
  * matrix cores instead of launching one small grid each.
  * Plans: split precision (all the same), resident_s, one slice group, the per-transition
- * detector sum (made with tuning key 6 = 0, or where it is not the window-Gram form).  Workspaces are
- * regions of one caller-owned arena: plan i at d_arena + ws_offsets[i] (256-byte aligned,
+ * detector sum (made with tuning key 6 = 0, or where the window-Gram form does not apply).
+ * Workspaces are regions of one caller-owned arena: plan i at d_arena + ws_offsets[i]
+ * (256-byte aligned,
  * eels_plan_workspace_bytes long, not overlapping, within arena_bytes).
  *   eels_batch_create   host only: checks the plans, builds and bounds-checks the merged
  *                       descriptors (their offsets count from the arena base).  The plans
@@ -245,8 +246,8 @@ eels_status eels_plan_s_signature(const eels_plan* p, uint64_t* sig);
  *                       i], zeroed by the sweeps-only execute).  d_H[i]: plan i's transition
  *                       potentials.  No allocation, no host synchronisation (capturable).
  * Results equal each plan's own eels_execute bit for bit.  Errors: INVALID_ARG (null
- * pointers, mixed or FP32 precision, non-resident or window-Gram plans, workspace regions), INTERNAL (a
- * merged descriptor outside its plan's workspace), DEVICE. */
+ * pointers, mixed or FP32 precision, non-resident or window-Gram plans, workspace
+ * regions), INTERNAL (a merged descriptor outside its plan's workspace), DEVICE. */
 typedef struct eels_batch eels_batch;
 eels_status eels_batch_create(eels_batch** out, const eels_plan* const* plans, int n_plans, const size_t* ws_offsets,
                               size_t arena_bytes);
