@@ -231,8 +231,7 @@ eels_status eels_plan_s_signature(const eels_plan* p, uint64_t* sig);
  * Plans: split precision (all the same), resident_s, one slice group, the per-transition
  * detector sum (made with tuning key 6 = 0, or where the window-Gram form does not apply).
  * Workspaces are regions of one caller-owned arena: plan i at d_arena + ws_offsets[i]
- * (256-byte aligned,
- * eels_plan_workspace_bytes long, not overlapping, within arena_bytes).
+ * (256-byte aligned, eels_plan_workspace_bytes long, not overlapping, within arena_bytes).
  *   eels_batch_create   host only: checks the plans, builds and bounds-checks the merged
  *                       descriptors (their offsets count from the arena base).  The plans
  *                       must outlive the batch.
