@@ -35,22 +35,25 @@ import numpy as np
 from .common import make_setup, site_H, site_window, site_eligible
 
 
-def forward_s1(prob, st, slices) -> Dict[int, np.ndarray]:
-    """S_1(j) for every j in ``slices`` (complex128 [N1, ny, nx])."""
-    need = set(int(j) for j in slices)
-    out: Dict[int, np.ndarray] = {}
-    if not need:
-        return out
+def forward_s1_iter(prob, st, j_last: int):
+    """Yield (j, S_1(j)) for j = 0 .. j_last (complex128 [N1, ny, nx]), one slice at a time:
+    the aperture plane waves e_k multisliced, S_1(j) = ifft2(M_{j-1} ... M_0 e_k)."""
     N1 = st.ab1.shape[0]
     x = np.zeros((N1, prob.ny, prob.nx), dtype=np.complex128)
     x[np.arange(N1), st.iy1, st.ix1] = 1.0
-    for j in range(max(need) + 1):
+    for j in range(j_last + 1):
         psi = np.fft.ifft2(x)
-        if j in need:
-            out[j] = psi
-        if j < max(need):
+        yield j, psi
+        if j < j_last:
             x = st.P[j] * np.fft.fft2(st.T[j] * psi)
-    return out
+
+
+def forward_s1(prob, st, slices) -> Dict[int, np.ndarray]:
+    """S_1(j) for every j in ``slices`` (complex128 [N1, ny, nx])."""
+    need = set(int(j) for j in slices)
+    if not need:
+        return {}
+    return {j: psi for j, psi in forward_s1_iter(prob, st, max(need)) if j in need}
 
 
 def inverse_s1(prob, st, slices) -> Dict[int, np.ndarray]:
@@ -161,26 +164,38 @@ def _beam_subset(st, which: int, beams):
     return dataclasses.replace(st, ab2=st.ab2[b], ix2=st.ix2[b], iy2=st.iy2[b])
 
 
-def probe_waves_partial(prob, beams, chunk: int = 16, st=None) -> Dict[int, np.ndarray]:
+def window_rows(Sj: np.ndarray, rows, cols) -> np.ndarray:
+    """The rows of a scattering matrix restricted to a window: [n_beams, K] (K = rows x cols)."""
+    return Sj[:, rows[:, None], cols[None, :]].reshape(Sj.shape[0], -1)
+
+
+def probe_waves_partial(prob, beams, chunk: int = 16, st=None, sink=None) -> Dict[int, np.ndarray]:
     """For every site s: the part of Psi_s = S_1w^T c (window pixels x eligible probes) that
-    comes from the aperture beams `beams`, processed `chunk` beams at a time."""
+    comes from the aperture beams `beams`, processed `chunk` beams at a time.  With a `sink`,
+    each ionised slice's parts are handed to sink(j, {s: part}) as the sweep passes the slice
+    (nothing is kept); otherwise they are summed and returned."""
     st = make_setup(prob) if st is None else st
     ion = sorted(st.sites_by_slice.keys())
     out: Dict[int, np.ndarray] = {}
+    if not ion:
+        return out
     beams = np.asarray(beams, dtype=np.int64)
     for c0 in range(0, len(beams), chunk):
         sub = _beam_subset(st, 1, beams[c0:c0 + chunk])
-        S1 = forward_s1(prob, sub, ion)
-        for j in ion:
-            for s in st.sites_by_slice[j]:
+        for j, S1j in forward_s1_iter(prob, sub, ion[-1]):
+            parts = {}
+            for s in st.sites_by_slice.get(j, []):
                 el = site_eligible(prob, st, s)
                 if not np.any(el):
                     continue
                 rows, cols = site_window(prob, st, s)
-                S1w = S1[j][:, rows][:, :, cols].reshape(sub.C.shape[0], -1)
-                part = S1w.T @ sub.C[:, el]
+                parts[s] = window_rows(S1j, rows, cols).T @ sub.C[:, el]
+            if sink is not None:
+                if parts:
+                    sink(j, parts)
+                continue
+            for s, part in parts.items():
                 out[s] = out[s] + part if s in out else part
-        del S1
     return out
 
 
@@ -202,7 +217,7 @@ def intensity_partial(prob, psi: Dict[int, np.ndarray], beams, chunk: int = 16, 
                     continue
                 el = site_eligible(prob, st, s)
                 rows, cols = site_window(prob, st, s)
-                S2w = S2[:, rows][:, :, cols].reshape(S2.shape[0], -1)
+                S2w = window_rows(S2, rows, cols)
                 for n in range(int(prob.site_ntrans[s])):
                     h = site_H(prob, s, n).reshape(-1)
                     A = S2w @ (h[:, None] * psi[s])

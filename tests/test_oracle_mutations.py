@@ -129,3 +129,18 @@ def test_wrong_eligibility_box_is_caught(monkeypatch):
         return orig(ix0, iy0, hx, hy, nx, ny, lx, ly, 2 * f if f > 1 else f, probes)
     monkeypatch.setattr(ph, "eligible", halved)
     assert pins.tiled_identity_gaps(2)[0] > 1e-3
+
+
+@pytest.mark.parametrize("wrong", ["quarter", "lambda_cubed", "sign"])
+def test_wrong_spherical_aberration_term_is_caught(monkeypatch, wrong):
+    """A C_s term with a quarter instead of a half, one more power of lambda, or the opposite
+    sign moves the aberrated probe's centroid off the transverse ray aberration."""
+    import math
+
+    def chi_wrong(k2, lam, defocus_A=0.0, cs_A=0.0):
+        c = {"quarter": 0.25 * cs_A * lam * lam, "lambda_cubed": 0.5 * cs_A * lam ** 3,
+             "sign": -0.5 * cs_A * lam * lam}[wrong]
+        return math.pi * lam * k2 * (c * k2 - defocus_A)
+    monkeypatch.setattr(ph, "aberration_chi", chi_wrong)
+    with pytest.raises(AssertionError):
+        pins.test_spherical_aberration_transverse_ray_aberration(5e5, 0.0)

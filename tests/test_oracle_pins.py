@@ -87,7 +87,61 @@ def test_op_counts():
             brute += nz
             assert models.ms_ops_sum(ns, nz) == brute
             assert models.ms_ops_sum(ns, nz) - models.ms_ops_printed(ns, nz) == ns * nz
-    assert models.prism_ops(10, 100, 200) == 10 * (100 + 200 * 11)
+
+
+# --------------------------------------------------------------------------- error metric
+
+def test_error_metric_known_values():
+    # Eq. nrmsse read as ||a - b||_2 / ||b||_2, worked by hand: a - b = (3, -4) has norm 5
+    # and ||b|| = 4, so 1.25 (a dropped square root would give 25/16)
+    assert metrics.rel_l2([3.0, 0.0], [0.0, 4.0]) == pytest.approx(1.25, abs=1e-15)
+    # (1, 2, 2) against (1, 0, 0): sqrt(0 + 4 + 4) / 1
+    assert metrics.rel_l2([1.0, 2.0, 2.0], [1.0, 0.0, 0.0]) == pytest.approx(math.sqrt(8.0), abs=1e-15)
+    # equal maps, and a zero reference (then the norm of a itself)
+    assert metrics.rel_l2([2.0, -1.0], [2.0, -1.0]) == 0.0
+    assert metrics.rel_l2([3.0, 4.0], [0.0, 0.0]) == pytest.approx(5.0, abs=1e-15)
+    # max pointwise error over the largest reference value: max |(-1, 1)| / max |(2, 4)|
+    assert metrics.max_rel([1.0, 5.0], [2.0, 4.0]) == pytest.approx(0.25, abs=1e-15)
+    # signs: |(-3) - 1| = 4 over max |(1, -8)| = 8
+    assert metrics.max_rel([-3.0, -8.0], [1.0, -8.0]) == pytest.approx(0.5, abs=1e-15)
+    # scale invariance of both (a relative metric)
+    rng = np.random.default_rng(3)
+    a, b = rng.standard_normal(50), rng.standard_normal(50)
+    assert metrics.rel_l2(7 * a, 7 * b) == pytest.approx(metrics.rel_l2(a, b), rel=1e-14)
+    assert metrics.max_rel(7 * a, 7 * b) == pytest.approx(metrics.max_rel(a, b), rel=1e-14)
+
+
+# --------------------------------------------------------------------------- aberrations
+
+@pytest.mark.parametrize("cs_A,defocus_A", [(5e5, 0.0), (-5e5, 0.0), (5e5, 60.0)])
+def test_spherical_aberration_transverse_ray_aberration(cs_A, defocus_A):
+    # Geometric optics fixes the C_s term of Eq. illum independently of how chi is written:
+    # a ray leaving the probe-forming lens at angle theta lands theta (C_s theta^2 - defocus)
+    # from the axis (third-order transverse aberration), and by the Fourier shift theorem a
+    # narrow bundle of plane waves with phases -chi(k) forms a packet centred at grad chi / 2 pi.
+    # So the intensity centroid of a probe built from a small off-axis aperture must sit at the
+    # bundle's mean of theta_x (C_s theta^2 - defocus), here several angstrom away from 0.
+    n, L, lam = 256, 40.0, LAM300
+    k0, dk = 0.025 / lam, 0.25                     # 25 mrad off axis, 0.25 1/A bundle radius
+    a = np.arange(-n // 2, n // 2)
+    AX, AY = np.meshgrid(a, a, indexing="xy")
+    KX, KY = AX / L, AY / L
+    inside = (KX - k0) ** 2 + KY ** 2 <= dk * dk
+    k2 = KX ** 2 + KY ** 2
+    chi = ph.aberration_chi(k2, lam, defocus_A=defocus_A, cs_A=cs_A)
+    spec = np.zeros((n, n), dtype=np.complex128)
+    spec[np.mod(AY[inside], n), np.mod(AX[inside], n)] = np.exp(-1j * chi[inside])
+    psi = np.fft.ifft2(spec)
+    ix = np.abs(psi) ** 2
+    prof_x, prof_y = ix.sum(axis=0), ix.sum(axis=1)
+    x = np.arange(n) * L / n
+    cx = L / (2 * np.pi) * np.angle(np.sum(prof_x * np.exp(2j * np.pi * x / L)))   # circular mean
+    cy = L / (2 * np.pi) * np.angle(np.sum(prof_y * np.exp(2j * np.pi * x / L)))
+    th_x, th2 = lam * KX[inside], lam * lam * k2[inside]
+    expect = float(np.mean(th_x * (cs_A * th2 - defocus_A)))
+    assert abs(expect) > 3.0                          # a displacement the test can see
+    assert cx == pytest.approx(expect, rel=0.03)
+    assert abs(cy) < 0.02 * abs(expect)               # the bundle is symmetric in y
 
 
 # --------------------------------------------------------------------------- transforms
