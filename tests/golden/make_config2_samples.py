@@ -20,13 +20,19 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 from oracle import conventional  # noqa: E402
 
-# (ix, iy) on the 64 x 64 raster (0.3125 A steps): next to a B column, on an A column,
-# between columns, and near another B column
-PROBES_IX_IY = [(6, 6), (0, 0), (19, 13), (45, 57)]
+# (ix, iy) on the 64 x 64 raster (0.3125 A steps, 4 A lattice period = 12.8 steps): next to a
+# B column, on an A column, between columns, near another B column; then A-column and
+# O-column positions far from every ionised B column (the darkest parts of the map), points
+# on the lines between columns, and a spread over the rest of the cell
+PROBES_IX_IY = [(6, 6), (0, 0), (19, 13), (45, 57),
+                (13, 13), (26, 0), (0, 39), (51, 51),
+                (6, 0), (0, 6), (32, 19), (19, 32),
+                (3, 10), (29, 44), (58, 22), (40, 3)]
 _P = None
 
 
 def _work(site_idx):
+    """The map contribution of a subset of the sites at the sampled probes."""
     p = _P
     sel = np.asarray(site_idx, dtype=np.int64)
     idx = np.array([iy * 64 + ix for ix, iy in PROBES_IX_IY])
