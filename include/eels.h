@@ -160,6 +160,7 @@ typedef struct {
     double sweep_beam_slices;/* beam-slice passes of the two sweeps                       */
     size_t workspace_bytes;
     int gram_form;           /* 1 if the detector sum uses the Gram form (EELS_DETSUM_GRAM) */
+    int window_gram_form;    /* 1 if order P uses the window-Gram detector sum (tuning key 6) */
 } eels_plan_info;
 
 typedef struct eels_plan eels_plan;
@@ -311,7 +312,7 @@ eels_status eels_debug_cgemm(int precision, int m, int n, int k, const void* d_A
  * key 5: tiles of the second contraction GEMM in split precision with the per-probe
  *        detector sum (not the Gram form): 1 (default) 256 x 128 tiles of 8 waves; 0
  *        128 x 128 tiles of 4 waves.
- * key 6: detector sum of order P in split precision with cropped windows (Sec. 3 second
+ * key 6: detector sum of order P with cropped windows, in every precision (Sec. 3 second
  *        algorithm, Eq. SHn0): 1 the window-Gram form.  Per site, M = S_2w^H S_2w over the
  *        detector beams (K x K window pixels, one Gram GEMM for all transitions), G = M o
  *        sum_t conj(H_t) H_t^T, and I(R) = f^2 Psi_R^H G Psi_R (one GEMM G Psi and a

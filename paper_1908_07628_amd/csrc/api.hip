@@ -306,16 +306,23 @@ void producers_after_gemm1(const Plan& p, const Dev& d, const float2* dH, const 
 }
 
 // Window-Gram form of the second product: M = S_2w^H S_2w per site (Gram tiles), G = M o
-// sum_t conj(H_t) H_t^T, Y^T = Psi G^T, and the per-probe dot products Re(Psi^H Y).
+// sum_t conj(H_t) H_t^T, Y^T = Psi G^T, and the per-probe dot products Re(Psi^H Y).  Split
+// precisions keep S_2w^T, G and Psi in SC storage; FP32 keeps them in complex64 and runs the
+// FP32 GEMM for the Gram tiles and for G Psi.
 void wgram_contract(const Plan& p, const Dev& d, const float2* dH, const Batch& b, hipStream_t st) {
     const int nst = tune_get(TUNE_SC_STAGES);
     // G's diagonal is about N_2 sum_t |H_t|^2 (unit-modulus S_2 rows): scale it by an exact power
     // of two into the FP16 range, and the dot products back
     const float gscale = std::ldexp(1.0f, -(int)std::ceil(std::log2((double)std::max(p.N2, 1))));
+    const bool split = p.precision != EELS_FP32;
     {
         TimeScope ts(EELS_PHASE_GRAM, st);
-        launch_cgemm_sc(p.precision, 2, nst, d.descs + b.dm_begin, b.dm_count, b.dm_tiles, d.mid2, d.mid2, nullptr,
-                        (float*)d.mid2, d.blob, st, GEMM_BM);
+        if (split)
+            launch_cgemm_sc(p.precision, 2, nst, d.descs + b.dm_begin, b.dm_count, b.dm_tiles, d.mid2, d.mid2, nullptr,
+                            (float*)d.mid2, d.blob, st, GEMM_BM);
+        else
+            launch_cgemm(EELS_FP32, 0, 2, d.descs + b.dm_begin, b.dm_count, b.dm_tiles, d.mid2, d.mid2, nullptr, nullptr,
+                         (float*)d.mid2, d.blob, st);
     }
     {
         TimeScope ts(EELS_PHASE_PRODUCER, st);
@@ -327,8 +334,12 @@ void wgram_contract(const Plan& p, const Dev& d, const float2* dH, const Batch& 
     }
     {
         TimeScope ts(EELS_PHASE_GEMM2, st);
-        launch_cgemm_sc(p.precision, 3, nst, d.descs + b.dy_begin, b.dy_count, b.dy_tiles, d.mid, d.mid2, d.mid2,
-                        nullptr, d.blob, st, b.dy_rows);
+        if (split)
+            launch_cgemm_sc(p.precision, 3, nst, d.descs + b.dy_begin, b.dy_count, b.dy_tiles, d.mid, d.mid2, d.mid2,
+                            nullptr, d.blob, st, b.dy_rows);
+        else
+            launch_cgemm(EELS_FP32, 0, 0, d.descs + b.dy_begin, b.dy_count, b.dy_tiles, d.mid, d.mid2, nullptr, d.mid2,
+                         nullptr, d.blob, st);
     }
     {
         TimeScope ts(EELS_PHASE_REDUCE, st);
@@ -538,6 +549,7 @@ eels_status eels_plan_info_get(const eels_plan* pl, eels_plan_info* info) {
     info->order = p.order;
     info->band_basis = p.recip ? 1 : 0;
     info->band_pixels = p.Kb;
+    info->window_gram_form = p.wgram ? 1 : 0;
     info->lambda_A = p.lam;
     info->sigma = p.sigma;
     info->gemm_flops = p.gemm_flops;

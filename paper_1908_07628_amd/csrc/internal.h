@@ -60,7 +60,7 @@ struct Batch {
     int64_t red_ent;                    // int offset of the CSR entries (pairs: desc, column)
     int64_t n_entries;
     int n_parts;                        // Gram form: FP32 partials of Z^H Z written by the second GEMM
-    // window-Gram form (order P, split, cropped windows): per site the Gram GEMM of the S_2
+    // window-Gram form (order P, cropped windows): per site the Gram GEMM of the S_2
     // window (dm) and the product of G with Psi (dy); the d2 range then only drives the reduction
     int dm_begin = 0, dm_count = 0, dm_tiles = 0;
     int dy_begin = 0, dy_count = 0, dy_tiles = 0, dy_rows = 128;
@@ -129,7 +129,7 @@ struct Plan {
     bool gram;                                  // detector sum in the Gram form (order S, f = 1)
     bool hs2 = false;                           // order P, split, cropped windows: H multiplies the S_2
                                                 // windows (N_2 rows) and Psi is the shared operand
-    bool wgram = false;                         // order P, split, cropped windows: the detector sum as
+    bool wgram = false;                         // order P, cropped windows: the detector sum as
                                                 // Psi^H (M o sum_t conj(H_t) H_t^T) Psi, M = S_2w^H S_2w
     bool s1_inverse = false;                    // S_1 retreated with the inverse multislice
     int n_img = 0;                              // elastic companion images

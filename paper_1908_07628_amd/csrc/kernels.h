@@ -96,13 +96,15 @@ void launch_cgemm(int precision, int kind, int epi, const GemmDesc* d_descs, int
 void launch_cgemm_sc(int precision, int epi, int nstage, const GemmDesc* d_descs, int n_desc, int total_tiles,
                      const void* A, const void* B, void* C, float* part, const int* idx, hipStream_t st,
                      int rows = 128);
-// S_1 window [n_beams][K] (complex64, rows wstride apart) -> SC [K][ldo] (its transpose,
-// beams n_beams .. ldo-1 zero; ldo a multiple of 4, dst 32-byte aligned)
+// S_1 or S_2 window [n_beams][K] (complex64, rows wstride apart) -> its transpose [K][ldo],
+// SC for the split precisions, complex64 for EELS_FP32 (beams n_beams .. ldo-1 zero; ldo a
+// multiple of 4, dst 32-byte aligned)
 void launch_window_t_sc(void* dst, const float2* src, int64_t wstride, int n_beams, int K, int ldo, int prec,
                         hipStream_t st);
-// Window-Gram detector sum: G = gscale M o sum_t conj(H_t) H_t^T as SC rows [K][ldg] from
-// the FP32 complex Gram tiles M [K][ldm] (upper 128-tiles valid); and out[i] = oscale sum_r
-// Re(conj(Psi)Y) over the rows of Psi (SC) and Y (complex64), both ld complex apart.
+// Window-Gram detector sum: G = gscale M o sum_t conj(H_t) H_t^T as SC rows [K][ldg]
+// (complex64 for EELS_FP32) from the FP32 complex Gram tiles M [K][ldm] (upper 128-tiles
+// valid); and out[i] = oscale sum_r Re(conj(Psi)Y) over the rows of Psi (SC, complex64 for
+// EELS_FP32) and Y (complex64), both ld complex apart.
 void launch_wgram_combine(void* G, const float2* M, const float2* H, int nt, int K, int ldm, int ldg, float gscale,
                           int prec, hipStream_t st);
 void launch_wgram_dot(float* out, const void* psi, const float2* Y, int rows, int K, int ld, float oscale, int prec,

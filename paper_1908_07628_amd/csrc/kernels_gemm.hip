@@ -698,10 +698,12 @@ __global__ void k_to_sc(uint32_t* __restrict__ dst, const float2* __restrict__ s
     sc_store(dst, i, v, prec);
 }
 
-// S_1 windows to the B operand of the split probe-wave product Psi = C S_1w: the window
-// [beam][pixel] (complex64, rows wstride apart) becomes SC rows [pixel][beam] of ldo
-// complex, beams n_beams .. ldo-1 zero.  A block moves a 64-pixel x 64-beam tile through
-// LDS, reading whole pixel runs of a beam and writing whole 4-beam SC groups of a pixel.
+// Window transpose for the order-P products: the window [beam][pixel] (complex64, rows
+// wstride apart) becomes rows [pixel][beam] of ldo complex, beams n_beams .. ldo-1 zero;
+// split precisions store SC rows (the B operand of the split probe-wave product Psi = C S_1w,
+// or of the window-Gram form's Gram GEMM), FP32 complex64 rows.  A block moves a 64-pixel x
+// 64-beam tile through LDS, reading whole pixel runs of a beam and writing whole 4-beam
+// groups of a pixel.
 template <int PREC>
 __global__ __launch_bounds__(256) void k_window_t_sc(uint32_t* __restrict__ dst, const float2* __restrict__ src,
                                                      int64_t wstride, int n_beams, int K, int ldo) {
@@ -717,18 +719,26 @@ __global__ __launch_bounds__(256) void k_window_t_sc(uint32_t* __restrict__ dst,
         const int px = w >> 4, g = w & 15;
         const int pix = p0 + px, b = b0 + 4 * g;
         if (pix >= K || b >= ldo) continue;
-        u32x4 hi, lo;
+        if constexpr (PREC == EELS_FP32) {
+            float4* o = (float4*)((float2*)dst + (int64_t)pix * ldo + b);
+            const float2 v0 = tile[4 * g][px], v1 = tile[4 * g + 1][px], v2 = tile[4 * g + 2][px],
+                         v3 = tile[4 * g + 3][px];
+            o[0] = make_float4(v0.x, v0.y, v1.x, v1.y);
+            o[1] = make_float4(v2.x, v2.y, v3.x, v3.y);
+        } else {
+            u32x4 hi, lo;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const float2 v = tile[4 * g + e][px];
-            uint32_t h, l;
-            split2<PREC>(v.x, v.y, h, l);
-            hi[e] = h;
-            lo[e] = l;
+            for (int e = 0; e < 4; ++e) {
+                const float2 v = tile[4 * g + e][px];
+                uint32_t h, l;
+                split2<PREC>(v.x, v.y, h, l);
+                hi[e] = h;
+                lo[e] = l;
+            }
+            uint32_t* o = dst + (((int64_t)pix * ldo + b) >> 2) * 8;
+            *(u32x4*)o = hi;
+            *(u32x4*)(o + 4) = lo;
         }
-        uint32_t* o = dst + (((int64_t)pix * ldo + b) >> 2) * 8;
-        *(u32x4*)o = hi;
-        *(u32x4*)(o + 4) = lo;
     }
 }
 
@@ -739,14 +749,17 @@ void launch_window_t_sc(void* dst, const float2* src, int64_t wstride, int n_bea
     if (prec == EELS_BF16_SPLIT)
         hipLaunchKernelGGL(k_window_t_sc<EELS_BF16_SPLIT>, grid, dim3(256), 0, st, (uint32_t*)dst, src, wstride,
                            n_beams, K, ldo);
-    else
+    else if (prec == EELS_FP16_SPLIT)
         hipLaunchKernelGGL(k_window_t_sc<EELS_FP16_SPLIT>, grid, dim3(256), 0, st, (uint32_t*)dst, src, wstride,
+                           n_beams, K, ldo);
+    else
+        hipLaunchKernelGGL(k_window_t_sc<EELS_FP32>, grid, dim3(256), 0, st, (uint32_t*)dst, src, wstride,
                            n_beams, K, ldo);
 }
 
 // Window-Gram form of the detector sum: G = gscale M o S with S[r][c] = sum_t conj(H_t[r]) H_t[c]
 // (H_t the site's transition potentials on its K window pixels), written as SC rows
-// [K][ldg] (columns K .. ldg-1 zero).  M holds FP32 complex Gram tiles [K][ldm] of the
+// [K][ldg] (columns K .. ldg-1 zero), or complex64 rows for FP32.  M holds FP32 complex Gram tiles [K][ldm] of the
 // 128 x 128 grid with tile column >= tile row only; the others are the conjugate transpose.
 // A block forms a 64 x 64 tile, both of whose 128-tiles are on one side of the diagonal,
 // so it reads either M's tile or the transposed tile (through LDS), and stages the H values
@@ -805,26 +818,37 @@ __global__ __launch_bounds__(256) void k_wgram_combine(uint32_t* __restrict__ ds
     for (int j = 0; j < 4; ++j) {
         const int y = rb + 16 * j, r = r0 + y, c = c0 + 4 * g;
         if (r >= K || c >= ldg) continue;
-        u32x4 hi, lo;
+        float vr[4], vi[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const float2 m = tile[y][4 * g + e];
-            float vr = gscale * (m.x * sr[j][e] - m.y * si[j][e]);
-            float vi = gscale * (m.x * si[j][e] + m.y * sr[j][e]);
-            if (c + e >= K) { vr = 0.f; vi = 0.f; }
-            uint32_t h, l;
-            split2<PREC>(vr, vi, h, l);
-            hi[e] = h;
-            lo[e] = l;
+            vr[e] = gscale * (m.x * sr[j][e] - m.y * si[j][e]);
+            vi[e] = gscale * (m.x * si[j][e] + m.y * sr[j][e]);
+            if (c + e >= K) { vr[e] = 0.f; vi[e] = 0.f; }
         }
-        uint32_t* o = dst + (((int64_t)r * ldg + c) >> 2) * 8;
-        *(u32x4*)o = hi;
-        *(u32x4*)(o + 4) = lo;
+        if constexpr (PREC == EELS_FP32) {
+            float4* o = (float4*)((float2*)dst + (int64_t)r * ldg + c);
+            o[0] = make_float4(vr[0], vi[0], vr[1], vi[1]);
+            o[1] = make_float4(vr[2], vi[2], vr[3], vi[3]);
+        } else {
+            u32x4 hi, lo;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                uint32_t h, l;
+                split2<PREC>(vr[e], vi[e], h, l);
+                hi[e] = h;
+                lo[e] = l;
+            }
+            uint32_t* o = dst + (((int64_t)r * ldg + c) >> 2) * 8;
+            *(u32x4*)o = hi;
+            *(u32x4*)(o + 4) = lo;
+        }
     }
 }
 
 // Window-Gram form: out[i] = oscale sum_r Re(conj(Psi[i][r]) Y[i][r]) over the K window pixels,
-// Psi in SC rows of ld complex, Y complex64 rows of ld; one wave per probe row.
+// Psi in SC rows of ld complex (complex64 for FP32), Y complex64 rows of ld; one wave per
+// probe row.
 template <int PREC>
 __global__ __launch_bounds__(256) void k_wgram_dot(float* __restrict__ out, const uint32_t* __restrict__ psi,
                                                    const float2* __restrict__ Y, int rows, int K, int ld,
@@ -835,6 +859,13 @@ __global__ __launch_bounds__(256) void k_wgram_dot(float* __restrict__ out, cons
     const uint32_t* prow = psi + ((int64_t)i * ld >> 2) * 8;
     const float2* yrow = Y + (int64_t)i * ld;
     float acc = 0.f;
+    if constexpr (PREC == EELS_FP32) {
+        const float2* prow2 = (const float2*)psi + (int64_t)i * ld;
+        for (int r = lane; r < K; r += 64) {
+            const float2 a = prow2[r], y = yrow[r];
+            acc += a.x * y.x + a.y * y.y;
+        }
+    } else
     for (int gi = lane; gi * 4 < K; gi += 64) {
         const u32x4 h = *(const u32x4*)(prow + 8 * gi);
         const u32x4 l = *(const u32x4*)(prow + 8 * gi + 4);
@@ -868,8 +899,11 @@ void launch_wgram_combine(void* G, const float2* M, const float2* H, int nt, int
     if (prec == EELS_BF16_SPLIT)
         hipLaunchKernelGGL(k_wgram_combine<EELS_BF16_SPLIT>, grid, dim3(256), 0, st, (uint32_t*)G, M, H, nt, K, ldm,
                            ldg, gscale);
-    else
+    else if (prec == EELS_FP16_SPLIT)
         hipLaunchKernelGGL(k_wgram_combine<EELS_FP16_SPLIT>, grid, dim3(256), 0, st, (uint32_t*)G, M, H, nt, K, ldm,
+                           ldg, gscale);
+    else
+        hipLaunchKernelGGL(k_wgram_combine<EELS_FP32>, grid, dim3(256), 0, st, (uint32_t*)G, M, H, nt, K, ldm,
                            ldg, gscale);
 }
 
@@ -880,8 +914,11 @@ void launch_wgram_dot(float* out, const void* psi, const float2* Y, int rows, in
     if (prec == EELS_BF16_SPLIT)
         hipLaunchKernelGGL(k_wgram_dot<EELS_BF16_SPLIT>, grid, dim3(256), 0, st, out, (const uint32_t*)psi, Y, rows,
                            K, ld, oscale);
-    else
+    else if (prec == EELS_FP16_SPLIT)
         hipLaunchKernelGGL(k_wgram_dot<EELS_FP16_SPLIT>, grid, dim3(256), 0, st, out, (const uint32_t*)psi, Y, rows,
+                           K, ld, oscale);
+    else
+        hipLaunchKernelGGL(k_wgram_dot<EELS_FP32>, grid, dim3(256), 0, st, out, (const uint32_t*)psi, Y, rows,
                            K, ld, oscale);
 }
 

@@ -285,7 +285,9 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     // window-Gram form (plan-time knob 6): I(R) = f^2 Psi_R^H (M o sum_t conj(H_t) H_t^T) Psi_R
     // with M = S_2w^H S_2w, one Gram GEMM per site instead of n_t products with N_2 rows
     const int wg_knob = tune_get(TUNE_WINDOW_GRAM);    // 0 never, 1 with fewer flops, 2 wherever it applies
-    p.wgram = p.hs2 && !p.full_window && p.Kpad <= 4096 && (wg_knob == 2 || (wg_knob == 1 && fl_W < fl_D));
+    // (FP32 too: an FP32 Gram GEMM, G in complex64 and an FP32 G Psi product)
+    p.wgram = !orderS && !p.recip && !p.full_window && p.Kpad <= 4096 &&
+              (wg_knob == 2 || (wg_knob == 1 && fl_W < fl_D));
     p.w2_sc = (split && !p.hs2) ? p.precision : 0;
     p.mid2_sc = split ? p.precision : 0;
 
@@ -317,7 +319,7 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     const int64_t wg_m = (int64_t)p.K * p.N2p, wg_g = wg_m + (int64_t)p.K * p.Kpad,
                   wg_y = wg_g + (int64_t)p.K * p.Kpad;
     auto site_mid2 = [&](int s) -> int64_t {
-        if (!p.recip && !split) return 0;
+        if (!p.recip && !split && !p.wgram) return 0;
         int64_t m2 = p.wgram ? wg_y + (int64_t)n_elig(s) * p.Kpad
                              : (int64_t)p.sites[s].n_trans * site_ni(s) * Kcpad;
         // order P, split: the site's S_1 window is first transposed here for the product C S_1w
@@ -540,13 +542,14 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
         }
         // producer jobs (band FFT or H multiply) write mid2 from S_1 windows (order S) or Psi (order P)
         bt.job_begin = (int)p.jobs.size();
-        if (p.recip || split) {
+        if (p.recip || split || p.wgram) {
             for (size_t si = 0; si < pb.sites.size(); ++si) {
                 int s = pb.sites[si];
                 Job jb{};
                 jb.from_mid = orderS ? 0 : (p.hs2 ? 2 : 1);
                 jb.w_off = orderS ? (int64_t)p.site_w1[s] * w1_stride
-                                  : (p.hs2 ? p.slice_w2[pb.slice] + (int64_t)p.site_w2[s] * w2_stride : site_moff[si]);
+                                  : ((p.hs2 || p.wgram) ? p.slice_w2[pb.slice] + (int64_t)p.site_w2[s] * w2_stride
+                                                        : site_moff[si]);
                 jb.win_off = (int64_t)p.site_w1[s] * w1_stride;
                 jb.Ni = (int)site_ni(s);
                 jb.nt = p.sites[s].n_trans;

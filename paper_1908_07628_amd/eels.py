@@ -55,7 +55,7 @@ class PlanInfo(C.Structure):
                 ("order", C.c_int), ("band_basis", C.c_int), ("band_pixels", C.c_int),
                 ("lambda_A", C.c_double), ("sigma", C.c_double), ("gemm_flops", C.c_double),
                 ("sweep_bytes", C.c_double), ("sweep_beam_slices", C.c_double), ("workspace_bytes", C.c_size_t),
-                ("gram_form", C.c_int)]
+                ("gram_form", C.c_int), ("window_gram_form", C.c_int)]
 
 
 _LIB: Optional[C.CDLL] = None

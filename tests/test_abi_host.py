@@ -332,20 +332,22 @@ def test_autotuner_plan_time_knobs(tmp_path, monkeypatch):
         autotune.set_knobs(autotune.DEFAULTS)
 
 
-def test_window_gram_form_chosen_by_flops():
-    """Order P in split precision with cropped windows: the default (knob 6 = 1) takes the
-    window-Gram form where it needs fewer flops than the per-transition products (many
-    eligible probes and transitions per site), and the per-transition form where few
-    probes see each site; knob 2 forces the form and 0 turns it off.  The two forms lay
-    out the contraction buffers differently, so the workspace size tells them apart."""
+@pytest.mark.parametrize("precision", ["bf16_split", "fp32"])
+def test_window_gram_form_chosen_by_flops(precision):
+    """Order P with cropped windows, in split precision and in FP32: the default (knob 6 = 1)
+    takes the window-Gram form where it needs fewer flops than the per-transition products
+    (many eligible probes and transitions per site), and the per-transition form where few
+    probes see each site; knob 2 forces the form and 0 turns it off.  The two forms lay out
+    the contraction buffers differently, so the workspace size differs too."""
     _lib()
 
-    def sizes(p):
+    def forms(p):
         out = {}
         try:
             for k in (0, 1, 2):
                 eels.tune_set(eels.TUNE_WINDOW_GRAM, k)
-                out[k] = eels.Plan(p, precision="bf16_split", order="probe_first").workspace_bytes
+                pl = eels.Plan(p, precision=precision, order="probe_first")
+                out[k] = (pl.info()["window_gram_form"], pl.workspace_bytes)
         finally:
             eels.tune_set(eels.TUNE_WINDOW_GRAM, 1)
         return out
@@ -353,10 +355,20 @@ def test_window_gram_form_chosen_by_flops():
     many = synth.random_problem(23, n=128, L=25.0, nz=3, n_sites=2, n_trans=9, window_A=4.0,
                                 det_outer_mrad=25.0, n_scan=40)
     few = many.replace(probes=many.probes[:4], probe_shape=(1, 4))
-    s = sizes(many)
-    assert s[1] == s[2] != s[0]
-    s = sizes(few)
-    assert s[1] == s[0] != s[2]
+    s = forms(many)
+    assert [s[k][0] for k in (0, 1, 2)] == [0, 1, 1]
+    assert s[1][1] == s[2][1] != s[0][1]
+    s = forms(few)
+    assert [s[k][0] for k in (0, 1, 2)] == [0, 0, 1]
+    assert s[1][1] == s[0][1] != s[2][1]
+    # full-cell windows and order S never take it
+    full = many.replace(window_A=0.0)
+    eels.tune_set(eels.TUNE_WINDOW_GRAM, 2)
+    try:
+        assert eels.Plan(full, precision=precision, order="probe_first").info()["window_gram_form"] == 0
+        assert eels.Plan(many, precision=precision, order="s_first").info()["window_gram_form"] == 0
+    finally:
+        eels.tune_set(eels.TUNE_WINDOW_GRAM, 1)
 
 
 def test_phase_names_match_the_header():

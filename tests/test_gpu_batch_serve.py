@@ -6,6 +6,7 @@ import sys
 import numpy as np
 import pytest
 
+from maptol import maps_close
 import synth
 from oracle import metrics, prism
 
@@ -47,7 +48,7 @@ def test_batch_graph_replays_match_eager_and_solo():
         solo = eels.solve(p, precision="fp32")
         assert np.array_equal(eager[i], solo), i
     ref = prism.prism_map(sp[0])
-    assert metrics.rel_l2(eager[0], ref) < 1e-4
+    assert maps_close(eager[0], ref, 1e-4)
     b.capture()
     for rep in range(3):
         b.maps.zero_()                                  # eager work between replays
@@ -84,7 +85,7 @@ def test_fused_batch_contraction_matches_per_specimen(prec):
     for i, solo in enumerate(solos):
         assert np.array_equal(fused[i], solo), i
     for i in (0, len(sp) - 2, len(sp) - 1):
-        assert metrics.rel_l2(fused[i], prism.prism_map(sp[i])) < 1e-3, i
+        assert maps_close(fused[i], prism.prism_map(sp[i]), 1e-3), i
     b.capture()
     for rep in range(3):
         b.maps.zero_()                                  # eager work between replays
@@ -149,14 +150,14 @@ def test_autotuner_caches_a_valid_setting(tmp_path, monkeypatch):
     tp.execute(V, H, out, ws)
     autotune.set_knobs(autotune.DEFAULTS)
     ref = prism.prism_map(p)
-    assert metrics.rel_l2(out.cpu().numpy(), ref) < 1e-3
+    assert maps_close(out.cpu().numpy(), ref, 1e-3)
     # every macro-tile shape gives the map to the same bar
     for pc in pcs:
         autotune.set_knobs(pc)
         q = plan.replan()
         autotune.set_knobs(autotune.PLAN_DEFAULTS)
         q.execute(V, H, out, q.alloc_workspace())
-        assert metrics.rel_l2(out.cpu().numpy(), ref) < 1e-3, pc
+        assert maps_close(out.cpu().numpy(), ref, 1e-3), pc
 
 
 @pytest.mark.parametrize("prec,detsum", [("fp32", "auto"), ("bf16_split", "auto"), ("bf16_split", "gram")])
@@ -177,7 +178,7 @@ def test_resident_s_matrices_serve_new_probes(prec, detsum):
     ref = eels.solve(q, precision=prec, detector_sum=detsum)
     assert np.array_equal(outb.cpu().numpy(), ref)
     tol = 1e-4 if prec == "fp32" else 1e-3
-    assert metrics.rel_l2(outb.cpu().numpy(), prism.prism_map(q)) < tol
+    assert maps_close(outb.cpu().numpy(), prism.prism_map(q), tol)
 
 
 def test_resident_s_matrices_serve_new_probes_window_gram():
@@ -205,7 +206,7 @@ def test_resident_s_matrices_serve_new_probes_window_gram():
     torch.cuda.synchronize()
     got = outb.cpu().numpy()
     assert np.array_equal(got, ref)
-    assert metrics.rel_l2(got, prism.prism_map(q)) < 1e-3
+    assert maps_close(got, prism.prism_map(q), 1e-3)
 
 
 def test_server_results_equal_alone_and_in_the_mix():
