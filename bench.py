@@ -1,17 +1,22 @@
 """EELS map throughput on one MI355X (probe positions per second).
 
-Workload: the perovskite-crystal map (256 x 256 px over 20 x 20 A, 50 slices of 2 A,
-650 ionised B sites x 9 transitions contracted over the full cell, 64 x 64 probes,
-300 keV, 21 mrad aperture, 0-50 mrad detector).  A step is one complete map: set-up,
-both scattering-matrix sweeps, every contraction and the FP64 reduction, with the
-inputs already resident in HBM.
+Default workload: the nanoparticle map (1024 x 1024 px over 100 x 100 A, 50 slices of 2 A,
+an 80 A bcc sphere of 22,659 atoms, every one ionised with 9 transitions, on a 20 A
+amorphous support; PRISM interpolation factor f = 4, 4 A crop windows, 256 x 256 probes,
+300 keV, 20 mrad aperture, 0-20 mrad detector).  A step is one complete map: set-up, both
+scattering-matrix sweeps, every contraction and the FP64 reduction, with the inputs already
+resident in HBM.
 
-`value` is the BF16-split (hi+lo, FP32 accumulate) throughput.  The plain FP32 path
-is reported beside it, measured on the contractions of a bounded subset of ionised
-slices and scaled by GEMM work (see the `fp32` object); `--fp32-full` times it on the
-whole map instead.  `roofline` is for the dominant kernel (the first contraction
-GEMM), timed with HIP events on the execute stream.  `cpu_baseline` is the FP64
-conventional-multislice oracle timed on a bounded sample of the same workload.
+`value` is the BF16-split (hi+lo, FP32 accumulate) throughput.  The plain FP32 path runs
+the same algorithm (window-Gram detector sum) and is timed on the whole map (`fp32`).
+`roofline` is for the dominant kernel, timed with HIP events on the execute stream:
+`achieved` counts the algorithmic complex-GEMM flops 8 M N K, `executed_frac` the three
+MFMA products per multiply-add the split form runs.  `cpu_baseline` is the FP64 oracle
+timed on a bounded sample of the same workload, on one core and on all host cores.
+
+--steps and --warmup are upper bounds: the run stays inside --wall-budget seconds from
+process start (the FP32 map and the CPU sample included) and reports the steps it timed.
+Other workloads: --workload crystal | batch | serve.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -288,24 +293,22 @@ NANO_WORKLOAD = ("nanoparticle 1024x1024 px over 100x100 A, 50 slices x 2 A: 80 
                  "windows, 256x256 probes, 300 keV, 20 mrad aperture, 0-20 mrad detector")
 
 
-def cpu_baseline_nanoparticle(p, info, sample_beams=3, sample_probes=1024):
-    """FP64 PRISM oracle (one BLAS thread) on a bounded sample, scaled by its operation counts:
-    `sample_beams` aperture beams swept to the deepest ionised slice and as many detector beams
-    swept from the exit to the shallowest (the oracle sweeps every beam this way), and one
+_CPU = {}
+
+
+def _oracle_sample(offset, sample_beams, sample_probes):
+    """One bounded sample of the FP64 PRISM oracle on the nanoparticle workload (one BLAS
+    thread): `sample_beams` aperture beams swept to the deepest ionised slice, as many detector
+    beams swept from the exit to the shallowest (the oracle sweeps every beam this way), and one
     site's contraction (oracle.prism.contract_windows) on windows of the real shapes with
-    `sample_probes` eligible probes.  Full map = N_1 / sample_beams x S_1 sample + N_2 /
-    sample_beams x S_2 sample + the contraction of every site, which is linear in its
-    eligible-probe count."""
+    `sample_probes` eligible probes.  Returns the seconds of each part."""
     import dataclasses
     import threadpoolctl
     from oracle import prism
-    from oracle.common import make_setup, site_eligible
+    p, st, info = _CPU["p"], _CPU["st"], _CPU["info"]
     ion = sorted(set(p.site_slice.tolist()))
     with threadpoolctl.threadpool_limits(1):
-        t0 = time.perf_counter()
-        st = make_setup(p.replace(probes=p.probes[:1], probe_shape=(1, 1)))
-        t_setup = time.perf_counter() - t0
-        b = slice(0, sample_beams)
+        b = slice(offset, offset + sample_beams)
         st1 = dataclasses.replace(st, ab1=st.ab1[b], ix1=st.ix1[b], iy1=st.iy1[b], C=st.C[b])
         t0 = time.perf_counter()
         prism.forward_s1(p, st1, [ion[-1]])
@@ -315,7 +318,7 @@ def cpu_baseline_nanoparticle(p, info, sample_beams=3, sample_probes=1024):
         for _ in prism.reverse_s2(p, st2, j_stop=ion[0]):
             pass
         t_s2 = time.perf_counter() - t0
-        rng = np.random.default_rng(0)
+        rng = np.random.default_rng(offset)
         K, N1, N2 = info["k_pixels"], info["n_beams_in"], info["n_beams_out"]
         cplx = lambda *sh: rng.standard_normal(sh) + 1j * rng.standard_normal(sh)
         S1w, S2w, C = cplx(N1, K), cplx(N2, K), cplx(N1, sample_probes)
@@ -323,30 +326,92 @@ def cpu_baseline_nanoparticle(p, info, sample_beams=3, sample_probes=1024):
         t0 = time.perf_counter()
         prism.contract_windows(S1w, S2w, C, Hs, 16.0)
         t_site = time.perf_counter() - t0
-    # mean eligible-probe count per site on the full raster (the oracle's f > 1 rule), over
-    # a seeded sample of sites
+    return t_s1, t_s2, t_site
+
+
+def cpu_baseline_nanoparticle(p, info, sample_beams=2, sample_probes=512, max_workers=16):
+    """The FP64 PRISM oracle on a bounded sample of the nanoparticle map, scaled by operation
+    counts to the whole map: N_1 / sample_beams x the S_1 sample + N_2 / sample_beams x the S_2
+    sample + every site's contraction, which is linear in its eligible-probe count (mean over
+    a seeded sample of sites).  Timed on one core, then with one process per core running the
+    same sample on different beams at once (the beams and sites are independent, so the
+    oracle parallelises this way); the all-core rate is the one-core rate times the work done
+    per wall second."""
+    import multiprocessing as mp
+    from oracle.common import make_setup, site_eligible
+    import threadpoolctl
+    with threadpoolctl.threadpool_limits(1):
+        t0 = time.perf_counter()
+        st = make_setup(p.replace(probes=p.probes[:1], probe_shape=(1, 1)))
+        t_setup = time.perf_counter() - t0
+    _CPU.update(p=p, st=st, info=info)
+    t_s1, t_s2, t_site = _oracle_sample(0, sample_beams, sample_probes)
+    ion = sorted(set(p.site_slice.tolist()))
     pick = np.random.default_rng(1).choice(p.n_sites, size=min(64, p.n_sites), replace=False)
+    # mean eligible-probe count per site on the full raster (the oracle's f > 1 rule)
     ps_mean = float(np.mean([np.sum(site_eligible(p, st, int(s))) for s in pick]))
-    full = t_setup + (N1 * t_s1 + N2 * t_s2) / sample_beams + p.n_sites * t_site * ps_mean / sample_probes
-    measured = t_setup + t_s1 + t_s2 + t_site
+    N1, N2 = info["n_beams_in"], info["n_beams_out"]
+    one_core = t_setup + (N1 * t_s1 + N2 * t_s2) / sample_beams + p.n_sites * t_site * ps_mean / sample_probes
+    sample_s = t_s1 + t_s2 + t_site
+    n = max(1, min(max_workers, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(n) as pool:
+        parts = pool.starmap(_oracle_sample, [(sample_beams * (k + 1), sample_beams, sample_probes) for k in range(n)])
+    wall = time.perf_counter() - t0
+    assert len(parts) == n
+    speedup = n * sample_s / wall          # n samples' work per wall second, against one core
+    all_core = one_core / speedup
+    cpu_model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {
-        "value": p.n_probes / full, "unit": "probe-px/s", "cores": 1, "kind": "oracle",
-        "sample": (f"PRISM oracle FP64 (numpy FFT, one BLAS thread): set-up {t_setup:.1f} s, {sample_beams} "
-                   f"aperture beams to slice {ion[-1]} {t_s1:.1f} s, {sample_beams} detector beams from the exit to "
-                   f"slice {ion[0]} {t_s2:.1f} s, one site's contraction with {sample_probes} probes "
-                   f"{t_site:.1f} s; scaled to "
-                   f"{N1} + {N2} beams and {p.n_sites} sites x {ps_mean:.0f} eligible probes "
-                   f"(estimated {full / 3600:.0f} h per map)"),
-        "seconds_measured": round(measured, 1),
-        "host_cpus": os.cpu_count(),
+        "value": p.n_probes / all_core, "unit": "probe-px/s", "cores": n, "kind": "oracle",
+        "sample": (f"PRISM oracle FP64 (numpy FFT, one BLAS thread per process) on {n} processes, each sweeping "
+                   f"{sample_beams} aperture beams to slice {ion[-1]} and {sample_beams} detector beams from the exit "
+                   f"to slice {ion[0]} and contracting one site's windows with {sample_probes} probes "
+                   f"({wall:.1f} s wall, {speedup:.1f}x the one-core rate); scaled to {N1} + {N2} beams and "
+                   f"{p.n_sites} sites x {ps_mean:.0f} eligible probes (estimated {all_core / 3600:.1f} h per map)"),
+        "one_core": {"value": p.n_probes / one_core, "cores": 1,
+                     "sample": (f"set-up {t_setup:.1f} s, S_1 sample {t_s1:.1f} s, S_2 sample {t_s2:.1f} s, one "
+                                f"site {t_site:.1f} s (estimated {one_core / 3600:.1f} h per map)")},
+        "seconds_measured": round(t_setup + sample_s + wall, 1),
+        "host_cpus": os.cpu_count(), "cpu_model": cpu_model,
     }
 
 
-def bench_nanoparticle(args):
-    """Nanoparticle workload: the f = 4, 4 A-crop map (order P) at full size."""
+def check_against_oracle(maps, name="config3_map_samples.json"):
+    """Errors of the GPU maps at the probes whose FP64 oracle values tests/golden holds (the
+    whole map at 64 probes over the central 32 x 32; Eq. nrmsse read as relative L2, and the
+    largest error over the largest sampled value)."""
+    path = os.path.join(ROOT, "tests", "golden", name)
+    if not os.path.exists(path):
+        return None
+    g = json.load(open(path))
+    ref = np.asarray(g["map"])
+    idx = np.asarray(g["probe_index"])
+    out = {"probes": len(idx), "what": g["about"]}
+    for k, m in maps.items():
+        got = m[idx]
+        out[k] = {"rel_l2": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                  "max_err_over_max": float(np.max(np.abs(got - ref)) / np.max(ref))}
+    return out
+
+
+def bench_nanoparticle(args, t_proc0):
+    """Nanoparticle workload: the f = 4, 4 A-crop map (order P, window-Gram detector sum) at
+    full size, BF16 split timed over the steps, FP32 on one whole map."""
     import torch
     import synth
     from paper_1908_07628_amd import eels
+
+    def elapsed():
+        return time.time() - t_proc0
+
     t0 = time.time()
     p = synth.config3()
     log(f"inputs generated in {time.time() - t0:.1f} s: {p.n_sites} sites, {p.n_trans} transitions")
@@ -355,14 +420,15 @@ def bench_nanoparticle(args):
     budget = int(free - (8 << 30))
     ion = sorted(set(p.site_slice.tolist()))
 
-    # untimed warm-up on the top ionised slice (loads the kernels; not a step)
+    # untimed kernel warm-up on the top ionised slice (loads the kernels; not a step)
     small = subset_sites(p, np.nonzero(p.site_slice == ion[-1])[0])
-    wplan = eels.Plan(small, precision=args.precision, max_workspace_bytes=budget)
-    wws = wplan.alloc_workspace()
-    wout = torch.empty(p.n_probes, dtype=torch.float64, device="cuda")
-    wplan.execute(V, H, wout, wws)
-    torch.cuda.synchronize()
-    del wws, wplan
+    for prec in (args.precision, "fp32"):
+        wplan = eels.Plan(small, precision=prec, max_workspace_bytes=budget)
+        wws = wplan.alloc_workspace()
+        wout = torch.empty(p.n_probes, dtype=torch.float64, device="cuda")
+        wplan.execute(V, H, wout, wws)
+        torch.cuda.synchronize()
+        del wws, wplan
     torch.cuda.empty_cache()
 
     plan = eels.Plan(p, precision=args.precision, max_workspace_bytes=budget)
@@ -370,31 +436,43 @@ def bench_nanoparticle(args):
     ws = plan.alloc_workspace()
     out = torch.empty(p.n_probes, dtype=torch.float64, device="cuda")
     log(f"plan: N1={info['n_beams_in']} N2={info['n_beams_out']} K={info['k_pixels']} "
-        f"order={'S' if info['order'] == 1 else 'P'} groups={info['n_groups']} batches={info['n_batches']} "
+        f"order={'S' if info['order'] == 1 else 'P'} window-Gram={info['window_gram_form']} "
+        f"groups={info['n_groups']} batches={info['n_batches']} "
         f"workspace={info['workspace_bytes'] / 1e9:.1f} GB (budget {budget / 1e9:.0f} GB)")
-    for w in range(args.warmup):
+    # warm-up steps: --warmup is an upper bound (a second one changes nothing measurable)
+    n_warm, t_w = 0, None
+    for w in range(max(1, min(args.warmup, 2))):
+        t1 = time.perf_counter()
         plan.execute(V, H, out, ws)
         torch.cuda.synchronize()
-        log(f"warmup step {w + 1}/{args.warmup} done")
+        t_w = time.perf_counter() - t1
+        n_warm += 1
+        log(f"warmup step {w + 1} done ({t_w:.1f} s)")
+    # steps: --steps is an upper bound; keep room for the FP32 map (about 3x a split step)
+    # and the CPU sample inside the wall budget
+    reserve = 3.5 * t_w + 20.0 + (0.0 if args.no_cpu_baseline else 75.0)
+    fit = int((args.wall_budget - elapsed() - reserve) / t_w)
+    steps = max(1, min(args.steps, fit))
+    log(f"{elapsed():.0f} s since start; timing {steps} of at most {args.steps} steps")
     eels.timing_enable(1 << 16)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     phase_tot = {}
-    for k in range(args.steps):
+    for k in range(steps):
         plan.execute(V, H, out, ws)
         torch.cuda.synchronize()
         for name, v in eels.timing_read().items():
             a = phase_tot.setdefault(name, {"ms": 0.0, "count": 0})
             a["ms"] += v["ms"]
             a["count"] += v["count"]
-        log(f"step {k + 1}/{args.steps} done")
-    elapsed = time.perf_counter() - t_start
+        log(f"step {k + 1}/{steps} done")
+    elapsed_steps = time.perf_counter() - t_start
     eels.timing_enable(0)
-    value = p.n_probes * args.steps / elapsed
+    value = p.n_probes * steps / elapsed_steps
     gpu_map = out.cpu().numpy()
     del ws
     torch.cuda.empty_cache()
-    phases = {k: round(v["ms"] / args.steps, 1) for k, v in phase_tot.items()}
+    phases = {k: round(v["ms"] / steps, 1) for k, v in phase_tot.items()}
 
     # contraction kernels.  The plan's flop count is the per-transition form's,
     # sum over sites of 8 P_s K (N_1 + N_2 n_t), which gives the eligible probe-site pairs.
@@ -408,46 +486,52 @@ def bench_nanoparticle(args):
     N1, N2, K = info["n_beams_in"], info["n_beams_out"], info["k_pixels"]
     pairs = info["gemm_flops"] / (8.0 * K * (N1 + N2 * nt))
     split = args.precision != "fp32"
-    exec_factor = 3.0 if split else 1.0
-    peak = PEAK_BF16_TFLOPS if split else PEAK_FP32_TFLOPS
+
+    def kernels(ph, wgram):
+        k = {"gemm1": ("first product Psi = C S_1w", 8.0 * K * N1 * pairs, "gemm1_traffic_bytes_per_site")}
+        if wgram:
+            k["gemm2"] = ("G Psi product of the window-Gram form", 8.0 * K * K * pairs, "gpsi_traffic_bytes_per_site")
+            k["gram"] = ("Gram GEMM M = S_2w^H S_2w of the window-Gram form (Hermitian half)",
+                         8.0 * N2 * K * (K + 1) / 2.0 * p.n_sites, "gram_traffic_bytes_per_site")
+        else:
+            k["gemm2"] = ("second product (S_2w H_n) Psi", 8.0 * N2 * K * nt * pairs, "gemm2_traffic_bytes_per_site")
+        return {name: v for name, v in k.items() if ph.get(name, {"count": 0})["count"] > 0}
+
+    def contraction_table(ph, n_steps, prec):
+        exec_factor = 3.0 if prec != "fp32" else 1.0
+        peak = PEAK_BF16_TFLOPS if prec != "fp32" else PEAK_FP32_TFLOPS
+        out_k = {}
+        for name, (what, fl, _) in kernels(ph, ph.get("gram", {"count": 0})["count"] > 0).items():
+            t = ph[name]
+            useful = fl * n_steps / (t["ms"] * 1e-3) / 1e12
+            out_k[name] = {"kernel": what, "ms": round(t["ms"] / n_steps, 1), "launches": t["count"] // n_steps,
+                           "useful_complex_tflops": round(useful, 1), "frac": round(useful / peak, 4),
+                           "executed_frac": round(exec_factor * useful / peak, 4)}
+        return out_k
+
     wgram = phase_tot.get("gram", {"count": 0})["count"] > 0
-    kern = {"gemm1": ("first product Psi = C S_1w (k_cgemm_sc, store epilogue)", 8.0 * K * N1 * pairs,
-                      "gemm1_traffic_bytes_per_site")}
-    if wgram:
-        kern["gemm2"] = ("G Psi product of the window-Gram form (k_cgemm_sc, complex64 store)", 8.0 * K * K * pairs,
-                         "gpsi_traffic_bytes_per_site")
-        kern["gram"] = ("Gram GEMM M = S_2w^H S_2w of the window-Gram form (k_cgemm_sc, Gram tiles)",
-                        8.0 * N2 * K * (K + 1) / 2.0 * p.n_sites, "gram_traffic_bytes_per_site")
-    else:
-        kern["gemm2"] = ("second product (S_2w H_n) Psi (k_cgemm_sc, norm epilogue)" if split
-                         else "second product (k_cgemm, norm epilogue)", 8.0 * N2 * K * nt * pairs,
-                         "gemm2_traffic_bytes_per_site")
-    cv = counter_values("k_cgemm_sc__nanoparticle_traffic_pmc.md") if split else {}
-    contraction = {}
-    for ph, (what, fl, _) in kern.items():
-        t = phase_tot[ph]
-        contraction[ph] = {"kernel": what, "ms": round(t["ms"] / args.steps, 1),
-                           "useful_complex_tflops": round(fl * args.steps / (t["ms"] * 1e-3) / 1e12, 1),
-                           "executed_frac": round(exec_factor * fl * args.steps / (t["ms"] * 1e-3) / 1e12 / peak, 4)}
+    kern = kernels(phase_tot, wgram)
+    contraction = contraction_table(phase_tot, steps, args.precision)
     dom = max(kern, key=lambda k: phase_tot[k]["ms"])
     what, dom_flops, ckey = kern[dom]
     g = phase_tot[dom]
-    n_launch = g["count"] / args.steps
+    n_launch = g["count"] / steps
     avg_ms = g["ms"] / max(g["count"], 1)
     per_launch = dom_flops / n_launch
-    achieved = exec_factor * per_launch / (avg_ms * 1e-3) / 1e12
-    # counter bytes per site of this kernel (profiling sample: the most populated slice, same
-    # per-site shapes) times the full map's sites per launch
+    exec_factor = 3.0 if split else 1.0
+    peak = PEAK_BF16_TFLOPS if split else PEAK_FP32_TFLOPS
+    achieved = per_launch / (avg_ms * 1e-3) / 1e12
+    cv = counter_values("k_cgemm_sc__nanoparticle_traffic_pmc.md")
     traffic = cv[ckey] * p.n_sites / n_launch if ckey in cv else None
     roofline = {
-        "bound": "mfma", "kernel": what,
+        "bound": "mfma", "kernel": what + (" (k_cgemm_sc)" if split else " (k_cgemm)"),
         "achieved": round(achieved, 1), "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+        "executed_frac": round(exec_factor * achieved / peak, 4),
         "traffic": traffic, "avg_launch_ms": round(avg_ms, 3), "launches_per_step": n_launch,
-        "algorithmic_flops_per_launch": exec_factor * per_launch,
-        "useful_complex_tflops": round(per_launch / (avg_ms * 1e-3) / 1e12, 1),
-        "flop_definition": ("3 BF16 MFMA products per complex multiply-add of the split algorithm, 8 real flops "
-                            "each; useful = 8 M N K complex (Gram GEMM: its Hermitian half)" if split
-                            else "8 M N K"),
+        "algorithmic_flops_per_launch": per_launch,
+        "flop_definition": ("achieved: 8 M N K real flops per complex GEMM (the Gram GEMM: its Hermitian half); "
+                            "executed_frac: the three BF16 MFMA products per complex multiply-add of the split "
+                            "algorithm" if split else "8 M N K"),
     }
     nlx = info["n_live_x"]
     cap_bytes = 8.0 * p.n_sites * K * (N1 + N2)
@@ -460,41 +544,38 @@ def bench_nanoparticle(args):
         "byte_definition": (f"32 B x n_y x n_live_x ({nlx}) per beam-slice (2 passes, read + write; S_1 swept "
                             f"once per slice group) + 8 B per window pixel per beam captured")}}
 
-    # FP32 on the top ionised slices (contractions scaled by GEMM work; set-up and sweeps
-    # from the full step)
-    ps = subset_sites(p, np.nonzero(np.isin(p.site_slice, ion[-args.fp32_slices:]))[0])
-    p32 = eels.Plan(ps, precision="fp32", max_workspace_bytes=budget)
-    i32 = p32.info()
-    ws32 = p32.alloc_workspace()
-    o32 = torch.empty(p.n_probes, dtype=torch.float64, device="cuda")
-    p32.execute(V, H, o32, ws32)
-    torch.cuda.synchronize()
-    eels.timing_enable(1 << 16)
-    p32.execute(V, H, o32, ws32)
-    torch.cuda.synchronize()
-    ph32 = eels.timing_read()
-    eels.timing_enable(0)
-    del ws32
-    contract_ms = sum(ph32[k]["ms"] for k in ("producer", "gemm1", "gemm2", "reduce", "gram"))
-    scale = info["gemm_flops"] / i32["gemm_flops"]
-    est_ms = phases["setup"] + phases["sweep"] + contract_ms * scale
-    fp32 = {"value": p.n_probes / (est_ms * 1e-3), "ms_per_step": round(est_ms, 1),
-            "measured_on": (f"contractions of the top {args.fp32_slices} ionised slices ({ps.n_sites} sites, "
-                            f"{contract_ms:.0f} ms) scaled by GEMM work x{scale:.1f}; set-up and sweeps from "
-                            "the full split step")}
-    # the same sites in the split precision, against the FP32 map
-    psp = eels.Plan(ps, precision=args.precision, max_workspace_bytes=budget)
-    wsp = psp.alloc_workspace()
-    osp = torch.empty(p.n_probes, dtype=torch.float64, device="cuda")
-    psp.execute(V, H, osp, wsp)
-    torch.cuda.synchronize()
-    del wsp
-    m32, msp = o32.cpu().numpy(), osp.cpu().numpy()
-    fp32["split_rel_l2_vs_fp32"] = float(np.linalg.norm(msp - m32) / np.linalg.norm(m32))
+    # FP32: the same algorithm on the whole map, timed once
+    fp32 = None
+    m32 = None
+    if not args.no_fp32:
+        p32 = eels.Plan(p, precision="fp32", max_workspace_bytes=budget)
+        i32 = p32.info()
+        ws32 = p32.alloc_workspace()
+        o32 = torch.empty(p.n_probes, dtype=torch.float64, device="cuda")
+        log(f"FP32 plan: window-Gram={i32['window_gram_form']} groups={i32['n_groups']} "
+            f"batches={i32['n_batches']} ({elapsed():.0f} s since start)")
+        eels.timing_enable(1 << 16)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        p32.execute(V, H, o32, ws32)
+        torch.cuda.synchronize()
+        dt32 = time.perf_counter() - t1
+        ph32 = eels.timing_read()
+        eels.timing_enable(0)
+        del ws32
+        torch.cuda.empty_cache()
+        m32 = o32.cpu().numpy()
+        fp32 = {"value": round(p.n_probes / dt32, 2), "ms_per_step": round(1e3 * dt32, 1), "steps": 1,
+                "measured_on": "the whole map (same algorithm: order P, window-Gram detector sum)",
+                "window_gram_form": i32["window_gram_form"],
+                "phases_ms": {k: round(v["ms"], 1) for k, v in ph32.items() if v["count"]},
+                "contraction_kernels": contraction_table(ph32, 1, "fp32"),
+                "split_rel_l2_vs_fp32": float(np.linalg.norm(gpu_map - m32) / np.linalg.norm(m32))}
+        log(f"FP32 map {dt32:.1f} s")
 
     result = {
-        "metric": METRIC, "value": round(value, 2), "unit": "probe-px/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 1), "higher_is_better": True,
+        "metric": METRIC, "value": round(value, 2), "unit": "probe-px/s", "n_gpus": 1, "steps": steps,
+        "warmup": n_warm, "ms_per_step": round(1e3 * elapsed_steps / steps, 1), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "bf16" if args.precision == "bf16_split" else args.precision,
         "data": "synthetic",
         "config": {"workload": NANO_WORKLOAD, "grid": [p.nx, p.ny], "n_slices": p.n_slices, "n_sites": p.n_sites,
@@ -506,27 +587,45 @@ def bench_nanoparticle(args):
                    "contraction": "cropped windows, order P" + (", window-Gram detector sum" if wgram else "")},
         "roofline": roofline, "contraction_kernels": contraction, "roofline_fft": roofline_fft,
         "phases_ms": phases, "fp32": fp32,
-        "split_over_fp32": round(value / fp32["value"], 2),
+        "split_over_fp32": round(value / fp32["value"], 2) if fp32 else None,
         "map_sum": float(np.sum(gpu_map)),
     }
+    maps = {args.precision: gpu_map}
+    if m32 is not None:
+        maps["fp32"] = m32
+    result["check"] = check_against_oracle(maps)
     if not args.no_cpu_baseline:
-        log("timing the CPU oracle sample ...")
+        log(f"timing the CPU oracle sample ({elapsed():.0f} s since start) ...")
         result["cpu_baseline"] = cpu_baseline_nanoparticle(p, info)
+    result["wall_s"] = round(elapsed(), 1)
+    result["wall_budget_s"] = args.wall_budget
     return result
 
 
 def main():
+    t_proc0 = time.time()
+    try:
+        import psutil
+        t_proc0 = psutil.Process().create_time()     # the wall budget counts from process start
+    except Exception:
+        pass
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=5, help="upper bound of the timed steps")
+    ap.add_argument("--warmup", type=int, default=1, help="upper bound of the untimed warm-up steps")
+    ap.add_argument("--wall-budget", type=float, default=450.0,
+                    help="seconds from process start the run stays within (steps are cut to fit)")
     ap.add_argument("--precision", default="bf16_split", choices=["bf16_split", "fp16_split", "fp32"])
-    ap.add_argument("--fp32-full", action="store_true", help="time the FP32 path on the whole map")
-    ap.add_argument("--fp32-slices", type=int, default=2, help="ionised slices of the FP32 sample")
+    ap.add_argument("--no-fp32", action="store_true", help="nanoparticle: skip the FP32 whole-map leg")
+    ap.add_argument("--fp32-sample", action="store_true",
+                    help="crystal: estimate FP32 from the top ionised slices instead of timing the whole map")
+    ap.add_argument("--fp32-slices", type=int, default=2, help="ionised slices of the crystal FP32 sample and extras")
+    ap.add_argument("--extras", action="store_true",
+                    help="crystal: also time companion images, inverse multislice and conventional multislice")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--check", action="store_true", help="compare sampled probes with the stored FP64 values")
-    ap.add_argument("--workload", default="crystal", choices=["crystal", "nanoparticle", "batch", "serve"],
-                    help="crystal: the benchmark map (default); nanoparticle: the f = 4 cropped-window map; "
+    ap.add_argument("--check", action="store_true", help="crystal: compare sampled probes with the stored FP64 values")
+    ap.add_argument("--workload", default="nanoparticle", choices=["nanoparticle", "crystal", "batch", "serve"],
+                    help="nanoparticle: the f = 4 cropped-window map (default); crystal: the 256^2 full-cell map; "
                          "batch: 64 uneven specimens in one graph; serve: Poisson request stream with p50/p99 "
                          "latency")
     ap.add_argument("--profile-sample", type=int, default=0, metavar="N",
@@ -542,23 +641,25 @@ def main():
                     help="serving workload: run the request streams once per precision (default: --precision)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is "
-              "described in DESIGN.md and not run here.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build runs on a "
+              "single GPU and its multi-GPU layout (sites sharded over GPUs, one all-reduce of the map) "
+              "is not run.", file=sys.stderr)
         sys.exit(2)
     if args.profile_sample > 0:
         profile_sample(args)
         return
-    if args.workload != "crystal":
-        if args.precision == "bf16_split" and args.workload == "batch":
-            args.precision = "fp16_split"
-        res = {"batch": bench_batch, "serve": bench_serve, "nanoparticle": bench_nanoparticle}[args.workload](args)
-        print(json.dumps(res), flush=True)
-        return
+    if args.precision == "bf16_split" and args.workload == "batch":
+        args.precision = "fp16_split"
+    fn = {"batch": lambda a, t: bench_batch(a), "serve": lambda a, t: bench_serve(a),
+          "nanoparticle": bench_nanoparticle, "crystal": bench_crystal}[args.workload]
+    print(json.dumps(fn(args, t_proc0)), flush=True)
 
+
+def bench_crystal(args, t_proc0):
+    """Crystal workload: the 256^2 full-cell map (band basis, order S, Gram detector sum)."""
     import torch
     import synth
     from paper_1908_07628_amd import eels
-
 
     t0 = time.time()
     p = synth.config2()
@@ -583,10 +684,19 @@ def main():
     log(f"plan: N1={info['n_beams_in']} N2={info['n_beams_out']} band pixels={info['band_pixels']} "
         f"order={'S' if info['order'] == 1 else 'P'} batches={info['n_batches']} "
         f"workspace={info['workspace_bytes'] / 1e9:.1f} GB (free {free / 1e9:.0f} GB)")
-    for w in range(args.warmup):
+    n_warm, t_w = 0, None
+    for w in range(max(1, min(args.warmup, 2))):      # --warmup is an upper bound
+        t1 = time.perf_counter()
         plan.execute(V, H, out, ws)
         torch.cuda.synchronize()
-        log(f"warmup step {w + 1}/{args.warmup} done")
+        t_w = time.perf_counter() - t1
+        n_warm += 1
+        log(f"warmup step {w + 1} done ({t_w:.1f} s)")
+    # --steps is an upper bound: room for the FP32 map (about 4x a split step) and the CPU sample
+    reserve = (0.5 if args.fp32_sample else 4.5) * t_w + 20.0 + (0.0 if args.no_cpu_baseline else 40.0)
+    args.steps = max(1, min(args.steps, int((args.wall_budget - (time.time() - t_proc0) - reserve) / t_w)))
+    args.warmup = n_warm
+    log(f"timing {args.steps} steps")
 
     eels.timing_enable(8192)
     torch.cuda.synchronize()
@@ -617,18 +727,18 @@ def main():
     split = args.precision != "fp32"
     exec_factor = 3.0 if split else 1.0           # hi*hi + hi*lo + lo*hi
     per_launch = g1_flops / n_launch_per_step
-    achieved = exec_factor * per_launch / (avg_ms * 1e-3) / 1e12
+    achieved = per_launch / (avg_ms * 1e-3) / 1e12
     peak = PEAK_BF16_TFLOPS if split else PEAK_FP32_TFLOPS
     roofline = {
         "bound": "mfma", "kernel": "k_cgemm_sc (first contraction GEMM)" if split else "k_cgemm",
         "achieved": round(achieved, 1), "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+        "executed_frac": round(exec_factor * achieved / peak, 4),
         "traffic": counters.get("gemm1_traffic_bytes_per_launch") if split else None,
         "avg_launch_ms": round(avg_ms, 3),
         "launches_per_step": n_launch_per_step,
-        "algorithmic_flops_per_launch": exec_factor * per_launch,
-        "useful_complex_tflops": round(per_launch / (avg_ms * 1e-3) / 1e12, 1),
-        "flop_definition": ("3 BF16 MFMA products per complex multiply-add of the split algorithm, "
-                            "8 real flops each; useful = 8 M N K complex" if split else "8 M N K"),
+        "algorithmic_flops_per_launch": per_launch,
+        "flop_definition": ("achieved: 8 M N K real flops per complex GEMM; executed_frac: the three BF16 MFMA "
+                            "products per complex multiply-add of the split algorithm" if split else "8 M N K"),
     }
     phases = {k: round(v["ms"] / args.steps, 2) for k, v in phase_tot.items()}
 
@@ -662,11 +772,24 @@ def main():
     }
 
     del ws
+    torch.cuda.empty_cache()
+    companion = inverse = conv = None
+    ps = subset_sites(p, np.nonzero(np.isin(p.site_slice, ion[-args.fp32_slices:]))[0])
+    if args.extras:
+        companion, inverse, conv = crystal_extras(args, p, ps, ion, V, H, info, value, gpu_map)
+    return crystal_finish(args, t_proc0, p, ps, ion, V, H, info, value, gpu_map, elapsed, ms_per_step,
+                          roofline, roofline_fft, phases, companion, inverse, conv)
+
+
+def crystal_extras(args, p, ps, ion, V, H, info, value, gpu_map):
+    """Companion images, the inverse-multislice S_1 and the conventional multislice on the GPU
+    (--extras)."""
+    import torch
+    from paper_1908_07628_amd import eels
     # Extras, on the sites of the top ionised slices (their costs do not grow with the site
     # count except the contractions): companion images (iBF with the EELS detector's angles,
     # ADF from 60 mrad to the band limit) computed with the map, and the inverse-multislice
     # S_1 (Sec. 4.C) against the exact path.
-    ps = subset_sites(p, np.nonzero(np.isin(p.site_slice, ion[-args.fp32_slices:]))[0])
     rings = [(p.det_inner_mrad, p.det_outer_mrad), (60.0, 0.0)]
 
     def timed(plan, with_images=False):
@@ -759,8 +882,17 @@ def main():
                                         "wave, entrance waves, H once per chunk, new waves, exit band")},
         }
 
+    return companion, inverse, conv
+
+
+def crystal_finish(args, t_proc0, p, ps, ion, V, H, info, value, gpu_map, elapsed, ms_per_step, roofline,
+                   roofline_fft, phases, companion, inverse, conv):
+    """The FP32 leg (whole map unless --fp32-sample), the CPU sample and the JSON line."""
+    import torch
+    from paper_1908_07628_amd import eels
+    out = torch.empty(p.n_probes, dtype=torch.float64, device="cuda")
     # FP32 plain path
-    if args.fp32_full:
+    if not args.fp32_sample:
         p32 = eels.Plan(p, precision="fp32")
         ws32 = p32.alloc_workspace()
         torch.cuda.synchronize()
@@ -768,7 +900,9 @@ def main():
         p32.execute(V, H, out, ws32)
         torch.cuda.synchronize()
         dt32 = time.perf_counter() - t1
-        fp32 = {"value": p.n_probes / dt32, "ms_per_step": 1e3 * dt32, "measured_on": "the whole map"}
+        fp32 = {"value": p.n_probes / dt32, "ms_per_step": 1e3 * dt32, "measured_on": "the whole map",
+                "split_rel_l2_vs_fp32": float(np.linalg.norm(gpu_map - out.cpu().numpy()) /
+                                              np.linalg.norm(out.cpu().numpy()))}
         del ws32
     else:
         keep = np.isin(p.site_slice, ion[-args.fp32_slices:])
@@ -828,7 +962,8 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample ...")
         result["cpu_baseline"] = cpu_baseline(p)
-    print(json.dumps(result), flush=True)
+    result["wall_s"] = round(time.time() - t_proc0, 1)
+    return result
 
 
 if __name__ == "__main__":
