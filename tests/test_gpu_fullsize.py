@@ -95,7 +95,7 @@ GOLD3 = os.path.join(os.path.dirname(__file__), "golden", "config3_samples.json"
 
 
 @pytest.mark.parametrize("precision,bar,wgram", [("bf16_split", 1e-3, 0), ("fp16_split", 1e-3, 0), ("fp32", 1e-4, 0),
-                                                 ("bf16_split", 1e-3, 1), ("fp16_split", 1e-3, 1)])
+                                                 ("bf16_split", 1e-3, 1), ("fp16_split", 1e-3, 1), ("fp32", 1e-4, 1)])
 def test_config3_sampled_probes(precision, bar, wgram):
     """Full-size nanoparticle geometry (1024^2, 50 slices, f = 4, 4 A crop, N_1 = N_2 = 2025)
     in the launch configuration of bench.py's nanoparticle workload (order P, memory budget
