@@ -234,12 +234,10 @@ def bench_serve(args):
     """Serving workload: Poisson arrivals, continuous batching, residency, p50/p99."""
     import torch
     import synth
-    from paper_1908_07628_amd.serve import specimen_key
     t0 = time.time()
     pool = synth.specimen_pool(55, args.pool, (128, 256, 512, 1024), (10, 60), (1, 20), (16, 64), "req",
                                workers=min(16, os.cpu_count() or 1))
     log(f"{len(pool)} specimens generated in {time.time() - t0:.1f} s")
-    keys = [specimen_key(p) for p in pool]
     free, _ = torch.cuda.mem_get_info()
     out = {"metric": METRIC, "unit": "probe-px/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
            "dtype": args.precision, "vs_baseline": None,
@@ -251,7 +249,7 @@ def bench_serve(args):
     out["by_precision"] = {}
     for prec in precisions:
         out["rates"] = {}
-        serve_rates(args, pool, keys, free, prec, out)
+        serve_rates(args, pool, free, prec, out)
         out["by_precision"][prec] = out["rates"]
     out["rates"] = out["by_precision"][precisions[0]]
     out["dtype"] = precisions[0]
@@ -260,13 +258,13 @@ def bench_serve(args):
     return out
 
 
-def serve_rates(args, pool, keys, free, precision, out):
-    """One Poisson stream per rate through a fresh server in the given precision."""
+def serve_rates(args, pool, free, precision, out):
+    """One Poisson stream per rate through a fresh server (eels_server_*) in the given precision."""
     import synth
     from paper_1908_07628_amd.serve import Server
     for rate in args.rates:
         reqs = synth.config5_stream(seed=5, rate_per_s=rate, n_requests=args.n_requests, pool=pool)
-        srv = Server(int(0.8 * free), max_slots=4, precision=precision, residency=True)
+        srv = Server(int(0.8 * free), max_slots=4, precision=precision)
         t0 = time.perf_counter()
         tickets = []
         for (t_arr, k, shift) in reqs:
@@ -274,7 +272,7 @@ def serve_rates(args, pool, keys, free, precision, out):
             if dt > 0:
                 time.sleep(dt)
             p = pool[k].replace(probes=pool[k].probes + shift)
-            tickets.append(srv.submit(p, key=keys[k]))
+            tickets.append(srv.submit(p))
         res = [srv.wait(t, timeout=900) for t in tickets]
         wall = time.perf_counter() - t0
         srv.close()

@@ -36,7 +36,7 @@ extern "C" {
 #endif
 
 #define EELS_VERSION_MAJOR 0
-#define EELS_VERSION_MINOR 3
+#define EELS_VERSION_MINOR 4
 
 typedef int eels_status;
 enum {
@@ -292,6 +292,90 @@ size_t eels_gemm_work_bytes(int m, int n, int k);
 eels_status eels_debug_cgemm(int precision, int m, int n, int k, const void* d_A, int lda,
                              const void* d_B, int ldb, void* d_C, int ldc, double* d_norm2,
                              void* d_work, void* stream);
+
+/* Map arithmetic on device maps (float64, caller-owned, enqueued on `stream`).
+ *   eels_map_mean   d_out[i] = (1 / n_maps) sum_c d_maps[c * n + i], summed in configuration
+ *                   order c = 0 .. n_maps-1 in FP64: the frozen-phonon map, the average of the
+ *                   maps of n_maps thermal configurations (the Results' nanoparticle run is one
+ *                   frozen-phonon pass; more passes are averaged).  d_out may alias no input.
+ *   eels_map_ratio  d_out[i] = d_num[i] / d_den[i] where d_den[i] > 0, else 0: the BF-corrected
+ *                   map, the EELS map divided by the incoherent bright-field image of the EELS
+ *                   detector's angles (Results, nanoparticle discussion).  d_out may be d_num.
+ * Errors: INVALID_ARG for null pointers, n_maps < 1 or n < 0; DEVICE for a failed launch. */
+eels_status eels_map_mean(double* d_out, const double* d_maps, int n_maps, int64_t n, void* stream);
+eels_status eels_map_ratio(double* d_out, const double* d_num, const double* d_den, int64_t n, void* stream);
+
+/* Serving: EELS-map requests solved as they arrive on one GPU (continuous batching).  The
+ * problem statement of each request is that of eels_plan_create (Sec. 3: specimen slices,
+ * transition potentials, probe positions, aperture and detector angles in, map out).
+ *
+ *   eels_server_create   starts a dispatcher thread on `device` with `max_slots` streams (1 to
+ *                        64) and an HBM budget for the workspaces it allocates (the caller's
+ *                        inputs and maps are not counted).
+ *   eels_server_submit   plans the request on the calling thread (resident_s forced, one slice
+ *                        group) and queues it.  d_V, d_H: the request's device inputs as for
+ *                        eels_execute, already written (the server hashes their content at
+ *                        submit); d_map: float64 [n_probes], written when the request is done.
+ *                        All three stay caller-owned and must stay valid until the request is
+ *                        done.  *ticket identifies the request.  Errors: those of
+ *                        eels_plan_create, OOM when the workspace exceeds the whole budget.
+ *   Admission           first fit in arrival order while a slot is free and the workspace fits
+ *                        the budget (idle resident workspaces are freed least recently used to
+ *                        make room); a request overtaken 4 times blocks the ones behind it
+ *                        until it fits.  Admitted requests run concurrently on their streams.
+ *   Residency           a finished request's workspace stays allocated (its S-matrix data),
+ *                        keyed by the content of V and H and the plan's S signature; a later
+ *                        request with the same key runs with EELS_EXEC_SKIP_SWEEPS on it.
+ *   eels_server_poll     *done = 1 once the request has finished (its map written) or ended with
+ *                        an error; `t` (may be null) receives its timing and status.
+ *   eels_server_wait     as poll, waiting up to timeout_s seconds for the request to finish.
+ *   eels_server_cancel   ends a queued request with EELS_ERR_CANCELLED; INVALID_ARG if it has
+ *                        started or finished.
+ *   eels_server_release  forgets a finished request's record (its ticket becomes invalid).
+ *   eels_server_get_stats  counters since creation and the memory the server holds.
+ *   eels_server_destroy  cancels queued requests, waits for running ones, frees every
+ *                        workspace and stops the thread.
+ * A request's map equals that of a lone eels_execute of the same problem bit for bit, alone
+ * and in any mix (same kernels in the same order, no atomics).  Failures of one request (a
+ * failed allocation, a launch error) end that request with its status and release its slot
+ * and memory.  The server's functions are thread-safe; destroy must not race other calls. */
+typedef struct eels_server eels_server;
+typedef struct {
+    double arrival_s, start_s, finish_s;   /* seconds since eels_server_create (steady clock)  */
+    int resident_hit;                      /* 1: ran on a resident workspace (sweeps skipped)   */
+    eels_status status;                    /* EELS_OK, or the error that ended the request      */
+    size_t workspace_bytes;                /* the request's footprint                           */
+} eels_request_timing;
+typedef struct {
+    int64_t submitted, completed, failed, cancelled, resident_hits, evictions;
+    size_t resident_bytes;                 /* workspaces kept for residency                     */
+    int64_t resident_entries;
+    size_t running_bytes;                  /* fresh workspaces of running requests              */
+} eels_server_stats;
+eels_status eels_server_create(eels_server** out, int device, size_t hbm_budget_bytes, int max_slots);
+eels_status eels_server_submit(eels_server* s, const eels_problem* prob, const float* d_V, const void* d_H,
+                               double* d_map, uint64_t* ticket);
+eels_status eels_server_poll(eels_server* s, uint64_t ticket, int* done, eels_request_timing* t);
+eels_status eels_server_wait(eels_server* s, uint64_t ticket, double timeout_s, int* done, eels_request_timing* t);
+eels_status eels_server_cancel(eels_server* s, uint64_t ticket);
+eels_status eels_server_release(eels_server* s, uint64_t ticket);
+eels_status eels_server_get_stats(eels_server* s, eels_server_stats* out);
+eels_status eels_server_destroy(eels_server* s);
+
+/* The server's admission policy on its own (host only, for schedulers and tests): requests
+ * (ticket, footprint, arrival) are offered in arrival order; eels_admission_admit returns up to
+ * max_out tickets to start now (first fit while fewer than max_slots run and used + footprint
+ * <= capacity; once the oldest queued request has been overtaken max_overtake times nothing
+ * behind it is admitted until it fits); finish releases a running ticket's footprint.  offer
+ * returns OOM for a footprint above the budget; cancel INVALID_ARG for a ticket not queued. */
+typedef struct eels_admission eels_admission;
+eels_status eels_admission_create(eels_admission** out, size_t budget_bytes, int max_slots, int max_overtake);
+eels_status eels_admission_offer(eels_admission* a, uint64_t ticket, size_t footprint, double arrival);
+int eels_admission_admit(eels_admission* a, size_t capacity, uint64_t* tickets, int max_out);
+eels_status eels_admission_finish(eels_admission* a, uint64_t ticket);
+eels_status eels_admission_cancel(eels_admission* a, uint64_t ticket);
+size_t eels_admission_used(const eels_admission* a);
+eels_status eels_admission_destroy(eels_admission* a);
 
 /* Process-wide kernel tuning knobs, read at launch time (keys 3 to 6: at plan time; the
  * autotuner sets keys 0, 1, 4 and 5).

@@ -13,9 +13,11 @@ from .eels import (  # noqa: F401
     device_inputs,
     bf_corrected,
     load_library,
+    map_mean,
+    map_ratio,
     solve,
     solve_conventional,
     solve_with_images,
 )
 
-__version__ = "0.3"
+__version__ = "0.4"

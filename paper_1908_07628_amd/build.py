@@ -17,7 +17,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libeels.so")
 
-SOURCES = ["plan.cpp", "kernels_sweep.hip", "kernels_gemm.hip", "kernels_gram.hip", "kernels_conv.hip", "api.hip"]
+SOURCES = ["plan.cpp", "server.cpp", "kernels_sweep.hip", "kernels_gemm.hip", "kernels_gram.hip", "kernels_conv.hip",
+           "kernels_misc.hip", "api.hip"]
 ARCH = "gfx950"
 # The packed-fp32 feature is disabled for device code: ordinary float code only.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -58,6 +58,17 @@ class PlanInfo(C.Structure):
                 ("gram_form", C.c_int), ("window_gram_form", C.c_int)]
 
 
+class RequestTiming(C.Structure):
+    _fields_ = [("arrival_s", C.c_double), ("start_s", C.c_double), ("finish_s", C.c_double),
+                ("resident_hit", C.c_int), ("status", C.c_int), ("workspace_bytes", C.c_size_t)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("cancelled", C.c_int64), ("resident_hits", C.c_int64), ("evictions", C.c_int64),
+                ("resident_bytes", C.c_size_t), ("resident_entries", C.c_int64), ("running_bytes", C.c_size_t)]
+
+
 _LIB: Optional[C.CDLL] = None
 
 EXPORTS = ["eels_get_version", "eels_status_string", "eels_last_error", "eels_plan_create",
@@ -66,7 +77,11 @@ EXPORTS = ["eels_get_version", "eels_status_string", "eels_last_error", "eels_pl
            "eels_tune_set", "eels_tune_get", "eels_timing_enable", "eels_timing_read", "eels_execute_ex",
            "eels_plan_s_signature", "eels_execute_images", "eels_conventional_workspace_bytes",
            "eels_conventional_map", "eels_batch_create", "eels_batch_table_bytes", "eels_batch_upload",
-           "eels_batch_contract", "eels_batch_destroy"]
+           "eels_batch_contract", "eels_batch_destroy", "eels_map_mean", "eels_map_ratio", "eels_server_create",
+           "eels_server_submit", "eels_server_poll", "eels_server_wait", "eels_server_cancel", "eels_server_release",
+           "eels_server_get_stats", "eels_server_destroy", "eels_admission_create", "eels_admission_offer",
+           "eels_admission_admit", "eels_admission_finish", "eels_admission_cancel", "eels_admission_used",
+           "eels_admission_destroy"]
 EXEC_SKIP_UPLOAD, EXEC_SKIP_SWEEPS, EXEC_SWEEPS_ONLY = 1, 2, 4
 PHASES = ["setup", "sweep", "producer", "gemm1", "gemm2", "reduce", "images", "gram"]
 
@@ -105,6 +120,26 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.eels_batch_upload.argtypes = [vp, vp, vp]
     lib.eels_batch_contract.argtypes = [vp, vp, vp, C.POINTER(vp), C.POINTER(vp), vp]
     lib.eels_batch_destroy.argtypes = [vp]
+    lib.eels_map_mean.argtypes = [vp, vp, C.c_int, C.c_int64, vp]
+    lib.eels_map_ratio.argtypes = [vp, vp, vp, C.c_int64, vp]
+    u64 = C.c_uint64
+    lib.eels_server_create.argtypes = [C.POINTER(vp), C.c_int, sz, C.c_int]
+    lib.eels_server_submit.argtypes = [vp, C.POINTER(ProblemC), vp, vp, vp, C.POINTER(u64)]
+    lib.eels_server_poll.argtypes = [vp, u64, C.POINTER(C.c_int), C.POINTER(RequestTiming)]
+    lib.eels_server_wait.argtypes = [vp, u64, C.c_double, C.POINTER(C.c_int), C.POINTER(RequestTiming)]
+    lib.eels_server_cancel.argtypes = [vp, u64]
+    lib.eels_server_release.argtypes = [vp, u64]
+    lib.eels_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
+    lib.eels_server_destroy.argtypes = [vp]
+    lib.eels_admission_create.argtypes = [C.POINTER(vp), sz, C.c_int, C.c_int]
+    lib.eels_admission_offer.argtypes = [vp, u64, sz, C.c_double]
+    lib.eels_admission_admit.argtypes = [vp, sz, C.POINTER(u64), C.c_int]
+    lib.eels_admission_admit.restype = C.c_int
+    lib.eels_admission_finish.argtypes = [vp, u64]
+    lib.eels_admission_cancel.argtypes = [vp, u64]
+    lib.eels_admission_used.argtypes = [vp]
+    lib.eels_admission_used.restype = sz
+    lib.eels_admission_destroy.argtypes = [vp]
     lib.eels_tune_set.argtypes = [C.c_int, C.c_int]
     lib.eels_tune_get.argtypes = [C.c_int]
     lib.eels_timing_enable.argtypes = [C.c_int]
@@ -130,6 +165,38 @@ def _stream(stream) -> int:
     return int(stream.cuda_stream)
 
 
+def problem_struct(pr: Any, precision: str = "fp32", order: str = "auto", max_workspace_bytes: int = 0,
+                   lambda_A: float = 0.0, sigma: float = 0.0, real_space: bool = False, resident_s: bool = False,
+                   detector_sum: str = "auto", images=(), s1_mode: str = "stored"):
+    """The C problem statement (eels_problem) of a problem object, and the arrays it points
+    into (keep them alive as long as the struct is used)."""
+    img = np.ascontiguousarray(np.asarray(images, dtype=np.float64).reshape(-1, 2))
+    dz = np.ascontiguousarray(pr.dz, dtype=np.float64)
+    probes = np.ascontiguousarray(pr.probes, dtype=np.float64).reshape(-1, 2)
+    S = len(pr.site_slice)
+    sites = (Site * max(S, 1))()
+    for s in range(S):
+        sites[s] = Site(int(pr.site_slice[s]), int(pr.site_ntrans[s]), float(pr.site_xy[s][0]),
+                        float(pr.site_xy[s][1]), int(pr.site_hoff[s]))
+    n_trans = int(pr.H.shape[0]) if getattr(pr, "H", None) is not None else int(
+        max([int(pr.site_hoff[s]) + int(pr.site_ntrans[s]) for s in range(S)], default=0))
+    pc = ProblemC(
+        nx=int(pr.nx), ny=int(pr.ny), lx_A=float(pr.lx), ly_A=float(pr.ly), n_slices=len(dz),
+        dz_A=dz.ctypes.data_as(C.POINTER(C.c_double)), energy_eV=float(pr.energy_eV),
+        lambda_A=float(lambda_A), sigma=float(sigma), aperture_mrad=float(pr.aperture_mrad),
+        det_inner_mrad=float(pr.det_inner_mrad), det_outer_mrad=float(pr.det_outer_mrad),
+        defocus_A=float(getattr(pr, "defocus_A", 0.0)), cs_A=float(getattr(pr, "cs_A", 0.0)),
+        interp_f=int(pr.interp_f), bandlimit=float(pr.bandlimit), window_A=float(pr.window_A),
+        n_probes=int(probes.shape[0]),
+        probe_xy=probes.ctypes.data_as(C.POINTER(C.c_double)), n_sites=S,
+        sites=sites, n_trans_total=n_trans, precision=PRECISIONS[precision], order=ORDERS[order],
+        max_workspace_bytes=int(max_workspace_bytes), real_space=int(bool(real_space)),
+        resident_s=int(bool(resident_s)), detector_sum=DETSUMS[detector_sum],
+        s1_mode={"stored": 0, "inverse": 1}[s1_mode], n_images=int(img.shape[0]),
+        image_detectors_mrad=img.ctypes.data_as(C.POINTER(C.c_double)))
+    return pc, {"img": img, "dz": dz, "probes": probes, "sites": sites}
+
+
 class Plan:
     """Host plan of one map request.  ``problem`` is any object with the fields of the
     problem statement (grid, cell, slices, optics, sites, probes; see include/eels.h)."""
@@ -146,32 +213,14 @@ class Plan:
         self._source = (problem, dict(precision=precision, order=order, max_workspace_bytes=max_workspace_bytes,
                                       lambda_A=lambda_A, sigma=sigma, real_space=real_space, resident_s=resident_s,
                                       detector_sum=detector_sum, images=images, s1_mode=s1_mode))
-        self._img = np.ascontiguousarray(np.asarray(images, dtype=np.float64).reshape(-1, 2))
-        self.n_images = int(self._img.shape[0])
+        self.problem, self._keep = problem_struct(
+            problem, precision=precision, order=order, max_workspace_bytes=max_workspace_bytes, lambda_A=lambda_A,
+            sigma=sigma, real_space=real_space, resident_s=resident_s, detector_sum=detector_sum, images=images,
+            s1_mode=s1_mode)
+        self.n_images = int(self.problem.n_images)
+        self._probes = self._keep["probes"]
+        self._dz = self._keep["dz"]
         pr = problem
-        self._dz = np.ascontiguousarray(pr.dz, dtype=np.float64)
-        self._probes = np.ascontiguousarray(pr.probes, dtype=np.float64).reshape(-1, 2)
-        S = len(pr.site_slice)
-        self._sites = (Site * max(S, 1))()
-        for s in range(S):
-            self._sites[s] = Site(int(pr.site_slice[s]), int(pr.site_ntrans[s]), float(pr.site_xy[s][0]),
-                                  float(pr.site_xy[s][1]), int(pr.site_hoff[s]))
-        n_trans = int(pr.H.shape[0]) if getattr(pr, "H", None) is not None else int(
-            max([int(pr.site_hoff[s]) + int(pr.site_ntrans[s]) for s in range(S)], default=0))
-        self.problem = ProblemC(
-            nx=int(pr.nx), ny=int(pr.ny), lx_A=float(pr.lx), ly_A=float(pr.ly), n_slices=len(self._dz),
-            dz_A=self._dz.ctypes.data_as(C.POINTER(C.c_double)), energy_eV=float(pr.energy_eV),
-            lambda_A=float(lambda_A), sigma=float(sigma), aperture_mrad=float(pr.aperture_mrad),
-            det_inner_mrad=float(pr.det_inner_mrad), det_outer_mrad=float(pr.det_outer_mrad),
-            defocus_A=float(getattr(pr, "defocus_A", 0.0)), cs_A=float(getattr(pr, "cs_A", 0.0)),
-            interp_f=int(pr.interp_f), bandlimit=float(pr.bandlimit), window_A=float(pr.window_A),
-            n_probes=int(self._probes.shape[0]),
-            probe_xy=self._probes.ctypes.data_as(C.POINTER(C.c_double)), n_sites=S,
-            sites=self._sites, n_trans_total=n_trans, precision=PRECISIONS[precision], order=ORDERS[order],
-            max_workspace_bytes=int(max_workspace_bytes), real_space=int(bool(real_space)),
-            resident_s=int(bool(resident_s)), detector_sum=DETSUMS[detector_sum],
-            s1_mode={"stored": 0, "inverse": 1}[s1_mode], n_images=self.n_images,
-            image_detectors_mrad=self._img.ctypes.data_as(C.POINTER(C.c_double)))
         self.precision = precision
         h = C.c_void_p()
         _check(lib.eels_plan_create(C.byref(h), C.byref(self.problem)))
@@ -370,9 +419,39 @@ def solve_with_images(problem, images, precision: str = "fp32", device="cuda", *
     return out.cpu().numpy(), img.cpu().numpy()
 
 
-def bf_corrected(eels_map, ibf):
-    """EELS map divided by the incoherent bright-field image of the EELS detector's angles."""
-    return np.asarray(eels_map) / np.asarray(ibf)
+def map_mean(maps, out=None, stream=None):
+    """Device mean over the first axis of maps (float64 [n_maps, n]) by eels_map_mean (FP64, in
+    configuration order); returns out (float64 [n])."""
+    import torch
+    if maps.dtype != torch.float64 or maps.dim() != 2 or not maps.is_contiguous():
+        raise EelsError(1, "maps must be a contiguous float64 [n_maps, n] device tensor")
+    if out is None:
+        out = torch.empty(maps.shape[1], dtype=torch.float64, device=maps.device)
+    _check(load_library().eels_map_mean(_ptr(out), _ptr(maps), int(maps.shape[0]), int(maps.shape[1]),
+                                        _stream(stream)))
+    return out
+
+
+def map_ratio(num, den, out=None, stream=None):
+    """Device num / den where den > 0, else 0 (eels_map_ratio), float64 tensors of one length."""
+    import torch
+    if num.numel() != den.numel() or num.dtype != torch.float64 or den.dtype != torch.float64:
+        raise EelsError(1, "num and den must be float64 tensors of one length")
+    if out is None:
+        out = torch.empty_like(num)
+    _check(load_library().eels_map_ratio(_ptr(out), _ptr(num), _ptr(den), int(num.numel()), _stream(stream)))
+    return out
+
+
+def bf_corrected(eels_map, ibf, device="cuda"):
+    """EELS map divided by the incoherent bright-field image of the EELS detector's angles
+    (device division by eels_map_ratio; host arrays in and out)."""
+    import torch
+    num = torch.as_tensor(np.ascontiguousarray(eels_map, dtype=np.float64)).to(device)
+    den = torch.as_tensor(np.ascontiguousarray(ibf, dtype=np.float64)).to(device)
+    out = map_ratio(num, den)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
 
 
 def gemm_work_bytes(m: int, n: int, k: int) -> int:

@@ -5,7 +5,8 @@ ones) by random offsets; the frozen-phonon map is the average of the maps of sev
 configurations (the Results' nanoparticle run is one such configuration, and the runtime
 discussion counts passes per configuration).  Every configuration is one full map through
 the C ABI; the maps share one workspace (their plans have the same layout when the
-configurations share grid, slices, sites' slices and probes).
+configurations share grid, slices, sites' slices and probes), and their mean is taken on
+the device by eels_map_mean.
 """
 from __future__ import annotations
 
@@ -33,6 +34,6 @@ def frozen_phonon_map(configs: Sequence, precision: str = "bf16_split", device: 
     for i, (c, pl) in enumerate(zip(configs, plans)):
         V, H = eels.device_inputs(c, device)
         pl.execute(V, H, maps[i], ws)
+    mean = eels.map_mean(maps)                 # FP64 mean on the device, in configuration order
     torch.cuda.synchronize()
-    per = maps.cpu().numpy()
-    return per.mean(axis=0), per
+    return mean.cpu().numpy(), maps.cpu().numpy()

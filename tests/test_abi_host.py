@@ -36,7 +36,7 @@ def test_version_and_status_strings():
     import ctypes as C
     a, b = C.c_int(), C.c_int()
     assert lib.eels_get_version(C.byref(a), C.byref(b)) == 0
-    assert (a.value, b.value) == (0, 3)
+    assert (a.value, b.value) == (0, 4)
     assert lib.eels_status_string(2) == b"beam outside the band limit"
 
 

@@ -209,24 +209,62 @@ def test_resident_s_matrices_serve_new_probes_window_gram():
     assert maps_close(got, prism.prism_map(q), 1e-3)
 
 
-def test_server_results_equal_alone_and_in_the_mix():
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16_split", 1e-3)])
+def test_server_results_equal_alone_and_in_the_mix(prec, tol):
+    """Requests served through eels_server_* (continuous batching on 3 streams) give maps bitwise
+    equal to a lone solve of each problem, and within the precision's bar of the oracle.  The
+    first request finishes before the rest arrive, so its repeat (new probes) runs on its
+    resident S-matrices."""
     eels = _gpu()
     from paper_1908_07628_amd.serve import Server
     sp = _specimens(4, seed=13)
-    reqs = [sp[0], sp[1], sp[2], sp[0].replace(probes=sp[0].probes + 0.37), sp[3],
+    reqs = [sp[1], sp[2], sp[0].replace(probes=sp[0].probes + 0.37), sp[3],
             sp[1].replace(probes=sp[1].probes + 0.11)]
-    solo = [eels.solve(r, precision="fp32") for r in reqs]
-    srv = Server(hbm_budget_bytes=int(40e9), max_slots=3, precision="fp32", residency=True)
+    first = sp[0]
+    solo = [eels.solve(r, precision=prec) for r in [first] + reqs]
+    srv = Server(hbm_budget_bytes=int(40e9), max_slots=3, precision=prec)
     try:
+        t0 = srv.submit(first)
+        r0 = srv.wait(t0, timeout=300)
+        assert r0.error is None and np.array_equal(r0.map, solo[0])
         tickets = [srv.submit(r) for r in reqs]
-        res = [srv.wait(t, timeout=300) for t in tickets]
+        res = [r0] + [srv.wait(t, timeout=300) for t in tickets]
         for k, r in enumerate(res):
             assert r.error is None, r.error
             assert np.array_equal(r.map, solo[k]), k
+            assert maps_close(r.map, prism.prism_map(([first] + reqs)[k]), tol), k
+        assert res[3].resident_hit                 # the repeat of the first specimen
         st = srv.latency_stats()
-        _say("serve stats", st)
-        assert st["n"] == len(reqs) and st["p99_s"] >= st["p50_s"] > 0
-        assert st["resident_hits"] >= 1
+        _say("serve stats", st, srv.stats())
+        assert st["n"] == len(res) and st["p99_s"] >= st["p50_s"] > 0
+        assert srv.stats()["completed"] == len(res)
+    finally:
+        srv.close()
+
+
+def test_server_evicts_and_readmits_under_a_small_budget():
+    """A budget that holds one workspace: each new specimen evicts the idle resident one, a
+    repeat of an evicted specimen runs afresh, a repeat of the resident one reuses it, and every
+    map equals the lone solve."""
+    eels = _gpu()
+    from paper_1908_07628_amd.serve import Server
+    sp = _specimens(2, seed=21)
+    a, b = sp[0], sp[1]
+    wa = eels.Plan(a, resident_s=True).workspace_bytes
+    wb = eels.Plan(b, resident_s=True).workspace_bytes
+    solo_a, solo_b = eels.solve(a), eels.solve(b)
+    budget = max(wa, wb) + min(wa, wb) // 2          # either alone, never both
+    srv = Server(hbm_budget_bytes=budget, max_slots=2)
+    try:
+        seq = [(a, solo_a, False), (b, solo_b, False), (a, solo_a, False), (a, solo_a, True)]
+        for k, (p, ref, hit) in enumerate(seq):
+            r = srv.wait(srv.submit(p), timeout=120)       # one at a time
+            assert r.error is None and np.array_equal(r.map, ref), k
+            assert r.resident_hit == hit, k
+        st = srv.stats()
+        _say("small-budget stats", st)
+        assert st["evictions"] == 2 and st["resident_hits"] == 1 and st["resident_entries"] == 1
+        assert st["resident_bytes"] <= budget
     finally:
         srv.close()
 
@@ -234,10 +272,32 @@ def test_server_results_equal_alone_and_in_the_mix():
 def test_server_rejects_request_over_budget():
     eels = _gpu()
     from paper_1908_07628_amd.serve import Server
-    srv = Server(hbm_budget_bytes=int(1e6), max_slots=1, precision="fp32", residency=False)
+    srv = Server(hbm_budget_bytes=int(1e6), max_slots=1, precision="fp32")
     try:
-        t = srv.submit(synth.config1())
-        r = srv.wait(t, timeout=30)
-        assert r.error is not None and "budget" in r.error
+        with pytest.raises(eels.EelsError) as e:
+            srv.submit(synth.config1())
+        assert e.value.args[0] == 5 and "budget" in e.value.args[1]      # EELS_ERR_OOM
+    finally:
+        srv.close()
+
+
+def test_server_recovers_from_a_failed_request():
+    """A request admitted under a budget larger than the device (the whole nanoparticle map with
+    every slice's S-matrix data resident, about 2 TB) fails to allocate its workspace: it ends
+    with EELS_ERR_OOM, and the slot and its footprint are released, so the next request runs."""
+    eels = _gpu()
+    from paper_1908_07628_amd.serve import Server
+    big = synth.config3()
+    small = _specimens(1, seed=5)[0]
+    ref = eels.solve(small)
+    srv = Server(hbm_budget_bytes=int(8e12), max_slots=1)
+    try:
+        r = srv.wait(srv.submit(big), timeout=120)
+        _say("big request", r.status, r.error, r.workspace_bytes / 1e12, "TB")
+        assert r.done and r.status == 5 and r.map is None
+        st = srv.stats()
+        assert st["failed"] == 1 and st["running_bytes"] == 0
+        r2 = srv.wait(srv.submit(small), timeout=120)
+        assert r2.error is None and np.array_equal(r2.map, ref)
     finally:
         srv.close()
