@@ -276,7 +276,7 @@ def test_server_rejects_request_over_budget():
     try:
         with pytest.raises(eels.EelsError) as e:
             srv.submit(synth.config1())
-        assert e.value.args[0] == 5 and "budget" in e.value.args[1]      # EELS_ERR_OOM
+        assert e.value.status == 5 and "budget" in str(e.value)      # EELS_ERR_OOM
     finally:
         srv.close()
 
