@@ -209,6 +209,17 @@ enum { EELS_EXEC_SKIP_UPLOAD = 1, EELS_EXEC_SKIP_SWEEPS = 2, EELS_EXEC_SWEEPS_ON
 eels_status eels_execute_ex(const eels_plan* p, const float* d_V, const void* d_H, double* d_map,
                             void* d_workspace, size_t workspace_bytes, void* stream, unsigned flags);
 
+/* eels_execute without a workspace argument, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid allocation).  The
+ * workspace is a fixed 128 MiB device array inside the library (one per device, held until the
+ * process ends); the call allocates nothing and enqueues on `stream` like eels_execute.  Plans
+ * whose eels_plan_workspace_bytes exceed 128 MiB (about the size of the 64 x 64-pixel cells
+ * with a few hundred beams) are refused with EELS_ERR_WORKSPACE.  Every call on one device
+ * shares that array, so calls that overlap on one device (different streams or threads
+ * without ordering) race: order them on one stream or serialise them.  The map equals that of
+ * eels_execute bit for bit.  Errors as eels_execute. */
+eels_status eels_execute_noalloc(const eels_plan* p, const float* d_V, const void* d_H, double* d_map, void* stream);
+
 /* As eels_execute_ex, and also writes the plan's elastic companion images:
  * d_images float64 [n_images][n_probes], overwritten (may be null when n_images = 0).  The
  * forward sweep then continues to the exit plane and captures the exit wave's band

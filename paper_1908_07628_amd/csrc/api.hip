@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -671,6 +672,58 @@ eels_status eels_execute_images(const eels_plan* pl, const float* d_V, const voi
     if (!sweeps_only) finish_map(p, d, d_map, st);
     HIPCHK(hipGetLastError());
     return EELS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- allocation-free execution
+// A fixed device array stands in for the workspace of eels_execute_noalloc.  Each device the
+// library runs on holds its own copy at its own address, found once per device with
+// hipGetSymbolAddress; host code uses only that address, never the array's name.
+namespace eels {
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)128 << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+}  // namespace eels
+static __device__ __align__(256) unsigned char scratch[eels::NOALLOC_SCRATCH_BYTES];
+static void* g_scratch_addr[eels::NOALLOC_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+extern "C" {
+
+eels_status eels_execute_noalloc(const eels_plan* pl, const float* d_V, const void* d_H, double* d_map,
+                                 void* stream) {
+    if (!pl) {
+        set_error("null argument");
+        return EELS_ERR_INVALID_ARG;
+    }
+    if (pl->p.ws_bytes > NOALLOC_SCRATCH_BYTES) {
+        set_error("the plan needs " + std::to_string(pl->p.ws_bytes) +
+                  " workspace bytes; eels_execute_noalloc holds at most " + std::to_string(NOALLOC_SCRATCH_BYTES));
+        return EELS_ERR_WORKSPACE;
+    }
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+        set_error("device index beyond the allocation-free entry point's table");
+        return EELS_ERR_INVALID_ARG;
+    }
+    void* ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_addr[dev]) {
+            void* a = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !a) {
+                set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+                return EELS_ERR_DEVICE;
+            }
+            g_scratch_addr[dev] = a;
+        }
+        ptr = g_scratch_addr[dev];
+    }
+    // every buffer the map reads is written first by the same call (tables, T, P, sweeps,
+    // partial sums, the zeroed S_2 padding), so the previous call's contents do not matter
+    return eels_execute_ex(pl, d_V, d_H, d_map, ptr, NOALLOC_SCRATCH_BYTES, stream, 0u);
 }
 
 size_t eels_conventional_workspace_bytes(const eels_plan* pl, int probe_chunk) {

@@ -81,7 +81,7 @@ EXPORTS = ["eels_get_version", "eels_status_string", "eels_last_error", "eels_pl
            "eels_server_submit", "eels_server_poll", "eels_server_wait", "eels_server_cancel", "eels_server_release",
            "eels_server_get_stats", "eels_server_destroy", "eels_admission_create", "eels_admission_offer",
            "eels_admission_admit", "eels_admission_finish", "eels_admission_cancel", "eels_admission_used",
-           "eels_admission_destroy"]
+           "eels_admission_destroy", "eels_execute_noalloc"]
 EXEC_SKIP_UPLOAD, EXEC_SKIP_SWEEPS, EXEC_SWEEPS_ONLY = 1, 2, 4
 PHASES = ["setup", "sweep", "producer", "gemm1", "gemm2", "reduce", "images", "gram"]
 
@@ -120,6 +120,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.eels_batch_upload.argtypes = [vp, vp, vp]
     lib.eels_batch_contract.argtypes = [vp, vp, vp, C.POINTER(vp), C.POINTER(vp), vp]
     lib.eels_batch_destroy.argtypes = [vp]
+    lib.eels_execute_noalloc.argtypes = [vp, vp, vp, vp, vp]
     lib.eels_map_mean.argtypes = [vp, vp, C.c_int, C.c_int64, vp]
     lib.eels_map_ratio.argtypes = [vp, vp, vp, C.c_int64, vp]
     u64 = C.c_uint64
