@@ -161,6 +161,7 @@ typedef struct {
     size_t workspace_bytes;
     int gram_form;           /* 1 if the detector sum uses the Gram form (EELS_DETSUM_GRAM) */
     int window_gram_form;    /* 1 if order P uses the window-Gram detector sum (tuning key 6) */
+    int raster_form;         /* DFT side M of its raster form (tuning key 7), 0 if not used  */
 } eels_plan_info;
 
 typedef struct eels_plan eels_plan;
@@ -388,7 +389,7 @@ eels_status eels_admission_cancel(eels_admission* a, uint64_t ticket);
 size_t eels_admission_used(const eels_admission* a);
 eels_status eels_admission_destroy(eels_admission* a);
 
-/* Process-wide kernel tuning knobs, read at launch time (keys 3 to 6: at plan time; the
+/* Process-wide kernel tuning knobs, read at launch time (keys 3 to 7: at plan time; the
  * autotuner sets keys 0, 1, 4 and 5).
  * key 0: LDS pipeline of the split-precision GEMM: 2 (two stages of 16-complex tiles, two
  *        workgroups per CU, default), 3 (three such stages, one workgroup per CU), 4 or 5
@@ -416,6 +417,15 @@ eels_status eels_admission_destroy(eels_admission* a);
  *        sites (it does with many eligible probes per site): 1 (default) this form where
  *        it needs fewer flops, 2 wherever it applies, 0 never (the per-transition
  *        products).  A fused batch (eels_batch_create) takes plans made with 0.
+ * key 7: the raster form of the window-Gram detector sum.  When every probe lies on a raster
+ *        aligned with the beam lattice, R = R_0 + (i L_x / (f M), j L_y / (f M)) with integer i, j
+ *        and M = 64 (e.g. a 256 x 256 scan at f = 4), and the aperture beams' lattice coordinates
+ *        (a, b) each span fewer than M values, c_k(R) = c_k(R_0) exp(-2 pi i (a i + b j) / M):
+ *        Psi for all probes is one M x M DFT over the beam lattice per window pixel, and so is
+ *        G Psi, from Z = G S_1w^T.  This replaces the products C S_1w (P_s K N_1) and G Psi
+ *        (P_s K^2) by one K^2 N_1 product and FFTs; the same sums, regrouped exactly.  1
+ *        (default) where it applies and needs fewer flops than the form chosen otherwise, 2
+ *        wherever it applies, 0 never.
  * Returns EELS_ERR_INVALID_ARG for an unknown key or an out-of-range value. */
 eels_status eels_tune_set(int key, int value);
 int eels_tune_get(int key);
@@ -434,7 +444,8 @@ enum {
     EELS_PHASE_REDUCE = 5,    /* FP64 per-probe reduction                                  */
     EELS_PHASE_IMAGES = 6,    /* elastic companion images (exit capture excluded)          */
     EELS_PHASE_GRAM = 7,      /* window-Gram form: Gram GEMM of each site's S_2 window     */
-    EELS_PHASES = 8
+    EELS_PHASE_RASTER = 8,    /* raster form: the DFTs of Psi and Y over the beam lattice  */
+    EELS_PHASES = 9
 };
 eels_status eels_timing_enable(int capacity);
 eels_status eels_timing_read(double* ms, int* counts);

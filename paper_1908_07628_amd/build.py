@@ -18,7 +18,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libeels.so")
 
 SOURCES = ["plan.cpp", "server.cpp", "kernels_sweep.hip", "kernels_gemm.hip", "kernels_gram.hip", "kernels_conv.hip",
-           "kernels_misc.hip", "api.hip"]
+           "kernels_misc.hip", "kernels_raster.hip", "api.hip"]
 ARCH = "gfx950"
 # The packed-fp32 feature is disabled for device code: ordinary float code only.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -34,7 +34,7 @@ namespace eels {
 static thread_local std::string g_err;
 void set_error(const std::string& m) { g_err = m; }
 
-static std::atomic<int> g_tune[TUNE_COUNT] = {{2}, {2}, {0}, {1}, {1}, {1}, {1}, {0}};
+static std::atomic<int> g_tune[TUNE_COUNT] = {{2}, {2}, {0}, {1}, {1}, {1}, {1}, {1}};
 int tune_get(int key) { return (key >= 0 && key < TUNE_COUNT) ? g_tune[key].load() : 0; }
 
 // Diagnostic phase timing (eels_timing_enable / eels_timing_read).
@@ -86,6 +86,7 @@ struct Dev {
     double* qpart;    // Gram form: per-probe partial quadratic forms
     float2 *img_exit, *img_masked, *img_part, *img_C;   // companion images
     double *img_G, *img_qpart;
+    float2 *r_c0, *r_tw;                                  // raster form: c_k(R_0), M-point twiddles
 };
 
 Dev make_dev(const Plan& p, void* ws_) {
@@ -120,6 +121,8 @@ Dev make_dev(const Plan& p, void* ws_) {
     d.img_C = (float2*)(d.ws + p.off_img_C);
     d.img_G = (double*)(d.ws + p.off_img_G);
     d.img_qpart = (double*)(d.ws + p.off_img_qpart);
+    d.r_c0 = (float2*)(d.ws + p.off_r_c0);
+    d.r_tw = (float2*)(d.ws + p.off_r_tw);
     return d;
 }
 
@@ -143,6 +146,10 @@ eels_status setup(const Plan& p, const Dev& d, const float* dV, hipStream_t st, 
     launch_twiddles(d.twy, p.ny, st);
     launch_transmission(d.T, dV, (int64_t)p.nz * p.ny * p.nx, p.sigma, st);
     launch_propagator(d.P, d.dz, p, st);
+    if (p.raster) {
+        launch_twiddles(d.r_tw, p.rM, st);
+        launch_probe_coefficients(d.r_c0, d.b1, d.probes, p, 0, st, 1);   // c_k(R_0), R_0 = the first probe
+    }
     return EELS_OK;
 }
 
@@ -281,7 +288,7 @@ void producers_before_gemm1(const Plan& p, const Dev& d, const float2* dH, const
     const bool split = p.precision != EELS_FP32;
     if (p.gram || p.order == EELS_ORDER_S_FIRST) {
         if (split || p.recip) run_jobs(p, d, dH, b, b.slice, st);
-    } else if (split) {
+    } else if (split && !p.raster) {
         // SC transposes of the sites' S_1 windows (mid2 holds them until the producer runs)
         TimeScope ts(EELS_PHASE_PRODUCER, st);
         for (int k = 0; k < b.job_count; ++k) {
@@ -300,6 +307,13 @@ void producers_after_gemm1(const Plan& p, const Dev& d, const float2* dH, const 
         for (int k = 0; k < b.job_count; ++k) {
             const Job& jb = p.jobs[b.job_begin + k];
             launch_window_t_sc(d.mid2 + jb.s2t_off, d.w2 + jb.w_off, p.Kpad, p.N2, p.K, p.N2p, p.precision, st);
+            if (p.raster) {
+                // the S_1 window transposed into beam-slot order (complex64, the DFTs' input) and,
+                // in split precision, its SC copy (the Z GEMM's B operand)
+                launch_window_t_sc(d.mid2 + jb.xt_off, d.w1 + jb.win_off, p.Kpad, p.N1, p.K, p.N1pad, EELS_FP32, st,
+                                   d.blob + p.r_perm_off);
+                if (split) launch_to_sc(d.mid2 + jb.s1sc_off, d.w1 + jb.win_off, p.N1, p.K, p.Kpad, p.precision, st);
+            }
         }
         return;
     }
@@ -332,6 +346,22 @@ void wgram_contract(const Plan& p, const Dev& d, const float2* dH, const Batch& 
             launch_wgram_combine(d.mid2 + jb.g_off, d.mid2 + jb.m_off, dH + jb.h_off, jb.nt, p.K, p.Kpad, p.Kpad,
                                  gscale, p.precision, st);
         }
+    }
+    if (p.raster) {
+        {
+            // Z = G S_1w^T, the window's beams gathered into slot order
+            TimeScope ts(EELS_PHASE_GEMM2, st);
+            if (split)
+                launch_cgemm_sc(p.precision, 3, nst, d.descs + b.dy_begin, b.dy_count, b.dy_tiles, d.mid2, d.mid2,
+                                d.mid2, nullptr, d.blob, st, b.dy_rows);
+            else
+                launch_cgemm(EELS_FP32, 0, 0, d.descs + b.dy_begin, b.dy_count, b.dy_tiles, d.mid2, d.w1, nullptr,
+                             d.mid2, nullptr, d.blob, st);
+        }
+        TimeScope ts(EELS_PHASE_RASTER, st);
+        launch_raster_dot((const RasterJob*)(d.blob + b.r_jobs), b.job_count, d.mid2, d.r_c0, d.blob + p.r_perm_off,
+                          d.blob + p.r_pos_off, p.rM, p.K, p.N1pad, p.r_chunk, 1.0f / gscale, d.r_tw, d.part, st);
+        return;
     }
     {
         TimeScope ts(EELS_PHASE_GEMM2, st);
@@ -551,6 +581,7 @@ eels_status eels_plan_info_get(const eels_plan* pl, eels_plan_info* info) {
     info->band_basis = p.recip ? 1 : 0;
     info->band_pixels = p.Kb;
     info->window_gram_form = p.wgram ? 1 : 0;
+    info->raster_form = p.raster ? p.rM : 0;
     info->lambda_A = p.lam;
     info->sigma = p.sigma;
     info->gemm_flops = p.gemm_flops;
@@ -977,6 +1008,7 @@ eels_status eels_tune_set(int key, int value) {
     if (key == TUNE_GEMM1_ROWS && (value < 0 || value > 1)) return EELS_ERR_INVALID_ARG;
     if (key == TUNE_GEMM2_ROWS && (value < 0 || value > 1)) return EELS_ERR_INVALID_ARG;
     if (key == TUNE_WINDOW_GRAM && (value < 0 || value > 2)) return EELS_ERR_INVALID_ARG;
+    if (key == TUNE_RASTER && (value < 0 || value > 2)) return EELS_ERR_INVALID_ARG;
     g_tune[key].store(value);
     return EELS_OK;
 }

@@ -44,7 +44,7 @@ static_assert(sizeof(GemmDesc) == 144, "GemmDesc layout");
 // Process-wide tuning knobs (set by eels_tune_set; read at launch time).
 enum TuneKey {
     TUNE_SC_STAGES = 0, TUNE_TILE_ORDER = 1, TUNE_SC_SCHED = 2, TUNE_GRAM_STACK = 3, TUNE_GEMM1_ROWS = 4,
-    TUNE_GEMM2_ROWS = 5, TUNE_WINDOW_GRAM = 6, TUNE_COUNT = 8
+    TUNE_GEMM2_ROWS = 5, TUNE_WINDOW_GRAM = 6, TUNE_RASTER = 7, TUNE_COUNT = 8
 };
 int tune_get(int key);
 
@@ -64,7 +64,16 @@ struct Batch {
     // window (dm) and the product of G with Psi (dy); the d2 range then only drives the reduction
     int dm_begin = 0, dm_count = 0, dm_tiles = 0;
     int dy_begin = 0, dy_count = 0, dy_tiles = 0, dy_rows = 128;
+    int64_t r_jobs = -1;                // raster form: int offset of the batch's RasterJob table
 };
+
+// Raster form of the window-Gram detector sum, per site: complex offsets (in mid2) of the
+// site's S_1 window transposed into beam-slot order Xt [K][N1pad] and of Z = G S_1w^T
+// [K][N1pad]; the float offset of its DFT-block partial sums in part.
+struct RasterJob {
+    int64_t xt, z, part;
+};
+static_assert(sizeof(RasterJob) == 24, "RasterJob layout");
 
 // Producer job: write the H-multiplied operand of one site into mid2, either in the band
 // basis (fft2 of T_j H_t W_i) or pixel-wise (H_t W_i), from S_1 windows or from Psi.
@@ -80,6 +89,9 @@ struct Job {
     // the site's first float in part; eligible probes P_s
     int64_t s2t_off = 0, m_off = 0, g_off = 0, y_off = 0, psi_off = 0, part_off = 0;
     int ps = 0;
+    // raster form: Xt (complex64, beam-slot order) and the split copy of the S_1 window [N_1][Kpad]
+    // (the Z GEMM's B operand); Z sits at y_off
+    int64_t xt_off = 0, s1sc_off = 0;
 };
 
 struct SliceInfo {
@@ -131,6 +143,13 @@ struct Plan {
                                                 // windows (N_2 rows) and Psi is the shared operand
     bool wgram = false;                         // order P, cropped windows: the detector sum as
                                                 // Psi^H (M o sum_t conj(H_t) H_t^T) Psi, M = S_2w^H S_2w
+    bool raster = false;                        // window-Gram form with Psi and Y = G Psi taken by M x M
+                                                // DFTs over the beam lattice (probes on an aligned raster)
+    int rM = 0;                                 // DFT side M of the raster form
+    int r_chunk = 0, r_chunks = 0;              // window pixels per DFT block, blocks per site
+    std::vector<int> r_res;                     // per probe: (i mod M) + M (j mod M), offsets from probe 0
+    int64_t r_perm_off = -1;                    // int offset: beam of each compact slot column q
+    int64_t r_pos_off = -1;                     // int offset: compact column of grid slot (b mod M) M + (a mod M)
     bool s1_inverse = false;                    // S_1 retreated with the inverse multislice
     int n_img = 0;                              // elastic companion images
     std::vector<double> img_in, img_out;        // their ring angles (rad; out < 0: band limit)
@@ -166,7 +185,7 @@ struct Plan {
     // workspace layout (byte offsets)
     size_t off_blob, off_twx, off_twy, off_T, off_P, off_C, off_s1, off_s2, off_w1, off_w2,
         off_mid, off_mid2, off_scratch, off_part, off_gtot, off_qpart, off_img_exit, off_img_masked, off_img_part,
-        off_img_G, off_img_qpart, off_img_C, ws_bytes;
+        off_img_G, off_img_qpart, off_img_C, off_r_c0, off_r_tw, ws_bytes;
 };
 
 eels_status build_plan(Plan& p, const eels_problem& prob);

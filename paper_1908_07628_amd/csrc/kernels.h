@@ -55,8 +55,9 @@ void launch_twiddles(float2* tw, int n, hipStream_t st);
 void launch_transmission(float2* T, const float* V, int64_t n, double sigma, hipStream_t st);
 // Propagator factor tables, slice j at P + j (nlx + ny): column factors then row factors.
 void launch_propagator(float2* P, const double* dz, const Plan& p, hipStream_t st);
+// c_k(R) for the first n_probes probes (-1: all of the plan's), rows of N1pad
 void launch_probe_coefficients(void* C, const int4* beams, const double* probes, const Plan& p, int sc,
-                               hipStream_t st);
+                               hipStream_t st, int n_probes = -1);
 void launch_init_band(void* bcap, int64_t bstride, const int4* beams, const int* band_h, const int* band_off,
                       const Plan& p, int sc, hipStream_t st);
 void launch_band_fft(int nx, int ny, const BandFft& a, hipStream_t st);
@@ -99,8 +100,16 @@ void launch_cgemm_sc(int precision, int epi, int nstage, const GemmDesc* d_descs
 // S_1 or S_2 window [n_beams][K] (complex64, rows wstride apart) -> its transpose [K][ldo],
 // SC for the split precisions, complex64 for EELS_FP32 (beams n_beams .. ldo-1 zero; ldo a
 // multiple of 4, dst 32-byte aligned)
+// perm (may be null): output column b takes source row perm[b]
 void launch_window_t_sc(void* dst, const float2* src, int64_t wstride, int n_beams, int K, int ldo, int prec,
-                        hipStream_t st);
+                        hipStream_t st, const int* perm = nullptr);
+// Raster form of the window-Gram detector sum (kernels_raster.hip): for each job (site) and
+// each block of `chunk` window pixels, the M x M DFTs of c0 o Xt[r] and c0 o Z[r] over the beam
+// lattice (column q of a row is grid slot pos^-1(q), beam perm[q]) and part[job.part + block
+// M^2 + i + M j] = oscale sum_r Re(conj(Psi) Y) at residue (i, j); Xt and Z rows ld complex.
+void launch_raster_dot(const RasterJob* jobs, int n_jobs, const float2* base, const float2* c0, const int* perm,
+                       const int* pos, int M, int K, int ld, int chunk, float oscale, const float2* tw, float* part,
+                       hipStream_t st);
 // Window-Gram detector sum: G = gscale M o sum_t conj(H_t) H_t^T as SC rows [K][ldg]
 // (complex64 for EELS_FP32) from the FP32 complex Gram tiles M [K][ldm] (upper 128-tiles
 // valid); and out[i] = oscale sum_r Re(conj(Psi)Y) over the rows of Psi (SC, complex64 for

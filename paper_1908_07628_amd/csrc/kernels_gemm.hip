@@ -706,13 +706,15 @@ __global__ void k_to_sc(uint32_t* __restrict__ dst, const float2* __restrict__ s
 // groups of a pixel.
 template <int PREC>
 __global__ __launch_bounds__(256) void k_window_t_sc(uint32_t* __restrict__ dst, const float2* __restrict__ src,
-                                                     int64_t wstride, int n_beams, int K, int ldo) {
+                                                     int64_t wstride, int n_beams, int K, int ldo,
+                                                     const int* __restrict__ perm) {
     __shared__ float2 tile[64][65];
     const int p0 = blockIdx.x * 64, b0 = blockIdx.y * 64;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     for (int r = ty; r < 64; r += 4) {
         const int b = b0 + r, px = p0 + tx;
-        tile[r][tx] = (b < n_beams && px < K) ? src[(int64_t)b * wstride + px] : make_float2(0.f, 0.f);
+        const int bs = (perm && b < n_beams) ? perm[b] : b;
+        tile[r][tx] = (b < n_beams && px < K) ? src[(int64_t)bs * wstride + px] : make_float2(0.f, 0.f);
     }
     __syncthreads();
     for (int w = threadIdx.x; w < 64 * 16; w += 256) {
@@ -743,18 +745,18 @@ __global__ __launch_bounds__(256) void k_window_t_sc(uint32_t* __restrict__ dst,
 }
 
 void launch_window_t_sc(void* dst, const float2* src, int64_t wstride, int n_beams, int K, int ldo, int prec,
-                        hipStream_t st) {
+                        hipStream_t st, const int* perm) {
     if (n_beams <= 0 || K <= 0) return;
     dim3 grid((unsigned)ceil_div(K, 64), (unsigned)ceil_div(ldo, 64));
     if (prec == EELS_BF16_SPLIT)
         hipLaunchKernelGGL(k_window_t_sc<EELS_BF16_SPLIT>, grid, dim3(256), 0, st, (uint32_t*)dst, src, wstride,
-                           n_beams, K, ldo);
+                           n_beams, K, ldo, perm);
     else if (prec == EELS_FP16_SPLIT)
         hipLaunchKernelGGL(k_window_t_sc<EELS_FP16_SPLIT>, grid, dim3(256), 0, st, (uint32_t*)dst, src, wstride,
-                           n_beams, K, ldo);
+                           n_beams, K, ldo, perm);
     else
         hipLaunchKernelGGL(k_window_t_sc<EELS_FP32>, grid, dim3(256), 0, st, (uint32_t*)dst, src, wstride,
-                           n_beams, K, ldo);
+                           n_beams, K, ldo, perm);
 }
 
 // Window-Gram form of the detector sum: G = gscale M o S with S[r][c] = sum_t conj(H_t[r]) H_t[c]

@@ -654,11 +654,12 @@ void launch_propagator(float2* P, const double* dz, const Plan& p, hipStream_t s
                        p.lx, p.ly, p.lam);
 }
 void launch_probe_coefficients(void* C, const int4* beams, const double* probes, const Plan& p, int sc,
-                               hipStream_t st) {
-    int64_t n = (int64_t)p.P * p.N1pad;
+                               hipStream_t st, int n_probes) {
+    const int np = n_probes < 0 ? p.P : n_probes;
+    int64_t n = (int64_t)np * p.N1pad;
     double scale = (double)p.f * p.f / std::sqrt((double)p.N1fine) * p.c_scale;
     hipLaunchKernelGGL(k_probe_coefficients, dim3(blocks_for(n, 256)), dim3(256), 0, st, C, beams, p.N1, p.N1pad,
-                       probes, p.P, p.f, p.lx, p.ly, p.lam, p.defocus, p.cs, scale, sc);
+                       probes, np, p.f, p.lx, p.ly, p.lam, p.defocus, p.cs, scale, sc);
 }
 void launch_init_forward(float2* S, const int4* beams, const Plan& p, hipStream_t st) {
     int64_t n = (int64_t)p.N1 * p.ny * p.nlx;

@@ -288,6 +288,48 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     // (FP32 too: an FP32 Gram GEMM, G in complex64 and an FP32 G Psi product)
     p.wgram = !orderS && !p.recip && !p.full_window && p.Kpad <= 4096 &&
               (wg_knob == 2 || (wg_knob == 1 && fl_W < fl_D));
+    // raster form of the window-Gram detector sum (plan-time knob 7: 0 never, 1 where it needs
+    // fewer flops, 2 wherever it applies).  When every probe sits on a raster aligned with the
+    // beam lattice, R = R_0 + (i L_x / (f M), j L_y / (f M)) with integers i, j, the probe phase
+    // exp(-2 pi i k.R) is exp(-2 pi i k.R_0) times the M x M DFT kernel exp(-2 pi i (a i + b j) / M)
+    // of the beam's lattice coordinates (a, b).  Psi(R, r) = sum_k c_k(R) S_1[k](r) for every
+    // probe is then one 2-D DFT per window pixel, and so is Y(R, r) = sum_r' G(r, r') Psi(R, r')
+    // from Z = G S_1w^T (K^2 N_1 GEMM flops instead of K N_1 P_s + K^2 P_s).  The DFT does not
+    // alias when the beams' a and b each span fewer than M values.
+    {
+        const int r_knob = tune_get(TUNE_RASTER);
+        const int M = 64;
+        p.raster = false;
+        if (!orderS && !p.recip && !p.full_window && p.Kpad <= 4096 && r_knob != 0 && wg_knob != 0) {
+            int amin = 1 << 30, amax = -(1 << 30), bmin = 1 << 30, bmax = -(1 << 30);
+            for (int b = 0; b < p.N1; ++b) {
+                amin = std::min(amin, p.ab1[2 * b]); amax = std::max(amax, p.ab1[2 * b]);
+                bmin = std::min(bmin, p.ab1[2 * b + 1]); bmax = std::max(bmax, p.ab1[2 * b + 1]);
+            }
+            bool ok = amax - amin < M && bmax - bmin < M;
+            std::vector<int> res(p.P);
+            for (int r = 0; ok && r < p.P; ++r) {
+                const double u = (p.probes[2 * r] - p.probes[0]) * p.f / p.lx * M;
+                const double v = (p.probes[2 * r + 1] - p.probes[1]) * p.f / p.ly * M;
+                const double ru = std::nearbyint(u), rv = std::nearbyint(v);
+                if (std::fabs(u - ru) > 1e-6 || std::fabs(v - rv) > 1e-6) ok = false;
+                else res[r] = imod((long long)ru, M) + M * imod((long long)rv, M);
+            }
+            double fl_R = 0;
+            for (int j : ion)
+                for (size_t t = 0; t < by_slice[j].size(); ++t)
+                    fl_R += 4.0 * p.N2 * (double)p.K * (p.K + 1.0) + 8.0 * (double)p.K * p.K * p.N1;
+            const double fl_cur = p.wgram ? fl_P - fl_D + fl_W : fl_P;
+            if (ok && (r_knob == 2 || fl_R < fl_cur)) {
+                p.raster = true;
+                p.wgram = true;
+                p.rM = M;
+                p.r_res = std::move(res);
+                p.r_chunk = 64;
+                p.r_chunks = (int)ceil_div(p.K, p.r_chunk);
+            }
+        }
+    }
     p.w2_sc = (split && !p.hs2) ? p.precision : 0;
     p.mid2_sc = split ? p.precision : 0;
 
@@ -311,6 +353,7 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     auto site_mid = [&](int s) -> int64_t {
         int nt = p.sites[s].n_trans;
         if (p.gram) return (int64_t)p.N1 * nt * p.N2p;     // Z rows [t k][q]
+        if (p.raster) return 0;                            // no Psi is stored
         return orderS ? (int64_t)nt * p.N2 * p.N1pad : (int64_t)n_elig(s) * p.Kpad;
     };
     auto site_ni = [&](int s) -> int64_t { return orderS ? p.N1 : (p.hs2 ? p.N2 : n_elig(s)); };
@@ -320,7 +363,9 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
                   wg_y = wg_g + (int64_t)p.K * p.Kpad;
     auto site_mid2 = [&](int s) -> int64_t {
         if (!p.recip && !split && !p.wgram) return 0;
-        int64_t m2 = p.wgram ? wg_y + (int64_t)n_elig(s) * p.Kpad
+        // raster form: Z [K][N_1p] at wg_y, then Xt [K][N_1p], then (split) S_1w as SC [N_1][Kpad]
+        int64_t m2 = p.raster ? wg_y + 2 * (int64_t)p.K * p.N1pad + (split ? (int64_t)p.N1 * p.Kpad : 0)
+                   : p.wgram ? wg_y + (int64_t)n_elig(s) * p.Kpad
                              : (int64_t)p.sites[s].n_trans * site_ni(s) * Kcpad;
         // order P, split: the site's S_1 window is first transposed here for the product C S_1w
         if (split && !orderS) m2 = std::max(m2, (int64_t)p.K * p.N1pad);
@@ -328,6 +373,7 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     };
     auto site_part = [&](int s) -> int64_t {
         if (p.gram) return 2 * (int64_t)p.sites[s].n_trans * p.N1pad * p.N1pad;   // FP32 partials of Z_t^H Z_t
+        if (p.raster) return (int64_t)p.r_chunks * p.rM * p.rM;                  // one per residue and DFT block
         if (p.wgram) return n_elig(s);                                            // one per eligible probe
         int nt = p.sites[s].n_trans;
         int64_t tm = ceil_div(p.N2, GEMM_BM);
@@ -349,6 +395,7 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
                    A(c8 * (size_t)p.N1 * p.ny * p.ldx) + A(c8 * (size_t)p.N2 * p.ny * p.ldx) +
                    A(c8 * (size_t)w2_elems) + A(c8 * (size_t)scratch) +
                    (p.gram ? A(16 * (size_t)p.N1 * p.N1) + A(8 * (size_t)p.P * ceil_div(p.N1, 64)) : 0) +
+                   (p.raster ? A(c8 * (size_t)p.N1pad) + A(c8 * (size_t)p.rM) : 0) +
                    (p.n_img > 0 ? 2 * A(c8 * (size_t)p.N1 * p.Kbpad) + A(c8 * (size_t)p.N1pad * p.N1pad) +
                                       A(16 * (size_t)p.N1 * p.N1) + A(8 * (size_t)p.P * ceil_div(p.N1, 64)) +
                                       A(c8 * (size_t)p.P * p.N1pad)
@@ -519,6 +566,28 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
             site_idx[s] = B.append(std::vector<int32_t>(p.site_probes[s].begin(), p.site_probes[s].end()));
         else site_idx[s] = p.ident_off;
     }
+    // raster form: the beams in the order the DFT block's threads read them (thread 4 y + x mod 4
+    // holds grid slot (x, y) = (a mod M, b mod M) in register x / 4, and consecutive threads of
+    // one register read consecutive columns), and each grid slot's column (-1: no beam)
+    if (p.raster) {
+        const int M = p.rM;
+        std::vector<std::pair<int, int>> key(p.N1);
+        std::vector<int> slot(p.N1);
+        for (int b = 0; b < p.N1; ++b) {
+            const int x = imod(p.ab1[2 * b], M), y = imod(p.ab1[2 * b + 1], M);
+            slot[b] = y * M + x;
+            key[b] = {(x >> 2) * 4 * M + 4 * y + (x & 3), b};
+        }
+        std::sort(key.begin(), key.end());
+        std::vector<int32_t> perm(p.N1), pos((size_t)M * M, -1);
+        for (int q = 0; q < p.N1; ++q) {
+            perm[q] = key[q].second;
+            if (pos[slot[key[q].second]] >= 0) return fail(EELS_ERR_INTERNAL, "two beams on one DFT slot");
+            pos[slot[key[q].second]] = q;
+        }
+        p.r_perm_off = B.append(perm);
+        p.r_pos_off = B.append(pos);
+    }
     // descriptors, producer jobs and reduction CSRs
     p.descs.clear();
     p.batches.clear();
@@ -562,6 +631,10 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
                     jb.y_off = site_m2off[si] + wg_y;
                     jb.psi_off = site_moff[si];
                     jb.ps = n_elig(s);
+                    if (p.raster) {
+                        jb.xt_off = jb.y_off + (int64_t)p.K * p.N1pad;
+                        jb.s1sc_off = jb.xt_off + (int64_t)p.K * p.N1pad;
+                    }
                 }
                 p.jobs.push_back(jb);
             }
@@ -570,7 +643,7 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
 
         bt.d1_begin = (int)p.descs.size();
         int tiles = 0;
-        for (size_t si = 0; si < pb.sites.size(); ++si) {
+        for (size_t si = 0; si < pb.sites.size() && !p.raster; ++si) {
             int s = pb.sites[si];
             const eels_site& st = p.sites[s];
             int Ps = n_elig(s);
@@ -669,15 +742,22 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
                 d.M = 0; d.N_inner = Ps; d.n_t = 1; d.K = 0;
                 d.tiles_m = 1; d.tiles_n = 0; d.tile_start = tiles;
                 d.p_off = poff; d.ld_part = Ps;
+                if (p.raster) {
+                    // the site's DFT blocks each leave M^2 partial sums, one per probe residue;
+                    // a probe's entry is its residue and the reduction adds the blocks' values
+                    d.N_inner = p.rM * p.rM;
+                    d.tiles_m = p.r_chunks;
+                    d.ld_part = (int64_t)p.rM * p.rM;
+                }
                 p.jobs[bt.job_begin + si].part_off = poff;
-                poff += Ps;
+                poff += d.tiles_m * d.ld_part;
                 int di = (int)p.descs.size();
                 p.descs.push_back(d);
-                if (p.f > 1)
+                if (p.f > 1 || p.raster)
                     for (int i = 0; i < Ps; ++i) {
                         int r = pl ? (*pl)[i] : i;
                         ent[r].push_back(di);
-                        ent[r].push_back(i);
+                        ent[r].push_back(p.raster ? p.r_res[r] : i);
                     }
                 continue;
             }
@@ -747,18 +827,30 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
             }
             bt.dm_count = (int)p.descs.size() - bt.dm_begin;
             bt.dm_tiles = tl;
-            // Y_s^T[i][r] = sum_r' Psi_s[i][r'] G_s[r][r']  (complex64 store)
+            // Y_s^T[i][r] = sum_r' Psi_s[i][r'] G_s[r][r']  (complex64 store), or in the raster
+            // form Z_s[r][q] = sum_r' G_s[r][r'] S_1w[perm(q)][r'] (the S_1 window's rows gathered
+            // into beam-slot order; FP32 reads them from the window buffer, split from their SC copy)
             bt.dy_begin = (int)p.descs.size();
             tl = 0;
             for (size_t si = 0; si < pb.sites.size(); ++si) {
                 const Job& jb = p.jobs[bt.job_begin + si];
                 GemmDesc d{};
-                d.a_off = jb.psi_off; d.lda = p.Kpad; d.b_off = jb.g_off; d.ldb = p.Kpad;
-                d.h_off = -1; d.idx_off = -1;
-                d.c_off = jb.y_off; d.ldc_m = p.Kpad; d.ldc_t = 0;
-                d.M = jb.ps; d.N_inner = p.K; d.n_t = 1; d.K = p.K;
-                d.tiles_m = (int)ceil_div(jb.ps, rows2);
-                d.tiles_n = (int)ceil_div(p.K, GEMM_BN);
+                if (p.raster) {
+                    d.a_off = jb.g_off; d.lda = p.Kpad;
+                    d.b_off = split ? jb.s1sc_off : jb.win_off; d.ldb = p.Kpad;
+                    d.h_off = -1; d.idx_off = p.r_perm_off;
+                    d.c_off = jb.y_off; d.ldc_m = p.N1pad; d.ldc_t = 0;
+                    d.M = p.K; d.N_inner = p.N1; d.n_t = 1; d.K = p.K;
+                    d.tiles_m = (int)ceil_div(p.K, rows2);
+                    d.tiles_n = (int)ceil_div(p.N1, GEMM_BN);
+                } else {
+                    d.a_off = jb.psi_off; d.lda = p.Kpad; d.b_off = jb.g_off; d.ldb = p.Kpad;
+                    d.h_off = -1; d.idx_off = -1;
+                    d.c_off = jb.y_off; d.ldc_m = p.Kpad; d.ldc_t = 0;
+                    d.M = jb.ps; d.N_inner = p.K; d.n_t = 1; d.K = p.K;
+                    d.tiles_m = (int)ceil_div(jb.ps, rows2);
+                    d.tiles_n = (int)ceil_div(p.K, GEMM_BN);
+                }
                 d.tile_start = tl;
                 tl += d.tiles_m * d.tiles_n;
                 p.descs.push_back(d);
@@ -768,7 +860,19 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
             bt.dy_rows = rows2;
             // every operand of the form stays inside the batch's mid, mid2 and part buffers
             const int64_t k16 = round_up(p.K, 16), n16 = round_up(p.N2, 16);
-            for (int k = 0; k < bt.job_count; ++k) {
+            for (int k = 0; k < bt.job_count && p.raster; ++k) {
+                const Job& jb = p.jobs[bt.job_begin + k];
+                const int64_t last_row = (int64_t)(p.K - 1) * p.N1pad + p.N1pad;
+                const bool ok = jb.s2t_off + (int64_t)(p.K - 1) * p.N2p + n16 <= m2off &&
+                                jb.m_off + (int64_t)(p.K - 1) * p.Kpad + p.K <= m2off &&
+                                jb.g_off + (int64_t)(p.K - 1) * p.Kpad + k16 <= m2off &&
+                                jb.y_off + last_row <= m2off && jb.xt_off + last_row <= m2off &&
+                                (!split || jb.s1sc_off + (int64_t)(p.N1 - 1) * p.Kpad + k16 <= m2off) &&
+                                jb.part_off + (int64_t)p.r_chunks * p.rM * p.rM <= poff &&
+                                n16 <= p.N2p && k16 <= p.Kpad && m2off <= p.mid2_elems && poff <= p.part_elems;
+                if (!ok) return fail(EELS_ERR_INTERNAL, "raster-form operands leave their buffers");
+            }
+            for (int k = 0; k < bt.job_count && !p.raster; ++k) {
                 const Job& jb = p.jobs[bt.job_begin + k];
                 const int64_t rows_y = std::max(jb.ps, 1) - 1;
                 const bool ok = jb.s2t_off + (int64_t)(p.K - 1) * p.N2p + n16 <= m2off &&
@@ -781,7 +885,17 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
                 if (!ok) return fail(EELS_ERR_INTERNAL, "window-Gram operands leave their buffers");
             }
         }
-        if (p.f > 1) {
+        if (p.raster) {
+            std::vector<int32_t> rj;
+            for (int k = 0; k < bt.job_count; ++k) {
+                const Job& jb = p.jobs[bt.job_begin + k];
+                const int64_t v[3] = {jb.xt_off, jb.y_off, jb.part_off};
+                const int32_t* w = (const int32_t*)v;
+                rj.insert(rj.end(), w, w + 6);
+            }
+            bt.r_jobs = B.append(rj);
+        }
+        if (p.f > 1 || p.raster) {
             std::vector<int32_t> ptr(p.P + 1, 0), flat;
             for (int r = 0; r < p.P; ++r) {
                 flat.insert(flat.end(), ent[r].begin(), ent[r].end());
@@ -907,6 +1021,8 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     p.off_img_G = take(img ? 16 * (size_t)p.N1 * p.N1 : 16);
     p.off_img_qpart = take(img ? 8 * (size_t)p.P * ceil_div(p.N1, 64) : 16);
     p.off_img_C = take(img ? c8 * (size_t)p.P * p.N1pad : 16);
+    p.off_r_c0 = take(p.raster ? c8 * (size_t)p.N1pad : 16);      // c_k(R_0)
+    p.off_r_tw = take(p.raster ? c8 * (size_t)p.rM : 16);          // M-point twiddles
     p.off_blob = take(p.blob.size() * 4);
     p.ws_bytes = off;
     if (budget > 0 && p.ws_bytes > budget) return fail(EELS_ERR_OOM, "workspace exceeds the memory budget");

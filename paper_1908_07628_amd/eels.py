@@ -55,7 +55,7 @@ class PlanInfo(C.Structure):
                 ("order", C.c_int), ("band_basis", C.c_int), ("band_pixels", C.c_int),
                 ("lambda_A", C.c_double), ("sigma", C.c_double), ("gemm_flops", C.c_double),
                 ("sweep_bytes", C.c_double), ("sweep_beam_slices", C.c_double), ("workspace_bytes", C.c_size_t),
-                ("gram_form", C.c_int), ("window_gram_form", C.c_int)]
+                ("gram_form", C.c_int), ("window_gram_form", C.c_int), ("raster_form", C.c_int)]
 
 
 class RequestTiming(C.Structure):
@@ -83,7 +83,7 @@ EXPORTS = ["eels_get_version", "eels_status_string", "eels_last_error", "eels_pl
            "eels_admission_admit", "eels_admission_finish", "eels_admission_cancel", "eels_admission_used",
            "eels_admission_destroy", "eels_execute_noalloc"]
 EXEC_SKIP_UPLOAD, EXEC_SKIP_SWEEPS, EXEC_SWEEPS_ONLY = 1, 2, 4
-PHASES = ["setup", "sweep", "producer", "gemm1", "gemm2", "reduce", "images", "gram"]
+PHASES = ["setup", "sweep", "producer", "gemm1", "gemm2", "reduce", "images", "gram", "raster"]
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:
@@ -466,6 +466,7 @@ TUNE_GRAM_STACK = 3
 TUNE_GEMM1_ROWS = 4
 TUNE_GEMM2_ROWS = 5
 TUNE_WINDOW_GRAM = 6
+TUNE_RASTER = 7
 
 
 def tune_set(key: int, value: int):

@@ -380,3 +380,37 @@ def test_phase_names_match_the_header():
     assert len(eels.PHASES) == n == len(ph)
     for i, name in enumerate(eels.PHASES):
         assert ph[name] == i, name
+
+
+def test_raster_form_needs_an_aligned_probe_raster():
+    """The raster form of the window-Gram detector sum is taken only when every probe offset
+    from the first is a whole multiple of L / (f M) (M = 64) in both axes and the aperture
+    beams span fewer than M lattice columns and rows; knob 7 turns it off (0) or forces it (2),
+    and the residues of the probes follow from the offsets."""
+    _lib()
+    keep = eels.tune_get(eels.TUNE_RASTER)
+    try:
+        p = synth.config3_subproblem(n=128, L=25.0, nz=3, n_scan=8, f=2)
+        for prec in ("bf16_split", "fp32"):
+            eels.tune_set(eels.TUNE_RASTER, 2)
+            assert eels.Plan(p, precision=prec, order="probe_first").info()["raster_form"] == 64
+            eels.tune_set(eels.TUNE_RASTER, 0)
+            assert eels.Plan(p, precision=prec, order="probe_first").info()["raster_form"] == 0
+        eels.tune_set(eels.TUNE_RASTER, 2)
+        off = p.replace(probes=p.probes + np.array([0.37 * 25.0 / 128, 0.0]))     # a shared shift: still a raster
+        assert eels.Plan(off, precision="fp32", order="probe_first").info()["raster_form"] == 64
+        bent = p.probes.copy()
+        bent[5, 0] += 0.01                                                        # one probe off the raster
+        assert eels.Plan(p.replace(probes=bent), precision="fp32", order="probe_first").info()["raster_form"] == 0
+        wide = synth.config3_subproblem(n=512, L=100.0, nz=3, n_scan=8, f=1)      # f = 1: a spans 203 columns
+        assert eels.Plan(wide, precision="fp32", order="probe_first").info()["raster_form"] == 0
+        full = p.replace(window_A=0.0, interp_f=1)
+        assert eels.Plan(full, precision="fp32").info()["raster_form"] == 0
+        with pytest.raises(eels.EelsError):
+            eels.tune_set(eels.TUNE_RASTER, 3)
+        # the nanoparticle map takes it by default
+        eels.tune_set(eels.TUNE_RASTER, 1)
+        big = synth.config3()
+        assert eels.Plan(big, precision="bf16_split", max_workspace_bytes=int(290e9)).info()["raster_form"] == 64
+    finally:
+        eels.tune_set(eels.TUNE_RASTER, keep)

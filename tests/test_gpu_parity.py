@@ -379,6 +379,42 @@ def test_window_gram_form(prec, tol):
         assert np.all(got[ref == 0] == 0)
 
 
+@pytest.mark.parametrize("prec,tol", [("bf16_split", 1e-3), ("fp16_split", 1e-3), ("fp32", 1e-4)])
+def test_raster_form(prec, tol):
+    """The raster form of the window-Gram detector sum (knob 7 = 2): Psi and G Psi for every
+    probe of a raster aligned with the beam lattice by 64 x 64 DFTs over the beam lattice per
+    window pixel.  Against the oracle at the precision's bar and against the window-Gram form
+    without it (knob 7 = 0): a sparse raster (every 8th residue), a dense one (all 64 residues
+    per axis, 4096 probes) and an f = 4 tiled specimen (its small cell's conventional map)."""
+    eels = _need_gpu()
+    ps = synth.random_problem(41, n=32, L=8.0, nz=3, n_sites=1, n_trans=3, window_A=4.0,
+                              aperture_mrad=15.0, det_outer_mrad=20.0)
+    g = np.arange(16) * 0.5                            # step L_small / 16 on the f = 4 tiled cell
+    tiled_probes = np.stack(np.meshgrid(g + 0.25, g + 0.25, indexing="xy"), axis=-1).reshape(-1, 2)
+    cases = [("f=2 sparse raster", synth.config3_subproblem(n=128, L=25.0, nz=5, n_scan=8, f=2)),
+             ("f=2 dense raster", synth.config3_subproblem(n=128, L=25.0, nz=3, n_scan=64, f=2)),
+             ("f=4 tiled", synth.tiled_problem(ps, 4, tiled_probes))]
+    for name, p in cases:
+        ref = prism.prism_map(p)
+        assert np.max(ref) > 0
+        keep = (eels.tune_get(eels.TUNE_WINDOW_GRAM), eels.tune_get(eels.TUNE_RASTER))
+        try:
+            eels.tune_set(eels.TUNE_WINDOW_GRAM, 2)
+            eels.tune_set(eels.TUNE_RASTER, 2)
+            assert eels.Plan(p, precision=prec, order="probe_first").info()["raster_form"] == 64, name
+            _say("raster form", name, prec, p.n_probes, "probes")
+            got = _map(eels, p, prec, "probe_first")
+            eels.tune_set(eels.TUNE_RASTER, 0)
+            wg = _map(eels, p, prec, "probe_first")
+        finally:
+            eels.tune_set(eels.TUNE_WINDOW_GRAM, keep[0])
+            eels.tune_set(eels.TUNE_RASTER, keep[1])
+        _say("  rel-L2 vs oracle", metrics.rel_l2(got, ref), "vs window Gram", metrics.rel_l2(got, wg))
+        assert maps_close(got, ref, tol)
+        assert maps_close(got, wg, tol)
+        assert np.all(got[ref == 0] == 0)
+
+
 def test_window_gram_fp16_range_at_many_detector_beams():
     """N_2 = 8093 detector beams and 9 transitions: unscaled, the window Gram matrix's
     diagonal (about N_2 sum_t |H_t|^2, rows of S_2 of unit mean square) would reach about
