@@ -435,6 +435,7 @@ def bench_nanoparticle(args, t_proc0):
     out = torch.empty(p.n_probes, dtype=torch.float64, device="cuda")
     log(f"plan: N1={info['n_beams_in']} N2={info['n_beams_out']} K={info['k_pixels']} "
         f"order={'S' if info['order'] == 1 else 'P'} window-Gram={info['window_gram_form']} "
+        f"raster={info['raster_form']} "
         f"groups={info['n_groups']} batches={info['n_batches']} "
         f"workspace={info['workspace_bytes'] / 1e9:.1f} GB (budget {budget / 1e9:.0f} GB)")
     # warm-up steps: --warmup is an upper bound (a second one changes nothing measurable)
@@ -485,7 +486,16 @@ def bench_nanoparticle(args, t_proc0):
     pairs = info["gemm_flops"] / (8.0 * K * (N1 + N2 * nt))
     split = args.precision != "fp32"
 
+    raster = info.get("raster_form", 0) > 0
+
     def kernels(ph, wgram):
+        if raster:
+            # raster form: no first product; Z = G S_1w^T (8 K^2 N_1 per site), the Gram GEMM, and
+            # the DFTs of Psi and Y over the beam lattice (VALU, timed as the raster phase)
+            return {"gemm2": ("Z = G S_1w^T of the raster window-Gram form", 8.0 * K * K * N1 * p.n_sites,
+                              "z_traffic_bytes_per_site"),
+                    "gram": ("Gram GEMM M = S_2w^H S_2w of the window-Gram form (Hermitian half)",
+                             8.0 * N2 * K * (K + 1) / 2.0 * p.n_sites, "gram_traffic_bytes_per_site")}
         k = {"gemm1": ("first product Psi = C S_1w", 8.0 * K * N1 * pairs, "gemm1_traffic_bytes_per_site")}
         if wgram:
             k["gemm2"] = ("G Psi product of the window-Gram form", 8.0 * K * K * pairs, "gpsi_traffic_bytes_per_site")
@@ -541,6 +551,18 @@ def bench_nanoparticle(args, t_proc0):
         "algorithmic_bytes_per_step": sweep_bytes,
         "byte_definition": (f"32 B x n_y x n_live_x ({nlx}) per beam-slice (2 passes, read + write; S_1 swept "
                             f"once per slice group) + 8 B per window pixel per beam captured")}}
+    if raster and phases.get("raster", 0) > 0:
+        # the DFTs of Psi and Y: two M^2-point 2-D FFTs per window pixel (5 N log2 N flops each),
+        # reading the pixel's row of Xt and of Z (N_1 complex64 each)
+        M2 = float(info["raster_form"]) ** 2
+        fl = 2.0 * 5.0 * M2 * np.log2(M2) * K * p.n_sites
+        by = 2.0 * 8.0 * N1 * K * p.n_sites
+        t = phases["raster"] * 1e-3
+        roofline_fft["raster_dft"] = {
+            "bound": "alu", "kernels": "k_raster_dot", "achieved_tflops": round(fl / t / 1e12, 2),
+            "peak_tflops": PEAK_FP32_TFLOPS, "frac": round(fl / t / 1e12 / PEAK_FP32_TFLOPS, 4),
+            "achieved_GBps": round(by / t / 1e9, 1), "hbm_frac": round(by / t / 1e9 / PEAK_HBM_GBPS, 4),
+            "definition": "2 x 5 M^2 log2(M^2) flops and 16 N_1 bytes read per window pixel per site"}
 
     # FP32: the same algorithm on the whole map, timed once
     fp32 = None
@@ -564,8 +586,9 @@ def bench_nanoparticle(args, t_proc0):
         torch.cuda.empty_cache()
         m32 = o32.cpu().numpy()
         fp32 = {"value": round(p.n_probes / dt32, 2), "ms_per_step": round(1e3 * dt32, 1), "steps": 1,
-                "measured_on": "the whole map (same algorithm: order P, window-Gram detector sum)",
-                "window_gram_form": i32["window_gram_form"],
+                "measured_on": "the whole map (same algorithm: order P, window-Gram detector sum" +
+                               (", raster form)" if i32["raster_form"] else ")"),
+                "window_gram_form": i32["window_gram_form"], "raster_form": i32["raster_form"],
                 "phases_ms": {k: round(v["ms"], 1) for k, v in ph32.items() if v["count"]},
                 "contraction_kernels": contraction_table(ph32, 1, "fp32"),
                 "split_rel_l2_vs_fp32": float(np.linalg.norm(gpu_map - m32) / np.linalg.norm(m32))}
@@ -582,7 +605,9 @@ def bench_nanoparticle(args, t_proc0):
                    "workspace_GB": round(info["workspace_bytes"] / 1e9, 1),
                    "precision": args.precision + " (hi+lo products, FP32 accumulate, FP64 map)"
                    if split else "fp32",
-                   "contraction": "cropped windows, order P" + (", window-Gram detector sum" if wgram else "")},
+                   "contraction": "cropped windows, order P" + (", window-Gram detector sum" if wgram else "") +
+                   (f", raster form (Psi and G Psi by {info['raster_form']}x{info['raster_form']} DFTs over the beam "
+                    "lattice)" if raster else "")},
         "roofline": roofline, "contraction_kernels": contraction, "roofline_fft": roofline_fft,
         "phases_ms": phases, "fp32": fp32,
         "split_over_fp32": round(value / fp32["value"], 2) if fp32 else None,
