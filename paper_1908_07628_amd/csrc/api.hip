@@ -291,6 +291,11 @@ void producers_before_gemm1(const Plan& p, const Dev& d, const float2* dH, const
     } else if (split && !p.raster) {
         // SC transposes of the sites' S_1 windows (mid2 holds them until the producer runs)
         TimeScope ts(EELS_PHASE_PRODUCER, st);
+        if (p.wgram) {   // one launch over the batch (the transposes sit where S_2w^T goes later)
+            launch_window_t_batched(d.mid2, d.w1, (const ProdJob*)(d.blob + b.p_jobs), b.job_count, 2, p.Kpad, p.N1,
+                                    p.K, p.N1pad, p.precision, nullptr, st);
+            return;
+        }
         for (int k = 0; k < b.job_count; ++k) {
             const Job& jb = p.jobs[b.job_begin + k];
             launch_window_t_sc(d.mid2 + jb.dst_off, d.w1 + jb.win_off, p.Kpad, p.N1, p.K, p.N1pad, p.precision, st);
@@ -302,18 +307,17 @@ void producers_before_gemm1(const Plan& p, const Dev& d, const float2* dH, const
 void producers_after_gemm1(const Plan& p, const Dev& d, const float2* dH, const Batch& b, hipStream_t st) {
     const bool split = p.precision != EELS_FP32;
     if (p.wgram) {
-        // window-Gram form: each site's S_2 window [N_2][K] becomes SC rows [K][N_2p]
+        // window-Gram form, one launch per producer over the batch's sites: each site's S_2 window
+        // [N_2][K] becomes rows [K][N_2p] (SC, or complex64 in FP32); in the raster form the S_1
+        // window is also transposed into beam-slot order (complex64, the DFTs' input) and, in split
+        // precision, copied to SC (the Z GEMM's B operand)
         TimeScope ts(EELS_PHASE_PRODUCER, st);
-        for (int k = 0; k < b.job_count; ++k) {
-            const Job& jb = p.jobs[b.job_begin + k];
-            launch_window_t_sc(d.mid2 + jb.s2t_off, d.w2 + jb.w_off, p.Kpad, p.N2, p.K, p.N2p, p.precision, st);
-            if (p.raster) {
-                // the S_1 window transposed into beam-slot order (complex64, the DFTs' input) and,
-                // in split precision, its SC copy (the Z GEMM's B operand)
-                launch_window_t_sc(d.mid2 + jb.xt_off, d.w1 + jb.win_off, p.Kpad, p.N1, p.K, p.N1pad, EELS_FP32, st,
-                                   d.blob + p.r_perm_off);
-                if (split) launch_to_sc(d.mid2 + jb.s1sc_off, d.w1 + jb.win_off, p.N1, p.K, p.Kpad, p.precision, st);
-            }
+        const ProdJob* jobs = (const ProdJob*)(d.blob + b.p_jobs);
+        launch_window_t_batched(d.mid2, d.w2, jobs, b.job_count, 0, p.Kpad, p.N2, p.K, p.N2p, p.precision, nullptr, st);
+        if (p.raster) {
+            launch_window_t_batched(d.mid2, d.w1, jobs, b.job_count, 1, p.Kpad, p.N1, p.K, p.N1pad, EELS_FP32,
+                                    d.blob + p.r_perm_off, st);
+            if (split) launch_to_sc_batched(d.mid2, d.w1, jobs, b.job_count, p.N1, p.K, p.Kpad, p.precision, st);
         }
         return;
     }
@@ -341,11 +345,8 @@ void wgram_contract(const Plan& p, const Dev& d, const float2* dH, const Batch& 
     }
     {
         TimeScope ts(EELS_PHASE_PRODUCER, st);
-        for (int k = 0; k < b.job_count; ++k) {
-            const Job& jb = p.jobs[b.job_begin + k];
-            launch_wgram_combine(d.mid2 + jb.g_off, d.mid2 + jb.m_off, dH + jb.h_off, jb.nt, p.K, p.Kpad, p.Kpad,
-                                 gscale, p.precision, st);
-        }
+        launch_wgram_combine_batched(d.mid2, dH, (const ProdJob*)(d.blob + b.p_jobs), b.job_count, p.K, p.Kpad, p.Kpad,
+                                     gscale, p.precision, st);
     }
     if (p.raster) {
         {

@@ -65,7 +65,16 @@ struct Batch {
     int dm_begin = 0, dm_count = 0, dm_tiles = 0;
     int dy_begin = 0, dy_count = 0, dy_tiles = 0, dy_rows = 128;
     int64_t r_jobs = -1;                // raster form: int offset of the batch's RasterJob table
+    int64_t p_jobs = -1;                // window-Gram form: int offset of the batch's ProdJob table
 };
+
+// Window-Gram producers of one site, for the batched launches (complex offsets: s2w in the S_2
+// capture, s1w in the S_1 windows, h in the transition potentials, the rest in mid2).
+struct ProdJob {
+    int64_t s2w, s2t, s1w, xt, s1sc, m, g, h;
+    int32_t nt, pad;
+};
+static_assert(sizeof(ProdJob) == 72, "ProdJob layout");
 
 // Raster form of the window-Gram detector sum, per site: complex offsets (in mid2) of the
 // site's S_1 window transposed into beam-slot order Xt [K][N1pad] and of Z = G S_1w^T

@@ -103,6 +103,18 @@ void launch_cgemm_sc(int precision, int epi, int nstage, const GemmDesc* d_descs
 // perm (may be null): output column b takes source row perm[b]
 void launch_window_t_sc(void* dst, const float2* src, int64_t wstride, int n_beams, int K, int ldo, int prec,
                         hipStream_t st, const int* perm = nullptr);
+// The same three producers over every site of a batch in one launch, the sites' offsets taken
+// from the device job table (ProdJob): the window transposes (which 0: the S_2 window s2w ->
+// s2t in `prec`; 1: the S_1 window s1w -> xt, rows gathered by perm; 2: the S_1 window s1w ->
+// s2t, the first product's operand before the S_2 transpose takes its place), the SC copy of the S_1
+// window (s1w -> s1sc) and G (m, h, nt -> g).  Source bases: the S_2 capture or the S_1
+// windows; destination base: mid2.
+void launch_window_t_batched(void* dst_base, const float2* src_base, const ProdJob* jobs, int n_jobs, int which,
+                             int64_t wstride, int n_beams, int K, int ldo, int prec, const int* perm, hipStream_t st);
+void launch_to_sc_batched(void* dst_base, const float2* src_base, const ProdJob* jobs, int n_jobs, int64_t rows, int K,
+                          int ld, int prec, hipStream_t st);
+void launch_wgram_combine_batched(void* mid2, const float2* H, const ProdJob* jobs, int n_jobs, int K, int ldm, int ldg,
+                                  float gscale, int prec, hipStream_t st);
 // Raster form of the window-Gram detector sum (kernels_raster.hip): for each job (site) and
 // each block of `chunk` window pixels, the M x M DFTs of c0 o Xt[r] and c0 o Z[r] over the beam
 // lattice (column q of a row is grid slot pos^-1(q), beam perm[q]) and part[job.part + block

@@ -688,11 +688,17 @@ __global__ __launch_bounds__(128 * WM, (ScPipe<UNITS, NSTAGE, WM>::WAVES_PER_EU)
     }
 }
 
-// complex64 -> SC conversion of rows [rows][ld] (K padding columns become zero)
+// complex64 -> SC conversion of rows [rows][ld] (K padding columns become zero); batched: job
+// blockIdx.y's S_1 window (s1w) into its s1sc slot
 __global__ void k_to_sc(uint32_t* __restrict__ dst, const float2* __restrict__ src, int64_t rows, int K, int ld,
-                        int prec) {
+                        int prec, const ProdJob* __restrict__ jobs) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= rows * ld) return;
+    if (jobs) {
+        const ProdJob& j = jobs[blockIdx.y];
+        src += j.s1w;
+        dst = (uint32_t*)((char*)dst + 8 * j.s1sc);
+    }
     int k = (int)(i % ld);
     float2 v = k < K ? src[i] : make_float2(0.f, 0.f);
     sc_store(dst, i, v, prec);
@@ -707,8 +713,14 @@ __global__ void k_to_sc(uint32_t* __restrict__ dst, const float2* __restrict__ s
 template <int PREC>
 __global__ __launch_bounds__(256) void k_window_t_sc(uint32_t* __restrict__ dst, const float2* __restrict__ src,
                                                      int64_t wstride, int n_beams, int K, int ldo,
-                                                     const int* __restrict__ perm) {
+                                                     const int* __restrict__ perm, const ProdJob* __restrict__ jobs,
+                                                     int which) {
     __shared__ float2 tile[64][65];
+    if (jobs) {   // batched: job blockIdx.z's window (which 0: S_2 -> s2t, 1: S_1 -> xt, 2: S_1 -> s2t)
+        const ProdJob& j = jobs[blockIdx.z];
+        src += which ? j.s1w : j.s2w;
+        dst = (uint32_t*)((char*)dst + 8 * (which == 1 ? j.xt : j.s2t));
+    }
     const int p0 = blockIdx.x * 64, b0 = blockIdx.y * 64;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     for (int r = ty; r < 64; r += 4) {
@@ -744,19 +756,29 @@ __global__ __launch_bounds__(256) void k_window_t_sc(uint32_t* __restrict__ dst,
     }
 }
 
-void launch_window_t_sc(void* dst, const float2* src, int64_t wstride, int n_beams, int K, int ldo, int prec,
-                        hipStream_t st, const int* perm) {
-    if (n_beams <= 0 || K <= 0) return;
-    dim3 grid((unsigned)ceil_div(K, 64), (unsigned)ceil_div(ldo, 64));
+static void window_t_go(void* dst, const float2* src, int64_t wstride, int n_beams, int K, int ldo, int prec,
+                        hipStream_t st, const int* perm, const ProdJob* jobs, int n_jobs, int which) {
+    if (n_beams <= 0 || K <= 0 || n_jobs <= 0) return;
+    dim3 grid((unsigned)ceil_div(K, 64), (unsigned)ceil_div(ldo, 64), (unsigned)n_jobs);
     if (prec == EELS_BF16_SPLIT)
         hipLaunchKernelGGL(k_window_t_sc<EELS_BF16_SPLIT>, grid, dim3(256), 0, st, (uint32_t*)dst, src, wstride,
-                           n_beams, K, ldo, perm);
+                           n_beams, K, ldo, perm, jobs, which);
     else if (prec == EELS_FP16_SPLIT)
         hipLaunchKernelGGL(k_window_t_sc<EELS_FP16_SPLIT>, grid, dim3(256), 0, st, (uint32_t*)dst, src, wstride,
-                           n_beams, K, ldo, perm);
+                           n_beams, K, ldo, perm, jobs, which);
     else
         hipLaunchKernelGGL(k_window_t_sc<EELS_FP32>, grid, dim3(256), 0, st, (uint32_t*)dst, src, wstride,
-                           n_beams, K, ldo, perm);
+                           n_beams, K, ldo, perm, jobs, which);
+}
+
+void launch_window_t_sc(void* dst, const float2* src, int64_t wstride, int n_beams, int K, int ldo, int prec,
+                        hipStream_t st, const int* perm) {
+    window_t_go(dst, src, wstride, n_beams, K, ldo, prec, st, perm, nullptr, 1, 0);
+}
+
+void launch_window_t_batched(void* dst_base, const float2* src_base, const ProdJob* jobs, int n_jobs, int which,
+                             int64_t wstride, int n_beams, int K, int ldo, int prec, const int* perm, hipStream_t st) {
+    window_t_go(dst_base, src_base, wstride, n_beams, K, ldo, prec, st, perm, jobs, n_jobs, which);
 }
 
 // Window-Gram form of the detector sum: G = gscale M o S with S[r][c] = sum_t conj(H_t[r]) H_t[c]
@@ -769,8 +791,15 @@ void launch_window_t_sc(void* dst, const float2* src, int64_t wstride, int n_bea
 template <int PREC>
 __global__ __launch_bounds__(256) void k_wgram_combine(uint32_t* __restrict__ dst, const float2* __restrict__ Mg,
                                                        const float2* __restrict__ H, int nt, int K, int ldm,
-                                                       int ldg, float gscale) {
+                                                       int ldg, float gscale, const ProdJob* __restrict__ jobs) {
     __shared__ float2 tile[64][65];
+    if (jobs) {   // batched: job blockIdx.z's G, M (both in the buffer dst and Mg point to) and H
+        const ProdJob& j = jobs[blockIdx.z];
+        dst = (uint32_t*)((char*)dst + 8 * j.g);
+        Mg += j.m;
+        H += j.h;
+        nt = j.nt;
+    }
     __shared__ float2 hr[16][64], hc[16][64];
     const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
@@ -894,19 +923,29 @@ __global__ __launch_bounds__(256) void k_wgram_dot(float* __restrict__ out, cons
     if (lane == 0) out[i] = oscale * acc;
 }
 
-void launch_wgram_combine(void* G, const float2* M, const float2* H, int nt, int K, int ldm, int ldg, float gscale,
-                          int prec, hipStream_t st) {
-    if (K <= 0) return;
-    dim3 grid((unsigned)ceil_div(ldg, 64), (unsigned)ceil_div(K, 64));
+static void combine_go(void* G, const float2* M, const float2* H, int nt, int K, int ldm, int ldg, float gscale,
+                       int prec, hipStream_t st, const ProdJob* jobs, int n_jobs) {
+    if (K <= 0 || n_jobs <= 0) return;
+    dim3 grid((unsigned)ceil_div(ldg, 64), (unsigned)ceil_div(K, 64), (unsigned)n_jobs);
     if (prec == EELS_BF16_SPLIT)
         hipLaunchKernelGGL(k_wgram_combine<EELS_BF16_SPLIT>, grid, dim3(256), 0, st, (uint32_t*)G, M, H, nt, K, ldm,
-                           ldg, gscale);
+                           ldg, gscale, jobs);
     else if (prec == EELS_FP16_SPLIT)
         hipLaunchKernelGGL(k_wgram_combine<EELS_FP16_SPLIT>, grid, dim3(256), 0, st, (uint32_t*)G, M, H, nt, K, ldm,
-                           ldg, gscale);
+                           ldg, gscale, jobs);
     else
         hipLaunchKernelGGL(k_wgram_combine<EELS_FP32>, grid, dim3(256), 0, st, (uint32_t*)G, M, H, nt, K, ldm,
-                           ldg, gscale);
+                           ldg, gscale, jobs);
+}
+
+void launch_wgram_combine(void* G, const float2* M, const float2* H, int nt, int K, int ldm, int ldg, float gscale,
+                          int prec, hipStream_t st) {
+    combine_go(G, M, H, nt, K, ldm, ldg, gscale, prec, st, nullptr, 1);
+}
+
+void launch_wgram_combine_batched(void* mid2, const float2* H, const ProdJob* jobs, int n_jobs, int K, int ldm, int ldg,
+                                  float gscale, int prec, hipStream_t st) {
+    combine_go(mid2, (const float2*)mid2, H, 0, K, ldm, ldg, gscale, prec, st, jobs, n_jobs);
 }
 
 void launch_wgram_dot(float* out, const void* psi, const float2* Y, int rows, int K, int ld, float oscale, int prec,
@@ -1032,7 +1071,15 @@ void launch_to_sc(void* dst, const float2* src, int64_t rows, int K, int ld, int
     int64_t n = rows * ld;
     if (n <= 0) return;
     hipLaunchKernelGGL(k_to_sc, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (uint32_t*)dst, src, rows, K, ld,
-                       prec);
+                       prec, (const ProdJob*)nullptr);
+}
+
+void launch_to_sc_batched(void* dst_base, const float2* src_base, const ProdJob* jobs, int n_jobs, int64_t rows, int K,
+                          int ld, int prec, hipStream_t st) {
+    int64_t n = rows * ld;
+    if (n <= 0 || n_jobs <= 0) return;
+    hipLaunchKernelGGL(k_to_sc, dim3((unsigned)((n + 255) / 256), (unsigned)n_jobs), dim3(256), 0, st,
+                       (uint32_t*)dst_base, src_base, rows, K, ld, prec, jobs);
 }
 
 }  // namespace eels

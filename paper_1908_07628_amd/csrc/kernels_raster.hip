@@ -10,9 +10,9 @@
 //
 // One block (256 threads) takes a run of a site's window pixels.  Per pixel it loads the two
 // grids straight into registers (thread 4 s + t holds grid row s, columns t + 4 m; the beams
-// were ordered so that these loads are contiguous), runs the row DFTs in registers
-// (fft_reg), transposes through LDS, runs the column DFTs, and accumulates
-// Re(conj(Psi) Y) per residue in registers.  The block's M^2 partial sums go to `part`; the
+// were ordered so that these loads are contiguous; the next pixel's loads are issued before
+// this pixel's transforms), runs the row DFTs in registers (fft_reg), transposes through LDS,
+// runs the column DFTs, and accumulates Re(conj(Psi) Y) per residue in registers.  The block's M^2 partial sums go to `part`; the
 // FP64 reduction adds a probe's residue over the site's blocks.
 #include <hip/hip_runtime.h>
 
@@ -24,17 +24,14 @@ namespace eels {
 
 namespace {
 
-template <int M>
-__device__ __forceinline__ void dft2d(float2 (&v)[16], float2* lds, int s, int t, const float2* __restrict__ tw) {
-    constexpr int LD = M + 1;
-    fft_reg<M, -1>(v, lds, s * LD, 1, t, tw);        // row s: on exit v[m] = frequency t + 4 m
-    __syncthreads();                                  // the rows' exchange reads are done
+// Loads the two grids of window pixel r (thread 4 s + t: row s, columns t + 4 m), scaled by c(R_0).
+__device__ __forceinline__ void load_grids(float2 (&a)[16], float2 (&b)[16], const float2* __restrict__ xr,
+                                           const float2* __restrict__ zr, const int (&q)[16], const float2 (&w)[16]) {
 #pragma unroll
-    for (int m = 0; m < 16; ++m) lds[s * LD + t + 4 * m] = v[m];
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < 16; ++m) v[m] = lds[(t + 4 * m) * LD + s];
-    fft_reg<M, -1>(v, lds, s * LD, 1, t, tw);        // column s (its first barrier orders the reads above)
+    for (int m = 0; m < 16; ++m) {
+        a[m] = q[m] >= 0 ? cmul(w[m], xr[q[m]]) : make_float2(0.f, 0.f);
+        b[m] = q[m] >= 0 ? cmul(w[m], zr[q[m]]) : make_float2(0.f, 0.f);
+    }
 }
 
 template <int M>
@@ -44,7 +41,10 @@ __global__ __launch_bounds__(256) void k_raster_dot(const RasterJob* __restrict_
                                                     float oscale, const float2* __restrict__ tw,
                                                     float* __restrict__ part) {
     static_assert(M == 64, "256 threads hold a 64 x 64 grid");
-    __shared__ float2 lds[M * (M + 1)];
+    constexpr int LD = M + 1;
+    // one grid per transform; row s is both the transpose slot of row s and the exchange space
+    // of the 64-point sequence that thread group s owns (rows first, then column s)
+    __shared__ float2 la[M * LD], lb[M * LD];
     const RasterJob jb = jobs[blockIdx.y];
     const int r0 = blockIdx.x * chunk, r1 = min(K, r0 + chunk);
     const int s = threadIdx.x >> 2, t = threadIdx.x & 3;
@@ -60,17 +60,32 @@ __global__ __launch_bounds__(256) void k_raster_dot(const RasterJob* __restrict_
     for (int m = 0; m < 16; ++m) acc[m] = 0.f;
     const float2* xt = base + jb.xt;
     const float2* z = base + jb.z;
+    float2 na[16], nb[16];
+    if (r0 < r1) load_grids(na, nb, xt + (int64_t)r0 * ld, z + (int64_t)r0 * ld, q, w);
     for (int r = r0; r < r1; ++r) {
         float2 a[16], b[16];
-        const float2* xr = xt + (int64_t)r * ld;
-        const float2* zr = z + (int64_t)r * ld;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) { a[m] = na[m]; b[m] = nb[m]; }
+        if (r + 1 < r1) load_grids(na, nb, xt + (int64_t)(r + 1) * ld, z + (int64_t)(r + 1) * ld, q, w);
+        // rows: the sequence of row s lies in the 4 lanes 4 s .. 4 s + 3 of one wavefront, so its
+        // exchange through row s of the grid needs wave-level ordering only
+        fft_reg<M, -1, false, true>(a, la, s * LD, 1, t, tw);
+        fft_reg<M, -1, false, true>(b, lb, s * LD, 1, t, tw);
+        lds_sync_wave();
 #pragma unroll
         for (int m = 0; m < 16; ++m) {
-            a[m] = q[m] >= 0 ? cmul(w[m], xr[q[m]]) : make_float2(0.f, 0.f);
-            b[m] = q[m] >= 0 ? cmul(w[m], zr[q[m]]) : make_float2(0.f, 0.f);
+            la[s * LD + t + 4 * m] = a[m];
+            lb[s * LD + t + 4 * m] = b[m];
         }
-        dft2d<M>(a, lds, s, t, tw);
-        dft2d<M>(b, lds, s, t, tw);
+        __syncthreads();                 // every row transformed and written
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            a[m] = la[(t + 4 * m) * LD + s];
+            b[m] = lb[(t + 4 * m) * LD + s];
+        }
+        __syncthreads();                 // every column read: the rows are free again
+        fft_reg<M, -1, false, true>(a, la, s * LD, 1, t, tw);     // column s
+        fft_reg<M, -1, false, true>(b, lb, s * LD, 1, t, tw);
 #pragma unroll
         for (int m = 0; m < 16; ++m) acc[m] = fmaf(a[m].x, b[m].x, fmaf(a[m].y, b[m].y, acc[m]));
     }

@@ -885,6 +885,17 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
                 if (!ok) return fail(EELS_ERR_INTERNAL, "window-Gram operands leave their buffers");
             }
         }
+        if (p.wgram) {
+            std::vector<int32_t> pj;
+            for (int k = 0; k < bt.job_count; ++k) {
+                const Job& jb = p.jobs[bt.job_begin + k];
+                ProdJob q{jb.w_off, jb.s2t_off, jb.win_off, jb.xt_off, jb.s1sc_off, jb.m_off, jb.g_off, jb.h_off,
+                          jb.nt, 0};
+                const int32_t* w = (const int32_t*)&q;
+                pj.insert(pj.end(), w, w + sizeof(ProdJob) / 4);
+            }
+            bt.p_jobs = B.append(pj);
+        }
         if (p.raster) {
             std::vector<int32_t> rj;
             for (int k = 0; k < bt.job_count; ++k) {
