@@ -10,9 +10,9 @@
 //
 // One block (256 threads) takes a run of a site's window pixels.  Per pixel it loads the two
 // grids straight into registers (thread 4 s + t holds grid row s, columns t + 4 m; the beams
-// were ordered so that these loads are contiguous; the next pixel's loads are issued before
-// this pixel's transforms), runs the row DFTs in registers (fft_reg), transposes through LDS,
-// runs the column DFTs, and accumulates Re(conj(Psi) Y) per residue in registers.  The block's M^2 partial sums go to `part`; the
+// were ordered so that these loads are contiguous), runs the row DFTs in registers (fft_reg),
+// transposes through LDS, runs the column DFTs, and accumulates Re(conj(Psi) Y) per residue in
+// registers.  Two blocks share a CU (two waves per SIMD hide the loads' latency).  The block's M^2 partial sums go to `part`; the
 // FP64 reduction adds a probe's residue over the site's blocks.
 #include <hip/hip_runtime.h>
 
@@ -60,13 +60,9 @@ __global__ __launch_bounds__(256) void k_raster_dot(const RasterJob* __restrict_
     for (int m = 0; m < 16; ++m) acc[m] = 0.f;
     const float2* xt = base + jb.xt;
     const float2* z = base + jb.z;
-    float2 na[16], nb[16];
-    if (r0 < r1) load_grids(na, nb, xt + (int64_t)r0 * ld, z + (int64_t)r0 * ld, q, w);
     for (int r = r0; r < r1; ++r) {
         float2 a[16], b[16];
-#pragma unroll
-        for (int m = 0; m < 16; ++m) { a[m] = na[m]; b[m] = nb[m]; }
-        if (r + 1 < r1) load_grids(na, nb, xt + (int64_t)(r + 1) * ld, z + (int64_t)(r + 1) * ld, q, w);
+        load_grids(a, b, xt + (int64_t)r * ld, z + (int64_t)r * ld, q, w);
         // rows: the sequence of row s lies in the 4 lanes 4 s .. 4 s + 3 of one wavefront, so its
         // exchange through row s of the grid needs wave-level ordering only
         fft_reg<M, -1, false, true>(a, la, s * LD, 1, t, tw);
