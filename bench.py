@@ -211,6 +211,21 @@ def bench_batch(args):
     fused_stable = all(np.array_equal(g, r) for g, r in zip(fused_graph, fused_eager))
     del bf
     torch.cuda.empty_cache()
+    # the same batch in plain FP32 (one captured graph on the same 4 branches)
+    b32 = Batch(specs, precision="fp32", n_streams=4, tuned=False)
+    b32.run_eager()
+    m32 = b32.maps_host()
+    b32.capture()
+    b32.replay()
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    for _ in range(args.steps):
+        b32.replay()
+    torch.cuda.synchronize()
+    t_fp32 = (time.perf_counter() - t4) / args.steps
+    fp32_vs = max(float(np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-300)) for g, r in zip(ref, m32))
+    del b32
+    torch.cuda.empty_cache()
     return {
         "metric": METRIC, "value": round(probes / t_graph, 2), "unit": "probe-px/s", "n_gpus": 1,
         "steps": args.steps, "warmup": 1, "ms_per_step": round(1e3 * t_graph, 1), "higher_is_better": True,
@@ -227,6 +242,10 @@ def bench_batch(args):
                   "what": ("specimens' sweeps on 4 stream branches, then each contraction level's GEMMs of "
                            "all specimens in one grouped launch per kernel variant (eels_batch_contract); "
                            "one captured graph")},
+        "fp32": {"value": round(probes / t_fp32, 2), "ms_per_step": round(1e3 * t_fp32, 1),
+                 "split_rel_l2_vs_fp32_worst": fp32_vs,
+                 "what": "the same specimens in plain FP32, one captured graph on 4 stream branches"},
+        "split_over_fp32": round(t_fp32 / t_graph, 2),
     }
 
 

@@ -248,7 +248,8 @@ eels_status eels_plan_s_signature(const eels_plan* p, uint64_t* sig);
  *   eels_batch_create   host only: checks the plans, builds and bounds-checks the merged
  *                       descriptors (their offsets count from the arena base).  The plans
  *                       must outlive the batch.
- *   eels_batch_table_bytes  device bytes of the merged table.
+ *   eels_batch_table_bytes  device bytes of the merged table (the descriptors and one work
+ *                       counter per grouped launch).
  *   eels_batch_upload   copies the table to d_table (256-byte aligned, caller-owned) on
  *                       `stream`; once, before any (captured) contraction.
  *   eels_batch_contract enqueues on `stream`, after every plan's eels_execute_ex with
@@ -257,6 +258,11 @@ eels_status eels_plan_s_signature(const eels_plan* p, uint64_t* sig);
  *                       level, the FP64 reductions into d_maps[i] (float64 [n_probes of plan
  *                       i], zeroed by the sweeps-only execute).  d_H[i]: plan i's transition
  *                       potentials.  No allocation, no host synchronisation (capturable).
+ *                       Each grouped GEMM runs as a persistent launch: the device's resident
+ *                       workgroups take (plan, site, tile) work items from that launch's
+ *                       counter in d_table, which the call first zeroes with a kernel (so
+ *                       every replay of a captured graph starts from zero; calls sharing one
+ *                       d_table must not overlap).
  * Results equal each plan's own eels_execute bit for bit.  Errors: INVALID_ARG (null
  * pointers, mixed or FP32 precision, non-resident or window-Gram plans, workspace
  * regions), INTERNAL (a merged descriptor outside its plan's workspace), DEVICE. */

@@ -1051,6 +1051,7 @@ eels_status eels_timing_read(double* ms, int* counts) {
 struct eels_batch {
     struct Launch {
         int epi, rows, begin, count, tiles;
+        int queue = 0;          // its work counter (index after the descriptors in the device table)
     };
     struct Member {
         int plan, batch;
@@ -1064,6 +1065,10 @@ struct eels_batch {
     std::vector<size_t> ws_off;
     std::vector<Level> levels;
     std::vector<GemmDesc> table;
+    int n_queues = 0;
+    // byte offset of the work counters in the device table (after the descriptors, 256-aligned)
+    size_t queue_off() const { return (size_t)round_up((int64_t)std::max<size_t>(table.size(), 1) * sizeof(GemmDesc), 256); }
+    size_t queue_bytes() const { return (size_t)round_up((int64_t)std::max(n_queues, 1) * 4, 16); }
 };
 
 namespace {
@@ -1206,6 +1211,7 @@ eels_status eels_batch_create(eels_batch** out, const eels_plan* const* plans, i
                 for (size_t q = 0; q < g.size(); ++q) {
                     g[q].begin = (int)b->table.size();
                     g[q].count = (int)dv[q].size();
+                    g[q].queue = b->n_queues++;
                     b->table.insert(b->table.end(), dv[q].begin(), dv[q].end());
                 }
             }
@@ -1221,7 +1227,7 @@ eels_status eels_batch_create(eels_batch** out, const eels_plan* const* plans, i
 
 eels_status eels_batch_table_bytes(const eels_batch* b, size_t* bytes) {
     if (!b || !bytes) return EELS_ERR_INVALID_ARG;
-    *bytes = std::max<size_t>(b->table.size(), 1) * sizeof(GemmDesc);
+    *bytes = b->queue_off() + b->queue_bytes();
     return EELS_OK;
 }
 
@@ -1251,10 +1257,14 @@ eels_status eels_batch_contract(const eels_batch* b, void* d_arena, const void* 
     hipStream_t st = (hipStream_t)stream;
     char* arena = (char*)d_arena;
     const GemmDesc* table = (const GemmDesc*)d_table;
+    // the grouped GEMMs run persistently: each launch's resident workgroups take tiles from its
+    // work counter, zeroed here by a kernel (so that a captured graph resets them on every replay)
+    int* queues = (int*)((char*)const_cast<void*>(d_table) + b->queue_off());
     std::vector<Dev> devs;
     for (int i = 0; i < n; ++i) devs.push_back(make_dev(b->plans[i]->p, arena + b->ws_off[i]));
     const int nst = tune_get(TUNE_SC_STAGES);
     g_timing.used = 0;
+    launch_fill_zero(queues, b->queue_bytes(), st);
     for (const auto& lv : b->levels) {
         for (const auto& m : lv.members) {
             const Plan& p = b->plans[m.plan]->p;
@@ -1264,7 +1274,7 @@ eels_status eels_batch_contract(const eels_batch* b, void* d_arena, const void* 
             TimeScope ts(EELS_PHASE_GEMM1, st);
             for (const auto& g : lv.g1)
                 launch_cgemm_sc(b->precision, g.epi, nst, table + g.begin, g.count, g.tiles, arena, arena, arena,
-                                (float*)arena, (const int*)arena, st, g.rows);
+                                (float*)arena, (const int*)arena, st, g.rows, queues + g.queue);
         }
         for (const auto& m : lv.members) {
             const Plan& p = b->plans[m.plan]->p;
@@ -1274,7 +1284,7 @@ eels_status eels_batch_contract(const eels_batch* b, void* d_arena, const void* 
             TimeScope ts(EELS_PHASE_GEMM2, st);
             for (const auto& g : lv.g2)
                 launch_cgemm_sc(b->precision, g.epi, nst, table + g.begin, g.count, g.tiles, arena, arena, arena,
-                                (float*)arena, (const int*)arena, st, g.rows);
+                                (float*)arena, (const int*)arena, st, g.rows, queues + g.queue);
         }
         for (const auto& m : lv.members) {
             const Plan& p = b->plans[m.plan]->p;

@@ -94,9 +94,12 @@ void launch_cgemm(int precision, int kind, int epi, const GemmDesc* d_descs, int
 // complex64.  The index list gathers B rows, or A rows with GD_IDX_A.
 // rows: A rows of a tile, 128, or 256 (epi 0 and 3 only; the descriptors' tiles_m must
 // count 256-row tiles).
+// queue (may be null): a device int, zero before the launch; the grid is then the device's
+// resident workgroups, which take tiles from the queue until all total_tiles are done
+// (persistent launch, tiles in m-fastest order).
 void launch_cgemm_sc(int precision, int epi, int nstage, const GemmDesc* d_descs, int n_desc, int total_tiles,
                      const void* A, const void* B, void* C, float* part, const int* idx, hipStream_t st,
-                     int rows = 128);
+                     int rows = 128, int* queue = nullptr);
 // S_1 or S_2 window [n_beams][K] (complex64, rows wstride apart) -> its transpose [K][ldo],
 // SC for the split precisions, complex64 for EELS_FP32 (beams n_beams .. ldo-1 zero; ldo a
 // multiple of 4, dst 32-byte aligned)

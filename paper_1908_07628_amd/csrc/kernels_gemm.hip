@@ -19,6 +19,7 @@
 // the store epilogue.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "internal.h"
@@ -88,10 +89,9 @@ __device__ __forceinline__ u32x4 swap_halves(u32x4 v) {  // (re, im) -> (im, re)
 // Returns the descriptor index.
 template <int G = 8>
 __device__ __forceinline__ int locate_tile(const GemmDesc* __restrict__ descs, int n_desc, int order, int& tm,
-                                           int& tn, int& t) {
-    int bid = blockIdx.x;
+                                           int& tn, int& t, int bid, int ntiles) {
     if (order == 2) {
-        const int nt = gridDim.x, x = bid & 7, s = bid >> 3, q = nt >> 3, r = nt & 7;
+        const int nt = ntiles, x = bid & 7, s = bid >> 3, q = nt >> 3, r = nt & 7;
         bid = x * q + min(x, r) + s;
     }
     int lo = 0, hi = n_desc - 1;
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(256) void k_cgemm(const GemmDesc* __restrict__ desc
 
     // ---- locate this block's problem and tile
     int tm, tn, t;
-    const GemmDesc& d = descs[locate_tile(descs, n_desc, order, tm, tn, t)];
+    const GemmDesc& d = descs[locate_tile(descs, n_desc, order, tm, tn, t, blockIdx.x, gridDim.x)];
     if constexpr (EPI == 2) {
         if (tn < tm) return;   // Gram tiles: the lower triangle is the conjugate transpose
     }
@@ -446,16 +446,20 @@ struct ScPipe {
 template <int PREC, int EPI, int NSTAGE, int UNITS, int SCHED, int WM>
 __global__ __launch_bounds__(128 * WM, (ScPipe<UNITS, NSTAGE, WM>::WAVES_PER_EU)) void k_cgemm_sc(
     const GemmDesc* __restrict__ descs, int n_desc, const uint32_t* __restrict__ Ab, const uint32_t* __restrict__ Bb,
-    uint32_t* __restrict__ Cb, float* __restrict__ Pb, const int* __restrict__ ib, int order) {
+    uint32_t* __restrict__ Cb, float* __restrict__ Pb, const int* __restrict__ ib, int order,
+    int* __restrict__ queue, int ntiles) {
     using SP = ScPipe<UNITS, NSTAGE, WM>;
     constexpr int STAGE = SP::STAGE, ROWB = SP::ROWB, QUADS = SP::QUADS, RPI = SP::RPI, NIA = SP::NIA, NIB = SP::NIB;
     constexpr int BMX = SP::BMX, NT = 128 * WM;
     constexpr int BKS = 4 * UNITS;  // complex per tile row
     static_assert(WM == 2 || EPI != 2, "the 256-row tile has no Gram epilogue");
     __shared__ __attribute__((aligned(1024))) char smem[NSTAGE * STAGE];
+    __shared__ int next_tile;
 
+  // one output tile (bid in 0 .. ntiles-1); a return skips the tile
+  auto run_tile = [&](const int bid) {
     int tm, tn, t;
-    const GemmDesc& d = descs[locate_tile<SP::G>(descs, n_desc, order, tm, tn, t)];
+    const GemmDesc& d = descs[locate_tile<SP::G>(descs, n_desc, order, tm, tn, t, bid, ntiles)];
     if constexpr (EPI == 2) {
         if (tn < tm) return;   // Gram tiles: the lower triangle is the conjugate transpose
     }
@@ -685,6 +689,21 @@ __global__ __launch_bounds__(128 * WM, (ScPipe<UNITS, NSTAGE, WM>::WAVES_PER_EU)
             for (int w = 1; w < WM; ++w) acc += red[w * BN + tid];
             if (i < N) Pb[d.p_off + (int64_t)tm * d.ld_part + (int64_t)t * N + i] = acc;
         }
+    }
+  };
+
+    if (!queue) {
+        run_tile(blockIdx.x);
+        return;
+    }
+    // persistent: the resident workgroups take tiles from the work queue until it runs dry
+    for (;;) {
+        if (threadIdx.x == 0) next_tile = atomicAdd(queue, 1);
+        __syncthreads();                 // the previous tile's LDS reads are done, next_tile set
+        const int bid = next_tile;
+        __syncthreads();                 // every thread has read next_tile
+        if (bid >= ntiles) break;
+        run_tile(bid);
     }
 }
 
@@ -996,18 +1015,38 @@ void launch_cgemm(int precision, int kind, int epi, const GemmDesc* dd, int nd, 
 }
 
 
+// Workgroups of one kernel that are resident at once on the whole device (persistent grids).
+template <typename KERN>
+static int resident_blocks(KERN kern, int block) {
+    static thread_local int n_cu = 0;
+    if (n_cu == 0) {
+        int dev = 0;
+        hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu <= 0) n_cu = 256;
+    }
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, block, 0) != hipSuccess || per <= 0) per = 1;
+    return n_cu * per;
+}
+
 template <int PREC, int EPI>
 static void go_sc(int nstage, int rows, const GemmDesc* dd, int nd, int tiles, const uint32_t* A, const uint32_t* B,
-                  uint32_t* C, float* P, const int* idx, hipStream_t st) {
+                  uint32_t* C, float* P, const int* idx, hipStream_t st, int* queue) {
     // pipeline variants: 2 / 3 stages of 16-complex tiles, 4 / 5 stages of 8-complex tiles;
-    // 256-row tiles (store epilogue) with two stages of 16-complex tiles
-    const int order = tune_get(TUNE_TILE_ORDER);
-#define SCV(NS, U, SC) \
-    hipLaunchKernelGGL((k_cgemm_sc<PREC, EPI, NS, U, SC, 2>), dim3(tiles), dim3(256), 0, st, dd, nd, A, B, C, P, idx, order)
+    // 256-row tiles (store epilogue) with two stages of 16-complex tiles.  With a work queue the
+    // grid is the device's resident workgroups, which take the tiles from the queue.
+    const int order = queue ? 0 : tune_get(TUNE_TILE_ORDER);
+#define SCV(NS, U, SC)                                                                                                 \
+    do {                                                                                                               \
+        auto kern = k_cgemm_sc<PREC, EPI, NS, U, SC, 2>;                                                               \
+        const int grid = queue ? std::min(tiles, resident_blocks(kern, 256)) : tiles;                                  \
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, st, dd, nd, A, B, C, P, idx, order, queue, tiles);         \
+    } while (0)
     if constexpr (EPI != 2) {
         if (rows == 256) {
-            hipLaunchKernelGGL((k_cgemm_sc<PREC, EPI, 2, 4, 0, 4>), dim3(tiles), dim3(512), 0, st, dd, nd, A, B, C, P,
-                               idx, order);
+            auto kern = k_cgemm_sc<PREC, EPI, 2, 4, 0, 4>;
+            const int grid = queue ? std::min(tiles, resident_blocks(kern, 512)) : tiles;
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(512), 0, st, dd, nd, A, B, C, P, idx, order, queue, tiles);
             return;
         }
     }
@@ -1028,20 +1067,20 @@ static void go_sc(int nstage, int rows, const GemmDesc* dd, int nd, int tiles, c
 }
 
 void launch_cgemm_sc(int precision, int epi, int nstage, const GemmDesc* dd, int nd, int tiles, const void* A,
-                     const void* B, void* C, float* part, const int* idx, hipStream_t st, int rows) {
+                     const void* B, void* C, float* part, const int* idx, hipStream_t st, int rows, int* queue) {
     if (tiles <= 0 || nd <= 0) return;
     const uint32_t *a = (const uint32_t*)A, *b = (const uint32_t*)B;
     uint32_t* c = (uint32_t*)C;
     if (precision == EELS_BF16_SPLIT) {
-        if (epi == 0) go_sc<EELS_BF16_SPLIT, 0>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st);
-        else if (epi == 2) go_sc<EELS_BF16_SPLIT, 2>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st);
-        else if (epi == 3) go_sc<EELS_BF16_SPLIT, 3>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st);
-        else go_sc<EELS_BF16_SPLIT, 1>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st);
+        if (epi == 0) go_sc<EELS_BF16_SPLIT, 0>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st, queue);
+        else if (epi == 2) go_sc<EELS_BF16_SPLIT, 2>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st, queue);
+        else if (epi == 3) go_sc<EELS_BF16_SPLIT, 3>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st, queue);
+        else go_sc<EELS_BF16_SPLIT, 1>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st, queue);
     } else {
-        if (epi == 0) go_sc<EELS_FP16_SPLIT, 0>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st);
-        else if (epi == 2) go_sc<EELS_FP16_SPLIT, 2>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st);
-        else if (epi == 3) go_sc<EELS_FP16_SPLIT, 3>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st);
-        else go_sc<EELS_FP16_SPLIT, 1>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st);
+        if (epi == 0) go_sc<EELS_FP16_SPLIT, 0>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st, queue);
+        else if (epi == 2) go_sc<EELS_FP16_SPLIT, 2>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st, queue);
+        else if (epi == 3) go_sc<EELS_FP16_SPLIT, 3>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st, queue);
+        else go_sc<EELS_FP16_SPLIT, 1>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st, queue);
     }
 }
 
