@@ -43,7 +43,7 @@ enum {
     EELS_OK = 0,
     EELS_ERR_INVALID_ARG = 1,      /* a size, pointer or parameter is out of range       */
     EELS_ERR_BANDLIMIT = 2,        /* an aperture or detector beam lies outside the band  */
-    EELS_ERR_UNSUPPORTED_SIZE = 3, /* grid side not a power of two in [16, 1024]         */
+    EELS_ERR_UNSUPPORTED_SIZE = 3, /* grid side not a power of two in [16, 1024] or 384  */
     EELS_ERR_WORKSPACE = 4,        /* workspace pointer null or smaller than required     */
     EELS_ERR_OOM = 5,              /* the problem does not fit the memory budget          */
     EELS_ERR_DEVICE = 6,           /* a HIP call failed (message via eels_last_error)     */

@@ -782,6 +782,10 @@ eels_status eels_conventional_map(const eels_plan* pl, const float* d_V, const v
         set_error("conventional multislice needs interp_f = 1");
         return EELS_ERR_INVALID_ARG;
     }
+    if ((p.nx & (p.nx - 1)) || (p.ny & (p.ny - 1))) {
+        set_error("conventional multislice needs power-of-two grid sides");
+        return EELS_ERR_UNSUPPORTED_SIZE;
+    }
     if (p.n_trans_total > 0 && !d_H) {
         set_error("transition potentials missing");
         return EELS_ERR_INVALID_ARG;

@@ -1,4 +1,5 @@
-// Register-resident Stockham FFT (radix 16 first, then 16/8/4/2), LDS only between stages.
+// Register-resident Stockham FFT (radix 16 first, then 16/8/4/2; sides with a factor 3: radix
+// 24 first, then 8 and 2), LDS only between stages.
 //
 // T = N / E threads cooperate on one sequence of length N; thread t holds the E elements
 // t + T m (m = 0 .. E-1) in v[m], both on entry and on exit.  The first stage has radix
@@ -51,22 +52,62 @@ __device__ __forceinline__ void dft16(float2* v) {
     }
 }
 
+// 3-point DFT: w = exp(DIR 2 pi i / 3) = -1/2 + DIR i sqrt(3)/2
+template <int DIR>
+__device__ __forceinline__ void dft3(float2& a, float2& b, float2& c) {
+    constexpr float h = 0.86602540378443865f;
+    const float2 s = cadd(b, c), d = csub(b, c);
+    const float2 m = make_float2(fmaf(-0.5f, s.x, a.x), fmaf(-0.5f, s.y, a.y));
+    const float2 r = mul_i<DIR>(make_float2(h * d.x, h * d.y));
+    a = cadd(a, s);
+    b = cadd(m, r);
+    c = csub(m, r);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft24(float2* v) {
+    // 24 = 3 x 8: x[8 n1 + n2] -> DFT3 over n1 (k1), twiddle W24^(n2 k1), DFT8 over n2 (k2);
+    // X[k1 + 3 k2].  W24^p = cos(2 pi p / 24) + DIR i sin(2 pi p / 24), p = n2 k1 <= 14.
+    constexpr float wc[15] = {1.0f, 0.9659258262890683f, 0.8660254037844387f, 0.7071067811865476f, 0.5000000000000001f, 0.25881904510252074f, 0.0f, -0.25881904510252063f, -0.4999999999999998f, -0.7071067811865475f, -0.8660254037844387f, -0.9659258262890682f, -1.0f, -0.9659258262890683f, -0.8660254037844388f};
+    constexpr float ws[15] = {0.0f, 0.25881904510252074f, 0.49999999999999994f, 0.7071067811865475f, 0.8660254037844386f, 0.9659258262890683f, 1.0f, 0.9659258262890683f, 0.8660254037844387f, 0.7071067811865476f, 0.49999999999999994f, 0.258819045102521f, 0.0f, -0.2588190451025208f, -0.4999999999999997f};
+    float2 a[3][8];
+#pragma unroll
+    for (int n2 = 0; n2 < 8; ++n2) {
+        float2 x0 = v[n2], x1 = v[8 + n2], x2 = v[16 + n2];
+        dft3<DIR>(x0, x1, x2);
+        a[0][n2] = x0;
+        a[1][n2] = n2 == 0 ? x1 : cmul(x1, make_float2(wc[n2], DIR * ws[n2]));
+        a[2][n2] = n2 == 0 ? x2 : cmul(x2, make_float2(wc[2 * n2], DIR * ws[2 * n2]));
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+        dft<8, DIR>(a[k1]);
+#pragma unroll
+        for (int k2 = 0; k2 < 8; ++k2) v[k1 + 3 * k2] = a[k1][k2];
+    }
+}
+
 template <int R, int DIR>
 __device__ __forceinline__ void dft_any(float2* v) {
     if constexpr (R == 16) dft16<DIR>(v);
+    else if constexpr (R == 24) dft24<DIR>(v);
     else dft<R, DIR>(v);
 }
 
+// Elements per thread: 16 (radix-16 first stage) for powers of two; sides with a factor 3
+// (384 = 3 x 128) hold 24 (a radix-24 = 3 x 8 first stage, then radices 8 and 2).
 template <int N>
 struct RegCfg {
-    static constexpr int E = N >= 16 ? 16 : N;
+    static constexpr int E = N % 3 == 0 ? 24 : (N >= 16 ? 16 : N);
     static constexpr int T = N / E;
 };
 
+// the largest radix of {16, 8, 4, 2} that divides both what is left of N and E
 template <int N, int Ns, int E>
 struct RegRadix {
     static constexpr int REM = N / Ns;
-    static constexpr int R = REM >= 16 && E >= 16 ? 16 : (REM >= 8 ? 8 : (REM >= 4 ? 4 : 2));
+    static constexpr int R = (REM % 16 == 0 && E % 16 == 0) ? 16
+                           : (REM % 8 == 0 && E % 8 == 0) ? 8 : (REM % 4 == 0 && E % 4 == 0) ? 4 : 2;
 };
 
 // stage with butterfly radix R on elements in registers (first stage) or LDS (later)
@@ -96,7 +137,7 @@ __device__ __forceinline__ void fft_reg_stages(float2 (&v)[E], float2* lds, int 
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         int j = t + b * T;
-        int k = j & (Ns - 1);
+        int k = (int)((unsigned)j % (unsigned)Ns);   // a mask for powers of two
         if constexpr (Ns > 1) {
 #pragma unroll
             for (int r = 1; r < R; ++r) {
@@ -119,7 +160,7 @@ __device__ __forceinline__ void fft_reg_stages(float2 (&v)[E], float2* lds, int 
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             int j = t + b * T;
-            int k = j & (Ns - 1);
+            int k = (int)((unsigned)j % (unsigned)Ns);   // a mask for powers of two
             int idxD = (j - k) * R + k;
 #pragma unroll
             for (int r = 0; r < R; ++r) at(idxD + r * Ns) = u[b][r];

@@ -314,9 +314,10 @@ __device__ __forceinline__ void row_pass_body(float2* __restrict__ state, int nb
 }
 
 // Two waves per SIMD, with and without capture (at N = 1024 the capturing variant spills
-// 36 bytes per lane to get there, and is faster for it than at one wave).
+// 36 bytes per lane to get there, and is faster for it than at one wave); one wave for the
+// 24-element sequences of the sides with a factor 3, whose registers do not fit two.
 template <int N, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_row_pass(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RegCfg<N>::E > 16 ? 1 : 2))) void k_row_pass(
     float2* __restrict__ state, int nbeam, int ny, int nlx, int hlx, int ldx, const float2* __restrict__ Tj,
     const float2* __restrict__ tw) {
     __shared__ float2 lds[(256 / RegCfg<N>::T) * PadLen<N>::value];
@@ -324,7 +325,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 }
 
 template <int N, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_row_pass_cap(float2* __restrict__ state, int nbeam, int ny, int nlx, int hlx,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RegCfg<N>::E > 16 ? 1 : 2))) void k_row_pass_cap(float2* __restrict__ state, int nbeam, int ny, int nlx, int hlx,
                                                       int ldx, const float2* __restrict__ Tj,
                                                       const float2* __restrict__ tw, const int* __restrict__ cap_ptr,
                                                       const int4* __restrict__ cap_rec, void* __restrict__ win,
@@ -418,7 +419,7 @@ __device__ __forceinline__ void col_pass_body(float2* __restrict__ state, int nb
 }
 
 template <int N, int MODE>
-__global__ __launch_bounds__(ColCfg<N>::NT) __attribute__((amdgpu_waves_per_eu(2))) void k_col_pass(
+__global__ __launch_bounds__(ColCfg<N>::NT) __attribute__((amdgpu_waves_per_eu(RegCfg<N>::E > 16 ? 1 : 2))) void k_col_pass(
     float2* __restrict__ state, int nbeam, int nlx, int ldx, const float2* __restrict__ Pj,
     const float2* __restrict__ tw, const int* __restrict__ band_h) {
     __shared__ float2 lds[N * ColCfg<N>::CW];
@@ -709,7 +710,7 @@ void launch_row_pass(int nx, int mode, const RowPassArgs& a, hipStream_t st) {
         else row_pass_n<NN, 2>(a, st);                \
         break;
     switch (nx) {
-        ROWCASE(16) ROWCASE(32) ROWCASE(64) ROWCASE(128) ROWCASE(256) ROWCASE(512) ROWCASE(1024)
+        ROWCASE(16) ROWCASE(32) ROWCASE(64) ROWCASE(128) ROWCASE(256) ROWCASE(384) ROWCASE(512) ROWCASE(1024)
         default: break;
     }
 #undef ROWCASE
@@ -738,7 +739,7 @@ void launch_col_pass(int ny, int mode, float2* state, int nbeam, int nlx, int ld
         else col_pass_n<NN, 2>(state, nbeam, nlx, ldx, Pj, tw, band_h, bc, st);    \
         break;
     switch (ny) {
-        COLCASE(16) COLCASE(32) COLCASE(64) COLCASE(128) COLCASE(256) COLCASE(512) COLCASE(1024)
+        COLCASE(16) COLCASE(32) COLCASE(64) COLCASE(128) COLCASE(256) COLCASE(384) COLCASE(512) COLCASE(1024)
         default: break;
     }
 #undef COLCASE

@@ -33,6 +33,8 @@ double sigma_VA(double eV, double lam_A) {
 }
 
 bool pow2_ok(int n) { return n >= 16 && n <= 1024 && (n & (n - 1)) == 0; }
+// grid sides of the sweeps: powers of two in [16, 1024], and 384 (= 3 x 128, radix-3 passes)
+bool side_ok(int n) { return pow2_ok(n) || n == 384; }
 
 // Plane waves k = (f a / lx, f b / ly) with th_lo <= lambda |k| <= th_hi, ordered by (b, a).
 std::vector<int> lattice(double lx, double ly, int f, double lam, double th_lo, double th_hi) {
@@ -70,8 +72,8 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     auto fail = [&](eels_status s, const std::string& m) { set_error(m); return s; };
     if (q.nx <= 0 || q.ny <= 0 || !(q.lx_A > 0) || !(q.ly_A > 0) || q.n_slices <= 0 || !q.dz_A)
         return fail(EELS_ERR_INVALID_ARG, "grid, cell or slices invalid");
-    if (!pow2_ok(q.nx) || !pow2_ok(q.ny))
-        return fail(EELS_ERR_UNSUPPORTED_SIZE, "grid sides must be powers of two in [16, 1024]");
+    if (!side_ok(q.nx) || !side_ok(q.ny))
+        return fail(EELS_ERR_UNSUPPORTED_SIZE, "grid sides must be powers of two in [16, 1024] or 384");
     if (q.n_probes <= 0 || !q.probe_xy) return fail(EELS_ERR_INVALID_ARG, "no probes");
     if (q.n_sites < 0 || (q.n_sites > 0 && !q.sites)) return fail(EELS_ERR_INVALID_ARG, "sites");
     if (q.interp_f < 1) return fail(EELS_ERR_INVALID_ARG, "interp_f must be >= 1");
@@ -239,6 +241,9 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     // full-cell windows contract in the band basis (exact): sum_r S_2 H S_1 equals the sum
     // over band pixels g of (P_j x_{j+1})(g) * fft2(T_j H S_1)(g)
     p.recip = p.full_window && !q.real_space;
+    if (p.recip && (!pow2_ok(p.nx) || !pow2_ok(p.ny)))
+        return fail(EELS_ERR_UNSUPPORTED_SIZE, "the band-basis contraction needs power-of-two grid sides "
+                                               "(use a crop window or real_space)");
     const bool split = p.precision != EELS_FP32;
     const int Kc = p.recip ? p.Kb : p.K;            // contraction length of the big GEMM
     const int Kcpad = p.recip ? p.Kbpad : p.Kpad;

@@ -535,11 +535,12 @@ def specimen_pool(seed: int, n_specimens: int, sizes, slices, ions, scans, prefi
     return [_pool_one(a) for a in args]
 
 
-def config4(seed: int = 4, n_specimens: int = 64, sizes=(128, 256, 512), slices=(10, 80),
+def config4(seed: int = 4, n_specimens: int = 64, sizes=(128, 256, 384, 512), slices=(10, 80),
             ions=(1, 20), scans=(16, 64), workers: int = 1) -> List[Problem]:
-    """The batching workload: specimens of uneven size drawn from a seed (grids 128^2 to
-    512^2 at 0.1 A/px with f = N/128, 10-80 slices of 2 A, 1-20 ionised atoms with 3-9
-    transitions each, 16^2 to 64^2 probes, 4 A crop, 20 mrad aperture, 0-40 mrad detector)."""
+    """The batching workload: specimens of uneven size drawn from a seed (grids 128^2, 256^2,
+    384^2 and 512^2 at 0.1 A/px with f = N/128, 10-80 slices of 2 A, 1-20 ionised atoms with
+    3-9 transitions each, 16^2 to 64^2 probes, 4 A crop, 20 mrad aperture, 0-40 mrad
+    detector)."""
     return specimen_pool(seed, n_specimens, sizes, slices, ions, scans, "config4", workers)
 
 

@@ -1,7 +1,7 @@
-"""Write config4_samples.json: FP64 PRISM map values of two specimens of the 64-specimen batch
-workload (synth.config4: the cheapest 128^2 specimen, f = 1, and the cheapest 256^2 one,
-f = 2, both with 4 A crop windows) at sampled probe positions, computed with the PRISM
-oracle only (oracle.prism.prism_map on the sampled probes).
+"""Write config4_samples.json: FP64 PRISM map values of three specimens of the 64-specimen
+batch workload (synth.config4: the cheapest 128^2 specimen, f = 1, the cheapest 256^2 one,
+f = 2, and the cheapest 384^2 one, f = 3, all with 4 A crop windows) at sampled probe
+positions, computed with the PRISM oracle only (oracle.prism.prism_map on the sampled probes).
 
 Usage: python tests/golden/make_config4_samples.py
 """
@@ -22,9 +22,9 @@ N_SAMPLES = 16
 
 
 def picks(specs):
-    """Index of the cheapest specimen (grid x slices) of each of the grids 128 and 256."""
+    """Index of the cheapest specimen (grid x slices) of each of the grids 128, 256 and 384."""
     out = []
-    for n in (128, 256):
+    for n in (128, 256, 384):
         cand = [i for i, p in enumerate(specs) if p.nx == n]
         out.append(min(cand, key=lambda i: (specs[i].n_slices, i)))
     return out
@@ -39,7 +39,7 @@ def sample_index(p):
 def main():
     t0 = time.time()
     specs = synth.config4(n_specimens=64, workers=min(8, os.cpu_count() or 1))
-    out = {"about": "FP64 PRISM EELS maps of two specimens of the batch workload (synth.config4, 64 "
+    out = {"about": "FP64 PRISM EELS maps of three specimens of the batch workload (synth.config4, 64 "
                     "specimens) at sampled probes; written by tests/golden/make_config4_samples.py "
                     "(oracle only)",
            "specimens": []}

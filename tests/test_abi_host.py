@@ -414,3 +414,21 @@ def test_raster_form_needs_an_aligned_probe_raster():
         assert eels.Plan(big, precision="bf16_split", max_workspace_bytes=int(290e9)).info()["raster_form"] == 64
     finally:
         eels.tune_set(eels.TUNE_RASTER, keep)
+
+
+def test_grid_sides_384_with_crop_windows_only():
+    """384 = 3 x 128 is a supported side for the sweeps (radix-3 passes) with cropped windows or
+    the real-space contraction; the band basis needs powers of two; other sides are refused."""
+    _lib()
+    rng = np.random.Generator(np.random.PCG64(1))
+    p = synth.random_lattice_specimen(rng, 384, 3, 2, nt_range=(3, 3), det_outer_mrad=20.0, n_scan=8)
+    assert eels.Plan(p).info()["k_pixels"] > 0
+    full = p.replace(window_A=0.0, interp_f=1)
+    with pytest.raises(eels.EelsError) as e:
+        eels.Plan(full)
+    assert e.value.status == 3
+    assert eels.Plan(full, real_space=True).info()["band_basis"] == 0
+    odd = synth.random_problem(3, n=48, L=8.0, nz=2)
+    with pytest.raises(eels.EelsError) as e:
+        eels.Plan(odd)
+    assert e.value.status == 3

@@ -102,8 +102,9 @@ GOLD4 = os.path.join(os.path.dirname(__file__), "golden", "config4_samples.json"
 
 def test_config4_batch_sampled_probes():
     """The 64-specimen batch workload in bench.py's fused configuration (FP16 split, four
-    stream branches, fused contraction, one captured graph, replayed): two of its specimens
-    (128^2 with f = 1 and 256^2 with f = 2) at sampled probes against the FP64 PRISM oracle
+    stream branches, fused contraction in persistent launches, one captured graph, replayed):
+    three of its specimens (128^2 with f = 1, 256^2 with f = 2 and 384^2 with f = 3, the last
+    through the radix-3 passes) at sampled probes against the FP64 PRISM oracle
     (tests/golden/config4_samples.json, written by make_config4_samples.py)."""
     import json
     eels = _gpu()
@@ -121,12 +122,13 @@ def test_config4_batch_sampled_probes():
     maps = bf.maps_host()
     del bf
     torch.cuda.empty_cache()
+    assert sorted(specs[s["index"]].nx for s in g["specimens"]) == [128, 256, 384]
     for s in g["specimens"]:
         got = maps[s["index"]][s["probe_index"]]
         ref = np.asarray(s["map"])
         _say("specimen", s["index"], "max rel err", float(np.max(np.abs(got - ref)) / np.max(ref)))
         assert np.all(np.isfinite(got)) and np.max(ref) > 0
-        assert np.max(np.abs(got - ref)) / np.max(ref) < 1e-3
+        assert maps_close(got, ref, 1e-3)
 
 
 def test_autotuner_caches_a_valid_setting(tmp_path, monkeypatch):

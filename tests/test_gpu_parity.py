@@ -120,9 +120,10 @@ def test_s2_rows_match_oracle():
         assert err < 2e-6 * (p.n_slices - j), (j, err)
 
 
-@pytest.mark.parametrize("n", [16, 32, 128, 256, 512, 1024])
+@pytest.mark.parametrize("n", [16, 32, 128, 256, 384, 512, 1024])
 def test_sweep_sizes(n):
-    """Every compiled transform length: one beam pair through two slices."""
+    """Every compiled transform length (384 = 3 x 128: the radix-24/8/2 passes): one beam pair
+    through two slices."""
     eels = _need_gpu()
     _say("sweep size", n)
     L = n * 0.1
@@ -130,7 +131,7 @@ def test_sweep_sizes(n):
     p = synth.random_problem(50 + n, n=n, L=L, nz=2, n_sites=1, n_trans=1, aperture_mrad=lam_mrad * 2.2 / L,
                              det_outer_mrad=lam_mrad * 3.2 / L, atoms_per_slice=3)
     st = make_setup(p)
-    plan = eels.Plan(p)
+    plan = eels.Plan(p, real_space=(n == 384))      # the band basis needs power-of-two sides
     V, H = eels.device_inputs(p)
     ws = plan.alloc_workspace()
     S1 = prism.forward_s1(p, st, [1])[1]
@@ -143,6 +144,27 @@ def test_sweep_sizes(n):
 
 
 # ------------------------------------------------------------------ whole maps
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16_split", 1e-3)])
+def test_radix3_grid_maps(prec, tol):
+    """A 384 x 384 specimen (f = 3, 4 A crop, order P) of the batch workload's kind: the map
+    through the radix-3 passes against the oracle; the full-cell band basis and the
+    conventional multislice refuse the size."""
+    eels = _need_gpu()
+    rng = np.random.Generator(np.random.PCG64(384))
+    p = synth.random_lattice_specimen(rng, 384, 3, 2, nt_range=(3, 3), det_outer_mrad=20.0, n_scan=8)
+    assert p.nx == 384 and p.interp_f == 3
+    ref = prism.prism_map(p)
+    assert np.max(ref) > 0
+    _say("384 grid", prec)
+    got = _map(eels, p, prec)
+    _say("  rel-L2", metrics.rel_l2(got, ref))
+    assert maps_close(got, ref, tol)
+    assert np.all(got[ref == 0] == 0)
+    with pytest.raises(eels.EelsError):
+        eels.Plan(p.replace(window_A=0.0, interp_f=1))
+
+
 
 def _map(eels, p, precision="fp32", order="auto", **kw):
     return eels.solve(p, precision=precision, order=order, **kw)
