@@ -119,8 +119,9 @@ def profile_sample(args):
                       "copy_bytes": 2 * a.numel() * 4}), flush=True)
 
 
-# sources whose change invalidates the committed counter figures (kernels and launch shapes)
-TRAFFIC_SOURCES = ["kernels_gemm.hip", "kernels_sweep.hip", "fft_reg.h", "fft_lds.h", "plan.cpp"]
+# sources whose change invalidates the committed counter figures of the contraction GEMMs (their
+# kernels, the shared device headers, and the planner that sets their shapes and batches)
+TRAFFIC_SOURCES = ["kernels_gemm.hip", "internal.h", "kernels.h", "plan.cpp"]
 
 
 def sources_digest():
