@@ -263,8 +263,9 @@ __device__ __forceinline__ void row_pass_body(float2* __restrict__ state, int nb
         constexpr float cap_scale = MODE == 2 ? (float)N : 1.0f;
         // Capture: the row is put in pixel order into its own exchange slots (free between the
         // two transforms; a row's T <= 64 threads are one wave, whose LDS operations complete
-        // in order), then each record's window row is written with one coalesced store per
-        // T pixels.
+        // in order), then the window rows it meets are written as one flat run of
+        // (record, pixel) pairs, T pairs per store, so that each store covers whole window rows
+        // back to back instead of one partly filled store per record.
         auto capture = [&]() {
             if constexpr (CAP) {
                 float2* crow = lds + s * L;
@@ -273,21 +274,30 @@ __device__ __forceinline__ void row_pass_body(float2* __restrict__ state, int nb
                 for (int m = 0; m < E; ++m) crow[t + T * m] = make_float2(v[m].x * cap_scale, v[m].y * cap_scale);
                 lds_sync_wave();
                 if (valid) {
-                    // the row's records are fetched T at a time, one per thread, and handed
-                    // round by shuffles within the row's threads (no load latency per record)
+                    // the row's records are fetched T at a time, one per thread; a pair's record
+                    // comes from its owner by a shuffle.  Every record of a plan has the same
+                    // width nw (the window's, or the whole row), so pair f belongs to record
+                    // f / nw, found exactly in FP32 (f < 64 nw, nw <= 1024).  The trip count is
+                    // the same for the row's T threads, so the shuffles always read active lanes.
                     const int r0 = cap_ptr[y], cnt = cap_ptr[y + 1] - r0;
+                    const int64_t bbase = beam * (int64_t)Kpad;
                     for (int c0 = 0; c0 < cnt; c0 += T) {
                         const int4 mine = c0 + t < cnt ? cap_rec[r0 + c0 + t] : make_int4(0, 0, 0, 0);
                         const int n = min(T, cnt - c0);
-                        for (int i = 0; i < n; ++i) {
-                            const int win_i = __shfl(mine.x, i, T), dy = __shfl(mine.y, i, T);
-                            const int x0 = __shfl(mine.z, i, T), nw = __shfl(mine.w, i, T);
-                            const int64_t dst = ((int64_t)win_i * win_beams + beam) * Kpad + (int64_t)dy * nw;
-                            for (int u = t; u < nw; u += T) {
-                                int px = x0 + u;
-                                if (px >= N) px -= N;
-                                store_c(win, dst + u, crow[px], sc);
-                            }
+                        const int nw = __shfl(mine.w, 0, T);
+                        const int pk = mine.z * 2048 + mine.y;    // x0 and dy (both < 2048)
+                        const float inv = 1.0f / (float)nw;
+                        const int tot = n * nw, iters = (tot + T - 1) / T;
+#pragma unroll 4
+                        for (int k = 0; k < iters; ++k) {
+                            const int f = min(t + T * k, tot - 1);
+                            const int i = (int)(((float)f + 0.5f) * inv);
+                            const int u = f - i * nw;
+                            const int win_i = __shfl(mine.x, i, T), xy = __shfl(pk, i, T);
+                            int px = (xy >> 11) + u;
+                            if (px >= N) px -= N;
+                            const int64_t dst = (int64_t)win_i * win_beams * Kpad + bbase + (int64_t)(xy & 2047) * nw + u;
+                            if (t + T * k < tot) store_c(win, dst, crow[px], sc);
                         }
                     }
                 }
