@@ -162,6 +162,7 @@ typedef struct {
     int gram_form;           /* 1 if the detector sum uses the Gram form (EELS_DETSUM_GRAM) */
     int window_gram_form;    /* 1 if order P uses the window-Gram detector sum (tuning key 6) */
     int raster_form;         /* DFT side M of its raster form (tuning key 7), 0 if not used  */
+    int n_checkpoints;       /* S_1 states kept for later slice groups (tuning key 8)      */
 } eels_plan_info;
 
 typedef struct eels_plan eels_plan;
@@ -432,6 +433,13 @@ eels_status eels_admission_destroy(eels_admission* a);
  *        (P_s K^2) by one K^2 N_1 product and FFTs; the same sums, regrouped exactly.  1
  *        (default) where it applies and needs fewer flops than the form chosen otherwise, 2
  *        wherever it applies, 0 never.
+ * key 8: S_1 checkpoints between slice groups.  When the S_1 windows of all ionised slices
+ *        do not fit the workspace budget, the slices form groups, and without checkpoints the
+ *        forward sweep reruns from slice 0 for each group.  With them the first group's sweep
+ *        saves the S_1 state at the entrance of every later group's lowest slice (N_1 x n_y x
+ *        live columns complex64 per saved state, taken from the windows' share of the budget),
+ *        and each later group resumes there.  The map is the same bit for bit.  1 (default)
+ *        where the sweeps then cost fewer passes, 2 whenever there are several groups, 0 never.
  * Returns EELS_ERR_INVALID_ARG for an unknown key or an out-of-range value. */
 eels_status eels_tune_set(int key, int value);
 int eels_tune_get(int key);

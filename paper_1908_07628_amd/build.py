@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libeels.so")
 
-SOURCES = ["plan.cpp", "server.cpp", "kernels_sweep.hip", "kernels_gemm.hip", "kernels_gram.hip", "kernels_conv.hip",
+SOURCES = ["plan.cpp", "server.cpp", "kernels_sweep.hip", "kernels_gemm.hip", "kernels_prod.hip", "kernels_gram.hip", "kernels_conv.hip",
            "kernels_misc.hip", "kernels_raster.hip", "api.hip"]
 ARCH = "gfx950"
 # The packed-fp32 feature is disabled for device code: ordinary float code only.

@@ -34,7 +34,7 @@ namespace eels {
 static thread_local std::string g_err;
 void set_error(const std::string& m) { g_err = m; }
 
-static std::atomic<int> g_tune[TUNE_COUNT] = {{2}, {2}, {0}, {1}, {1}, {1}, {1}, {1}};
+static std::atomic<int> g_tune[TUNE_COUNT] = {{2}, {2}, {0}, {1}, {1}, {1}, {1}, {1}, {1}};
 int tune_get(int key) { return (key >= 0 && key < TUNE_COUNT) ? g_tune[key].load() : 0; }
 
 // Diagnostic phase timing (eels_timing_enable / eels_timing_read).
@@ -87,6 +87,7 @@ struct Dev {
     float2 *img_exit, *img_masked, *img_part, *img_C;   // companion images
     double *img_G, *img_qpart;
     float2 *r_c0, *r_tw;                                  // raster form: c_k(R_0), M-point twiddles
+    float2* ckpt;                                         // S_1 checkpoint slots
 };
 
 Dev make_dev(const Plan& p, void* ws_) {
@@ -123,6 +124,7 @@ Dev make_dev(const Plan& p, void* ws_) {
     d.img_qpart = (double*)(d.ws + p.off_img_qpart);
     d.r_c0 = (float2*)(d.ws + p.off_r_c0);
     d.r_tw = (float2*)(d.ws + p.off_r_tw);
+    d.ckpt = (float2*)(d.ws + p.off_ckpt);
     return d;
 }
 
@@ -162,11 +164,20 @@ const float2* Pj(const Plan& p, const Dev& d, int j) { return d.P + (int64_t)j *
 // full real-space S_1(dbg_slice) into dbg_out.  With exit_cap (j_end = n_z - 1) the last
 // column pass also runs and captures the band coefficients of the exit wave
 // P_{nz-1} fft2(T_{nz-1} psi) of every beam into exit_cap [N_1][Kb pad].
+// A group with a checkpoint slot resumes from S_1 at the entrance of its lowest slice, which
+// the first group's sweep saved there (slices[j].ckpt_save) on its way up.
 void forward_sweep(const Plan& p, const Dev& d, int j_end, int group, int dbg_slice, float2* dbg_out,
                    hipStream_t st, float2* exit_cap = nullptr, bool last_col = false) {
     TimeScope ts(EELS_PHASE_SWEEP, st);
-    launch_init_forward(d.s1, d.b1, p, st);
-    for (int j = 0; j <= j_end; ++j) {
+    const int64_t state = (int64_t)p.N1 * p.ny * p.ldx;
+    const int64_t slot = (int64_t)ceil_div(8 * state, 256) * 256 / 8;   // a slot's complex elements
+    const int ck = group >= 0 && !dbg_out ? p.groups[group].ckpt : -1;
+    const int j_begin = ck >= 0 ? p.groups[group].j_lo : 0;
+    if (ck >= 0) launch_copy(d.s1, d.ckpt + ck * slot, state, st);
+    else launch_init_forward(d.s1, d.b1, p, st);
+    for (int j = j_begin; j <= j_end; ++j) {
+        if (group == 0 && !dbg_out && p.slices[j].ckpt_save >= 0)
+            launch_copy(d.ckpt + p.slices[j].ckpt_save * slot, d.s1, state, st);
         RowPassArgs a{d.s1, p.N1, p.ny, p.nlx, p.hlx, Tj(p, d, j), d.twx, nullptr, nullptr, d.w1, p.N1, p.Kpad, 0,
                       p.ldx};
         if (dbg_out && j == dbg_slice) {
@@ -316,8 +327,7 @@ void producers_after_gemm1(const Plan& p, const Dev& d, const float2* dH, const 
         launch_window_t_batched(d.mid2, d.w2, jobs, b.job_count, 0, p.Kpad, p.N2, p.K, p.N2p, p.precision, nullptr, st);
         if (p.raster) {
             launch_window_t_batched(d.mid2, d.w1, jobs, b.job_count, 1, p.Kpad, p.N1, p.K, p.N1pad, EELS_FP32,
-                                    d.blob + p.r_perm_off, st);
-            if (split) launch_to_sc_batched(d.mid2, d.w1, jobs, b.job_count, p.N1, p.K, p.Kpad, p.precision, st);
+                                    d.blob + p.r_perm_off, st, split ? p.precision : 0, p.Kpad);
         }
         return;
     }
@@ -583,6 +593,7 @@ eels_status eels_plan_info_get(const eels_plan* pl, eels_plan_info* info) {
     info->band_pixels = p.Kb;
     info->window_gram_form = p.wgram ? 1 : 0;
     info->raster_form = p.raster ? p.rM : 0;
+    info->n_checkpoints = p.n_ckpt;
     info->lambda_A = p.lam;
     info->sigma = p.sigma;
     info->gemm_flops = p.gemm_flops;
@@ -1014,6 +1025,7 @@ eels_status eels_tune_set(int key, int value) {
     if (key == TUNE_GEMM2_ROWS && (value < 0 || value > 1)) return EELS_ERR_INVALID_ARG;
     if (key == TUNE_WINDOW_GRAM && (value < 0 || value > 2)) return EELS_ERR_INVALID_ARG;
     if (key == TUNE_RASTER && (value < 0 || value > 2)) return EELS_ERR_INVALID_ARG;
+    if (key == TUNE_CHECKPOINT && (value < 0 || value > 2)) return EELS_ERR_INVALID_ARG;
     g_tune[key].store(value);
     return EELS_OK;
 }

@@ -44,7 +44,7 @@ static_assert(sizeof(GemmDesc) == 144, "GemmDesc layout");
 // Process-wide tuning knobs (set by eels_tune_set; read at launch time).
 enum TuneKey {
     TUNE_SC_STAGES = 0, TUNE_TILE_ORDER = 1, TUNE_SC_SCHED = 2, TUNE_GRAM_STACK = 3, TUNE_GEMM1_ROWS = 4,
-    TUNE_GEMM2_ROWS = 5, TUNE_WINDOW_GRAM = 6, TUNE_RASTER = 7, TUNE_COUNT = 8
+    TUNE_GEMM2_ROWS = 5, TUNE_WINDOW_GRAM = 6, TUNE_RASTER = 7, TUNE_CHECKPOINT = 8, TUNE_COUNT = 9
 };
 int tune_get(int key);
 
@@ -108,12 +108,14 @@ struct SliceInfo {
     int group = -1;
     int64_t cap1_ptr = -1, cap1_rec = -1;  // int offsets of the S_1 capture CSR (rows, records)
     int64_t cap2_ptr = -1, cap2_rec = -1;  // same for S_2
+    int ckpt_save = -1;                   // S_1 checkpoint slot saved at this slice's entrance
     std::vector<int> batches;
 };
 
 struct Group {
     int j_lo, j_hi;                       // ionised slices j_lo..j_hi (inclusive) are captured
     int n_windows;
+    int ckpt = -1;                        // checkpoint slot holding S_1 at the entrance of j_lo
 };
 
 struct Plan {
@@ -178,6 +180,7 @@ struct Plan {
     std::vector<GemmDesc> descs;
     std::vector<Job> jobs;
     int max_w1, max_w2;
+    int n_ckpt = 0;                             // S_1 checkpoints (slots of off_ckpt)
     int64_t mid_elems, mid2_elems, part_elems, scratch_elems;   // per batch maxima
     double gemm_flops = 0, sweep_bytes = 0, sweep_beam_slices = 0;
     float c_scale = 1.0f;                       // probe coefficient pre-scale (FP16 range)
@@ -194,7 +197,7 @@ struct Plan {
     // workspace layout (byte offsets)
     size_t off_blob, off_twx, off_twy, off_T, off_P, off_C, off_s1, off_s2, off_w1, off_w2,
         off_mid, off_mid2, off_scratch, off_part, off_gtot, off_qpart, off_img_exit, off_img_masked, off_img_part,
-        off_img_G, off_img_qpart, off_img_C, off_r_c0, off_r_tw, ws_bytes;
+        off_img_G, off_img_qpart, off_img_C, off_r_c0, off_r_tw, off_ckpt, ws_bytes;
 };
 
 eels_status build_plan(Plan& p, const eels_problem& prob);

@@ -111,9 +111,12 @@ void launch_window_t_sc(void* dst, const float2* src, int64_t wstride, int n_bea
 // s2t in `prec`; 1: the S_1 window s1w -> xt, rows gathered by perm; 2: the S_1 window s1w ->
 // s2t, the first product's operand before the S_2 transpose takes its place), the SC copy of the S_1
 // window (s1w -> s1sc) and G (m, h, nt -> g).  Source bases: the S_2 capture or the S_1
-// windows; destination base: mid2.
+// windows; destination base: mid2.  With copy_prec a split precision, the transpose of the S_1
+// window (which 1) also writes that window's SC copy [n_beams][copy_ld] (s1sc) from the same
+// reads, in place of a separate launch_to_sc_batched.
 void launch_window_t_batched(void* dst_base, const float2* src_base, const ProdJob* jobs, int n_jobs, int which,
-                             int64_t wstride, int n_beams, int K, int ldo, int prec, const int* perm, hipStream_t st);
+                             int64_t wstride, int n_beams, int K, int ldo, int prec, const int* perm, hipStream_t st,
+                             int copy_prec = 0, int copy_ld = 0);
 void launch_to_sc_batched(void* dst_base, const float2* src_base, const ProdJob* jobs, int n_jobs, int64_t rows, int K,
                           int ld, int prec, hipStream_t st);
 void launch_wgram_combine_batched(void* mid2, const float2* H, const ProdJob* jobs, int n_jobs, int K, int ldm, int ldg,

@@ -470,31 +470,86 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
         }
         if (!ion.empty()) p.groups.push_back(Group{ion.front(), ion.back(), maxw});
     } else {
-        int gi = -1;
-        size_t gbytes = 0;
-        int gwin = 0;
-        for (int idx = (int)ion.size() - 1; idx >= 0; --idx) {
-            int j = ion[idx];
-            size_t need = (size_t)slice_windows(j) * win1_bytes;
-            if (need > w1_cap) return fail(EELS_ERR_OOM, "one slice's S_1 windows exceed the budget");
-            if (gi < 0 || gbytes + need > w1_cap) {
-                p.groups.push_back(Group{j, j, 0});
-                gi = (int)p.groups.size() - 1;
-                gbytes = 0; gwin = 0;
+        // Groups from the top ionised slice down, each holding as many slices' S_1 windows as
+        // w1_cap allows; (j_hi, j_lo) per group.
+        auto form = [&](size_t cap, std::vector<std::pair<int, int>>& gr) -> bool {
+            gr.clear();
+            size_t gbytes = 0;
+            for (int idx = (int)ion.size() - 1; idx >= 0; --idx) {
+                const int j = ion[idx];
+                const size_t need = (size_t)slice_windows(j) * win1_bytes;
+                if (need > cap) return false;
+                if (gr.empty() || gbytes + need > cap) {
+                    gr.push_back({j, j});
+                    gbytes = 0;
+                }
+                gr.back().second = j;
+                gbytes += need;
             }
-            Group& g = p.groups[gi];
-            g.j_lo = j;
-            p.slices[j].group = gi;
-            int base = gwin;
-            if (p.full_window) {
-                for (int s : by_slice[j]) p.site_w1[s] = base;
-                gwin += 1;
-            } else {
-                for (size_t t = 0; t < by_slice[j].size(); ++t) p.site_w1[by_slice[j][t]] = base + (int)t;
-                gwin += (int)by_slice[j].size();
+            return true;
+        };
+        // Forward-sweep cost in beam-slice passes: without a checkpoint a group sweeps S_1 from
+        // slice 0 to its top slice; with one, a group after the first resumes from S_1 at the
+        // entrance of its lowest slice, saved while the first group's sweep passed it (two copies
+        // of the state, counted as one pass), which saves j_lo - 1 passes.
+        auto cost = [&](const std::vector<std::pair<int, int>>& g, const std::vector<char>& ck) {
+            double c = 0;
+            for (size_t k = 0; k < g.size(); ++k) c += ck[k] ? g[k].first - g[k].second + 2 : g[k].first + 1;
+            return c;
+        };
+        // n slots go to the n later groups whose lowest slice is highest (the largest savings)
+        auto assign = [&](const std::vector<std::pair<int, int>>& g, size_t n, std::vector<char>& ck) {
+            ck.assign(g.size(), 0);
+            std::vector<size_t> cand;
+            for (size_t k = 1; k < g.size(); ++k)
+                if (g[k].second > 1) cand.push_back(k);
+            std::sort(cand.begin(), cand.end(), [&](size_t a, size_t b) { return g[a].second > g[b].second; });
+            for (size_t i = 0; i < cand.size() && i < n; ++i) ck[cand[i]] = 1;
+        };
+        std::vector<std::pair<int, int>> gr, grk;
+        std::vector<char> ck, ckk;
+        if (!form(w1_cap, gr)) return fail(EELS_ERR_OOM, "one slice's S_1 windows exceed the budget");
+        ck.assign(gr.size(), 0);
+        // S_1 checkpoints (tuning key 8: 0 never, 1 where the sweeps cost less, 2 whenever there
+        // are several groups): n slots take n ckpt_bytes from the windows' share, so the groups
+        // are formed again for each n; the n of the lowest cost is taken
+        const int ck_knob = tune_get(TUNE_CHECKPOINT);
+        const size_t ckpt_bytes = A(c8 * (size_t)p.N1 * p.ny * p.ldx);
+        if (gr.size() > 1 && ck_knob != 0 && budget > 0 && !p.resident) {
+            double best = ck_knob == 2 ? 1e300 : cost(gr, ck);
+            std::vector<std::pair<int, int>> keep_gr = gr;
+            for (size_t n = 1; n <= ion.size() && n * ckpt_bytes < w1_cap; ++n) {
+                if (!form(w1_cap - n * ckpt_bytes, grk)) break;
+                assign(grk, n, ckk);
+                if (std::count(ckk.begin(), ckk.end(), 1) < (long)n) break;   // more slots than groups to use them
+                const double c = cost(grk, ckk);
+                if (c < best) { best = c; keep_gr = grk; ck = ckk; }
+            }
+            gr = keep_gr;
+            if (ck.size() != gr.size()) ck.assign(gr.size(), 0);
+        }
+        p.n_ckpt = 0;
+        for (size_t gi = 0; gi < gr.size(); ++gi) {
+            Group g{gr[gi].second, gr[gi].first, 0};
+            if (ck[gi]) {
+                g.ckpt = p.n_ckpt++;
+                p.slices[g.j_lo].ckpt_save = g.ckpt;
+            }
+            int gwin = 0;
+            for (int idx = (int)ion.size() - 1; idx >= 0; --idx) {
+                const int j = ion[idx];
+                if (j > g.j_hi || j < g.j_lo) continue;
+                p.slices[j].group = (int)gi;
+                if (p.full_window) {
+                    for (int s : by_slice[j]) p.site_w1[s] = gwin;
+                    gwin += 1;
+                } else {
+                    for (size_t t = 0; t < by_slice[j].size(); ++t) p.site_w1[by_slice[j][t]] = gwin + (int)t;
+                    gwin += (int)by_slice[j].size();
+                }
             }
             g.n_windows = gwin;
-            gbytes += need;
+            p.groups.push_back(g);
         }
     }
     if (p.resident && p.groups.size() > 1)
@@ -1005,7 +1060,8 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     double fwd = 0, rev = 0;
     if (!ion.empty()) {
         if (p.s1_inverse) fwd = (double)(2 * p.nz - ion.front()) * p.N1;   // to the exit and back
-        else for (auto& g : p.groups) fwd += (double)(g.j_hi + 1) * p.N1;
+        else
+            for (auto& g : p.groups) fwd += (double)(g.ckpt >= 0 ? g.j_hi - g.j_lo + 1 : g.j_hi + 1) * p.N1;
         rev = (double)(p.nz - ion.front()) * p.N2;
     }
     p.sweep_beam_slices = fwd + rev;
@@ -1039,6 +1095,7 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     p.off_img_C = take(img ? c8 * (size_t)p.P * p.N1pad : 16);
     p.off_r_c0 = take(p.raster ? c8 * (size_t)p.N1pad : 16);      // c_k(R_0)
     p.off_r_tw = take(p.raster ? c8 * (size_t)p.rM : 16);          // M-point twiddles
+    p.off_ckpt = take(p.n_ckpt > 0 ? (size_t)p.n_ckpt * A(c8 * (size_t)p.N1 * p.ny * p.ldx) : 16);
     p.off_blob = take(p.blob.size() * 4);
     p.ws_bytes = off;
     if (budget > 0 && p.ws_bytes > budget) return fail(EELS_ERR_OOM, "workspace exceeds the memory budget");

@@ -55,7 +55,8 @@ class PlanInfo(C.Structure):
                 ("order", C.c_int), ("band_basis", C.c_int), ("band_pixels", C.c_int),
                 ("lambda_A", C.c_double), ("sigma", C.c_double), ("gemm_flops", C.c_double),
                 ("sweep_bytes", C.c_double), ("sweep_beam_slices", C.c_double), ("workspace_bytes", C.c_size_t),
-                ("gram_form", C.c_int), ("window_gram_form", C.c_int), ("raster_form", C.c_int)]
+                ("gram_form", C.c_int), ("window_gram_form", C.c_int), ("raster_form", C.c_int),
+                ("n_checkpoints", C.c_int)]
 
 
 class RequestTiming(C.Structure):
@@ -467,6 +468,7 @@ TUNE_GEMM1_ROWS = 4
 TUNE_GEMM2_ROWS = 5
 TUNE_WINDOW_GRAM = 6
 TUNE_RASTER = 7
+TUNE_CHECKPOINT = 8
 
 
 def tune_set(key: int, value: int):

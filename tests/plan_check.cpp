@@ -37,7 +37,8 @@ namespace {
 
 int g_failures = 0;
 std::string g_case;
-long g_descs = 0, g_batches = 0, g_entries = 0, g_plans = 0, g_raster = 0, g_wgram = 0, g_gram = 0, g_groups = 0;
+long g_descs = 0, g_batches = 0, g_entries = 0, g_plans = 0, g_raster = 0, g_wgram = 0, g_gram = 0, g_groups = 0,
+     g_ckpt = 0;
 
 #define CHECK(cond, ...)                                               \
     do {                                                               \
@@ -63,10 +64,11 @@ struct Case {
     int s1_mode = EELS_S1_STORED, resident = 0, real_space = 0, n_images = 0;
     size_t budget = 0;
     bool tight_budget = false; // the budget is the smallest one the planner accepts (bisection)
+    double budget_frac = 0;    // > 0: the budget is this fraction of the unconstrained workspace
     double aperture = 20, det_in = 10, det_out = 40;
-    int knobs[TUNE_COUNT] = {0, 0, 0, 0, 0, 0, 1, 1};
+    int knobs[TUNE_COUNT] = {0, 0, 0, 0, 0, 0, 1, 1, 1};
     eels_status expect = EELS_OK;
-    int want_raster = -1, want_wgram = -1, want_gram = -1, want_groups_gt1 = -1;
+    int want_raster = -1, want_wgram = -1, want_gram = -1, want_groups_gt1 = -1, want_ckpt = -1;
 };
 
 enum Buf { B_NONE, B_W1, B_W2, B_C, B_MID, B_MID2, B_PART, B_IMG_MASKED, B_IMG_PART, B_H, B_COUNT };
@@ -243,7 +245,7 @@ void check_plan(const Plan& p, const Case& c, size_t budget) {
     const size_t offs[] = {p.off_twx, p.off_twy, p.off_T, p.off_P, p.off_s1, p.off_s2, p.off_w1, p.off_w2, p.off_C,
                            p.off_mid, p.off_mid2, p.off_scratch, p.off_part, p.off_gtot, p.off_qpart,
                            p.off_img_exit, p.off_img_masked, p.off_img_part, p.off_img_G, p.off_img_qpart,
-                           p.off_img_C, p.off_r_c0, p.off_r_tw, p.off_blob};
+                           p.off_img_C, p.off_r_c0, p.off_r_tw, p.off_ckpt, p.off_blob};
     const int n_offs = (int)(sizeof(offs) / sizeof(offs[0]));
     for (int i = 0; i < n_offs; ++i) {
         CHECK(offs[i] % 256 == 0, "workspace buffer %d at %zu not 256-byte aligned", i, offs[i]);
@@ -253,6 +255,26 @@ void check_plan(const Plan& p, const Case& c, size_t budget) {
     if (budget > 0) CHECK(p.ws_bytes <= budget, "workspace %zu over the budget %zu", p.ws_bytes, budget);
     CHECK(p.off_s1 + 8 * (size_t)p.N1 * p.ny * p.ldx <= p.off_s2, "S_1 state overlaps S_2");
     CHECK(p.ldx >= p.nlx && p.ldx % 16 == 0, "ldx %d for %d live columns", p.ldx, p.nlx);
+    // S_1 checkpoints: one slot per later group that resumes above slice 0, saved at that
+    // slice's entrance by the first group's sweep (which must pass it), all inside their region
+    {
+        const size_t slot = (8 * (size_t)p.N1 * p.ny * p.ldx + 255) / 256 * 256;
+        CHECK(p.n_ckpt == 0 || p.off_ckpt + (size_t)p.n_ckpt * slot <= p.off_blob, "checkpoints overlap the blob");
+        int seen = 0;
+        for (size_t g = 0; g < p.groups.size(); ++g) {
+            const Group& gr = p.groups[g];
+            CHECK(gr.j_lo <= gr.j_hi, "group %zu slices %d..%d", g, gr.j_lo, gr.j_hi);
+            if (g > 0) CHECK(gr.j_hi < p.groups[g - 1].j_lo, "group %zu not below group %zu", g, g - 1);
+            if (gr.ckpt < 0) continue;
+            ++seen;
+            CHECK(g > 0 && gr.j_lo > 0 && gr.ckpt < p.n_ckpt, "group %zu checkpoint %d", g, gr.ckpt);
+            CHECK(gr.j_lo <= p.groups[0].j_hi, "checkpoint of group %zu above the first group's sweep", g);
+            CHECK(p.slices[gr.j_lo].ckpt_save == gr.ckpt, "slice %d saves slot %d, group %zu reads %d", gr.j_lo,
+                  p.slices[gr.j_lo].ckpt_save, g, gr.ckpt);
+        }
+        CHECK(seen == p.n_ckpt, "%d groups read checkpoints, %d slots", seen, p.n_ckpt);
+        if (p.resident) CHECK(p.n_ckpt == 0, "resident plan with checkpoints");
+    }
 
     Sizes sz;
     sz.e[B_W1] = (int64_t)std::max(p.max_w1, 1) * p.N1 * p.Kpad;
@@ -320,6 +342,7 @@ void check_plan(const Plan& p, const Case& c, size_t budget) {
     const int nd = (int)p.descs.size();
     ++g_plans;
     g_raster += p.raster; g_wgram += p.wgram; g_gram += p.gram; g_groups += p.groups.size() > 1;
+    g_ckpt += p.n_ckpt > 0;
     for (size_t bi = 0; bi < p.batches.size(); ++bi) {
         const Batch& b = p.batches[bi];
         ++g_batches;
@@ -496,6 +519,7 @@ void check_plan(const Plan& p, const Case& c, size_t budget) {
     if (c.want_gram >= 0) CHECK((int)p.gram == c.want_gram, "Gram form %d, expected %d", (int)p.gram, c.want_gram);
     if (c.want_groups_gt1 >= 0)
         CHECK(((int)p.groups.size() > 1) == (c.want_groups_gt1 != 0), "%zu slice groups", p.groups.size());
+    if (c.want_ckpt >= 0) CHECK((p.n_ckpt > 0) == (c.want_ckpt != 0), "%d checkpoints", p.n_ckpt);
     (void)s_signature(p);
 }
 
@@ -569,6 +593,9 @@ void run_case(const Case& c) {
             else lo = mid;
         }
         q.max_workspace_bytes = hi;
+    } else if (c.budget_frac > 0) {
+        CHECK(build_plan(p, q) == EELS_OK, "unconstrained plan: %s", g_err_text.c_str());
+        q.max_workspace_bytes = (size_t)(c.budget_frac * (double)p.ws_bytes);
     }
     const eels_status s = build_plan(p, q);
     CHECK(s == c.expect, "status %d (%s), expected %d", (int)s, g_err_text.c_str(), (int)c.expect);
@@ -643,6 +670,14 @@ int main() {
         { Case c = mk(""); c.name = "groups-budget-" + ps; c.n = 256; c.window_A = 6.0; c.nz = 16; c.n_sites = 40;
           c.det_in = 5; c.det_out = 20;
           c.precision = prec; c.tight_budget = true; c.want_groups_gt1 = 1; cases.push_back(c); }
+        // slice groups resuming from S_1 checkpoints (forced), and under the default rule
+        for (double fr : {0.8, 0.6, 0.4}) {
+            Case c = mk(""); c.name = "groups-checkpoint-" + std::to_string((int)(100 * fr)) + "-" + ps; c.n = 256;
+            c.window_A = 6.0; c.nz = 16; c.n_sites = 800; c.det_in = 5; c.det_out = 20; c.precision = prec;
+            c.budget_frac = fr; c.knobs[TUNE_CHECKPOINT] = 2; c.want_groups_gt1 = 1; cases.push_back(c);
+            c.name = "groups-checkpoint-rule-" + std::to_string((int)(100 * fr)) + "-" + ps;
+            c.knobs[TUNE_CHECKPOINT] = 1; c.want_groups_gt1 = -1; cases.push_back(c);
+        }
         { Case c = mk(""); c.name = "resident-" + ps; c.n = 256; c.window_A = 6.0; c.nz = 8; c.n_sites = 12;
           c.precision = prec; c.resident = 1; cases.push_back(c); }
         { Case c = mk(""); c.name = "inverse-" + ps; c.n = 256; c.window_A = 6.0; c.nz = 8; c.n_sites = 10;
@@ -677,8 +712,8 @@ int main() {
         std::fprintf(stderr, "plan_check: %d failed checks over %zu cases\n", g_failures, cases.size());
         return 1;
     }
-    std::printf("plan_check: %zu cases ok (%ld plans: %ld raster, %ld window-Gram, %ld Gram, %ld with slice groups; "
-                "%ld batches, %ld launched descriptors, %ld reduction entries)\n",
-                cases.size(), g_plans, g_raster, g_wgram, g_gram, g_groups, g_batches, g_descs, g_entries);
+    std::printf("plan_check: %zu cases ok (%ld plans: %ld raster, %ld window-Gram, %ld Gram, %ld with slice groups, "
+                "%ld with S_1 checkpoints; %ld batches, %ld launched descriptors, %ld reduction entries)\n",
+                cases.size(), g_plans, g_raster, g_wgram, g_gram, g_groups, g_ckpt, g_batches, g_descs, g_entries);
     return 0;
 }

@@ -110,6 +110,32 @@ def test_budget_splits_slices_into_groups():
     assert small["n_groups"] >= 2 or small["n_batches"] > full["n_batches"]
 
 
+def test_checkpoints_cut_the_forward_sweeps_of_the_nanoparticle_map():
+    """On the full nanoparticle workload at the bench's budget the S_1 windows need several
+    slice groups; with S_1 checkpoints (tuning key 8 = 1, the default) the later groups resume
+    from saved states, which the planner takes only where the sweeps then cost fewer passes."""
+    _lib()
+    p = synth.config3()
+    budget = 296 * 10**9
+    keep = eels.tune_get(eels.TUNE_CHECKPOINT)
+    try:
+        eels.tune_set(eels.TUNE_CHECKPOINT, 0)
+        a = eels.Plan(p, precision="bf16_split", max_workspace_bytes=budget).info()
+        eels.tune_set(eels.TUNE_CHECKPOINT, 1)
+        b = eels.Plan(p, precision="bf16_split", max_workspace_bytes=budget).info()
+    finally:
+        eels.tune_set(eels.TUNE_CHECKPOINT, keep)
+    assert a["n_groups"] > 1 and a["n_checkpoints"] == 0
+    assert b["n_checkpoints"] >= 1 and b["workspace_bytes"] <= budget
+    assert b["sweep_beam_slices"] < a["sweep_beam_slices"]
+    # the transposed sweep runs once in both; the forward sweeps shrink
+    n1, n2, nz = a["n_beams_in"], a["n_beams_out"], p.n_slices
+    rev = n2 * (nz - int(np.min(p.site_slice)))
+    assert (b["sweep_beam_slices"] - rev) / n1 < (a["sweep_beam_slices"] - rev) / n1
+    with pytest.raises(eels.EelsError):
+        eels.tune_set(eels.TUNE_CHECKPOINT, 3)
+
+
 def test_contraction_order_choice():
     _lib()
     p = synth.config1()

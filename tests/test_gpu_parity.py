@@ -482,6 +482,51 @@ def test_memory_budget_grouping_same_map():
     assert metrics.rel_l2(a, prism.prism_map(p)) < 1e-4
 
 
+def _checkpoint_budget(eels, p, prec):
+    """A workspace budget at which the planner makes several slice groups without S_1
+    checkpoints and at least one checkpoint when forced (tuning key 8 = 2); host planning only."""
+    ws = eels.Plan(p, precision=prec).info()["workspace_bytes"]
+    keep = eels.tune_get(eels.TUNE_CHECKPOINT)
+    try:
+        for frac in np.arange(0.99, 0.3, -0.01):
+            b = int(ws * frac)
+            try:
+                eels.tune_set(eels.TUNE_CHECKPOINT, 0)
+                a = eels.Plan(p, precision=prec, max_workspace_bytes=b).info()
+                eels.tune_set(eels.TUNE_CHECKPOINT, 2)
+                c = eels.Plan(p, precision=prec, max_workspace_bytes=b).info()
+            except eels.EelsError:
+                continue
+            if a["n_groups"] > 1 and a["n_checkpoints"] == 0 and c["n_checkpoints"] > 0:
+                return b
+    finally:
+        eels.tune_set(eels.TUNE_CHECKPOINT, keep)
+    return None
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16_split", 1e-3)])
+def test_checkpointed_groups_same_map(prec, tol):
+    """Slice groups that resume the forward sweep from saved S_1 states give the map of groups
+    that sweep again from slice 0, bit for bit (the same kernels on the same states), and both
+    meet the oracle."""
+    eels = _need_gpu()
+    p = synth.random_problem(82, n=64, L=12.0, nz=6, atoms_per_slice=20, n_sites=100, window_A=4.0,
+                             aperture_mrad=18.0, det_outer_mrad=30.0)
+    b = _checkpoint_budget(eels, p, prec)
+    assert b is not None
+    keep = eels.tune_get(eels.TUNE_CHECKPOINT)
+    maps = {}
+    try:
+        for k in (0, 2):
+            eels.tune_set(eels.TUNE_CHECKPOINT, k)
+            _say("checkpoints", prec, "key 8 =", k, "budget", b)
+            maps[k] = _map(eels, p, prec, max_workspace_bytes=b)
+    finally:
+        eels.tune_set(eels.TUNE_CHECKPOINT, keep)
+    assert np.array_equal(maps[0], maps[2])
+    assert maps_close(maps[2], prism.prism_map(p), tol)
+
+
 def test_zero_transition_potential_gives_zero_map():
     eels = _need_gpu()
     p = synth.config1()

@@ -2,7 +2,7 @@
 
 tests/plan_check.cpp plans a matrix of problems (every precision and contraction form, crop windows
 and full cells, interp_f 1 .. 4, 384 and power-of-two grids, slice groups at the smallest accepted
-budget, resident S-matrices, the inverse multislice, companion images, invalid problems) and checks
+budget and with S_1 checkpoints, resident S-matrices, the inverse multislice, companion images, invalid problems) and checks
 every table of each plan against the buffers the device path binds it to.  Built with g++ (host
 code only, no device code), so it runs without a GPU.
 """
@@ -34,6 +34,6 @@ def test_planner_under_asan_and_ubsan(tmp_path):
     assert r.returncode == 0, (r.stdout + r.stderr)[-6000:]
     assert "cases ok" in r.stdout
     # the matrix reached every form it is meant to cover
-    for what in ("raster", "window-Gram", "Gram", "with slice groups"):
+    for what in ("raster", "window-Gram", "Gram", "with slice groups", "with S_1 checkpoints"):
         m = re.search(r"(\d+) %s[,;]" % re.escape(what), r.stdout)
         assert m and int(m.group(1)) > 0, (what, r.stdout)
