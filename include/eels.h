@@ -440,6 +440,10 @@ eels_status eels_admission_destroy(eels_admission* a);
  *        live columns complex64 per saved state, taken from the windows' share of the budget),
  *        and each later group resumes there.  The map is the same bit for bit.  1 (default)
  *        where the sweeps then cost fewer passes, 2 whenever there are several groups, 0 never.
+ * key 9: the window-Gram form in split precision forms G = M o sum_t conj(H_t) H_t^T in the
+ *        epilogue of the Gram GEMM (both triangles, in the SC format of the next product)
+ *        instead of writing M and combining it in a separate pass: 1 (default) where every
+ *        site has at most 32 transitions, 0 never.
  * Returns EELS_ERR_INVALID_ARG for an unknown key or an out-of-range value. */
 eels_status eels_tune_set(int key, int value);
 int eels_tune_get(int key);

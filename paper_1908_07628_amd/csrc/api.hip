@@ -34,7 +34,7 @@ namespace eels {
 static thread_local std::string g_err;
 void set_error(const std::string& m) { g_err = m; }
 
-static std::atomic<int> g_tune[TUNE_COUNT] = {{2}, {2}, {0}, {1}, {1}, {1}, {1}, {1}, {1}};
+static std::atomic<int> g_tune[TUNE_COUNT] = {{2}, {2}, {0}, {1}, {1}, {1}, {1}, {1}, {1}, {1}};
 int tune_get(int key) { return (key >= 0 && key < TUNE_COUNT) ? g_tune[key].load() : 0; }
 
 // Diagnostic phase timing (eels_timing_enable / eels_timing_read).
@@ -346,14 +346,17 @@ void wgram_contract(const Plan& p, const Dev& d, const float2* dH, const Batch& 
     const bool split = p.precision != EELS_FP32;
     {
         TimeScope ts(EELS_PHASE_GRAM, st);
-        if (split)
+        if (p.wg_fused)   // G straight from the Gram tiles' epilogue
+            launch_cgemm_sc(p.precision, 4, nst, d.descs + b.dm_begin, b.dm_count, b.dm_tiles, d.mid2, d.mid2, d.mid2,
+                            nullptr, d.blob, st, GEMM_BM, nullptr, dH, gscale);
+        else if (split)
             launch_cgemm_sc(p.precision, 2, nst, d.descs + b.dm_begin, b.dm_count, b.dm_tiles, d.mid2, d.mid2, nullptr,
                             (float*)d.mid2, d.blob, st, GEMM_BM);
         else
             launch_cgemm(EELS_FP32, 0, 2, d.descs + b.dm_begin, b.dm_count, b.dm_tiles, d.mid2, d.mid2, nullptr, nullptr,
                          (float*)d.mid2, d.blob, st);
     }
-    {
+    if (!p.wg_fused) {
         TimeScope ts(EELS_PHASE_PRODUCER, st);
         launch_wgram_combine_batched(d.mid2, dH, (const ProdJob*)(d.blob + b.p_jobs), b.job_count, p.K, p.Kpad, p.Kpad,
                                      gscale, p.precision, st);
@@ -1026,6 +1029,7 @@ eels_status eels_tune_set(int key, int value) {
     if (key == TUNE_WINDOW_GRAM && (value < 0 || value > 2)) return EELS_ERR_INVALID_ARG;
     if (key == TUNE_RASTER && (value < 0 || value > 2)) return EELS_ERR_INVALID_ARG;
     if (key == TUNE_CHECKPOINT && (value < 0 || value > 2)) return EELS_ERR_INVALID_ARG;
+    if (key == TUNE_WG_FUSED && (value < 0 || value > 1)) return EELS_ERR_INVALID_ARG;
     g_tune[key].store(value);
     return EELS_OK;
 }

@@ -44,7 +44,8 @@ static_assert(sizeof(GemmDesc) == 144, "GemmDesc layout");
 // Process-wide tuning knobs (set by eels_tune_set; read at launch time).
 enum TuneKey {
     TUNE_SC_STAGES = 0, TUNE_TILE_ORDER = 1, TUNE_SC_SCHED = 2, TUNE_GRAM_STACK = 3, TUNE_GEMM1_ROWS = 4,
-    TUNE_GEMM2_ROWS = 5, TUNE_WINDOW_GRAM = 6, TUNE_RASTER = 7, TUNE_CHECKPOINT = 8, TUNE_COUNT = 9
+    TUNE_GEMM2_ROWS = 5, TUNE_WINDOW_GRAM = 6, TUNE_RASTER = 7, TUNE_CHECKPOINT = 8, TUNE_WG_FUSED = 9,
+    TUNE_COUNT = 10
 };
 int tune_get(int key);
 
@@ -154,6 +155,8 @@ struct Plan {
                                                 // windows (N_2 rows) and Psi is the shared operand
     bool wgram = false;                         // order P, cropped windows: the detector sum as
                                                 // Psi^H (M o sum_t conj(H_t) H_t^T) Psi, M = S_2w^H S_2w
+    bool wg_fused = false;                      // split window-Gram form: G formed in the Gram GEMM's
+                                                // epilogue (every site at most 32 transitions)
     bool raster = false;                        // window-Gram form with Psi and Y = G Psi taken by M x M
                                                 // DFTs over the beam lattice (probes on an aligned raster)
     int rM = 0;                                 // DFT side M of the raster form

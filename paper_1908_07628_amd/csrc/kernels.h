@@ -91,7 +91,10 @@ void launch_cgemm(int precision, int kind, int epi, const GemmDesc* d_descs, int
 // Split-precision grouped GEMM on SC operands (see kernels_gemm.hip); B rows of column
 // block t start at b_off + t * ldh.  epi 0 stores C in SC form, epi 1 writes norm partials,
 // epi 2 the Gram tile conj(A) B^T as FP32 complex (as launch_cgemm), epi 3 stores C as
-// complex64.  The index list gathers B rows, or A rows with GD_IDX_A.
+// complex64, epi 4 the window-Gram G = gscale (conj(A) B^T) o sum_t conj(H_t) H_t^T in SC,
+// both triangles (the descriptor's h_off / ldh locate the site's transition potentials in H,
+// ld_part holds their count, at most 32).  The index list gathers B rows, or A rows with
+// GD_IDX_A.
 // rows: A rows of a tile, 128, or 256 (epi 0 and 3 only; the descriptors' tiles_m must
 // count 256-row tiles).
 // queue (may be null): a device int, zero before the launch; the grid is then the device's
@@ -99,7 +102,7 @@ void launch_cgemm(int precision, int kind, int epi, const GemmDesc* d_descs, int
 // (persistent launch, tiles in m-fastest order).
 void launch_cgemm_sc(int precision, int epi, int nstage, const GemmDesc* d_descs, int n_desc, int total_tiles,
                      const void* A, const void* B, void* C, float* part, const int* idx, hipStream_t st,
-                     int rows = 128, int* queue = nullptr);
+                     int rows = 128, int* queue = nullptr, const float2* H = nullptr, float gscale = 0.f);
 // S_1 or S_2 window [n_beams][K] (complex64, rows wstride apart) -> its transpose [K][ldo],
 // SC for the split precisions, complex64 for EELS_FP32 (beams n_beams .. ldo-1 zero; ldo a
 // multiple of 4, dst 32-byte aligned)

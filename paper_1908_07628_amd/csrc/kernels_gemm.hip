@@ -416,12 +416,13 @@ template <int PREC, int EPI, int NSTAGE, int UNITS, int SCHED, int WM>
 __global__ __launch_bounds__(128 * WM, (ScPipe<UNITS, NSTAGE, WM>::WAVES_PER_EU)) void k_cgemm_sc(
     const GemmDesc* __restrict__ descs, int n_desc, const uint32_t* __restrict__ Ab, const uint32_t* __restrict__ Bb,
     uint32_t* __restrict__ Cb, float* __restrict__ Pb, const int* __restrict__ ib, int order,
-    int* __restrict__ queue, int ntiles) {
+    int* __restrict__ queue, int ntiles, const float2* __restrict__ Hb, float gscale) {
     using SP = ScPipe<UNITS, NSTAGE, WM>;
     constexpr int STAGE = SP::STAGE, ROWB = SP::ROWB, QUADS = SP::QUADS, RPI = SP::RPI, NIA = SP::NIA, NIB = SP::NIB;
     constexpr int BMX = SP::BMX, NT = 128 * WM;
     constexpr int BKS = 4 * UNITS;  // complex per tile row
-    static_assert(WM == 2 || EPI != 2, "the 256-row tile has no Gram epilogue");
+    static_assert(WM == 2 || (EPI != 2 && EPI != 4), "the 256-row tile has no Gram epilogue");
+    static_assert(EPI != 4 || NSTAGE * STAGE >= 2 * 32 * 128 * 8, "the G epilogue stages H in the LDS ring");
     __shared__ __attribute__((aligned(1024))) char smem[NSTAGE * STAGE];
     __shared__ int next_tile;
 
@@ -429,7 +430,7 @@ __global__ __launch_bounds__(128 * WM, (ScPipe<UNITS, NSTAGE, WM>::WAVES_PER_EU)
   auto run_tile = [&](const int bid) {
     int tm, tn, t;
     const GemmDesc& d = descs[locate_tile<SP::G>(descs, n_desc, order, tm, tn, t, bid, ntiles)];
-    if constexpr (EPI == 2) {
+    if constexpr (EPI == 2 || EPI == 4) {
         if (tn < tm) return;   // Gram tiles: the lower triangle is the conjugate transpose
     }
     const int M = d.M, N = d.N_inner;
@@ -520,7 +521,7 @@ __global__ __launch_bounds__(128 * WM, (ScPipe<UNITS, NSTAGE, WM>::WAVES_PER_EU)
             // Re C = A'.(Br, -Bi), Im C = A'.(Bi, Br); with conj(A) (Gram tiles):
             // Re C = A'.(Br, Bi), Im C = A'.(Bi, -Br)
             u32x4 brh, brl, bih, bil;
-            if constexpr (EPI == 2) {
+            if constexpr (EPI == 2 || EPI == 4) {
                 brh = f.bh[bn]; brl = f.bl[bn];
                 bih = neg_imag(swap_halves(f.bh[bn])); bil = neg_imag(swap_halves(f.bl[bn]));
             } else {
@@ -585,6 +586,82 @@ __global__ __launch_bounds__(128 * WM, (ScPipe<UNITS, NSTAGE, WM>::WAVES_PER_EU)
                     int m = m0 + wm * 64 + bm * 32 + 8 * (v >> 2) + 4 * hl + (v & 3);
                     if (m < M) G[(int64_t)m * d.ldc_m + i] = make_float2(accR[bm][bn][v], accI[bm][bn][v]);
                 }
+        }
+    } else if constexpr (EPI == 4) {
+        // Window-Gram G tile: G = gscale M o S with M this Gram tile and S(m, i) =
+        // sum_t conj(H_t[m]) H_t[i] over the site's nt <= 32 transitions (h_off, ldh apart;
+        // ld_part holds nt), stored SC at [m][i], and off the diagonal also its conjugate
+        // transpose at [i][m] (G is Hermitian); columns N .. ldc_m - 1 of every row are zero.
+        __syncthreads();                 // every wave is past its last fragment read: the ring is free
+        const int nt = (int)d.ld_part;
+        const float2* Hs = Hb + d.h_off;
+        float2* hrow = (float2*)smem;    // [t][128]: H_t at the tile's rows m0 + x
+        float2* hcol = hrow + 32 * 128;  // [t][128]: H_t at its columns n0 + x
+        for (int w = tid; w < nt * 128; w += NT) {
+            const int tt = w >> 7, x = w & 127;
+            hrow[w] = m0 + x < M ? Hs[(int64_t)tt * d.ldh + m0 + x] : make_float2(0.f, 0.f);
+            hcol[w] = n0 + x < N ? Hs[(int64_t)tt * d.ldh + n0 + x] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+        const int64_t cbase = d.c_off, ldg = d.ldc_m;
+        if (n0 + BN > N && n0 < ldg) {
+            for (int e = tid; e < BMX * 16; e += NT) {
+                const int m = m0 + e / 16, i = N + e % 16;
+                if (m < M && i < ldg && i >= n0 && i < n0 + BN)
+                    sc_store(Cb, cbase + (int64_t)m * ldg + i, make_float2(0.f, 0.f), PREC);
+            }
+        }
+        const bool mirror = tn > tm;
+#pragma unroll
+        for (int bn = 0; bn < 2; ++bn) {
+            const int il = wn * 64 + bn * 32 + li, i = n0 + il;
+#pragma unroll
+            for (int bm = 0; bm < 2; ++bm) {
+                const int mb = wm * 64 + bm * 32 + 4 * hl;   // row of v = 0 in the tile
+                float sr[16], si[16];
+#pragma unroll
+                for (int v = 0; v < 16; ++v) { sr[v] = 0.f; si[v] = 0.f; }
+                for (int tt = 0; tt < nt; ++tt) {
+                    const float2 b = hcol[tt * 128 + il];
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) {
+                        const float2 a = hrow[tt * 128 + mb + 8 * (v >> 2) + (v & 3)];
+                        sr[v] += a.x * b.x + a.y * b.y;     // conj(a) b
+                        si[v] += a.x * b.y - a.y * b.x;
+                    }
+                }
+                float gr[16], gi[16];
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const float mr = accR[bm][bn][v], mi = accI[bm][bn][v];
+                    gr[v] = gscale * (mr * sr[v] - mi * si[v]);
+                    gi[v] = gscale * (mr * si[v] + mi * sr[v]);
+                }
+                if (i >= N) continue;
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int m = m0 + mb + 8 * (v >> 2) + (v & 3);
+                    if (m < M) sc_store(Cb, cbase + (int64_t)m * ldg + i, make_float2(gr[v], gi[v]), PREC);
+                }
+                if (!mirror) continue;
+#pragma unroll
+                for (int g4 = 0; g4 < 4; ++g4) {
+                    const int m4 = m0 + mb + 8 * g4;         // four consecutive columns of row i
+                    if (m4 >= ldg) continue;
+                    u32x4 hi, lo;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const bool in = m4 + e < M;
+                        uint32_t h, l;
+                        split2<PREC>(in ? gr[4 * g4 + e] : 0.f, in ? -gi[4 * g4 + e] : 0.f, h, l);
+                        hi[e] = h;
+                        lo[e] = l;
+                    }
+                    uint32_t* o = Cb + ((cbase + (int64_t)i * ldg + m4) >> 2) * 8;
+                    *(u32x4*)o = hi;
+                    *(u32x4*)(o + 4) = lo;
+                }
+            }
         }
     } else if constexpr (EPI == 0) {
         // store the product in SC form; the padding columns N .. ceil16(N)-1 get zeros so
@@ -726,7 +803,7 @@ static int resident_blocks(KERN kern, int block) {
 
 template <int PREC, int EPI>
 static void go_sc(int nstage, int rows, const GemmDesc* dd, int nd, int tiles, const uint32_t* A, const uint32_t* B,
-                  uint32_t* C, float* P, const int* idx, hipStream_t st, int* queue) {
+                  uint32_t* C, float* P, const int* idx, hipStream_t st, int* queue, const float2* H, float gscale) {
     // pipeline variants: 2 / 3 stages of 16-complex tiles, 4 / 5 stages of 8-complex tiles;
     // 256-row tiles (store epilogue) with two stages of 16-complex tiles.  With a work queue the
     // grid is the device's resident workgroups, which take the tiles from the queue.
@@ -735,13 +812,17 @@ static void go_sc(int nstage, int rows, const GemmDesc* dd, int nd, int tiles, c
     do {                                                                                                               \
         auto kern = k_cgemm_sc<PREC, EPI, NS, U, SC, 2>;                                                               \
         const int grid = queue ? std::min(tiles, resident_blocks(kern, 256)) : tiles;                                  \
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, st, dd, nd, A, B, C, P, idx, order, queue, tiles);         \
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, st, dd, nd, A, B, C, P, idx, order, queue, tiles, H,      \
+                           gscale);                                                                                    \
     } while (0)
-    if constexpr (EPI != 2) {
+    if constexpr (EPI != 2 && EPI != 4) {
         if (rows == 256) {
+            // two stages of 16-complex tiles (96 KB of LDS; three stages measured slower on the
+            // nanoparticle map's Z product, 2.87 against 2.82 s per map)
             auto kern = k_cgemm_sc<PREC, EPI, 2, 4, 0, 4>;
             const int grid = queue ? std::min(tiles, resident_blocks(kern, 512)) : tiles;
-            hipLaunchKernelGGL(kern, dim3(grid), dim3(512), 0, st, dd, nd, A, B, C, P, idx, order, queue, tiles);
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(512), 0, st, dd, nd, A, B, C, P, idx, order, queue, tiles, H,
+                               gscale);
             return;
         }
     }
@@ -762,21 +843,22 @@ static void go_sc(int nstage, int rows, const GemmDesc* dd, int nd, int tiles, c
 }
 
 void launch_cgemm_sc(int precision, int epi, int nstage, const GemmDesc* dd, int nd, int tiles, const void* A,
-                     const void* B, void* C, float* part, const int* idx, hipStream_t st, int rows, int* queue) {
+                     const void* B, void* C, float* part, const int* idx, hipStream_t st, int rows, int* queue,
+                     const float2* H, float gscale) {
     if (tiles <= 0 || nd <= 0) return;
     const uint32_t *a = (const uint32_t*)A, *b = (const uint32_t*)B;
     uint32_t* c = (uint32_t*)C;
-    if (precision == EELS_BF16_SPLIT) {
-        if (epi == 0) go_sc<EELS_BF16_SPLIT, 0>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st, queue);
-        else if (epi == 2) go_sc<EELS_BF16_SPLIT, 2>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st, queue);
-        else if (epi == 3) go_sc<EELS_BF16_SPLIT, 3>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st, queue);
-        else go_sc<EELS_BF16_SPLIT, 1>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st, queue);
-    } else {
-        if (epi == 0) go_sc<EELS_FP16_SPLIT, 0>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st, queue);
-        else if (epi == 2) go_sc<EELS_FP16_SPLIT, 2>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st, queue);
-        else if (epi == 3) go_sc<EELS_FP16_SPLIT, 3>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st, queue);
-        else go_sc<EELS_FP16_SPLIT, 1>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st, queue);
-    }
+#define SCE(P_)                                                                                                        \
+    do {                                                                                                               \
+        if (epi == 0) go_sc<P_, 0>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st, queue, H, gscale);             \
+        else if (epi == 2) go_sc<P_, 2>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st, queue, H, gscale);        \
+        else if (epi == 3) go_sc<P_, 3>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st, queue, H, gscale);        \
+        else if (epi == 4) go_sc<P_, 4>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st, queue, H, gscale);        \
+        else go_sc<P_, 1>(nstage, rows, dd, nd, tiles, a, b, c, part, idx, st, queue, H, gscale);                      \
+    } while (0)
+    if (precision == EELS_BF16_SPLIT) SCE(EELS_BF16_SPLIT);
+    else SCE(EELS_FP16_SPLIT);
+#undef SCE
 }
 
 

@@ -41,9 +41,13 @@ __global__ __launch_bounds__(256) void k_raster_dot(const RasterJob* __restrict_
                                                     float oscale, const float2* __restrict__ tw,
                                                     float* __restrict__ part) {
     static_assert(M == 64, "256 threads hold a 64 x 64 grid");
-    constexpr int LD = M + 1;
     // one grid per transform; row s is both the transpose slot of row s and the exchange space
-    // of the 64-point sequence that thread group s owns (rows first, then column s)
+    // of the 64-point sequence that thread group s owns (rows first, then column s).  Rows are
+    // PadLen<64> = 68 slots apart and the exchanges keep element i at i + i / 16 of its row:
+    // a quarter-wave (4 rows x 4 threads) then meets 16 distinct 8-byte bank pairs in every
+    // exchange and transpose access (with rows 65 slots apart and no padding, 4 lanes met in
+    // one bank pair).
+    constexpr int LD = PadLen<M>::value;
     __shared__ float2 la[M * LD], lb[M * LD];
     const RasterJob jb = jobs[blockIdx.y];
     const int r0 = blockIdx.x * chunk, r1 = min(K, r0 + chunk);
@@ -65,8 +69,8 @@ __global__ __launch_bounds__(256) void k_raster_dot(const RasterJob* __restrict_
         load_grids(a, b, xt + (int64_t)r * ld, z + (int64_t)r * ld, q, w);
         // rows: the sequence of row s lies in the 4 lanes 4 s .. 4 s + 3 of one wavefront, so its
         // exchange through row s of the grid needs wave-level ordering only
-        fft_reg<M, -1, false, true>(a, la, s * LD, 1, t, tw);
-        fft_reg<M, -1, false, true>(b, lb, s * LD, 1, t, tw);
+        fft_reg<M, -1, true, true>(a, la, s * LD, 1, t, tw);
+        fft_reg<M, -1, true, true>(b, lb, s * LD, 1, t, tw);
         lds_sync_wave();
 #pragma unroll
         for (int m = 0; m < 16; ++m) {
@@ -80,8 +84,8 @@ __global__ __launch_bounds__(256) void k_raster_dot(const RasterJob* __restrict_
             b[m] = lb[(t + 4 * m) * LD + s];
         }
         __syncthreads();                 // every column read: the rows are free again
-        fft_reg<M, -1, false, true>(a, la, s * LD, 1, t, tw);     // column s
-        fft_reg<M, -1, false, true>(b, lb, s * LD, 1, t, tw);
+        fft_reg<M, -1, true, true>(a, la, s * LD, 1, t, tw);      // column s
+        fft_reg<M, -1, true, true>(b, lb, s * LD, 1, t, tw);
 #pragma unroll
         for (int m = 0; m < 16; ++m) acc[m] = fmaf(a[m].x, b[m].x, fmaf(a[m].y, b[m].y, acc[m]));
     }

@@ -335,6 +335,13 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
             }
         }
     }
+    // split window-Gram form: G from the Gram GEMM's epilogue (tuning key 9: 1 where every site
+    // has at most 32 transitions, 0 never: the Gram tiles M and a separate combine kernel)
+    {
+        int max_nt = 0;
+        for (const auto& st : p.sites) max_nt = std::max(max_nt, st.n_trans);
+        p.wg_fused = split && p.wgram && max_nt <= 32 && tune_get(TUNE_WG_FUSED) != 0;
+    }
     p.w2_sc = (split && !p.hs2) ? p.precision : 0;
     p.mid2_sc = split ? p.precision : 0;
 
@@ -869,7 +876,9 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
         bt.d2_tiles = tiles;
         bt.d2_rows = p.gram ? GEMM_BM : rows2;
         if (p.wgram) {
-            // M_s[r][r'] = sum_q conj(S2w[q][r]) S2w[q][r']  (upper 128-tiles, FP32 complex)
+            // M_s[r][r'] = sum_q conj(S2w[q][r]) S2w[q][r']  (upper 128-tiles, FP32 complex), or in
+            // split precision with the G epilogue, G_s = gscale M_s o sum_t conj(H_t) H_t^T in SC
+            // (both triangles; the H of the site at h_off, K apart, ld_part transitions)
             bt.dm_begin = (int)p.descs.size();
             int tl = 0;
             for (size_t si = 0; si < pb.sites.size(); ++si) {
@@ -878,6 +887,9 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
                 d.a_off = jb.s2t_off; d.lda = p.N2p; d.b_off = jb.s2t_off; d.ldb = p.N2p;
                 d.h_off = -1; d.idx_off = -1;
                 d.p_off = jb.m_off; d.ldc_m = p.Kpad; d.ldc_t = 0;
+                if (p.wg_fused) {
+                    d.c_off = jb.g_off; d.h_off = jb.h_off; d.ldh = p.K; d.ld_part = jb.nt;
+                }
                 d.M = p.K; d.N_inner = p.K; d.n_t = 1; d.K = p.N2;
                 d.tiles_m = (int)ceil_div(p.K, GEMM_BM);
                 d.tiles_n = (int)ceil_div(p.K, GEMM_BN);

@@ -469,6 +469,7 @@ TUNE_GEMM2_ROWS = 5
 TUNE_WINDOW_GRAM = 6
 TUNE_RASTER = 7
 TUNE_CHECKPOINT = 8
+TUNE_WG_FUSED = 9
 
 
 def tune_set(key: int, value: int):

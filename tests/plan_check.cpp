@@ -66,7 +66,7 @@ struct Case {
     bool tight_budget = false; // the budget is the smallest one the planner accepts (bisection)
     double budget_frac = 0;    // > 0: the budget is this fraction of the unconstrained workspace
     double aperture = 20, det_in = 10, det_out = 40;
-    int knobs[TUNE_COUNT] = {0, 0, 0, 0, 0, 0, 1, 1, 1};
+    int knobs[TUNE_COUNT] = {0, 0, 0, 0, 0, 0, 1, 1, 1, 1};
     eels_status expect = EELS_OK;
     int want_raster = -1, want_wgram = -1, want_gram = -1, want_groups_gt1 = -1, want_ckpt = -1;
 };
@@ -84,7 +84,7 @@ struct Role {
     Buf a = B_NONE, b = B_NONE, h = B_NONE, c = B_NONE, p = B_NONE;
     bool split = false;
     int kind = 0;
-    int epi = 0;   // 0/3 store C, 1 norm partials (floats), 2 Gram tiles (float2 into p)
+    int epi = 0;   // 0/3 store C, 1 norm partials (floats), 2 Gram tiles (float2 into p), 4 G (SC into c)
 };
 
 int64_t blob_ints(const Plan& p) { return (int64_t)p.blob.size(); }
@@ -153,6 +153,15 @@ void check_desc(const Plan& p, int di, const Role& r, const Sizes& sz) {
         // float2 Gram tiles: for the part buffer (floats) count in floats
         const int64_t end = d.p_off + t1 * d.ldc_t + (int64_t)(d.M - 1) * d.ldc_m + d.N_inner;
         check_extent("Gram tiles", di, r.p, r.p == B_PART ? 2 * end : end, sz);
+    } else if (r.epi == 4) {
+        // G in SC, both triangles of the square: every row N .. ldc_m - 1 padded; H of ld_part
+        // transitions, ldh apart
+        CHECK(d.M == d.N_inner && d.ldc_m >= round_up(d.N_inner, 16) && d.ldc_m % 4 == 0,
+              "descriptor %d: G tile shape", di);
+        check_extent("G", di, r.c, d.c_off + (int64_t)(d.M - 1) * d.ldc_m + d.ldc_m, sz);
+        CHECK(d.ld_part >= 1 && d.ld_part <= 32 && d.ldh >= d.M, "descriptor %d: %lld transitions", di,
+              (long long)d.ld_part);
+        check_extent("H", di, r.h, d.h_off + (d.ld_part - 1) * d.ldh + d.M, sz);
     }
 }
 
@@ -191,6 +200,7 @@ Role role_dm(const Plan& p) {
     r.split = p.precision != EELS_FP32;
     r.a = r.b = r.p = B_MID2;
     r.epi = 2;
+    if (p.wg_fused) { r.epi = 4; r.c = B_MID2; r.h = B_H; }
     return r;
 }
 

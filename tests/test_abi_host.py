@@ -134,6 +134,8 @@ def test_checkpoints_cut_the_forward_sweeps_of_the_nanoparticle_map():
     assert (b["sweep_beam_slices"] - rev) / n1 < (a["sweep_beam_slices"] - rev) / n1
     with pytest.raises(eels.EelsError):
         eels.tune_set(eels.TUNE_CHECKPOINT, 3)
+    with pytest.raises(eels.EelsError):
+        eels.tune_set(eels.TUNE_WG_FUSED, 2)
 
 
 def test_contraction_order_choice():
