@@ -7,9 +7,10 @@
 // stage's outputs j + r N / R (j = t + b T) are again t + T (b + r E / R).  Middle
 // stages exchange through lds[base + i * es] with a barrier on each side, so every
 // thread of the block must call the transform the same number of times.
-// PAD (es = 1 only): element i sits at lds[base + i + i / 16].  A contiguous sequence's first
-// exchange writes elements 16 t + r from thread t; unpadded, all lanes of a wave would hit one
-// LDS bank, padded they spread over all banks.  The sequence then needs N + N / 16 slots.
+// PAD: element i sits at lds[base + (i + i / 16) * es].  A sequence's first exchange writes
+// elements 16 t + r from thread t; unpadded, the lanes of neighbouring threads t (contiguous
+// sequences, or interleaved ones es apart) meet in the same LDS banks, padded they spread over
+// the banks.  The sequence then needs N + N / 16 slots (es apart).
 // DIR = -1: forward exp(-2 pi i n k / N); DIR = +1: unnormalised inverse.
 // WAVE: every sequence's T <= 64 threads lie in one wavefront (contiguous sequences of a
 // row pass), so the exchanges need only wave-level ordering: a wavefront's LDS operations
@@ -115,7 +116,7 @@ template <int N, int E, int DIR, int Ns, bool PAD, bool WAVE>
 __device__ __forceinline__ void fft_reg_stages(float2 (&v)[E], float2* lds, int base, int es, int t,
                                                const float2* __restrict__ tw) {
     static_assert(!WAVE || N / E <= 64, "wave-local exchange needs the sequence in one wavefront");
-    auto at = [&](int i) -> float2& { return PAD ? lds[base + i + (i >> 4)] : lds[base + i * es]; };
+    auto at = [&](int i) -> float2& { return PAD ? lds[base + (i + (i >> 4)) * es] : lds[base + i * es]; };
     constexpr int T = N / E;
     constexpr int R = (Ns == 1) ? E : RegRadix<N, Ns, E>::R;
     constexpr int NB = E / R;

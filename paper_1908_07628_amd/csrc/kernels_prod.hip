@@ -39,7 +39,11 @@ __global__ __launch_bounds__(256) void k_window_t_sc(uint32_t* __restrict__ dst,
                                                      int64_t wstride, int n_beams, int K, int ldo,
                                                      const int* __restrict__ perm, const ProdJob* __restrict__ jobs,
                                                      int which, int copy_prec, int copy_ld) {
-    __shared__ float2 tile[64][65];
+    // The tile holds beam row r, pixel c at tile[r][c ^ ((r >> 2) & 15)].  The swizzle puts the
+    // 16 rows 4g + e (g = 0 .. 15) that a quarter-wave reads for one pixel in 16 distinct 8-byte
+    // bank pairs (a padded 65-slot row left 4 of them in each), keeps every 4-pixel group of a
+    // row in one aligned 32-byte block, and permutes a row's pixels (conflict-free row writes).
+    __shared__ __attribute__((aligned(16))) float2 tile[64][64];
     uint32_t* cp = nullptr;
     if (jobs) {   // batched: job blockIdx.z's window (which 0: S_2 -> s2t, 1: S_1 -> xt, 2: S_1 -> s2t)
         const ProdJob& j = jobs[blockIdx.z];
@@ -52,24 +56,25 @@ __global__ __launch_bounds__(256) void k_window_t_sc(uint32_t* __restrict__ dst,
     for (int r = ty; r < 64; r += 4) {
         const int b = b0 + r, px = p0 + tx;
         const int bs = (perm && b < n_beams) ? perm[b] : b;
-        tile[r][tx] = (b < n_beams && px < K) ? src[(int64_t)bs * wstride + px] : make_float2(0.f, 0.f);
+        tile[r][tx ^ ((r >> 2) & 15)] = (b < n_beams && px < K) ? src[(int64_t)bs * wstride + px] : make_float2(0.f, 0.f);
     }
     __syncthreads();
     for (int w = threadIdx.x; w < 64 * 16; w += 256) {
         const int px = w >> 4, g = w & 15;
         const int pix = p0 + px, b = b0 + 4 * g;
         if (pix >= K || b >= ldo) continue;
+        const int pc = px ^ g;            // rows 4 g .. 4 g + 3 all swizzle by g
         if constexpr (PREC == EELS_FP32) {
             float4* o = (float4*)((float2*)dst + (int64_t)pix * ldo + b);
-            const float2 v0 = tile[4 * g][px], v1 = tile[4 * g + 1][px], v2 = tile[4 * g + 2][px],
-                         v3 = tile[4 * g + 3][px];
+            const float2 v0 = tile[4 * g][pc], v1 = tile[4 * g + 1][pc], v2 = tile[4 * g + 2][pc],
+                         v3 = tile[4 * g + 3][pc];
             o[0] = make_float4(v0.x, v0.y, v1.x, v1.y);
             o[1] = make_float4(v2.x, v2.y, v3.x, v3.y);
         } else {
             u32x4 hi, lo;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const float2 v = tile[4 * g + e][px];
+                const float2 v = tile[4 * g + e][pc];
                 uint32_t h, l;
                 split2<PREC>(v.x, v.y, h, l);
                 hi[e] = h;
@@ -82,19 +87,27 @@ __global__ __launch_bounds__(256) void k_window_t_sc(uint32_t* __restrict__ dst,
     }
     if (cp) {
         // the same tile untransposed into the window's SC copy [beam][copy_ld] (the raster form's Z
-        // GEMM operand): slot b's row goes back to beam perm[b], pixels K .. copy_ld - 1 are zero
+        // GEMM operand): slot b's row goes back to beam perm[b], pixels K .. copy_ld - 1 are zero.
+        // Pixels 4g .. 4g + 3 of row r sit in the aligned block 4 (g ^ (z >> 2)), z = (r >> 2) & 15,
+        // pixel 4g + e at position e ^ (z & 3); a quarter-wave reads one row's 16 blocks.
         for (int w = threadIdx.x; w < 64 * 16; w += 256) {
             const int r = w >> 4, g = w & 15;
             const int b = b0 + r, px = p0 + 4 * g;
             if (b >= n_beams || px >= copy_ld) continue;
             const int bs = perm ? perm[b] : b;
+            const int z = (r >> 2) & 15;
+            const float4* blk = (const float4*)&tile[r][4 * (g ^ (z >> 2))];
+            const float4 q0 = blk[0], q1 = blk[1];
+            float2 v[4] = {make_float2(q0.x, q0.y), make_float2(q0.z, q0.w), make_float2(q1.x, q1.y),
+                           make_float2(q1.z, q1.w)};
+            if (z & 1) { const float2 a = v[0]; v[0] = v[1]; v[1] = a; const float2 c = v[2]; v[2] = v[3]; v[3] = c; }
+            if (z & 2) { const float2 a = v[0]; v[0] = v[2]; v[2] = a; const float2 c = v[1]; v[1] = v[3]; v[3] = c; }
             u32x4 hi, lo;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const float2 v = tile[r][4 * g + e];
                 uint32_t h, l;
-                if (copy_prec == EELS_BF16_SPLIT) split2<EELS_BF16_SPLIT>(v.x, v.y, h, l);
-                else split2<EELS_FP16_SPLIT>(v.x, v.y, h, l);
+                if (copy_prec == EELS_BF16_SPLIT) split2<EELS_BF16_SPLIT>(v[e].x, v[e].y, h, l);
+                else split2<EELS_FP16_SPLIT>(v[e].x, v[e].y, h, l);
                 hi[e] = h;
                 lo[e] = l;
             }

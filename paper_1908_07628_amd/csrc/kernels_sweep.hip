@@ -401,7 +401,7 @@ __device__ __forceinline__ void col_pass_body(float2* __restrict__ state, int nb
         float2* plane = state + beam * (int64_t)N * ldx;
         if (it + G < items) load(it + G);
         constexpr int S1 = MODE == 1 ? +1 : -1;   // first transform's sign (-1: FFT_y)
-        fft_reg<N, S1>(v, lds, col, CW, t, tw);
+        fft_reg<N, S1, true>(v, lds, col, CW, t, tw);
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             const int ys = signed_index(t + T * m, N);
@@ -420,7 +420,7 @@ __device__ __forceinline__ void col_pass_body(float2* __restrict__ state, int nb
                 if (r >= 0) store_c(bcap, dst + r, v[m], sc);
             }
         }
-        fft_reg<N, -S1>(v, lds, col, CW, t, tw);
+        fft_reg<N, -S1, true>(v, lds, col, CW, t, tw);
         if (live) {
 #pragma unroll
             for (int m = 0; m < E; ++m) plane[(int64_t)(t + T * m) * ldx + pc] = v[m];
@@ -432,7 +432,7 @@ template <int N, int MODE>
 __global__ __launch_bounds__(ColCfg<N>::NT) __attribute__((amdgpu_waves_per_eu(RegCfg<N>::E > 16 ? 1 : 2))) void k_col_pass(
     float2* __restrict__ state, int nbeam, int nlx, int ldx, const float2* __restrict__ Pj,
     const float2* __restrict__ tw, const int* __restrict__ band_h) {
-    __shared__ float2 lds[N * ColCfg<N>::CW];
+    __shared__ float2 lds[PadLen<N>::value * ColCfg<N>::CW];
     col_pass_body<N, MODE, false>(state, nbeam, nlx, ldx, Pj, tw, band_h, nullptr, nullptr, 0, 0, lds);
 }
 
@@ -443,7 +443,7 @@ __global__ __launch_bounds__(ColCfg<N>::NT) void k_col_pass_cap(float2* __restri
                                                                 const int* __restrict__ band_h,
                                                                 const int* __restrict__ band_off,
                                                                 void* __restrict__ bcap, int64_t bstride, int sc) {
-    __shared__ float2 lds[N * ColCfg<N>::CW];
+    __shared__ float2 lds[PadLen<N>::value * ColCfg<N>::CW];
     col_pass_body<N, MODE, true>(state, nbeam, nlx, ldx, Pj, tw, band_h, band_off, bcap, bstride, sc, lds);
 }
 
@@ -537,7 +537,7 @@ __global__ __launch_bounds__(ColCfg<N>::NT) __attribute__((amdgpu_waves_per_eu(2
                                                              const float2* __restrict__ tw, int sc) {
     using C = ColCfg<N>;
     constexpr int CW = C::CW, T = C::T, E = C::E, NT = C::NT;
-    __shared__ float2 lds[N * CW];
+    __shared__ float2 lds[PadLen<N>::value * CW];
     const int tid = threadIdx.x;
     const int strips = (ldx + CW - 1) / CW;
     const int64_t items = n_planes * strips;
@@ -561,7 +561,7 @@ __global__ __launch_bounds__(ColCfg<N>::NT) __attribute__((amdgpu_waves_per_eu(2
         const int c = logical_of_phys(pc, nlx, ldx);
         const bool live = c >= 0;
         if (it + gridDim.x < items) load(it + gridDim.x);
-        fft_reg<N, -1>(v, lds, col, CW, t, tw);
+        fft_reg<N, -1, true>(v, lds, col, CW, t, tw);
         if (live) {
             const int h = band_h[c];
             const int64_t o = plane * dstride + band_off[c];
