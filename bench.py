@@ -120,9 +120,9 @@ def profile_sample(args):
 
 
 # sources whose change invalidates the committed counter figures of the contraction GEMMs (their
-# kernels, the SC operand format, the shared device headers, and the planner that sets their shapes
-# and batches)
-TRAFFIC_SOURCES = ["kernels_gemm.hip", "sc_format.h", "internal.h", "kernels.h", "plan.cpp"]
+# kernels, the SC operand format, the descriptor and plan structures, and the planner that sets
+# their shapes and batches)
+TRAFFIC_SOURCES = ["kernels_gemm.hip", "sc_format.h", "internal.h", "plan.cpp"]
 
 
 def sources_digest():
