@@ -444,6 +444,9 @@ eels_status eels_admission_destroy(eels_admission* a);
  *        epilogue of the Gram GEMM (both triangles, in the SC format of the next product)
  *        instead of writing M and combining it in a separate pass: 1 (default) where every
  *        site has at most 32 transitions, 0 never.
+ * key 10: tiles of that Gram GEMM with the G epilogue: 0 (default) 128 x 128 tiles of 4
+ *        waves, 1 256 x 128 tiles of 8 waves.  Tiles with no element on or above the diagonal
+ *        are skipped either way, and the maps are the same.
  * Returns EELS_ERR_INVALID_ARG for an unknown key or an out-of-range value. */
 eels_status eels_tune_set(int key, int value);
 int eels_tune_get(int key);

@@ -34,7 +34,7 @@ namespace eels {
 static thread_local std::string g_err;
 void set_error(const std::string& m) { g_err = m; }
 
-static std::atomic<int> g_tune[TUNE_COUNT] = {{2}, {2}, {0}, {1}, {1}, {1}, {1}, {1}, {1}, {1}};
+static std::atomic<int> g_tune[TUNE_COUNT] = {{2}, {2}, {0}, {1}, {1}, {1}, {1}, {1}, {1}, {1}, {0}};
 int tune_get(int key) { return (key >= 0 && key < TUNE_COUNT) ? g_tune[key].load() : 0; }
 
 // Diagnostic phase timing (eels_timing_enable / eels_timing_read).
@@ -326,8 +326,10 @@ void producers_after_gemm1(const Plan& p, const Dev& d, const float2* dH, const 
         const ProdJob* jobs = (const ProdJob*)(d.blob + b.p_jobs);
         launch_window_t_batched(d.mid2, d.w2, jobs, b.job_count, 0, p.Kpad, p.N2, p.K, p.N2p, p.precision, nullptr, st);
         if (p.raster) {
+            // split precision: c_k(R_0) folded into Xt and into the Z GEMM's operand
             launch_window_t_batched(d.mid2, d.w1, jobs, b.job_count, 1, p.Kpad, p.N1, p.K, p.N1pad, EELS_FP32,
-                                    d.blob + p.r_perm_off, st, split ? p.precision : 0, p.Kpad);
+                                    d.blob + p.r_perm_off, st, split ? p.precision : 0, p.Kpad,
+                                    split ? d.r_c0 : nullptr);
         }
         return;
     }
@@ -348,7 +350,7 @@ void wgram_contract(const Plan& p, const Dev& d, const float2* dH, const Batch& 
         TimeScope ts(EELS_PHASE_GRAM, st);
         if (p.wg_fused)   // G straight from the Gram tiles' epilogue
             launch_cgemm_sc(p.precision, 4, nst, d.descs + b.dm_begin, b.dm_count, b.dm_tiles, d.mid2, d.mid2, d.mid2,
-                            nullptr, d.blob, st, GEMM_BM, nullptr, dH, gscale);
+                            nullptr, d.blob, st, b.dm_rows, nullptr, dH, gscale);
         else if (split)
             launch_cgemm_sc(p.precision, 2, nst, d.descs + b.dm_begin, b.dm_count, b.dm_tiles, d.mid2, d.mid2, nullptr,
                             (float*)d.mid2, d.blob, st, GEMM_BM);
@@ -374,7 +376,8 @@ void wgram_contract(const Plan& p, const Dev& d, const float2* dH, const Batch& 
         }
         TimeScope ts(EELS_PHASE_RASTER, st);
         launch_raster_dot((const RasterJob*)(d.blob + b.r_jobs), b.job_count, d.mid2, d.r_c0, d.blob + p.r_perm_off,
-                          d.blob + p.r_pos_off, p.rM, p.K, p.N1pad, p.r_chunk, 1.0f / gscale, d.r_tw, d.part, st);
+                          d.blob + p.r_pos_off, p.rM, p.K, p.N1pad, p.r_chunk, 1.0f / gscale, d.r_tw, d.part, st,
+                          split);
         return;
     }
     {
@@ -1030,6 +1033,7 @@ eels_status eels_tune_set(int key, int value) {
     if (key == TUNE_RASTER && (value < 0 || value > 2)) return EELS_ERR_INVALID_ARG;
     if (key == TUNE_CHECKPOINT && (value < 0 || value > 2)) return EELS_ERR_INVALID_ARG;
     if (key == TUNE_WG_FUSED && (value < 0 || value > 1)) return EELS_ERR_INVALID_ARG;
+    if (key == TUNE_GRAM_ROWS && (value < 0 || value > 1)) return EELS_ERR_INVALID_ARG;
     g_tune[key].store(value);
     return EELS_OK;
 }

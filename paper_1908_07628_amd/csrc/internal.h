@@ -45,7 +45,7 @@ static_assert(sizeof(GemmDesc) == 144, "GemmDesc layout");
 enum TuneKey {
     TUNE_SC_STAGES = 0, TUNE_TILE_ORDER = 1, TUNE_SC_SCHED = 2, TUNE_GRAM_STACK = 3, TUNE_GEMM1_ROWS = 4,
     TUNE_GEMM2_ROWS = 5, TUNE_WINDOW_GRAM = 6, TUNE_RASTER = 7, TUNE_CHECKPOINT = 8, TUNE_WG_FUSED = 9,
-    TUNE_COUNT = 10
+    TUNE_GRAM_ROWS = 10, TUNE_COUNT = 11
 };
 int tune_get(int key);
 
@@ -63,7 +63,7 @@ struct Batch {
     int n_parts;                        // Gram form: FP32 partials of Z^H Z written by the second GEMM
     // window-Gram form (order P, cropped windows): per site the Gram GEMM of the S_2
     // window (dm) and the product of G with Psi (dy); the d2 range then only drives the reduction
-    int dm_begin = 0, dm_count = 0, dm_tiles = 0;
+    int dm_begin = 0, dm_count = 0, dm_tiles = 0, dm_rows = 128;
     int dy_begin = 0, dy_count = 0, dy_tiles = 0, dy_rows = 128;
     int64_t r_jobs = -1;                // raster form: int offset of the batch's RasterJob table
     int64_t p_jobs = -1;                // window-Gram form: int offset of the batch's ProdJob table

@@ -116,10 +116,11 @@ void launch_window_t_sc(void* dst, const float2* src, int64_t wstride, int n_bea
 // window (s1w -> s1sc) and G (m, h, nt -> g).  Source bases: the S_2 capture or the S_1
 // windows; destination base: mid2.  With copy_prec a split precision, the transpose of the S_1
 // window (which 1) also writes that window's SC copy [n_beams][copy_ld] (s1sc) from the same
-// reads, in place of a separate launch_to_sc_batched.
+// reads, in place of a separate launch_to_sc_batched.  cph (may be null): every beam b's window
+// row is multiplied by cph[b] first (the raster form folds c_k(R_0) into both outputs).
 void launch_window_t_batched(void* dst_base, const float2* src_base, const ProdJob* jobs, int n_jobs, int which,
                              int64_t wstride, int n_beams, int K, int ldo, int prec, const int* perm, hipStream_t st,
-                             int copy_prec = 0, int copy_ld = 0);
+                             int copy_prec = 0, int copy_ld = 0, const float2* cph = nullptr);
 void launch_to_sc_batched(void* dst_base, const float2* src_base, const ProdJob* jobs, int n_jobs, int64_t rows, int K,
                           int ld, int prec, hipStream_t st);
 void launch_wgram_combine_batched(void* mid2, const float2* H, const ProdJob* jobs, int n_jobs, int K, int ldm, int ldg,
@@ -130,7 +131,7 @@ void launch_wgram_combine_batched(void* mid2, const float2* H, const ProdJob* jo
 // M^2 + i + M j] = oscale sum_r Re(conj(Psi) Y) at residue (i, j); Xt and Z rows ld complex.
 void launch_raster_dot(const RasterJob* jobs, int n_jobs, const float2* base, const float2* c0, const int* perm,
                        const int* pos, int M, int K, int ld, int chunk, float oscale, const float2* tw, float* part,
-                       hipStream_t st);
+                       hipStream_t st, bool premultiplied);
 // Window-Gram detector sum: G = gscale M o sum_t conj(H_t) H_t^T as SC rows [K][ldg]
 // (complex64 for EELS_FP32) from the FP32 complex Gram tiles M [K][ldm] (upper 128-tiles
 // valid); and out[i] = oscale sum_r Re(conj(Psi)Y) over the rows of Psi (SC, complex64 for

@@ -421,8 +421,8 @@ __global__ __launch_bounds__(128 * WM, (ScPipe<UNITS, NSTAGE, WM>::WAVES_PER_EU)
     constexpr int STAGE = SP::STAGE, ROWB = SP::ROWB, QUADS = SP::QUADS, RPI = SP::RPI, NIA = SP::NIA, NIB = SP::NIB;
     constexpr int BMX = SP::BMX, NT = 128 * WM;
     constexpr int BKS = 4 * UNITS;  // complex per tile row
-    static_assert(WM == 2 || (EPI != 2 && EPI != 4), "the 256-row tile has no Gram epilogue");
-    static_assert(EPI != 4 || NSTAGE * STAGE >= 2 * 32 * 128 * 8, "the G epilogue stages H in the LDS ring");
+    static_assert(WM == 2 || EPI != 2, "the 256-row tile has no FP32 Gram-tile epilogue");
+    static_assert(EPI != 4 || NSTAGE * STAGE >= 32 * (BMX + 128) * 8, "the G epilogue stages H in the LDS ring");
     __shared__ __attribute__((aligned(1024))) char smem[NSTAGE * STAGE];
     __shared__ int next_tile;
 
@@ -431,7 +431,9 @@ __global__ __launch_bounds__(128 * WM, (ScPipe<UNITS, NSTAGE, WM>::WAVES_PER_EU)
     int tm, tn, t;
     const GemmDesc& d = descs[locate_tile<SP::G>(descs, n_desc, order, tm, tn, t, bid, ntiles)];
     if constexpr (EPI == 2 || EPI == 4) {
-        if (tn < tm) return;   // Gram tiles: the lower triangle is the conjugate transpose
+        // Gram tiles: the lower triangle is the conjugate transpose; a tile with no element on
+        // or above the diagonal is skipped
+        if (tn * BN + BN - 1 < tm * BMX) return;
     }
     const int M = d.M, N = d.N_inner;
     const int m0 = tm * BMX, n0 = tn * BN;
@@ -590,16 +592,20 @@ __global__ __launch_bounds__(128 * WM, (ScPipe<UNITS, NSTAGE, WM>::WAVES_PER_EU)
     } else if constexpr (EPI == 4) {
         // Window-Gram G tile: G = gscale M o S with M this Gram tile and S(m, i) =
         // sum_t conj(H_t[m]) H_t[i] over the site's nt <= 32 transitions (h_off, ldh apart;
-        // ld_part holds nt), stored SC at [m][i], and off the diagonal also its conjugate
-        // transpose at [i][m] (G is Hermitian); columns N .. ldc_m - 1 of every row are zero.
+        // ld_part holds nt).  G is Hermitian: an element on or above the diagonal (i >= m) is
+        // stored SC at [m][i], and one above it also as its conjugate at [i][m], so every element
+        // of G is written once; columns N .. ldc_m - 1 of every row are zero.
         __syncthreads();                 // every wave is past its last fragment read: the ring is free
         const int nt = (int)d.ld_part;
         const float2* Hs = Hb + d.h_off;
-        float2* hrow = (float2*)smem;    // [t][128]: H_t at the tile's rows m0 + x
-        float2* hcol = hrow + 32 * 128;  // [t][128]: H_t at its columns n0 + x
+        float2* hrow = (float2*)smem;    // [t][BMX]: H_t at the tile's rows m0 + x
+        float2* hcol = hrow + 32 * BMX;  // [t][128]: H_t at its columns n0 + x
+        for (int w = tid; w < nt * BMX; w += NT) {
+            const int tt = w / BMX, x = w % BMX;
+            hrow[w] = m0 + x < M ? Hs[(int64_t)tt * d.ldh + m0 + x] : make_float2(0.f, 0.f);
+        }
         for (int w = tid; w < nt * 128; w += NT) {
             const int tt = w >> 7, x = w & 127;
-            hrow[w] = m0 + x < M ? Hs[(int64_t)tt * d.ldh + m0 + x] : make_float2(0.f, 0.f);
             hcol[w] = n0 + x < N ? Hs[(int64_t)tt * d.ldh + n0 + x] : make_float2(0.f, 0.f);
         }
         __syncthreads();
@@ -611,7 +617,6 @@ __global__ __launch_bounds__(128 * WM, (ScPipe<UNITS, NSTAGE, WM>::WAVES_PER_EU)
                     sc_store(Cb, cbase + (int64_t)m * ldg + i, make_float2(0.f, 0.f), PREC);
             }
         }
-        const bool mirror = tn > tm;
 #pragma unroll
         for (int bn = 0; bn < 2; ++bn) {
             const int il = wn * 64 + bn * 32 + li, i = n0 + il;
@@ -625,7 +630,7 @@ __global__ __launch_bounds__(128 * WM, (ScPipe<UNITS, NSTAGE, WM>::WAVES_PER_EU)
                     const float2 b = hcol[tt * 128 + il];
 #pragma unroll
                     for (int v = 0; v < 16; ++v) {
-                        const float2 a = hrow[tt * 128 + mb + 8 * (v >> 2) + (v & 3)];
+                        const float2 a = hrow[tt * BMX + mb + 8 * (v >> 2) + (v & 3)];
                         sr[v] += a.x * b.x + a.y * b.y;     // conj(a) b
                         si[v] += a.x * b.y - a.y * b.x;
                     }
@@ -641,25 +646,31 @@ __global__ __launch_bounds__(128 * WM, (ScPipe<UNITS, NSTAGE, WM>::WAVES_PER_EU)
 #pragma unroll
                 for (int v = 0; v < 16; ++v) {
                     const int m = m0 + mb + 8 * (v >> 2) + (v & 3);
-                    if (m < M) sc_store(Cb, cbase + (int64_t)m * ldg + i, make_float2(gr[v], gi[v]), PREC);
+                    if (m < M && i >= m) sc_store(Cb, cbase + (int64_t)m * ldg + i, make_float2(gr[v], gi[v]), PREC);
                 }
-                if (!mirror) continue;
 #pragma unroll
                 for (int g4 = 0; g4 < 4; ++g4) {
                     const int m4 = m0 + mb + 8 * g4;         // four consecutive columns of row i
-                    if (m4 >= ldg) continue;
-                    u32x4 hi, lo;
+                    if (i <= m4) continue;                   // none of them below the diagonal
+                    if (i > m4 + 3) {                        // all four (and all < i < M)
+                        u32x4 hi, lo;
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const bool in = m4 + e < M;
-                        uint32_t h, l;
-                        split2<PREC>(in ? gr[4 * g4 + e] : 0.f, in ? -gi[4 * g4 + e] : 0.f, h, l);
-                        hi[e] = h;
-                        lo[e] = l;
+                        for (int e = 0; e < 4; ++e) {
+                            uint32_t h, l;
+                            split2<PREC>(gr[4 * g4 + e], -gi[4 * g4 + e], h, l);
+                            hi[e] = h;
+                            lo[e] = l;
+                        }
+                        uint32_t* o = Cb + ((cbase + (int64_t)i * ldg + m4) >> 2) * 8;
+                        *(u32x4*)o = hi;
+                        *(u32x4*)(o + 4) = lo;
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (m4 + e < i)
+                                sc_store(Cb, cbase + (int64_t)i * ldg + m4 + e,
+                                         make_float2(gr[4 * g4 + e], -gi[4 * g4 + e]), PREC);
                     }
-                    uint32_t* o = Cb + ((cbase + (int64_t)i * ldg + m4) >> 2) * 8;
-                    *(u32x4*)o = hi;
-                    *(u32x4*)(o + 4) = lo;
                 }
             }
         }
@@ -815,7 +826,7 @@ static void go_sc(int nstage, int rows, const GemmDesc* dd, int nd, int tiles, c
         hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, st, dd, nd, A, B, C, P, idx, order, queue, tiles, H,      \
                            gscale);                                                                                    \
     } while (0)
-    if constexpr (EPI != 2 && EPI != 4) {
+    if constexpr (EPI != 2) {
         if (rows == 256) {
             // two stages of 16-complex tiles (96 KB of LDS; three stages measured slower on the
             // nanoparticle map's Z product, 2.87 against 2.82 s per map)

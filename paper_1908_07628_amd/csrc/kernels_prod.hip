@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstdint>
 
+#include "fft_lds.h"
 #include "internal.h"
 #include "kernels.h"
 #include "sc_format.h"
@@ -38,7 +39,8 @@ template <int PREC>
 __global__ __launch_bounds__(256) void k_window_t_sc(uint32_t* __restrict__ dst, const float2* __restrict__ src,
                                                      int64_t wstride, int n_beams, int K, int ldo,
                                                      const int* __restrict__ perm, const ProdJob* __restrict__ jobs,
-                                                     int which, int copy_prec, int copy_ld) {
+                                                     int which, int copy_prec, int copy_ld,
+                                                     const float2* __restrict__ cph) {
     // The tile holds beam row r, pixel c at tile[r][c ^ ((r >> 2) & 15)].  The swizzle puts the
     // 16 rows 4g + e (g = 0 .. 15) that a quarter-wave reads for one pixel in 16 distinct 8-byte
     // bank pairs (a padded 65-slot row left 4 of them in each), keeps every 4-pixel group of a
@@ -56,7 +58,9 @@ __global__ __launch_bounds__(256) void k_window_t_sc(uint32_t* __restrict__ dst,
     for (int r = ty; r < 64; r += 4) {
         const int b = b0 + r, px = p0 + tx;
         const int bs = (perm && b < n_beams) ? perm[b] : b;
-        tile[r][tx ^ ((r >> 2) & 15)] = (b < n_beams && px < K) ? src[(int64_t)bs * wstride + px] : make_float2(0.f, 0.f);
+        float2 v = (b < n_beams && px < K) ? src[(int64_t)bs * wstride + px] : make_float2(0.f, 0.f);
+        if (cph && b < n_beams) v = cmul(cph[bs], v);   // the beam's factor, folded into both outputs
+        tile[r][tx ^ ((r >> 2) & 15)] = v;
     }
     __syncthreads();
     for (int w = threadIdx.x; w < 64 * 16; w += 256) {
@@ -120,30 +124,30 @@ __global__ __launch_bounds__(256) void k_window_t_sc(uint32_t* __restrict__ dst,
 
 static void window_t_go(void* dst, const float2* src, int64_t wstride, int n_beams, int K, int ldo, int prec,
                         hipStream_t st, const int* perm, const ProdJob* jobs, int n_jobs, int which, int copy_prec,
-                        int copy_ld) {
+                        int copy_ld, const float2* cph) {
     if (n_beams <= 0 || K <= 0 || n_jobs <= 0) return;
     dim3 grid((unsigned)ceil_div(K, 64), (unsigned)ceil_div(ldo, 64), (unsigned)n_jobs);
     if (prec == EELS_BF16_SPLIT)
         hipLaunchKernelGGL(k_window_t_sc<EELS_BF16_SPLIT>, grid, dim3(256), 0, st, (uint32_t*)dst, src, wstride,
-                           n_beams, K, ldo, perm, jobs, which, copy_prec, copy_ld);
+                           n_beams, K, ldo, perm, jobs, which, copy_prec, copy_ld, cph);
     else if (prec == EELS_FP16_SPLIT)
         hipLaunchKernelGGL(k_window_t_sc<EELS_FP16_SPLIT>, grid, dim3(256), 0, st, (uint32_t*)dst, src, wstride,
-                           n_beams, K, ldo, perm, jobs, which, copy_prec, copy_ld);
+                           n_beams, K, ldo, perm, jobs, which, copy_prec, copy_ld, cph);
     else
         hipLaunchKernelGGL(k_window_t_sc<EELS_FP32>, grid, dim3(256), 0, st, (uint32_t*)dst, src, wstride,
-                           n_beams, K, ldo, perm, jobs, which, copy_prec, copy_ld);
+                           n_beams, K, ldo, perm, jobs, which, copy_prec, copy_ld, cph);
 }
 
 void launch_window_t_sc(void* dst, const float2* src, int64_t wstride, int n_beams, int K, int ldo, int prec,
                         hipStream_t st, const int* perm) {
-    window_t_go(dst, src, wstride, n_beams, K, ldo, prec, st, perm, nullptr, 1, 0, 0, 0);
+    window_t_go(dst, src, wstride, n_beams, K, ldo, prec, st, perm, nullptr, 1, 0, 0, 0, nullptr);
 }
 
 void launch_window_t_batched(void* dst_base, const float2* src_base, const ProdJob* jobs, int n_jobs, int which,
                              int64_t wstride, int n_beams, int K, int ldo, int prec, const int* perm, hipStream_t st,
-                             int copy_prec, int copy_ld) {
+                             int copy_prec, int copy_ld, const float2* cph) {
     window_t_go(dst_base, src_base, wstride, n_beams, K, ldo, prec, st, perm, jobs, n_jobs, which, copy_prec,
-                copy_ld);
+                copy_ld, cph);
 }
 
 // Window-Gram form of the detector sum: G = gscale M o S with S[r][c] = sum_t conj(H_t[r]) H_t[c]

@@ -10,7 +10,8 @@
 //
 // One block (256 threads) takes a run of a site's window pixels.  Per pixel it loads the two
 // grids straight into registers (thread 4 s + t holds grid row s, columns t + 4 m; the beams
-// were ordered so that these loads are contiguous), runs the row DFTs in registers (fft_reg),
+// were ordered so that these loads are contiguous; in split precision one pixel ahead), runs the
+// row DFTs in registers (fft_reg),
 // transposes through LDS, runs the column DFTs, and accumulates Re(conj(Psi) Y) per residue in
 // registers.  Two blocks share a CU (two waves per SIMD hide the loads' latency).  The block's M^2 partial sums go to `part`; the
 // FP64 reduction adds a probe's residue over the site's blocks.
@@ -24,17 +25,20 @@ namespace eels {
 
 namespace {
 
-// Loads the two grids of window pixel r (thread 4 s + t: row s, columns t + 4 m), scaled by c(R_0).
+// Loads the two grids of window pixel r (thread 4 s + t: row s, columns t + 4 m).
 __device__ __forceinline__ void load_grids(float2 (&a)[16], float2 (&b)[16], const float2* __restrict__ xr,
-                                           const float2* __restrict__ zr, const int (&q)[16], const float2 (&w)[16]) {
+                                           const float2* __restrict__ zr, const int (&q)[16]) {
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
-        a[m] = q[m] >= 0 ? cmul(w[m], xr[q[m]]) : make_float2(0.f, 0.f);
-        b[m] = q[m] >= 0 ? cmul(w[m], zr[q[m]]) : make_float2(0.f, 0.f);
+        a[m] = q[m] >= 0 ? xr[q[m]] : make_float2(0.f, 0.f);
+        b[m] = q[m] >= 0 ? zr[q[m]] : make_float2(0.f, 0.f);
     }
 }
 
-template <int M>
+// PRE: Xt and Z already hold the factor c_k(R_0) of their beam (the split path folds it into the
+// S_1 window transpose and its SC copy), and the registers this frees hold the next pixel's grids,
+// loaded while the current pixel is transformed.  Otherwise (FP32) the factors are applied here.
+template <int M, bool PRE>
 __global__ __launch_bounds__(256) void k_raster_dot(const RasterJob* __restrict__ jobs, const float2* __restrict__ base,
                                                     const float2* __restrict__ c0, const int* __restrict__ perm,
                                                     const int* __restrict__ pos, int K, int ld, int chunk,
@@ -53,20 +57,32 @@ __global__ __launch_bounds__(256) void k_raster_dot(const RasterJob* __restrict_
     const int r0 = blockIdx.x * chunk, r1 = min(K, r0 + chunk);
     const int s = threadIdx.x >> 2, t = threadIdx.x & 3;
     int q[16];
-    float2 w[16];
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-        q[m] = pos[s * M + t + 4 * m];
-        w[m] = q[m] >= 0 ? c0[perm[q[m]]] : make_float2(0.f, 0.f);
-    }
+    for (int m = 0; m < 16; ++m) q[m] = pos[s * M + t + 4 * m];
     float acc[16];
 #pragma unroll
     for (int m = 0; m < 16; ++m) acc[m] = 0.f;
     const float2* xt = base + jb.xt;
     const float2* z = base + jb.z;
+    // PRE: the next pixel's grids; otherwise the beams' factors c_k(R_0)
+    float2 na[16], nb[16];
+    if constexpr (PRE) {
+        if (r0 < r1) load_grids(na, nb, xt + (int64_t)r0 * ld, z + (int64_t)r0 * ld, q);
+    } else {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) na[m] = q[m] >= 0 ? c0[perm[q[m]]] : make_float2(0.f, 0.f);
+    }
     for (int r = r0; r < r1; ++r) {
         float2 a[16], b[16];
-        load_grids(a, b, xt + (int64_t)r * ld, z + (int64_t)r * ld, q, w);
+        if constexpr (PRE) {
+#pragma unroll
+            for (int m = 0; m < 16; ++m) { a[m] = na[m]; b[m] = nb[m]; }
+            if (r + 1 < r1) load_grids(na, nb, xt + (int64_t)(r + 1) * ld, z + (int64_t)(r + 1) * ld, q);
+        } else {
+            load_grids(a, b, xt + (int64_t)r * ld, z + (int64_t)r * ld, q);
+#pragma unroll
+            for (int m = 0; m < 16; ++m) { a[m] = cmul(na[m], a[m]); b[m] = cmul(na[m], b[m]); }
+        }
         // rows: the sequence of row s lies in the 4 lanes 4 s .. 4 s + 3 of one wavefront, so its
         // exchange through row s of the grid needs wave-level ordering only
         fft_reg<M, -1, true, true>(a, la, s * LD, 1, t, tw);
@@ -99,12 +115,16 @@ __global__ __launch_bounds__(256) void k_raster_dot(const RasterJob* __restrict_
 
 void launch_raster_dot(const RasterJob* jobs, int n_jobs, const float2* base, const float2* c0, const int* perm,
                        const int* pos, int M, int K, int ld, int chunk, float oscale, const float2* tw, float* part,
-                       hipStream_t st) {
+                       hipStream_t st, bool premultiplied) {
     if (n_jobs <= 0 || K <= 0) return;
     dim3 grid((unsigned)ceil_div(K, chunk), (unsigned)n_jobs);
-    if (M == 64)
-        hipLaunchKernelGGL(k_raster_dot<64>, grid, dim3(256), 0, st, jobs, base, c0, perm, pos, K, ld, chunk, oscale,
-                           tw, part);
+    if (M != 64) return;
+    if (premultiplied)
+        hipLaunchKernelGGL((k_raster_dot<64, true>), grid, dim3(256), 0, st, jobs, base, c0, perm, pos, K, ld, chunk,
+                           oscale, tw, part);
+    else
+        hipLaunchKernelGGL((k_raster_dot<64, false>), grid, dim3(256), 0, st, jobs, base, c0, perm, pos, K, ld, chunk,
+                           oscale, tw, part);
 }
 
 }  // namespace eels

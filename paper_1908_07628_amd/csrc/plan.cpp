@@ -880,6 +880,8 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
             // split precision with the G epilogue, G_s = gscale M_s o sum_t conj(H_t) H_t^T in SC
             // (both triangles; the H of the site at h_off, K apart, ld_part transitions)
             bt.dm_begin = (int)p.descs.size();
+            // the G epilogue on 128-row tiles, or 256-row ones (tuning key 10 = 1)
+            bt.dm_rows = (p.wg_fused && tune_get(TUNE_GRAM_ROWS) != 0) ? 256 : GEMM_BM;
             int tl = 0;
             for (size_t si = 0; si < pb.sites.size(); ++si) {
                 const Job& jb = p.jobs[bt.job_begin + si];
@@ -891,7 +893,7 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
                     d.c_off = jb.g_off; d.h_off = jb.h_off; d.ldh = p.K; d.ld_part = jb.nt;
                 }
                 d.M = p.K; d.N_inner = p.K; d.n_t = 1; d.K = p.N2;
-                d.tiles_m = (int)ceil_div(p.K, GEMM_BM);
+                d.tiles_m = (int)ceil_div(p.K, bt.dm_rows);
                 d.tiles_n = (int)ceil_div(p.K, GEMM_BN);
                 d.tile_start = tl;
                 tl += d.tiles_m * d.tiles_n;

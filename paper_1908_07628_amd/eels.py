@@ -470,6 +470,7 @@ TUNE_WINDOW_GRAM = 6
 TUNE_RASTER = 7
 TUNE_CHECKPOINT = 8
 TUNE_WG_FUSED = 9
+TUNE_GRAM_ROWS = 10
 
 
 def tune_set(key: int, value: int):

@@ -66,7 +66,7 @@ struct Case {
     bool tight_budget = false; // the budget is the smallest one the planner accepts (bisection)
     double budget_frac = 0;    // > 0: the budget is this fraction of the unconstrained workspace
     double aperture = 20, det_in = 10, det_out = 40;
-    int knobs[TUNE_COUNT] = {0, 0, 0, 0, 0, 0, 1, 1, 1, 1};
+    int knobs[TUNE_COUNT] = {0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 0};
     eels_status expect = EELS_OK;
     int want_raster = -1, want_wgram = -1, want_gram = -1, want_groups_gt1 = -1, want_ckpt = -1;
 };
@@ -374,7 +374,7 @@ void check_plan(const Plan& p, const Case& c, size_t budget) {
             }
             CHECK(tiles == rg.tiles, "batch %zu %s: %d tiles, table says %d", bi, rg.name, tiles, rg.tiles);
             // row tiles of the launch (128 or 256 rows)
-            const int rows = rg.role == &r1 ? b.d1_rows : rg.role == &r2 ? b.d2_rows : rg.role == &ry ? b.dy_rows : GEMM_BM;
+            const int rows = rg.role == &r1 ? b.d1_rows : rg.role == &r2 ? b.d2_rows : rg.role == &ry ? b.dy_rows : b.dm_rows;
             CHECK(rows == 128 || rows == 256, "batch %zu %s rows %d", bi, rg.name, rows);
             for (int k = 0; k < rg.count && rg.launched; ++k) {
                 const GemmDesc& d = p.descs[rg.begin + k];
@@ -680,6 +680,10 @@ int main() {
         { Case c = mk(""); c.name = "groups-budget-" + ps; c.n = 256; c.window_A = 6.0; c.nz = 16; c.n_sites = 40;
           c.det_in = 5; c.det_out = 20;
           c.precision = prec; c.tight_budget = true; c.want_groups_gt1 = 1; cases.push_back(c); }
+        // window-Gram G epilogue on 256-row Gram tiles (tuning key 10)
+        { Case c = mk(""); c.name = "wgram-gram256-" + ps; c.n = 128; c.window_A = 4.0; c.f = 2;
+          c.order = EELS_ORDER_PROBE_FIRST; c.precision = prec; c.knobs[TUNE_WINDOW_GRAM] = 2;
+          c.knobs[TUNE_GRAM_ROWS] = 1; c.want_wgram = 1; cases.push_back(c); }
         // slice groups resuming from S_1 checkpoints (forced), and under the default rule
         for (double fr : {0.8, 0.6, 0.4}) {
             Case c = mk(""); c.name = "groups-checkpoint-" + std::to_string((int)(100 * fr)) + "-" + ps; c.n = 256;

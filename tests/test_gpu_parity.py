@@ -404,30 +404,36 @@ def test_window_gram_form(prec, tol):
 @pytest.mark.parametrize("prec", ["bf16_split", "fp16_split"])
 def test_window_gram_g_epilogue_matches_combine(prec):
     """Split window-Gram form: G formed in the Gram GEMM's epilogue (tuning key 9 = 1, the
-    default) against the Gram tiles M and the separate combine pass (key 9 = 0).  Both round G
-    from the same FP32 M and S, in different orders, so the maps agree to FP32 rounding, and
-    both meet the oracle; with and without the raster form, at 1, 3 and 9 transitions."""
+    default) on 256-row tiles (key 10 = 1) and on 128-row tiles (the default), against the Gram
+    tiles M and the separate combine pass (key 9 = 0).  All round G from the same FP32 M and S,
+    in different orders, so the maps agree to FP32 rounding, and they meet the oracle; with and
+    without the raster form, at 1, 3 and 9 transitions."""
     eels = _need_gpu()
     cases = [("nanoparticle-like f=2 raster", synth.config3_subproblem(n=128, L=25.0, nz=5, n_scan=8, f=2), 2),
              ("random f=1 crop, 3 transitions", synth.random_problem(12, n=64, L=12.0, nz=3, window_A=4.0,
                                                                      n_sites=3, n_trans=3), 0),
              ("random f=1 crop, 1 transition", synth.random_problem(13, n=64, L=12.0, nz=3, window_A=4.0,
                                                                     n_sites=4, n_trans=1), 0)]
-    keep = {k: eels.tune_get(k) for k in (eels.TUNE_WINDOW_GRAM, eels.TUNE_RASTER, eels.TUNE_WG_FUSED)}
+    keys = (eels.TUNE_WINDOW_GRAM, eels.TUNE_RASTER, eels.TUNE_WG_FUSED, eels.TUNE_GRAM_ROWS)
+    keep = {k: eels.tune_get(k) for k in keys}
     try:
         for name, p, raster in cases:
             ref = prism.prism_map(p)
             eels.tune_set(eels.TUNE_WINDOW_GRAM, 2)
             eels.tune_set(eels.TUNE_RASTER, raster)
             maps = {}
-            for fused in (1, 0):
+            # (key 9, key 10): G epilogue on 256-row and on 128-row tiles, then the combine pass
+            for fused, rows in ((1, 1), (1, 0), (0, 1)):
                 eels.tune_set(eels.TUNE_WG_FUSED, fused)
-                _say("G epilogue", name, prec, "key 9 =", fused)
-                maps[fused] = _map(eels, p, prec, "probe_first")
-            _say("  fused vs combine", metrics.rel_l2(maps[1], maps[0]), "vs oracle", metrics.rel_l2(maps[1], ref))
-            assert metrics.rel_l2(maps[1], maps[0]) < 1e-6
-            assert maps_close(maps[1], ref, 1e-3)
-            assert np.all(maps[1][ref == 0] == 0)
+                eels.tune_set(eels.TUNE_GRAM_ROWS, rows)
+                _say("G epilogue", name, prec, "key 9 =", fused, "key 10 =", rows)
+                maps[fused, rows] = _map(eels, p, prec, "probe_first")
+            for k in ((1, 0), (0, 1)):
+                _say("  ", k, "vs (1, 1)", metrics.rel_l2(maps[k], maps[1, 1]))
+                assert metrics.rel_l2(maps[k], maps[1, 1]) < 1e-6
+            _say("  vs oracle", metrics.rel_l2(maps[1, 1], ref))
+            assert maps_close(maps[1, 1], ref, 1e-3)
+            assert np.all(maps[1, 1][ref == 0] == 0)
     finally:
         for k, v in keep.items():
             eels.tune_set(k, v)
