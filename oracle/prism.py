@@ -79,6 +79,30 @@ def inverse_s1(prob, st, slices) -> Dict[int, np.ndarray]:
     return out
 
 
+def inverse_s2(prob, st, slices) -> Dict[int, np.ndarray]:
+    """S_2(j) the way Sec. 4.C prints the inverse multislice: S_2 is first formed for the
+    entrance (slice 0) by the exact transposed sweep from the exit, x_0 = M_0^T ... M_{n_z-1}^T e_q,
+    then retreated one slice at a time towards the exit with the inverse of each transposed
+    step, the transmission and propagator conjugated and their order reversed,
+        x_{j+1} = (M_j^T)^-1 x_j = conj(P_j) * ifft2(conj(T_j) * fft2(x_j)),
+    and S_2(j) = fft2(x_j) (the transposed sweep's S_2(j) = T_j * fft2(P_j * x_{j+1}) has
+    ifft2(S_2(j)) = x_j).  Exact where nothing left the band limit; otherwise approximate."""
+    need = set(int(j) for j in slices)
+    out: Dict[int, np.ndarray] = {}
+    if not need:
+        return out
+    N2 = st.ab2.shape[0]
+    x = np.zeros((N2, prob.ny, prob.nx), dtype=np.complex128)
+    x[np.arange(N2), st.iy2, st.ix2] = 1.0
+    for j in range(prob.n_slices - 1, -1, -1):
+        x = np.fft.ifft2(st.T[j] * np.fft.fft2(st.P[j] * x))
+    for j in range(0, max(need) + 1):
+        if j in need:
+            out[j] = np.fft.fft2(x)
+        x = np.conj(st.P[j]) * np.fft.ifft2(np.conj(st.T[j]) * np.fft.fft2(x))
+    return out
+
+
 def reverse_s2(prob, st, j_stop: int = 0):
     """Yield (j, S_2(j)) for j = n_z-1 down to j_stop (exact transposed multislice)."""
     N2 = st.ab2.shape[0]
@@ -116,12 +140,20 @@ def contract_site(prob, st, s: int, S1j: np.ndarray, S2j: np.ndarray, I: np.ndar
 
 
 def prism_map(prob, lam=None, sigma=None, st=None, s1_mode: str = "stored") -> np.ndarray:
-    """The map; s1_mode "stored" uses the forward S_1 (exact), "inverse" the inverse-multislice
-    S_1 (Sec. 4.C)."""
+    """The map; s1_mode "stored" uses the forward S_1 and the transposed S_2 sweep (exact),
+    "inverse" the inverse-multislice S_1, "inverse_s2" the inverse-multislice S_2 (Sec. 4.C
+    as printed: S_2 retreated towards the exit)."""
     st = make_setup(prob, lam, sigma) if st is None else st
     I = np.zeros(prob.n_probes, dtype=np.float64)
     ion = sorted(st.sites_by_slice.keys())
     if not ion:
+        return I
+    if s1_mode == "inverse_s2":
+        S1 = forward_s1(prob, st, ion)
+        S2 = inverse_s2(prob, st, ion)
+        for j in reversed(ion):
+            for s in st.sites_by_slice.get(j, []):
+                contract_site(prob, st, s, S1[j], S2[j], I)
         return I
     S1 = forward_s1(prob, st, ion) if s1_mode == "stored" else inverse_s1(prob, st, ion)
     for j, S2 in reverse_s2(prob, st, j_stop=min(ion)):
