@@ -106,7 +106,8 @@ typedef struct {
                                 (needs one slice group), so that a later eels_execute_ex with
                                 EELS_EXEC_SKIP_SWEEPS can reuse the S-matrices              */
     int detector_sum;        /* EELS_DETSUM_*: how sum_{n,q} |A_n(q,R)|^2 is formed (order S)  */
-    int s1_mode;             /* EELS_S1_STORED (exact) or EELS_S1_INVERSE (Sec. 4.C)        */
+    int s1_mode;             /* EELS_S1_STORED (exact), EELS_S1_INVERSE or EELS_S2_RETREAT
+                                (the inverse multislice of Sec. 4.C on S_1 or on S_2)         */
     int n_images;            /* elastic companion images (0 .. EELS_MAX_IMAGES), interp_f = 1  */
     const double* image_detectors_mrad;  /* [n_images][2] inner, outer semi-angle (inclusive);
                                 outer <= 0 means the band limit                              */
@@ -137,7 +138,14 @@ enum { EELS_DETSUM_AUTO = 0, EELS_DETSUM_DIRECT = 1, EELS_DETSUM_GRAM = 2 };
  * with M_j^-1 = F conj(T_j) F^-1 conj(P_j) in step with the S_2 sweep, so only one slice's
  * windows are ever held.  Approximate: intensity that multislice pushed beyond the band
  * limit is not recovered.  Not combinable with resident_s. */
-enum { EELS_S1_STORED = 0, EELS_S1_INVERSE = 1 };
+/* EELS_S1_STORED: S_1 windows of the ionised slices stored by the forward sweep, S_2 by one
+ * exact transposed sweep (exact).  EELS_S1_INVERSE: S_1 multisliced to the exit and retreated
+ * slice by slice with the inverse multislice (Eq. MSinvop) beside the transposed sweep.
+ * EELS_S2_RETREAT: as Sec. 4.C describes it, S_2 formed for the entrance by the transposed sweep
+ * and retreated towards the exit with the inverse of each transposed step, beside the forward
+ * S_1 sweep.  Both inverse modes keep one slice's windows and are approximate where intensity
+ * left the band limit.  EELS_S2_RETREAT plans contract in real space (real_space implied). */
+enum { EELS_S1_STORED = 0, EELS_S1_INVERSE = 1, EELS_S2_RETREAT = 2 };
 
 /* Derived sizes of a plan (filled by eels_plan_info). */
 typedef struct {

@@ -212,6 +212,35 @@ void inverse_step(const Plan& p, const Dev& d, int j, bool capture, hipStream_t 
     launch_row_pass(p.nx, 2, a, st);
 }
 
+// One slice of the S_2 retreat (Sec. 4.C applied to S_2) beside the forward S_1 sweep.  With
+// `rows`, both row passes of slice j: S_1's (capturing the windows of slice j's sites when
+// `capture`) and the inverse of the transposed step's row pass, FFT_x -> (capture S_2(j), the
+// value the transposed sweep captures there) -> * conj(T_j) -> iFFT_x.  At slice 0 the state is
+// the transposed sweep's before its last row pass, and that pass's capture is taken instead
+// (mode 4: the state comes back times nx^2, the scale the inverse row pass leaves).  Otherwise
+// both column passes: S_1 to the entrance of slice j+1 and S_2 back to where the transposed
+// sweep stood after slice j+1 (iFFT_y -> * conj(P_j) / (nx ny) -> FFT_y).
+void retreat_step(const Plan& p, const Dev& d, int j, bool capture, bool rows, hipStream_t st) {
+    TimeScope ts(EELS_PHASE_SWEEP, st);
+    if (!rows) {
+        launch_col_pass(p.ny, 0, d.s1, p.N1, p.nlx, p.ldx, Pj(p, d, j), d.twy, d.band_h, BandCap{}, st);
+        launch_col_pass(p.ny, 3, d.s2, p.N2, p.nlx, p.ldx, Pj(p, d, j), d.twy, d.band_h, BandCap{}, st);
+        return;
+    }
+    RowPassArgs a{d.s1, p.N1, p.ny, p.nlx, p.hlx, Tj(p, d, j), d.twx, nullptr, nullptr, d.w1, p.N1, p.Kpad, 0,
+                  p.ldx};
+    RowPassArgs b{d.s2, p.N2, p.ny, p.nlx, p.hlx, Tj(p, d, j), d.twx, nullptr, nullptr, d.w2 + p.slice_w2[j], p.N2,
+                  p.Kpad, p.w2_sc, p.ldx};
+    if (capture) {
+        a.cap_ptr = d.blob + p.slices[j].cap1_ptr;
+        a.cap_rec = d.blob + p.slices[j].cap1_rec;
+        b.cap_ptr = d.blob + p.slices[j].cap2_ptr;
+        b.cap_rec = d.blob + p.slices[j].cap2_rec;
+    }
+    launch_row_pass(p.nx, 0, a, st);
+    launch_row_pass(p.nx, j == 0 ? 4 : 3, b, st);
+}
+
 // One step of the transposed sweep: bring S_2 to slice j (from j+1, or start at n_z-1)
 // and capture what the contraction at j needs: the S_2 windows (real-space contraction,
 // in the row pass) or the band coefficients of P_j x_{j+1} (band basis, in the column
@@ -699,6 +728,32 @@ eels_status eels_execute_images(const eels_plan* pl, const float* d_V, const voi
             inverse_step(p, d, j, p.slices[j].ion, st);
             if (p.slices[j].ion)
                 for (int bi : p.slices[j].batches) contract(p, d, (const float2*)d_H, d_map, bi, st);
+        }
+        finish_map(p, d, d_map, st);
+        HIPCHK(hipGetLastError());
+        return EELS_OK;
+    }
+    if (p.s2_retreat && !p.groups.empty()) {
+        // S_2 through every slice to the entrance, then back up with the inverse of each
+        // transposed step beside the forward S_1 sweep, slice by slice up to the top site
+        if (images) {
+            forward_sweep(p, d, p.nz - 1, -1, -1, nullptr, st, d.img_exit);
+            companion_images(p, d, d_images, st);
+        }
+        for (int j = p.nz - 1; j >= 1; --j) reverse_step(p, d, j, false, nullptr, st);
+        const int j_top = p.groups[0].j_hi;
+        {
+            // the state before the row pass of slice 0 (band-limited, so held exactly)
+            TimeScope ts(EELS_PHASE_SWEEP, st);
+            if (p.nz == 1) launch_init_reverse(d.s2, d.b2, p, st);
+            else launch_col_pass(p.ny, 1, d.s2, p.N2, p.nlx, p.ldx, Pj(p, d, 0), d.twy, d.band_h, BandCap{}, st);
+            launch_init_forward(d.s1, d.b1, p, st);
+        }
+        for (int j = 0; j <= j_top; ++j) {
+            retreat_step(p, d, j, p.slices[j].ion, true, st);
+            if (p.slices[j].ion)
+                for (int bi : p.slices[j].batches) contract(p, d, (const float2*)d_H, d_map, bi, st);
+            if (j < j_top) retreat_step(p, d, j, false, false, st);
         }
         finish_map(p, d, d_map, st);
         HIPCHK(hipGetLastError());

@@ -12,6 +12,14 @@
 // which retreats S_1 by a slice, is
 //   column pass  FFT_y  -> * conj(P_j) / (nx ny) -> iFFT_y
 //   row pass     iFFT_x -> * conj(T_j) -> (capture S_1 windows) -> FFT_x
+// while the inverse of a transposed step, (M_j^T)^-1 = conj(P_j) F^-1 conj(T_j) F, which
+// retreats S_2 by a slice towards the exit (mode 3), is
+//   row pass     FFT_x  -> (capture S_2 windows) -> * conj(T_j) -> iFFT_x
+//   column pass  iFFT_y -> * conj(P_j) / (nx ny) -> FFT_y
+// The retreat starts from the transposed sweep's state before the row pass of slice 0, which is
+// still band-limited; its first row pass (mode 4) is
+//   row pass     FFT_x  -> * T_j -> (capture S_2 windows) -> * conj(T_j) nx -> iFFT_x
+// which captures what the transposed sweep captures there and stores its input times nx^2.
 // Transforms are unnormalised; the 1/(nx ny) folded into P keeps S_2 exactly at the
 // scale of its definition and S_1 at nx*ny times it (unit-modulus plane waves at j = 0).
 #include <hip/hip_runtime.h>
@@ -224,7 +232,8 @@ __global__ void k_copy(float2* dst, const float2* src, int64_t n) {
 // overlaps the FFT arithmetic of the same wave (the grid is capped, see row_grid).
 // mode 0: forward sweep (iFFT_x, capture, x T, FFT_x); mode 1: transposed sweep (FFT_x, x T,
 // capture, iFFT_x); mode 2: inverse multislice, Eq. MSinvop (iFFT_x, x conj(T), capture the
-// slice's entrance wave, FFT_x).  CAP = false: no capture (its code and registers left out).
+// slice's entrance wave, FFT_x); mode 3: the transposed step undone (FFT_x, capture the S_2 row
+// of this slice, x conj(T), iFFT_x).  CAP = false: no capture (its code and registers left out).
 template <int N, int MODE, bool CAP>
 __device__ __forceinline__ void row_pass_body(float2* __restrict__ state, int nbeam, int ny, int nlx, int hlx, int ldx,
                                               const float2* __restrict__ Tj, const float2* __restrict__ tw,
@@ -254,13 +263,16 @@ __device__ __forceinline__ void row_pass_body(float2* __restrict__ state, int nb
         const int y = valid ? (int)(g % ny) : 0;
         const int64_t beam = valid ? g / ny : 0;
         if (grp + gridDim.x < ngroups) load(grp + gridDim.x);
-        constexpr int S1 = MODE == 1 ? -1 : +1;   // first transform's sign (+1: inverse FFT_x)
+        constexpr int S1 = (MODE == 1 || MODE >= 3) ? -1 : +1;   // first transform's sign (+1: inverse FFT_x)
         fft_reg<N, S1, true, true>(v, lds, s * L, 1, t, tw);
 
         // In mode 2 the column pass's conj(P_j) / (nx ny) leaves this pass's input 1/nx of the
         // forward row pass's output (the state after the final FFT_x is exact), so the captured
         // entrance wave is scaled by nx (exact) to match the forward capture.
-        constexpr float cap_scale = MODE == 2 ? (float)N : 1.0f;
+        // In mode 3 the row's FFT_x of the transposed sweep's state is N times the S_2 row that
+        // the transposed sweep captured at this slice (its FFT_x / iFFT_x pair is unnormalised),
+        // so the capture is scaled by 1/N (exact).
+        constexpr float cap_scale = MODE == 2 ? (float)N : MODE == 3 ? 1.0f / (float)N : 1.0f;
         // Capture: the row is put in pixel order into its own exchange slots (free between the
         // two transforms; a row's T <= 64 threads are one wave, whose LDS operations complete
         // in order), then the window rows it meets are written as one flat run of
@@ -304,15 +316,26 @@ __device__ __forceinline__ void row_pass_body(float2* __restrict__ state, int nb
                 lds_sync_wave();
             }
         };
-        if constexpr (MODE == 0) capture();
+        if constexpr (MODE == 0 || MODE == 3) capture();
         const float2* Trow = Tj + (int64_t)y * N;
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             float2 tv = Trow[t + T * m];
-            if constexpr (MODE == 2) tv.y = -tv.y;
+            if constexpr (MODE == 2 || MODE == 3) tv.y = -tv.y;
             v[m] = cmul(v[m], tv);
         }
-        if constexpr (MODE != 0) capture();
+        if constexpr (MODE == 1 || MODE == 2 || MODE == 4) capture();
+        if constexpr (MODE == 4) {
+            // the row's T_j goes to the capture only: undo it, with the factor N that makes the
+            // stored row N^2 times its input (the scale the retreat's column pass expects)
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                float2 tv = Trow[t + T * m];
+                tv.x *= (float)N;
+                tv.y *= -(float)N;
+                v[m] = cmul(v[m], tv);
+            }
+        }
 
         fft_reg<N, -S1, true, true>(v, lds, s * L, 1, t, tw);
 #pragma unroll
@@ -400,13 +423,13 @@ __device__ __forceinline__ void col_pass_body(float2* __restrict__ state, int nb
         const float2 pxc = live ? px[c] : make_float2(0.f, 0.f);
         float2* plane = state + beam * (int64_t)N * ldx;
         if (it + G < items) load(it + G);
-        constexpr int S1 = MODE == 1 ? +1 : -1;   // first transform's sign (-1: FFT_y)
+        constexpr int S1 = (MODE == 1 || MODE == 3) ? +1 : -1;   // first transform's sign (-1: FFT_y)
         fft_reg<N, S1, true>(v, lds, col, CW, t, tw);
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             const int ys = signed_index(t + T * m, N);
             float2 pv = (ys <= h && -ys <= h) ? cmul(pxc, py[t + T * m]) : make_float2(0.f, 0.f);
-            if constexpr (MODE == 2) pv.y = -pv.y;   // inverse multislice: conj(P)
+            if constexpr (MODE == 2 || MODE == 3) pv.y = -pv.y;   // inverse multislice: conj(P)
             v[m] = cmul(v[m], pv);
         }
         if (CAP && live) {
@@ -717,7 +740,9 @@ void launch_row_pass(int nx, int mode, const RowPassArgs& a, hipStream_t st) {
     case NN:                                          \
         if (mode == 0) row_pass_n<NN, 0>(a, st);      \
         else if (mode == 1) row_pass_n<NN, 1>(a, st); \
-        else row_pass_n<NN, 2>(a, st);                \
+        else if (mode == 2) row_pass_n<NN, 2>(a, st); \
+        else if (mode == 3) row_pass_n<NN, 3>(a, st); \
+        else row_pass_n<NN, 4>(a, st);                \
         break;
     switch (nx) {
         ROWCASE(16) ROWCASE(32) ROWCASE(64) ROWCASE(128) ROWCASE(256) ROWCASE(384) ROWCASE(512) ROWCASE(1024)
@@ -746,7 +771,8 @@ void launch_col_pass(int ny, int mode, float2* state, int nbeam, int nlx, int ld
     case NN:                                                          \
         if (mode == 0) col_pass_n<NN, 0>(state, nbeam, nlx, ldx, Pj, tw, band_h, bc, st); \
         else if (mode == 1) col_pass_n<NN, 1>(state, nbeam, nlx, ldx, Pj, tw, band_h, bc, st); \
-        else col_pass_n<NN, 2>(state, nbeam, nlx, ldx, Pj, tw, band_h, bc, st);    \
+        else if (mode == 2) col_pass_n<NN, 2>(state, nbeam, nlx, ldx, Pj, tw, band_h, bc, st); \
+        else col_pass_n<NN, 3>(state, nbeam, nlx, ldx, Pj, tw, band_h, bc, st);    \
         break;
     switch (ny) {
         COLCASE(16) COLCASE(32) COLCASE(64) COLCASE(128) COLCASE(256) COLCASE(384) COLCASE(512) COLCASE(1024)

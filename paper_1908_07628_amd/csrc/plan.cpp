@@ -83,8 +83,9 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     if (q.order < EELS_ORDER_AUTO || q.order > EELS_ORDER_PROBE_FIRST) return fail(EELS_ERR_INVALID_ARG, "order");
     if (q.detector_sum < EELS_DETSUM_AUTO || q.detector_sum > EELS_DETSUM_GRAM)
         return fail(EELS_ERR_INVALID_ARG, "detector_sum");
-    if (q.s1_mode != EELS_S1_STORED && q.s1_mode != EELS_S1_INVERSE) return fail(EELS_ERR_INVALID_ARG, "s1_mode");
-    if (q.s1_mode == EELS_S1_INVERSE && q.resident_s)
+    if (q.s1_mode != EELS_S1_STORED && q.s1_mode != EELS_S1_INVERSE && q.s1_mode != EELS_S2_RETREAT)
+        return fail(EELS_ERR_INVALID_ARG, "s1_mode");
+    if (q.s1_mode != EELS_S1_STORED && q.resident_s)
         return fail(EELS_ERR_INVALID_ARG, "the inverse multislice keeps no S_1 windows to make resident");
     if (q.n_images < 0 || q.n_images > EELS_MAX_IMAGES || (q.n_images > 0 && !q.image_detectors_mrad))
         return fail(EELS_ERR_INVALID_ARG, "n_images / image_detectors_mrad");
@@ -240,7 +241,8 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     }
     // full-cell windows contract in the band basis (exact): sum_r S_2 H S_1 equals the sum
     // over band pixels g of (P_j x_{j+1})(g) * fft2(T_j H S_1)(g)
-    p.recip = p.full_window && !q.real_space;
+    // (the S_2 retreat captures real-space windows only: its plans always contract in real space)
+    p.recip = p.full_window && !q.real_space && q.s1_mode != EELS_S2_RETREAT;
     if (p.recip && (!pow2_ok(p.nx) || !pow2_ok(p.ny)))
         return fail(EELS_ERR_UNSUPPORTED_SIZE, "the band-basis contraction needs power-of-two grid sides "
                                                "(use a crop window or real_space)");
@@ -464,7 +466,8 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     p.site_w1.assign(S, -1);
     p.site_w2.assign(S, -1);
     p.s1_inverse = q.s1_mode == EELS_S1_INVERSE;
-    if (p.s1_inverse) {
+    p.s2_retreat = q.s1_mode == EELS_S2_RETREAT;
+    if (p.s1_inverse || p.s2_retreat) {
         // one pass; the windows of one slice at a time
         int maxw = 0;
         for (int j : ion) {
@@ -1074,9 +1077,11 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     double fwd = 0, rev = 0;
     if (!ion.empty()) {
         if (p.s1_inverse) fwd = (double)(2 * p.nz - ion.front()) * p.N1;   // to the exit and back
+        else if (p.s2_retreat) fwd = (double)(ion.back() + 1) * p.N1;     // up to the top site
         else
             for (auto& g : p.groups) fwd += (double)(g.ckpt >= 0 ? g.j_hi - g.j_lo + 1 : g.j_hi + 1) * p.N1;
-        rev = (double)(p.nz - ion.front()) * p.N2;
+        rev = p.s2_retreat ? (double)(p.nz + ion.back()) * p.N2           // to the entrance, then back up
+                           : (double)(p.nz - ion.front()) * p.N2;
     }
     p.sweep_beam_slices = fwd + rev;
     p.sweep_bytes = p.sweep_beam_slices * 32.0 * p.ny * p.nlx;

@@ -194,7 +194,7 @@ def problem_struct(pr: Any, precision: str = "fp32", order: str = "auto", max_wo
         sites=sites, n_trans_total=n_trans, precision=PRECISIONS[precision], order=ORDERS[order],
         max_workspace_bytes=int(max_workspace_bytes), real_space=int(bool(real_space)),
         resident_s=int(bool(resident_s)), detector_sum=DETSUMS[detector_sum],
-        s1_mode={"stored": 0, "inverse": 1}[s1_mode], n_images=int(img.shape[0]),
+        s1_mode={"stored": 0, "inverse": 1, "inverse_s2": 2}[s1_mode], n_images=int(img.shape[0]),
         image_detectors_mrad=img.ctypes.data_as(C.POINTER(C.c_double)))
     return pc, {"img": img, "dz": dz, "probes": probes, "sites": sites}
 
@@ -209,7 +209,9 @@ class Plan:
                  images=(), s1_mode: str = "stored"):
         """images: elastic companion-image rings [(inner_mrad, outer_mrad), ...]; outer <= 0
         means the band limit (e.g. ((0, det_outer), (60, 0)) for iBF and ADF).  s1_mode:
-        "stored" (exact) or "inverse" (inverse multislice, Sec. 4.C)."""
+        "stored" (exact), "inverse" (S_1 retreated with the inverse multislice, Sec. 4.C) or
+        "inverse_s2" (S_2 formed at the entrance and retreated towards the exit, as Sec. 4.C
+        describes it; contracts in real space)."""
         lib = load_library()
         self._window_gram = tune_get(TUNE_WINDOW_GRAM)     # plan-time form of the detector sum
         self._source = (problem, dict(precision=precision, order=order, max_workspace_bytes=max_workspace_bytes,

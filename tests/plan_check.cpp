@@ -696,6 +696,10 @@ int main() {
           c.precision = prec; c.resident = 1; cases.push_back(c); }
         { Case c = mk(""); c.name = "inverse-" + ps; c.n = 256; c.window_A = 6.0; c.nz = 8; c.n_sites = 10;
           c.precision = prec; c.s1_mode = EELS_S1_INVERSE; cases.push_back(c); }
+        { Case c = mk(""); c.name = "s2-retreat-" + ps; c.n = 256; c.window_A = 6.0; c.nz = 8; c.n_sites = 10;
+          c.precision = prec; c.s1_mode = EELS_S2_RETREAT; cases.push_back(c); }
+        { Case c = mk(""); c.name = "s2-retreat-full-cell-" + ps; c.nz = 4; c.n_sites = 4; c.precision = prec;
+          c.s1_mode = EELS_S2_RETREAT; cases.push_back(c); }
         { Case c = mk(""); c.name = "images-" + ps; c.precision = prec; c.n_images = 2; cases.push_back(c); }
     }
     // sizes and probe counts at the edges
@@ -712,6 +716,9 @@ int main() {
     { Case c = mk("f-without-window"); c.f = 2; c.expect = EELS_ERR_INVALID_ARG; cases.push_back(c); }
     { Case c = mk("inverse-resident"); c.s1_mode = EELS_S1_INVERSE; c.resident = 1; c.expect = EELS_ERR_INVALID_ARG;
       cases.push_back(c); }
+    { Case c = mk("s2-retreat-resident"); c.s1_mode = EELS_S2_RETREAT; c.resident = 1; c.expect = EELS_ERR_INVALID_ARG;
+      cases.push_back(c); }
+    { Case c = mk("s1-mode-3"); c.s1_mode = 3; c.expect = EELS_ERR_INVALID_ARG; cases.push_back(c); }
     { Case c = mk("images-with-f2"); c.window_A = 6.0; c.n = 256; c.f = 2; c.n_images = 1; c.expect = EELS_ERR_INVALID_ARG;
       cases.push_back(c); }
     { Case c = mk("detector-beyond-band"); c.dx = 0.5; c.expect = EELS_ERR_BANDLIMIT; cases.push_back(c); }

@@ -216,6 +216,24 @@ def test_inverse_multislice_plan():
     assert e.value.status == 1
 
 
+def test_s2_retreat_plan():
+    """S_2 retreat: one slice's windows, S_2 to the entrance and back up to the top site beside
+    S_1 up to it, real-space contraction, and no resident S-matrices."""
+    _lib()
+    p = synth.random_problem(6, n=64, L=10.0, nz=8, n_sites=6, atoms_per_slice=3, window_A=0.0)
+    a = eels.Plan(p).info()
+    b = eels.Plan(p, s1_mode="inverse_s2").info()
+    assert a["band_basis"] == 1 and b["band_basis"] == 0
+    assert b["n_groups"] == 1
+    top = int(np.max(p.site_slice))
+    assert b["sweep_beam_slices"] == (top + 1) * b["n_beams_in"] + (p.n_slices + top) * b["n_beams_out"]
+    with pytest.raises(eels.EelsError) as e:
+        eels.Plan(p, s1_mode="inverse_s2", resident_s=True)
+    assert e.value.status == 1
+    with pytest.raises(KeyError):
+        eels.Plan(p, s1_mode="retreat")
+
+
 def test_band_table_matches_oracle_mask():
     """Band pixel count equals the oracle's circular mask count (same inclusive rule)."""
     _lib()

@@ -73,3 +73,54 @@ def test_inverse_multislice_exact_for_uniform_potential_and_images_unchanged():
     m1, i1 = eels.solve_with_images(p, rings)
     m2, i2 = eels.solve_with_images(p, rings, s1_mode="inverse")
     assert np.array_equal(i1, i2)          # same forward sweep to the exit
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("order", ["s_first", "probe_first"])
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16_split", 1e-3)])
+def test_s2_retreat_matches_oracle(name, order, prec, tol):
+    """S_2 formed at the entrance and retreated towards the exit (Sec. 4.C as printed)."""
+    eels = _gpu()
+    p = CASES[name]()
+    _say("inverse_s2", name, order, prec)
+    ref = prism.prism_map(p, s1_mode="inverse_s2")
+    g = eels.solve(p, precision=prec, order=order, s1_mode="inverse_s2")
+    assert maps_close(g, ref, tol)
+
+
+def test_s2_retreat_error_against_exact_path():
+    eels = _gpu()
+    p = CASES["strong_full_cell"]()
+    exact_o = prism.prism_map(p)
+    inv_o = prism.prism_map(p, s1_mode="inverse_s2")
+    e_oracle = metrics.rel_l2(inv_o, exact_o)
+    g_exact = eels.solve(p)
+    g_inv = eels.solve(p, s1_mode="inverse_s2")
+    e_gpu = metrics.rel_l2(g_inv, g_exact)
+    _say("inverse_s2 error oracle", e_oracle, "gpu", e_gpu)
+    assert 1e-7 < e_oracle < 0.05
+    assert abs(e_gpu - e_oracle) < 0.1 * e_oracle + 2e-5
+
+
+def test_s2_retreat_exact_for_uniform_potential_and_images_unchanged():
+    eels = _gpu()
+    p = synth.random_problem(34, n=128, L=12.0, nz=4, n_sites=3, n_trans=2, aperture_mrad=20.0,
+                             det_outer_mrad=30.0, n_scan=4, widths=(0.12, 0.4))
+    u = p.replace(V=np.full_like(p.V, 25.0))
+    assert metrics.rel_l2(eels.solve(u, s1_mode="inverse_s2"), eels.solve(u)) < 1e-5
+    rings = [(0.0, 30.0), (60.0, 0.0)]
+    m1, i1 = eels.solve_with_images(p, rings)
+    m2, i2 = eels.solve_with_images(p, rings, s1_mode="inverse_s2")
+    assert np.array_equal(i1, i2)          # same forward sweep to the exit
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16_split", 1e-3)])
+def test_s2_retreat_entrance_slice_is_exact(prec, tol):
+    """At slice 0 the retreat takes the transposed sweep's own capture, so a one-slice specimen
+    (and the entrance slice of any) gives the stored path's map."""
+    eels = _gpu()
+    p = synth.random_problem(35, n=64, L=10.0, nz=1, n_sites=3, n_trans=2, atoms_per_slice=6,
+                             widths=(0.15, 0.5), amp=(120.0, 32.0), aperture_mrad=18.0, det_outer_mrad=28.0)
+    ref = prism.prism_map(p, s1_mode="inverse_s2")
+    assert metrics.rel_l2(ref, prism.prism_map(p)) < 1e-12
+    assert maps_close(eels.solve(p, precision=prec, s1_mode="inverse_s2"), ref, tol)
