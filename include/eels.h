@@ -455,6 +455,11 @@ eels_status eels_admission_destroy(eels_admission* a);
  * key 10: tiles of that Gram GEMM with the G epilogue: 0 (default) 128 x 128 tiles of 4
  *        waves, 1 256 x 128 tiles of 8 waves.  Tiles with no element on or above the diagonal
  *        are skipped either way, and the maps are the same.
+ * key 11: operand staging of the two-stage split GEMMs (16-complex tiles): 0 global_load_lds
+ *        straight into the LDS ring everywhere; 1 (default) on the 256-row tiles, global loads
+ *        into registers one tile ahead, written to the ring at the top of the next step (the
+ *        nanoparticle map's Z product 2.86 -> 2.66 s); 2 that on the 128-row tiles too (its
+ *        Gram tiles measured 2% slower so).  The maps are the same bit for bit.
  * Returns EELS_ERR_INVALID_ARG for an unknown key or an out-of-range value. */
 eels_status eels_tune_set(int key, int value);
 int eels_tune_get(int key);

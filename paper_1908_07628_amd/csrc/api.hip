@@ -34,7 +34,7 @@ namespace eels {
 static thread_local std::string g_err;
 void set_error(const std::string& m) { g_err = m; }
 
-static std::atomic<int> g_tune[TUNE_COUNT] = {{2}, {2}, {0}, {1}, {1}, {1}, {1}, {1}, {1}, {1}, {0}};
+static std::atomic<int> g_tune[TUNE_COUNT] = {{2}, {2}, {0}, {1}, {1}, {1}, {1}, {1}, {1}, {1}, {0}, {1}};
 int tune_get(int key) { return (key >= 0 && key < TUNE_COUNT) ? g_tune[key].load() : 0; }
 
 // Diagnostic phase timing (eels_timing_enable / eels_timing_read).
@@ -1089,6 +1089,7 @@ eels_status eels_tune_set(int key, int value) {
     if (key == TUNE_CHECKPOINT && (value < 0 || value > 2)) return EELS_ERR_INVALID_ARG;
     if (key == TUNE_WG_FUSED && (value < 0 || value > 1)) return EELS_ERR_INVALID_ARG;
     if (key == TUNE_GRAM_ROWS && (value < 0 || value > 1)) return EELS_ERR_INVALID_ARG;
+    if (key == TUNE_GEMM_STAGING && (value < 0 || value > 2)) return EELS_ERR_INVALID_ARG;
     g_tune[key].store(value);
     return EELS_OK;
 }

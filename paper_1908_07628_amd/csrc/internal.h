@@ -45,7 +45,7 @@ static_assert(sizeof(GemmDesc) == 144, "GemmDesc layout");
 enum TuneKey {
     TUNE_SC_STAGES = 0, TUNE_TILE_ORDER = 1, TUNE_SC_SCHED = 2, TUNE_GRAM_STACK = 3, TUNE_GEMM1_ROWS = 4,
     TUNE_GEMM2_ROWS = 5, TUNE_WINDOW_GRAM = 6, TUNE_RASTER = 7, TUNE_CHECKPOINT = 8, TUNE_WG_FUSED = 9,
-    TUNE_GRAM_ROWS = 10, TUNE_COUNT = 11
+    TUNE_GRAM_ROWS = 10, TUNE_GEMM_STAGING = 11, TUNE_COUNT = 12
 };
 int tune_get(int key);
 

@@ -422,6 +422,10 @@ __global__ __launch_bounds__(128 * WM, (ScPipe<UNITS, NSTAGE, WM>::WAVES_PER_EU)
     constexpr int BMX = SP::BMX, NT = 128 * WM;
     constexpr int BKS = 4 * UNITS;  // complex per tile row
     static_assert(WM == 2 || EPI != 2, "the 256-row tile has no FP32 Gram-tile epilogue");
+    // SCHED bit 2: operands staged through registers (global loads into VGPRs, one tile ahead,
+    // written to the LDS stage at the top of the next step) instead of global_load_lds
+    constexpr bool REG = (SCHED & 4) != 0;
+    static_assert(!REG || NSTAGE == 2, "register staging keeps one tile in flight");
     static_assert(EPI != 4 || NSTAGE * STAGE >= 32 * (BMX + 128) * 8, "the G epilogue stages H in the LDS ring");
     __shared__ __attribute__((aligned(1024))) char smem[NSTAGE * STAGE];
     __shared__ int next_tile;
@@ -543,18 +547,45 @@ __global__ __launch_bounds__(128 * WM, (ScPipe<UNITS, NSTAGE, WM>::WAVES_PER_EU)
         if constexpr (SCHED & 2) __builtin_amdgcn_s_setprio(0);
     };
 
+    // register staging: this lane's quads of the next tile, at the LDS positions global_load_lds
+    // would give them (lane l of a load writes bytes 16 l .. 16 l + 15 of its rows' block)
+    u32x4 stg[REG ? NIA + NIB : 1];
+    auto load_stg = [&](int kt) {
+        const int64_t koff = (int64_t)kt * ROWB;
 #pragma unroll
-    for (int s = 0; s < NSTAGE - 1; ++s)
-        if (s < nk) issue(s);
+        for (int c = 0; c < NIA; ++c) stg[c] = *(const u32x4*)(asrc[c] + koff);
+#pragma unroll
+        for (int c = 0; c < NIB; ++c) stg[NIA + c] = *(const u32x4*)(bsrc[c] + koff);
+    };
+    if constexpr (REG) {
+        if (nk > 0) load_stg(0);
+    } else {
+#pragma unroll
+        for (int s = 0; s < NSTAGE - 1; ++s)
+            if (s < nk) issue(s);
+    }
 
     for (int kt = 0; kt < nk; ++kt) {
-        // this wave's loads of tile kt are done once at most the later tiles' loads remain;
-        // the barrier then covers every wave's part of the tile and frees the stage that was
-        // multiplied in the previous iteration (its LDS reads fed MFMAs, so they completed)
-        if (nk - 1 - kt >= NSTAGE - 2) wait_vmcnt<(NIA + NIB) * (NSTAGE - 2)>();
-        else wait_vmcnt<0>();
-        __builtin_amdgcn_s_barrier();
-        if (kt + NSTAGE - 1 < nk) issue(kt + NSTAGE - 1);
+        if constexpr (REG) {
+            // stage kt % 2 was last read in step kt - 2, which every wave finished before the
+            // barrier of step kt - 1
+            char* stw = smem + (kt % NSTAGE) * STAGE;
+#pragma unroll
+            for (int c = 0; c < NIA; ++c) *(u32x4*)(stw + (wave * 32 + c * RPI) * ROWB + lane * 16) = stg[c];
+#pragma unroll
+            for (int c = 0; c < NIB; ++c)
+                *(u32x4*)(stw + BMX * ROWB + (wave * BRW + c * RPI) * ROWB + lane * 16) = stg[NIA + c];
+            __syncthreads();
+            if (kt + 1 < nk) load_stg(kt + 1);
+        } else {
+            // this wave's loads of tile kt are done once at most the later tiles' loads remain;
+            // the barrier then covers every wave's part of the tile and frees the stage that was
+            // multiplied in the previous iteration (its LDS reads fed MFMAs, so they completed)
+            if (nk - 1 - kt >= NSTAGE - 2) wait_vmcnt<(NIA + NIB) * (NSTAGE - 2)>();
+            else wait_vmcnt<0>();
+            __builtin_amdgcn_s_barrier();
+            if (kt + NSTAGE - 1 < nk) issue(kt + NSTAGE - 1);
+        }
         const char* st = smem + (kt % NSTAGE) * STAGE;
         if constexpr (SCHED & 1) {
             // fragments of the next 8-complex step are read while this step's MFMAs run
@@ -826,14 +857,22 @@ static void go_sc(int nstage, int rows, const GemmDesc* dd, int nd, int tiles, c
         hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, st, dd, nd, A, B, C, P, idx, order, queue, tiles, H,      \
                            gscale);                                                                                    \
     } while (0)
+    // register staging of the operands: 256-row tiles with key 11 >= 1, 128-row ones with 2
+    const int staging = tune_get(TUNE_GEMM_STAGING);
     if constexpr (EPI != 2) {
         if (rows == 256) {
             // two stages of 16-complex tiles (96 KB of LDS; three stages measured slower on the
             // nanoparticle map's Z product, 2.87 against 2.82 s per map)
-            auto kern = k_cgemm_sc<PREC, EPI, 2, 4, 0, 4>;
-            const int grid = queue ? std::min(tiles, resident_blocks(kern, 512)) : tiles;
-            hipLaunchKernelGGL(kern, dim3(grid), dim3(512), 0, st, dd, nd, A, B, C, P, idx, order, queue, tiles, H,
-                               gscale);
+#define SC256(SC)                                                                                                      \
+    do {                                                                                                               \
+        auto kern = k_cgemm_sc<PREC, EPI, 2, 4, SC, 4>;                                                                \
+        const int grid = queue ? std::min(tiles, resident_blocks(kern, 512)) : tiles;                                  \
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(512), 0, st, dd, nd, A, B, C, P, idx, order, queue, tiles, H,      \
+                           gscale);                                                                                    \
+    } while (0)
+            if (staging >= 1) SC256(4);
+            else SC256(0);
+#undef SC256
             return;
         }
     }
@@ -842,6 +881,10 @@ static void go_sc(int nstage, int rows, const GemmDesc* dd, int nd, int tiles, c
         case 4: SCV(4, 2, 0); break;
         case 5: SCV(5, 2, 0); break;
         default:
+            if (staging == 2) {
+                SCV(2, 4, 4);
+                break;
+            }
             switch (tune_get(TUNE_SC_SCHED)) {
                 case 1: SCV(2, 4, 1); break;
                 case 2: SCV(2, 4, 2); break;

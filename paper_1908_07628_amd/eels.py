@@ -473,6 +473,7 @@ TUNE_RASTER = 7
 TUNE_CHECKPOINT = 8
 TUNE_WG_FUSED = 9
 TUNE_GRAM_ROWS = 10
+TUNE_GEMM_STAGING = 11
 
 
 def tune_set(key: int, value: int):

@@ -66,7 +66,7 @@ struct Case {
     bool tight_budget = false; // the budget is the smallest one the planner accepts (bisection)
     double budget_frac = 0;    // > 0: the budget is this fraction of the unconstrained workspace
     double aperture = 20, det_in = 10, det_out = 40;
-    int knobs[TUNE_COUNT] = {0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 0};
+    int knobs[TUNE_COUNT] = {0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 0, 1};
     eels_status expect = EELS_OK;
     int want_raster = -1, want_wgram = -1, want_gram = -1, want_groups_gt1 = -1, want_ckpt = -1;
 };

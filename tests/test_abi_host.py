@@ -270,13 +270,13 @@ def test_tuning_knob_ranges_and_gram_stack_plan():
     rows by default (plan-time knob 3)."""
     _lib()
     for key, bad in ((0, 1), (0, 6), (1, 3), (2, 4), (3, 2), (3, -1), (4, 2), (5, 2), (5, -1), (6, 3), (6, -1),
-                     (7, 3), (8, 3), (9, 2), (9, -1), (10, 2), (11, 0)):
+                     (7, 3), (8, 3), (9, 2), (9, -1), (10, 2), (11, 3), (11, -1), (12, 0)):
         with pytest.raises(eels.EelsError):
             eels.tune_set(key, bad)
     assert eels.tune_get(eels.TUNE_GRAM_STACK) == 1 and eels.tune_get(eels.TUNE_GEMM1_ROWS) == 1
     assert eels.tune_get(eels.TUNE_GEMM2_ROWS) == 1 and eels.tune_get(eels.TUNE_WINDOW_GRAM) == 1
     assert eels.tune_get(eels.TUNE_CHECKPOINT) == 1 and eels.tune_get(eels.TUNE_WG_FUSED) == 1
-    assert eels.tune_get(eels.TUNE_GRAM_ROWS) == 0
+    assert eels.tune_get(eels.TUNE_GRAM_ROWS) == 0 and eels.tune_get(eels.TUNE_GEMM_STAGING) == 1
 
 
 def test_fused_batch_plan_checks():

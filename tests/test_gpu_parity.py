@@ -578,3 +578,47 @@ def test_no_sites_gives_zero_map():
     q = p.replace(site_slice=p.site_slice[:0], site_xy=p.site_xy[:0], site_ntrans=p.site_ntrans[:0],
                   site_hoff=p.site_hoff[:0])
     assert np.all(_map(eels, q) == 0)
+
+
+@pytest.mark.parametrize("prec", ["bf16_split", "fp16_split"])
+def test_gemm_register_staging_same_maps(prec):
+    """Tuning key 11 stages the split GEMMs' operands through registers instead of loading them
+    straight into LDS (1: 256-row tiles, 2: all): the same tiles reach the same LDS positions, so every product (store, norm,
+    Gram and G epilogues, 128- and 256-row tiles) and every map is bitwise the same."""
+    eels = _need_gpu()
+    cases = [("config1 order S", synth.config1(), "s_first", {}),
+             ("crop order P per transition", synth.random_problem(12, n=64, L=12.0, nz=3, window_A=4.0,
+                                                                  n_sites=3, n_trans=3), "probe_first",
+              {eels.TUNE_WINDOW_GRAM: 0}),
+             ("crop order P window Gram", synth.random_problem(13, n=64, L=12.0, nz=3, window_A=4.0,
+                                                               n_sites=4, n_trans=2), "probe_first",
+              {eels.TUNE_WINDOW_GRAM: 2, eels.TUNE_RASTER: 0}),
+             ("raster 256-row Gram tiles", synth.config3_subproblem(n=128, L=25.0, nz=5, n_scan=8, f=2),
+              "probe_first", {eels.TUNE_WINDOW_GRAM: 2, eels.TUNE_RASTER: 2, eels.TUNE_GRAM_ROWS: 1}),
+             ("raster, combine pass", synth.config3_subproblem(n=128, L=25.0, nz=5, n_scan=8, f=2),
+              "probe_first", {eels.TUNE_WINDOW_GRAM: 2, eels.TUNE_RASTER: 2, eels.TUNE_WG_FUSED: 0})]
+    keys = (eels.TUNE_WINDOW_GRAM, eels.TUNE_RASTER, eels.TUNE_GRAM_ROWS, eels.TUNE_WG_FUSED,
+            eels.TUNE_GEMM_STAGING)
+    keep = {k: eels.tune_get(k) for k in keys}
+    try:
+        for name, p, order, knobs in cases:
+            for k, v in knobs.items():
+                eels.tune_set(k, v)
+            maps = []
+            for staging in (0, 1, 2):
+                eels.tune_set(eels.TUNE_GEMM_STAGING, staging)
+                _say("register staging", name, prec, "key 11 =", staging)
+                maps.append(_map(eels, p, prec, order))
+            assert np.array_equal(maps[0], maps[1]) and np.array_equal(maps[0], maps[2]), name
+            for k in knobs:
+                eels.tune_set(k, keep[k])
+        # the Gram form of order S (its Gram tiles in the SC kernel) and the debug GEMM
+        p = synth.config1()
+        maps = []
+        for staging in (0, 2):
+            eels.tune_set(eels.TUNE_GEMM_STAGING, staging)
+            maps.append(eels.solve(p, precision=prec, order="s_first", detector_sum="gram"))
+        assert np.array_equal(maps[0], maps[1])
+    finally:
+        for k, v in keep.items():
+            eels.tune_set(k, v)
