@@ -10,6 +10,7 @@
 #include "internal.h"
 #include "kernels.h"
 #include "sc_format.h"
+#include "stream_store.h"
 
 namespace eels {
 
@@ -72,8 +73,8 @@ __global__ __launch_bounds__(256) void k_window_t_sc(uint32_t* __restrict__ dst,
             float4* o = (float4*)((float2*)dst + (int64_t)pix * ldo + b);
             const float2 v0 = tile[4 * g][pc], v1 = tile[4 * g + 1][pc], v2 = tile[4 * g + 2][pc],
                          v3 = tile[4 * g + 3][pc];
-            o[0] = make_float4(v0.x, v0.y, v1.x, v1.y);
-            o[1] = make_float4(v2.x, v2.y, v3.x, v3.y);
+            st_stream(o, make_float4(v0.x, v0.y, v1.x, v1.y));
+            st_stream(o + 1, make_float4(v2.x, v2.y, v3.x, v3.y));
         } else {
             u32x4 hi, lo;
 #pragma unroll
@@ -85,8 +86,8 @@ __global__ __launch_bounds__(256) void k_window_t_sc(uint32_t* __restrict__ dst,
                 lo[e] = l;
             }
             uint32_t* o = dst + (((int64_t)pix * ldo + b) >> 2) * 8;
-            *(u32x4*)o = hi;
-            *(u32x4*)(o + 4) = lo;
+            st_stream_vec((u32x4*)o, hi);
+            st_stream_vec((u32x4*)(o + 4), lo);
         }
     }
     if (cp) {
@@ -116,8 +117,8 @@ __global__ __launch_bounds__(256) void k_window_t_sc(uint32_t* __restrict__ dst,
                 lo[e] = l;
             }
             uint32_t* o = cp + (((int64_t)bs * copy_ld + px) >> 2) * 8;
-            *(u32x4*)o = hi;
-            *(u32x4*)(o + 4) = lo;
+            st_stream_vec((u32x4*)o, hi);
+            st_stream_vec((u32x4*)(o + 4), lo);
         }
     }
 }

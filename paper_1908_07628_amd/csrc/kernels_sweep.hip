@@ -31,6 +31,7 @@
 #include "fft_reg.h"
 #include "internal.h"
 #include "kernels.h"
+#include "stream_store.h"
 
 namespace eels {
 
@@ -55,7 +56,7 @@ __device__ __forceinline__ void split_c(float2 v, int sc, uint32_t& hi, uint32_t
 }
 __device__ __forceinline__ void store_c(void* base, int64_t off, float2 v, int sc) {
     if (sc == 0) {
-        ((float2*)base)[off] = v;
+        st_stream((float2*)base + off, v);
         return;
     }
     uint32_t hi, lo;
@@ -63,8 +64,8 @@ __device__ __forceinline__ void store_c(void* base, int64_t off, float2 v, int s
     uint32_t* b = (uint32_t*)base;
     int64_t u = off >> 2;
     int pos = (int)(off & 3);
-    b[u * 8 + pos] = hi;
-    b[u * 8 + 4 + pos] = lo;
+    st_stream(b + u * 8 + pos, hi);
+    st_stream(b + u * 8 + 4 + pos, lo);
 }
 
 // --------------------------------------------------------------------- set-up kernels
