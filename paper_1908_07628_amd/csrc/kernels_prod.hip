@@ -59,7 +59,7 @@ __global__ __launch_bounds__(256) void k_window_t_sc(uint32_t* __restrict__ dst,
     for (int r = ty; r < 64; r += 4) {
         const int b = b0 + r, px = p0 + tx;
         const int bs = (perm && b < n_beams) ? perm[b] : b;
-        float2 v = (b < n_beams && px < K) ? src[(int64_t)bs * wstride + px] : make_float2(0.f, 0.f);
+        float2 v = (b < n_beams && px < K) ? ld_stream(src + (int64_t)bs * wstride + px) : make_float2(0.f, 0.f);
         if (cph && b < n_beams) v = cmul(cph[bs], v);   // the beam's factor, folded into both outputs
         tile[r][tx ^ ((r >> 2) & 15)] = v;
     }

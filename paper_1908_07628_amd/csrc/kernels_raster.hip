@@ -20,6 +20,7 @@
 #include "fft_reg.h"
 #include "internal.h"
 #include "kernels.h"
+#include "stream_store.h"
 
 namespace eels {
 
@@ -30,8 +31,8 @@ __device__ __forceinline__ void load_grids(float2 (&a)[16], float2 (&b)[16], con
                                            const float2* __restrict__ zr, const int (&q)[16]) {
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
-        a[m] = q[m] >= 0 ? xr[q[m]] : make_float2(0.f, 0.f);
-        b[m] = q[m] >= 0 ? zr[q[m]] : make_float2(0.f, 0.f);
+        a[m] = q[m] >= 0 ? ld_stream(xr + q[m]) : make_float2(0.f, 0.f);
+        b[m] = q[m] >= 0 ? ld_stream(zr + q[m]) : make_float2(0.f, 0.f);
     }
 }
 
