@@ -124,3 +124,22 @@ def test_s2_retreat_entrance_slice_is_exact(prec, tol):
     ref = prism.prism_map(p, s1_mode="inverse_s2")
     assert metrics.rel_l2(ref, prism.prism_map(p)) < 1e-12
     assert maps_close(eels.solve(p, precision=prec, s1_mode="inverse_s2"), ref, tol)
+
+
+@pytest.mark.parametrize("wgram", [0, 2])
+def test_s2_retreat_interpolated_crop_cell(wgram):
+    """The S_2 retreat with interpolation factor 2 and 4 A crop windows (the nanoparticle's
+    geometry on a small cell), with the per-transition products and with the window-Gram
+    detector sum, in BF16 split, against the oracle's inverse_s2 map."""
+    eels = _gpu()
+    p = synth.config3_subproblem(n=128, L=25.0, nz=5, n_scan=8, f=2)
+    ref = prism.prism_map(p, s1_mode="inverse_s2")
+    keep = eels.tune_get(eels.TUNE_WINDOW_GRAM)
+    try:
+        eels.tune_set(eels.TUNE_WINDOW_GRAM, wgram)
+        _say("inverse_s2 f=2 crop, window-Gram key", wgram)
+        g = eels.solve(p, precision="bf16_split", order="probe_first", s1_mode="inverse_s2")
+    finally:
+        eels.tune_set(eels.TUNE_WINDOW_GRAM, keep)
+    assert maps_close(g, ref, 1e-3)
+    assert np.all(g[ref == 0] == 0)
