@@ -159,6 +159,13 @@ const float2* Tj(const Plan& p, const Dev& d, int j) { return d.T + (int64_t)j *
 // slice j's propagator factor tables (nlx column factors, then ny row factors)
 const float2* Pj(const Plan& p, const Dev& d, int j) { return d.P + (int64_t)j * (p.nlx + p.ny); }
 
+// The S_1 windows' storage: complex64, or (raster form in split precision) SC with each beam's
+// c_k(R_0) folded in, which makes them the Z product's operand as captured.
+void s1_capture_format(const Plan& p, const Dev& d, RowPassArgs& a) {
+    a.sc = p.w1_sc;
+    a.cfac = p.w1_sc ? d.r_c0 : nullptr;
+}
+
 // Forward sweep of S_1 through slices 0..j_end (row pass of j_end included, its column
 // pass not).  Captures the windows of the ionised slices of `group` (if >= 0), or the
 // full real-space S_1(dbg_slice) into dbg_out.  With exit_cap (j_end = n_z - 1) the last
@@ -188,6 +195,7 @@ void forward_sweep(const Plan& p, const Dev& d, int j_end, int group, int dbg_sl
         } else if (group >= 0 && p.slices[j].ion && p.slices[j].group == group) {
             a.cap_ptr = d.blob + p.slices[j].cap1_ptr;
             a.cap_rec = d.blob + p.slices[j].cap1_rec;
+            s1_capture_format(p, d, a);
         }
         launch_row_pass(p.nx, 0, a, st);
         if (j < j_end) launch_col_pass(p.ny, 0, d.s1, p.N1, p.nlx, p.ldx, Pj(p, d, j), d.twy, d.band_h, BandCap{}, st);
@@ -208,6 +216,7 @@ void inverse_step(const Plan& p, const Dev& d, int j, bool capture, hipStream_t 
     if (capture) {
         a.cap_ptr = d.blob + p.slices[j].cap1_ptr;
         a.cap_rec = d.blob + p.slices[j].cap1_rec;
+        s1_capture_format(p, d, a);
     }
     launch_row_pass(p.nx, 2, a, st);
 }
@@ -234,6 +243,7 @@ void retreat_step(const Plan& p, const Dev& d, int j, bool capture, bool rows, h
     if (capture) {
         a.cap_ptr = d.blob + p.slices[j].cap1_ptr;
         a.cap_rec = d.blob + p.slices[j].cap1_rec;
+        s1_capture_format(p, d, a);
         b.cap_ptr = d.blob + p.slices[j].cap2_ptr;
         b.cap_rec = d.blob + p.slices[j].cap2_rec;
     }
@@ -356,9 +366,10 @@ void producers_after_gemm1(const Plan& p, const Dev& d, const float2* dH, const 
         launch_window_t_batched(d.mid2, d.w2, jobs, b.job_count, 0, p.Kpad, p.N2, p.K, p.N2p, p.precision, nullptr, st);
         if (p.raster) {
             // split precision: c_k(R_0) folded into Xt and into the Z GEMM's operand
+            const bool copy = split && !p.w1_sc;   // SC windows are the Z operand already
             launch_window_t_batched(d.mid2, d.w1, jobs, b.job_count, 1, p.Kpad, p.N1, p.K, p.N1pad, EELS_FP32,
-                                    d.blob + p.r_perm_off, st, split ? p.precision : 0, p.Kpad,
-                                    split ? d.r_c0 : nullptr);
+                                    d.blob + p.r_perm_off, st, copy ? p.precision : 0, p.Kpad,
+                                    copy ? d.r_c0 : nullptr, p.w1_sc);
         }
         return;
     }
@@ -394,11 +405,13 @@ void wgram_contract(const Plan& p, const Dev& d, const float2* dH, const Batch& 
     }
     if (p.raster) {
         {
-            // Z = G S_1w^T, the window's beams gathered into slot order
+            // Z = G S_1w^T, the window's beams gathered into slot order (from the SC windows as
+            // captured, or from their SC copy in mid2)
             TimeScope ts(EELS_PHASE_GEMM2, st);
             if (split)
-                launch_cgemm_sc(p.precision, 3, nst, d.descs + b.dy_begin, b.dy_count, b.dy_tiles, d.mid2, d.mid2,
-                                d.mid2, nullptr, d.blob, st, b.dy_rows);
+                launch_cgemm_sc(p.precision, 3, nst, d.descs + b.dy_begin, b.dy_count, b.dy_tiles, d.mid2,
+                                p.w1_sc ? (const void*)d.w1 : (const void*)d.mid2, d.mid2, nullptr, d.blob, st,
+                                b.dy_rows);
             else
                 launch_cgemm(EELS_FP32, 0, 0, d.descs + b.dy_begin, b.dy_count, b.dy_tiles, d.mid2, d.w1, nullptr,
                              d.mid2, nullptr, d.blob, st);
@@ -716,8 +729,10 @@ eels_status eels_execute_images(const eels_plan* pl, const float* d_V, const voi
         HIPCHK(hipGetLastError());
         return EELS_OK;
     }
-    // split operands are read in whole 16-element K tiles: the S_2 capture's padding must be zero
+    // split operands are read in whole 16-element K tiles: the S_2 capture's padding must be zero,
+    // and so must the SC S_1 windows' (the captures write pixels 0 .. K-1 of every row)
     if (p.precision != EELS_FP32) launch_fill_zero(d.w2, p.off_C - p.off_w2, st);
+    if (p.w1_sc) launch_sc_zero_cols(d.w1, (int64_t)std::max(p.max_w1, 1) * p.N1, p.Kpad, p.K, st);
     if (p.s1_inverse && !p.groups.empty()) {
         // S_1 through every slice to the exit (capturing the exit wave for the images), then
         // back down with the inverse multislice beside the transposed S_2 sweep

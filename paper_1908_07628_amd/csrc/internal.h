@@ -166,6 +166,8 @@ struct Plan {
     int64_t r_pos_off = -1;                     // int offset: compact column of grid slot (b mod M) M + (a mod M)
     bool s1_inverse = false;                    // S_1 retreated with the inverse multislice
     bool s2_retreat = false;                    // S_2 retreated towards the exit (inverse multislice)
+    int w1_sc = 0;                              // S_1 windows captured SC with c_k(R_0) folded in (raster
+                                                // form, split precision, S-matrices not resident), else 0
     int n_img = 0;                              // elastic companion images
     std::vector<double> img_in, img_out;        // their ring angles (rad; out < 0: band limit)
     int img_desc = -1;                          // descriptor of the images' Gram GEMM

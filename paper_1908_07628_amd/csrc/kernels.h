@@ -21,6 +21,7 @@ struct RowPassArgs {
     int Kpad;
     int sc;                 // capture format: 0 complex64, else the split precision
     int ldx;                // row stride of the state (live columns padded to 16)
+    const float2* cfac = nullptr;   // per-beam factor folded into the captured values (or none)
 };
 
 // Band capture of the transposed column pass (after the P multiply): beam b's band
@@ -118,9 +119,12 @@ void launch_window_t_sc(void* dst, const float2* src, int64_t wstride, int n_bea
 // window (which 1) also writes that window's SC copy [n_beams][copy_ld] (s1sc) from the same
 // reads, in place of a separate launch_to_sc_batched.  cph (may be null): every beam b's window
 // row is multiplied by cph[b] first (the raster form folds c_k(R_0) into both outputs).
+// in_sc: the source windows are stored SC in that split precision (else complex64).
 void launch_window_t_batched(void* dst_base, const float2* src_base, const ProdJob* jobs, int n_jobs, int which,
                              int64_t wstride, int n_beams, int K, int ldo, int prec, const int* perm, hipStream_t st,
-                             int copy_prec = 0, int copy_ld = 0, const float2* cph = nullptr);
+                             int copy_prec = 0, int copy_ld = 0, const float2* cph = nullptr, int in_sc = 0);
+// Zeroes complex slots K .. ld-1 of `rows` SC rows of ld slots (the K padding a split GEMM reads).
+void launch_sc_zero_cols(void* base, int64_t rows, int ld, int K, hipStream_t st);
 void launch_to_sc_batched(void* dst_base, const float2* src_base, const ProdJob* jobs, int n_jobs, int64_t rows, int K,
                           int ld, int prec, hipStream_t st);
 void launch_wgram_combine_batched(void* mid2, const float2* H, const ProdJob* jobs, int n_jobs, int K, int ldm, int ldg,

@@ -36,12 +36,24 @@ __global__ void k_to_sc(uint32_t* __restrict__ dst, const float2* __restrict__ s
 // or of the window-Gram form's Gram GEMM), FP32 complex64 rows.  A block moves a 64-pixel x
 // 64-beam tile through LDS, reading whole pixel runs of a beam and writing whole 4-beam
 // groups of a pixel.
+// x = hi + lo from an SC pair (hi and lo: (re, im) half pairs of one complex slot)
+__device__ __forceinline__ float2 sc_value(uint32_t hi, uint32_t lo, int prec) {
+    if (prec == EELS_BF16_SPLIT)
+        return make_float2(__uint_as_float(hi << 16) + __uint_as_float(lo << 16),
+                           __uint_as_float(hi & 0xffff0000u) + __uint_as_float(lo & 0xffff0000u));
+    const _Float16 hr = __builtin_bit_cast(_Float16, (uint16_t)(hi & 0xffffu));
+    const _Float16 hi2 = __builtin_bit_cast(_Float16, (uint16_t)(hi >> 16));
+    const _Float16 lr = __builtin_bit_cast(_Float16, (uint16_t)(lo & 0xffffu));
+    const _Float16 li = __builtin_bit_cast(_Float16, (uint16_t)(lo >> 16));
+    return make_float2((float)hr + (float)lr, (float)hi2 + (float)li);
+}
+
 template <int PREC>
 __global__ __launch_bounds__(256) void k_window_t_sc(uint32_t* __restrict__ dst, const float2* __restrict__ src,
                                                      int64_t wstride, int n_beams, int K, int ldo,
                                                      const int* __restrict__ perm, const ProdJob* __restrict__ jobs,
                                                      int which, int copy_prec, int copy_ld,
-                                                     const float2* __restrict__ cph) {
+                                                     const float2* __restrict__ cph, int in_sc) {
     // The tile holds beam row r, pixel c at tile[r][c ^ ((r >> 2) & 15)].  The swizzle puts the
     // 16 rows 4g + e (g = 0 .. 15) that a quarter-wave reads for one pixel in 16 distinct 8-byte
     // bank pairs (a padded 65-slot row left 4 of them in each), keeps every 4-pixel group of a
@@ -59,7 +71,16 @@ __global__ __launch_bounds__(256) void k_window_t_sc(uint32_t* __restrict__ dst,
     for (int r = ty; r < 64; r += 4) {
         const int b = b0 + r, px = p0 + tx;
         const int bs = (perm && b < n_beams) ? perm[b] : b;
-        float2 v = (b < n_beams && px < K) ? ld_stream(src + (int64_t)bs * wstride + px) : make_float2(0.f, 0.f);
+        float2 v = make_float2(0.f, 0.f);
+        if (b < n_beams && px < K) {
+            const int64_t o = (int64_t)bs * wstride + px;
+            if (in_sc) {
+                const uint32_t* w = (const uint32_t*)src + (o >> 2) * 8 + (o & 3);
+                v = sc_value(w[0], w[4], in_sc);
+            } else {
+                v = ld_stream(src + o);
+            }
+        }
         if (cph && b < n_beams) v = cmul(cph[bs], v);   // the beam's factor, folded into both outputs
         tile[r][tx ^ ((r >> 2) & 15)] = v;
     }
@@ -125,18 +146,18 @@ __global__ __launch_bounds__(256) void k_window_t_sc(uint32_t* __restrict__ dst,
 
 static void window_t_go(void* dst, const float2* src, int64_t wstride, int n_beams, int K, int ldo, int prec,
                         hipStream_t st, const int* perm, const ProdJob* jobs, int n_jobs, int which, int copy_prec,
-                        int copy_ld, const float2* cph) {
+                        int copy_ld, const float2* cph, int in_sc = 0) {
     if (n_beams <= 0 || K <= 0 || n_jobs <= 0) return;
     dim3 grid((unsigned)ceil_div(K, 64), (unsigned)ceil_div(ldo, 64), (unsigned)n_jobs);
     if (prec == EELS_BF16_SPLIT)
         hipLaunchKernelGGL(k_window_t_sc<EELS_BF16_SPLIT>, grid, dim3(256), 0, st, (uint32_t*)dst, src, wstride,
-                           n_beams, K, ldo, perm, jobs, which, copy_prec, copy_ld, cph);
+                           n_beams, K, ldo, perm, jobs, which, copy_prec, copy_ld, cph, in_sc);
     else if (prec == EELS_FP16_SPLIT)
         hipLaunchKernelGGL(k_window_t_sc<EELS_FP16_SPLIT>, grid, dim3(256), 0, st, (uint32_t*)dst, src, wstride,
-                           n_beams, K, ldo, perm, jobs, which, copy_prec, copy_ld, cph);
+                           n_beams, K, ldo, perm, jobs, which, copy_prec, copy_ld, cph, in_sc);
     else
         hipLaunchKernelGGL(k_window_t_sc<EELS_FP32>, grid, dim3(256), 0, st, (uint32_t*)dst, src, wstride,
-                           n_beams, K, ldo, perm, jobs, which, copy_prec, copy_ld, cph);
+                           n_beams, K, ldo, perm, jobs, which, copy_prec, copy_ld, cph, in_sc);
 }
 
 void launch_window_t_sc(void* dst, const float2* src, int64_t wstride, int n_beams, int K, int ldo, int prec,
@@ -146,9 +167,28 @@ void launch_window_t_sc(void* dst, const float2* src, int64_t wstride, int n_bea
 
 void launch_window_t_batched(void* dst_base, const float2* src_base, const ProdJob* jobs, int n_jobs, int which,
                              int64_t wstride, int n_beams, int K, int ldo, int prec, const int* perm, hipStream_t st,
-                             int copy_prec, int copy_ld, const float2* cph) {
+                             int copy_prec, int copy_ld, const float2* cph, int in_sc) {
     window_t_go(dst_base, src_base, wstride, n_beams, K, ldo, prec, st, perm, jobs, n_jobs, which, copy_prec,
-                copy_ld, cph);
+                copy_ld, cph, in_sc);
+}
+
+// zero complex slots K .. ld-1 of every SC row (a thread per row and padding slot)
+__global__ void k_sc_zero_cols(uint32_t* __restrict__ base, int64_t rows, int ld, int K) {
+    const int pad = ld - K;
+    const int64_t n = rows * pad;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = (i / pad) * ld + K + (int)(i % pad);
+        uint32_t* w = base + (o >> 2) * 8 + (o & 3);
+        w[0] = 0u;
+        w[4] = 0u;
+    }
+}
+
+void launch_sc_zero_cols(void* base, int64_t rows, int ld, int K, hipStream_t st) {
+    if (rows <= 0 || ld <= K) return;
+    const int64_t n = rows * (ld - K);
+    hipLaunchKernelGGL(k_sc_zero_cols, dim3((unsigned)std::min<int64_t>(ceil_div(n, 256), 8192)), dim3(256), 0, st,
+                       (uint32_t*)base, rows, ld, K);
 }
 
 // Window-Gram form of the detector sum: G = gscale M o S with S[r][c] = sum_t conj(H_t[r]) H_t[c]

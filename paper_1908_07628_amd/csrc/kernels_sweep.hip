@@ -240,7 +240,7 @@ __device__ __forceinline__ void row_pass_body(float2* __restrict__ state, int nb
                                               const float2* __restrict__ Tj, const float2* __restrict__ tw,
                                               const int* __restrict__ cap_ptr, const int4* __restrict__ cap_rec,
                                               void* __restrict__ win, int64_t win_beams, int Kpad, int sc,
-                                              float2* lds) {
+                                              float2* lds, const float2* __restrict__ cfac = nullptr) {
     constexpr int E = RegCfg<N>::E, T = RegCfg<N>::T, S = 256 / T, L = PadLen<N>::value;
     const int tid = threadIdx.x, s = tid / T, t = tid % T;
     const int64_t total = (int64_t)nbeam * ny;
@@ -283,8 +283,16 @@ __device__ __forceinline__ void row_pass_body(float2* __restrict__ state, int nb
             if constexpr (CAP) {
                 float2* crow = lds + s * L;
                 lds_sync_wave();
+                if (cfac) {
+                    // the beam's factor (times the capture scale) goes into every captured value
+                    const float2 cb = cfac[beam];
+                    const float2 cs = make_float2(cb.x * cap_scale, cb.y * cap_scale);
 #pragma unroll
-                for (int m = 0; m < E; ++m) crow[t + T * m] = make_float2(v[m].x * cap_scale, v[m].y * cap_scale);
+                    for (int m = 0; m < E; ++m) crow[t + T * m] = cmul(v[m], cs);
+                } else {
+#pragma unroll
+                    for (int m = 0; m < E; ++m) crow[t + T * m] = make_float2(v[m].x * cap_scale, v[m].y * cap_scale);
+                }
                 lds_sync_wave();
                 if (valid) {
                     // the row's records are fetched T at a time, one per thread; a pair's record
@@ -363,10 +371,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RegCfg<N>::
                                                       int ldx, const float2* __restrict__ Tj,
                                                       const float2* __restrict__ tw, const int* __restrict__ cap_ptr,
                                                       const int4* __restrict__ cap_rec, void* __restrict__ win,
-                                                      int64_t win_beams, int Kpad, int sc) {
+                                                      int64_t win_beams, int Kpad, int sc,
+                                                      const float2* __restrict__ cfac) {
     __shared__ float2 lds[(256 / RegCfg<N>::T) * PadLen<N>::value];
     row_pass_body<N, MODE, true>(state, nbeam, ny, nlx, hlx, ldx, Tj, tw, cap_ptr, cap_rec, win, win_beams, Kpad, sc,
-                                 lds);
+                                 lds, cfac);
 }
 
 // --------------------------------------------------------------------- column pass
@@ -730,7 +739,8 @@ static void row_pass_n(const RowPassArgs& a, hipStream_t st) {
     const dim3 grid(strided_grid(blocks_for(rows, S)));
     if (a.cap_ptr)
         hipLaunchKernelGGL((k_row_pass_cap<N, MODE>), grid, dim3(256), 0, st, a.state, a.nbeam, a.ny, a.nlx, a.hlx,
-                           a.ldx, a.Tj, a.tw, a.cap_ptr, (const int4*)a.cap_rec, a.win, a.win_beams, a.Kpad, a.sc);
+                           a.ldx, a.Tj, a.tw, a.cap_ptr, (const int4*)a.cap_rec, a.win, a.win_beams, a.Kpad, a.sc,
+                           a.cfac);
     else
         hipLaunchKernelGGL((k_row_pass<N, MODE>), grid, dim3(256), 0, st, a.state, a.nbeam, a.ny, a.nlx, a.hlx, a.ldx,
                            a.Tj, a.tw);

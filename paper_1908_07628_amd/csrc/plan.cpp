@@ -354,6 +354,10 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
     p.max_w2 = max_w2;
     const int64_t w2_slice = p.recip ? (int64_t)p.N2 * p.Kbpad : (int64_t)max_w2 * p.N2 * p.Kpad;
     p.resident = q.resident_s != 0;
+    // raster form in split precision: the S_1 capture writes the windows SC with each beam's
+    // c_k(R_0) folded in, so they are the Z product's operand as they stand (resident windows
+    // serve new probes, whose c_k(R_0) differ, and keep complex64)
+    p.w1_sc = (p.raster && split && !p.resident) ? p.precision : 0;
     p.slice_w2.assign(p.nz, 0);
     int64_t w2_elems = w2_slice;
     if (p.resident) {
@@ -377,8 +381,9 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
                   wg_y = wg_g + (int64_t)p.K * p.Kpad;
     auto site_mid2 = [&](int s) -> int64_t {
         if (!p.recip && !split && !p.wgram) return 0;
-        // raster form: Z [K][N_1p] at wg_y, then Xt [K][N_1p], then (split) S_1w as SC [N_1][Kpad]
-        int64_t m2 = p.raster ? wg_y + 2 * (int64_t)p.K * p.N1pad + (split ? (int64_t)p.N1 * p.Kpad : 0)
+        // raster form: Z [K][N_1p] at wg_y, then Xt [K][N_1p], then (split, windows not captured
+        // SC) S_1w as SC [N_1][Kpad]
+        int64_t m2 = p.raster ? wg_y + 2 * (int64_t)p.K * p.N1pad + (split && !p.w1_sc ? (int64_t)p.N1 * p.Kpad : 0)
                    : p.wgram ? wg_y + (int64_t)n_elig(s) * p.Kpad
                              : (int64_t)p.sites[s].n_trans * site_ni(s) * Kcpad;
         // order P, split: the site's S_1 window is first transposed here for the product C S_1w
@@ -906,7 +911,8 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
             bt.dm_tiles = tl;
             // Y_s^T[i][r] = sum_r' Psi_s[i][r'] G_s[r][r']  (complex64 store), or in the raster
             // form Z_s[r][q] = sum_r' G_s[r][r'] S_1w[perm(q)][r'] (the S_1 window's rows gathered
-            // into beam-slot order; FP32 reads them from the window buffer, split from their SC copy)
+            // into beam-slot order from the window buffer, or in split precision with complex64
+            // windows from their SC copy)
             bt.dy_begin = (int)p.descs.size();
             tl = 0;
             for (size_t si = 0; si < pb.sites.size(); ++si) {
@@ -914,7 +920,7 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
                 GemmDesc d{};
                 if (p.raster) {
                     d.a_off = jb.g_off; d.lda = p.Kpad;
-                    d.b_off = split ? jb.s1sc_off : jb.win_off; d.ldb = p.Kpad;
+                    d.b_off = (split && !p.w1_sc) ? jb.s1sc_off : jb.win_off; d.ldb = p.Kpad;
                     d.h_off = -1; d.idx_off = p.r_perm_off;
                     d.c_off = jb.y_off; d.ldc_m = p.N1pad; d.ldc_t = 0;
                     d.M = p.K; d.N_inner = p.N1; d.n_t = 1; d.K = p.K;
@@ -944,7 +950,7 @@ static eels_status build_plan_impl(Plan& p, const eels_problem& q, size_t blob_r
                                 jb.m_off + (int64_t)(p.K - 1) * p.Kpad + p.K <= m2off &&
                                 jb.g_off + (int64_t)(p.K - 1) * p.Kpad + k16 <= m2off &&
                                 jb.y_off + last_row <= m2off && jb.xt_off + last_row <= m2off &&
-                                (!split || jb.s1sc_off + (int64_t)(p.N1 - 1) * p.Kpad + k16 <= m2off) &&
+                                (!split || p.w1_sc || jb.s1sc_off + (int64_t)(p.N1 - 1) * p.Kpad + k16 <= m2off) &&
                                 jb.part_off + (int64_t)p.r_chunks * p.rM * p.rM <= poff &&
                                 n16 <= p.N2p && k16 <= p.Kpad && m2off <= p.mid2_elems && poff <= p.part_elems;
                 if (!ok) return fail(EELS_ERR_INTERNAL, "raster-form operands leave their buffers");
@@ -1132,7 +1138,7 @@ uint64_t s_signature(const Plan& p) {
     add(p.nx); add(p.ny); add(p.lx); add(p.ly); add(p.nz);
     fnv(h, p.dz.data(), p.dz.size() * sizeof(double));
     add(p.lam); add(p.sigma); add(p.alpha); add(p.beta_in); add(p.beta_out); add(p.f); add(p.kmax);
-    add(p.full_window); add(p.recip); add(p.resident); add(p.hwx); add(p.hwy); add(p.Kpad); add(p.Kbpad);
+    add(p.full_window); add(p.recip); add(p.resident); add(p.w1_sc); add(p.hwx); add(p.hwy); add(p.Kpad); add(p.Kbpad);
     add(p.w2_sc); add(p.N1); add(p.N2);
     fnv(h, p.ab1.data(), p.ab1.size() * sizeof(int));
     fnv(h, p.ab2.data(), p.ab2.size() * sizeof(int));

@@ -209,7 +209,7 @@ Role role_dy(const Plan& p) {
     r.split = p.precision != EELS_FP32;
     r.c = B_MID2;
     r.epi = r.split ? 3 : 0;
-    if (p.raster) { r.a = B_MID2; r.b = r.split ? B_MID2 : B_W1; }
+    if (p.raster) { r.a = B_MID2; r.b = (r.split && !p.w1_sc) ? B_MID2 : B_W1; }
     else { r.a = B_MID; r.b = B_MID2; }
     return r;
 }
@@ -406,7 +406,7 @@ void check_plan(const Plan& p, const Case& c, size_t budget) {
                 if (p.raster) {
                     regs.push_back({jb.y_off, jb.y_off + (int64_t)p.K * p.N1pad, "Z", k});
                     regs.push_back({jb.xt_off, jb.xt_off + (int64_t)p.K * p.N1pad, "Xt", k});
-                    if (p.precision != EELS_FP32)
+                    if (p.precision != EELS_FP32 && !p.w1_sc)
                         regs.push_back({jb.s1sc_off, jb.s1sc_off + (int64_t)p.N1 * p.Kpad, "S_1w SC", k});
                 } else {
                     regs.push_back({jb.y_off, jb.y_off + (int64_t)std::max(jb.ps, 1) * p.Kpad, "Y^T", k});
@@ -525,6 +525,9 @@ void check_plan(const Plan& p, const Case& c, size_t budget) {
 
     // ---- expectations of the case
     if (c.want_raster >= 0) CHECK((int)p.raster == c.want_raster, "raster form %d, expected %d", (int)p.raster, c.want_raster);
+    // SC S_1 windows exactly for the raster form in split precision without resident S-matrices
+    CHECK(p.w1_sc == ((p.raster && p.precision != EELS_FP32 && !p.resident) ? p.precision : 0),
+          "S_1 window format %d", p.w1_sc);
     if (c.want_wgram >= 0) CHECK((int)p.wgram == c.want_wgram, "window-Gram form %d, expected %d", (int)p.wgram, c.want_wgram);
     if (c.want_gram >= 0) CHECK((int)p.gram == c.want_gram, "Gram form %d, expected %d", (int)p.gram, c.want_gram);
     if (c.want_groups_gt1 >= 0)
