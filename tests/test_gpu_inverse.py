@@ -143,3 +143,26 @@ def test_s2_retreat_interpolated_crop_cell(wgram):
         eels.tune_set(eels.TUNE_WINDOW_GRAM, keep)
     assert maps_close(g, ref, 1e-3)
     assert np.all(g[ref == 0] == 0)
+
+
+@pytest.mark.parametrize("mode", ["inverse", "inverse_s2"])
+@pytest.mark.parametrize("prec", ["bf16_split", "fp16_split"])
+def test_inverse_modes_in_the_raster_form(mode, prec):
+    """Both inverse multislice modes with the raster form forced (its S_1 windows captured SC
+    with c_k(R_0) folded in, by the inverse row pass for the S_1 retreat and by the forward
+    row pass beside the S_2 retreat), against the oracle's map of the same mode."""
+    eels = _gpu()
+    p = synth.config3_subproblem(n=128, L=25.0, nz=5, n_scan=8, f=2)
+    ref = prism.prism_map(p, s1_mode=mode)
+    keep = (eels.tune_get(eels.TUNE_WINDOW_GRAM), eels.tune_get(eels.TUNE_RASTER))
+    try:
+        eels.tune_set(eels.TUNE_WINDOW_GRAM, 2)
+        eels.tune_set(eels.TUNE_RASTER, 2)
+        assert eels.Plan(p, precision=prec, order="probe_first", s1_mode=mode).info()["raster_form"] == 64
+        _say("raster form", mode, prec)
+        g = eels.solve(p, precision=prec, order="probe_first", s1_mode=mode)
+    finally:
+        eels.tune_set(eels.TUNE_WINDOW_GRAM, keep[0])
+        eels.tune_set(eels.TUNE_RASTER, keep[1])
+    assert maps_close(g, ref, 1e-3)
+    assert np.all(g[ref == 0] == 0)
